@@ -1,0 +1,497 @@
+"""Pins of the CPU oracle against closed forms, invariants and special cases.
+
+Both oracle implementations (NumPy brute force and the C footprint splatter)
+are checked against values fixed by geometry, not against themselves:
+  * sphere depth along a pixel ray (high-precision closed form),
+  * the perspective silhouette of a sphere (analytic ellipse of the view cone),
+  * the orthographic disk (exact lattice count) and its depth profile,
+  * cylinder end-cap and side-on geometry (disk, rectangle, depth profile,
+    two-halves colouring),
+  * visibility order (coaxial spheres, the analytic intersection plane of
+    interpenetrating spheres, tie-break by id, permutation invariance),
+  * near-plane rule (front root only),
+  * headlight shading at n.V = 1 and the background colour,
+  * SSAO special cases (flat surfaces, vanishing radius, a step whose
+    occluded pixels follow from the sample geometry).
+"""
+import math
+from fractions import Fraction
+
+import mpmath
+import numpy as np
+import pytest
+
+from oracle import ofull, osplat
+from paper_2501_12750_amd import scenes
+
+mpmath.mp.dps = 50
+ORACLES = {"ofull": ofull, "osplat": osplat}
+BG = 0xFFFFFFFF
+
+
+def make_scene(centers, radii, colors=None, bonds=None):
+    pos = np.array(centers, dtype=np.float32).reshape(-1, 3)
+    n = pos.shape[0]
+    rad = np.array(radii, dtype=np.float32).reshape(n)
+    if colors is None:
+        colors = [scenes.ELEMENT_COLOR[0]] * n
+    col = np.array(colors, dtype=np.uint32).reshape(n)
+    b = np.zeros((0, 2), dtype=np.uint32) if bonds is None else np.array(bonds, dtype=np.uint32).reshape(-1, 2)
+    return scenes.Scene(pos, rad, col, b)
+
+
+def persp(eye, target, fovy_deg=45.0, up=(0, 1, 0), znear=1.0, zfar=1e5):
+    return scenes.Camera(eye=eye, target=target, up=up, fovy=math.radians(fovy_deg), znear=znear, zfar=zfar)
+
+
+def ortho(eye, target, half_h, up=(0, 1, 0), znear=1.0, zfar=1e5):
+    return scenes.Camera(eye=eye, target=target, up=up, projection=scenes.ORTHOGRAPHIC,
+                         ortho_half_height=half_h, znear=znear, zfar=zfar)
+
+
+@pytest.fixture(params=sorted(ORACLES))
+def oracle(request):
+    return ORACLES[request.param]
+
+
+# ---------------------------------------------------------------------------
+# sphere depth: z = (D cos(theta) - sqrt(r^2 - D^2 sin^2(theta))) * (d . f)
+# ---------------------------------------------------------------------------
+def test_sphere_depth_closed_form(oracle):
+    c = (3.25, -2.5, -4.0)
+    r = 6.0
+    cam = persp(eye=(1.0, 2.0, 60.0), target=(0.0, 0.0, 0.0), fovy_deg=40.0)
+    W, H = 48, 40
+    sc = make_scene([c], [r])
+    g = oracle.gbuffer(sc, cam, scenes.Options(), W, H)
+    hits = np.argwhere(g["id"] == 0)
+    assert len(hits) > 60
+    eye = [mpmath.mpf(v) for v in cam.eye]
+    tgt = [mpmath.mpf(v) for v in cam.target]
+    up = [mpmath.mpf(v) for v in cam.up]
+
+    def sub(a, b):
+        return [a[i] - b[i] for i in range(3)]
+
+    def dot(a, b):
+        return sum(a[i] * b[i] for i in range(3))
+
+    def cross(a, b):
+        return [a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]]
+
+    def unit(a):
+        n = mpmath.sqrt(dot(a, a))
+        return [x / n for x in a]
+
+    f = unit(sub(tgt, eye))
+    s = unit(cross(f, up))
+    u = cross(s, f)
+    th = mpmath.tan(mpmath.mpf(cam.fovy) / 2)
+    cc = [mpmath.mpf(float(v)) for v in np.array(c, dtype=np.float32)]
+    rr = mpmath.mpf(float(np.float32(r)))
+    oc = sub(cc, eye)
+    D = mpmath.sqrt(dot(oc, oc))
+    rng = np.random.default_rng(0)
+    for j, i in hits[rng.choice(len(hits), 60, replace=False)]:
+        nx = 2 * (mpmath.mpf(int(i)) + mpmath.mpf(1) / 2) / W - 1
+        ny = 1 - 2 * (mpmath.mpf(int(j)) + mpmath.mpf(1) / 2) / H
+        d = unit([f[k] + nx * th * mpmath.mpf(W) / H * s[k] + ny * th * u[k] for k in range(3)])
+        cos_t = dot(d, oc) / D
+        theta = mpmath.acos(cos_t)
+        t = D * mpmath.cos(theta) - mpmath.sqrt(rr ** 2 - D ** 2 * mpmath.sin(theta) ** 2)
+        z = t * dot(d, f)
+        assert abs(g["z"][j, i] - float(z)) <= 1e-12 * float(z)
+
+
+# ---------------------------------------------------------------------------
+# perspective silhouette: pixel centres inside the cone's conic section
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("center,r", [((9.0, 5.5, -3.0), 2.75), ((-14.0, -7.0, 10.0), 4.0), ((0.0, 0.0, 0.0), 5.0)])
+def test_sphere_silhouette_is_view_cone_ellipse(oracle, center, r):
+    W, H = 64, 48
+    fovy = 50.0
+    cam = persp(eye=(0.0, 0.0, 50.0), target=(0.0, 0.0, 0.0), fovy_deg=fovy)
+    sc = make_scene([center], [r])
+    g = oracle.gbuffer(sc, cam, scenes.Options(), W, H)
+    c32 = np.array(center, dtype=np.float32).astype(np.float64)
+    r32 = float(np.float32(r))
+    # camera looks down -z with up +y: view x = world x, view y = world y, view z = 50 - world z
+    v = np.array([c32[0], c32[1], 50.0 - c32[2]])
+    D = np.linalg.norm(v)
+    sin_a = r32 / D
+    cos_a = math.sqrt(1 - sin_a ** 2)
+    cos_p = v[2] / D
+    sin_p = math.sqrt(max(0.0, 1 - cos_p ** 2))
+    k = cos_p ** 2 - sin_a ** 2
+    semi_r = sin_a * cos_a / k
+    semi_t = sin_a / math.sqrt(k)
+    off = sin_p * cos_p / k
+    radial = v[:2] / np.linalg.norm(v[:2]) if np.linalg.norm(v[:2]) > 0 else np.array([1.0, 0.0])
+    th = math.tan(math.radians(fovy) / 2)
+    jj, ii = np.mgrid[0:H, 0:W]
+    X = (2 * (ii + 0.5) / W - 1) * th * W / H
+    Y = (1 - 2 * (jj + 0.5) / H) * th
+    pr = X * radial[0] + Y * radial[1]
+    pt = -X * radial[1] + Y * radial[0]
+    val = ((pr - off) / semi_r) ** 2 + (pt / semi_t) ** 2
+    inside = val <= 1.0
+    firm = np.abs(val - 1.0) > 1e-9
+    assert inside.sum() > 20
+    assert np.array_equal((g["id"] == 0)[firm], inside[firm])
+
+
+# ---------------------------------------------------------------------------
+# orthographic sphere: lattice count of a disk and the depth profile
+# ---------------------------------------------------------------------------
+def test_orthographic_sphere_disk(oracle):
+    W, H, hh = 64, 64, 8.0
+    scale = Fraction(H, 2) / Fraction(8)                    # pixels per angstrom
+    cx, cy, r = Fraction(7, 16), Fraction(-5, 8), Fraction(5, 2)
+    cam = ortho(eye=(0.0, 0.0, 30.0), target=(0.0, 0.0, 0.0), half_h=hh)
+    sc = make_scene([(float(cx), float(cy), 0.0)], [float(r)])
+    g = oracle.gbuffer(sc, cam, scenes.Options(), W, H)
+    pcx = Fraction(W, 2) + cx * scale
+    pcy = Fraction(H, 2) - cy * scale
+    rp2 = (r * scale) ** 2
+    inside = np.zeros((H, W), dtype=bool)
+    boundary = np.zeros((H, W), dtype=bool)
+    for j in range(H):
+        for i in range(W):
+            d2 = (i + Fraction(1, 2) - pcx) ** 2 + (j + Fraction(1, 2) - pcy) ** 2
+            inside[j, i] = d2 <= rp2
+            boundary[j, i] = d2 == rp2
+    assert inside.sum() - boundary.sum() <= np.count_nonzero(g["id"] == 0) <= inside.sum()
+    assert np.array_equal((g["id"] == 0)[~boundary], inside[~boundary])
+    # depth D - sqrt(r^2 - rho^2), D = 30 along the view axis
+    for j, i in np.argwhere(inside & ~boundary)[::7]:
+        x = (Fraction(2 * int(i) + 1, W) - 1) * Fraction(W, H) * 8
+        y = (1 - Fraction(2 * int(j) + 1, H)) * 8
+        rho2 = (x - cx) ** 2 + (y - cy) ** 2
+        dz2 = r ** 2 - rho2
+        z = 30 - mpmath.sqrt(mpmath.mpf(dz2.numerator) / dz2.denominator)
+        assert abs(g["z"][j, i] - float(z)) <= 1e-12 * 30
+
+
+# ---------------------------------------------------------------------------
+# cylinders
+# ---------------------------------------------------------------------------
+RED = scenes.pack_rgba(255, 13, 13)
+BLUE = scenes.pack_rgba(48, 80, 248)
+
+
+def test_cylinder_end_cap_facing_camera(oracle):
+    W, H, hh = 48, 48, 2.0
+    rho = 0.75
+    cam = ortho(eye=(0.0, 0.0, 10.0), target=(0.0, 0.0, 0.0), half_h=hh)
+    # atom 0 nearer the camera; its cap (normal -a) faces the camera
+    sc = make_scene([(0, 0, -1.0), (0, 0, -3.0)], [0.01, 0.01], colors=[RED, BLUE], bonds=[(0, 1)])
+    opts = scenes.Options(bond_radius=rho)
+    res = oracle.render(sc, cam, opts, W, H)
+    scale = (H / 2) / hh
+    jj, ii = np.mgrid[0:H, 0:W]
+    X = (ii + 0.5 - W / 2) / scale
+    Y = (H / 2 - jj - 0.5) / scale
+    dist = np.hypot(X, Y)
+    firm = np.abs(dist - rho) > 1e-9
+    disk = dist <= rho
+    hit_bond = res["id"] == 2
+    assert np.array_equal(hit_bond[firm], disk[firm])
+    assert np.all(res["z"][disk & firm] == 11.0)
+    nvw = res["normal_view"][disk & firm]
+    assert np.allclose(nvw, [0.0, 0.0, -1.0], atol=0)
+    # n.V = 1: colour = albedo (ka + kd) + ks, identical over the disk
+    exp = [math.floor(255 * min(1.0, ch / 255 * (0.2 + 0.8) + 0.25) + 0.5) for ch in (255, 13, 13)]
+    exp_rgba = exp[0] | (exp[1] << 8) | (exp[2] << 16) | (255 << 24)
+    assert np.all(res["rgba"][disk & firm] == exp_rgba)
+    assert np.all(res["rgba"][~disk & firm] == 0)
+
+
+def test_cylinder_side_on_rectangle_and_halves(oracle):
+    W, H, hh = 80, 40, 1.5
+    rho = 0.5
+    cam = ortho(eye=(0.0, 0.0, 10.0), target=(0.0, 0.0, 0.0), half_h=hh)
+    sc = make_scene([(-2.0, 0, 0), (2.0, 0, 0)], [0.01, 0.01], colors=[RED, BLUE], bonds=[(0, 1)])
+    g = oracle.gbuffer(sc, cam, scenes.Options(bond_radius=rho), W, H)
+    scale = (H / 2) / hh
+    jj, ii = np.mgrid[0:H, 0:W]
+    X = (ii + 0.5 - W / 2) / scale
+    Y = (H / 2 - jj - 0.5) / scale
+    rect = (np.abs(Y) <= rho) & (np.abs(X) <= 2.0)
+    firm = (np.abs(np.abs(Y) - rho) > 1e-9) & (np.abs(np.abs(X) - 2.0) > 1e-9)
+    assert np.array_equal((g["id"] == 2)[firm], rect[firm])
+    m = rect & firm
+    zexp = 10.0 - np.sqrt(rho ** 2 - Y[m] ** 2)
+    assert np.max(np.abs(g["z"][m] - zexp)) <= 1e-12 * 10
+    # two halves: x < 0 takes atom 0's colour
+    assert np.all(g["albedo"][m & (X < 0)] == RED)
+    assert np.all(g["albedo"][m & (X > 0)] == BLUE)
+    # lateral normal (0, y/rho, sqrt(rho^2-y^2)/rho) in world = (0, y/rho, -sqrt(..)/rho) in view
+    n = g["normal_view"][m]
+    assert np.allclose(n[:, 1], Y[m] / rho, atol=1e-12)
+    assert np.allclose(n[:, 2], -np.sqrt(rho ** 2 - Y[m] ** 2) / rho, atol=1e-12)
+
+
+def test_cylinder_perspective_depth_matches_sampled_surface(oracle):
+    # an oblique bond: every hit's 3D point lies on the closed cylinder surface
+    cam = persp(eye=(3.0, 4.0, 25.0), target=(0.0, 0.0, 0.0), fovy_deg=30.0)
+    A = np.array([-3.0, -1.0, 0.5], dtype=np.float32)
+    B = np.array([2.5, 1.5, -2.0], dtype=np.float32)
+    rho = 0.6
+    sc = make_scene([A, B], [0.01, 0.01], bonds=[(0, 1)])
+    W, H = 64, 64
+    g = oracle.gbuffer(sc, cam, scenes.Options(bond_radius=rho), W, H)
+    o, d = ofull.pixel_rays(cam, W, H, (0, 0, W, H))
+    e, s, u, f = ofull.camera_frame(cam)
+    ids = g["id"].ravel()
+    m = ids == 2
+    assert m.sum() > 50
+    z = g["z"].ravel()[m]
+    t = z / (d[m] @ f)
+    x = o[m] + t[:, None] * d[m]
+    a64, b64 = A.astype(np.float64), B.astype(np.float64)
+    L = np.linalg.norm(b64 - a64)
+    ax = (b64 - a64) / L
+    sv = (x - a64) @ ax
+    radial = np.linalg.norm((x - a64) - sv[:, None] * ax, axis=1)
+    rho = float(np.float32(rho))        # the option is an FP32 value
+    on_side = np.abs(radial - rho) <= 1e-9
+    on_cap = (np.abs(sv) <= 1e-9) | (np.abs(sv - L) <= 1e-9)
+    assert np.all(on_side | (on_cap & (radial <= rho + 1e-9)))
+    assert np.all((sv >= -1e-9) & (sv <= L + 1e-9))
+
+
+def test_degenerate_bonds_are_skipped(oracle):
+    cam = ortho(eye=(0.0, 0.0, 10.0), target=(0.0, 0.0, 0.0), half_h=2.0)
+    sc = make_scene([(0, 0, 0), (0, 0, 0), (5, 5, 5)], [0.01, 0.01, 0.01], bonds=[(0, 1), (2, 2)])
+    g = oracle.gbuffer(sc, cam, scenes.Options(bond_radius=1.0), 16, 16)
+    assert not np.any(g["id"] >= 3) or np.all(g["id"][g["id"] >= 3] == BG)
+
+
+# ---------------------------------------------------------------------------
+# visibility
+# ---------------------------------------------------------------------------
+def test_coaxial_spheres_nearer_wins(oracle):
+    cam = persp(eye=(0.0, 0.0, 40.0), target=(0.0, 0.0, 0.0))
+    sc = make_scene([(0, 0, -5.0), (0, 0, 5.0)], [3.0, 2.0])
+    g = oracle.gbuffer(sc, cam, scenes.Options(), 32, 32)
+    # the small near sphere occludes the centre of the big far one
+    assert g["id"][16, 16] == 1
+    assert set(np.unique(g["id"])) == {0, 1, BG}
+
+
+def test_interpenetrating_spheres_split_at_intersection_plane(oracle):
+    # ortho view down -z; spheres on the x axis: the visible boundary is the
+    # projection of the intersection circle, x* = (d^2 + r1^2 - r2^2) / (2 d) + c1
+    W, H, hh = 96, 64, 4.0
+    c1, c2, r1, r2 = -1.0, 1.5, 3.0, 2.5
+    cam = ortho(eye=(0.0, 0.0, 20.0), target=(0.0, 0.0, 0.0), half_h=hh)
+    sc = make_scene([(c1, 0, 0), (c2, 0, 0)], [r1, r2])
+    g = oracle.gbuffer(sc, cam, scenes.Options(), W, H)
+    dd = c2 - c1
+    xstar = (dd ** 2 + r1 ** 2 - r2 ** 2) / (2 * dd) + c1
+    scale = (H / 2) / hh
+    jj, ii = np.mgrid[0:H, 0:W]
+    X = (ii + 0.5 - W / 2) / scale
+    Y = (H / 2 - jj - 0.5) / scale
+    both = ((X - c1) ** 2 + Y ** 2 < r1 ** 2 - 1e-9) & ((X - c2) ** 2 + Y ** 2 < r2 ** 2 - 1e-9)
+    firm = both & (np.abs(X - xstar) > 1e-9)
+    assert firm.sum() > 50
+    assert np.all(g["id"][firm & (X < xstar)] == 0)
+    assert np.all(g["id"][firm & (X > xstar)] == 1)
+
+
+def test_exact_tie_goes_to_smaller_id(oracle):
+    cam = persp(eye=(0.0, 0.0, 40.0), target=(0.0, 0.0, 0.0))
+    sc = make_scene([(1, 2, 3), (1, 2, 3), (1, 2, 3)], [5.0, 5.0, 5.0])
+    g = oracle.gbuffer(sc, cam, scenes.Options(), 24, 24)
+    hit = g["id"] != BG
+    assert hit.sum() > 10 and np.all(g["id"][hit] == 0)
+    # every duplicate is an equally correct answer
+    assert np.all(g["acc_n"][hit] == 3)
+
+
+def test_permutation_invariance(oracle):
+    wl = scenes.ball_and_stick(n_globules=2, atoms_per_globule=150, sigma=3.0, pitch=5.0,
+                               width=72, height=56, ssao_samples=0)
+    sc = wl.scene
+    g0 = oracle.gbuffer(sc, wl.camera, wl.options, wl.width, wl.height)
+    rng = np.random.default_rng(7)
+    pa = rng.permutation(sc.n_atoms)
+    pb = rng.permutation(sc.n_bonds)
+    sp = sc.permuted(pa, pb)
+    g1 = oracle.gbuffer(sp, wl.camera, wl.options, wl.width, wl.height)
+    assert np.array_equal(g0["z"], g1["z"])
+    inv_a = np.empty_like(pa)
+    inv_a[pa] = np.arange(pa.size)
+    inv_b = np.empty_like(pb)
+    inv_b[pb] = np.arange(pb.size)
+    N = sc.n_atoms
+    ids1 = g1["id"]
+    mapped = np.where(ids1 == BG, BG, np.where(ids1 < N, pa[np.minimum(ids1, N - 1)],
+                                                  N + pb[np.clip(ids1 - N, 0, pb.size - 1)]))
+    strict = g0["acc_n"] == 1
+    assert np.array_equal(mapped[strict], g0["id"][strict])
+
+
+def test_near_plane_front_root_only(oracle):
+    # camera inside a big sphere: its front root is behind the eye, so it is
+    # invisible everywhere (its back root is never used) and the small atom
+    # outside it shows through
+    cam = persp(eye=(0.0, 0.0, 0.0), target=(0.0, 0.0, -1.0), znear=1.0)
+    sc = make_scene([(0, 0, 0), (0, 0, -30.0)], [10.0, 2.0])
+    g = oracle.gbuffer(sc, cam, scenes.Options(), 32, 32)
+    assert not np.any(g["id"] == 0)
+    assert g["id"][16, 16] == 1
+    # a sphere sliced by the near plane: pixels whose front root is nearer than
+    # znear show what lies behind
+    cam2 = persp(eye=(0.0, 0.0, 0.0), target=(0.0, 0.0, -1.0), znear=5.0)
+    sc2 = make_scene([(0, 0, -5.5), (0, 0, -30.0)], [1.0, 2.0])
+    g2 = oracle.gbuffer(sc2, cam2, scenes.Options(), 32, 32)
+    assert g2["id"][16, 16] == 1          # front root at z = 4.5 < znear is clipped
+    assert np.any(g2["id"] == 0)          # the rim (front root beyond znear) remains
+
+
+def test_far_plane(oracle):
+    cam = persp(eye=(0.0, 0.0, 0.0), target=(0.0, 0.0, -1.0), zfar=20.0)
+    sc = make_scene([(0, 0, -30.0)], [2.0])
+    g = oracle.gbuffer(sc, cam, scenes.Options(), 16, 16)
+    assert np.all(g["id"] == BG)
+
+
+def test_row_zero_is_top_and_x_grows_right(oracle):
+    cam = persp(eye=(0.0, 0.0, 40.0), target=(0.0, 0.0, 0.0))
+    sc = make_scene([(-8.0, 8.0, 0.0)], [2.0])          # upper-left in the view
+    g = oracle.gbuffer(sc, cam, scenes.Options(), 40, 40)
+    jj, ii = np.nonzero(g["id"] == 0)
+    assert jj.max() < 20 and ii.max() < 20
+
+
+# ---------------------------------------------------------------------------
+# shading
+# ---------------------------------------------------------------------------
+def test_headlight_centre_of_sphere(oracle):
+    # orthographic ray through the sphere centre has n.V = 1
+    W, H = 33, 33
+    grey = scenes.pack_rgba(144, 100, 30)
+    cam = ortho(eye=(0.0, 0.0, 20.0), target=(0.0, 0.0, 0.0), half_h=4.0)
+    sc = make_scene([(0.0, 0.0, 0.0)], [3.0], colors=[grey])
+    bgc = scenes.pack_rgba(10, 20, 30, 40)
+    res = oracle.render(sc, cam, scenes.Options(background=bgc), W, H)
+    exp = [math.floor(255 * min(1.0, ch / 255 + 0.25) + 0.5) for ch in (144, 100, 30)]
+    assert res["rgba"][16, 16] == (exp[0] | (exp[1] << 8) | (exp[2] << 16) | (255 << 24))
+    assert res["rgba"][0, 0] == bgc
+    assert np.all(res["rgba"][res["id"] == BG] == bgc)
+
+
+def test_shading_darkens_towards_silhouette(oracle):
+    W, H = 65, 65
+    cam = ortho(eye=(0.0, 0.0, 20.0), target=(0.0, 0.0, 0.0), half_h=4.0)
+    sc = make_scene([(0.0, 0.0, 0.0)], [3.5], colors=[scenes.pack_rgba(200, 200, 200)])
+    res = oracle.render(sc, cam, scenes.Options(), W, H)
+    row = res["rgba"][32] & 255
+    hit = res["id"][32] == 0
+    vals = row[hit]
+    mid = len(vals) // 2
+    assert np.all(np.diff(vals[: mid + 1].astype(int)) >= 0)
+    assert np.all(np.diff(vals[mid:].astype(int)) <= 0)
+
+
+# ---------------------------------------------------------------------------
+# SSAO
+# ---------------------------------------------------------------------------
+def test_ssao_kernel_and_basis_properties():
+    for K in (1, 2, 16, 64):
+        hk, sk = ofull.ssao_kernel(K)
+        assert np.allclose(np.linalg.norm(hk, axis=1), 1.0, atol=1e-6)
+        assert np.all(hk[:, 2] > 0) and np.all((sk > 0.1 - 1e-7) & (sk <= 1.0 + 1e-7))
+    rng = np.random.default_rng(3)
+    n = rng.normal(size=(500, 3))
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    T, B = ofull.onb_duff(n)
+    assert np.allclose(np.einsum("ij,ij->i", T, B), 0, atol=1e-12)
+    assert np.allclose(np.einsum("ij,ij->i", T, n), 0, atol=1e-12)
+    assert np.allclose(np.linalg.norm(T, axis=1), 1, atol=1e-12)
+    assert np.allclose(np.cross(T, B), n, atol=1e-12)       # right-handed (T, B, N)
+
+
+def _cap_scene(disks):
+    """Flat disks facing an orthographic camera looking down -z: each is the
+    near cap of a short bond along the view axis.  disks = [(x, y, zworld, colour)]."""
+    pos, cols, bonds = [], [], []
+    for k, (x, y, zw, c) in enumerate(disks):
+        pos += [(x, y, zw), (x, y, zw - 0.5)]
+        cols += [c, c]
+        bonds.append((2 * k, 2 * k + 1))
+    return make_scene(pos, [1e-3] * len(pos), colors=cols, bonds=bonds)
+
+
+def test_ssao_flat_surface_is_unoccluded(oracle):
+    W, H, hh = 48, 48, 6.0
+    cam = ortho(eye=(0.0, 0.0, 20.0), target=(0.0, 0.0, 0.0), half_h=hh)
+    sc = _cap_scene([(0.0, 0.0, 0.0, scenes.pack_rgba(200, 200, 200))])
+    opts = scenes.Options(bond_radius=50.0, ssao_samples=16, ssao_radius=2.0)
+    res = oracle.render(sc, cam, opts, W, H)
+    assert np.all(res["id"] != BG)
+    assert np.all(res["ao"] == 1.0)
+
+
+def test_ssao_vanishing_radius_gives_one(oracle):
+    wl = scenes.plain_small(n_atoms=200, width=48, height=40)
+    opts = scenes.Options(ssao_samples=16, ssao_radius=1e-6, ssao_bias=0.05)
+    res = oracle.render(wl.scene, wl.camera, opts, wl.width, wl.height)
+    assert np.all(res["ao"] == 1.0)
+
+
+@pytest.mark.parametrize("K", [1, 2])
+def test_ssao_step_occlusion_from_geometry(oracle, K):
+    """Far disk at depth 20 (world z = 0), near disk at depth 19 (world z = 1)
+    whose edge crosses the image.  The normal is (0, 0, -1) in view space; for
+    it the basis is T = (1, 0, 0), B = (0, -1, 0) (derived by hand from the
+    branchless construction with sign = -1, a = 1/2).  A sample with
+    hemisphere direction h and scale s lands R s (h.x, -h.y) to the right/up in
+    the view plane and R s h.z nearer to the camera; it is occluded iff its
+    pixel lies on the near disk and 19 <= 20 - R s h.z - bias, with weight
+    smoothstep(R / 1)."""
+    W, H, hh = 64, 48, 4.0
+    R, bias = 1.5, 0.05
+    cam = ortho(eye=(0.0, 0.0, 20.0), target=(0.0, 0.0, 0.0), half_h=hh)
+    far = (0.0, 0.0, 0.0, scenes.pack_rgba(200, 200, 200))
+    near_c = (7.0, 0.3)
+    near_r = 6.0
+    # both disks have the bond radius (6 A): the far one is centred on the
+    # axis, the near one 7 A to the right, so its edge crosses the far disk
+    sc = _cap_scene([far, (near_c[0], near_c[1], 1.0, scenes.pack_rgba(90, 90, 90))])
+    opts = scenes.Options(bond_radius=near_r, ssao_samples=K, ssao_radius=R, ssao_bias=bias)
+    res = oracle.render(sc, cam, opts, W, H)
+    scale = (H / 2) / hh
+    jj, ii = np.mgrid[0:H, 0:W]
+    X = (ii + 0.5 - W / 2) / scale
+    Y = (H / 2 - jj - 0.5) / scale
+    on_near = (X - near_c[0]) ** 2 + (Y - near_c[1]) ** 2 <= near_r ** 2
+    on_far = (X ** 2 + Y ** 2 <= near_r ** 2) & ~on_near
+    hk = []
+    for k in range(K):
+        ct = 1.0 - (k + 0.5) / K
+        st = math.sqrt(1 - ct * ct)
+        ph = 2 * math.pi * ((k * 0.6180339887498949) % 1.0)
+        hk.append((float(np.float32(st * math.cos(ph))), float(np.float32(st * math.sin(ph))),
+                   float(np.float32(ct)), float(np.float32(0.1 + 0.9 * ((k + 1) / K) ** 2))))
+    wgt = 1.0    # smoothstep(R / |20 - 19|) with R >= 1
+    exp = np.ones((H, W))
+    for (hx, hy, hz, s) in hk:
+        sx = X + R * s * hx
+        sy = Y - R * s * hy
+        sz = 20.0 - R * s * hz
+        qx = np.floor(W / 2 + sx * scale)
+        qy = np.floor(H / 2 - sy * scale)
+        cxq = (qx + 0.5 - W / 2) / scale
+        cyq = (H / 2 - qy - 0.5) / scale
+        q_near = (cxq - near_c[0]) ** 2 + (cyq - near_c[1]) ** 2 <= near_r ** 2
+        inside = (qx >= 0) & (qx < W) & (qy >= 0) & (qy < H)
+        occl = inside & q_near & (19.0 <= sz - bias)
+        exp -= np.where(occl, wgt / K, 0.0)
+    stable = res["ssao_unstable"] == 0
+    m = on_far & stable
+    assert m.sum() > 100
+    assert np.any(exp[m] < 1.0)
+    assert np.allclose(res["ao"][m], exp[m], atol=1e-12)
