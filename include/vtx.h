@@ -1,0 +1,211 @@
+/*
+ * vtx.h - C ABI of the MI355X impostor renderer for massive molecular scenes.
+ *
+ * The renderer draws the "meshless" representations of VTX (Maria et al.,
+ * "VTX: Real-time high-performance molecular structure and dynamics
+ * visualization software", Bioinformatics 2025): a molecule is the positions
+ * of its atoms, their radii and their connectivity (Methods, "Molecular
+ * Graphics Engine"); atoms are spheres and bonds are cylinders, each
+ * displayed by ray-casting its implicit surface, which gives pixel-exact
+ * images (same section, "Meshless Representations"); a deferred pass then
+ * applies screen-space ambient occlusion and shading over the G-buffer
+ * (Methods, "High Quality Rendering").
+ *
+ * Conventions shared by every entry point
+ *  - Array arguments are DEVICE pointers (hipMalloc'd or torch CUDA tensor
+ *    storage) on the current HIP device.  The caller owns them; the library
+ *    never frees or keeps them beyond the call's stream work.
+ *  - Work is queued on `stream` (a hipStream_t; NULL = the null stream) and
+ *    the call returns without waiting for it, except where stated.
+ *  - Return value: VTX_OK (0) or a negative VTX_E* code; vtx_last_error()
+ *    then gives a message (per host thread).  On an error nothing has been
+ *    queued and the outputs are unchanged.
+ *  - Images are row-major, W x H, row 0 is the TOP row, column 0 the left.
+ *  - View space: x right, y up, z forward (away from the eye).  Depth is the
+ *    view z of the surface point in the length unit of the positions
+ *    (angstrom), +inf where no primitive is hit.
+ *  - Primitive ids: atom i has id i, bond b has id n_atoms + b; background
+ *    is VTX_BACKGROUND_ID.  The visible primitive at a pixel is the one with
+ *    the smallest (depth, id), so equal depths go to the smaller id.
+ *  - Colours are RGBA8 packed in a uint32, R in the low byte.
+ *  - Per-stream scratch memory (tile bins) is owned by the library, grows on
+ *    demand and is released by vtx_release_scratch().  Calls queued on the
+ *    same stream are ordered; calls on different streams use separate
+ *    scratch and may overlap.
+ */
+#ifndef VTX_H
+#define VTX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VTX_OK 0
+#define VTX_EINVAL (-1)     /* invalid argument */
+#define VTX_ENOMEM (-2)     /* device or pinned allocation failed */
+#define VTX_EHIP (-3)       /* a HIP runtime call failed */
+#define VTX_EOVERFLOW (-4)  /* a size exceeds what the library supports */
+#define VTX_EBUSY (-5)      /* admission refused (budget or slots exhausted) */
+
+#define VTX_PERSPECTIVE 0
+#define VTX_ORTHOGRAPHIC 1
+
+#define VTX_BACKGROUND_ID 0xFFFFFFFFu
+#define VTX_MAX_PIXELS (7680 * 4320)   /* 8K, the paper's largest export size */
+#define VTX_MAX_SSAO_SAMPLES 64
+
+/* options.flags */
+#define VTX_FLAG_STATS 1u        /* count every (primitive, pixel) hit exactly;
+                                    disables the depth early-outs */
+#define VTX_FLAG_TIMING 2u       /* vtx_render records a HIP event before and after
+                                    each kernel, read back by vtx_read_timings */
+
+/*
+ * Camera (paper, "Improved user experience": trackball and free-fly cameras
+ * both reduce to a pose and a projection).  The view basis is
+ * f = normalize(target - eye), s = normalize(f x up), u = s x f.  Pixel
+ * (i, j) has the normalized device coordinates
+ * (2 (i + 1/2) / W - 1, 1 - 2 (j + 1/2) / H); a perspective ray leaves the eye
+ * through that point of the image plane at tan(fovy/2) (times W/H in x); an
+ * orthographic ray is parallel to f from the point eye + ndc_x h (W/H) s +
+ * ndc_y h u.  Only surface points with znear <= depth <= zfar are drawn.
+ */
+typedef struct vtx_camera {
+    float eye[3];
+    float target[3];
+    float up[3];
+    float fovy;               /* radians, vertical field of view (perspective) */
+    float ortho_half_height;  /* h: half height of the view volume (orthographic) */
+    int32_t projection;       /* VTX_PERSPECTIVE or VTX_ORTHOGRAPHIC */
+    float znear;              /* > 0 */
+    float zfar;               /* > znear */
+} vtx_camera;
+
+/*
+ * Rendering options (paper, "High Quality Rendering": deferred shading with
+ * ambient occlusion computed every frame, custom background with
+ * transparency).  Pass NULL for the defaults shown.
+ */
+typedef struct vtx_options {
+    float bond_radius;        /* cylinder radius of every bond (0.15) */
+    int32_t ssao_samples;     /* K hemisphere samples, 0 = no ambient occlusion (0) */
+    float ssao_radius;        /* hemisphere radius (2.0) */
+    float ssao_bias;          /* depth bias of the occlusion test (0.05) */
+    uint32_t background;      /* RGBA8 of pixels hit by nothing (0 = transparent black) */
+    int32_t tile_size;        /* screen tile edge in pixels: 0 (default), 8, 16 or 32 */
+    uint32_t flags;           /* VTX_FLAG_* */
+} vtx_options;
+
+/* Per-frame counters of the last frame queued on a stream. */
+typedef struct vtx_stats {
+    uint64_t visible;          /* primitives that survived frustum culling */
+    uint64_t pairs;            /* (primitive, tile) bin entries */
+    uint64_t fragments_tested; /* (primitive, pixel) ray tests run (VTX_FLAG_STATS) */
+    uint64_t fragments_hit;    /* tests that hit: atom-fragments (VTX_FLAG_STATS) */
+    uint64_t fragments_hit_bond; /* of which on bond cylinders (VTX_FLAG_STATS) */
+    uint64_t overflow_tiles;   /* tiles resolved by the slow path because the bins were full */
+    uint64_t bin_capacity;     /* bin entries available for that frame */
+    uint64_t bad_bonds;        /* bonds skipped because an index was >= n_atoms */
+} vtx_stats;
+
+/* Average device time per kernel of the frames rendered with VTX_FLAG_TIMING. */
+typedef struct vtx_timings {
+    uint64_t frames;        /* frames averaged */
+    double ms_clear;        /* clear the tile counters */
+    double ms_project;      /* project, cull, count per tile */
+    double ms_scan;         /* prefix sum of the tile counts */
+    double ms_scatter;      /* fill the tile lists */
+    double ms_resolve;      /* per-tile ray casting into the G-buffer */
+    double ms_shade;        /* SSAO and shading */
+} vtx_timings;
+
+/*
+ * vtx_render - one frame: visibility then deferred shading.
+ *
+ * The paper's statement of the problem (Methods, "Molecular Graphics
+ * Engine"): positions, radii and connectivity in, an image out.
+ *   positions  n_atoms x 3 float, AoS (x, y, z per atom)
+ *   radii      n_atoms float; atoms with radius <= 0 are not drawn
+ *   colors     n_atoms RGBA8
+ *   bonds      n_bonds x 2 uint32 atom indices (NULL if n_bonds == 0); bonds
+ *              whose two atoms coincide are not drawn, bonds with an index
+ *              >= n_atoms are skipped and counted in vtx_stats.bad_bonds
+ *   cam, opt   host structs, read during the call only (opt may be NULL)
+ *   rgba       W x H RGBA8 out (required)
+ *   depth      W x H float out (required: the G-buffer the deferred pass reads)
+ *   id         W x H uint32 out (required)
+ * Requires n_atoms >= 0, n_bonds >= 0, n_atoms + n_bonds < 2^32 - 1,
+ * 1 <= W, H and W * H <= VTX_MAX_PIXELS.  Errors: VTX_EINVAL, VTX_ENOMEM, VTX_EHIP.
+ */
+int vtx_render(const float* positions, const float* radii, const uint32_t* colors, int64_t n_atoms,
+               const uint32_t* bonds, int64_t n_bonds, const vtx_camera* cam, const vtx_options* opt,
+               int32_t W, int32_t H, uint32_t* rgba, float* depth, uint32_t* id, void* stream);
+
+/*
+ * vtx_gbuffer - visibility only: bin the primitives into screen tiles and
+ * ray-cast each pixel against its tile's primitives (Methods, "Meshless
+ * Representations": a quad per primitive, then ray-casting of the implicit
+ * surface).  Same arguments as vtx_render without rgba; writes depth and id.
+ */
+int vtx_gbuffer(const float* positions, const float* radii, const uint32_t* colors, int64_t n_atoms,
+                const uint32_t* bonds, int64_t n_bonds, const vtx_camera* cam, const vtx_options* opt,
+                int32_t W, int32_t H, float* depth, uint32_t* id, void* stream);
+
+/*
+ * vtx_shade - the deferred pass over an existing G-buffer (Methods, "High
+ * Quality Rendering": screen-space ambient occlusion recomputed every frame,
+ * then lighting).  depth and id are inputs in the layout vtx_gbuffer writes;
+ * the surface normal and colour of each pixel are derived from the primitive
+ * named by id and the depth.  Optional outputs (NULL to skip), for
+ * inspection: normal (W x H x 3 float, view space, unit), albedo (W x H
+ * RGBA8), ao (W x H float in [0, 1]).
+ */
+int vtx_shade(const float* positions, const float* radii, const uint32_t* colors, int64_t n_atoms,
+              const uint32_t* bonds, int64_t n_bonds, const vtx_camera* cam, const vtx_options* opt,
+              int32_t W, int32_t H, const float* depth, const uint32_t* id, uint32_t* rgba,
+              float* normal, uint32_t* albedo, float* ao, void* stream);
+
+/*
+ * vtx_read_stats - waits for `stream` to drain, then returns the counters of
+ * the last frame queued on it by this library.  VTX_EINVAL if none was.
+ */
+int vtx_read_stats(void* stream, vtx_stats* out);
+
+/*
+ * vtx_set_bin_capacity - fixes the number of tile-bin entries of the
+ * stream's scratch (entries >= 1), or restores automatic sizing (entries = 0:
+ * the bins start at max(2^20, 2 (n_atoms + n_bonds)) entries and grow after a
+ * frame that needed more).  A frame whose bins overflow is still exact: the
+ * tiles that did not fit are resolved from the list of visible primitives,
+ * more slowly, and counted in vtx_stats.overflow_tiles.  Waits for the
+ * stream.  VTX_EINVAL if entries > 2^31.
+ */
+int vtx_set_bin_capacity(void* stream, uint64_t entries);
+
+/*
+ * vtx_read_timings - waits for `stream`, then returns the per-kernel averages
+ * over the frames queued on it with VTX_FLAG_TIMING since the last
+ * vtx_reset_timings (frames = 0 if none).
+ */
+int vtx_read_timings(void* stream, vtx_timings* out);
+
+/* vtx_reset_timings - waits for `stream` and clears its timing averages. */
+int vtx_reset_timings(void* stream);
+
+/* vtx_release_scratch - waits for the stream and frees its scratch memory. */
+int vtx_release_scratch(void* stream);
+
+/* vtx_last_error - message of the last failed call on this host thread ("" if none). */
+const char* vtx_last_error(void);
+
+/* vtx_version - library version string. */
+const char* vtx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VTX_H */

@@ -491,7 +491,8 @@ def shade(Nv, Vv, albedo, ao, hit, background):
     return np.where(hit, rgba, np.uint32(background)).astype(np.uint32)
 
 
-def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=None, depth_win=None):
+def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=None, depth_win=None,
+                  edge_px=1e-3, depth_rel=1e-5):
     """Deferred pass: SSAO then shading over ``window``.
 
     z, normal_view, albedo cover the window; depth_buf/depth_win give the depth
@@ -506,14 +507,15 @@ def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=Non
     if depth_buf is None:
         depth_buf, depth_win = z, window
     ao, uns, outside = ssao(cam, W, H, window, Pv, Nv, hit, depth_buf, depth_win,
-                            int(opts.ssao_samples), float(opts.ssao_radius), float(opts.ssao_bias))
+                            int(opts.ssao_samples), float(opts.ssao_radius), float(opts.ssao_bias),
+                            edge_px=edge_px, depth_rel=depth_rel)
     Vv = -view_dir(cam, W, H, window)
     rgba = shade(Nv, Vv, albedo.ravel().astype(np.uint32), ao, hit, int(opts.background))
     return dict(rgba=rgba.reshape(h, w), ao=ao.reshape(h, w),
                 ssao_unstable=uns.reshape(h, w), ssao_outside=outside.reshape(h, w))
 
 
-def render(scene, cam, opts, W, H, window=None, halo=0):
+def render(scene, cam, opts, W, H, window=None, halo=0, edge_px=1e-3, depth_rel=1e-5):
     """End to end: G-buffer over the window grown by ``halo`` pixels, then
     SSAO and shading of the window.  Returns the G-buffer dict restricted to
     the window plus rgba/ao/ssao_unstable/ssao_outside."""
@@ -527,6 +529,6 @@ def render(scene, cam, opts, W, H, window=None, halo=0):
     sl = (slice(y0 - gy0, y0 - gy0 + h), slice(x0 - gx0, x0 - gx0 + w))
     inner = {k: (v[sl] if isinstance(v, np.ndarray) and v.ndim >= 2 else v) for k, v in g.items()}
     sh = shade_gbuffer(cam, opts, W, H, window, inner["z"], inner["normal_view"], inner["albedo"],
-                       depth_buf=g["z"], depth_win=gwin)
+                       depth_buf=g["z"], depth_win=gwin, edge_px=edge_px, depth_rel=depth_rel)
     inner.update(sh)
     return inner

@@ -426,8 +426,8 @@ static double os_smooth(double x) {
 int osplat_shade(const double* cam, int W, int H, int x0, int y0, int w, int h,
                  const double* z, const double* nrm, const uint32_t* alb,
                  const double* depth_buf, int bx0, int by0, int bw, int bh,
-                 int K, double R, double bias, uint32_t background, int nthreads,
-                 uint32_t* rgba, double* ao_out, int32_t* unstable_out, int32_t* outside_out) {
+                 int K, double R, double bias, uint32_t background, double edge_px, double depth_rel,
+                 int nthreads, uint32_t* rgba, double* ao_out, int32_t* unstable_out, int32_t* outside_out) {
     if (K < 0 || K > 1024) return -1;
     os_cam c;
     os_make_cam(cam, W, H, &c);
@@ -483,7 +483,7 @@ int osplat_shade(const double* cam, int W, int H, int x0, int y0, int w, int h,
                     double px, py;
                     int front = S[2] > c.znear;
                     double za = fabs(S[2]) > c.znear ? fabs(S[2]) : c.znear;
-                    int near_edge = fabs(S[2] - c.znear) <= 1e-5 * za;
+                    int near_edge = fabs(S[2] - c.znear) <= depth_rel * za;
                     if (c.proj == 0) {
                         px = W / 2.0 + fpx * S[0] / S[2];
                         py = H / 2.0 - fpx * S[1] / S[2];
@@ -494,7 +494,7 @@ int osplat_shade(const double* cam, int W, int H, int x0, int y0, int w, int h,
                     double qx = floor(px), qy = floor(py);
                     int onscreen = front && qx >= 0 && qx < W && qy >= 0 && qy < H;
                     double fx = px - qx, fy = py - qy;
-                    int edge = (fmin(fx, 1 - fx) <= 1e-3) || (fmin(fy, 1 - fy) <= 1e-3);
+                    int edge = (fmin(fx, 1 - fx) <= edge_px) || (fmin(fy, 1 - fy) <= edge_px);
                     int in_buf = 0, ok = 0;
                     double zq = INFINITY;
                     if (onscreen) {
@@ -505,7 +505,7 @@ int osplat_shade(const double* cam, int W, int H, int x0, int y0, int w, int h,
                     }
                     double thr = S[2] - bias;
                     if (ok && zq <= thr && isfinite(zq)) occ += os_smooth(R / fabs(Pv[2] - zq));
-                    int margin = ok && fabs(zq - thr) <= 1e-5 * fabs(S[2]);
+                    int margin = ok && fabs(zq - thr) <= depth_rel * fabs(S[2]);
                     if ((front && edge) || near_edge || margin) ++uns;
                 }
             }

@@ -48,7 +48,7 @@ def lib():
                                    ctypes.c_int, ctypes.c_int, P, P, P, P,
                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
-                                   ctypes.c_int, P, P, P, P]
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P, P, P]
         _lib = L
     return _lib
 
@@ -115,7 +115,7 @@ def gbuffer(scene, cam, opts, W, H, window=None, nthreads=None):
 
 
 def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=None, depth_win=None,
-                  nthreads=None):
+                  nthreads=None, edge_px=1e-3, depth_rel=1e-5):
     x0, y0, w, h = window
     if depth_buf is None:
         depth_buf, depth_win = z, window
@@ -133,7 +133,7 @@ def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=Non
     rc = lib().osplat_shade(_ptr(ca), W, H, x0, y0, w, h, _ptr(zz), _ptr(nn), _ptr(al), _ptr(db),
                             bx0, by0, bw, bh, int(opts.ssao_samples), float(opts.ssao_radius),
                             float(opts.ssao_bias), int(opts.background) & 0xFFFFFFFF,
-                            nthreads or default_threads(),
+                            float(edge_px), float(depth_rel), nthreads or default_threads(),
                             _ptr(rgba), _ptr(ao), _ptr(uns), _ptr(outside))
     if rc != 0:
         raise RuntimeError(f"osplat_shade failed: {rc}")
@@ -141,7 +141,7 @@ def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=Non
                 ssao_outside=outside.reshape(h, w))
 
 
-def render(scene, cam, opts, W, H, window=None, halo=0, nthreads=None):
+def render(scene, cam, opts, W, H, window=None, halo=0, nthreads=None, edge_px=1e-3, depth_rel=1e-5):
     """G-buffer over the window grown by ``halo`` pixels, then SSAO + shading of the window."""
     if window is None:
         window = (0, 0, W, H)
@@ -154,6 +154,7 @@ def render(scene, cam, opts, W, H, window=None, halo=0, nthreads=None):
     inner = {k: (np.ascontiguousarray(v[sl]) if isinstance(v, np.ndarray) and v.ndim >= 2 else v)
              for k, v in g.items()}
     sh = shade_gbuffer(cam, opts, W, H, window, inner["z"], inner["normal_view"], inner["albedo"],
-                       depth_buf=g["z"], depth_win=gwin, nthreads=nthreads)
+                       depth_buf=g["z"], depth_win=gwin, nthreads=nthreads, edge_px=edge_px,
+                       depth_rel=depth_rel)
     inner.update(sh)
     return inner

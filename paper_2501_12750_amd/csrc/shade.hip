@@ -1,0 +1,193 @@
+// Deferred pass: screen-space ambient occlusion and shading over the G-buffer
+// (paper, Methods, "High Quality Rendering": a deferred shading pipeline
+// computes lighting on the surfaces and applies screen-space post-processes,
+// with ambient occlusion recomputed every frame because dynamic data cannot
+// be precomputed).
+//
+// The G-buffer is the (depth, id) pair the resolve writes.  Each pixel's view
+// position is rebuilt from its ray and depth, and its normal and colour from
+// the primitive named by id, so no normal or colour buffer is stored.  The
+// occlusion test of each hemisphere sample reads the depth at the sample's
+// pixel: a 16x16 tile with a 16-pixel halo is staged in LDS and samples that
+// land farther away read the depth buffer through the cache.
+#include "vtx_internal.h"
+
+namespace vtx {
+
+namespace {
+
+constexpr int kTile = 16;
+constexpr int kHalo = 16;
+constexpr int kSpan = kTile + 2 * kHalo;
+
+constexpr float kKa = 0.2f, kKd = 0.8f, kKs = 0.25f;
+
+__device__ inline float smooth01(float x) {
+    x = fminf(fmaxf(x, 0.0f), 1.0f);
+    return x * x * (3.0f - 2.0f * x);
+}
+
+__device__ inline uint32_t quantize(float c) {
+    c = fminf(fmaxf(c, 0.0f), 1.0f);
+    return (uint32_t)floorf(fmaf(255.0f, c, 0.5f));
+}
+
+__global__ void __launch_bounds__(kBlock) k_shade(Frame F, SampleKernel K, const float* __restrict__ pos,
+                                                  const float* __restrict__ rad, const uint32_t* __restrict__ col,
+                                                  const uint32_t* __restrict__ bonds,
+                                                  const float* __restrict__ depth, const uint32_t* __restrict__ ids,
+                                                  uint32_t* __restrict__ rgba, float* __restrict__ normal_out,
+                                                  uint32_t* __restrict__ albedo_out, float* __restrict__ ao_out) {
+    __shared__ float zt[kSpan * kSpan];
+    const int tiles_x = (F.W + kTile - 1) / kTile, tiles_y = (F.H + kTile - 1) / kTile;
+    const int T = tiles_x * tiles_y;
+    const int t = xcd_contiguous(blockIdx.x, T);
+    if (t >= T) return;
+    const int tid = threadIdx.x;
+    const int tx0 = (t % tiles_x) * kTile, ty0 = (t / tiles_x) * kTile;
+    const int bx0 = tx0 - kHalo, by0 = ty0 - kHalo;
+    if (K.count > 0) {
+        for (int i = tid; i < kSpan * kSpan; i += kBlock) {
+            const int yy = by0 + i / kSpan, xx = bx0 + i % kSpan;
+            zt[i] = (xx >= 0 && xx < F.W && yy >= 0 && yy < F.H) ? depth[(size_t)yy * F.W + xx] : INFINITY;
+        }
+        __syncthreads();
+    }
+    const int x = tx0 + (tid & (kTile - 1)), y = ty0 + (tid >> 4);
+    if (x >= F.W || y >= F.H) return;
+    const size_t p = (size_t)y * F.W + x;
+    const uint32_t pid = ids[p];
+    const float z = depth[p];
+    const uint32_t nprim = F.n_atoms + F.n_bonds;
+
+    const float ndx = fmaf((float)x + 0.5f, F.inv_w2, -1.0f);
+    const float ndy = fmaf(-((float)y + 0.5f), F.inv_h2, 1.0f);
+    float Px, Py, Vx, Vy, Vz;
+    if (F.proj == 0) {
+        const float Dx = ndx * F.txf, Dy = ndy * F.tyf;
+        Px = z * Dx;
+        Py = z * Dy;
+        const float inv = rsqrtf(fmaf(Dx, Dx, fmaf(Dy, Dy, 1.0f)));
+        Vx = -Dx * inv; Vy = -Dy * inv; Vz = -inv;
+    } else {
+        Px = ndx * F.hxf;
+        Py = ndy * F.hyf;
+        Vx = 0.f; Vy = 0.f; Vz = -1.f;
+    }
+    const float Pz = z;
+
+    bool hit = pid < nprim && z < INFINITY;
+    float nx = 0.f, ny = 0.f, nz = 0.f;
+    uint32_t alb = 0;
+    if (hit) {
+        if (pid < F.n_atoms) {
+            double cx, cy, cz;
+            to_view(F, pos[3 * (size_t)pid], pos[3 * (size_t)pid + 1], pos[3 * (size_t)pid + 2], cx, cy, cz);
+            nx = Px - (float)cx;
+            ny = Py - (float)cy;
+            nz = Pz - (float)cz;
+            alb = col[pid];
+        } else {
+            const size_t b = pid - F.n_atoms;
+            const uint32_t ia = bonds[2 * b], ib = bonds[2 * b + 1];
+            if (ia >= F.n_atoms || ib >= F.n_atoms) {
+                hit = false;
+            } else {
+                double A[3], B[3];
+                to_view(F, pos[3 * (size_t)ia], pos[3 * (size_t)ia + 1], pos[3 * (size_t)ia + 2], A[0], A[1], A[2]);
+                to_view(F, pos[3 * (size_t)ib], pos[3 * (size_t)ib + 1], pos[3 * (size_t)ib + 2], B[0], B[1], B[2]);
+                const double ex = B[0] - A[0], ey = B[1] - A[1], ez = B[2] - A[2];
+                const double Ld = sqrt(ex * ex + ey * ey + ez * ez);
+                const float ax = (float)(ex / Ld), ay = (float)(ey / Ld), az = (float)(ez / Ld), L = (float)Ld;
+                const float rx = Px - (float)A[0], ry = Py - (float)A[1], rz = Pz - (float)A[2];
+                const float s = fmaf(rx, ax, fmaf(ry, ay, rz * az));
+                const float qx = fmaf(-s, ax, rx), qy = fmaf(-s, ay, ry), qz = fmaf(-s, az, rz);
+                const float ql = sqrtf(fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
+                const float d_side = fabsf(ql - F.bond_radius), d_a = fabsf(s), d_b = fabsf(s - L);
+                if (d_side <= fminf(d_a, d_b)) {
+                    nx = qx; ny = qy; nz = qz;
+                    alb = s < 0.5f * L ? col[ia] : col[ib];
+                } else if (d_a <= d_b) {
+                    nx = -ax; ny = -ay; nz = -az;
+                    alb = col[ia];
+                } else {
+                    nx = ax; ny = ay; nz = az;
+                    alb = col[ib];
+                }
+            }
+        }
+        const float inv = rsqrtf(fmaf(nx, nx, fmaf(ny, ny, nz * nz)));
+        nx *= inv; ny *= inv; nz *= inv;
+    }
+
+    float ao = 1.0f;
+    if (hit && K.count > 0) {
+        // orthonormal basis from the normal (Duff et al., JCGT 2017, branchless form)
+        const float sg = copysignf(1.0f, nz);
+        const float a = -1.0f / (sg + nz);
+        const float bb = nx * ny * a;
+        const float Tx = 1.0f + sg * nx * nx * a, Ty = sg * bb, Tz = -sg * nx;
+        const float Bx = bb, By = sg + ny * ny * a, Bz = -ny;
+        const float fpx = 0.5f * (float)F.H / F.tyf;
+        const float osc = 0.5f * (float)F.H / F.hyf;
+        float occ = 0.0f;
+        for (int k = 0; k < K.count; ++k) {
+            const float4 h = K.h[k];
+            const float sr = K.radius * h.w;
+            const float dx = fmaf(h.x, Tx, fmaf(h.y, Bx, h.z * nx));
+            const float dy = fmaf(h.x, Ty, fmaf(h.y, By, h.z * ny));
+            const float dz = fmaf(h.x, Tz, fmaf(h.y, Bz, h.z * nz));
+            const float Sx = fmaf(sr, dx, Px), Sy = fmaf(sr, dy, Py), Sz = fmaf(sr, dz, Pz);
+            if (!(Sz > F.znear)) continue;
+            float spx, spy;
+            if (F.proj == 0) {
+                spx = fmaf(fpx, Sx / Sz, 0.5f * (float)F.W);
+                spy = fmaf(-fpx, Sy / Sz, 0.5f * (float)F.H);
+            } else {
+                spx = fmaf(Sx, osc, 0.5f * (float)F.W);
+                spy = fmaf(-Sy, osc, 0.5f * (float)F.H);
+            }
+            if (!(spx >= 0.0f && spx < (float)F.W && spy >= 0.0f && spy < (float)F.H)) continue;
+            const int qx = (int)spx, qy = (int)spy;
+            const int lx = qx - bx0, ly = qy - by0;
+            const float zq = (lx >= 0 && lx < kSpan && ly >= 0 && ly < kSpan) ? zt[ly * kSpan + lx]
+                                                                              : depth[(size_t)qy * F.W + qx];
+            if (zq <= Sz - K.bias) occ += smooth01(K.radius / fabsf(Pz - zq));
+        }
+        ao = 1.0f - occ / (float)K.count;
+    }
+
+    uint32_t out = K.background;
+    if (hit) {
+        const float nv = fmaxf(0.0f, fmaf(nx, Vx, fmaf(ny, Vy, nz * Vz)));
+        float sp = fmaxf(0.0f, fmaf(2.0f * nv, nv, -1.0f));
+        sp *= sp; sp *= sp; sp *= sp; sp *= sp; sp *= sp;     // ^32
+        const float spec = kKs * sp;
+        const float diff = fmaf(kKd, nv, kKa) * ao;
+        const float r = (float)(alb & 255u) * (1.0f / 255.0f);
+        const float g = (float)((alb >> 8) & 255u) * (1.0f / 255.0f);
+        const float bch = (float)((alb >> 16) & 255u) * (1.0f / 255.0f);
+        out = quantize(fmaf(r, diff, spec)) | (quantize(fmaf(g, diff, spec)) << 8) |
+              (quantize(fmaf(bch, diff, spec)) << 16) | (255u << 24);
+    }
+    rgba[p] = out;
+    if (normal_out) {
+        normal_out[3 * p] = nx;
+        normal_out[3 * p + 1] = ny;
+        normal_out[3 * p + 2] = nz;
+    }
+    if (albedo_out) albedo_out[p] = hit ? alb : 0u;
+    if (ao_out) ao_out[p] = ao;
+}
+
+}  // namespace
+
+hipError_t launch_shade(const Frame& F, const SampleKernel& K, const float* pos, const float* rad,
+                        const uint32_t* col, const uint32_t* bonds, const float* depth, const uint32_t* id,
+                        uint32_t* rgba, float* normal, uint32_t* albedo, float* ao, hipStream_t stream) {
+    const int tiles = ((F.W + kTile - 1) / kTile) * ((F.H + kTile - 1) / kTile);
+    k_shade<<<xcd_grid(tiles), kBlock, 0, stream>>>(F, K, pos, rad, col, bonds, depth, id, rgba, normal, albedo, ao);
+    return hipGetLastError();
+}
+
+}  // namespace vtx

@@ -1,0 +1,175 @@
+// Internal declarations of the HIP renderer: frame constants, device counters,
+// geometry helpers shared by the kernels, and the host launch wrappers.
+//
+// Method: paper, Methods, "Molecular Graphics Engine" (spheres for atoms,
+// cylinders for bonds, one screen footprint per primitive, then a ray-cast of
+// the implicit surface per pixel) and "High Quality Rendering" (deferred
+// shading with screen-space ambient occlusion).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vtx {
+
+constexpr int kBlock = 256;                  // threads per workgroup (4 waves of 64)
+constexpr uint32_t kBackground = 0xFFFFFFFFu;
+constexpr int kMaxSamples = 64;
+
+// Per-frame constants, passed by value to every kernel.
+struct Frame {
+    double eye[3], s[3], u[3], f[3];   // world -> view basis (x right, y up, z forward)
+    double tx, ty;                     // perspective: tan(fovy/2) * W/H, tan(fovy/2)
+    double hx, hy;                     // orthographic: h * W/H, h
+    float txf, tyf, hxf, hyf;
+    float inv_w2, inv_h2;              // 2/W, 2/H
+    float znear, zfar;
+    float bond_radius;
+    int32_t proj;                      // 0 perspective, 1 orthographic
+    int32_t W, H;
+    int32_t tile, tiles_x, tiles_y;
+    uint32_t n_atoms, n_bonds;
+    uint32_t flags;
+};
+
+// SSAO sample set (hemisphere direction xyz, radius scale w).
+struct SampleKernel {
+    float4 h[kMaxSamples];
+    int32_t count;
+    float radius, bias;
+    uint32_t background;
+};
+
+// Device-side counters of one frame.
+struct Counters {
+    unsigned int vis_count;
+    unsigned int overflow;
+    unsigned int bad_bonds;
+    unsigned int overflow_tiles;
+    unsigned long long pairs;
+    unsigned long long frag_tested;
+    unsigned long long frag_hit;
+    unsigned long long frag_hit_bond;
+};
+
+// ---------------------------------------------------------------------------
+// geometry helpers (device)
+// ---------------------------------------------------------------------------
+__device__ inline void to_view(const Frame& F, float px, float py, float pz, double& vx, double& vy,
+                               double& vz) {
+    const double rx = (double)px - F.eye[0], ry = (double)py - F.eye[1], rz = (double)pz - F.eye[2];
+    vx = rx * F.s[0] + ry * F.s[1] + rz * F.s[2];
+    vy = rx * F.u[0] + ry * F.u[1] + rz * F.u[2];
+    vz = rx * F.f[0] + ry * F.f[1] + rz * F.f[2];
+}
+
+// Interval of NDC coordinates along one image axis covered by a sphere of
+// view-space centre (c, vz) (c = x or y) and radius r.  Perspective: the two
+// planes through the eye tangent to the sphere have slopes
+// (c vz -+ r sqrt(c^2 + vz^2 - r^2)) / (vz^2 - r^2) when the sphere lies in
+// front of the eye plane; otherwise the footprint is unbounded.
+__device__ inline bool sphere_ndc_interval(const Frame& F, double c, double vz, double r, double tscale,
+                                           double hscale, double& lo, double& hi) {
+    if (F.proj == 0) {
+        if (!(vz > r)) return false;   // unbounded: caller uses the whole axis
+        const double den = vz * vz - r * r;
+        const double sq = r * sqrt(c * c + den);
+        lo = (c * vz - sq) / den / tscale;
+        hi = (c * vz + sq) / den / tscale;
+    } else {
+        lo = (c - r) / hscale;
+        hi = (c + r) / hscale;
+    }
+    return true;
+}
+
+// Inclusive pixel index range of the pixel centres whose NDC lies in [lo, hi]
+// along an axis of n pixels; `flip` for the y axis (row 0 at the top).
+__device__ inline void ndc_to_pixels(double lo, double hi, int n, bool flip, int& p0, int& p1) {
+    const double eps = 1e-3;
+    double a, b;
+    if (!flip) {
+        a = (lo + 1.0) * 0.5 * n;
+        b = (hi + 1.0) * 0.5 * n;
+    } else {
+        a = (1.0 - hi) * 0.5 * n;
+        b = (1.0 - lo) * 0.5 * n;
+    }
+    a = ceil(a - 0.5 - eps);
+    b = floor(b - 0.5 + eps);
+    a = fmax(a, 0.0);
+    b = fmin(b, (double)(n - 1));
+    p0 = (int)fmin(a, (double)n);
+    p1 = (int)fmax(b, -1.0);
+}
+
+// Conservative pixel rectangle of a sphere of view centre v and radius r.
+// Returns false when no pixel can hold a hit with znear <= z <= zfar.
+__device__ inline bool sphere_rect(const Frame& F, double vx, double vy, double vz, double r, int& x0,
+                                   int& y0, int& x1, int& y1) {
+    if (!(r > 0.0)) return false;
+    if (vz + r < F.znear || vz - r > F.zfar) return false;
+    double lo, hi;
+    if (sphere_ndc_interval(F, vx, vz, r, F.tx, F.hx, lo, hi)) ndc_to_pixels(lo, hi, F.W, false, x0, x1);
+    else { x0 = 0; x1 = F.W - 1; }
+    if (sphere_ndc_interval(F, vy, vz, r, F.ty, F.hy, lo, hi)) ndc_to_pixels(lo, hi, F.H, true, y0, y1);
+    else { y0 = 0; y1 = F.H - 1; }
+    return x0 <= x1 && y0 <= y1;
+}
+
+// Conservative pixel rectangle of a capped cylinder of radius rho between
+// view points A and B: it lies inside the capsule (the convex hull of the two
+// end balls), whose projection's bounding box is the union of the two balls'
+// boxes when both lie in front of the eye plane.
+__device__ inline bool bond_rect(const Frame& F, const double* A, const double* B, double rho, int& x0,
+                                 int& y0, int& x1, int& y1) {
+    const double zlo = fmin(A[2], B[2]) - rho, zhi = fmax(A[2], B[2]) + rho;
+    if (zhi < F.znear || zlo > F.zfar) return false;
+    if (F.proj == 0 && !(zlo > 0.0)) {
+        x0 = 0; y0 = 0; x1 = F.W - 1; y1 = F.H - 1;
+        return true;
+    }
+    double la, ha, lb, hb;
+    sphere_ndc_interval(F, A[0], A[2], rho, F.tx, F.hx, la, ha);
+    sphere_ndc_interval(F, B[0], B[2], rho, F.tx, F.hx, lb, hb);
+    ndc_to_pixels(fmin(la, lb), fmax(ha, hb), F.W, false, x0, x1);
+    sphere_ndc_interval(F, A[1], A[2], rho, F.ty, F.hy, la, ha);
+    sphere_ndc_interval(F, B[1], B[2], rho, F.ty, F.hy, lb, hb);
+    ndc_to_pixels(fmin(la, lb), fmax(ha, hb), F.H, true, y0, y1);
+    return x0 <= x1 && y0 <= y1;
+}
+
+// Hardware dispatch places workgroup b on XCD (b mod 8).  Give each XCD one
+// contiguous range of work items so neighbouring tiles share an L2.
+__device__ inline int xcd_contiguous(int b, int nblocks) {
+    const int per = (nblocks + 7) >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+inline int xcd_grid(int nblocks) { return ((nblocks + 7) >> 3) << 3; }
+
+// ---------------------------------------------------------------------------
+// host launch wrappers (one per kernel file)
+// ---------------------------------------------------------------------------
+struct BinBuffers {
+    uint32_t* tile_cnt;     // T
+    uint64_t* tile_off;     // T
+    uint32_t* tile_fill;    // T
+    uint32_t* vis_id;       // n_atoms + n_bonds
+    uint2* vis_rect;        // n_atoms + n_bonds, tile rectangle packed (x0 | y0 << 16, x1 | y1 << 16)
+    uint32_t* list;         // capacity entries
+    uint64_t capacity;
+    Counters* ctr;
+};
+
+// `marks`, when not null, holds events recorded before each kernel launch
+// (bin: clear, project, scan, scatter) for per-kernel timing.
+hipError_t launch_bin(const Frame& F, const float* pos, const float* rad, const uint32_t* bonds,
+                      const BinBuffers& bb, hipStream_t stream, hipEvent_t* marks = nullptr);
+hipError_t launch_resolve(const Frame& F, const float* pos, const float* rad, const uint32_t* bonds,
+                          const BinBuffers& bb, float* depth, uint32_t* id, hipStream_t stream);
+hipError_t launch_shade(const Frame& F, const SampleKernel& K, const float* pos, const float* rad,
+                        const uint32_t* col, const uint32_t* bonds, const float* depth, const uint32_t* id,
+                        uint32_t* rgba, float* normal, uint32_t* albedo, float* ao, hipStream_t stream);
+
+}  // namespace vtx

@@ -1,0 +1,272 @@
+"""Python binding of libvtx (include/vtx.h): argument marshalling only.
+
+Every function of the C ABI is exposed under the same name; all rendering
+work runs in the HIP kernels of libvtx.so.  Torch supplies device memory and
+streams: array arguments are CUDA (HIP) tensors or raw device addresses.
+There is no CPU fallback: importing this module without the built library
+raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libvtx.so")
+
+VTX_OK = 0
+VTX_EINVAL = -1
+VTX_ENOMEM = -2
+VTX_EHIP = -3
+VTX_EOVERFLOW = -4
+VTX_EBUSY = -5
+VTX_PERSPECTIVE = 0
+VTX_ORTHOGRAPHIC = 1
+VTX_BACKGROUND_ID = 0xFFFFFFFF
+VTX_MAX_PIXELS = 7680 * 4320
+VTX_MAX_SSAO_SAMPLES = 64
+VTX_FLAG_STATS = 1
+VTX_FLAG_TIMING = 2
+
+# Every symbol include/vtx.h declares.
+EXPORTS = ("vtx_render", "vtx_gbuffer", "vtx_shade", "vtx_read_stats", "vtx_set_bin_capacity",
+           "vtx_read_timings", "vtx_reset_timings", "vtx_release_scratch", "vtx_last_error", "vtx_version")
+
+
+class vtx_camera(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_float * 3), ("target", ctypes.c_float * 3), ("up", ctypes.c_float * 3),
+                ("fovy", ctypes.c_float), ("ortho_half_height", ctypes.c_float),
+                ("projection", ctypes.c_int32), ("znear", ctypes.c_float), ("zfar", ctypes.c_float)]
+
+
+class vtx_options(ctypes.Structure):
+    _fields_ = [("bond_radius", ctypes.c_float), ("ssao_samples", ctypes.c_int32),
+                ("ssao_radius", ctypes.c_float), ("ssao_bias", ctypes.c_float),
+                ("background", ctypes.c_uint32), ("tile_size", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class vtx_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("visible", "pairs", "fragments_tested", "fragments_hit",
+                                               "fragments_hit_bond", "overflow_tiles", "bin_capacity",
+                                               "bad_bonds")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class vtx_timings(ctypes.Structure):
+    _fields_ = [("frames", ctypes.c_uint64)] + [(k, ctypes.c_double) for k in (
+        "ms_clear", "ms_project", "ms_scan", "ms_scatter", "ms_resolve", "ms_shade")]
+
+    def as_dict(self):
+        return {k: (int(getattr(self, k)) if k == "frames" else float(getattr(self, k))) for k, _ in self._fields_}
+
+
+class VtxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"vtx error {code}: {msg}")
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2501_12750_amd.build` "
+                      "(the renderer has no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_CAM = ctypes.POINTER(vtx_camera)
+_OPT = ctypes.POINTER(vtx_options)
+
+_lib.vtx_render.restype = ctypes.c_int
+_lib.vtx_render.argtypes = [_P, _P, _P, _I64, _P, _I64, _CAM, _OPT, _I32, _I32, _P, _P, _P, _P]
+_lib.vtx_gbuffer.restype = ctypes.c_int
+_lib.vtx_gbuffer.argtypes = [_P, _P, _P, _I64, _P, _I64, _CAM, _OPT, _I32, _I32, _P, _P, _P]
+_lib.vtx_shade.restype = ctypes.c_int
+_lib.vtx_shade.argtypes = [_P, _P, _P, _I64, _P, _I64, _CAM, _OPT, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]
+_lib.vtx_read_stats.restype = ctypes.c_int
+_lib.vtx_read_stats.argtypes = [_P, ctypes.POINTER(vtx_stats)]
+_lib.vtx_set_bin_capacity.restype = ctypes.c_int
+_lib.vtx_set_bin_capacity.argtypes = [_P, ctypes.c_uint64]
+_lib.vtx_read_timings.restype = ctypes.c_int
+_lib.vtx_read_timings.argtypes = [_P, ctypes.POINTER(vtx_timings)]
+_lib.vtx_reset_timings.restype = ctypes.c_int
+_lib.vtx_reset_timings.argtypes = [_P]
+_lib.vtx_release_scratch.restype = ctypes.c_int
+_lib.vtx_release_scratch.argtypes = [_P]
+_lib.vtx_last_error.restype = ctypes.c_char_p
+_lib.vtx_last_error.argtypes = []
+_lib.vtx_version.restype = ctypes.c_char_p
+_lib.vtx_version.argtypes = []
+
+
+def _addr(x):
+    """Device address of a tensor (or an int address, or None -> NULL)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check(rc):
+    if rc != VTX_OK:
+        raise VtxError(rc, vtx_last_error())
+
+
+def camera_struct(cam) -> vtx_camera:
+    c = vtx_camera()
+    c.eye[:] = list(cam.eye)
+    c.target[:] = list(cam.target)
+    c.up[:] = list(cam.up)
+    c.fovy = cam.fovy
+    c.ortho_half_height = cam.ortho_half_height
+    c.projection = int(cam.projection)
+    c.znear = cam.znear
+    c.zfar = cam.zfar
+    return c
+
+
+def options_struct(opts) -> vtx_options:
+    o = vtx_options()
+    o.bond_radius = opts.bond_radius
+    o.ssao_samples = int(opts.ssao_samples)
+    o.ssao_radius = opts.ssao_radius
+    o.ssao_bias = opts.ssao_bias
+    o.background = int(opts.background) & 0xFFFFFFFF
+    o.tile_size = int(getattr(opts, "tile_size", 0))
+    o.flags = int(getattr(opts, "flags", 0))
+    return o
+
+
+def _cam_opt(cam, opts):
+    c = cam if isinstance(cam, vtx_camera) else camera_struct(cam)
+    o = None if opts is None else (opts if isinstance(opts, vtx_options) else options_struct(opts))
+    return ctypes.byref(c), (ctypes.byref(o) if o is not None else None), (c, o)
+
+
+def vtx_render(positions, radii, colors, n_atoms, bonds, n_bonds, cam, opts, W, H, rgba, depth, id,
+               stream=None):
+    cp, op, _keep = _cam_opt(cam, opts)
+    _check(_lib.vtx_render(_addr(positions), _addr(radii), _addr(colors), n_atoms, _addr(bonds), n_bonds,
+                           cp, op, W, H, _addr(rgba), _addr(depth), _addr(id), _stream(stream)))
+
+
+def vtx_gbuffer(positions, radii, colors, n_atoms, bonds, n_bonds, cam, opts, W, H, depth, id, stream=None):
+    cp, op, _keep = _cam_opt(cam, opts)
+    _check(_lib.vtx_gbuffer(_addr(positions), _addr(radii), _addr(colors), n_atoms, _addr(bonds), n_bonds,
+                            cp, op, W, H, _addr(depth), _addr(id), _stream(stream)))
+
+
+def vtx_shade(positions, radii, colors, n_atoms, bonds, n_bonds, cam, opts, W, H, depth, id, rgba,
+              normal=None, albedo=None, ao=None, stream=None):
+    cp, op, _keep = _cam_opt(cam, opts)
+    _check(_lib.vtx_shade(_addr(positions), _addr(radii), _addr(colors), n_atoms, _addr(bonds), n_bonds,
+                          cp, op, W, H, _addr(depth), _addr(id), _addr(rgba), _addr(normal), _addr(albedo),
+                          _addr(ao), _stream(stream)))
+
+
+def vtx_read_stats(stream=None) -> dict:
+    st = vtx_stats()
+    _check(_lib.vtx_read_stats(_stream(stream), ctypes.byref(st)))
+    return st.as_dict()
+
+
+def vtx_set_bin_capacity(entries, stream=None):
+    _check(_lib.vtx_set_bin_capacity(_stream(stream), int(entries)))
+
+
+def vtx_read_timings(stream=None) -> dict:
+    t = vtx_timings()
+    _check(_lib.vtx_read_timings(_stream(stream), ctypes.byref(t)))
+    return t.as_dict()
+
+
+def vtx_reset_timings(stream=None):
+    _check(_lib.vtx_reset_timings(_stream(stream)))
+
+
+def vtx_release_scratch(stream=None):
+    _check(_lib.vtx_release_scratch(_stream(stream)))
+
+
+def vtx_last_error() -> str:
+    return (_lib.vtx_last_error() or b"").decode()
+
+
+def vtx_version() -> str:
+    return (_lib.vtx_version() or b"").decode()
+
+
+# ---------------------------------------------------------------------------
+# convenience: scenes resident in device memory, outputs allocated by torch
+# ---------------------------------------------------------------------------
+class DeviceScene:
+    """Device copies (torch tensors) of a scene's arrays."""
+
+    def __init__(self, scene, device="cuda"):
+        import torch
+        self.n_atoms = int(scene.n_atoms)
+        self.n_bonds = int(scene.n_bonds)
+        self.positions = torch.from_numpy(np.ascontiguousarray(scene.positions, dtype=np.float32)).to(device)
+        self.radii = torch.from_numpy(np.ascontiguousarray(scene.radii, dtype=np.float32)).to(device)
+        self.colors = torch.from_numpy(np.ascontiguousarray(scene.colors, dtype=np.uint32).view(np.int32)).to(device)
+        b = np.ascontiguousarray(scene.bonds, dtype=np.uint32).reshape(-1, 2)
+        self.bonds = torch.from_numpy(b.view(np.int32)).to(device) if self.n_bonds else None
+
+    def args(self):
+        return (self.positions, self.radii, self.colors, self.n_atoms, self.bonds, self.n_bonds)
+
+
+class Frame:
+    """Output buffers of one W x H frame (torch tensors on the device)."""
+
+    def __init__(self, W, H, device="cuda", aux=False):
+        import torch
+        self.W, self.H = W, H
+        self.rgba = torch.empty((H, W), dtype=torch.int32, device=device)
+        self.depth = torch.empty((H, W), dtype=torch.float32, device=device)
+        self.id = torch.empty((H, W), dtype=torch.int32, device=device)
+        if aux:
+            self.normal = torch.empty((H, W, 3), dtype=torch.float32, device=device)
+            self.albedo = torch.empty((H, W), dtype=torch.int32, device=device)
+            self.ao = torch.empty((H, W), dtype=torch.float32, device=device)
+
+    def numpy(self):
+        out = {"rgba": self.rgba.cpu().numpy().view(np.uint32), "depth": self.depth.cpu().numpy(),
+               "id": self.id.cpu().numpy().view(np.uint32)}
+        if hasattr(self, "normal"):
+            out["normal"] = self.normal.cpu().numpy()
+            out["albedo"] = self.albedo.cpu().numpy().view(np.uint32)
+            out["ao"] = self.ao.cpu().numpy()
+        return out
+
+
+def render(dscene, cam, opts, W, H, frame=None, stream=None) -> Frame:
+    fr = frame if frame is not None else Frame(W, H)
+    vtx_render(*dscene.args(), cam, opts, W, H, fr.rgba, fr.depth, fr.id, stream)
+    return fr
+
+
+def gbuffer(dscene, cam, opts, W, H, frame=None, stream=None) -> Frame:
+    fr = frame if frame is not None else Frame(W, H)
+    vtx_gbuffer(*dscene.args(), cam, opts, W, H, fr.depth, fr.id, stream)
+    return fr
+
+
+def shade(dscene, cam, opts, W, H, frame, stream=None) -> Frame:
+    vtx_shade(*dscene.args(), cam, opts, W, H, frame.depth, frame.id, frame.rgba,
+              getattr(frame, "normal", None), getattr(frame, "albedo", None), getattr(frame, "ao", None), stream)
+    return frame

@@ -1,0 +1,243 @@
+"""Device renderer vs the CPU oracle, through the C ABI (needs an MI355X).
+
+Visibility (depth, id) is compared on every pixel with the accept-set rules;
+normals and albedo at strict pixels; the deferred pass both cross-fed (oracle
+SSAO + shading on the device's own G-buffer) and end to end.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import compare, osplat
+from paper_2501_12750_amd import scenes
+from tests.gpu_util import assert_clean, crop, run_device, run_render, windows, with_opts
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vtx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2501_12750_amd import vtx as v
+    return v
+
+
+def full_parity(vtx, wl, e2e_edge_px=0.02, check_shading=True, name=""):
+    sc, cam, opts, W, H = wl.scene, wl.camera, wl.options, wl.width, wl.height
+    ds = vtx.DeviceScene(sc)
+    dev = run_device(vtx, ds, cam, opts, W, H)
+    ref = osplat.render(sc, cam, opts, W, H, edge_px=e2e_edge_px, depth_rel=1e-4)
+    rep = compare.check_gbuffer(dev["depth"], dev["id"], ref)
+    rep.update(compare.check_surface(dev["normal"], dev["albedo"], ref, sc, opts))
+    if check_shading:
+        rep.update(compare.check_shading_crossfed(cam, opts, W, H, dev))
+        rep.update(compare.check_end_to_end(dev["rgba"], ref))
+    print(name, rep, flush=True)
+    assert_clean(rep, name)
+    assert rep["strict"] > 0.9 * rep["pixels"]
+    return dev, ref, rep
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_plain_small(vtx, tile):
+    wl = scenes.plain_small()
+    wl.options = with_opts(wl.options, tile_size=tile)
+    dev, ref, rep = full_parity(vtx, wl, name=f"plain_small tile={tile}")
+    assert rep["hits"] > 10000
+
+
+def test_ball_and_stick_small_ragged(vtx):
+    # 333 x 221: neither side a multiple of any tile size
+    wl = scenes.ball_and_stick(n_globules=27, atoms_per_globule=300, sigma=5.0, pitch=8.0,
+                               width=333, height=221, ssao_samples=16)
+    dev, ref, rep = full_parity(vtx, wl, name="ball_and_stick_small")
+    ids = dev["id"]
+    assert np.any((ids >= wl.scene.n_atoms) & (ids != 0xFFFFFFFF)), "no bond visible"
+    assert rep["shade_checked"] > 0.9 * rep["pixels"]
+
+
+def test_orthographic(vtx):
+    wl = scenes.ball_and_stick(n_globules=8, atoms_per_globule=300, sigma=4.0, pitch=6.0,
+                               width=200, height=150, ssao_samples=8)
+    c = wl.camera.target
+    wl.camera = scenes.Camera(eye=(c[0] + 5.0, c[1] + 60.0, c[2] + 7.0), target=c, up=(0, 0, 1),
+                              projection=scenes.ORTHOGRAPHIC, ortho_half_height=14.0)
+    full_parity(vtx, wl, name="orthographic")
+
+
+def _adversarial(kind, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "near":
+        c = rng.uniform([-6, -6, 2], [6, 6, 9], size=(60, 3))
+        r = rng.uniform(0.5, 3.0, size=60)
+        cam = scenes.Camera(eye=(0, 0, 12.0), target=(0, 0, 0), fovy=math.radians(70), znear=0.5)
+    elif kind == "eyeplane":
+        c = rng.uniform([-8, -8, 6], [8, 8, 16], size=(60, 3))
+        r = rng.uniform(0.5, 4.0, size=60)
+        cam = scenes.Camera(eye=(0, 0, 12.0), target=(0, 0, 0), fovy=math.radians(60), znear=1.5)
+    else:
+        c = rng.uniform(-30, 30, size=(400, 3))
+        r = rng.uniform(0.5, 2.5, size=400)
+        cam = scenes.Camera(eye=(0, 0, 25.0), target=(5, -3, 0), fovy=math.radians(100), znear=0.5)
+    n = c.shape[0]
+    bonds = np.stack([np.arange(0, n - 1, 2), np.arange(1, n, 2)], axis=1).astype(np.uint32)
+    sc = scenes.Scene(c.astype(np.float32), r.astype(np.float32),
+                      scenes.ELEMENT_COLOR[rng.integers(0, 5, n)].astype(np.uint32), bonds)
+    return scenes.Workload(kind, sc, cam, scenes.Options(bond_radius=0.7, ssao_samples=8), 240, 180)
+
+
+@pytest.mark.parametrize("kind", ["near", "eyeplane", "wide"])
+def test_adversarial_footprints(vtx, kind):
+    full_parity(vtx, _adversarial(kind, 21), name=kind)
+
+
+def test_bin_overflow_is_exact(vtx):
+    import torch
+    wl = scenes.ball_and_stick(n_globules=8, atoms_per_globule=300, sigma=4.0, pitch=6.0,
+                               width=256, height=192, ssao_samples=0)
+    ds = vtx.DeviceScene(wl.scene)
+    s = torch.cuda.Stream()
+    base = run_device(vtx, ds, wl.camera, wl.options, wl.width, wl.height, aux=False, stream=s)
+    st0 = vtx.vtx_read_stats(s)
+    assert st0["overflow_tiles"] == 0
+    vtx.vtx_set_bin_capacity(64, s)
+    small = run_device(vtx, ds, wl.camera, wl.options, wl.width, wl.height, aux=False, stream=s)
+    st1 = vtx.vtx_read_stats(s)
+    vtx.vtx_set_bin_capacity(0, s)
+    assert st1["overflow_tiles"] > 0 and st1["bin_capacity"] == 64
+    for k in ("depth", "id", "rgba"):
+        assert np.array_equal(base[k], small[k]), k
+    again = run_device(vtx, ds, wl.camera, wl.options, wl.width, wl.height, aux=False, stream=s)
+    assert vtx.vtx_read_stats(s)["overflow_tiles"] == 0
+    assert np.array_equal(base["id"], again["id"])
+
+
+def test_permutation_and_determinism(vtx):
+    wl = scenes.ball_and_stick(n_globules=8, atoms_per_globule=300, sigma=4.0, pitch=6.0,
+                               width=300, height=200, ssao_samples=16)
+    sc = wl.scene
+    ds = vtx.DeviceScene(sc)
+    a = run_render(vtx, ds, wl.camera, wl.options, wl.width, wl.height)
+    b = run_render(vtx, ds, wl.camera, wl.options, wl.width, wl.height)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    rng = np.random.default_rng(5)
+    pa, pb = rng.permutation(sc.n_atoms), rng.permutation(sc.n_bonds)
+    sp = sc.permuted(pa, pb)
+    c = run_render(vtx, vtx.DeviceScene(sp), wl.camera, wl.options, wl.width, wl.height)
+    assert np.array_equal(a["depth"], c["depth"])
+    N = sc.n_atoms
+    ids = c["id"].astype(np.int64)
+    mapped = np.where(ids == 0xFFFFFFFF, 0xFFFFFFFF,
+                      np.where(ids < N, pa[np.minimum(ids, N - 1)], N + pb[np.clip(ids - N, 0, pb.size - 1)]))
+    same = mapped == a["id"].astype(np.int64)
+    # only exact depth ties may map differently
+    assert same.mean() > 0.999
+
+
+def test_edge_cases(vtx):
+    import torch
+    cam = scenes.Camera(eye=(0, 0, 30.0), target=(0, 0, 0))
+    opts = scenes.Options(ssao_samples=4, background=scenes.pack_rgba(1, 2, 3, 4))
+    # empty scene
+    empty = scenes.Scene(np.zeros((0, 3), np.float32), np.zeros(0, np.float32), np.zeros(0, np.uint32),
+                         np.zeros((0, 2), np.uint32))
+    d = run_render(vtx, vtx.DeviceScene(empty), cam, opts, 37, 23)
+    assert np.all(d["id"] == 0xFFFFFFFF) and np.all(np.isinf(d["depth"])) and np.all(d["rgba"] == opts.background)
+    # 1 x 1 image, a single atom on the axis
+    one = scenes.Scene(np.zeros((1, 3), np.float32), np.ones(1, np.float32),
+                       np.array([scenes.ELEMENT_COLOR[0]], np.uint32), np.zeros((0, 2), np.uint32))
+    d = run_render(vtx, vtx.DeviceScene(one), cam, opts, 1, 1)
+    assert d["id"][0, 0] == 0 and abs(d["depth"][0, 0] - 29.0) <= 29.0 * 1e-5
+    # every atom at one point: all tie, smallest id wins
+    pile = scenes.Scene(np.full((5000, 3), 0.25, np.float32), np.full(5000, 2.0, np.float32),
+                        np.full(5000, scenes.ELEMENT_COLOR[1], np.uint32), np.zeros((0, 2), np.uint32))
+    d = run_render(vtx, vtx.DeviceScene(pile), cam, opts, 64, 64)
+    hit = d["id"] != 0xFFFFFFFF
+    assert hit.sum() > 20 and np.all(d["id"][hit] == 0)
+    # bad and degenerate bonds: skipped, counted
+    pos = np.array([[0, 0.1, 0], [0, 0.1, 0], [3, 0.1, 0]], np.float32)
+    bonds = np.array([[0, 1], [1, 1], [0, 7], [0, 2]], np.uint32)
+    sc = scenes.Scene(pos, np.full(3, 0.2, np.float32), np.full(3, scenes.ELEMENT_COLOR[2], np.uint32), bonds)
+    s = torch.cuda.Stream()
+    ds = vtx.DeviceScene(sc)
+    fr = vtx.Frame(96, 64)
+    vtx.vtx_render(*ds.args(), cam, with_opts(opts, bond_radius=0.5), 96, 64, fr.rgba, fr.depth, fr.id, s)
+    st = vtx.vtx_read_stats(s)
+    assert st["bad_bonds"] == 1
+    ids = fr.numpy()["id"]
+    assert np.any(ids == 3 + 3) and not np.any((ids >= 3) & (ids < 3 + 3))
+    # camera inside a huge sphere sees through it
+    inside = scenes.Scene(np.array([[0, 0, 30.0], [0, 0, 0]], np.float32), np.array([50.0, 1.0], np.float32),
+                          np.full(2, scenes.ELEMENT_COLOR[0], np.uint32), np.zeros((0, 2), np.uint32))
+    d = run_render(vtx, vtx.DeviceScene(inside), cam, opts, 48, 48)
+    assert not np.any(d["id"] == 0) and np.any(d["id"] == 1)
+
+
+def test_invalid_arguments_raise(vtx):
+    wl = scenes.plain_small(n_atoms=10, width=8, height=8)
+    ds = vtx.DeviceScene(wl.scene)
+    fr = vtx.Frame(8, 8)
+    with pytest.raises(vtx.VtxError):
+        vtx.vtx_render(*ds.args(), wl.camera, wl.options, 0, 8, fr.rgba, fr.depth, fr.id)
+    with pytest.raises(vtx.VtxError):
+        vtx.vtx_render(*ds.args(), wl.camera, with_opts(wl.options, tile_size=12), 8, 8, fr.rgba, fr.depth, fr.id)
+    with pytest.raises(vtx.VtxError):
+        vtx.vtx_render(*ds.args(), wl.camera, wl.options, 8, 8, None, fr.depth, fr.id)
+
+
+def test_fragment_count_matches_oracle(vtx):
+    import torch
+    wl = scenes.plain_small()
+    opts = with_opts(wl.options, flags=vtx.VTX_FLAG_STATS)
+    s = torch.cuda.Stream()
+    ds = vtx.DeviceScene(wl.scene)
+    fr = vtx.Frame(wl.width, wl.height)
+    vtx.vtx_render(*ds.args(), wl.camera, opts, wl.width, wl.height, fr.rgba, fr.depth, fr.id, s)
+    st = vtx.vtx_read_stats(s)
+    ref = osplat.gbuffer(wl.scene, wl.camera, wl.options, wl.width, wl.height)
+    assert abs(st["fragments_hit"] - ref["fragments"]) <= max(10, 1e-4 * ref["fragments"])
+    assert st["fragments_tested"] >= st["fragments_hit"]
+    # the early-outs do not change the image
+    plain = run_render(vtx, ds, wl.camera, wl.options, wl.width, wl.height)
+    assert np.array_equal(plain["id"], fr.numpy()["id"])
+
+
+def test_ball_and_stick_full_size_sampled(vtx):
+    """1M atoms + ~1.05M bonds at 1920x1080 with SSAO 16, in the benchmark's
+    launch configuration; windows of the frame against the oracle's crops."""
+    wl = scenes.ball_and_stick()
+    sc, cam, opts, W, H = wl.scene, wl.camera, wl.options, wl.width, wl.height
+    ds = vtx.DeviceScene(sc)
+    dev = run_device(vtx, ds, cam, opts, W, H)
+    rep_x = compare.check_shading_crossfed(cam, opts, W, H, dev)
+    print("crossfed", rep_x, flush=True)
+    assert_clean(rep_x, "crossfed")
+    for win in windows(W, H, 64, 6, seed=1) + [(W // 2 - 32, H // 2 - 32, 64, 64)]:
+        ref = osplat.render(sc, cam, opts, W, H, window=win, halo=24, edge_px=0.02, depth_rel=1e-4)
+        dv = crop(dev, win)
+        rep = compare.check_gbuffer(dv["depth"], dv["id"], ref)
+        rep.update(compare.check_surface(dv["normal"], dv["albedo"], ref, sc, opts))
+        rep.update(compare.check_end_to_end(dv["rgba"], ref))
+        print(win, rep, flush=True)
+        assert_clean(rep, str(win))
+
+
+def test_whole_cell_10m_sampled(vtx):
+    """Whole-cell generator at 10M atoms and 4K: windows against the oracle."""
+    wl = scenes.whole_cell(n_atoms=10_000_000)
+    sc, cam, opts, W, H = wl.scene, wl.camera, wl.options, wl.width, wl.height
+    ds = vtx.DeviceScene(sc)
+    dev = run_device(vtx, ds, cam, opts, W, H)
+    hit = dev["id"] != 0xFFFFFFFF
+    assert hit.mean() > 0.05
+    for win in windows(W, H, 48, 5, seed=2):
+        ref = osplat.render(sc, cam, opts, W, H, window=win, halo=48, edge_px=0.05, depth_rel=1e-4)
+        dv = crop(dev, win)
+        rep = compare.check_gbuffer(dv["depth"], dv["id"], ref)
+        rep.update(compare.check_surface(dv["normal"], dv["albedo"], ref, sc, opts))
+        rep.update(compare.check_end_to_end(dv["rgba"], ref))
+        print(win, rep, flush=True)
+        assert_clean(rep, str(win))
