@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="tile size (0 = library default)")
     ap.add_argument("--latency-frames", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="before timing, run one device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the renderer has no multi-GPU path "
@@ -102,6 +104,15 @@ def main():
     ids = frame.id.cpu().numpy().view(np.uint32)
     hit_px = int(np.count_nonzero(ids != 0xFFFFFFFF))
     log(f"stats {st}, hit pixels {hit_px}")
+
+    if args.calibrate_copy_mb:
+        src = torch.empty(args.calibrate_copy_mb << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calibrate_copy_mb} MiB done")
+        del src, dst
 
     opts_t = dataclasses.replace(wl.options, flags=vtx.VTX_FLAG_TIMING)
     for _ in range(args.warmup):
@@ -176,8 +187,9 @@ def main():
                    "ssao_samples": K, "tile_size": wl.options.tile_size or 16},
         "atom_fragments_per_s": round(f_total * fps, 1),
         "atom_fragments": f_total,
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                       "p99": round(float(np.percentile(lat, 99)), 4), "frames": int(lat.size)},
+        "latency_ms": ({"p50": round(float(np.percentile(lat, 50)), 4),
+                        "p99": round(float(np.percentile(lat, 99)), 4), "frames": int(lat.size)}
+                       if lat.size else None),
         "kernels": kern,
         "roofline": roof,
         "bins": {"visible": st["visible"], "pairs": st["pairs"], "overflow_tiles": st_after["overflow_tiles"]},

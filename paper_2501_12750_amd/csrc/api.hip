@@ -54,6 +54,8 @@ struct Workspace {
     BinBuffers bb{};
     size_t tiles_cap = 0;
     size_t vis_cap = 0;
+    size_t groups_cap = 0;
+    size_t hist_cap = 0;
     size_t list_alloc = 0;          // allocated bin entries (>= bb.capacity, the entries in use)
     Counters* host_ctr = nullptr;
     hipEvent_t done = nullptr;
@@ -81,7 +83,13 @@ int free_ws_buffers(Workspace* ws) {
     hipFree(ws->bb.tile_fill);
     hipFree(ws->bb.vis_id);
     hipFree(ws->bb.vis_rect);
+    hipFree(ws->bb.vis_cnt);
+    hipFree(ws->bb.hist);
     hipFree(ws->bb.list);
+    ws->bb.vis_cnt = nullptr;
+    ws->bb.hist = nullptr;
+    ws->groups_cap = 0;
+    ws->hist_cap = 0;
     ws->bb.tile_cnt = nullptr;
     ws->bb.tile_off = nullptr;
     ws->bb.tile_fill = nullptr;
@@ -208,12 +216,27 @@ int ensure_buffers(Workspace* ws, int T, uint64_t nprim) {
         if ((rc = grow(&ws->bb.tile_fill, c3, (size_t)T, ws->stream, "tile cursors"))) return rc;
         ws->tiles_cap = (size_t)T;
     }
-    const size_t nv = nprim > 0 ? (size_t)nprim : 1;
+    uint32_t groups, chunk;
+    vtx::bin_grid(nprim, &groups, &chunk);
+    ws->bb.groups = groups;
+    ws->bb.chunk = chunk;
+    const size_t nv = (size_t)groups * chunk;
     if (nv > ws->vis_cap || !ws->bb.vis_id) {
         size_t c1 = ws->vis_cap, c2 = ws->vis_cap;
         if ((rc = grow(&ws->bb.vis_id, c1, nv, ws->stream, "visible list"))) return rc;
         if ((rc = grow(&ws->bb.vis_rect, c2, nv, ws->stream, "visible rectangles"))) return rc;
         ws->vis_cap = nv;
+    }
+    if ((size_t)groups > ws->groups_cap || !ws->bb.vis_cnt) {
+        size_t c1 = ws->groups_cap;
+        if ((rc = grow(&ws->bb.vis_cnt, c1, (size_t)vtx::kMaxBinGroups, ws->stream, "visible counts"))) return rc;
+        ws->groups_cap = vtx::kMaxBinGroups;
+    }
+    const size_t nh = (size_t)groups * (size_t)T;
+    if (nh > ws->hist_cap || !ws->bb.hist) {
+        size_t c1 = ws->hist_cap;
+        if ((rc = grow(&ws->bb.hist, c1, nh, ws->stream, "tile histograms"))) return rc;
+        ws->hist_cap = nh;
     }
     uint64_t want = ws->want_capacity;
     if (want == 0) {
@@ -253,8 +276,8 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
         return fail(VTX_EINVAL, "ssao_samples must be in 0..%d", VTX_MAX_SSAO_SAMPLES);
     if (o.ssao_samples > 0 && (!(o.ssao_radius >= 0.0f) || !std::isfinite(o.ssao_radius) || !std::isfinite(o.ssao_bias)))
         return fail(VTX_EINVAL, "ssao radius/bias must be finite, radius >= 0");
-    if (o.tile_size != 0 && o.tile_size != 8 && o.tile_size != 16 && o.tile_size != 32)
-        return fail(VTX_EINVAL, "tile_size must be 0, 8, 16 or 32");
+    if (o.tile_size != 0 && o.tile_size != 8 && o.tile_size != 16 && o.tile_size != 32 && o.tile_size != 64)
+        return fail(VTX_EINVAL, "tile_size must be 0, 8, 16, 32 or 64");
 
     double e[3], f[3], up[3], s[3], u[3];
     for (int k = 0; k < 3; ++k) {
@@ -300,7 +323,12 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
     F->proj = cam->projection;
     F->W = W;
     F->H = H;
-    F->tile = o.tile_size ? o.tile_size : 16;
+    // the binner keeps one tile histogram per workgroup in LDS: raise the tile
+    // size until the tile grid fits it
+    int ts = o.tile_size ? o.tile_size : 16;
+    while ((int64_t)((W + ts - 1) / ts) * ((H + ts - 1) / ts) > vtx::kMaxLdsTiles) ts *= 2;
+    if (ts > 64) return fail(VTX_EINVAL, "image %dx%d needs more than %d tiles of 64 pixels", W, H, vtx::kMaxLdsTiles);
+    F->tile = ts;
     F->tiles_x = (W + F->tile - 1) / F->tile;
     F->tiles_y = (H + F->tile - 1) / F->tile;
     F->n_atoms = (uint32_t)n;

@@ -1,17 +1,24 @@
-// Screen-tile binning of atoms and bonds (a prefix-sum binner).
+// Screen-tile binning of atoms and bonds: a counting sort by tile.
 //
 // The paper rasterizes one screen quad per primitive and lets the fixed
 // function rasterizer find the pixels it covers (Methods, "Meshless
 // Representations").  Here the quad's role, a conservative footprint, becomes
-// an exact tile rectangle computed per primitive, and the rasterizer becomes
-// three compute passes:
-//   project  each primitive -> view space (FP64), cull, footprint rectangle,
-//            one count per covered tile, compacted list of visible primitives;
+// an exact tile rectangle per primitive, and the rasterizer becomes a
+// counting sort of (tile, primitive) pairs:
+//   count    G workgroups each own a contiguous run of primitives: view
+//            transform (FP64), culling, footprint rectangle, a compacted
+//            per-workgroup list of the visible ones, and a tile histogram
+//            in LDS; the histogram row is stored and its non-zero entries are
+//            added to the global tile counts (one atomic per touched tile);
 //   scan     exclusive prefix sum of the tile counts -> list offsets;
-//   scatter  each visible primitive id into the lists of its tiles.
-// Lists that would not fit the bin capacity are left empty; the resolve pass
-// finds their tiles from the compacted visible list instead, so every frame
-// is exact whatever the capacity.
+//   scatter  each workgroup reserves, per touched tile, one run of the
+//            tile's list (one atomic), then places its primitives with LDS
+//            atomics.
+// So the global atomics scale with (workgroup, touched tile) pairs rather
+// than with (primitive, tile) pairs.  Lists that would not fit the bin
+// capacity are left empty; the resolve pass then finds those tiles' primitives
+// in the per-workgroup visible lists, so every frame is exact whatever the
+// capacity.
 #include "vtx_internal.h"
 
 namespace vtx {
@@ -49,35 +56,56 @@ __device__ inline bool primitive_rect(const Frame& F, uint32_t p, const float* _
     return bond_rect(F, A, B, (double)F.bond_radius, x0, y0, x1, y1);
 }
 
-// One lane per primitive.  Visible primitives get a slot in the compacted
-// list (one atomic per wave), and every tile of their rectangle one count.
-__global__ void __launch_bounds__(kBlock) k_project(Frame F, const float* __restrict__ pos,
-                                                    const float* __restrict__ rad,
-                                                    const uint32_t* __restrict__ bonds, uint32_t* tile_cnt,
-                                                    uint32_t* vis_id, uint2* vis_rect, Counters* ctr) {
+__global__ void __launch_bounds__(kBinThreads) k_count(Frame F, const float* __restrict__ pos,
+                                                       const float* __restrict__ rad,
+                                                       const uint32_t* __restrict__ bonds, uint32_t chunk,
+                                                       uint32_t* __restrict__ vis_id, uint2* __restrict__ vis_rect,
+                                                       uint32_t* __restrict__ vis_cnt, uint32_t* __restrict__ hist_out,
+                                                       uint32_t* __restrict__ tile_cnt, Counters* ctr) {
+    extern __shared__ uint32_t hist[];
+    __shared__ uint32_t local_n;
+    const int T = F.tiles_x * F.tiles_y;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < T; t += kBinThreads) hist[t] = 0;
+    if (tid == 0) local_n = 0;
+    __syncthreads();
+
     const uint64_t total = (uint64_t)F.n_atoms + F.n_bonds;
+    const uint64_t start = (uint64_t)blockIdx.x * chunk;
+    const uint64_t end = min(total, start + chunk);
     const int ts = F.tile;
-    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < total;
-         base += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t p = base + threadIdx.x;
+    uint32_t bad_count = 0;
+    for (uint64_t base = start; base < end; base += kBinThreads) {
+        const uint64_t p = base + tid;
         int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
         bool bad = false;
-        const bool vis = p < total && primitive_rect(F, (uint32_t)p, pos, rad, bonds, x0, y0, x1, y1, bad);
+        const bool vis = p < end && primitive_rect(F, (uint32_t)p, pos, rad, bonds, x0, y0, x1, y1, bad);
+        bad_count += bad ? 1u : 0u;
         const unsigned long long vmask = __ballot(vis);
-        const unsigned long long bmask = __ballot(bad);
         uint32_t slot_base = 0;
         const int leader = __ffsll((long long)(vmask | 1ull)) - 1;
-        if (vmask && (int)__lane_id() == leader) slot_base = atomicAdd(&ctr->vis_count, (uint32_t)__popcll(vmask));
-        if (bmask && __lane_id() == 0) atomicAdd(&ctr->bad_bonds, (uint32_t)__popcll(bmask));
+        if (vmask && (int)__lane_id() == leader) slot_base = atomicAdd(&local_n, (uint32_t)__popcll(vmask));
         slot_base = __shfl(slot_base, leader);
         if (vis) {
-            const uint32_t slot = slot_base + (uint32_t)__popcll(vmask & __lanemask_lt());
+            const uint64_t slot = start + slot_base + (uint32_t)__popcll(vmask & __lanemask_lt());
             const int tx0 = x0 / ts, tx1 = x1 / ts, ty0 = y0 / ts, ty1 = y1 / ts;
             vis_id[slot] = (uint32_t)p;
-            vis_rect[slot] = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
+            vis_rect[slot] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
             for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&tile_cnt[ty * F.tiles_x + tx], 1u);
+                for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&hist[ty * F.tiles_x + tx], 1u);
         }
+    }
+    if (bad_count) atomicAdd(&ctr->bad_bonds, bad_count);
+    __syncthreads();
+    uint32_t* row = hist_out + (size_t)blockIdx.x * T;
+    for (int t = tid; t < T; t += kBinThreads) {
+        const uint32_t h = hist[t];
+        row[t] = h;
+        if (h) atomicAdd(&tile_cnt[t], h);
+    }
+    if (tid == 0) {
+        vis_cnt[blockIdx.x] = local_n;
+        atomicAdd(&ctr->vis_count, local_n);
     }
 }
 
@@ -114,52 +142,76 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(const uint32_t* __restric
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_scatter(Frame F, const uint32_t* __restrict__ vis_id,
-                                                    const uint2* __restrict__ vis_rect,
-                                                    const uint32_t* __restrict__ cnt,
-                                                    const uint64_t* __restrict__ off, uint32_t* fill,
-                                                    uint32_t* list, uint64_t capacity, const Counters* ctr) {
-    const uint32_t nvis = ctr->vis_count;
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nvis; k += gridDim.x * blockDim.x) {
-        const uint32_t id = vis_id[k];
-        const uint2 r = vis_rect[k];
-        const int tx0 = r.x & 0xFFFF, ty0 = r.x >> 16, tx1 = r.y & 0xFFFF, ty1 = r.y >> 16;
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx) {
+constexpr uint32_t kNoRun = 0xFFFFFFFFu;
+
+__global__ void __launch_bounds__(kBinThreads) k_scatter(Frame F, uint32_t chunk, const uint32_t* __restrict__ vis_id,
+                                                         const uint2* __restrict__ vis_rect,
+                                                         const uint32_t* __restrict__ vis_cnt,
+                                                         const uint32_t* __restrict__ hist_in,
+                                                         const uint32_t* __restrict__ cnt,
+                                                         const uint64_t* __restrict__ off, uint32_t* fill,
+                                                         uint2* __restrict__ list, uint64_t capacity) {
+    extern __shared__ uint32_t cur[];
+    const int T = F.tiles_x * F.tiles_y;
+    const int tid = threadIdx.x;
+    const uint32_t* row = hist_in + (size_t)blockIdx.x * T;
+    for (int t = tid; t < T; t += kBinThreads) {
+        const uint32_t h = row[t];
+        const uint64_t o = off[t];
+        uint32_t c = kNoRun;
+        if (h && o + cnt[t] <= capacity) c = (uint32_t)(o + atomicAdd(&fill[t], h));
+        cur[t] = c;
+    }
+    __syncthreads();
+    const uint32_t n = vis_cnt[blockIdx.x];
+    const uint64_t start = (uint64_t)blockIdx.x * chunk;
+    const int ts = F.tile;
+    for (uint32_t k = tid; k < n; k += kBinThreads) {
+        const uint32_t id = vis_id[start + k];
+        const uint2 r = vis_rect[start + k];
+        const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16;
+        for (int ty = y0 / ts; ty <= y1 / ts; ++ty)
+            for (int tx = x0 / ts; tx <= x1 / ts; ++tx) {
                 const int t = ty * F.tiles_x + tx;
-                const uint64_t o = off[t];
-                if (o + cnt[t] <= capacity) {
-                    const uint32_t slot = atomicAdd(&fill[t], 1u);
-                    list[o + slot] = id;
-                }
+                if (cur[t] == kNoRun) continue;
+                // the footprint clipped to this tile, in tile-local pixels
+                const int lx0 = max(x0 - tx * ts, 0), ly0 = max(y0 - ty * ts, 0);
+                const int lx1 = min(x1 - tx * ts, ts - 1), ly1 = min(y1 - ty * ts, ts - 1);
+                const uint32_t lr = (uint32_t)lx0 | ((uint32_t)ly0 << 8) | ((uint32_t)(lx1 - lx0 + 1) << 16) |
+                                    ((uint32_t)(ly1 - ly0 + 1) << 24);
+                list[atomicAdd(&cur[t], 1u)] = make_uint2(id, lr);
             }
     }
 }
 
 }  // namespace
 
+void bin_grid(uint64_t nprim, uint32_t* groups, uint32_t* chunk) {
+    uint64_t g = (nprim + 4095) / 4096;
+    if (g < 1) g = 1;
+    if (g > kMaxBinGroups) g = kMaxBinGroups;
+    uint64_t c = (nprim + g - 1) / g;
+    if (c < 1) c = 1;
+    *groups = (uint32_t)g;
+    *chunk = (uint32_t)c;
+}
+
 hipError_t launch_bin(const Frame& F, const float* pos, const float* rad, const uint32_t* bonds,
                       const BinBuffers& bb, hipStream_t stream, hipEvent_t* marks) {
     const int T = F.tiles_x * F.tiles_y;
+    if (T > kMaxLdsTiles) return hipErrorInvalidValue;
     const int nclear = T > 64 ? T : 64;
+    const size_t lds = (size_t)T * sizeof(uint32_t);
     if (marks) (void)hipEventRecord(marks[0], stream);
     k_clear<<<(nclear + kBlock - 1) / kBlock, kBlock, 0, stream>>>(bb.tile_cnt, T, bb.ctr);
-    const uint64_t total = (uint64_t)F.n_atoms + F.n_bonds;
     if (marks) (void)hipEventRecord(marks[1], stream);
-    if (total > 0) {
-        const uint64_t want = (total + kBlock - 1) / kBlock;
-        const int grid = (int)(want < 8192 ? want : 8192);
-        k_project<<<grid, kBlock, 0, stream>>>(F, pos, rad, bonds, bb.tile_cnt, bb.vis_id, bb.vis_rect, bb.ctr);
-    }
+    k_count<<<bb.groups, kBinThreads, lds, stream>>>(F, pos, rad, bonds, bb.chunk, bb.vis_id, bb.vis_rect, bb.vis_cnt,
+                                                     bb.hist, bb.tile_cnt, bb.ctr);
     if (marks) (void)hipEventRecord(marks[2], stream);
     k_scan<<<1, kScanThreads, 0, stream>>>(bb.tile_cnt, bb.tile_off, bb.tile_fill, T, bb.capacity, bb.ctr);
     if (marks) (void)hipEventRecord(marks[3], stream);
-    if (total > 0) {
-        const uint64_t want = (total + kBlock - 1) / kBlock;
-        const int grid = (int)(want < 4096 ? want : 4096);
-        k_scatter<<<grid, kBlock, 0, stream>>>(F, bb.vis_id, bb.vis_rect, bb.tile_cnt, bb.tile_off,
-                                                bb.tile_fill, bb.list, bb.capacity, bb.ctr);
-    }
+    k_scatter<<<bb.groups, kBinThreads, lds, stream>>>(F, bb.chunk, bb.vis_id, bb.vis_rect, bb.vis_cnt, bb.hist,
+                                                       bb.tile_cnt, bb.tile_off, bb.tile_fill, bb.list, bb.capacity);
     return hipGetLastError();
 }
 

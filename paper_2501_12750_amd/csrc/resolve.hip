@@ -102,9 +102,11 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Frame F, const float* __rest
                                                     const uint32_t* __restrict__ bonds,
                                                     const uint32_t* __restrict__ cnt,
                                                     const uint64_t* __restrict__ off,
-                                                    const uint32_t* __restrict__ list, uint64_t capacity,
+                                                    const uint2* __restrict__ list, uint64_t capacity,
                                                     const uint32_t* __restrict__ vis_id,
-                                                    const uint2* __restrict__ vis_rect, Counters* ctr,
+                                                    const uint2* __restrict__ vis_rect,
+                                                    const uint32_t* __restrict__ vis_cnt, uint32_t chunk,
+                                                    uint32_t groups, Counters* ctr,
                                                     float* __restrict__ depth, uint32_t* __restrict__ out_id) {
     __shared__ unsigned long long keys[TS * TS];
     __shared__ Rec recs[kChunk];
@@ -123,8 +125,9 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Frame F, const float* __rest
 
     const uint32_t n = cnt[t];
     const uint64_t o = off[t];
+    // a tile whose list did not fit the bins scans every workgroup's visible list
     const bool overflow = o + n > capacity;
-    const uint32_t nsrc = overflow ? ctr->vis_count : n;
+    const uint64_t nsrc = overflow ? (uint64_t)groups * chunk : n;
     if (overflow && tid == 0) atomicAdd(&ctr->overflow_tiles, 1u);
     const bool stats = (F.flags & 1u) != 0;
     const bool persp = F.proj == 0;
@@ -132,65 +135,63 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Frame F, const float* __rest
     unsigned long long n_tested = 0, n_hit = 0, n_hit_bond = 0;
     __syncthreads();
 
-    for (uint32_t base = 0; base < nsrc; base += kChunk) {
-        const uint32_t k = base + tid;
+    for (uint64_t base = 0; base < nsrc; base += kChunk) {
+        const uint64_t k = base + tid;
         uint32_t area = 0;
+        uint32_t pid = 0, lrect = 0;
+        bool take = false;
         if (k < nsrc) {
-            uint32_t pid;
-            bool take;
             if (!overflow) {
-                pid = list[o + k];
+                const uint2 e = list[o + k];
+                pid = e.x;
+                lrect = e.y;
                 take = true;
             } else {
-                const uint2 r = vis_rect[k];
-                take = tx >= (int)(r.x & 0xFFFF) && tx <= (int)(r.y & 0xFFFF) && ty >= (int)(r.x >> 16) &&
-                       ty <= (int)(r.y >> 16);
-                pid = vis_id[k];
-            }
-            if (take) {
-                Rec rec;
-                int x0, y0, x1, y1;
-                bool vis;
-                if (pid < F.n_atoms) {
-                    double vx, vy, vz;
-                    to_view(F, pos[3 * (size_t)pid], pos[3 * (size_t)pid + 1], pos[3 * (size_t)pid + 2], vx, vy,
-                            vz);
-                    const double r = rad[pid];
-                    vis = sphere_rect(F, vx, vy, vz, r, x0, y0, x1, y1);
-                    rec.a = make_float4((float)vx, (float)vy, (float)vz, (float)r);
-                    rec.b = make_float4(0.f, 0.f, 0.f, 0.f);
-                    rec.zcull = (float)((vz - r) * (1.0 - 1e-5));
-                    rec.kind = 0;
-                } else {
-                    const size_t b = pid - F.n_atoms;
-                    const uint32_t ia = bonds[2 * b], ib = bonds[2 * b + 1];
-                    double A[3], B[3];
-                    to_view(F, pos[3 * (size_t)ia], pos[3 * (size_t)ia + 1], pos[3 * (size_t)ia + 2], A[0], A[1],
-                            A[2]);
-                    to_view(F, pos[3 * (size_t)ib], pos[3 * (size_t)ib + 1], pos[3 * (size_t)ib + 2], B[0], B[1],
-                            B[2]);
-                    const double rho = F.bond_radius;
-                    vis = bond_rect(F, A, B, rho, x0, y0, x1, y1);
-                    const double ex = B[0] - A[0], ey = B[1] - A[1], ez = B[2] - A[2];
-                    const double L = sqrt(ex * ex + ey * ey + ez * ez);
-                    rec.a = make_float4((float)A[0], (float)A[1], (float)A[2], (float)rho);
-                    rec.b = make_float4((float)(ex / L), (float)(ey / L), (float)(ez / L), (float)L);
-                    rec.zcull = (float)((fmin(A[2], B[2]) - rho) * (1.0 - 1e-5) - 1e-6);
-                    rec.kind = 1;
-                }
-                if (vis) {
-                    x0 = max(x0, px0) - px0;
-                    y0 = max(y0, py0) - py0;
-                    x1 = min(x1, px0 + tw - 1) - px0;
-                    y1 = min(y1, py0 + th - 1) - py0;
-                    if (x0 <= x1 && y0 <= y1 && (stats || !(rec.zcull > tile_zmax))) {
-                        const uint32_t w = x1 - x0 + 1, h = y1 - y0 + 1;
-                        area = w * h;
-                        rec.id = pid;
-                        rec.rect = (uint32_t)x0 | ((uint32_t)y0 << 8) | (w << 16) | (h << 24);
-                        recs[tid] = rec;
+                const uint32_t g = (uint32_t)(k / chunk);
+                if ((uint32_t)(k - (uint64_t)g * chunk) < vis_cnt[g]) {
+                    const uint2 r = vis_rect[k];
+                    const int x0 = max((int)(r.x & 0xFFFF), px0) - px0, y0 = max((int)(r.x >> 16), py0) - py0;
+                    const int x1 = min((int)(r.y & 0xFFFF), px0 + TS - 1) - px0;
+                    const int y1 = min((int)(r.y >> 16), py0 + TS - 1) - py0;
+                    if (x0 <= x1 && y0 <= y1) {
+                        pid = vis_id[k];
+                        lrect = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)(x1 - x0 + 1) << 16) |
+                                ((uint32_t)(y1 - y0 + 1) << 24);
+                        take = true;
                     }
                 }
+            }
+        }
+        if (take) {
+            Rec rec;
+            if (pid < F.n_atoms) {
+                double vx, vy, vz;
+                to_view(F, pos[3 * (size_t)pid], pos[3 * (size_t)pid + 1], pos[3 * (size_t)pid + 2], vx, vy, vz);
+                const double r = rad[pid];
+                rec.a = make_float4((float)vx, (float)vy, (float)vz, (float)r);
+                rec.b = make_float4(0.f, 0.f, 0.f, 0.f);
+                rec.zcull = (float)((vz - r) * (1.0 - 1e-5));
+                rec.kind = 0;
+            } else {
+                const size_t b = pid - F.n_atoms;
+                const uint32_t ia = bonds[2 * b], ib = bonds[2 * b + 1];
+                double A[3], B[3];
+                to_view(F, pos[3 * (size_t)ia], pos[3 * (size_t)ia + 1], pos[3 * (size_t)ia + 2], A[0], A[1], A[2]);
+                to_view(F, pos[3 * (size_t)ib], pos[3 * (size_t)ib + 1], pos[3 * (size_t)ib + 2], B[0], B[1], B[2]);
+                const double rho = F.bond_radius;
+                const double ex = B[0] - A[0], ey = B[1] - A[1], ez = B[2] - A[2];
+                const double L = sqrt(ex * ex + ey * ey + ez * ez);
+                const double inv = 1.0 / L;
+                rec.a = make_float4((float)A[0], (float)A[1], (float)A[2], (float)rho);
+                rec.b = make_float4((float)(ex * inv), (float)(ey * inv), (float)(ez * inv), (float)L);
+                rec.zcull = (float)((fmin(A[2], B[2]) - rho) * (1.0 - 1e-5) - 1e-6);
+                rec.kind = 1;
+            }
+            if (stats || !(rec.zcull > tile_zmax)) {
+                area = ((lrect >> 16) & 0xFF) * (lrect >> 24);
+                rec.id = pid;
+                rec.rect = lrect;
+                recs[tid] = rec;
             }
         }
         // exclusive prefix of the fragment counts over the workgroup
@@ -290,22 +291,18 @@ hipError_t launch_resolve(const Frame& F, const float* pos, const float* rad, co
                           const BinBuffers& bb, float* depth, uint32_t* id, hipStream_t stream) {
     const int T = F.tiles_x * F.tiles_y;
     const int grid = xcd_grid(T);
+#define VTX_RESOLVE(TS)                                                                                  \
+    k_resolve<TS><<<grid, kBlock, 0, stream>>>(F, pos, rad, bonds, bb.tile_cnt, bb.tile_off, bb.list, bb.capacity, \
+                                               bb.vis_id, bb.vis_rect, bb.vis_cnt, bb.chunk, bb.groups, bb.ctr,   \
+                                               depth, id)
     switch (F.tile) {
-        case 8:
-            k_resolve<8><<<grid, kBlock, 0, stream>>>(F, pos, rad, bonds, bb.tile_cnt, bb.tile_off, bb.list,
-                                                      bb.capacity, bb.vis_id, bb.vis_rect, bb.ctr, depth, id);
-            break;
-        case 16:
-            k_resolve<16><<<grid, kBlock, 0, stream>>>(F, pos, rad, bonds, bb.tile_cnt, bb.tile_off, bb.list,
-                                                       bb.capacity, bb.vis_id, bb.vis_rect, bb.ctr, depth, id);
-            break;
-        case 32:
-            k_resolve<32><<<grid, kBlock, 0, stream>>>(F, pos, rad, bonds, bb.tile_cnt, bb.tile_off, bb.list,
-                                                       bb.capacity, bb.vis_id, bb.vis_rect, bb.ctr, depth, id);
-            break;
-        default:
-            return hipErrorInvalidValue;
+        case 8: VTX_RESOLVE(8); break;
+        case 16: VTX_RESOLVE(16); break;
+        case 32: VTX_RESOLVE(32); break;
+        case 64: VTX_RESOLVE(64); break;
+        default: return hipErrorInvalidValue;
     }
+#undef VTX_RESOLVE
     return hipGetLastError();
 }
 

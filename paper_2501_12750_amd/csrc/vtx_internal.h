@@ -13,6 +13,9 @@
 namespace vtx {
 
 constexpr int kBlock = 256;                  // threads per workgroup (4 waves of 64)
+constexpr int kBinThreads = 1024;            // binning workgroups (16 waves)
+constexpr int kMaxLdsTiles = 16320;          // tile histogram of one binning workgroup (< 64 KiB of LDS)
+constexpr uint32_t kMaxBinGroups = 512;
 constexpr uint32_t kBackground = 0xFFFFFFFFu;
 constexpr int kMaxSamples = 64;
 
@@ -151,16 +154,25 @@ inline int xcd_grid(int nblocks) { return ((nblocks + 7) >> 3) << 3; }
 // ---------------------------------------------------------------------------
 // host launch wrappers (one per kernel file)
 // ---------------------------------------------------------------------------
+// Binning scratch.  The `groups` binning workgroups each own `chunk`
+// consecutive primitives and the same range of the visible-list arrays.
 struct BinBuffers {
     uint32_t* tile_cnt;     // T
     uint64_t* tile_off;     // T
     uint32_t* tile_fill;    // T
-    uint32_t* vis_id;       // n_atoms + n_bonds
-    uint2* vis_rect;        // n_atoms + n_bonds, tile rectangle packed (x0 | y0 << 16, x1 | y1 << 16)
-    uint32_t* list;         // capacity entries
+    uint32_t* vis_id;       // groups * chunk
+    uint2* vis_rect;        // groups * chunk, pixel rectangle packed (x0 | y0 << 16, x1 | y1 << 16)
+    uint32_t* vis_cnt;      // groups: visible primitives of each workgroup
+    uint32_t* hist;         // groups * T: tile histogram of each workgroup
+    uint2* list;            // capacity entries: (primitive id, footprint in the tile packed as
+                            // x0 | y0 << 8 | w << 16 | h << 24, tile-local pixels; w = 64 stored as 64)
     uint64_t capacity;
+    uint32_t groups, chunk;
     Counters* ctr;
 };
+
+// Binning grid for n primitives (groups <= kMaxBinGroups, groups * chunk >= n).
+void bin_grid(uint64_t nprim, uint32_t* groups, uint32_t* chunk);
 
 // `marks`, when not null, holds events recorded before each kernel launch
 // (bin: clear, project, scan, scatter) for per-kernel timing.

@@ -241,3 +241,19 @@ def test_whole_cell_10m_sampled(vtx):
         rep.update(compare.check_end_to_end(dv["rgba"], ref))
         print(win, rep, flush=True)
         assert_clean(rep, str(win))
+
+
+def test_max_image_8k(vtx):
+    """7680 x 4320, the largest image the library accepts (the tile size is
+    raised to 64 so the tile grid fits the binner); windows against the oracle."""
+    wl = scenes.plain_small(n_atoms=20000, width=7680, height=4320)
+    sc, cam, opts, W, H = wl.scene, wl.camera, wl.options, wl.width, wl.height
+    dev = run_device(vtx, vtx.DeviceScene(sc), cam, opts, W, H)
+    for win in windows(W, H, 64, 4, seed=3) + [(W // 2 - 40, H // 2 - 40, 80, 80), (W - 30, H - 20, 30, 20)]:
+        ref = osplat.render(sc, cam, opts, W, H, window=win, halo=0)
+        dv = crop(dev, win)
+        rep = compare.check_gbuffer(dv["depth"], dv["id"], ref)
+        rep.update(compare.check_surface(dv["normal"], dv["albedo"], ref, sc, opts))
+        rep.update(compare.check_end_to_end(dv["rgba"], ref))
+        assert_clean(rep, str(win))
+    assert np.count_nonzero(dev["id"] != 0xFFFFFFFF) > 1e6
