@@ -178,13 +178,13 @@ int vtx_shade(const float* positions, const float* radii, const uint32_t* colors
 int vtx_read_stats(void* stream, vtx_stats* out);
 
 /*
- * vtx_set_bin_capacity - fixes the number of tile-bin entries of the
- * stream's scratch (entries >= 1), or restores automatic sizing (entries = 0:
- * the bins start at max(2^20, 2 (n_atoms + n_bonds)) entries and grow after a
- * frame that needed more).  A frame whose bins overflow is still exact: the
+ * vtx_set_bin_capacity - fixes the number of tile-bin entries (32 bytes
+ * each) of the stream's scratch (entries >= 1), or restores automatic sizing
+ * (entries = 0: the bins start at max(2^20, (n_atoms + n_bonds) / 2) entries
+ * and grow after a frame that needed more).  A frame whose bins overflow is still exact: the
  * tiles that did not fit are resolved from the list of visible primitives,
  * more slowly, and counted in vtx_stats.overflow_tiles.  Waits for the
- * stream.  VTX_EINVAL if entries > 2^31.
+ * stream.  VTX_EINVAL if entries > 2^28.
  */
 int vtx_set_bin_capacity(void* stream, uint64_t entries);
 

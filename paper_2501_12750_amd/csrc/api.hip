@@ -74,14 +74,14 @@ struct Workspace {
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 
-constexpr uint64_t kMaxCapacity = 1ull << 31;        // bin entries (8 GiB of ids)
+constexpr uint64_t kMaxCapacity = 1ull << 28;        // bin entries (8 GiB of 32-byte records)
 constexpr uint64_t kMinCapacity = 1ull << 20;
 
 int free_ws_buffers(Workspace* ws) {
     hipFree(ws->bb.tile_cnt);
     hipFree(ws->bb.tile_off);
     hipFree(ws->bb.tile_fill);
-    hipFree(ws->bb.vis_id);
+    hipFree(ws->bb.vis_rec);
     hipFree(ws->bb.vis_rect);
     hipFree(ws->bb.vis_cnt);
     hipFree(ws->bb.hist);
@@ -93,7 +93,7 @@ int free_ws_buffers(Workspace* ws) {
     ws->bb.tile_cnt = nullptr;
     ws->bb.tile_off = nullptr;
     ws->bb.tile_fill = nullptr;
-    ws->bb.vis_id = nullptr;
+    ws->bb.vis_rec = nullptr;
     ws->bb.vis_rect = nullptr;
     ws->bb.list = nullptr;
     ws->bb.capacity = 0;
@@ -174,12 +174,20 @@ int get_workspace(hipStream_t stream, Workspace** out) {
         delete ws;
         return fail(VTX_ENOMEM, "cannot allocate frame counters");
     }
-    if (hipHostMalloc(&ws->host_ctr, sizeof(Counters), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(&ws->host_ctr, sizeof(Counters), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
         hipFree(ws->bb.ctr);
         delete ws;
         return fail(VTX_ENOMEM, "cannot allocate pinned counters");
     }
     std::memset(ws->host_ctr, 0, sizeof(Counters));
+    void* dptr = nullptr;
+    if (hipHostGetDevicePointer(&dptr, ws->host_ctr, 0) != hipSuccess) {
+        hipFree(ws->bb.ctr);
+        hipHostFree(ws->host_ctr);
+        delete ws;
+        return fail(VTX_EHIP, "cannot map pinned counters");
+    }
+    ws->bb.host_ctr = static_cast<Counters*>(dptr);
     if (hipEventCreateWithFlags(&ws->done, hipEventDisableTiming) != hipSuccess) {
         hipFree(ws->bb.ctr);
         hipHostFree(ws->host_ctr);
@@ -221,9 +229,9 @@ int ensure_buffers(Workspace* ws, int T, uint64_t nprim) {
     ws->bb.groups = groups;
     ws->bb.chunk = chunk;
     const size_t nv = (size_t)groups * chunk;
-    if (nv > ws->vis_cap || !ws->bb.vis_id) {
+    if (nv > ws->vis_cap || !ws->bb.vis_rec) {
         size_t c1 = ws->vis_cap, c2 = ws->vis_cap;
-        if ((rc = grow(&ws->bb.vis_id, c1, nv, ws->stream, "visible list"))) return rc;
+        if ((rc = grow(&ws->bb.vis_rec, c1, nv, ws->stream, "visible records"))) return rc;
         if ((rc = grow(&ws->bb.vis_rect, c2, nv, ws->stream, "visible rectangles"))) return rc;
         ws->vis_cap = nv;
     }
@@ -240,7 +248,7 @@ int ensure_buffers(Workspace* ws, int T, uint64_t nprim) {
     }
     uint64_t want = ws->want_capacity;
     if (want == 0) {
-        want = 2 * nprim;
+        want = nprim / 2;
         if (want < kMinCapacity) want = kMinCapacity;
         if (want > kMaxCapacity) want = kMaxCapacity;
         ws->want_capacity = want;
@@ -390,9 +398,8 @@ int gbuffer_locked(const float* positions, const float* radii, int64_t n, const 
     VTX_HIP(vtx::launch_bin(F, positions, radii, bonds, ws->bb, stream, marks));
     if (marks) VTX_HIP(hipEventRecord(marks[4], stream));
     VTX_HIP(vtx::launch_resolve(F, positions, radii, bonds, ws->bb, depth, id, stream));
-    // Stream order keeps this copy behind the previous frame's; the host only
-    // reads the pinned counters once the latest recorded event has completed.
-    VTX_HIP(hipMemcpyAsync(ws->host_ctr, ws->bb.ctr, sizeof(Counters), hipMemcpyDeviceToHost, stream));
+    // The resolve's last workgroup writes the counters into the mapped pinned
+    // buffer; the host reads them once the latest recorded event has completed.
     VTX_HIP(hipEventRecord(ws->done, stream));
     ws->pending = true;
     ws->pending_capacity = ws->bb.capacity;
@@ -480,7 +487,7 @@ int vtx_read_stats(void* stream, vtx_stats* out) {
 }
 
 int vtx_set_bin_capacity(void* stream, uint64_t entries) {
-    if (entries > kMaxCapacity) return fail(VTX_EINVAL, "capacity %llu > 2^31", (unsigned long long)entries);
+    if (entries > kMaxCapacity) return fail(VTX_EINVAL, "capacity %llu > 2^28", (unsigned long long)entries);
     std::lock_guard<std::mutex> lk(g_mu);
     Workspace* ws = nullptr;
     int rc = get_workspace((hipStream_t)stream, &ws);

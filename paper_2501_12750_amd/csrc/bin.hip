@@ -31,14 +31,18 @@ __global__ void __launch_bounds__(kBlock) k_clear(uint32_t* tile_cnt, int T, Cou
     if (i < (int)(sizeof(Counters) / sizeof(unsigned int))) reinterpret_cast<unsigned int*>(ctr)[i] = 0;
 }
 
-__device__ inline bool primitive_rect(const Frame& F, uint32_t p, const float* __restrict__ pos,
-                                      const float* __restrict__ rad, const uint32_t* __restrict__ bonds,
-                                      int& x0, int& y0, int& x1, int& y1, bool& bad) {
+// Footprint and view-space record of primitive p; false if it cannot show.
+__device__ inline bool primitive_record(const Frame& F, uint32_t p, const float* __restrict__ pos,
+                                        const float* __restrict__ rad, const uint32_t* __restrict__ bonds,
+                                        int& x0, int& y0, int& x1, int& y1, PrimRec& rec, bool& bad) {
     bad = false;
     if (p < F.n_atoms) {
         double vx, vy, vz;
         to_view(F, pos[3 * (size_t)p], pos[3 * (size_t)p + 1], pos[3 * (size_t)p + 2], vx, vy, vz);
-        return sphere_rect(F, vx, vy, vz, (double)rad[p], x0, y0, x1, y1);
+        const double r = (double)rad[p];
+        rec.g0 = make_float4((float)vx, (float)vy, (float)vz, (float)r);
+        rec.g1 = make_uint4(0u, 0u, p, 0u);
+        return sphere_rect(F, vx, vy, vz, r, x0, y0, x1, y1);
     }
     const size_t b = p - F.n_atoms;
     const uint32_t ia = bonds[2 * b], ib = bonds[2 * b + 1];
@@ -53,13 +57,15 @@ __device__ inline bool primitive_rect(const Frame& F, uint32_t p, const float* _
     double A[3], B[3];
     to_view(F, ax, ay, az, A[0], A[1], A[2]);
     to_view(F, bx, by, bz, B[0], B[1], B[2]);
+    rec.g0 = make_float4((float)A[0], (float)A[1], (float)A[2], (float)(B[0] - A[0]));
+    rec.g1 = make_uint4(__float_as_uint((float)(B[1] - A[1])), __float_as_uint((float)(B[2] - A[2])), p, 0u);
     return bond_rect(F, A, B, (double)F.bond_radius, x0, y0, x1, y1);
 }
 
 __global__ void __launch_bounds__(kBinThreads) k_count(Frame F, const float* __restrict__ pos,
                                                        const float* __restrict__ rad,
                                                        const uint32_t* __restrict__ bonds, uint32_t chunk,
-                                                       uint32_t* __restrict__ vis_id, uint2* __restrict__ vis_rect,
+                                                       PrimRec* __restrict__ vis_rec, uint2* __restrict__ vis_rect,
                                                        uint32_t* __restrict__ vis_cnt, uint32_t* __restrict__ hist_out,
                                                        uint32_t* __restrict__ tile_cnt, Counters* ctr) {
     extern __shared__ uint32_t hist[];
@@ -79,7 +85,8 @@ __global__ void __launch_bounds__(kBinThreads) k_count(Frame F, const float* __r
         const uint64_t p = base + tid;
         int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
         bool bad = false;
-        const bool vis = p < end && primitive_rect(F, (uint32_t)p, pos, rad, bonds, x0, y0, x1, y1, bad);
+        PrimRec rec;
+        const bool vis = p < end && primitive_record(F, (uint32_t)p, pos, rad, bonds, x0, y0, x1, y1, rec, bad);
         bad_count += bad ? 1u : 0u;
         const unsigned long long vmask = __ballot(vis);
         uint32_t slot_base = 0;
@@ -89,7 +96,7 @@ __global__ void __launch_bounds__(kBinThreads) k_count(Frame F, const float* __r
         if (vis) {
             const uint64_t slot = start + slot_base + (uint32_t)__popcll(vmask & __lanemask_lt());
             const int tx0 = x0 / ts, tx1 = x1 / ts, ty0 = y0 / ts, ty1 = y1 / ts;
-            vis_id[slot] = (uint32_t)p;
+            vis_rec[slot] = rec;
             vis_rect[slot] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
             for (int ty = ty0; ty <= ty1; ++ty)
                 for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&hist[ty * F.tiles_x + tx], 1u);
@@ -115,14 +122,17 @@ __global__ void __launch_bounds__(kBinThreads) k_count(Frame F, const float* __r
 constexpr int kScanThreads = 1024;
 
 __global__ void __launch_bounds__(kScanThreads) k_scan(const uint32_t* __restrict__ cnt, uint64_t* off,
-                                                       uint32_t* fill, int T, uint64_t capacity, Counters* ctr) {
+                                                       uint32_t* fill, int T, uint64_t capacity, Counters* ctr,
+                                                       Counters* host_ctr) {
     __shared__ unsigned long long part[kScanThreads];
+    __shared__ unsigned int n_over;
     const int tid = threadIdx.x;
     const int per = (T + kScanThreads - 1) / kScanThreads;
     const int b = tid * per, e = min(T, b + per);
     unsigned long long s = 0;
     for (int i = b; i < e; ++i) s += cnt[i];
     part[tid] = s;
+    if (tid == 0) n_over = 0;
     __syncthreads();
     for (int d = 1; d < kScanThreads; d <<= 1) {
         const unsigned long long v = tid >= d ? part[tid - d] : 0ull;
@@ -131,26 +141,44 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(const uint32_t* __restric
         __syncthreads();
     }
     unsigned long long run = part[tid] - s;   // exclusive prefix of this lane's run
+    unsigned int over = 0;
     for (int i = b; i < e; ++i) {
         off[i] = run;
         fill[i] = 0;
         run += cnt[i];
+        over += run > capacity ? 1u : 0u;      // this tile's list does not fit the bins
     }
+    if (over) atomicAdd(&n_over, over);
+    __syncthreads();
     if (tid == kScanThreads - 1) {
         ctr->pairs = part[tid];
         ctr->overflow = part[tid] > capacity ? 1u : 0u;
+        ctr->overflow_tiles = n_over;
+        // every counter but the stats-mode fragment counts is final here:
+        // publish them to the host-mapped copy
+        if (host_ctr) {
+            host_ctr->vis_count = ctr->vis_count;
+            host_ctr->bad_bonds = ctr->bad_bonds;
+            host_ctr->pairs = part[tid];
+            host_ctr->overflow = part[tid] > capacity ? 1u : 0u;
+            host_ctr->overflow_tiles = n_over;
+            host_ctr->frag_tested = 0;
+            host_ctr->frag_hit = 0;
+            host_ctr->frag_hit_bond = 0;
+            __threadfence_system();
+        }
     }
 }
 
 constexpr uint32_t kNoRun = 0xFFFFFFFFu;
 
-__global__ void __launch_bounds__(kBinThreads) k_scatter(Frame F, uint32_t chunk, const uint32_t* __restrict__ vis_id,
+__global__ void __launch_bounds__(kBinThreads) k_scatter(Frame F, uint32_t chunk, const PrimRec* __restrict__ vis_rec,
                                                          const uint2* __restrict__ vis_rect,
                                                          const uint32_t* __restrict__ vis_cnt,
                                                          const uint32_t* __restrict__ hist_in,
                                                          const uint32_t* __restrict__ cnt,
                                                          const uint64_t* __restrict__ off, uint32_t* fill,
-                                                         uint2* __restrict__ list, uint64_t capacity) {
+                                                         PrimRec* __restrict__ list, uint64_t capacity) {
     extern __shared__ uint32_t cur[];
     const int T = F.tiles_x * F.tiles_y;
     const int tid = threadIdx.x;
@@ -167,7 +195,7 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(Frame F, uint32_t chunk
     const uint64_t start = (uint64_t)blockIdx.x * chunk;
     const int ts = F.tile;
     for (uint32_t k = tid; k < n; k += kBinThreads) {
-        const uint32_t id = vis_id[start + k];
+        PrimRec rec = vis_rec[start + k];
         const uint2 r = vis_rect[start + k];
         const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16;
         for (int ty = y0 / ts; ty <= y1 / ts; ++ty)
@@ -177,9 +205,9 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(Frame F, uint32_t chunk
                 // the footprint clipped to this tile, in tile-local pixels
                 const int lx0 = max(x0 - tx * ts, 0), ly0 = max(y0 - ty * ts, 0);
                 const int lx1 = min(x1 - tx * ts, ts - 1), ly1 = min(y1 - ty * ts, ts - 1);
-                const uint32_t lr = (uint32_t)lx0 | ((uint32_t)ly0 << 8) | ((uint32_t)(lx1 - lx0 + 1) << 16) |
-                                    ((uint32_t)(ly1 - ly0 + 1) << 24);
-                list[atomicAdd(&cur[t], 1u)] = make_uint2(id, lr);
+                rec.g1.w = (uint32_t)lx0 | ((uint32_t)ly0 << 8) | ((uint32_t)(lx1 - lx0 + 1) << 16) |
+                           ((uint32_t)(ly1 - ly0 + 1) << 24);
+                list[atomicAdd(&cur[t], 1u)] = rec;
             }
     }
 }
@@ -205,12 +233,13 @@ hipError_t launch_bin(const Frame& F, const float* pos, const float* rad, const 
     if (marks) (void)hipEventRecord(marks[0], stream);
     k_clear<<<(nclear + kBlock - 1) / kBlock, kBlock, 0, stream>>>(bb.tile_cnt, T, bb.ctr);
     if (marks) (void)hipEventRecord(marks[1], stream);
-    k_count<<<bb.groups, kBinThreads, lds, stream>>>(F, pos, rad, bonds, bb.chunk, bb.vis_id, bb.vis_rect, bb.vis_cnt,
+    k_count<<<bb.groups, kBinThreads, lds, stream>>>(F, pos, rad, bonds, bb.chunk, bb.vis_rec, bb.vis_rect, bb.vis_cnt,
                                                      bb.hist, bb.tile_cnt, bb.ctr);
     if (marks) (void)hipEventRecord(marks[2], stream);
-    k_scan<<<1, kScanThreads, 0, stream>>>(bb.tile_cnt, bb.tile_off, bb.tile_fill, T, bb.capacity, bb.ctr);
+    k_scan<<<1, kScanThreads, 0, stream>>>(bb.tile_cnt, bb.tile_off, bb.tile_fill, T, bb.capacity, bb.ctr,
+                                           bb.host_ctr);
     if (marks) (void)hipEventRecord(marks[3], stream);
-    k_scatter<<<bb.groups, kBinThreads, lds, stream>>>(F, bb.chunk, bb.vis_id, bb.vis_rect, bb.vis_cnt, bb.hist,
+    k_scatter<<<bb.groups, kBinThreads, lds, stream>>>(F, bb.chunk, bb.vis_rec, bb.vis_rect, bb.vis_cnt, bb.hist,
                                                        bb.tile_cnt, bb.tile_off, bb.tile_fill, bb.list, bb.capacity);
     return hipGetLastError();
 }

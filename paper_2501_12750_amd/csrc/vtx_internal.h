@@ -43,7 +43,8 @@ struct SampleKernel {
     uint32_t background;
 };
 
-// Device-side counters of one frame.
+// Device-side counters of one frame.  The last resolve workgroup copies them
+// to host-mapped memory.
 struct Counters {
     unsigned int vis_count;
     unsigned int overflow;
@@ -53,6 +54,21 @@ struct Counters {
     unsigned long long frag_tested;
     unsigned long long frag_hit;
     unsigned long long frag_hit_bond;
+    unsigned int done_blocks;
+    unsigned int pad[3];
+};
+
+// View-space record of one visible primitive (32 bytes), computed once per
+// frame from FP64 and rounded to FP32.
+//   sphere: g0 = (centre x, y, z, radius),      g1 = (0, 0, id, footprint)
+//   bond:   g0 = (A x, y, z, (B - A).x),         g1 = ((B - A).y, (B - A).z, id, footprint)
+// id >= n_atoms marks a bond.  In the visible list the footprint word is
+// unused (the pixel rectangle is kept beside it); in a tile list it is the
+// footprint clipped to the tile, x0 | y0 << 8 | w << 16 | h << 24 in
+// tile-local pixels.
+struct PrimRec {
+    float4 g0;
+    uint4 g1;
 };
 
 // ---------------------------------------------------------------------------
@@ -160,15 +176,15 @@ struct BinBuffers {
     uint32_t* tile_cnt;     // T
     uint64_t* tile_off;     // T
     uint32_t* tile_fill;    // T
-    uint32_t* vis_id;       // groups * chunk
+    PrimRec* vis_rec;       // groups * chunk visible-primitive records
     uint2* vis_rect;        // groups * chunk, pixel rectangle packed (x0 | y0 << 16, x1 | y1 << 16)
     uint32_t* vis_cnt;      // groups: visible primitives of each workgroup
     uint32_t* hist;         // groups * T: tile histogram of each workgroup
-    uint2* list;            // capacity entries: (primitive id, footprint in the tile packed as
-                            // x0 | y0 << 8 | w << 16 | h << 24, tile-local pixels; w = 64 stored as 64)
+    PrimRec* list;          // capacity entries, each tile's records contiguous
     uint64_t capacity;
     uint32_t groups, chunk;
     Counters* ctr;
+    Counters* host_ctr;     // device address of host-mapped counters (may be null)
 };
 
 // Binning grid for n primitives (groups <= kMaxBinGroups, groups * chunk >= n).
