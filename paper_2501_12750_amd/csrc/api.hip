@@ -64,6 +64,7 @@ struct Workspace {
     uint64_t pending_capacity = 0;
     uint64_t want_capacity = 0;
     bool fixed_capacity = false;
+    bool dirty = true;              // tile counts / counters must be zeroed before the next frame
     vtx_stats last{};
     TimingSlot* tslots = nullptr;   // ring of kTimingRing, created on first timed frame
     int tnext = 0;
@@ -223,6 +224,15 @@ int ensure_buffers(Workspace* ws, int T, uint64_t nprim) {
         if ((rc = grow(&ws->bb.tile_off, c2, (size_t)T, ws->stream, "tile offsets"))) return rc;
         if ((rc = grow(&ws->bb.tile_fill, c3, (size_t)T, ws->stream, "tile cursors"))) return rc;
         ws->tiles_cap = (size_t)T;
+        ws->dirty = true;
+    }
+    if (ws->dirty) {
+        // every frame leaves the tile counts and the counters zeroed for the
+        // next one; fresh or abandoned scratch is zeroed here instead
+        VTX_HIP(vtx::launch_zero(ws->bb.tile_cnt, ws->tiles_cap, ws->stream));
+        VTX_HIP(vtx::launch_zero(reinterpret_cast<uint32_t*>(ws->bb.ctr), sizeof(Counters) / sizeof(uint32_t),
+                                 ws->stream));
+        ws->dirty = false;
     }
     uint32_t groups, chunk;
     vtx::bin_grid(nprim, &groups, &chunk);
@@ -395,9 +405,11 @@ int gbuffer_locked(const float* positions, const float* radii, int64_t n, const 
     harvest(ws);
     const int T = F.tiles_x * F.tiles_y;
     if ((rc = ensure_buffers(ws, T, (uint64_t)n + (uint64_t)m))) return rc;
+    ws->dirty = true;   // until the resolve that re-zeroes the tile counts is queued
     VTX_HIP(vtx::launch_bin(F, positions, radii, bonds, ws->bb, stream, marks));
     if (marks) VTX_HIP(hipEventRecord(marks[4], stream));
     VTX_HIP(vtx::launch_resolve(F, positions, radii, bonds, ws->bb, depth, id, stream));
+    ws->dirty = false;
     // The resolve's last workgroup writes the counters into the mapped pinned
     // buffer; the host reads them once the latest recorded event has completed.
     VTX_HIP(hipEventRecord(ws->done, stream));

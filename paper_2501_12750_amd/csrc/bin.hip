@@ -25,10 +25,10 @@ namespace vtx {
 
 namespace {
 
-__global__ void __launch_bounds__(kBlock) k_clear(uint32_t* tile_cnt, int T, Counters* ctr) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < T) tile_cnt[i] = 0;
-    if (i < (int)(sizeof(Counters) / sizeof(unsigned int))) reinterpret_cast<unsigned int*>(ctr)[i] = 0;
+// Zeroes n words (allocation time only: afterwards every frame leaves the
+// tile counts and the frame counters at zero for the next one).
+__global__ void __launch_bounds__(kBlock) k_zero(uint32_t* p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
 // Footprint and view-space record of primitive p; false if it cannot show.
@@ -117,30 +117,39 @@ __global__ void __launch_bounds__(kBinThreads) k_count(Frame F, const float* __r
 }
 
 // Exclusive scan of the tile counts by one workgroup of 1024 lanes: each lane
-// sums a contiguous run, the run totals are scanned in LDS, then each lane
-// writes its run's offsets.  Also clears the scatter cursors.
+// sums a contiguous run, the run totals are scanned with wave shuffles and one
+// LDS exchange between the 16 waves, then each lane writes its run's offsets.
+// Also clears the scatter cursors, counts the tiles whose lists do not fit the
+// bins, publishes the frame counters to the host-mapped copy and re-arms the
+// device counters for the next frame.
 constexpr int kScanThreads = 1024;
 
 __global__ void __launch_bounds__(kScanThreads) k_scan(const uint32_t* __restrict__ cnt, uint64_t* off,
                                                        uint32_t* fill, int T, uint64_t capacity, Counters* ctr,
                                                        Counters* host_ctr) {
-    __shared__ unsigned long long part[kScanThreads];
+    __shared__ unsigned long long wtot[kScanThreads / 64];
     __shared__ unsigned int n_over;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
     const int per = (T + kScanThreads - 1) / kScanThreads;
     const int b = tid * per, e = min(T, b + per);
     unsigned long long s = 0;
     for (int i = b; i < e; ++i) s += cnt[i];
-    part[tid] = s;
+    unsigned long long incl = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) wtot[wave] = incl;
     if (tid == 0) n_over = 0;
     __syncthreads();
-    for (int d = 1; d < kScanThreads; d <<= 1) {
-        const unsigned long long v = tid >= d ? part[tid - d] : 0ull;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
+    unsigned long long wbase = 0, total = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        const unsigned long long v = wtot[w];
+        wbase += w < wave ? v : 0ull;
+        total += v;
     }
-    unsigned long long run = part[tid] - s;   // exclusive prefix of this lane's run
+    unsigned long long run = wbase + incl - s;   // exclusive prefix of this lane's run
     unsigned int over = 0;
     for (int i = b; i < e; ++i) {
         off[i] = run;
@@ -150,17 +159,22 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(const uint32_t* __restric
     }
     if (over) atomicAdd(&n_over, over);
     __syncthreads();
-    if (tid == kScanThreads - 1) {
-        ctr->pairs = part[tid];
-        ctr->overflow = part[tid] > capacity ? 1u : 0u;
+    if (tid == 0) {
+        const unsigned int vis = ctr->vis_count, bad = ctr->bad_bonds;
+        ctr->pairs = total;
+        ctr->overflow = total > capacity ? 1u : 0u;
         ctr->overflow_tiles = n_over;
-        // every counter but the stats-mode fragment counts is final here:
-        // publish them to the host-mapped copy
+        ctr->vis_count = 0;            // the next frame's count kernel adds to these
+        ctr->bad_bonds = 0;
+        ctr->frag_tested = 0;          // this frame's resolve adds to these
+        ctr->frag_hit = 0;
+        ctr->frag_hit_bond = 0;
+        ctr->done_blocks = 0;
         if (host_ctr) {
-            host_ctr->vis_count = ctr->vis_count;
-            host_ctr->bad_bonds = ctr->bad_bonds;
-            host_ctr->pairs = part[tid];
-            host_ctr->overflow = part[tid] > capacity ? 1u : 0u;
+            host_ctr->vis_count = vis;
+            host_ctr->bad_bonds = bad;
+            host_ctr->pairs = total;
+            host_ctr->overflow = total > capacity ? 1u : 0u;
             host_ctr->overflow_tiles = n_over;
             host_ctr->frag_tested = 0;
             host_ctr->frag_hit = 0;
@@ -224,14 +238,20 @@ void bin_grid(uint64_t nprim, uint32_t* groups, uint32_t* chunk) {
     *chunk = (uint32_t)c;
 }
 
+hipError_t launch_zero(uint32_t* p, size_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    k_zero<<<(unsigned)blocks, kBlock, 0, stream>>>(p, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_bin(const Frame& F, const float* pos, const float* rad, const uint32_t* bonds,
                       const BinBuffers& bb, hipStream_t stream, hipEvent_t* marks) {
     const int T = F.tiles_x * F.tiles_y;
     if (T > kMaxLdsTiles) return hipErrorInvalidValue;
-    const int nclear = T > 64 ? T : 64;
     const size_t lds = (size_t)T * sizeof(uint32_t);
     if (marks) (void)hipEventRecord(marks[0], stream);
-    k_clear<<<(nclear + kBlock - 1) / kBlock, kBlock, 0, stream>>>(bb.tile_cnt, T, bb.ctr);
     if (marks) (void)hipEventRecord(marks[1], stream);
     k_count<<<bb.groups, kBinThreads, lds, stream>>>(F, pos, rad, bonds, bb.chunk, bb.vis_rec, bb.vis_rect, bb.vis_cnt,
                                                      bb.hist, bb.tile_cnt, bb.ctr);

@@ -120,7 +120,7 @@ __device__ inline Rec make_rec(const Frame& F, const PrimRec& p) {
 }
 
 template <int TS>
-__global__ void __launch_bounds__(kBlock) k_resolve(Frame F, const uint32_t* __restrict__ cnt,
+__global__ void __launch_bounds__(kBlock) k_resolve(Frame F, uint32_t* __restrict__ cnt,
                                                     const uint64_t* __restrict__ off,
                                                     const PrimRec* __restrict__ list, uint64_t capacity,
                                                     const PrimRec* __restrict__ vis_rec,
@@ -148,6 +148,7 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Frame F, const uint32_t* __r
 
         const uint32_t n = cnt[t];
         const uint64_t o = off[t];
+        if (tid == 0) cnt[t] = 0;   // re-armed for the next frame's count kernel (no later reader)
         // a tile whose list did not fit the bins scans every workgroup's visible list
         const bool overflow = o + n > capacity;
         const uint64_t nsrc = overflow ? (uint64_t)groups * chunk : n;

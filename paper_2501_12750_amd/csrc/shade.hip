@@ -141,8 +141,11 @@ __global__ void __launch_bounds__(kBlock) k_shade(Frame F, SampleKernel K, const
             if (!(Sz > F.znear)) continue;
             float spx, spy;
             if (F.proj == 0) {
-                spx = fmaf(fpx, Sx / Sz, 0.5f * (float)F.W);
-                spy = fmaf(-fpx, Sy / Sz, 0.5f * (float)F.H);
+                // hardware reciprocal (1 ulp): moves the sample by far less than
+                // the 1e-3 px within which a pixel edge makes a sample unstable
+                const float iz = fpx * __builtin_amdgcn_rcpf(Sz);
+                spx = fmaf(Sx, iz, 0.5f * (float)F.W);
+                spy = fmaf(-Sy, iz, 0.5f * (float)F.H);
             } else {
                 spx = fmaf(Sx, osc, 0.5f * (float)F.W);
                 spy = fmaf(-Sy, osc, 0.5f * (float)F.H);
@@ -152,7 +155,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(Frame F, SampleKernel K, const
             const int lx = qx - bx0, ly = qy - by0;
             const float zq = (lx >= 0 && lx < kSpan && ly >= 0 && ly < kSpan) ? zt[ly * kSpan + lx]
                                                                               : depth[(size_t)qy * F.W + qx];
-            if (zq <= Sz - K.bias) occ += smooth01(K.radius / fabsf(Pz - zq));
+            if (zq <= Sz - K.bias) occ += smooth01(K.radius * __builtin_amdgcn_rcpf(fabsf(Pz - zq)));
         }
         ao = 1.0f - occ / (float)K.count;
     }

@@ -190,6 +190,10 @@ struct BinBuffers {
 // Binning grid for n primitives (groups <= kMaxBinGroups, groups * chunk >= n).
 void bin_grid(uint64_t nprim, uint32_t* groups, uint32_t* chunk);
 
+// Zeroes n 32-bit words (used when scratch is allocated; the frame kernels
+// leave the tile counts and the counters zeroed for the next frame).
+hipError_t launch_zero(uint32_t* p, size_t n, hipStream_t stream);
+
 // `marks`, when not null, holds events recorded before each kernel launch
 // (bin: clear, project, scan, scatter) for per-kernel timing.
 hipError_t launch_bin(const Frame& F, const float* pos, const float* rad, const uint32_t* bonds,

@@ -170,7 +170,9 @@ def greedy_bonds(pos32: np.ndarray, cutoff=1.6, max_degree=4) -> np.ndarray:
             deg[a] += 1
             deg[b] += 1
             keep[k] = True
-    return np.ascontiguousarray(np.stack([lo[keep], hi[keep]], axis=1).astype(np.uint32))
+    out = np.stack([lo[keep], hi[keep]], axis=1)
+    out = out[np.lexsort((out[:, 1], out[:, 0]))]      # listed in atom order, like a topology
+    return np.ascontiguousarray(out.astype(np.uint32))
 
 
 def fit_camera(pos32: np.ndarray, fovy_deg=45.0) -> Camera:
@@ -185,12 +187,9 @@ def fit_camera(pos32: np.ndarray, fovy_deg=45.0) -> Camera:
 def ball_and_stick(n_globules=2000, atoms_per_globule=500, sigma=12.0, pitch=14.3,
                    width=1920, height=1080, seed=2, ssao_samples=16) -> Workload:
     rng = np.random.default_rng(seed)
-    g = int(math.ceil(n_globules ** (1.0 / 3.0) - 1e-9))
-    g = max(g, 1)
+    g = max(1, int(round(n_globules ** (1.0 / 3.0))))
     while g ** 3 < n_globules:
         g += 1
-    if n_globules == 2000:
-        g = 13
     cells = np.stack(np.meshgrid(np.arange(g), np.arange(g), np.arange(g), indexing="ij"),
                      axis=-1).reshape(-1, 3)[:n_globules]
     centres = (cells + 0.5) * pitch + rng.uniform(-pitch / 4, pitch / 4, size=(n_globules, 3))
