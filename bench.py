@@ -68,6 +68,9 @@ def main():
     ap.add_argument("--workload", default="ball_and_stick", choices=["ball_and_stick", "whole_cell", "plain_small"])
     ap.add_argument("--tile", type=int, default=0, help="tile size (0 = library default)")
     ap.add_argument("--latency-frames", type=int, default=50)
+    ap.add_argument("--kernel-events", choices=["timed", "separate"], default="separate",
+                    help="record the per-kernel HIP events inside the timed region, or in a separate "
+                         "pass of the same length after it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before timing, run one device copy of this many MiB (reference for HBM counters)")
@@ -121,12 +124,16 @@ def main():
     vtx.vtx_reset_timings(stream)
     log(f"warmup {args.warmup} done; timing {args.steps} steps")
 
+    opts_main = opts_t if args.kernel_events == "timed" else wl.options
     torch.cuda.synchronize()
     ts = time.perf_counter()
     for _ in range(args.steps):
-        vtx.vtx_render(*ds.args(), wl.camera, opts_t, W, H, frame.rgba, frame.depth, frame.id, stream)
+        vtx.vtx_render(*ds.args(), wl.camera, opts_main, W, H, frame.rgba, frame.depth, frame.id, stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - ts
+    if args.kernel_events == "separate":
+        for _ in range(args.steps):
+            vtx.vtx_render(*ds.args(), wl.camera, opts_t, W, H, frame.rgba, frame.depth, frame.id, stream)
     timings = vtx.vtx_read_timings(stream)
     st_after = vtx.vtx_read_stats(stream)
     ms_per_step = elapsed / args.steps * 1e3

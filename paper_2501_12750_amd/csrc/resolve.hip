@@ -8,13 +8,15 @@
 // with no gathers.  Records are staged through LDS 256 at a time; their
 // footprints' pixel counts are prefix-summed and the resulting (record,
 // pixel) fragments are dealt to the 256 lanes round-robin, so the load is
-// balanced whatever the mix of tiny and large primitives.  A hit is folded into the tile's depth
+// balanced whatever the mix of tiny and large primitives, and lanes of one
+// wave work on neighbouring pixels of the same few records.  A hit is folded into the tile's depth
 // buffer in LDS with one 64-bit atomicMin of the packed key
 // (float bits of z) << 32 | id: positive floats order like their bit
 // patterns, so the minimum key is the nearest hit and equal depths go to the
 // smaller id, in any order of evaluation.  Depth early-outs skip a record
-// whose nearest possible depth lies behind everything the tile already
-// holds, and a fragment whose pixel already holds a nearer hit.
+// whose nearest possible depth lies behind everything the 4x4-pixel blocks
+// under its footprint already hold, and a fragment whose pixel already holds
+// a nearer hit.
 #include "vtx_internal.h"
 
 namespace vtx {
@@ -22,6 +24,10 @@ namespace vtx {
 namespace {
 
 constexpr int kChunk = kBlock;
+template <int TS>
+struct HzGrid {
+    static constexpr int kBlocks = (TS / 4) * (TS / 4);
+};
 
 struct Rec {
     float4 a;          // sphere: centre (view), radius | cylinder: A (view), radius
@@ -51,14 +57,20 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v) {
 // Sphere: front root of |o + t D - c| = r with D = (Dx, Dy, 1), so t is the
 // view depth.  Stable form: b = (c-o).D / D.D, q = (c-o) - b D,
 // t = b - sqrt((r^2 - q.q) / D.D).
+// The hardware reciprocal and square root (<= 1 ulp) are used throughout:
+// their error is a few parts in 1e7 of the distance, far inside the 1e-5
+// depth tolerance and the grazing band the oracle allows.
+__device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 __device__ inline float hit_sphere(const float4 s, float ox, float oy, float Dx, float Dy) {
     const float cx = s.x - ox, cy = s.y - oy, cz = s.z;
-    const float dd = fmaf(Dx, Dx, fmaf(Dy, Dy, 1.0f));
-    const float b = fmaf(cx, Dx, fmaf(cy, Dy, cz)) / dd;
+    const float inv_dd = fast_rcp(fmaf(Dx, Dx, fmaf(Dy, Dy, 1.0f)));
+    const float b = fmaf(cx, Dx, fmaf(cy, Dy, cz)) * inv_dd;
     const float qx = fmaf(-b, Dx, cx), qy = fmaf(-b, Dy, cy), qz = cz - b;
     const float disc = fmaf(s.w, s.w, -fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
     if (disc < 0.0f) return INFINITY;
-    return b - sqrtf(disc / dd);
+    return b - fast_sqrt(disc * inv_dd);
 }
 
 // Closed cylinder of radius rho from A along unit axis a for length L: the
@@ -76,17 +88,18 @@ __device__ inline float hit_cylinder(const float4 ca, const float4 cb, float ox,
     const float k = fmaf(px, px, fmaf(py, py, pz * pz));
     float t = INFINITY;
     if (k > 0.0f) {
-        const float tc = -fmaf(qx, px, fmaf(qy, py, qz * pz)) / k;
+        const float inv_k = fast_rcp(k);
+        const float tc = -fmaf(qx, px, fmaf(qy, py, qz * pz)) * inv_k;
         const float rx = fmaf(tc, px, qx), ry = fmaf(tc, py, qy), rz = fmaf(tc, pz, qz);
         const float disc = rho2 - fmaf(rx, rx, fmaf(ry, ry, rz * rz));
         if (disc >= 0.0f) {
-            const float ts = tc - sqrtf(disc / k);
+            const float ts = tc - fast_sqrt(disc * inv_k);
             const float s = fmaf(ts, da, wa);
             if (s >= 0.0f && s <= cb.w) t = ts;
         }
     }
     if (da != 0.0f) {
-        const float tp = (da > 0.0f ? -wa : cb.w - wa) / da;
+        const float tp = (da > 0.0f ? -wa : cb.w - wa) * fast_rcp(da);
         const float off = da > 0.0f ? 0.0f : cb.w;
         const float ex = fmaf(tp, Dx, wx) - off * cb.x;
         const float ey = fmaf(tp, Dy, wy) - off * cb.y;
@@ -108,8 +121,8 @@ __device__ inline Rec make_rec(const Frame& F, const PrimRec& p) {
         r.kind = 0;
     } else {
         const float dx = p.g0.w, dy = __uint_as_float(p.g1.x), dz = __uint_as_float(p.g1.y);
-        const float L = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-        const float inv = 1.0f / L;
+        const float L = fast_sqrt(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        const float inv = fast_rcp(L);
         const float rho = F.bond_radius;
         r.a = make_float4(p.g0.x, p.g0.y, p.g0.z, rho);
         r.b = make_float4(dx * inv, dy * inv, dz * inv, L);
@@ -132,7 +145,8 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Frame F, uint32_t* __restric
     __shared__ Rec recs[kChunk];
     __shared__ uint32_t pref[kChunk + 1];
     __shared__ uint32_t wsum[kBlock / 64];
-    __shared__ float wmax[kBlock / 64];
+    constexpr int kHzBlocks = HzGrid<TS>::kBlocks;
+    __shared__ uint32_t hz[kHzBlocks];
 
     const int T = F.tiles_x * F.tiles_y;
     const int t = xcd_contiguous(blockIdx.x, T);
@@ -148,44 +162,88 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Frame F, uint32_t* __restric
 
         const uint32_t n = cnt[t];
         const uint64_t o = off[t];
-        if (tid == 0) cnt[t] = 0;   // re-armed for the next frame's count kernel (no later reader)
         // a tile whose list did not fit the bins scans every workgroup's visible list
         const bool overflow = o + n > capacity;
         const uint64_t nsrc = overflow ? (uint64_t)groups * chunk : n;
         const bool persp = F.proj == 0;
-        float tile_zmax = INFINITY;
         __syncthreads();
+        // every wave has read the tile's count (it sets the trip count of the
+        // barrier loop below): re-arm it for the next frame's count kernel
+        if (tid == 0) cnt[t] = 0;
 
-        for (uint64_t base = 0; base < nsrc; base += kChunk) {
-            const uint64_t k = base + tid;
-            uint32_t area = 0;
-            bool take = false;
-            PrimRec pr;
-            if (k < nsrc) {
-                if (!overflow) {
-                    pr = list[o + k];
-                    take = true;
-                } else {
-                    const uint32_t g = (uint32_t)(k / chunk);
-                    if ((uint32_t)(k - (uint64_t)g * chunk) < vis_cnt[g]) {
-                        const uint2 r = vis_rect[k];
-                        const int x0 = max((int)(r.x & 0xFFFF), px0) - px0, y0 = max((int)(r.x >> 16), py0) - py0;
-                        const int x1 = min((int)(r.y & 0xFFFF), px0 + TS - 1) - px0;
-                        const int y1 = min((int)(r.y >> 16), py0 + TS - 1) - py0;
-                        if (x0 <= x1 && y0 <= y1) {
-                            pr = vis_rec[k];
-                            pr.g1.w = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)(x1 - x0 + 1) << 16) |
-                                      ((uint32_t)(y1 - y0 + 1) << 24);
-                            take = true;
-                        }
-                    }
-                }
+        // one (record, pixel) ray test folded into the tile's LDS depth buffer
+        auto test_pixel = [&](const Rec& rc, int lx, int ly) {
+            const int slot = ly * TS + lx;
+            if (!stats) {
+                const unsigned long long cur = keys[slot];
+                if (__uint_as_float((uint32_t)(cur >> 32)) < rc.zcull) return;
             }
-            if (take) {
-                const Rec rec = make_rec(F, pr);
-                if (stats || !(rec.zcull > tile_zmax)) {
-                    area = ((rec.rect >> 16) & 0xFF) * (rec.rect >> 24);
-                    recs[tid] = rec;
+            const float ndx = fmaf((float)(px0 + lx) + 0.5f, F.inv_w2, -1.0f);
+            const float ndy = fmaf(-((float)(py0 + ly) + 0.5f), F.inv_h2, 1.0f);
+            float ox, oy, Dx, Dy;
+            if (persp) {
+                ox = 0.f; oy = 0.f; Dx = ndx * F.txf; Dy = ndy * F.tyf;
+            } else {
+                ox = ndx * F.hxf; oy = ndy * F.hyf; Dx = 0.f; Dy = 0.f;
+            }
+            const float z = rc.kind == 0 ? hit_sphere(rc.a, ox, oy, Dx, Dy) : hit_cylinder(rc.a, rc.b, ox, oy, Dx, Dy);
+            const bool hit = z >= F.znear && z <= F.zfar;
+            if (stats) {
+                n_tested += 1;
+                n_hit += hit ? 1 : 0;
+                n_hit_bond += (hit && rc.kind == 1) ? 1 : 0;
+            }
+            if (hit) atomicMin(&keys[slot], ((unsigned long long)__float_as_uint(z) << 32) | rc.id);
+        };
+        // entry k of the tile's list, or of the visible lists when the tile overflowed
+        auto fetch = [&](uint64_t k, PrimRec& pr) -> bool {
+            if (!overflow) {
+                pr = list[o + k];
+                return true;
+            }
+            const uint32_t g = (uint32_t)(k / chunk);
+            if ((uint32_t)(k - (uint64_t)g * chunk) >= vis_cnt[g]) return false;
+            const uint2 r = vis_rect[k];
+            const int x0 = max((int)(r.x & 0xFFFF), px0) - px0, y0 = max((int)(r.x >> 16), py0) - py0;
+            const int x1 = min((int)(r.y & 0xFFFF), px0 + TS - 1) - px0;
+            const int y1 = min((int)(r.y >> 16), py0 + TS - 1) - py0;
+            if (x0 > x1 || y0 > y1) return false;
+            pr = vis_rec[k];
+            pr.g1.w = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)(x1 - x0 + 1) << 16) |
+                      ((uint32_t)(y1 - y0 + 1) << 24);
+            return true;
+        };
+
+        // hz[b]: float bits of the farthest depth held by 4x4-pixel block b
+        // (+inf while any of its pixels is empty).  It only decreases during
+        // the frame, so a stale value is a safe bound.
+        for (int i = tid; i < kHzBlocks; i += kBlock) hz[i] = 0x7F800000u;
+        // The tile's list is staged 256 records at a time; the next chunk's
+        // records are loaded while this chunk is resolved.
+        PrimRec nxt;
+        bool nxt_ok = (uint64_t)tid < nsrc && fetch(tid, nxt);
+        __syncthreads();
+        for (uint64_t base = 0; base < nsrc; base += kChunk) {
+            const PrimRec pr = nxt;
+            const bool have = nxt_ok;
+            nxt_ok = base + kChunk + tid < nsrc && fetch(base + kChunk + tid, nxt);
+            uint32_t area = 0;
+            if (have) {
+                const Rec rc = make_rec(F, pr);
+                bool keep = true;
+                if (!stats) {
+                    // record cull: its nearest depth lies behind everything the
+                    // 4x4 blocks under its footprint already hold
+                    const int x0 = (int)(rc.rect & 0xFF), y0 = (int)((rc.rect >> 8) & 0xFF);
+                    const int x1 = x0 + (int)((rc.rect >> 16) & 0xFF) - 1, y1 = y0 + (int)(rc.rect >> 24) - 1;
+                    uint32_t m = 0;
+                    for (int by = y0 >> 2; by <= (y1 >> 2); ++by)
+                        for (int bx = x0 >> 2; bx <= (x1 >> 2); ++bx) m = max(m, hz[by * (TS / 4) + bx]);
+                    keep = !(__float_as_uint(rc.zcull) > m && rc.zcull > 0.0f);
+                }
+                if (keep) {
+                    area = ((rc.rect >> 16) & 0xFF) * (rc.rect >> 24);
+                    recs[tid] = rc;
                 }
             }
             // exclusive prefix of the fragment counts over the workgroup
@@ -198,10 +256,9 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Frame F, uint32_t* __restric
             if (tid == kBlock - 1) pref[kChunk] = wbase + incl;
             __syncthreads();
             const uint32_t total = pref[kChunk];
-
             // fragments are dealt round-robin: the 64 lanes of a wave take 64
-            // consecutive fragments, i.e. neighbouring pixels of a few
-            // adjacent records of the same kind
+            // consecutive fragments, i.e. neighbouring pixels of a few adjacent
+            // records, so early-out decisions agree across the wave
             for (uint32_t f = tid; f < total; f += kBlock) {
                 int lo = 0, hi = kChunk;
                 while (hi - lo > 1) {
@@ -216,50 +273,25 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Frame F, uint32_t* __restric
                 // (local + 1/2) / rw is far below its distance to an integer
                 const uint32_t dy = (uint32_t)(((float)local + 0.5f) * __builtin_amdgcn_rcpf((float)rw));
                 const uint32_t dx = local - dy * rw;
-                const int lx = (int)(rc.rect & 0xFF) + (int)dx, ly = (int)((rc.rect >> 8) & 0xFF) + (int)dy;
-                const int slot = ly * TS + lx;
-                if (!stats) {
-                    const unsigned long long cur = keys[slot];
-                    if (__uint_as_float((uint32_t)(cur >> 32)) < rc.zcull) continue;
-                }
-                const float ndx = fmaf((float)(px0 + lx) + 0.5f, F.inv_w2, -1.0f);
-                const float ndy = fmaf(-((float)(py0 + ly) + 0.5f), F.inv_h2, 1.0f);
-                float ox, oy, Dx, Dy;
-                if (persp) {
-                    ox = 0.f; oy = 0.f; Dx = ndx * F.txf; Dy = ndy * F.tyf;
-                } else {
-                    ox = ndx * F.hxf; oy = ndy * F.hyf; Dx = 0.f; Dy = 0.f;
-                }
-                const float z = rc.kind == 0 ? hit_sphere(rc.a, ox, oy, Dx, Dy)
-                                             : hit_cylinder(rc.a, rc.b, ox, oy, Dx, Dy);
-                const bool hit = z >= F.znear && z <= F.zfar;
-                if (stats) {
-                    n_tested += 1;
-                    n_hit += hit ? 1 : 0;
-                    n_hit_bond += (hit && rc.kind == 1) ? 1 : 0;
-                }
-                if (hit) {
-                    const unsigned long long key = ((unsigned long long)__float_as_uint(z) << 32) | rc.id;
-                    atomicMin(&keys[slot], key);
-                }
+                test_pixel(rc, (int)(rc.rect & 0xFF) + (int)dx, (int)((rc.rect >> 8) & 0xFF) + (int)dy);
             }
             __syncthreads();
             if (!stats && base + kChunk < nsrc) {
-                float m = 0.0f;
+                // refresh the block depths for the next chunk's record cull
+                for (int i = tid; i < kHzBlocks; i += kBlock) hz[i] = 0u;
+                __syncthreads();
                 for (int i = tid; i < TS * TS; i += kBlock) {
                     const int ly = i / TS, lx = i - ly * TS;
-                    if (lx < tw && ly < th) {
-                        const unsigned long long kk = keys[i];
-                        m = fmaxf(m, kk == ~0ull ? INFINITY : __uint_as_float((uint32_t)(kk >> 32)));
-                    }
+                    const unsigned long long kk = keys[i];
+                    // pixels outside the image never hold a hit: they do not
+                    // bound the block
+                    const uint32_t zb = (lx < tw && ly < th) ? (kk == ~0ull ? 0x7F800000u : (uint32_t)(kk >> 32)) : 0u;
+                    atomicMax(&hz[(ly >> 2) * (TS / 4) + (lx >> 2)], zb);
                 }
-                m = wave_max(m);
-                if (lane == 0) wmax[wave] = m;
-                __syncthreads();
-                tile_zmax = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
                 __syncthreads();
             }
         }
+        __syncthreads();
 
         for (int i = tid; i < TS * TS; i += kBlock) {
             const int ly = i / TS, lx = i - ly * TS;

@@ -257,3 +257,23 @@ def test_max_image_8k(vtx):
         rep.update(compare.check_end_to_end(dv["rgba"], ref))
         assert_clean(rep, str(win))
     assert np.count_nonzero(dev["id"] != 0xFFFFFFFF) > 1e6
+
+
+def test_many_consecutive_frames_identical(vtx):
+    """Back-to-back frames on one stream reuse the tile counts each frame
+    re-arms for the next; 300 frames without synchronization must all
+    reproduce the first frame bit for bit (tiles with several chunks)."""
+    import torch
+    wl = scenes.ball_and_stick(n_globules=64, atoms_per_globule=400, sigma=5.0, pitch=7.0,
+                               width=640, height=480, ssao_samples=8)
+    ds = vtx.DeviceScene(wl.scene)
+    ref = run_render(vtx, ds, wl.camera, wl.options, wl.width, wl.height)
+    frames = [vtx.Frame(wl.width, wl.height) for _ in range(4)]
+    for i in range(300):
+        fr = frames[i % 4]
+        vtx.vtx_render(*ds.args(), wl.camera, wl.options, wl.width, wl.height, fr.rgba, fr.depth, fr.id)
+    torch.cuda.synchronize()
+    for fr in frames:
+        d = fr.numpy()
+        for k in ("rgba", "depth", "id"):
+            assert np.array_equal(d[k], ref[k]), k
