@@ -97,7 +97,7 @@ typedef struct vtx_options {
     uint32_t background;      /* RGBA8 of pixels hit by nothing (0 = transparent black) */
     int32_t tile_size;        /* screen tile edge in pixels: 0 (default 16), 8, 16, 32 or 64;
                                  raised to the next of these while the image has
-                                 more than 16320 tiles (VTX_EINVAL if 64 is not
+                                 more than 15360 tiles (VTX_EINVAL if 64 is not
                                  enough: extreme aspect ratios) */
     uint32_t flags;           /* VTX_FLAG_* */
 } vtx_options;

@@ -230,6 +230,7 @@ int ensure_buffers(Workspace* ws, int T, uint64_t nprim) {
         // every frame leaves the tile counts and the counters zeroed for the
         // next one; fresh or abandoned scratch is zeroed here instead
         VTX_HIP(vtx::launch_zero(ws->bb.tile_cnt, ws->tiles_cap, ws->stream));
+        VTX_HIP(vtx::launch_zero(ws->bb.tile_fill, ws->tiles_cap, ws->stream));
         VTX_HIP(vtx::launch_zero(reinterpret_cast<uint32_t*>(ws->bb.ctr), sizeof(Counters) / sizeof(uint32_t),
                                  ws->stream));
         ws->dirty = false;

@@ -10,8 +10,8 @@
 //            per-workgroup list of the visible ones, and a tile histogram
 //            in LDS; the histogram row is stored and its non-zero entries are
 //            added to the global tile counts (one atomic per touched tile);
-//   scan     exclusive prefix sum of the tile counts -> list offsets;
-//   scatter  each workgroup reserves, per touched tile, one run of the
+//   scatter  each workgroup rebuilds the exclusive prefix sum of the tile
+//            counts (list offsets), reserves, per touched tile, one run of the
 //            tile's list (one atomic), then places its primitives with LDS
 //            atomics.
 // So the global atomics scale with (workgroup, touched tile) pairs rather
@@ -116,25 +116,33 @@ __global__ void __launch_bounds__(kBinThreads) k_count(Frame F, const float* __r
     }
 }
 
-// Exclusive scan of the tile counts by one workgroup of 1024 lanes: each lane
-// sums a contiguous run, the run totals are scanned with wave shuffles and one
-// LDS exchange between the 16 waves, then each lane writes its run's offsets.
-// Also clears the scatter cursors, counts the tiles whose lists do not fit the
-// bins, publishes the frame counters to the host-mapped copy and re-arms the
-// device counters for the next frame.
-constexpr int kScanThreads = 1024;
+constexpr uint32_t kNoRun = 0xFFFFFFFFu;
 
-__global__ void __launch_bounds__(kScanThreads) k_scan(const uint32_t* __restrict__ cnt, uint64_t* off,
-                                                       uint32_t* fill, int T, uint64_t capacity, Counters* ctr,
-                                                       Counters* host_ctr) {
-    __shared__ unsigned long long wtot[kScanThreads / 64];
+// Scatter.  Every workgroup first rebuilds the exclusive prefix sum of the
+// tile counts for itself (one read of T counts from L2; lane j owns a
+// contiguous run of tiles, the run totals are scanned with wave shuffles and
+// one LDS exchange), and while walking its run reserves, for each tile its
+// primitives touch, one run of that tile's list (one global atomic).  It then
+// places its primitives with LDS atomics.  Workgroup 0 also stores the tile
+// offsets for the resolve and publishes the frame counters.
+__global__ void __launch_bounds__(kBinThreads) k_scatter(Frame F, uint32_t chunk, const PrimRec* __restrict__ vis_rec,
+                                                         const uint2* __restrict__ vis_rect,
+                                                         const uint32_t* __restrict__ vis_cnt,
+                                                         const uint32_t* __restrict__ hist_in,
+                                                         const uint32_t* __restrict__ cnt, uint64_t* __restrict__ off,
+                                                         uint32_t* fill, PrimRec* __restrict__ list, uint64_t capacity,
+                                                         Counters* ctr, Counters* host_ctr) {
+    extern __shared__ uint32_t cur[];
+    __shared__ unsigned long long wtot[kBinThreads / 64];
     __shared__ unsigned int n_over;
+    const int T = F.tiles_x * F.tiles_y;
     const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
-    const int per = (T + kScanThreads - 1) / kScanThreads;
-    const int b = tid * per, e = min(T, b + per);
-    unsigned long long s = 0;
-    for (int i = b; i < e; ++i) s += cnt[i];
-    unsigned long long incl = s;
+    const bool lead = blockIdx.x == 0;
+    const int per = (T + kBinThreads - 1) / kBinThreads;
+    const int b = min(T, tid * per), e = min(T, b + per);
+    unsigned long long sum = 0;
+    for (int t = b; t < e; ++t) sum += cnt[t];
+    unsigned long long incl = sum;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const unsigned long long v = __shfl_up(incl, o);
@@ -143,66 +151,51 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(const uint32_t* __restric
     if (lane == 63) wtot[wave] = incl;
     if (tid == 0) n_over = 0;
     __syncthreads();
-    unsigned long long wbase = 0, total = 0;
-    for (int w = 0; w < kScanThreads / 64; ++w) {
+    unsigned long long run = incl - sum, total = 0;
+    for (int w = 0; w < kBinThreads / 64; ++w) {
         const unsigned long long v = wtot[w];
-        wbase += w < wave ? v : 0ull;
+        run += w < wave ? v : 0ull;
         total += v;
     }
-    unsigned long long run = wbase + incl - s;   // exclusive prefix of this lane's run
-    unsigned int over = 0;
-    for (int i = b; i < e; ++i) {
-        off[i] = run;
-        fill[i] = 0;
-        run += cnt[i];
-        over += run > capacity ? 1u : 0u;      // this tile's list does not fit the bins
-    }
-    if (over) atomicAdd(&n_over, over);
-    __syncthreads();
-    if (tid == 0) {
-        const unsigned int vis = ctr->vis_count, bad = ctr->bad_bonds;
-        ctr->pairs = total;
-        ctr->overflow = total > capacity ? 1u : 0u;
-        ctr->overflow_tiles = n_over;
-        ctr->vis_count = 0;            // the next frame's count kernel adds to these
-        ctr->bad_bonds = 0;
-        ctr->frag_tested = 0;          // this frame's resolve adds to these
-        ctr->frag_hit = 0;
-        ctr->frag_hit_bond = 0;
-        ctr->done_blocks = 0;
-        if (host_ctr) {
-            host_ctr->vis_count = vis;
-            host_ctr->bad_bonds = bad;
-            host_ctr->pairs = total;
-            host_ctr->overflow = total > capacity ? 1u : 0u;
-            host_ctr->overflow_tiles = n_over;
-            host_ctr->frag_tested = 0;
-            host_ctr->frag_hit = 0;
-            host_ctr->frag_hit_bond = 0;
-            __threadfence_system();
-        }
-    }
-}
-
-constexpr uint32_t kNoRun = 0xFFFFFFFFu;
-
-__global__ void __launch_bounds__(kBinThreads) k_scatter(Frame F, uint32_t chunk, const PrimRec* __restrict__ vis_rec,
-                                                         const uint2* __restrict__ vis_rect,
-                                                         const uint32_t* __restrict__ vis_cnt,
-                                                         const uint32_t* __restrict__ hist_in,
-                                                         const uint32_t* __restrict__ cnt,
-                                                         const uint64_t* __restrict__ off, uint32_t* fill,
-                                                         PrimRec* __restrict__ list, uint64_t capacity) {
-    extern __shared__ uint32_t cur[];
-    const int T = F.tiles_x * F.tiles_y;
-    const int tid = threadIdx.x;
     const uint32_t* row = hist_in + (size_t)blockIdx.x * T;
-    for (int t = tid; t < T; t += kBinThreads) {
+    unsigned int over = 0;
+    for (int t = b; t < e; ++t) {
+        const uint32_t c = cnt[t];
+        const bool fits = run + c <= capacity;      // else the resolve rebuilds this tile from the visible lists
         const uint32_t h = row[t];
-        const uint64_t o = off[t];
-        uint32_t c = kNoRun;
-        if (h && o + cnt[t] <= capacity) c = (uint32_t)(o + atomicAdd(&fill[t], h));
-        cur[t] = c;
+        uint32_t r = kNoRun;
+        if (h && fits) r = (uint32_t)(run + atomicAdd(&fill[t], h));
+        cur[t] = r;
+        if (lead) off[t] = run;
+        over += fits ? 0u : 1u;
+        run += c;
+    }
+    if (lead) {
+        if (over) atomicAdd(&n_over, over);
+        __syncthreads();
+        if (tid == 0) {
+            const unsigned int vis = ctr->vis_count, bad = ctr->bad_bonds;
+            ctr->pairs = total;
+            ctr->overflow = total > capacity ? 1u : 0u;
+            ctr->overflow_tiles = n_over;
+            ctr->vis_count = 0;            // the next frame's count kernel adds to these
+            ctr->bad_bonds = 0;
+            ctr->frag_tested = 0;          // this frame's resolve adds to these
+            ctr->frag_hit = 0;
+            ctr->frag_hit_bond = 0;
+            ctr->done_blocks = 0;
+            if (host_ctr) {
+                host_ctr->vis_count = vis;
+                host_ctr->bad_bonds = bad;
+                host_ctr->pairs = total;
+                host_ctr->overflow = total > capacity ? 1u : 0u;
+                host_ctr->overflow_tiles = n_over;
+                host_ctr->frag_tested = 0;
+                host_ctr->frag_hit = 0;
+                host_ctr->frag_hit_bond = 0;
+                __threadfence_system();
+            }
+        }
     }
     __syncthreads();
     const uint32_t n = vis_cnt[blockIdx.x];
@@ -256,11 +249,10 @@ hipError_t launch_bin(const Frame& F, const float* pos, const float* rad, const 
     k_count<<<bb.groups, kBinThreads, lds, stream>>>(F, pos, rad, bonds, bb.chunk, bb.vis_rec, bb.vis_rect, bb.vis_cnt,
                                                      bb.hist, bb.tile_cnt, bb.ctr);
     if (marks) (void)hipEventRecord(marks[2], stream);
-    k_scan<<<1, kScanThreads, 0, stream>>>(bb.tile_cnt, bb.tile_off, bb.tile_fill, T, bb.capacity, bb.ctr,
-                                           bb.host_ctr);
     if (marks) (void)hipEventRecord(marks[3], stream);
     k_scatter<<<bb.groups, kBinThreads, lds, stream>>>(F, bb.chunk, bb.vis_rec, bb.vis_rect, bb.vis_cnt, bb.hist,
-                                                       bb.tile_cnt, bb.tile_off, bb.tile_fill, bb.list, bb.capacity);
+                                                       bb.tile_cnt, bb.tile_off, bb.tile_fill, bb.list, bb.capacity,
+                                                       bb.ctr, bb.host_ctr);
     return hipGetLastError();
 }
 

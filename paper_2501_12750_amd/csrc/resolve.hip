@@ -139,7 +139,8 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Frame F, uint32_t* __restric
                                                     const PrimRec* __restrict__ vis_rec,
                                                     const uint2* __restrict__ vis_rect,
                                                     const uint32_t* __restrict__ vis_cnt, uint32_t chunk,
-                                                    uint32_t groups, Counters* ctr, Counters* host_ctr,
+                                                    uint32_t groups, uint32_t* __restrict__ fill,
+                                                    Counters* ctr, Counters* host_ctr,
                                                     float* __restrict__ depth, uint32_t* __restrict__ out_id) {
     __shared__ unsigned long long keys[TS * TS];
     __shared__ Rec recs[kChunk];
@@ -169,7 +170,10 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Frame F, uint32_t* __restric
         __syncthreads();
         // every wave has read the tile's count (it sets the trip count of the
         // barrier loop below): re-arm it for the next frame's count kernel
-        if (tid == 0) cnt[t] = 0;
+        if (tid == 0) {
+            cnt[t] = 0;
+            fill[t] = 0;
+        }
 
         // one (record, pixel) ray test folded into the tile's LDS depth buffer
         auto test_pixel = [&](const Rec& rc, int lx, int ly) {
@@ -346,7 +350,8 @@ hipError_t launch_resolve(const Frame& F, const float* pos, const float* rad, co
     const int grid = xcd_grid(T);
 #define VTX_RESOLVE(TS)                                                                                      \
     k_resolve<TS><<<grid, kBlock, 0, stream>>>(F, bb.tile_cnt, bb.tile_off, bb.list, bb.capacity, bb.vis_rec, \
-                                               bb.vis_rect, bb.vis_cnt, bb.chunk, bb.groups, bb.ctr,         \
+                                               bb.vis_rect, bb.vis_cnt, bb.chunk, bb.groups, bb.tile_fill,   \
+                                               bb.ctr,                                                        \
                                                bb.host_ctr, depth, id)
     switch (F.tile) {
         case 8: VTX_RESOLVE(8); break;

@@ -14,7 +14,7 @@ namespace vtx {
 
 constexpr int kBlock = 256;                  // threads per workgroup (4 waves of 64)
 constexpr int kBinThreads = 1024;            // binning workgroups (16 waves)
-constexpr int kMaxLdsTiles = 16320;          // tile histogram of one binning workgroup (< 64 KiB of LDS)
+constexpr int kMaxLdsTiles = 15360;          // tile histogram of one binning workgroup (< 64 KiB of LDS)
 constexpr uint32_t kMaxBinGroups = 512;
 constexpr uint32_t kBackground = 0xFFFFFFFFu;
 constexpr int kMaxSamples = 64;
