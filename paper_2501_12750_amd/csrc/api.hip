@@ -65,6 +65,8 @@ struct Workspace {
     uint64_t want_capacity = 0;
     bool fixed_capacity = false;
     bool dirty = true;              // tile counts / counters must be zeroed before the next frame
+    uint64_t sized_nprim = ~0ull;   // scene and image size the bins were last sized for
+    int sized_w = -1, sized_h = -1;
     vtx_stats last{};
     TimingSlot* tslots = nullptr;   // ring of kTimingRing, created on first timed frame
     int tnext = 0;
@@ -85,7 +87,9 @@ int free_ws_buffers(Workspace* ws) {
     hipFree(ws->bb.vis_rec);
     hipFree(ws->bb.vis_rect);
     hipFree(ws->bb.vis_cnt);
+    hipFree(ws->bb.vis_box);
     hipFree(ws->bb.hist);
+    ws->bb.vis_box = nullptr;
     hipFree(ws->bb.list);
     ws->bb.vis_cnt = nullptr;
     ws->bb.hist = nullptr;
@@ -120,7 +124,7 @@ void harvest(Workspace* ws) {
     ws->have_stats = true;
     ws->pending = false;
     if (c.pairs > ws->bb.capacity && !ws->fixed_capacity) {
-        uint64_t want = c.pairs + c.pairs / 4 + 1024;
+        uint64_t want = c.pairs + c.pairs / 2 + 1024;
         if (want > kMaxCapacity) want = kMaxCapacity;
         if (want > ws->want_capacity) ws->want_capacity = want;
     }
@@ -247,8 +251,9 @@ int ensure_buffers(Workspace* ws, int T, uint64_t nprim) {
         ws->vis_cap = nv;
     }
     if ((size_t)groups > ws->groups_cap || !ws->bb.vis_cnt) {
-        size_t c1 = ws->groups_cap;
+        size_t c1 = ws->groups_cap, c2 = ws->groups_cap;
         if ((rc = grow(&ws->bb.vis_cnt, c1, (size_t)vtx::kMaxBinGroups, ws->stream, "visible counts"))) return rc;
+        if ((rc = grow(&ws->bb.vis_box, c2, (size_t)vtx::kMaxBinGroups, ws->stream, "visible boxes"))) return rc;
         ws->groups_cap = vtx::kMaxBinGroups;
     }
     const size_t nh = (size_t)groups * (size_t)T;
@@ -407,7 +412,26 @@ int gbuffer_locked(const float* positions, const float* radii, int64_t n, const 
     const int T = F.tiles_x * F.tiles_y;
     if ((rc = ensure_buffers(ws, T, (uint64_t)n + (uint64_t)m))) return rc;
     ws->dirty = true;   // until the resolve that re-zeroes the tile counts is queued
-    VTX_HIP(vtx::launch_bin(F, positions, radii, bonds, ws->bb, stream, marks));
+    VTX_HIP(vtx::launch_count(F, positions, radii, bonds, ws->bb, stream, marks));
+    const uint64_t nprim = (uint64_t)n + (uint64_t)m;
+    if (!ws->fixed_capacity && (nprim != ws->sized_nprim || W != ws->sized_w || H != ws->sized_h)) {
+        // first frame of a new scene or image size: wait for the tile counts
+        // and size the bins, so the frame does not take the overflow path
+        unsigned long long counted = 0;
+        VTX_HIP(hipMemcpyAsync(&counted, &ws->bb.ctr->pairs_counted, sizeof(counted), hipMemcpyDeviceToHost, stream));
+        VTX_HIP(hipStreamSynchronize(stream));
+        uint64_t want = counted + counted / 2 + 1024;
+        if (want > kMaxCapacity) want = kMaxCapacity;
+        if (want > ws->want_capacity) ws->want_capacity = want;
+        if (ws->want_capacity > ws->list_alloc) {
+            if ((rc = grow(&ws->bb.list, ws->list_alloc, (size_t)ws->want_capacity, ws->stream, "tile lists"))) return rc;
+        }
+        ws->bb.capacity = ws->want_capacity;
+        ws->sized_nprim = nprim;
+        ws->sized_w = W;
+        ws->sized_h = H;
+    }
+    VTX_HIP(vtx::launch_scatter(F, ws->bb, stream, marks));
     if (marks) VTX_HIP(hipEventRecord(marks[4], stream));
     VTX_HIP(vtx::launch_resolve(F, positions, radii, bonds, ws->bb, depth, id, stream));
     ws->dirty = false;
@@ -416,8 +440,6 @@ int gbuffer_locked(const float* positions, const float* radii, int64_t n, const 
     VTX_HIP(hipEventRecord(ws->done, stream));
     ws->pending = true;
     ws->pending_capacity = ws->bb.capacity;
-    (void)W;
-    (void)H;
     return VTX_OK;
 }
 

@@ -66,15 +66,25 @@ __global__ void __launch_bounds__(kBinThreads) k_count(Frame F, const float* __r
                                                        const float* __restrict__ rad,
                                                        const uint32_t* __restrict__ bonds, uint32_t chunk,
                                                        PrimRec* __restrict__ vis_rec, uint2* __restrict__ vis_rect,
-                                                       uint32_t* __restrict__ vis_cnt, uint32_t* __restrict__ hist_out,
+                                                       uint32_t* __restrict__ vis_cnt, uint2* __restrict__ vis_box,
+                                                       uint32_t* __restrict__ hist_out,
                                                        uint32_t* __restrict__ tile_cnt, Counters* ctr) {
     extern __shared__ uint32_t hist[];
-    __shared__ uint32_t local_n;
+    __shared__ uint32_t local_n, bx0, by0, bx1, by1;
+    __shared__ unsigned long long local_pairs;
     const int T = F.tiles_x * F.tiles_y;
     const int tid = threadIdx.x;
     for (int t = tid; t < T; t += kBinThreads) hist[t] = 0;
-    if (tid == 0) local_n = 0;
+    if (tid == 0) {
+        local_n = 0;
+        local_pairs = 0;
+        bx0 = 0xFFFF;
+        by0 = 0xFFFF;
+        bx1 = 0;
+        by1 = 0;
+    }
     __syncthreads();
+    uint32_t mx0 = 0xFFFF, my0 = 0xFFFF, mx1 = 0, my1 = 0, my_pairs = 0;
 
     const uint64_t total = (uint64_t)F.n_atoms + F.n_bonds;
     const uint64_t start = (uint64_t)blockIdx.x * chunk;
@@ -100,9 +110,21 @@ __global__ void __launch_bounds__(kBinThreads) k_count(Frame F, const float* __r
             vis_rect[slot] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
             for (int ty = ty0; ty <= ty1; ++ty)
                 for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&hist[ty * F.tiles_x + tx], 1u);
+            mx0 = min(mx0, (uint32_t)tx0);
+            my0 = min(my0, (uint32_t)ty0);
+            mx1 = max(mx1, (uint32_t)tx1);
+            my1 = max(my1, (uint32_t)ty1);
+            my_pairs += (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
         }
     }
     if (bad_count) atomicAdd(&ctr->bad_bonds, bad_count);
+    if (my_pairs) {
+        atomicMin(&bx0, mx0);
+        atomicMin(&by0, my0);
+        atomicMax(&bx1, mx1);
+        atomicMax(&by1, my1);
+        atomicAdd(&local_pairs, (unsigned long long)my_pairs);
+    }
     __syncthreads();
     uint32_t* row = hist_out + (size_t)blockIdx.x * T;
     for (int t = tid; t < T; t += kBinThreads) {
@@ -112,7 +134,9 @@ __global__ void __launch_bounds__(kBinThreads) k_count(Frame F, const float* __r
     }
     if (tid == 0) {
         vis_cnt[blockIdx.x] = local_n;
+        vis_box[blockIdx.x] = make_uint2(bx0 | (by0 << 16), bx1 | (by1 << 16));
         atomicAdd(&ctr->vis_count, local_n);
+        if (local_pairs) atomicAdd(&ctr->pairs_counted, local_pairs);
     }
 }
 
@@ -184,6 +208,7 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(Frame F, uint32_t chunk
             ctr->frag_hit = 0;
             ctr->frag_hit_bond = 0;
             ctr->done_blocks = 0;
+            ctr->pairs_counted = 0;
             if (host_ctr) {
                 host_ctr->vis_count = vis;
                 host_ctr->bad_bonds = bad;
@@ -239,15 +264,21 @@ hipError_t launch_zero(uint32_t* p, size_t n, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_bin(const Frame& F, const float* pos, const float* rad, const uint32_t* bonds,
-                      const BinBuffers& bb, hipStream_t stream, hipEvent_t* marks) {
+hipError_t launch_count(const Frame& F, const float* pos, const float* rad, const uint32_t* bonds,
+                        const BinBuffers& bb, hipStream_t stream, hipEvent_t* marks) {
     const int T = F.tiles_x * F.tiles_y;
     if (T > kMaxLdsTiles) return hipErrorInvalidValue;
     const size_t lds = (size_t)T * sizeof(uint32_t);
     if (marks) (void)hipEventRecord(marks[0], stream);
     if (marks) (void)hipEventRecord(marks[1], stream);
     k_count<<<bb.groups, kBinThreads, lds, stream>>>(F, pos, rad, bonds, bb.chunk, bb.vis_rec, bb.vis_rect, bb.vis_cnt,
-                                                     bb.hist, bb.tile_cnt, bb.ctr);
+                                                     bb.vis_box, bb.hist, bb.tile_cnt, bb.ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const Frame& F, const BinBuffers& bb, hipStream_t stream, hipEvent_t* marks) {
+    const int T = F.tiles_x * F.tiles_y;
+    const size_t lds = (size_t)T * sizeof(uint32_t);
     if (marks) (void)hipEventRecord(marks[2], stream);
     if (marks) (void)hipEventRecord(marks[3], stream);
     k_scatter<<<bb.groups, kBinThreads, lds, stream>>>(F, bb.chunk, bb.vis_rec, bb.vis_rect, bb.vis_cnt, bb.hist,

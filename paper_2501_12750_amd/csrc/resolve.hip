@@ -138,7 +138,8 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Frame F, uint32_t* __restric
                                                     const PrimRec* __restrict__ list, uint64_t capacity,
                                                     const PrimRec* __restrict__ vis_rec,
                                                     const uint2* __restrict__ vis_rect,
-                                                    const uint32_t* __restrict__ vis_cnt, uint32_t chunk,
+                                                    const uint32_t* __restrict__ vis_cnt,
+                                                    const uint2* __restrict__ vis_box, uint32_t chunk,
                                                     uint32_t groups, uint32_t* __restrict__ fill,
                                                     Counters* ctr, Counters* host_ctr,
                                                     float* __restrict__ depth, uint32_t* __restrict__ out_id) {
@@ -207,6 +208,10 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Frame F, uint32_t* __restric
             }
             const uint32_t g = (uint32_t)(k / chunk);
             if ((uint32_t)(k - (uint64_t)g * chunk) >= vis_cnt[g]) return false;
+            const uint2 gb = vis_box[g];    // skip workgroups whose primitives cannot touch this tile
+            if (tx < (int)(gb.x & 0xFFFF) || tx > (int)(gb.y & 0xFFFF) || ty < (int)(gb.x >> 16) ||
+                ty > (int)(gb.y >> 16))
+                return false;
             const uint2 r = vis_rect[k];
             const int x0 = max((int)(r.x & 0xFFFF), px0) - px0, y0 = max((int)(r.x >> 16), py0) - py0;
             const int x1 = min((int)(r.y & 0xFFFF), px0 + TS - 1) - px0;
@@ -350,7 +355,8 @@ hipError_t launch_resolve(const Frame& F, const float* pos, const float* rad, co
     const int grid = xcd_grid(T);
 #define VTX_RESOLVE(TS)                                                                                      \
     k_resolve<TS><<<grid, kBlock, 0, stream>>>(F, bb.tile_cnt, bb.tile_off, bb.list, bb.capacity, bb.vis_rec, \
-                                               bb.vis_rect, bb.vis_cnt, bb.chunk, bb.groups, bb.tile_fill,   \
+                                               bb.vis_rect, bb.vis_cnt, bb.vis_box, bb.chunk, bb.groups,     \
+                                               bb.tile_fill,                                                  \
                                                bb.ctr,                                                        \
                                                bb.host_ctr, depth, id)
     switch (F.tile) {

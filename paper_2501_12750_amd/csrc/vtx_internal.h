@@ -55,7 +55,8 @@ struct Counters {
     unsigned long long frag_hit;
     unsigned long long frag_hit_bond;
     unsigned int done_blocks;
-    unsigned int pad[3];
+    unsigned int pad;
+    unsigned long long pairs_counted;   // total of the tile counts, added by the count kernel
 };
 
 // View-space record of one visible primitive (32 bytes), computed once per
@@ -122,31 +123,55 @@ __device__ inline void ndc_to_pixels(double lo, double hi, int n, bool flip, int
     p1 = (int)fmax(b, -1.0);
 }
 
+// NDC interval along one axis covered by the view-space box
+// [c_lo, c_hi] x [z_lo, z_hi] with z_lo > 0 (perspective): the projection of
+// a box in front of the eye is the convex hull of its projected corners.
+__device__ inline void box_ndc_interval(double c_lo, double c_hi, double z_lo, double z_hi, double tscale,
+                                        double& lo, double& hi) {
+    lo = fmin(c_lo / z_lo, c_lo / z_hi) / tscale;
+    hi = fmax(c_hi / z_lo, c_hi / z_hi) / tscale;
+}
+
 // Conservative pixel rectangle of a sphere of view centre v and radius r.
-// Returns false when no pixel can hold a hit with znear <= z <= zfar.
+// Returns false when no pixel can hold a hit with znear <= z <= zfar.  A
+// sphere that reaches the eye plane has an unbounded projection, but only its
+// part with z >= znear can be hit: that part lies in its bounding box cut at
+// znear, whose projected corners bound it.
 __device__ inline bool sphere_rect(const Frame& F, double vx, double vy, double vz, double r, int& x0,
                                    int& y0, int& x1, int& y1) {
     if (!(r > 0.0)) return false;
     if (vz + r < F.znear || vz - r > F.zfar) return false;
     double lo, hi;
-    if (sphere_ndc_interval(F, vx, vz, r, F.tx, F.hx, lo, hi)) ndc_to_pixels(lo, hi, F.W, false, x0, x1);
-    else { x0 = 0; x1 = F.W - 1; }
-    if (sphere_ndc_interval(F, vy, vz, r, F.ty, F.hy, lo, hi)) ndc_to_pixels(lo, hi, F.H, true, y0, y1);
-    else { y0 = 0; y1 = F.H - 1; }
+    if (sphere_ndc_interval(F, vx, vz, r, F.tx, F.hx, lo, hi)) {
+        ndc_to_pixels(lo, hi, F.W, false, x0, x1);
+        sphere_ndc_interval(F, vy, vz, r, F.ty, F.hy, lo, hi);
+        ndc_to_pixels(lo, hi, F.H, true, y0, y1);
+    } else {
+        const double zl = F.znear, zh = vz + r;
+        box_ndc_interval(vx - r, vx + r, zl, zh, F.tx, lo, hi);
+        ndc_to_pixels(lo, hi, F.W, false, x0, x1);
+        box_ndc_interval(vy - r, vy + r, zl, zh, F.ty, lo, hi);
+        ndc_to_pixels(lo, hi, F.H, true, y0, y1);
+    }
     return x0 <= x1 && y0 <= y1;
 }
 
 // Conservative pixel rectangle of a capped cylinder of radius rho between
 // view points A and B: it lies inside the capsule (the convex hull of the two
 // end balls), whose projection's bounding box is the union of the two balls'
-// boxes when both lie in front of the eye plane.
+// boxes when both lie in front of the eye plane; otherwise its part with
+// z >= znear lies in the capsule's bounding box cut at znear.
 __device__ inline bool bond_rect(const Frame& F, const double* A, const double* B, double rho, int& x0,
                                  int& y0, int& x1, int& y1) {
     const double zlo = fmin(A[2], B[2]) - rho, zhi = fmax(A[2], B[2]) + rho;
     if (zhi < F.znear || zlo > F.zfar) return false;
     if (F.proj == 0 && !(zlo > 0.0)) {
-        x0 = 0; y0 = 0; x1 = F.W - 1; y1 = F.H - 1;
-        return true;
+        double lo, hi;
+        box_ndc_interval(fmin(A[0], B[0]) - rho, fmax(A[0], B[0]) + rho, F.znear, zhi, F.tx, lo, hi);
+        ndc_to_pixels(lo, hi, F.W, false, x0, x1);
+        box_ndc_interval(fmin(A[1], B[1]) - rho, fmax(A[1], B[1]) + rho, F.znear, zhi, F.ty, lo, hi);
+        ndc_to_pixels(lo, hi, F.H, true, y0, y1);
+        return x0 <= x1 && y0 <= y1;
     }
     double la, ha, lb, hb;
     sphere_ndc_interval(F, A[0], A[2], rho, F.tx, F.hx, la, ha);
@@ -179,6 +204,8 @@ struct BinBuffers {
     PrimRec* vis_rec;       // groups * chunk visible-primitive records
     uint2* vis_rect;        // groups * chunk, pixel rectangle packed (x0 | y0 << 16, x1 | y1 << 16)
     uint32_t* vis_cnt;      // groups: visible primitives of each workgroup
+    uint2* vis_box;         // groups: tile-space bounding box of each workgroup's visible
+                            // primitives, packed like vis_rect (empty: x0 > x1)
     uint32_t* hist;         // groups * T: tile histogram of each workgroup
     PrimRec* list;          // capacity entries, each tile's records contiguous
     uint64_t capacity;
@@ -196,8 +223,9 @@ hipError_t launch_zero(uint32_t* p, size_t n, hipStream_t stream);
 
 // `marks`, when not null, holds events recorded before each kernel launch
 // (bin: clear, project, scan, scatter) for per-kernel timing.
-hipError_t launch_bin(const Frame& F, const float* pos, const float* rad, const uint32_t* bonds,
-                      const BinBuffers& bb, hipStream_t stream, hipEvent_t* marks = nullptr);
+hipError_t launch_count(const Frame& F, const float* pos, const float* rad, const uint32_t* bonds,
+                        const BinBuffers& bb, hipStream_t stream, hipEvent_t* marks = nullptr);
+hipError_t launch_scatter(const Frame& F, const BinBuffers& bb, hipStream_t stream, hipEvent_t* marks = nullptr);
 hipError_t launch_resolve(const Frame& F, const float* pos, const float* rad, const uint32_t* bonds,
                           const BinBuffers& bb, float* depth, uint32_t* id, hipStream_t stream);
 hipError_t launch_shade(const Frame& F, const SampleKernel& K, const float* pos, const float* rad,
