@@ -171,6 +171,69 @@ int vtx_shade(const float* positions, const float* radii, const uint32_t* colors
               int32_t W, int32_t H, const float* depth, const uint32_t* id, uint32_t* rgba,
               float* normal, uint32_t* albedo, float* ao, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Resident scenes.  A context tracks the device memory its scenes hold
+ * against a budget; a scene is a library-owned copy of a molecule kept in
+ * device memory across frames, laid out for the per-frame passes (atoms
+ * reordered along a Morton curve into one xyzr stream, with per-cluster
+ * bounding boxes for frustum culling), following the paper's "adapted data
+ * structures" for millions of atoms (Methods, "Molecular Graphics Engine").
+ * Rendering a scene gives exactly the images vtx_render gives for the same
+ * arrays (ids are the original atom and bond indices).
+ * ------------------------------------------------------------------------- */
+typedef struct vtx_context vtx_context;
+typedef struct vtx_scene vtx_scene;
+
+/* vtx_context_create - context on HIP device `device`; scenes created in it
+ * may hold at most hbm_budget_bytes of device memory (0 = no limit).
+ * VTX_EINVAL for a bad device. */
+int vtx_context_create(int device, size_t hbm_budget_bytes, vtx_context** out);
+/* vtx_context_destroy - frees the context (its scenes must be destroyed first). */
+void vtx_context_destroy(vtx_context* ctx);
+/* vtx_context_bytes_in_use - device bytes held by the context's scenes. */
+size_t vtx_context_bytes_in_use(const vtx_context* ctx);
+
+/* vtx_scene_footprint_bytes - device bytes a scene of this size holds. */
+size_t vtx_scene_footprint_bytes(int64_t n_atoms, int64_t n_bonds);
+/* vtx_frame_scratch_bytes - device bytes of per-stream scratch a frame of
+ * this size needs at the start (tile bins grow afterwards if needed). */
+size_t vtx_frame_scratch_bytes(int32_t W, int32_t H, int64_t n_atoms, int64_t n_bonds);
+
+/*
+ * vtx_scene_create - copies the arrays (same meaning as for vtx_render; all
+ * device pointers, which the caller may free afterwards) into a new scene of
+ * `ctx` on the current device (which must be the context's) and lays them
+ * out.  Runs on `stream` and waits for it.  Bonds with an index >= n_atoms
+ * are dropped (vtx_scene_info reports how many).  VTX_EBUSY if the scene
+ * would exceed the context's budget; VTX_ENOMEM, VTX_EINVAL, VTX_EHIP.
+ */
+int vtx_scene_create(vtx_context* ctx, const float* positions, const float* radii, const uint32_t* colors,
+                     int64_t n_atoms, const uint32_t* bonds, int64_t n_bonds, void* stream, vtx_scene** out);
+
+/*
+ * vtx_scene_update_positions - new positions (n_atoms x 3 float, device,
+ * original atom order) for the next frames, e.g. a trajectory frame (paper,
+ * "High Quality Rendering": dynamic data is re-rendered every frame).  Radii,
+ * colours and bonds are kept.  Queued on `stream`; frames queued on that
+ * stream afterwards see the new positions.
+ */
+int vtx_scene_update_positions(vtx_scene* scene, const float* positions, void* stream);
+
+/* vtx_scene_info - sizes of a scene and how many bonds were dropped. */
+int vtx_scene_info(const vtx_scene* scene, int64_t* n_atoms, int64_t* n_bonds, uint64_t* bad_bonds, size_t* bytes);
+
+/* vtx_scene_destroy - waits for the device and frees the scene. */
+void vtx_scene_destroy(vtx_scene* scene);
+
+/*
+ * vtx_render_scene - vtx_render for a resident scene: the frame's visibility
+ * pass starts by testing the scene's clusters against the view volume and
+ * only bins the atoms and bonds of the clusters that pass.  Outputs as for
+ * vtx_render.
+ */
+int vtx_render_scene(vtx_scene* scene, const vtx_camera* cam, const vtx_options* opt, int32_t W, int32_t H,
+                     uint32_t* rgba, float* depth, uint32_t* id, void* stream);
+
 /*
  * vtx_read_stats - waits for `stream` to drain, then returns the counters of
  * the last frame queued on it by this library.  VTX_EINVAL if none was.

@@ -219,7 +219,7 @@ int grow(T** p, size_t& cap, size_t want, hipStream_t stream, const char* what) 
     return VTX_OK;
 }
 
-int ensure_buffers(Workspace* ws, int T, uint64_t nprim) {
+int ensure_buffers(Workspace* ws, int T, uint64_t nprim, uint32_t groups, uint32_t chunk) {
     size_t tc = ws->tiles_cap;
     int rc;
     if ((size_t)T > ws->tiles_cap || !ws->bb.tile_cnt) {
@@ -239,8 +239,6 @@ int ensure_buffers(Workspace* ws, int T, uint64_t nprim) {
                                  ws->stream));
         ws->dirty = false;
     }
-    uint32_t groups, chunk;
-    vtx::bin_grid(nprim, &groups, &chunk);
     ws->bb.groups = groups;
     ws->bb.chunk = chunk;
     const size_t nv = (size_t)groups * chunk;
@@ -337,6 +335,8 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
     F->hy = (double)cam->ortho_half_height;
     F->txf = (float)F->tx;
     F->tyf = (float)F->ty;
+    F->sxf = (float)std::sqrt(1.0 + F->tx * F->tx) * (1.0f + 1e-6f);
+    F->syf = (float)std::sqrt(1.0 + F->ty * F->ty) * (1.0f + 1e-6f);
     F->hxf = (float)F->hx;
     F->hyf = (float)F->hy;
     F->inv_w2 = 2.0f / (float)W;
@@ -404,15 +404,31 @@ void sample_kernel(const vtx_options& o, vtx::SampleKernel* K) {
 
 int gbuffer_locked(const float* positions, const float* radii, int64_t n, const uint32_t* bonds, int64_t m,
                    const Frame& F, int32_t W, int32_t H, float* depth, uint32_t* id, hipStream_t stream,
-                   hipEvent_t* marks = nullptr) {
+                   hipEvent_t* marks = nullptr, const vtx::SceneDev* scene = nullptr) {
     Workspace* ws = nullptr;
     int rc = get_workspace(stream, &ws);
     if (rc) return rc;
     harvest(ws);
     const int T = F.tiles_x * F.tiles_y;
-    if ((rc = ensure_buffers(ws, T, (uint64_t)n + (uint64_t)m))) return rc;
+    uint32_t groups, chunk;
+    if (!scene) {
+        vtx::bin_grid((uint64_t)n + (uint64_t)m, &groups, &chunk);
+    } else {
+        // resident scene: each binning workgroup takes whole clusters
+        const uint64_t nc = (uint64_t)scene->atom_clusters + scene->bond_clusters;
+        vtx::bin_grid((uint64_t)n + (uint64_t)m, &groups, &chunk);
+        const uint64_t cpw = (nc + groups - 1) / groups;
+        chunk = (uint32_t)((cpw ? cpw : 1) * vtx::kCluster);
+    }
+    if ((rc = ensure_buffers(ws, T, (uint64_t)n + (uint64_t)m, groups, chunk))) return rc;
     ws->dirty = true;   // until the resolve that re-zeroes the tile counts is queued
-    VTX_HIP(vtx::launch_count(F, positions, radii, bonds, ws->bb, stream, marks));
+    if (!scene) {
+        VTX_HIP(vtx::launch_count(F, positions, radii, bonds, ws->bb, stream, marks));
+    } else {
+        if (marks) VTX_HIP(hipEventRecord(marks[0], stream));
+        VTX_HIP(vtx::launch_cluster_cull(F, *scene, ws->bb.ctr, stream));
+        VTX_HIP(vtx::launch_count_scene(F, *scene, ws->bb, stream, marks));
+    }
     const uint64_t nprim = (uint64_t)n + (uint64_t)m;
     if (!ws->fixed_capacity && (nprim != ws->sized_nprim || W != ws->sized_w || H != ws->sized_h)) {
         // first frame of a new scene or image size: wait for the tile counts
@@ -440,6 +456,64 @@ int gbuffer_locked(const float* positions, const float* radii, int64_t n, const 
     VTX_HIP(hipEventRecord(ws->done, stream));
     ws->pending = true;
     ws->pending_capacity = ws->bb.capacity;
+    return VTX_OK;
+}
+
+}  // namespace
+
+struct vtx_context {
+    int device = 0;
+    size_t budget = 0;       // bytes of scenes this context may keep resident (0 = no limit)
+    size_t used = 0;
+    std::mutex mu;
+};
+
+struct vtx_scene {
+    vtx_context* ctx = nullptr;
+    int device = 0;
+    int64_t n = 0, m = 0;
+    uint32_t bad_bonds = 0;
+    size_t bytes = 0;
+    vtx::SceneDev S{};
+    float4* xyzr = nullptr;
+    uint32_t* atom_id = nullptr;
+    uint4* bond_rec = nullptr;
+    float4* cluster_box = nullptr;
+    uint32_t* vis_clusters = nullptr;
+    // caller's arrays in their original order (the deferred pass reads them by id)
+    float* pos = nullptr;
+    float* rad = nullptr;
+    uint32_t* col = nullptr;
+    uint32_t* bonds = nullptr;
+};
+
+namespace {
+
+size_t scene_bytes(int64_t n, int64_t m) {
+    const size_t nc = (size_t)((n + vtx::kCluster - 1) / vtx::kCluster + (m + vtx::kCluster - 1) / vtx::kCluster);
+    return (size_t)n * (sizeof(float4) + sizeof(uint32_t) + 3 * sizeof(float) + sizeof(float) + sizeof(uint32_t)) +
+           (size_t)m * (sizeof(uint4) + 2 * sizeof(uint32_t)) + nc * (2 * sizeof(float4) + sizeof(uint32_t));
+}
+
+void scene_free(vtx_scene* sc) {
+    hipFree(sc->xyzr);
+    hipFree(sc->atom_id);
+    hipFree(sc->bond_rec);
+    hipFree(sc->cluster_box);
+    hipFree(sc->vis_clusters);
+    hipFree(sc->pos);
+    hipFree(sc->rad);
+    hipFree(sc->col);
+    hipFree(sc->bonds);
+}
+
+template <class T>
+int dev_alloc(T** p, size_t count, const char* what) {
+    *p = nullptr;
+    if (hipMalloc(p, (count ? count : 1) * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(VTX_ENOMEM, "cannot allocate %zu bytes for %s", (count ? count : 1) * sizeof(T), what);
+    }
     return VTX_OK;
 }
 
@@ -502,6 +576,172 @@ int vtx_render(const float* positions, const float* radii, const uint32_t* color
     if (marks) VTX_HIP(hipEventRecord(marks[5], (hipStream_t)stream));
     VTX_HIP(vtx::launch_shade(F, K, positions, radii, colors, bonds, depth, id, rgba, nullptr, nullptr, nullptr,
                               (hipStream_t)stream));
+    if (marks) VTX_HIP(hipEventRecord(marks[6], (hipStream_t)stream));
+    return VTX_OK;
+}
+
+int vtx_context_create(int device, size_t hbm_budget_bytes, vtx_context** out) {
+    if (!out) return fail(VTX_EINVAL, "out is NULL");
+    int count = 0;
+    VTX_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(VTX_EINVAL, "device %d not in 0..%d", device, count - 1);
+    vtx_context* c = new vtx_context();
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    *out = c;
+    return VTX_OK;
+}
+
+void vtx_context_destroy(vtx_context* ctx) { delete ctx; }
+
+size_t vtx_context_bytes_in_use(const vtx_context* ctx) { return ctx ? ctx->used : 0; }
+
+size_t vtx_scene_footprint_bytes(int64_t n_atoms, int64_t n_bonds) {
+    if (n_atoms < 0 || n_bonds < 0) return 0;
+    return scene_bytes(n_atoms, n_bonds);
+}
+
+size_t vtx_frame_scratch_bytes(int32_t W, int32_t H, int64_t n_atoms, int64_t n_bonds) {
+    if (W < 1 || H < 1 || n_atoms < 0 || n_bonds < 0) return 0;
+    int ts = 16;
+    while ((int64_t)((W + ts - 1) / ts) * ((H + ts - 1) / ts) > vtx::kMaxLdsTiles) ts *= 2;
+    const uint64_t T = (uint64_t)((W + ts - 1) / ts) * ((H + ts - 1) / ts);
+    const uint64_t nprim = (uint64_t)n_atoms + (uint64_t)n_bonds;
+    uint32_t groups, chunk;
+    vtx::bin_grid(nprim, &groups, &chunk);
+    uint64_t cap = nprim / 2;
+    if (cap < kMinCapacity) cap = kMinCapacity;
+    return (size_t)(T * 16 + (uint64_t)groups * chunk * (sizeof(vtx::PrimRec) + sizeof(uint2)) +
+                    (uint64_t)groups * T * 4 + cap * sizeof(vtx::PrimRec) + sizeof(Counters) + 4096);
+}
+
+int vtx_scene_create(vtx_context* ctx, const float* positions, const float* radii, const uint32_t* colors,
+                     int64_t n_atoms, const uint32_t* bonds, int64_t n_bonds, void* stream, vtx_scene** out) {
+    if (!ctx || !out) return fail(VTX_EINVAL, "context/out is NULL");
+    if (n_atoms < 0 || n_bonds < 0 || n_atoms + n_bonds >= (int64_t)0xFFFFFFFFll)
+        return fail(VTX_EINVAL, "n_atoms=%lld n_bonds=%lld out of range", (long long)n_atoms, (long long)n_bonds);
+    int rc = check_inputs(positions, radii, colors, n_atoms, bonds, n_bonds, true);
+    if (rc) return rc;
+    int dev = 0;
+    VTX_HIP(hipGetDevice(&dev));
+    if (dev != ctx->device) return fail(VTX_EINVAL, "current device %d is not the context's %d", dev, ctx->device);
+    const size_t bytes = scene_bytes(n_atoms, n_bonds);
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->budget && ctx->used + bytes > ctx->budget)
+            return fail(VTX_EBUSY, "scene of %zu bytes exceeds the context budget (%zu of %zu in use)", bytes,
+                        ctx->used, ctx->budget);
+        ctx->used += bytes;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    vtx_scene* sc = new vtx_scene();
+    sc->ctx = ctx;
+    sc->device = dev;
+    sc->n = n_atoms;
+    sc->m = n_bonds;
+    sc->bytes = bytes;
+    const size_t na = (size_t)n_atoms, nb = (size_t)n_bonds;
+    const size_t ncl = (na + vtx::kCluster - 1) / vtx::kCluster + (nb + vtx::kCluster - 1) / vtx::kCluster;
+    void* tmp = nullptr;
+    const size_t tmp_bytes = vtx::scene_build_temp_bytes(na, nb);
+    uint32_t m_valid = 0, n_bad = 0;
+    auto bail = [&](int code) {
+        scene_free(sc);
+        hipFree(tmp);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->used -= bytes;
+        delete sc;
+        return code;
+    };
+    if ((rc = dev_alloc(&sc->xyzr, na, "atom stream")) || (rc = dev_alloc(&sc->atom_id, na, "atom ids")) ||
+        (rc = dev_alloc(&sc->bond_rec, nb, "bond records")) || (rc = dev_alloc(&sc->cluster_box, 2 * ncl, "cluster boxes")) ||
+        (rc = dev_alloc(&sc->vis_clusters, ncl, "visible clusters")) || (rc = dev_alloc(&sc->pos, 3 * na, "positions")) ||
+        (rc = dev_alloc(&sc->rad, na, "radii")) || (rc = dev_alloc(&sc->col, na, "colours")) ||
+        (rc = dev_alloc(&sc->bonds, 2 * nb, "bonds")))
+        return bail(rc);
+    if (hipMalloc(&tmp, tmp_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(fail(VTX_ENOMEM, "cannot allocate %zu bytes of build scratch", tmp_bytes));
+    }
+    if ((na && (hipMemcpyAsync(sc->pos, positions, 3 * na * sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(sc->rad, radii, na * sizeof(float), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(sc->col, colors, na * sizeof(uint32_t), hipMemcpyDeviceToDevice, st) != hipSuccess)) ||
+        (nb && hipMemcpyAsync(sc->bonds, bonds, 2 * nb * sizeof(uint32_t), hipMemcpyDeviceToDevice, st) != hipSuccess))
+        return bail(fail(VTX_EHIP, "copying the scene arrays failed"));
+    sc->S.n_atoms = (uint32_t)na;
+    sc->S.n_bonds_total = (uint32_t)nb;
+    sc->S.xyzr = sc->xyzr;
+    sc->S.atom_id = sc->atom_id;
+    sc->S.bond_rec = sc->bond_rec;
+    sc->S.vis_clusters = sc->vis_clusters;
+    hipError_t e = vtx::scene_build(sc->pos, sc->rad, sc->bonds, na, nb, sc->S, sc->xyzr, sc->atom_id, sc->bond_rec,
+                                    sc->cluster_box, tmp, tmp_bytes, &m_valid, &n_bad, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bail(fail(VTX_EHIP, "building the scene failed: %s", hipGetErrorString(e)));
+    hipFree(tmp);
+    sc->bad_bonds = n_bad;
+    *out = sc;
+    return VTX_OK;
+}
+
+int vtx_scene_update_positions(vtx_scene* scene, const float* positions, void* stream) {
+    if (!scene || (scene->n > 0 && !positions)) return fail(VTX_EINVAL, "scene/positions is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    if (scene->n)
+        VTX_HIP(hipMemcpyAsync(scene->pos, positions, 3 * (size_t)scene->n * sizeof(float), hipMemcpyDeviceToDevice, st));
+    VTX_HIP(vtx::scene_update_positions(scene->pos, scene->S, scene->xyzr, scene->cluster_box, st));
+    return VTX_OK;
+}
+
+int vtx_scene_info(const vtx_scene* scene, int64_t* n_atoms, int64_t* n_bonds, uint64_t* bad_bonds,
+                   size_t* bytes) {
+    if (!scene) return fail(VTX_EINVAL, "scene is NULL");
+    if (n_atoms) *n_atoms = scene->n;
+    if (n_bonds) *n_bonds = scene->m;
+    if (bad_bonds) *bad_bonds = scene->bad_bonds;
+    if (bytes) *bytes = scene->bytes;
+    return VTX_OK;
+}
+
+void vtx_scene_destroy(vtx_scene* scene) {
+    if (!scene) return;
+    (void)hipDeviceSynchronize();
+    scene_free(scene);
+    if (scene->ctx) {
+        std::lock_guard<std::mutex> lk(scene->ctx->mu);
+        scene->ctx->used -= scene->bytes;
+    }
+    delete scene;
+}
+
+int vtx_render_scene(vtx_scene* scene, const vtx_camera* cam, const vtx_options* opt, int32_t W, int32_t H,
+                     uint32_t* rgba, float* depth, uint32_t* id, void* stream) {
+    if (!scene) return fail(VTX_EINVAL, "scene is NULL");
+    const vtx_options o = resolve_options(opt);
+    Frame F;
+    int rc = make_frame(cam, o, W, H, scene->n, scene->m, &F);
+    if (rc) return rc;
+    if (!depth || !id || !rgba) return fail(VTX_EINVAL, "rgba/depth/id outputs are NULL");
+    int dev = 0;
+    VTX_HIP(hipGetDevice(&dev));
+    if (dev != scene->device) return fail(VTX_EINVAL, "scene lives on device %d, current is %d", scene->device, dev);
+    vtx::SampleKernel K;
+    sample_kernel(o, &K);
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipEvent_t* marks = nullptr;
+    if (o.flags & VTX_FLAG_TIMING) {
+        Workspace* ws = nullptr;
+        if ((rc = get_workspace((hipStream_t)stream, &ws))) return rc;
+        TimingSlot* slot = nullptr;
+        if ((rc = timing_slot(ws, &slot))) return rc;
+        marks = slot->ev;
+    }
+    rc = gbuffer_locked(scene->pos, scene->rad, scene->n, scene->bonds, scene->m, F, W, H, depth, id,
+                        (hipStream_t)stream, marks, &scene->S);
+    if (rc) return rc;
+    if (marks) VTX_HIP(hipEventRecord(marks[5], (hipStream_t)stream));
+    VTX_HIP(vtx::launch_shade(F, K, scene->pos, scene->rad, scene->col, scene->bonds, depth, id, rgba, nullptr,
+                              nullptr, nullptr, (hipStream_t)stream));
     if (marks) VTX_HIP(hipEventRecord(marks[6], (hipStream_t)stream));
     return VTX_OK;
 }

@@ -31,6 +31,30 @@ __global__ void __launch_bounds__(kBlock) k_zero(uint32_t* p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
+// View-space record and footprint of a sphere (id = primitive id); false if
+// it cannot show.  The FP32 frustum test rejects most off-screen spheres
+// before the exact FP64 footprint.
+__device__ inline bool sphere_record(const Frame& F, double vx, double vy, double vz, double r, uint32_t id, int& x0,
+                                     int& y0, int& x1, int& y1, PrimRec& rec) {
+    if (!(r > 0.0) || !sphere_in_frustum(F, vx, vy, vz, r)) return false;
+    rec.g0 = make_float4((float)vx, (float)vy, (float)vz, (float)r);
+    rec.g1 = make_uint4(0u, 0u, id, 0u);
+    return sphere_rect(F, vx, vy, vz, r, x0, y0, x1, y1);
+}
+
+// Same for a bond between view points A and B (the difference B - A is kept
+// from FP64, so the axis is accurate however far the bond is).
+__device__ inline bool bond_record(const Frame& F, const double* A, const double* B, uint32_t id, int& x0, int& y0,
+                                   int& x1, int& y1, PrimRec& rec) {
+    const double rho = F.bond_radius;
+    const double dx = B[0] - A[0], dy = B[1] - A[1], dz = B[2] - A[2];
+    const double half = 0.5 * sqrt(dx * dx + dy * dy + dz * dz);
+    if (!sphere_in_frustum(F, A[0] + 0.5 * dx, A[1] + 0.5 * dy, A[2] + 0.5 * dz, half + rho)) return false;
+    rec.g0 = make_float4((float)A[0], (float)A[1], (float)A[2], (float)dx);
+    rec.g1 = make_uint4(__float_as_uint((float)dy), __float_as_uint((float)dz), id, 0u);
+    return bond_rect(F, A, B, rho, x0, y0, x1, y1);
+}
+
 // Footprint and view-space record of primitive p; false if it cannot show.
 __device__ inline bool primitive_record(const Frame& F, uint32_t p, const float* __restrict__ pos,
                                         const float* __restrict__ rad, const uint32_t* __restrict__ bonds,
@@ -39,10 +63,7 @@ __device__ inline bool primitive_record(const Frame& F, uint32_t p, const float*
     if (p < F.n_atoms) {
         double vx, vy, vz;
         to_view(F, pos[3 * (size_t)p], pos[3 * (size_t)p + 1], pos[3 * (size_t)p + 2], vx, vy, vz);
-        const double r = (double)rad[p];
-        rec.g0 = make_float4((float)vx, (float)vy, (float)vz, (float)r);
-        rec.g1 = make_uint4(0u, 0u, p, 0u);
-        return sphere_rect(F, vx, vy, vz, r, x0, y0, x1, y1);
+        return sphere_record(F, vx, vy, vz, (double)rad[p], p, x0, y0, x1, y1, rec);
     }
     const size_t b = p - F.n_atoms;
     const uint32_t ia = bonds[2 * b], ib = bonds[2 * b + 1];
@@ -57,14 +78,72 @@ __device__ inline bool primitive_record(const Frame& F, uint32_t p, const float*
     double A[3], B[3];
     to_view(F, ax, ay, az, A[0], A[1], A[2]);
     to_view(F, bx, by, bz, B[0], B[1], B[2]);
-    rec.g0 = make_float4((float)A[0], (float)A[1], (float)A[2], (float)(B[0] - A[0]));
-    rec.g1 = make_uint4(__float_as_uint((float)(B[1] - A[1])), __float_as_uint((float)(B[2] - A[2])), p, 0u);
-    return bond_rect(F, A, B, (double)F.bond_radius, x0, y0, x1, y1);
+    return bond_record(F, A, B, p, x0, y0, x1, y1, rec);
 }
 
-__global__ void __launch_bounds__(kBinThreads) k_count(Frame F, const float* __restrict__ pos,
-                                                       const float* __restrict__ rad,
-                                                       const uint32_t* __restrict__ bonds, uint32_t chunk,
+// Primitive sources of the count kernel.  Workgroup b owns items
+// [0, items(b)) and the visible-list region [b * chunk, (b + 1) * chunk).
+struct PlainSource {     // the caller's arrays, primitives in their given order
+    const float* pos;
+    const float* rad;
+    const uint32_t* bonds;
+    uint64_t total;
+    uint32_t chunk;
+    __device__ uint64_t items(uint32_t b) const {
+        const uint64_t s = (uint64_t)b * chunk;
+        return s < total ? min((uint64_t)chunk, total - s) : 0;
+    }
+    __device__ bool record(const Frame& F, uint32_t b, uint64_t k, int& x0, int& y0, int& x1, int& y1, PrimRec& rec,
+                           bool& bad) const {
+        return primitive_record(F, (uint32_t)((uint64_t)b * chunk + k), pos, rad, bonds, x0, y0, x1, y1, rec, bad);
+    }
+};
+
+struct SceneSource {     // a resident scene: the clusters that passed the frustum test
+    SceneDev S;
+    const Counters* ctr;
+    uint32_t groups;
+    __device__ void range(uint32_t b, uint32_t& c0, uint32_t& c1) const {
+        const uint32_t nvc = ctr->vis_clusters;
+        const uint32_t cpw = (nvc + groups - 1) / groups;
+        c0 = min(nvc, b * cpw);
+        c1 = min(nvc, c0 + cpw);
+    }
+    __device__ uint64_t items(uint32_t b) const {
+        uint32_t c0, c1;
+        range(b, c0, c1);
+        return (uint64_t)(c1 - c0) * kCluster;
+    }
+    __device__ bool record(const Frame& F, uint32_t b, uint64_t k, int& x0, int& y0, int& x1, int& y1, PrimRec& rec,
+                           bool& bad) const {
+        bad = false;
+        uint32_t c0, c1;
+        range(b, c0, c1);
+        const uint32_t c = S.vis_clusters[c0 + (uint32_t)(k / kCluster)];
+        const uint32_t slot = (uint32_t)(k % kCluster);
+        if (c < S.atom_clusters) {
+            const uint32_t i = c * kCluster + slot;
+            if (i >= S.n_atoms) return false;
+            const float4 a = S.xyzr[i];
+            double vx, vy, vz;
+            to_view(F, a.x, a.y, a.z, vx, vy, vz);
+            return sphere_record(F, vx, vy, vz, (double)a.w, S.atom_id[i], x0, y0, x1, y1, rec);
+        }
+        const uint32_t j = (c - S.atom_clusters) * kCluster + slot;
+        if (j >= S.n_bonds) return false;
+        const uint4 br = S.bond_rec[j];
+        if (br.x == br.y) return false;
+        const float4 a = S.xyzr[br.x], bb = S.xyzr[br.y];
+        if (a.x == bb.x && a.y == bb.y && a.z == bb.z) return false;
+        double A[3], B[3];
+        to_view(F, a.x, a.y, a.z, A[0], A[1], A[2]);
+        to_view(F, bb.x, bb.y, bb.z, B[0], B[1], B[2]);
+        return bond_record(F, A, B, F.n_atoms + br.z, x0, y0, x1, y1, rec);
+    }
+};
+
+template <class Src>
+__global__ void __launch_bounds__(kBinThreads) k_count(Frame F, Src src, uint32_t chunk,
                                                        PrimRec* __restrict__ vis_rec, uint2* __restrict__ vis_rect,
                                                        uint32_t* __restrict__ vis_cnt, uint2* __restrict__ vis_box,
                                                        uint32_t* __restrict__ hist_out,
@@ -86,17 +165,16 @@ __global__ void __launch_bounds__(kBinThreads) k_count(Frame F, const float* __r
     __syncthreads();
     uint32_t mx0 = 0xFFFF, my0 = 0xFFFF, mx1 = 0, my1 = 0, my_pairs = 0;
 
-    const uint64_t total = (uint64_t)F.n_atoms + F.n_bonds;
     const uint64_t start = (uint64_t)blockIdx.x * chunk;
-    const uint64_t end = min(total, start + chunk);
+    const uint64_t nitems = src.items(blockIdx.x);
     const int ts = F.tile;
     uint32_t bad_count = 0;
-    for (uint64_t base = start; base < end; base += kBinThreads) {
-        const uint64_t p = base + tid;
+    for (uint64_t base = 0; base < nitems; base += kBinThreads) {
+        const uint64_t k = base + tid;
         int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
         bool bad = false;
         PrimRec rec;
-        const bool vis = p < end && primitive_record(F, (uint32_t)p, pos, rad, bonds, x0, y0, x1, y1, rec, bad);
+        const bool vis = k < nitems && src.record(F, blockIdx.x, k, x0, y0, x1, y1, rec, bad);
         bad_count += bad ? 1u : 0u;
         const unsigned long long vmask = __ballot(vis);
         uint32_t slot_base = 0;
@@ -209,6 +287,7 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(Frame F, uint32_t chunk
             ctr->frag_hit_bond = 0;
             ctr->done_blocks = 0;
             ctr->pairs_counted = 0;
+            ctr->vis_clusters = 0;         // the next frame's cluster test adds to this
             if (host_ctr) {
                 host_ctr->vis_count = vis;
                 host_ctr->bad_bonds = bad;
@@ -271,8 +350,21 @@ hipError_t launch_count(const Frame& F, const float* pos, const float* rad, cons
     const size_t lds = (size_t)T * sizeof(uint32_t);
     if (marks) (void)hipEventRecord(marks[0], stream);
     if (marks) (void)hipEventRecord(marks[1], stream);
-    k_count<<<bb.groups, kBinThreads, lds, stream>>>(F, pos, rad, bonds, bb.chunk, bb.vis_rec, bb.vis_rect, bb.vis_cnt,
-                                                     bb.vis_box, bb.hist, bb.tile_cnt, bb.ctr);
+    const PlainSource src{pos, rad, bonds, (uint64_t)F.n_atoms + F.n_bonds, bb.chunk};
+    k_count<PlainSource><<<bb.groups, kBinThreads, lds, stream>>>(F, src, bb.chunk, bb.vis_rec, bb.vis_rect, bb.vis_cnt,
+                                                                  bb.vis_box, bb.hist, bb.tile_cnt, bb.ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_scene(const Frame& F, const SceneDev& S, const BinBuffers& bb, hipStream_t stream,
+                              hipEvent_t* marks) {
+    const int T = F.tiles_x * F.tiles_y;
+    if (T > kMaxLdsTiles) return hipErrorInvalidValue;
+    const size_t lds = (size_t)T * sizeof(uint32_t);
+    if (marks) (void)hipEventRecord(marks[1], stream);
+    const SceneSource src{S, bb.ctr, bb.groups};
+    k_count<SceneSource><<<bb.groups, kBinThreads, lds, stream>>>(F, src, bb.chunk, bb.vis_rec, bb.vis_rect, bb.vis_cnt,
+                                                                  bb.vis_box, bb.hist, bb.tile_cnt, bb.ctr);
     return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ struct Frame {
     double tx, ty;                     // perspective: tan(fovy/2) * W/H, tan(fovy/2)
     double hx, hy;                     // orthographic: h * W/H, h
     float txf, tyf, hxf, hyf;
+    float sxf, syf;                    // perspective: sqrt(1 + tx^2), sqrt(1 + ty^2)
     float inv_w2, inv_h2;              // 2/W, 2/H
     float znear, zfar;
     float bond_radius;
@@ -55,7 +56,7 @@ struct Counters {
     unsigned long long frag_hit;
     unsigned long long frag_hit_bond;
     unsigned int done_blocks;
-    unsigned int pad;
+    unsigned int vis_clusters;          // resident scenes: clusters that passed the frustum test
     unsigned long long pairs_counted;   // total of the tile counts, added by the count kernel
 };
 
@@ -183,6 +184,20 @@ __device__ inline bool bond_rect(const Frame& F, const double* A, const double* 
     return x0 <= x1 && y0 <= y1;
 }
 
+// Cheap conservative frustum test of a view-space bounding sphere, in FP32
+// (the margin covers the rounding of the view coordinates): false when no
+// point of the sphere is inside the view volume.
+__device__ inline bool sphere_in_frustum(const Frame& F, double vx, double vy, double vz, double r) {
+    const float z = (float)vz, x = (float)vx, y = (float)vy;
+    const float rr = (float)r + 1e-4f * (fabsf(x) + fabsf(y) + fabsf(z) + (float)r);
+    if (z + rr < F.znear || z - rr > F.zfar) return false;
+    if (F.proj == 0) {
+        const float ex = rr * F.sxf, ey = rr * F.syf;
+        return !(x - F.txf * z > ex || -x - F.txf * z > ex || y - F.tyf * z > ey || -y - F.tyf * z > ey);
+    }
+    return !(fabsf(x) > F.hxf + rr || fabsf(y) > F.hyf + rr);
+}
+
 // Hardware dispatch places workgroup b on XCD (b mod 8).  Give each XCD one
 // contiguous range of work items so neighbouring tiles share an L2.
 __device__ inline int xcd_contiguous(int b, int nblocks) {
@@ -216,6 +231,30 @@ struct BinBuffers {
 
 // Binning grid for n primitives (groups <= kMaxBinGroups, groups * chunk >= n).
 void bin_grid(uint64_t nprim, uint32_t* groups, uint32_t* chunk);
+
+// Resident scene (device arrays owned by the library).  Atoms are stored in
+// Morton order as an xyzr stream, grouped in clusters of kCluster; bonds are
+// re-indexed to those positions and sorted by their first atom.
+constexpr int kCluster = 256;
+struct SceneDev {
+    uint32_t n_atoms, n_bonds;          // n_bonds: valid bonds (both indices < n_atoms)
+    uint32_t n_bonds_total;             // bonds as given (ids run over these)
+    uint32_t atom_clusters, bond_clusters;
+    const float4* xyzr;                 // n_atoms, Morton order
+    const uint32_t* atom_id;            // n_atoms: original index of each stored atom
+    const uint4* bond_rec;              // n_bonds: (stored index a, stored index b, original bond index, 0)
+    const float4* cluster_box;          // 2 per cluster: (min xyz, -), (max xyz, -); bond boxes exclude the radius
+    uint32_t* vis_clusters;             // atom_clusters + bond_clusters: visible cluster ids (per frame)
+};
+hipError_t launch_cluster_cull(const Frame& F, const SceneDev& S, Counters* ctr, hipStream_t stream);
+size_t scene_build_temp_bytes(uint64_t n, uint64_t m);
+hipError_t scene_build(const float* pos, const float* rad, const uint32_t* bonds, uint64_t n, uint64_t m,
+                       SceneDev& S, float4* xyzr, uint32_t* atom_id, uint4* bond_rec, float4* cluster_box,
+                       void* tmp, size_t tmp_bytes, uint32_t* m_valid, uint32_t* n_bad, hipStream_t stream);
+hipError_t scene_update_positions(const float* pos, SceneDev& S, float4* xyzr, float4* cluster_box,
+                                  hipStream_t stream);
+hipError_t launch_count_scene(const Frame& F, const SceneDev& S, const BinBuffers& bb, hipStream_t stream,
+                              hipEvent_t* marks = nullptr);
 
 // Zeroes n 32-bit words (used when scratch is allocated; the frame kernels
 // leave the tile counts and the counters zeroed for the next frame).

@@ -32,7 +32,10 @@ VTX_FLAG_TIMING = 2
 
 # Every symbol include/vtx.h declares.
 EXPORTS = ("vtx_render", "vtx_gbuffer", "vtx_shade", "vtx_read_stats", "vtx_set_bin_capacity",
-           "vtx_read_timings", "vtx_reset_timings", "vtx_release_scratch", "vtx_last_error", "vtx_version")
+           "vtx_read_timings", "vtx_reset_timings", "vtx_release_scratch", "vtx_last_error", "vtx_version",
+           "vtx_context_create", "vtx_context_destroy", "vtx_context_bytes_in_use", "vtx_scene_footprint_bytes",
+           "vtx_frame_scratch_bytes", "vtx_scene_create", "vtx_scene_update_positions", "vtx_scene_info",
+           "vtx_scene_destroy", "vtx_render_scene")
 
 
 class vtx_camera(ctypes.Structure):
@@ -97,6 +100,27 @@ _lib.vtx_reset_timings.restype = ctypes.c_int
 _lib.vtx_reset_timings.argtypes = [_P]
 _lib.vtx_release_scratch.restype = ctypes.c_int
 _lib.vtx_release_scratch.argtypes = [_P]
+_lib.vtx_context_create.restype = ctypes.c_int
+_lib.vtx_context_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_P)]
+_lib.vtx_context_destroy.restype = None
+_lib.vtx_context_destroy.argtypes = [_P]
+_lib.vtx_context_bytes_in_use.restype = ctypes.c_size_t
+_lib.vtx_context_bytes_in_use.argtypes = [_P]
+_lib.vtx_scene_footprint_bytes.restype = ctypes.c_size_t
+_lib.vtx_scene_footprint_bytes.argtypes = [_I64, _I64]
+_lib.vtx_frame_scratch_bytes.restype = ctypes.c_size_t
+_lib.vtx_frame_scratch_bytes.argtypes = [_I32, _I32, _I64, _I64]
+_lib.vtx_scene_create.restype = ctypes.c_int
+_lib.vtx_scene_create.argtypes = [_P, _P, _P, _P, _I64, _P, _I64, _P, ctypes.POINTER(_P)]
+_lib.vtx_scene_update_positions.restype = ctypes.c_int
+_lib.vtx_scene_update_positions.argtypes = [_P, _P, _P]
+_lib.vtx_scene_info.restype = ctypes.c_int
+_lib.vtx_scene_info.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_uint64),
+                                ctypes.POINTER(ctypes.c_size_t)]
+_lib.vtx_scene_destroy.restype = None
+_lib.vtx_scene_destroy.argtypes = [_P]
+_lib.vtx_render_scene.restype = ctypes.c_int
+_lib.vtx_render_scene.argtypes = [_P, _CAM, _OPT, _I32, _I32, _P, _P, _P, _P]
 _lib.vtx_last_error.restype = ctypes.c_char_p
 _lib.vtx_last_error.argtypes = []
 _lib.vtx_version.restype = ctypes.c_char_p
@@ -202,6 +226,54 @@ def vtx_release_scratch(stream=None):
     _check(_lib.vtx_release_scratch(_stream(stream)))
 
 
+def vtx_context_create(device=0, hbm_budget_bytes=0) -> int:
+    h = _P()
+    _check(_lib.vtx_context_create(int(device), int(hbm_budget_bytes), ctypes.byref(h)))
+    return h.value
+
+
+def vtx_context_destroy(ctx):
+    _lib.vtx_context_destroy(ctx)
+
+
+def vtx_context_bytes_in_use(ctx) -> int:
+    return int(_lib.vtx_context_bytes_in_use(ctx))
+
+
+def vtx_scene_footprint_bytes(n_atoms, n_bonds) -> int:
+    return int(_lib.vtx_scene_footprint_bytes(int(n_atoms), int(n_bonds)))
+
+
+def vtx_frame_scratch_bytes(W, H, n_atoms, n_bonds) -> int:
+    return int(_lib.vtx_frame_scratch_bytes(int(W), int(H), int(n_atoms), int(n_bonds)))
+
+
+def vtx_scene_create(ctx, positions, radii, colors, n_atoms, bonds, n_bonds, stream=None) -> int:
+    h = _P()
+    _check(_lib.vtx_scene_create(ctx, _addr(positions), _addr(radii), _addr(colors), n_atoms, _addr(bonds),
+                                 n_bonds, _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def vtx_scene_update_positions(scene, positions, stream=None):
+    _check(_lib.vtx_scene_update_positions(scene, _addr(positions), _stream(stream)))
+
+
+def vtx_scene_info(scene) -> dict:
+    n, m, bad, nbytes = _I64(), _I64(), ctypes.c_uint64(), ctypes.c_size_t()
+    _check(_lib.vtx_scene_info(scene, ctypes.byref(n), ctypes.byref(m), ctypes.byref(bad), ctypes.byref(nbytes)))
+    return {"n_atoms": n.value, "n_bonds": m.value, "bad_bonds": bad.value, "bytes": nbytes.value}
+
+
+def vtx_scene_destroy(scene):
+    _lib.vtx_scene_destroy(scene)
+
+
+def vtx_render_scene(scene, cam, opts, W, H, rgba, depth, id, stream=None):
+    cp, op, _keep = _cam_opt(cam, opts)
+    _check(_lib.vtx_render_scene(scene, cp, op, W, H, _addr(rgba), _addr(depth), _addr(id), _stream(stream)))
+
+
 def vtx_last_error() -> str:
     return (_lib.vtx_last_error() or b"").decode()
 
@@ -270,3 +342,34 @@ def shade(dscene, cam, opts, W, H, frame, stream=None) -> Frame:
     vtx_shade(*dscene.args(), cam, opts, W, H, frame.depth, frame.id, frame.rgba,
               getattr(frame, "normal", None), getattr(frame, "albedo", None), getattr(frame, "ao", None), stream)
     return frame
+
+
+class ResidentScene:
+    """A scene kept in device memory by the library (vtx_scene_create)."""
+
+    def __init__(self, ctx, dscene, stream=None):
+        self.ctx = ctx
+        self.n_atoms, self.n_bonds = dscene.n_atoms, dscene.n_bonds
+        self.handle = vtx_scene_create(ctx, *dscene.args(), stream=stream)
+
+    def update_positions(self, positions, stream=None):
+        vtx_scene_update_positions(self.handle, positions, stream)
+
+    def render(self, cam, opts, W, H, frame=None, stream=None) -> Frame:
+        fr = frame if frame is not None else Frame(W, H)
+        vtx_render_scene(self.handle, cam, opts, W, H, fr.rgba, fr.depth, fr.id, stream)
+        return fr
+
+    def info(self):
+        return vtx_scene_info(self.handle)
+
+    def close(self):
+        if self.handle:
+            vtx_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
