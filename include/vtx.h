@@ -219,7 +219,27 @@ int vtx_scene_create(vtx_context* ctx, const float* positions, const float* radi
  */
 int vtx_scene_update_positions(vtx_scene* scene, const float* positions, void* stream);
 
-/* vtx_scene_info - sizes of a scene and how many bonds were dropped. */
+/*
+ * vtx_scene_add_frames - stores n_frames more trajectory frames in the scene
+ * (paper, "High Quality Rendering" and Results: molecular dynamics
+ * trajectories are played back frame by frame, and dynamic data cannot be
+ * precomputed).  `positions` is n_frames x n_atoms x 3 float, device, each
+ * frame in the original atom order; the caller may free it once the stream
+ * has passed this call.  The frames get the indices *first_frame,
+ * *first_frame + 1, ... (frame 0 is the positions given at creation or by the
+ * last vtx_scene_update_positions) and are selected per job by
+ * vtx_render_batch.  Each frame holds vtx_scene_frame_bytes bytes, counted
+ * against the context budget (VTX_EBUSY when over).  Queued on `stream`.
+ */
+int vtx_scene_add_frames(vtx_scene* scene, const float* positions, int32_t n_frames, void* stream,
+                         int32_t* first_frame);
+/* vtx_scene_frames - number of stored frames, frame 0 included (0 for NULL). */
+int32_t vtx_scene_frames(const vtx_scene* scene);
+/* vtx_scene_frame_bytes - device bytes of one added trajectory frame. */
+size_t vtx_scene_frame_bytes(int64_t n_atoms, int64_t n_bonds);
+
+/* vtx_scene_info - sizes of a scene and how many bonds were dropped; bytes
+ * includes its added frames. */
 int vtx_scene_info(const vtx_scene* scene, int64_t* n_atoms, int64_t* n_bonds, uint64_t* bad_bonds, size_t* bytes);
 
 /* vtx_scene_destroy - waits for the device and frees the scene. */
@@ -235,8 +255,41 @@ int vtx_render_scene(vtx_scene* scene, const vtx_camera* cam, const vtx_options*
                      uint32_t* rgba, float* depth, uint32_t* id, void* stream);
 
 /*
+ * One render of a batch: a frame of a resident scene seen by a camera into
+ * the job's own device images (each height x width, layouts as for
+ * vtx_render).
+ */
+typedef struct vtx_job {
+    vtx_scene* scene;
+    int32_t frame;             /* trajectory frame: 0 .. vtx_scene_frames(scene) - 1 */
+    vtx_camera camera;
+    vtx_options options;
+    int32_t width, height;
+    uint32_t* rgba;
+    float* depth;
+    uint32_t* id;
+} vtx_job;
+
+/*
+ * vtx_render_batch - renders n_jobs (0 .. 4096) independent jobs with one
+ * launch per pass for the whole batch (cluster test, count, scatter, one
+ * resolve per tile size, shade), so that many small renders (trajectory
+ * frames, several viewports, the frames of several clients) fill the device
+ * together; the paper's renders are independent frames of the same
+ * per-frame method (Methods, "Molecular Graphics Engine" and "High Quality
+ * Rendering").  Each job's images equal those vtx_render_scene gives for the
+ * same scene frame, camera and options.  Scenes must belong to `ctx`, on the
+ * current device; output images must not overlap.  Queued on `stream`
+ * (scratch for each job is kept per stream; the first batch of a new shape
+ * waits for its counts to size the bins).  vtx_read_stats afterwards sums the
+ * counters over the batch's jobs.  VTX_EINVAL names the offending job.
+ */
+int vtx_render_batch(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, void* stream);
+
+/*
  * vtx_read_stats - waits for `stream` to drain, then returns the counters of
- * the last frame queued on it by this library.  VTX_EINVAL if none was.
+ * the last call queued on it by this library (summed over its jobs for a
+ * batch).  VTX_EINVAL if none was.
  */
 int vtx_read_stats(void* stream, vtx_stats* out);
 

@@ -1,6 +1,7 @@
 // C ABI of the renderer (declared in include/vtx.h): argument checks, frame
 // constants, per-stream scratch (tile bins) and the launch sequence
-// bin -> resolve -> shade.
+// cull -> count -> scatter -> resolve -> shade, for one render or a batch.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -9,6 +10,7 @@
 #include <mutex>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "vtx.h"
 #include "vtx_internal.h"
@@ -39,39 +41,55 @@ int fail(int code, const char* fmt, ...) {
 
 constexpr int kTimingRing = 64;
 constexpr int kMarks = 7;   // before clear, project, scan, scatter, resolve, shade; after shade
+constexpr int kMaxBatch = 4096;
 
 struct TimingSlot {
     hipEvent_t ev[kMarks] = {};
     bool inflight = false;
 };
 
-// Scratch of one (device, stream): tile bins, the compacted visible list and
-// the frame counters, plus a pinned copy of the counters that the host reads
-// once the frame's event has completed.
-struct Workspace {
-    int device = 0;
-    hipStream_t stream = nullptr;
+// Binning scratch of one render slot: a single render uses slot 0, job i of a
+// batch uses slot i.  Every frame leaves the tile counts, cursors and counters
+// zeroed for the next one.
+struct Bins {
     BinBuffers bb{};
     size_t tiles_cap = 0;
     size_t vis_cap = 0;
     size_t groups_cap = 0;
     size_t hist_cap = 0;
     size_t list_alloc = 0;          // allocated bin entries (>= bb.capacity, the entries in use)
-    Counters* host_ctr = nullptr;
-    hipEvent_t done = nullptr;
-    bool pending = false;
-    bool have_stats = false;
-    uint64_t pending_capacity = 0;
+    size_t vc_cap = 0;
+    uint32_t* vis_clusters = nullptr;   // resident scenes: the clusters that passed the frustum test
+    Counters* host_ctr = nullptr;       // host view of the mapped counters
     uint64_t want_capacity = 0;
-    bool fixed_capacity = false;
+    uint64_t pending_capacity = 0;
     bool dirty = true;              // tile counts / counters must be zeroed before the next frame
     uint64_t sized_nprim = ~0ull;   // scene and image size the bins were last sized for
     int sized_w = -1, sized_h = -1;
+};
+
+// Scratch of one (device, stream).
+struct Workspace {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::vector<Bins*> slots;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    int pending_n = 0;
+    bool have_stats = false;
+    bool fixed_capacity = false;
+    uint64_t fixed_entries = 0;
     vtx_stats last{};
     TimingSlot* tslots = nullptr;   // ring of kTimingRing, created on first timed frame
     int tnext = 0;
     uint64_t tframes = 0;
     double tsum[kMarks - 1] = {};
+    // job tables of batched launches: device copy and pinned staging
+    char* d_tab = nullptr;
+    char* h_tab = nullptr;
+    size_t tab_cap = 0;
+    hipEvent_t staged = nullptr;
+    bool stage_busy = false;
 };
 
 std::mutex g_mu;
@@ -80,54 +98,75 @@ std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
 constexpr uint64_t kMaxCapacity = 1ull << 28;        // bin entries (8 GiB of 32-byte records)
 constexpr uint64_t kMinCapacity = 1ull << 20;
 
-int free_ws_buffers(Workspace* ws) {
-    hipFree(ws->bb.tile_cnt);
-    hipFree(ws->bb.tile_off);
-    hipFree(ws->bb.tile_fill);
-    hipFree(ws->bb.vis_rec);
-    hipFree(ws->bb.vis_rect);
-    hipFree(ws->bb.vis_cnt);
-    hipFree(ws->bb.vis_box);
-    hipFree(ws->bb.hist);
-    ws->bb.vis_box = nullptr;
-    hipFree(ws->bb.list);
-    ws->bb.vis_cnt = nullptr;
-    ws->bb.hist = nullptr;
-    ws->groups_cap = 0;
-    ws->hist_cap = 0;
-    ws->bb.tile_cnt = nullptr;
-    ws->bb.tile_off = nullptr;
-    ws->bb.tile_fill = nullptr;
-    ws->bb.vis_rec = nullptr;
-    ws->bb.vis_rect = nullptr;
-    ws->bb.list = nullptr;
-    ws->bb.capacity = 0;
-    ws->tiles_cap = 0;
-    ws->vis_cap = 0;
-    ws->list_alloc = 0;
+void bins_free(Bins* b) {
+    hipFree(b->bb.tile_cnt);
+    hipFree(b->bb.tile_off);
+    hipFree(b->bb.tile_fill);
+    hipFree(b->bb.vis_rec);
+    hipFree(b->bb.vis_rect);
+    hipFree(b->bb.vis_cnt);
+    hipFree(b->bb.vis_box);
+    hipFree(b->bb.hist);
+    hipFree(b->bb.list);
+    hipFree(b->bb.ctr);
+    hipFree(b->vis_clusters);
+    hipHostFree(b->host_ctr);
+    delete b;
+}
+
+int bins_new(Bins** out) {
+    Bins* b = new Bins();
+    if (hipMalloc(&b->bb.ctr, sizeof(Counters)) != hipSuccess) {
+        (void)hipGetLastError();
+        delete b;
+        return fail(VTX_ENOMEM, "cannot allocate frame counters");
+    }
+    if (hipHostMalloc(&b->host_ctr, sizeof(Counters), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        (void)hipGetLastError();
+        hipFree(b->bb.ctr);
+        delete b;
+        return fail(VTX_ENOMEM, "cannot allocate pinned counters");
+    }
+    std::memset(b->host_ctr, 0, sizeof(Counters));
+    void* dptr = nullptr;
+    if (hipHostGetDevicePointer(&dptr, b->host_ctr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        hipFree(b->bb.ctr);
+        hipHostFree(b->host_ctr);
+        delete b;
+        return fail(VTX_EHIP, "cannot map pinned counters");
+    }
+    b->bb.host_ctr = static_cast<Counters*>(dptr);
+    *out = b;
     return VTX_OK;
 }
 
-// Reads the counters of a completed frame into ws->last.
+// Reads the counters of a completed call into ws->last (sums over its renders)
+// and grows the bins of any render whose lists overflowed.
 void harvest(Workspace* ws) {
     if (!ws->pending) return;
     if (hipEventQuery(ws->done) != hipSuccess) return;
-    const Counters& c = *ws->host_ctr;
-    ws->last.visible = c.vis_count;
-    ws->last.pairs = c.pairs;
-    ws->last.fragments_tested = c.frag_tested;
-    ws->last.fragments_hit = c.frag_hit;
-    ws->last.fragments_hit_bond = c.frag_hit_bond;
-    ws->last.overflow_tiles = c.overflow_tiles;
-    ws->last.bin_capacity = ws->pending_capacity;
-    ws->last.bad_bonds = c.bad_bonds;
+    vtx_stats s{};
+    for (int i = 0; i < ws->pending_n; ++i) {
+        Bins* b = ws->slots[i];
+        const Counters& c = *b->host_ctr;
+        s.visible += c.vis_count;
+        s.pairs += c.pairs;
+        s.fragments_tested += c.frag_tested;
+        s.fragments_hit += c.frag_hit;
+        s.fragments_hit_bond += c.frag_hit_bond;
+        s.overflow_tiles += c.overflow_tiles;
+        s.bin_capacity += b->pending_capacity;
+        s.bad_bonds += c.bad_bonds;
+        if (c.pairs > b->bb.capacity && !ws->fixed_capacity) {
+            uint64_t want = c.pairs + c.pairs / 2 + 1024;
+            if (want > kMaxCapacity) want = kMaxCapacity;
+            if (want > b->want_capacity) b->want_capacity = want;
+        }
+    }
+    ws->last = s;
     ws->have_stats = true;
     ws->pending = false;
-    if (c.pairs > ws->bb.capacity && !ws->fixed_capacity) {
-        uint64_t want = c.pairs + c.pairs / 2 + 1024;
-        if (want > kMaxCapacity) want = kMaxCapacity;
-        if (want > ws->want_capacity) ws->want_capacity = want;
-    }
 }
 
 void harvest_timings(Workspace* ws, bool wait) {
@@ -175,29 +214,12 @@ int get_workspace(hipStream_t stream, Workspace** out) {
     Workspace* ws = new Workspace();
     ws->device = dev;
     ws->stream = stream;
-    if (hipMalloc(&ws->bb.ctr, sizeof(Counters)) != hipSuccess) {
+    if (hipEventCreateWithFlags(&ws->done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ws->staged, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (ws->done) hipEventDestroy(ws->done);
         delete ws;
-        return fail(VTX_ENOMEM, "cannot allocate frame counters");
-    }
-    if (hipHostMalloc(&ws->host_ctr, sizeof(Counters), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
-        hipFree(ws->bb.ctr);
-        delete ws;
-        return fail(VTX_ENOMEM, "cannot allocate pinned counters");
-    }
-    std::memset(ws->host_ctr, 0, sizeof(Counters));
-    void* dptr = nullptr;
-    if (hipHostGetDevicePointer(&dptr, ws->host_ctr, 0) != hipSuccess) {
-        hipFree(ws->bb.ctr);
-        hipHostFree(ws->host_ctr);
-        delete ws;
-        return fail(VTX_EHIP, "cannot map pinned counters");
-    }
-    ws->bb.host_ctr = static_cast<Counters*>(dptr);
-    if (hipEventCreateWithFlags(&ws->done, hipEventDisableTiming) != hipSuccess) {
-        hipFree(ws->bb.ctr);
-        hipHostFree(ws->host_ctr);
-        delete ws;
-        return fail(VTX_EHIP, "cannot create event");
+        return fail(VTX_EHIP, "cannot create events");
     }
     g_ws[key] = ws;
     *out = ws;
@@ -219,59 +241,77 @@ int grow(T** p, size_t& cap, size_t want, hipStream_t stream, const char* what) 
     return VTX_OK;
 }
 
-int ensure_buffers(Workspace* ws, int T, uint64_t nprim, uint32_t groups, uint32_t chunk) {
-    size_t tc = ws->tiles_cap;
+// Sizes slot b for a render with T tiles, nprim primitives binned by
+// `groups` workgroups of `chunk`, and nc scene clusters (0 for the plain path).
+int ensure_bins(Workspace* ws, Bins* b, int T, uint64_t nprim, uint32_t groups, uint32_t chunk, uint32_t nc) {
     int rc;
-    if ((size_t)T > ws->tiles_cap || !ws->bb.tile_cnt) {
-        size_t c1 = tc, c2 = tc, c3 = tc;
-        if ((rc = grow(&ws->bb.tile_cnt, c1, (size_t)T, ws->stream, "tile counts"))) return rc;
-        if ((rc = grow(&ws->bb.tile_off, c2, (size_t)T, ws->stream, "tile offsets"))) return rc;
-        if ((rc = grow(&ws->bb.tile_fill, c3, (size_t)T, ws->stream, "tile cursors"))) return rc;
-        ws->tiles_cap = (size_t)T;
-        ws->dirty = true;
+    hipStream_t st = ws->stream;
+    if ((size_t)T > b->tiles_cap || !b->bb.tile_cnt) {
+        size_t c1 = b->tiles_cap, c2 = b->tiles_cap, c3 = b->tiles_cap;
+        if ((rc = grow(&b->bb.tile_cnt, c1, (size_t)T, st, "tile counts"))) return rc;
+        if ((rc = grow(&b->bb.tile_off, c2, (size_t)T, st, "tile offsets"))) return rc;
+        if ((rc = grow(&b->bb.tile_fill, c3, (size_t)T, st, "tile cursors"))) return rc;
+        b->tiles_cap = (size_t)T;
+        b->dirty = true;
     }
-    if (ws->dirty) {
-        // every frame leaves the tile counts and the counters zeroed for the
-        // next one; fresh or abandoned scratch is zeroed here instead
-        VTX_HIP(vtx::launch_zero(ws->bb.tile_cnt, ws->tiles_cap, ws->stream));
-        VTX_HIP(vtx::launch_zero(ws->bb.tile_fill, ws->tiles_cap, ws->stream));
-        VTX_HIP(vtx::launch_zero(reinterpret_cast<uint32_t*>(ws->bb.ctr), sizeof(Counters) / sizeof(uint32_t),
-                                 ws->stream));
-        ws->dirty = false;
+    if (b->dirty) {
+        // fresh or abandoned scratch: zero what every frame otherwise leaves zeroed
+        VTX_HIP(vtx::launch_zero(b->bb.tile_cnt, b->tiles_cap, st));
+        VTX_HIP(vtx::launch_zero(b->bb.tile_fill, b->tiles_cap, st));
+        VTX_HIP(vtx::launch_zero(reinterpret_cast<uint32_t*>(b->bb.ctr), sizeof(Counters) / sizeof(uint32_t), st));
+        b->dirty = false;
     }
-    ws->bb.groups = groups;
-    ws->bb.chunk = chunk;
+    b->bb.groups = groups;
+    b->bb.chunk = chunk;
     const size_t nv = (size_t)groups * chunk;
-    if (nv > ws->vis_cap || !ws->bb.vis_rec) {
-        size_t c1 = ws->vis_cap, c2 = ws->vis_cap;
-        if ((rc = grow(&ws->bb.vis_rec, c1, nv, ws->stream, "visible records"))) return rc;
-        if ((rc = grow(&ws->bb.vis_rect, c2, nv, ws->stream, "visible rectangles"))) return rc;
-        ws->vis_cap = nv;
+    if (nv > b->vis_cap || !b->bb.vis_rec) {
+        size_t c1 = b->vis_cap, c2 = b->vis_cap;
+        if ((rc = grow(&b->bb.vis_rec, c1, nv, st, "visible records"))) return rc;
+        if ((rc = grow(&b->bb.vis_rect, c2, nv, st, "visible rectangles"))) return rc;
+        b->vis_cap = nv;
     }
-    if ((size_t)groups > ws->groups_cap || !ws->bb.vis_cnt) {
-        size_t c1 = ws->groups_cap, c2 = ws->groups_cap;
-        if ((rc = grow(&ws->bb.vis_cnt, c1, (size_t)vtx::kMaxBinGroups, ws->stream, "visible counts"))) return rc;
-        if ((rc = grow(&ws->bb.vis_box, c2, (size_t)vtx::kMaxBinGroups, ws->stream, "visible boxes"))) return rc;
-        ws->groups_cap = vtx::kMaxBinGroups;
+    if ((size_t)groups > b->groups_cap || !b->bb.vis_cnt) {
+        size_t c1 = b->groups_cap, c2 = b->groups_cap;
+        if ((rc = grow(&b->bb.vis_cnt, c1, (size_t)vtx::kMaxBinGroups, st, "visible counts"))) return rc;
+        if ((rc = grow(&b->bb.vis_box, c2, (size_t)vtx::kMaxBinGroups, st, "visible boxes"))) return rc;
+        b->groups_cap = vtx::kMaxBinGroups;
     }
     const size_t nh = (size_t)groups * (size_t)T;
-    if (nh > ws->hist_cap || !ws->bb.hist) {
-        size_t c1 = ws->hist_cap;
-        if ((rc = grow(&ws->bb.hist, c1, nh, ws->stream, "tile histograms"))) return rc;
-        ws->hist_cap = nh;
+    if (nh > b->hist_cap || !b->bb.hist) {
+        size_t c1 = b->hist_cap;
+        if ((rc = grow(&b->bb.hist, c1, nh, st, "tile histograms"))) return rc;
+        b->hist_cap = nh;
     }
-    uint64_t want = ws->want_capacity;
+    if (nc && ((size_t)nc > b->vc_cap || !b->vis_clusters)) {
+        if ((rc = grow(&b->vis_clusters, b->vc_cap, (size_t)nc, st, "visible clusters"))) return rc;
+    }
+    uint64_t want = ws->fixed_capacity ? ws->fixed_entries : b->want_capacity;
     if (want == 0) {
         want = nprim / 2;
         if (want < kMinCapacity) want = kMinCapacity;
         if (want > kMaxCapacity) want = kMaxCapacity;
-        ws->want_capacity = want;
+        b->want_capacity = want;
     }
-    if (want > ws->list_alloc || !ws->bb.list) {
-        if ((rc = grow(&ws->bb.list, ws->list_alloc, (size_t)want, ws->stream, "tile lists"))) return rc;
+    if (want > b->list_alloc || !b->bb.list) {
+        if ((rc = grow(&b->bb.list, b->list_alloc, (size_t)want, st, "tile lists"))) return rc;
     }
-    ws->bb.capacity = want;
+    b->bb.capacity = want;
     return VTX_OK;
+}
+
+void workspace_free(Workspace* ws) {
+    for (Bins* b : ws->slots) bins_free(b);
+    ws->slots.clear();
+    if (ws->tslots) {
+        for (int i = 0; i < kTimingRing; ++i)
+            for (int m = 0; m < kMarks; ++m) hipEventDestroy(ws->tslots[i].ev[m]);
+        delete[] ws->tslots;
+    }
+    hipFree(ws->d_tab);
+    hipHostFree(ws->h_tab);
+    hipEventDestroy(ws->done);
+    hipEventDestroy(ws->staged);
+    delete ws;
 }
 
 bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
@@ -402,62 +442,6 @@ void sample_kernel(const vtx_options& o, vtx::SampleKernel* K) {
     }
 }
 
-int gbuffer_locked(const float* positions, const float* radii, int64_t n, const uint32_t* bonds, int64_t m,
-                   const Frame& F, int32_t W, int32_t H, float* depth, uint32_t* id, hipStream_t stream,
-                   hipEvent_t* marks = nullptr, const vtx::SceneDev* scene = nullptr) {
-    Workspace* ws = nullptr;
-    int rc = get_workspace(stream, &ws);
-    if (rc) return rc;
-    harvest(ws);
-    const int T = F.tiles_x * F.tiles_y;
-    uint32_t groups, chunk;
-    if (!scene) {
-        vtx::bin_grid((uint64_t)n + (uint64_t)m, &groups, &chunk);
-    } else {
-        // resident scene: each binning workgroup takes whole clusters
-        const uint64_t nc = (uint64_t)scene->atom_clusters + scene->bond_clusters;
-        vtx::bin_grid((uint64_t)n + (uint64_t)m, &groups, &chunk);
-        const uint64_t cpw = (nc + groups - 1) / groups;
-        chunk = (uint32_t)((cpw ? cpw : 1) * vtx::kCluster);
-    }
-    if ((rc = ensure_buffers(ws, T, (uint64_t)n + (uint64_t)m, groups, chunk))) return rc;
-    ws->dirty = true;   // until the resolve that re-zeroes the tile counts is queued
-    if (!scene) {
-        VTX_HIP(vtx::launch_count(F, positions, radii, bonds, ws->bb, stream, marks));
-    } else {
-        if (marks) VTX_HIP(hipEventRecord(marks[0], stream));
-        VTX_HIP(vtx::launch_cluster_cull(F, *scene, ws->bb.ctr, stream));
-        VTX_HIP(vtx::launch_count_scene(F, *scene, ws->bb, stream, marks));
-    }
-    const uint64_t nprim = (uint64_t)n + (uint64_t)m;
-    if (!ws->fixed_capacity && (nprim != ws->sized_nprim || W != ws->sized_w || H != ws->sized_h)) {
-        // first frame of a new scene or image size: wait for the tile counts
-        // and size the bins, so the frame does not take the overflow path
-        unsigned long long counted = 0;
-        VTX_HIP(hipMemcpyAsync(&counted, &ws->bb.ctr->pairs_counted, sizeof(counted), hipMemcpyDeviceToHost, stream));
-        VTX_HIP(hipStreamSynchronize(stream));
-        uint64_t want = counted + counted / 2 + 1024;
-        if (want > kMaxCapacity) want = kMaxCapacity;
-        if (want > ws->want_capacity) ws->want_capacity = want;
-        if (ws->want_capacity > ws->list_alloc) {
-            if ((rc = grow(&ws->bb.list, ws->list_alloc, (size_t)ws->want_capacity, ws->stream, "tile lists"))) return rc;
-        }
-        ws->bb.capacity = ws->want_capacity;
-        ws->sized_nprim = nprim;
-        ws->sized_w = W;
-        ws->sized_h = H;
-    }
-    VTX_HIP(vtx::launch_scatter(F, ws->bb, stream, marks));
-    if (marks) VTX_HIP(hipEventRecord(marks[4], stream));
-    VTX_HIP(vtx::launch_resolve(F, positions, radii, bonds, ws->bb, depth, id, stream));
-    ws->dirty = false;
-    // The resolve's last workgroup writes the counters into the mapped pinned
-    // buffer; the host reads them once the latest recorded event has completed.
-    VTX_HIP(hipEventRecord(ws->done, stream));
-    ws->pending = true;
-    ws->pending_capacity = ws->bb.capacity;
-    return VTX_OK;
-}
 
 }  // namespace
 
@@ -468,31 +452,47 @@ struct vtx_context {
     std::mutex mu;
 };
 
+// Positions of one stored trajectory frame.
+struct SceneFrame {
+    float* pos;              // caller's order (deferred pass)
+    float4* xyzr;            // stored (Morton) order
+    float4* cluster_box;
+};
+
 struct vtx_scene {
     vtx_context* ctx = nullptr;
     int device = 0;
     int64_t n = 0, m = 0;
     uint32_t bad_bonds = 0;
     size_t bytes = 0;
-    vtx::SceneDev S{};
+    vtx::SceneDev S{};       // frame 0
     float4* xyzr = nullptr;
     uint32_t* atom_id = nullptr;
     uint4* bond_rec = nullptr;
     float4* cluster_box = nullptr;
-    uint32_t* vis_clusters = nullptr;
     // caller's arrays in their original order (the deferred pass reads them by id)
     float* pos = nullptr;
     float* rad = nullptr;
     uint32_t* col = nullptr;
     uint32_t* bonds = nullptr;
+    std::vector<SceneFrame> frames;     // frames 1, 2, ... added after creation
+    std::vector<void*> frame_blocks;    // their allocations
 };
 
 namespace {
 
+size_t scene_clusters(int64_t n, int64_t m) {
+    return (size_t)((n + vtx::kCluster - 1) / vtx::kCluster + (m + vtx::kCluster - 1) / vtx::kCluster);
+}
+
 size_t scene_bytes(int64_t n, int64_t m) {
-    const size_t nc = (size_t)((n + vtx::kCluster - 1) / vtx::kCluster + (m + vtx::kCluster - 1) / vtx::kCluster);
     return (size_t)n * (sizeof(float4) + sizeof(uint32_t) + 3 * sizeof(float) + sizeof(float) + sizeof(uint32_t)) +
-           (size_t)m * (sizeof(uint4) + 2 * sizeof(uint32_t)) + nc * (2 * sizeof(float4) + sizeof(uint32_t));
+           (size_t)m * (sizeof(uint4) + 2 * sizeof(uint32_t)) + scene_clusters(n, m) * 2 * sizeof(float4);
+}
+
+// Device bytes of one added trajectory frame.
+size_t frame_bytes(int64_t n, int64_t m) {
+    return (size_t)n * (3 * sizeof(float) + sizeof(float4)) + scene_clusters(n, m) * 2 * sizeof(float4);
 }
 
 void scene_free(vtx_scene* sc) {
@@ -500,11 +500,13 @@ void scene_free(vtx_scene* sc) {
     hipFree(sc->atom_id);
     hipFree(sc->bond_rec);
     hipFree(sc->cluster_box);
-    hipFree(sc->vis_clusters);
     hipFree(sc->pos);
     hipFree(sc->rad);
     hipFree(sc->col);
     hipFree(sc->bonds);
+    for (void* p : sc->frame_blocks) hipFree(p);
+    sc->frame_blocks.clear();
+    sc->frames.clear();
 }
 
 template <class T>
@@ -515,6 +517,277 @@ int dev_alloc(T** p, size_t count, const char* what) {
         return fail(VTX_ENOMEM, "cannot allocate %zu bytes for %s", (count ? count : 1) * sizeof(T), what);
     }
     return VTX_OK;
+}
+
+// The scene arrays of trajectory frame f (0 = the positions given at creation
+// or by the last update).
+void scene_frame(const vtx_scene* sc, int f, vtx::SceneDev* S, const float** pos) {
+    *S = sc->S;
+    *pos = sc->pos;
+    if (f > 0) {
+        const SceneFrame& fr = sc->frames[(size_t)f - 1];
+        S->xyzr = fr.xyzr;
+        S->cluster_box = fr.cluster_box;
+        *pos = fr.pos;
+    }
+}
+
+// Host description of one render.
+struct JobDesc {
+    Frame F;
+    vtx::SampleKernel K;
+    const float* pos;
+    const float* rad;
+    const uint32_t* col;
+    const uint32_t* bonds;
+    bool scene;
+    vtx::SceneDev S;
+    float* depth;
+    uint32_t* id;
+    uint32_t* rgba;
+    float* normal;
+    uint32_t* albedo;
+    float* ao;
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Copies the job tables of a batched launch to the device (through pinned
+// staging that is reused once the previous copy has finished).
+int upload_tables(Workspace* ws, const std::vector<vtx::Job>& jobs, const std::vector<JobDesc>& d,
+                  const std::vector<uint32_t>& starts, size_t* k_off, size_t* s_off) {
+    const size_t n = jobs.size();
+    *k_off = align_up(n * sizeof(vtx::Job), 256);
+    *s_off = align_up(*k_off + n * sizeof(vtx::SampleKernel), 256);
+    const size_t bytes = *s_off + starts.size() * sizeof(uint32_t);
+    if (ws->stage_busy) VTX_HIP(hipEventSynchronize(ws->staged));
+    ws->stage_busy = false;
+    if (bytes > ws->tab_cap) {
+        VTX_HIP(hipStreamSynchronize(ws->stream));   // the old device table may still be read
+        hipFree(ws->d_tab);
+        hipHostFree(ws->h_tab);
+        ws->d_tab = nullptr;
+        ws->h_tab = nullptr;
+        ws->tab_cap = 0;
+        const size_t cap = align_up(bytes + bytes / 2, 4096);
+        if (hipMalloc(&ws->d_tab, cap) != hipSuccess || hipHostMalloc(&ws->h_tab, cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(VTX_ENOMEM, "cannot allocate %zu bytes of job tables", cap);
+        }
+        ws->tab_cap = cap;
+    }
+    std::memcpy(ws->h_tab, jobs.data(), n * sizeof(vtx::Job));
+    for (size_t i = 0; i < n; ++i)
+        std::memcpy(ws->h_tab + *k_off + i * sizeof(vtx::SampleKernel), &d[i].K, sizeof(vtx::SampleKernel));
+    std::memcpy(ws->h_tab + *s_off, starts.data(), starts.size() * sizeof(uint32_t));
+    VTX_HIP(hipMemcpyAsync(ws->d_tab, ws->h_tab, bytes, hipMemcpyHostToDevice, ws->stream));
+    VTX_HIP(hipEventRecord(ws->staged, ws->stream));
+    ws->stage_busy = true;
+    return VTX_OK;
+}
+
+// Queues the renders `d` on `stream`: binning and resolve into each job's
+// depth/id when `bin`, the deferred pass into its rgba when `shade`.  One
+// render launches with its job in the kernel arguments; several launch each
+// kernel once over all of them, from device tables.  Caller holds g_mu.
+int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t stream) {
+    Workspace* ws = nullptr;
+    int rc = get_workspace(stream, &ws);
+    if (rc) return rc;
+    harvest(ws);
+    const size_t n = d.size();
+    if (n == 0) return VTX_OK;
+    // one resolve launch per tile size: keep the jobs of a size together
+    if (n > 1) std::stable_sort(d.begin(), d.end(), [](const JobDesc& a, const JobDesc& b) { return a.F.tile < b.F.tile; });
+    bool timing = false, scene = false;
+    for (const JobDesc& j : d) {
+        timing |= (j.F.flags & VTX_FLAG_TIMING) != 0;
+        scene |= j.scene;
+    }
+    hipEvent_t* marks = nullptr;
+    if (timing) {
+        TimingSlot* slot = nullptr;
+        if ((rc = timing_slot(ws, &slot))) return rc;
+        marks = slot->ev;
+    }
+    while (bin && ws->slots.size() < n) {
+        Bins* b = nullptr;
+        if ((rc = bins_new(&b))) return rc;
+        ws->slots.push_back(b);
+    }
+    std::vector<vtx::Job> jobs(n);
+    std::vector<uint64_t> nprims(n, 0);
+    uint32_t g_cull = 0, g_bin = 0, g_shade = 0;
+    int max_tiles = 0;
+    std::vector<uint32_t> starts;
+    // start tables: cull, bin, shade (n + 1 each), then one per tile-size group
+    starts.assign(3 * (n + 1), 0);
+    for (size_t i = 0; i < n; ++i) {
+        vtx::Job& J = jobs[i];
+        std::memset(&J, 0, sizeof(J));
+        const JobDesc& s = d[i];
+        J.F = s.F;
+        J.pos = s.pos;
+        J.rad = s.rad;
+        J.col = s.col;
+        J.bonds = s.bonds;
+        J.depth = s.depth;
+        J.id = s.id;
+        J.rgba = s.rgba;
+        J.normal = s.normal;
+        J.albedo = s.albedo;
+        J.ao = s.ao;
+        starts[2 * (n + 1) + i] = g_shade;
+        g_shade += vtx::shade_blocks(s.F);
+        if (!bin) continue;
+        const int T = s.F.tiles_x * s.F.tiles_y;
+        max_tiles = std::max(max_tiles, T);
+        const uint64_t nprim = (uint64_t)s.F.n_atoms + s.F.n_bonds;
+        nprims[i] = nprim;
+        uint32_t groups, chunk, nc = 0;
+        vtx::bin_grid(nprim, &groups, &chunk);
+        if (s.scene) {
+            // each binning workgroup takes whole clusters
+            nc = s.S.atom_clusters + s.S.bond_clusters;
+            const uint64_t cpw = ((uint64_t)nc + groups - 1) / groups;
+            chunk = (uint32_t)((cpw ? cpw : 1) * vtx::kCluster);
+        }
+        Bins* b = ws->slots[i];
+        if ((rc = ensure_bins(ws, b, T, nprim, groups, chunk, nc))) return rc;
+        b->dirty = true;   // until the resolve that re-zeroes the tile counts is queued
+        J.bb = b->bb;
+        if (s.scene) {
+            J.S = s.S;
+            J.S.vis_clusters = b->vis_clusters;
+        }
+        starts[i] = g_cull;
+        starts[(n + 1) + i] = g_bin;
+        g_cull += s.scene ? vtx::cull_blocks(s.S) : 0u;
+        g_bin += groups;
+    }
+    starts[n] = g_cull;
+    starts[2 * (n + 1) - 1] = g_bin;
+    starts[3 * (n + 1) - 1] = g_shade;
+    // tile-size groups [a, b) of the sorted jobs
+    std::vector<std::pair<size_t, size_t>> groups_ts;
+    std::vector<size_t> groups_off;
+    std::vector<uint32_t> groups_grid;
+    for (size_t a = 0; a < n;) {
+        size_t b = a;
+        while (b < n && d[b].F.tile == d[a].F.tile) ++b;
+        groups_ts.push_back({a, b});
+        groups_off.push_back(starts.size());
+        uint32_t acc = 0;
+        for (size_t i = a; i < b; ++i) {
+            starts.push_back(acc);
+            acc += (uint32_t)(d[i].F.tiles_x * d[i].F.tiles_y);
+        }
+        starts.push_back(acc);
+        groups_grid.push_back(acc);
+        a = b;
+    }
+
+    size_t k_off = 0, s_off = 0;
+    auto list_of = [&](size_t first, size_t count, size_t start_index) {
+        const vtx::Job* dj = reinterpret_cast<const vtx::Job*>(ws->d_tab) + first;
+        const vtx::SampleKernel* dk = reinterpret_cast<const vtx::SampleKernel*>(ws->d_tab + k_off) + first;
+        const uint32_t* ds = reinterpret_cast<const uint32_t*>(ws->d_tab + s_off) + start_index;
+        return vtx::JobList{dj, dk, ds, (uint32_t)count};
+    };
+    if (n > 1 && (rc = upload_tables(ws, jobs, d, starts, &k_off, &s_off))) return rc;
+    auto one = [&](uint32_t blocks) {
+        vtx::OneJob o;
+        o.j = jobs[0];
+        o.K = d[0].K;
+        o.blocks = blocks;
+        return o;
+    };
+
+    if (marks) VTX_HIP(hipEventRecord(marks[0], stream));
+    if (marks) VTX_HIP(hipEventRecord(marks[1], stream));
+    if (bin) {
+        if (scene) {
+            if (n == 1) VTX_HIP(vtx::launch_cluster_cull(one(g_cull), g_cull, stream));
+            else VTX_HIP(vtx::launch_cluster_cull(list_of(0, n, 0), g_cull, stream));
+        }
+        if (n == 1) VTX_HIP(vtx::launch_count(one(g_bin), scene, g_bin, max_tiles, stream));
+        else VTX_HIP(vtx::launch_count(list_of(0, n, n + 1), scene, g_bin, max_tiles, stream));
+        // first frame of a new scene or image size in a slot: wait for the
+        // tile counts and size its lists, so the frame does not take the
+        // overflow path
+        std::vector<size_t> need;
+        for (size_t i = 0; i < n; ++i) {
+            const Bins* b = ws->slots[i];
+            if (!ws->fixed_capacity && (nprims[i] != b->sized_nprim || d[i].F.W != b->sized_w || d[i].F.H != b->sized_h))
+                need.push_back(i);
+        }
+        if (!need.empty()) {
+            std::vector<unsigned long long> counted(n, 0);
+            for (size_t i : need)
+                VTX_HIP(hipMemcpyAsync(&counted[i], &ws->slots[i]->bb.ctr->pairs_counted, sizeof(unsigned long long),
+                                       hipMemcpyDeviceToHost, stream));
+            VTX_HIP(hipStreamSynchronize(stream));
+            for (size_t i : need) {
+                Bins* b = ws->slots[i];
+                uint64_t want = counted[i] + counted[i] / 2 + 1024;
+                if (want > kMaxCapacity) want = kMaxCapacity;
+                if (want > b->want_capacity) b->want_capacity = want;
+                if (b->want_capacity > b->list_alloc) {
+                    if ((rc = grow(&b->bb.list, b->list_alloc, (size_t)b->want_capacity, stream, "tile lists"))) return rc;
+                }
+                b->bb.capacity = b->want_capacity;
+                b->sized_nprim = nprims[i];
+                b->sized_w = d[i].F.W;
+                b->sized_h = d[i].F.H;
+                jobs[i].bb.list = b->bb.list;
+                jobs[i].bb.capacity = b->bb.capacity;
+            }
+            if (n > 1 && (rc = upload_tables(ws, jobs, d, starts, &k_off, &s_off))) return rc;
+        }
+        if (marks) VTX_HIP(hipEventRecord(marks[2], stream));
+        if (marks) VTX_HIP(hipEventRecord(marks[3], stream));
+        if (n == 1) VTX_HIP(vtx::launch_scatter(one(g_bin), g_bin, max_tiles, stream));
+        else VTX_HIP(vtx::launch_scatter(list_of(0, n, n + 1), g_bin, max_tiles, stream));
+        if (marks) VTX_HIP(hipEventRecord(marks[4], stream));
+        for (size_t g = 0; g < groups_ts.size(); ++g) {
+            const size_t a = groups_ts[g].first, b = groups_ts[g].second;
+            if (n == 1) VTX_HIP(vtx::launch_resolve(one(groups_grid[g]), d[0].F.tile, groups_grid[g], stream));
+            else VTX_HIP(vtx::launch_resolve(list_of(a, b - a, groups_off[g]), d[a].F.tile, groups_grid[g], stream));
+        }
+        for (size_t i = 0; i < n; ++i) {
+            ws->slots[i]->dirty = false;
+            ws->slots[i]->pending_capacity = ws->slots[i]->bb.capacity;
+        }
+        // The scatter's first workgroup (and, with statistics on, the
+        // resolve's last one) writes each render's counters into its mapped
+        // pinned buffer; the host reads them once this event has completed.
+        VTX_HIP(hipEventRecord(ws->done, stream));
+        ws->pending = true;
+        ws->pending_n = (int)n;
+    } else if (marks) {
+        for (int k = 2; k <= 4; ++k) VTX_HIP(hipEventRecord(marks[k], stream));
+    }
+    if (marks) VTX_HIP(hipEventRecord(marks[5], stream));
+    if (shade) {
+        if (n == 1) VTX_HIP(vtx::launch_shade(one(g_shade), g_shade, stream));
+        else VTX_HIP(vtx::launch_shade(list_of(0, n, 2 * (n + 1)), g_shade, stream));
+    }
+    if (marks) VTX_HIP(hipEventRecord(marks[6], stream));
+    return VTX_OK;
+}
+
+JobDesc plain_desc(const Frame& F, const vtx_options& o, const float* pos, const float* rad, const uint32_t* col,
+                   const uint32_t* bonds) {
+    JobDesc j;
+    std::memset(&j, 0, sizeof(j));
+    j.F = F;
+    sample_kernel(o, &j.K);
+    j.pos = pos;
+    j.rad = rad;
+    j.col = col;
+    j.bonds = bonds;
+    j.scene = false;
+    return j;
 }
 
 }  // namespace
@@ -530,8 +803,11 @@ int vtx_gbuffer(const float* positions, const float* radii, const uint32_t* colo
     if (rc) return rc;
     if ((rc = check_inputs(positions, radii, colors, n_atoms, bonds, n_bonds, false))) return rc;
     if (!depth || !id) return fail(VTX_EINVAL, "depth/id outputs are NULL");
+    std::vector<JobDesc> d{plain_desc(F, o, positions, radii, colors, bonds)};
+    d[0].depth = depth;
+    d[0].id = id;
     std::lock_guard<std::mutex> lk(g_mu);
-    return gbuffer_locked(positions, radii, n_atoms, bonds, n_bonds, F, W, H, depth, id, (hipStream_t)stream);
+    return render_locked(d, true, false, (hipStream_t)stream);
 }
 
 int vtx_shade(const float* positions, const float* radii, const uint32_t* colors, int64_t n_atoms,
@@ -544,11 +820,15 @@ int vtx_shade(const float* positions, const float* radii, const uint32_t* colors
     if (rc) return rc;
     if ((rc = check_inputs(positions, radii, colors, n_atoms, bonds, n_bonds, true))) return rc;
     if (!depth || !id || !rgba) return fail(VTX_EINVAL, "depth/id/rgba are NULL");
-    vtx::SampleKernel K;
-    sample_kernel(o, &K);
-    VTX_HIP(vtx::launch_shade(F, K, positions, radii, colors, bonds, depth, id, rgba, normal, albedo, ao,
-                              (hipStream_t)stream));
-    return VTX_OK;
+    std::vector<JobDesc> d{plain_desc(F, o, positions, radii, colors, bonds)};
+    d[0].depth = const_cast<float*>(depth);
+    d[0].id = const_cast<uint32_t*>(id);
+    d[0].rgba = rgba;
+    d[0].normal = normal;
+    d[0].albedo = albedo;
+    d[0].ao = ao;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return render_locked(d, false, true, (hipStream_t)stream);
 }
 
 int vtx_render(const float* positions, const float* radii, const uint32_t* colors, int64_t n_atoms,
@@ -560,24 +840,12 @@ int vtx_render(const float* positions, const float* radii, const uint32_t* color
     if (rc) return rc;
     if ((rc = check_inputs(positions, radii, colors, n_atoms, bonds, n_bonds, true))) return rc;
     if (!depth || !id || !rgba) return fail(VTX_EINVAL, "rgba/depth/id outputs are NULL");
-    vtx::SampleKernel K;
-    sample_kernel(o, &K);
+    std::vector<JobDesc> d{plain_desc(F, o, positions, radii, colors, bonds)};
+    d[0].depth = depth;
+    d[0].id = id;
+    d[0].rgba = rgba;
     std::lock_guard<std::mutex> lk(g_mu);
-    hipEvent_t* marks = nullptr;
-    if (o.flags & VTX_FLAG_TIMING) {
-        Workspace* ws = nullptr;
-        if ((rc = get_workspace((hipStream_t)stream, &ws))) return rc;
-        TimingSlot* slot = nullptr;
-        if ((rc = timing_slot(ws, &slot))) return rc;
-        marks = slot->ev;
-    }
-    rc = gbuffer_locked(positions, radii, n_atoms, bonds, n_bonds, F, W, H, depth, id, (hipStream_t)stream, marks);
-    if (rc) return rc;
-    if (marks) VTX_HIP(hipEventRecord(marks[5], (hipStream_t)stream));
-    VTX_HIP(vtx::launch_shade(F, K, positions, radii, colors, bonds, depth, id, rgba, nullptr, nullptr, nullptr,
-                              (hipStream_t)stream));
-    if (marks) VTX_HIP(hipEventRecord(marks[6], (hipStream_t)stream));
-    return VTX_OK;
+    return render_locked(d, true, true, (hipStream_t)stream);
 }
 
 int vtx_context_create(int device, size_t hbm_budget_bytes, vtx_context** out) {
@@ -601,6 +869,11 @@ size_t vtx_scene_footprint_bytes(int64_t n_atoms, int64_t n_bonds) {
     return scene_bytes(n_atoms, n_bonds);
 }
 
+size_t vtx_scene_frame_bytes(int64_t n_atoms, int64_t n_bonds) {
+    if (n_atoms < 0 || n_bonds < 0) return 0;
+    return frame_bytes(n_atoms, n_bonds);
+}
+
 size_t vtx_frame_scratch_bytes(int32_t W, int32_t H, int64_t n_atoms, int64_t n_bonds) {
     if (W < 1 || H < 1 || n_atoms < 0 || n_bonds < 0) return 0;
     int ts = 16;
@@ -612,7 +885,8 @@ size_t vtx_frame_scratch_bytes(int32_t W, int32_t H, int64_t n_atoms, int64_t n_
     uint64_t cap = nprim / 2;
     if (cap < kMinCapacity) cap = kMinCapacity;
     return (size_t)(T * 16 + (uint64_t)groups * chunk * (sizeof(vtx::PrimRec) + sizeof(uint2)) +
-                    (uint64_t)groups * T * 4 + cap * sizeof(vtx::PrimRec) + sizeof(Counters) + 4096);
+                    (uint64_t)groups * T * 4 + cap * sizeof(vtx::PrimRec) + scene_clusters(n_atoms, n_bonds) * 4 +
+                    sizeof(Counters) + 4096);
 }
 
 int vtx_scene_create(vtx_context* ctx, const float* positions, const float* radii, const uint32_t* colors,
@@ -641,7 +915,7 @@ int vtx_scene_create(vtx_context* ctx, const float* positions, const float* radi
     sc->m = n_bonds;
     sc->bytes = bytes;
     const size_t na = (size_t)n_atoms, nb = (size_t)n_bonds;
-    const size_t ncl = (na + vtx::kCluster - 1) / vtx::kCluster + (nb + vtx::kCluster - 1) / vtx::kCluster;
+    const size_t ncl = scene_clusters(n_atoms, n_bonds);
     void* tmp = nullptr;
     const size_t tmp_bytes = vtx::scene_build_temp_bytes(na, nb);
     uint32_t m_valid = 0, n_bad = 0;
@@ -655,9 +929,8 @@ int vtx_scene_create(vtx_context* ctx, const float* positions, const float* radi
     };
     if ((rc = dev_alloc(&sc->xyzr, na, "atom stream")) || (rc = dev_alloc(&sc->atom_id, na, "atom ids")) ||
         (rc = dev_alloc(&sc->bond_rec, nb, "bond records")) || (rc = dev_alloc(&sc->cluster_box, 2 * ncl, "cluster boxes")) ||
-        (rc = dev_alloc(&sc->vis_clusters, ncl, "visible clusters")) || (rc = dev_alloc(&sc->pos, 3 * na, "positions")) ||
-        (rc = dev_alloc(&sc->rad, na, "radii")) || (rc = dev_alloc(&sc->col, na, "colours")) ||
-        (rc = dev_alloc(&sc->bonds, 2 * nb, "bonds")))
+        (rc = dev_alloc(&sc->pos, 3 * na, "positions")) || (rc = dev_alloc(&sc->rad, na, "radii")) ||
+        (rc = dev_alloc(&sc->col, na, "colours")) || (rc = dev_alloc(&sc->bonds, 2 * nb, "bonds")))
         return bail(rc);
     if (hipMalloc(&tmp, tmp_bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -673,7 +946,7 @@ int vtx_scene_create(vtx_context* ctx, const float* positions, const float* radi
     sc->S.xyzr = sc->xyzr;
     sc->S.atom_id = sc->atom_id;
     sc->S.bond_rec = sc->bond_rec;
-    sc->S.vis_clusters = sc->vis_clusters;
+    sc->S.vis_clusters = nullptr;   // per render, in the stream's scratch
     hipError_t e = vtx::scene_build(sc->pos, sc->rad, sc->bonds, na, nb, sc->S, sc->xyzr, sc->atom_id, sc->bond_rec,
                                     sc->cluster_box, tmp, tmp_bytes, &m_valid, &n_bad, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -683,6 +956,64 @@ int vtx_scene_create(vtx_context* ctx, const float* positions, const float* radi
     *out = sc;
     return VTX_OK;
 }
+
+int vtx_scene_add_frames(vtx_scene* scene, const float* positions, int32_t n_frames, void* stream,
+                         int32_t* first_frame) {
+    if (!scene) return fail(VTX_EINVAL, "scene is NULL");
+    if (n_frames < 1) return fail(VTX_EINVAL, "n_frames must be >= 1");
+    if (scene->n > 0 && !positions) return fail(VTX_EINVAL, "positions are NULL");
+    if ((int64_t)scene->frames.size() + n_frames > 1000000) return fail(VTX_EINVAL, "too many frames");
+    int dev = 0;
+    VTX_HIP(hipGetDevice(&dev));
+    if (dev != scene->device) return fail(VTX_EINVAL, "scene lives on device %d, current is %d", scene->device, dev);
+    const size_t na = (size_t)scene->n, nc = scene_clusters(scene->n, scene->m);
+    const size_t pos_b = align_up(na * 3 * sizeof(float), 256), xyzr_b = align_up(na * sizeof(float4), 256),
+                 box_b = align_up(nc * 2 * sizeof(float4), 256);
+    const size_t bytes = (size_t)n_frames * frame_bytes(scene->n, scene->m);
+    vtx_context* ctx = scene->ctx;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->budget && ctx->used + bytes > ctx->budget)
+            return fail(VTX_EBUSY, "%d frames of %zu bytes exceed the context budget (%zu of %zu in use)", n_frames,
+                        bytes, ctx->used, ctx->budget);
+        ctx->used += bytes;
+    }
+    char* block = nullptr;
+    const size_t per = pos_b + xyzr_b + box_b;
+    if (hipMalloc(&block, per * (size_t)n_frames) != hipSuccess) {
+        (void)hipGetLastError();
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->used -= bytes;
+        return fail(VTX_ENOMEM, "cannot allocate %zu bytes for %d frames", per * (size_t)n_frames, n_frames);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t first = (int32_t)scene->frames.size() + 1;
+    for (int32_t f = 0; f < n_frames; ++f) {
+        SceneFrame fr;
+        char* base = block + per * (size_t)f;
+        fr.pos = reinterpret_cast<float*>(base);
+        fr.xyzr = reinterpret_cast<float4*>(base + pos_b);
+        fr.cluster_box = reinterpret_cast<float4*>(base + pos_b + xyzr_b);
+        hipError_t e = hipSuccess;
+        if (na) e = hipMemcpyAsync(fr.pos, positions + (size_t)f * na * 3, na * 3 * sizeof(float), hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = vtx::scene_update_positions(fr.pos, scene->S, fr.xyzr, fr.cluster_box, st);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(st);
+            hipFree(block);
+            scene->frames.resize((size_t)first - 1);
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->used -= bytes;
+            return fail(VTX_EHIP, "storing frame %d failed: %s", f, hipGetErrorString(e));
+        }
+        scene->frames.push_back(fr);
+    }
+    scene->frame_blocks.push_back(block);
+    scene->bytes += bytes;
+    if (first_frame) *first_frame = first;
+    return VTX_OK;
+}
+
+int32_t vtx_scene_frames(const vtx_scene* scene) { return scene ? (int32_t)scene->frames.size() + 1 : 0; }
 
 int vtx_scene_update_positions(vtx_scene* scene, const float* positions, void* stream) {
     if (!scene || (scene->n > 0 && !positions)) return fail(VTX_EINVAL, "scene/positions is NULL");
@@ -725,25 +1056,49 @@ int vtx_render_scene(vtx_scene* scene, const vtx_camera* cam, const vtx_options*
     int dev = 0;
     VTX_HIP(hipGetDevice(&dev));
     if (dev != scene->device) return fail(VTX_EINVAL, "scene lives on device %d, current is %d", scene->device, dev);
-    vtx::SampleKernel K;
-    sample_kernel(o, &K);
+    std::vector<JobDesc> d{plain_desc(F, o, scene->pos, scene->rad, scene->col, scene->bonds)};
+    d[0].scene = true;
+    d[0].S = scene->S;
+    d[0].depth = depth;
+    d[0].id = id;
+    d[0].rgba = rgba;
     std::lock_guard<std::mutex> lk(g_mu);
-    hipEvent_t* marks = nullptr;
-    if (o.flags & VTX_FLAG_TIMING) {
-        Workspace* ws = nullptr;
-        if ((rc = get_workspace((hipStream_t)stream, &ws))) return rc;
-        TimingSlot* slot = nullptr;
-        if ((rc = timing_slot(ws, &slot))) return rc;
-        marks = slot->ev;
+    return render_locked(d, true, true, (hipStream_t)stream);
+}
+
+int vtx_render_batch(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, void* stream) {
+    if (!ctx) return fail(VTX_EINVAL, "context is NULL");
+    if (n_jobs < 0 || n_jobs > kMaxBatch) return fail(VTX_EINVAL, "n_jobs=%d not in 0..%d", n_jobs, kMaxBatch);
+    if (n_jobs == 0) return VTX_OK;
+    if (!jobs) return fail(VTX_EINVAL, "jobs is NULL");
+    int dev = 0;
+    VTX_HIP(hipGetDevice(&dev));
+    if (dev != ctx->device) return fail(VTX_EINVAL, "current device %d is not the context's %d", dev, ctx->device);
+    std::vector<JobDesc> d((size_t)n_jobs);
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        const vtx_job& j = jobs[i];
+        const vtx_scene* sc = j.scene;
+        if (!sc) return fail(VTX_EINVAL, "job %d: scene is NULL", i);
+        if (sc->ctx != ctx) return fail(VTX_EINVAL, "job %d: scene belongs to another context", i);
+        if (j.frame < 0 || j.frame > (int32_t)sc->frames.size())
+            return fail(VTX_EINVAL, "job %d: frame %d not in 0..%zu", i, j.frame, sc->frames.size());
+        if (!j.rgba || !j.depth || !j.id) return fail(VTX_EINVAL, "job %d: rgba/depth/id outputs are NULL", i);
+        const vtx_options o = resolve_options(&j.options);
+        Frame F;
+        int rc = make_frame(&j.camera, o, j.width, j.height, sc->n, sc->m, &F);
+        if (rc) return fail(rc, "job %d: %s", i, g_error.c_str());
+        vtx::SceneDev S;
+        const float* pos = nullptr;
+        scene_frame(sc, j.frame, &S, &pos);
+        d[(size_t)i] = plain_desc(F, o, pos, sc->rad, sc->col, sc->bonds);
+        d[(size_t)i].scene = true;
+        d[(size_t)i].S = S;
+        d[(size_t)i].depth = j.depth;
+        d[(size_t)i].id = j.id;
+        d[(size_t)i].rgba = j.rgba;
     }
-    rc = gbuffer_locked(scene->pos, scene->rad, scene->n, scene->bonds, scene->m, F, W, H, depth, id,
-                        (hipStream_t)stream, marks, &scene->S);
-    if (rc) return rc;
-    if (marks) VTX_HIP(hipEventRecord(marks[5], (hipStream_t)stream));
-    VTX_HIP(vtx::launch_shade(F, K, scene->pos, scene->rad, scene->col, scene->bonds, depth, id, rgba, nullptr,
-                              nullptr, nullptr, (hipStream_t)stream));
-    if (marks) VTX_HIP(hipEventRecord(marks[6], (hipStream_t)stream));
-    return VTX_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return render_locked(d, true, true, (hipStream_t)stream);
 }
 
 int vtx_read_stats(void* stream, vtx_stats* out) {
@@ -770,7 +1125,11 @@ int vtx_set_bin_capacity(void* stream, uint64_t entries) {
     VTX_HIP(hipStreamSynchronize(ws->stream));
     harvest(ws);
     ws->fixed_capacity = entries > 0;
-    ws->want_capacity = entries;   // 0: re-derived from the next frame's size
+    ws->fixed_entries = entries;
+    for (Bins* b : ws->slots) {
+        b->want_capacity = entries;   // 0: re-derived from the next frame's size
+        b->sized_nprim = ~0ull;
+    }
     return VTX_OK;
 }
 
@@ -816,22 +1175,13 @@ int vtx_release_scratch(void* stream) {
     if (it == g_ws.end()) return VTX_OK;
     Workspace* ws = it->second;
     VTX_HIP(hipStreamSynchronize(ws->stream));
-    free_ws_buffers(ws);
-    if (ws->tslots) {
-        for (int i = 0; i < kTimingRing; ++i)
-            for (int m = 0; m < kMarks; ++m) hipEventDestroy(ws->tslots[i].ev[m]);
-        delete[] ws->tslots;
-    }
-    hipFree(ws->bb.ctr);
-    hipHostFree(ws->host_ctr);
-    hipEventDestroy(ws->done);
-    delete ws;
+    workspace_free(ws);
     g_ws.erase(it);
     return VTX_OK;
 }
 
 const char* vtx_last_error(void) { return g_error.c_str(); }
 
-const char* vtx_version(void) { return "vtx-mi355x 0.1.0 (gfx950)"; }
+const char* vtx_version(void) { return "vtx-mi355x 0.2.0 (gfx950)"; }
 
 }  // extern "C"

@@ -142,15 +142,39 @@ struct SceneSource {     // a resident scene: the clusters that passed the frust
     }
 };
 
-template <class Src>
-__global__ void __launch_bounds__(kBinThreads) k_count(Frame F, Src src, uint32_t chunk,
-                                                       PrimRec* __restrict__ vis_rec, uint2* __restrict__ vis_rect,
-                                                       uint32_t* __restrict__ vis_cnt, uint2* __restrict__ vis_box,
-                                                       uint32_t* __restrict__ hist_out,
-                                                       uint32_t* __restrict__ tile_cnt, Counters* ctr) {
+template <bool kScene>
+struct SourceOf;
+template <>
+struct SourceOf<false> {
+    __device__ static PlainSource make(const Job& J) {
+        return PlainSource{J.pos, J.rad, J.bonds, (uint64_t)J.F.n_atoms + J.F.n_bonds, J.bb.chunk};
+    }
+};
+template <>
+struct SourceOf<true> {
+    __device__ static SceneSource make(const Job& J) { return SceneSource{J.S, J.bb.ctr, J.bb.groups}; }
+};
+
+// Count.  Work block b of a job is that job's binning workgroup b.
+template <class JS, bool kScene>
+__global__ void __launch_bounds__(kBinThreads) k_count(JS js) {
     extern __shared__ uint32_t hist[];
     __shared__ uint32_t local_n, bx0, by0, bx1, by1;
     __shared__ unsigned long long local_pairs;
+    uint32_t blk;
+    const int ji = js.find(blockIdx.x, blk);
+    if (ji < 0) return;
+    const Job& J = js.job(ji);
+    const Frame F = J.F;
+    const auto src = SourceOf<kScene>::make(J);
+    const uint32_t chunk = J.bb.chunk;
+    PrimRec* __restrict__ const vis_rec = J.bb.vis_rec;
+    uint2* __restrict__ const vis_rect = J.bb.vis_rect;
+    uint32_t* __restrict__ const vis_cnt = J.bb.vis_cnt;
+    uint2* __restrict__ const vis_box = J.bb.vis_box;
+    uint32_t* __restrict__ const hist_out = J.bb.hist;
+    uint32_t* __restrict__ const tile_cnt = J.bb.tile_cnt;
+    Counters* const ctr = J.bb.ctr;
     const int T = F.tiles_x * F.tiles_y;
     const int tid = threadIdx.x;
     for (int t = tid; t < T; t += kBinThreads) hist[t] = 0;
@@ -165,8 +189,8 @@ __global__ void __launch_bounds__(kBinThreads) k_count(Frame F, Src src, uint32_
     __syncthreads();
     uint32_t mx0 = 0xFFFF, my0 = 0xFFFF, mx1 = 0, my1 = 0, my_pairs = 0;
 
-    const uint64_t start = (uint64_t)blockIdx.x * chunk;
-    const uint64_t nitems = src.items(blockIdx.x);
+    const uint64_t start = (uint64_t)blk * chunk;
+    const uint64_t nitems = src.items(blk);
     const int ts = F.tile;
     uint32_t bad_count = 0;
     for (uint64_t base = 0; base < nitems; base += kBinThreads) {
@@ -174,7 +198,7 @@ __global__ void __launch_bounds__(kBinThreads) k_count(Frame F, Src src, uint32_
         int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
         bool bad = false;
         PrimRec rec;
-        const bool vis = k < nitems && src.record(F, blockIdx.x, k, x0, y0, x1, y1, rec, bad);
+        const bool vis = k < nitems && src.record(F, blk, k, x0, y0, x1, y1, rec, bad);
         bad_count += bad ? 1u : 0u;
         const unsigned long long vmask = __ballot(vis);
         uint32_t slot_base = 0;
@@ -204,15 +228,15 @@ __global__ void __launch_bounds__(kBinThreads) k_count(Frame F, Src src, uint32_
         atomicAdd(&local_pairs, (unsigned long long)my_pairs);
     }
     __syncthreads();
-    uint32_t* row = hist_out + (size_t)blockIdx.x * T;
+    uint32_t* row = hist_out + (size_t)blk * T;
     for (int t = tid; t < T; t += kBinThreads) {
         const uint32_t h = hist[t];
         row[t] = h;
         if (h) atomicAdd(&tile_cnt[t], h);
     }
     if (tid == 0) {
-        vis_cnt[blockIdx.x] = local_n;
-        vis_box[blockIdx.x] = make_uint2(bx0 | (by0 << 16), bx1 | (by1 << 16));
+        vis_cnt[blk] = local_n;
+        vis_box[blk] = make_uint2(bx0 | (by0 << 16), bx1 | (by1 << 16));
         atomicAdd(&ctr->vis_count, local_n);
         if (local_pairs) atomicAdd(&ctr->pairs_counted, local_pairs);
     }
@@ -227,19 +251,31 @@ constexpr uint32_t kNoRun = 0xFFFFFFFFu;
 // primitives touch, one run of that tile's list (one global atomic).  It then
 // places its primitives with LDS atomics.  Workgroup 0 also stores the tile
 // offsets for the resolve and publishes the frame counters.
-__global__ void __launch_bounds__(kBinThreads) k_scatter(Frame F, uint32_t chunk, const PrimRec* __restrict__ vis_rec,
-                                                         const uint2* __restrict__ vis_rect,
-                                                         const uint32_t* __restrict__ vis_cnt,
-                                                         const uint32_t* __restrict__ hist_in,
-                                                         const uint32_t* __restrict__ cnt, uint64_t* __restrict__ off,
-                                                         uint32_t* fill, PrimRec* __restrict__ list, uint64_t capacity,
-                                                         Counters* ctr, Counters* host_ctr) {
+template <class JS>
+__global__ void __launch_bounds__(kBinThreads) k_scatter(JS js) {
     extern __shared__ uint32_t cur[];
     __shared__ unsigned long long wtot[kBinThreads / 64];
     __shared__ unsigned int n_over;
+    uint32_t blk;
+    const int ji = js.find(blockIdx.x, blk);
+    if (ji < 0) return;
+    const Job& J = js.job(ji);
+    const Frame F = J.F;
+    const uint32_t chunk = J.bb.chunk;
+    const PrimRec* __restrict__ const vis_rec = J.bb.vis_rec;
+    const uint2* __restrict__ const vis_rect = J.bb.vis_rect;
+    const uint32_t* __restrict__ const vis_cnt = J.bb.vis_cnt;
+    const uint32_t* __restrict__ const hist_in = J.bb.hist;
+    const uint32_t* __restrict__ const cnt = J.bb.tile_cnt;
+    uint64_t* __restrict__ const off = J.bb.tile_off;
+    uint32_t* const fill = J.bb.tile_fill;
+    PrimRec* __restrict__ const list = J.bb.list;
+    const uint64_t capacity = J.bb.capacity;
+    Counters* const ctr = J.bb.ctr;
+    Counters* const host_ctr = J.bb.host_ctr;
     const int T = F.tiles_x * F.tiles_y;
     const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
-    const bool lead = blockIdx.x == 0;
+    const bool lead = blk == 0;
     const int per = (T + kBinThreads - 1) / kBinThreads;
     const int b = min(T, tid * per), e = min(T, b + per);
     unsigned long long sum = 0;
@@ -259,7 +295,7 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(Frame F, uint32_t chunk
         run += w < wave ? v : 0ull;
         total += v;
     }
-    const uint32_t* row = hist_in + (size_t)blockIdx.x * T;
+    const uint32_t* row = hist_in + (size_t)blk * T;
     unsigned int over = 0;
     for (int t = b; t < e; ++t) {
         const uint32_t c = cnt[t];
@@ -302,11 +338,12 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(Frame F, uint32_t chunk
         }
     }
     __syncthreads();
-    const uint32_t n = vis_cnt[blockIdx.x];
-    const uint64_t start = (uint64_t)blockIdx.x * chunk;
+    const uint32_t n = vis_cnt[blk];
+    const uint64_t start = (uint64_t)blk * chunk;
     const int ts = F.tile;
     for (uint32_t k = tid; k < n; k += kBinThreads) {
-        PrimRec rec = vis_rec[start + k];
+        const float4 g0 = vis_rec[start + k].g0;
+        const uint4 g1 = vis_rec[start + k].g1;
         const uint2 r = vis_rect[start + k];
         const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16;
         for (int ty = y0 / ts; ty <= y1 / ts; ++ty)
@@ -316,9 +353,11 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(Frame F, uint32_t chunk
                 // the footprint clipped to this tile, in tile-local pixels
                 const int lx0 = max(x0 - tx * ts, 0), ly0 = max(y0 - ty * ts, 0);
                 const int lx1 = min(x1 - tx * ts, ts - 1), ly1 = min(y1 - ty * ts, ts - 1);
-                rec.g1.w = (uint32_t)lx0 | ((uint32_t)ly0 << 8) | ((uint32_t)(lx1 - lx0 + 1) << 16) |
-                           ((uint32_t)(ly1 - ly0 + 1) << 24);
-                list[atomicAdd(&cur[t], 1u)] = rec;
+                const uint32_t fp = (uint32_t)lx0 | ((uint32_t)ly0 << 8) | ((uint32_t)(lx1 - lx0 + 1) << 16) |
+                                    ((uint32_t)(ly1 - ly0 + 1) << 24);
+                PrimRec* dst = &list[atomicAdd(&cur[t], 1u)];
+                dst->g0 = g0;
+                dst->g1 = make_uint4(g1.x, g1.y, g1.z, fp);
             }
     }
 }
@@ -343,40 +382,35 @@ hipError_t launch_zero(uint32_t* p, size_t n, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_count(const Frame& F, const float* pos, const float* rad, const uint32_t* bonds,
-                        const BinBuffers& bb, hipStream_t stream, hipEvent_t* marks) {
-    const int T = F.tiles_x * F.tiles_y;
-    if (T > kMaxLdsTiles) return hipErrorInvalidValue;
-    const size_t lds = (size_t)T * sizeof(uint32_t);
-    if (marks) (void)hipEventRecord(marks[0], stream);
-    if (marks) (void)hipEventRecord(marks[1], stream);
-    const PlainSource src{pos, rad, bonds, (uint64_t)F.n_atoms + F.n_bonds, bb.chunk};
-    k_count<PlainSource><<<bb.groups, kBinThreads, lds, stream>>>(F, src, bb.chunk, bb.vis_rec, bb.vis_rect, bb.vis_cnt,
-                                                                  bb.vis_box, bb.hist, bb.tile_cnt, bb.ctr);
+template <class JS>
+hipError_t count_impl(const JS& js, bool scene, uint32_t grid, int max_tiles, hipStream_t stream) {
+    if (max_tiles > kMaxLdsTiles) return hipErrorInvalidValue;
+    if (grid == 0) return hipSuccess;
+    const size_t lds = (size_t)max_tiles * sizeof(uint32_t);
+    if (scene) k_count<JS, true><<<grid, kBinThreads, lds, stream>>>(js);
+    else k_count<JS, false><<<grid, kBinThreads, lds, stream>>>(js);
     return hipGetLastError();
 }
 
-hipError_t launch_count_scene(const Frame& F, const SceneDev& S, const BinBuffers& bb, hipStream_t stream,
-                              hipEvent_t* marks) {
-    const int T = F.tiles_x * F.tiles_y;
-    if (T > kMaxLdsTiles) return hipErrorInvalidValue;
-    const size_t lds = (size_t)T * sizeof(uint32_t);
-    if (marks) (void)hipEventRecord(marks[1], stream);
-    const SceneSource src{S, bb.ctr, bb.groups};
-    k_count<SceneSource><<<bb.groups, kBinThreads, lds, stream>>>(F, src, bb.chunk, bb.vis_rec, bb.vis_rect, bb.vis_cnt,
-                                                                  bb.vis_box, bb.hist, bb.tile_cnt, bb.ctr);
+template <class JS>
+hipError_t scatter_impl(const JS& js, uint32_t grid, int max_tiles, hipStream_t stream) {
+    if (max_tiles > kMaxLdsTiles) return hipErrorInvalidValue;
+    if (grid == 0) return hipSuccess;
+    k_scatter<JS><<<grid, kBinThreads, (size_t)max_tiles * sizeof(uint32_t), stream>>>(js);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const Frame& F, const BinBuffers& bb, hipStream_t stream, hipEvent_t* marks) {
-    const int T = F.tiles_x * F.tiles_y;
-    const size_t lds = (size_t)T * sizeof(uint32_t);
-    if (marks) (void)hipEventRecord(marks[2], stream);
-    if (marks) (void)hipEventRecord(marks[3], stream);
-    k_scatter<<<bb.groups, kBinThreads, lds, stream>>>(F, bb.chunk, bb.vis_rec, bb.vis_rect, bb.vis_cnt, bb.hist,
-                                                       bb.tile_cnt, bb.tile_off, bb.tile_fill, bb.list, bb.capacity,
-                                                       bb.ctr, bb.host_ctr);
-    return hipGetLastError();
+hipError_t launch_count(const OneJob& js, bool scene, uint32_t grid, int max_tiles, hipStream_t stream) {
+    return count_impl(js, scene, grid, max_tiles, stream);
+}
+hipError_t launch_count(const JobList& js, bool scene, uint32_t grid, int max_tiles, hipStream_t stream) {
+    return count_impl(js, scene, grid, max_tiles, stream);
+}
+hipError_t launch_scatter(const OneJob& js, uint32_t grid, int max_tiles, hipStream_t stream) {
+    return scatter_impl(js, grid, max_tiles, stream);
+}
+hipError_t launch_scatter(const JobList& js, uint32_t grid, int max_tiles, hipStream_t stream) {
+    return scatter_impl(js, grid, max_tiles, stream);
 }
 
 }  // namespace vtx

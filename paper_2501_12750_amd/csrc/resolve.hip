@@ -132,17 +132,10 @@ __device__ inline Rec make_rec(const Frame& F, const PrimRec& p) {
     return r;
 }
 
-template <int TS>
-__global__ void __launch_bounds__(kBlock) k_resolve(Frame F, uint32_t* __restrict__ cnt,
-                                                    const uint64_t* __restrict__ off,
-                                                    const PrimRec* __restrict__ list, uint64_t capacity,
-                                                    const PrimRec* __restrict__ vis_rec,
-                                                    const uint2* __restrict__ vis_rect,
-                                                    const uint32_t* __restrict__ vis_cnt,
-                                                    const uint2* __restrict__ vis_box, uint32_t chunk,
-                                                    uint32_t groups, uint32_t* __restrict__ fill,
-                                                    Counters* ctr, Counters* host_ctr,
-                                                    float* __restrict__ depth, uint32_t* __restrict__ out_id) {
+// Work block t of a job is that job's tile t; the launch's blocks are spread
+// over the XCDs in contiguous ranges.
+template <int TS, class JS>
+__global__ void __launch_bounds__(kBlock) k_resolve(JS js) {
     __shared__ unsigned long long keys[TS * TS];
     __shared__ Rec recs[kChunk];
     __shared__ uint32_t pref[kChunk + 1];
@@ -150,8 +143,28 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Frame F, uint32_t* __restric
     constexpr int kHzBlocks = HzGrid<TS>::kBlocks;
     __shared__ uint32_t hz[kHzBlocks];
 
+    uint32_t tu;
+    const int ji = js.find((uint32_t)xcd_contiguous(blockIdx.x, gridDim.x), tu);
+    if (ji < 0) return;
+    const Job& J = js.job(ji);
+    const Frame F = J.F;
+    uint32_t* __restrict__ const cnt = J.bb.tile_cnt;
+    const uint64_t* __restrict__ const off = J.bb.tile_off;
+    const PrimRec* __restrict__ const list = J.bb.list;
+    const uint64_t capacity = J.bb.capacity;
+    const PrimRec* __restrict__ const vis_rec = J.bb.vis_rec;
+    const uint2* __restrict__ const vis_rect = J.bb.vis_rect;
+    const uint32_t* __restrict__ const vis_cnt = J.bb.vis_cnt;
+    const uint2* __restrict__ const vis_box = J.bb.vis_box;
+    const uint32_t chunk = J.bb.chunk, groups = J.bb.groups;
+    uint32_t* __restrict__ const fill = J.bb.tile_fill;
+    Counters* const ctr = J.bb.ctr;
+    Counters* const host_ctr = J.bb.host_ctr;
+    float* __restrict__ const depth = J.depth;
+    uint32_t* __restrict__ const out_id = J.id;
+
     const int T = F.tiles_x * F.tiles_y;
-    const int t = xcd_contiguous(blockIdx.x, T);
+    const int t = (int)tu;
     const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
     const bool stats = (F.flags & 1u) != 0;
     unsigned long long n_tested = 0, n_hit = 0, n_hit_bond = 0;
@@ -332,7 +345,7 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Frame F, uint32_t* __restric
         if (tid == 0) {
             __threadfence();
             const unsigned int ticket = atomicAdd(&ctr->done_blocks, 1u);
-            if (ticket == gridDim.x - 1) {
+            if (ticket == (unsigned int)T - 1) {
                 __threadfence();
                 const volatile Counters* src = ctr;
                 host_ctr->frag_tested = src->frag_tested;
@@ -346,28 +359,25 @@ __global__ void __launch_bounds__(kBlock) k_resolve(Frame F, uint32_t* __restric
 
 }  // namespace
 
-hipError_t launch_resolve(const Frame& F, const float* pos, const float* rad, const uint32_t* bonds,
-                          const BinBuffers& bb, float* depth, uint32_t* id, hipStream_t stream) {
-    (void)pos;
-    (void)rad;
-    (void)bonds;
-    const int T = F.tiles_x * F.tiles_y;
-    const int grid = xcd_grid(T);
-#define VTX_RESOLVE(TS)                                                                                      \
-    k_resolve<TS><<<grid, kBlock, 0, stream>>>(F, bb.tile_cnt, bb.tile_off, bb.list, bb.capacity, bb.vis_rec, \
-                                               bb.vis_rect, bb.vis_cnt, bb.vis_box, bb.chunk, bb.groups,     \
-                                               bb.tile_fill,                                                  \
-                                               bb.ctr,                                                        \
-                                               bb.host_ctr, depth, id)
-    switch (F.tile) {
-        case 8: VTX_RESOLVE(8); break;
-        case 16: VTX_RESOLVE(16); break;
-        case 32: VTX_RESOLVE(32); break;
-        case 64: VTX_RESOLVE(64); break;
+template <class JS>
+hipError_t resolve_impl(const JS& js, int tile, uint32_t grid, hipStream_t stream) {
+    if (grid == 0) return hipSuccess;
+    const unsigned g = (unsigned)xcd_grid((int)grid);
+    switch (tile) {
+        case 8: k_resolve<8, JS><<<g, kBlock, 0, stream>>>(js); break;
+        case 16: k_resolve<16, JS><<<g, kBlock, 0, stream>>>(js); break;
+        case 32: k_resolve<32, JS><<<g, kBlock, 0, stream>>>(js); break;
+        case 64: k_resolve<64, JS><<<g, kBlock, 0, stream>>>(js); break;
         default: return hipErrorInvalidValue;
     }
-#undef VTX_RESOLVE
     return hipGetLastError();
+}
+
+hipError_t launch_resolve(const OneJob& js, int tile, uint32_t grid, hipStream_t stream) {
+    return resolve_impl(js, tile, grid, stream);
+}
+hipError_t launch_resolve(const JobList& js, int tile, uint32_t grid, hipStream_t stream) {
+    return resolve_impl(js, tile, grid, stream);
 }
 
 }  // namespace vtx

@@ -92,13 +92,15 @@ __global__ void __launch_bounds__(kBlock) k_gather_atoms(const float* __restrict
 }
 
 // New positions for a trajectory frame (radii kept).
+// New positions of the stored atoms; the radii come from the scene's own
+// stream (`rsrc`, which may be `xyzr` itself).
 __global__ void __launch_bounds__(kBlock) k_update_positions(const float* __restrict__ pos,
                                                              const uint32_t* __restrict__ atom_id, uint32_t n,
-                                                             float4* xyzr) {
+                                                             const float4* rsrc, float4* xyzr) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t a = atom_id[i];
-    const float r = xyzr[i].w;
+    const float r = rsrc[i].w;
     xyzr[i] = make_float4(pos[3 * (size_t)a], pos[3 * (size_t)a + 1], pos[3 * (size_t)a + 2], r);
 }
 
@@ -168,10 +170,18 @@ __global__ void __launch_bounds__(kBlock) k_cluster_boxes(SceneDev S, float4* bo
 
 // Per frame: clusters whose bounding sphere meets the view volume, appended
 // to S.vis_clusters (one atomic per wave).
-__global__ void __launch_bounds__(kBlock) k_cluster_cull(Frame F, SceneDev S, Counters* ctr) {
+template <class JS>
+__global__ void __launch_bounds__(kBlock) k_cluster_cull(JS js) {
+    uint32_t blk;
+    const int ji = js.find(blockIdx.x, blk);
+    if (ji < 0) return;
+    const Job& J = js.job(ji);
+    const Frame F = J.F;
+    const SceneDev S = J.S;
+    Counters* const ctr = J.bb.ctr;
     const uint32_t nc = S.atom_clusters + S.bond_clusters;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < nc; base += gridDim.x * blockDim.x) {
-        const uint32_t c = base + threadIdx.x;
+    {
+        const uint32_t c = blk * kBlock + threadIdx.x;
         bool vis = false;
         if (c < nc) {
             const float4 lo = S.cluster_box[2 * (size_t)c], hi = S.cluster_box[2 * (size_t)c + 1];
@@ -188,7 +198,7 @@ __global__ void __launch_bounds__(kBlock) k_cluster_cull(Frame F, SceneDev S, Co
             }
         }
         const unsigned long long vmask = __ballot(vis);
-        if (!vmask) continue;
+        if (!vmask) return;
         const int leader = __ffsll((long long)vmask) - 1;
         uint32_t slot = 0;
         if ((int)__lane_id() == leader) slot = atomicAdd(&ctr->vis_clusters, (uint32_t)__popcll(vmask));
@@ -276,21 +286,28 @@ hipError_t scene_build(const float* pos, const float* rad, const uint32_t* bonds
     return hipGetLastError();
 }
 
+// Writes the atom stream `xyzr` and the cluster boxes of new positions `pos`
+// (caller's order) in the scene's stored order; radii are read from S.xyzr.
+// `xyzr` may be S.xyzr (in-place update) or another frame's stream.
 hipError_t scene_update_positions(const float* pos, SceneDev& S, float4* xyzr, float4* cluster_box,
                                   hipStream_t stream) {
-    if (S.n_atoms) k_update_positions<<<grid_for(S.n_atoms), kBlock, 0, stream>>>(pos, S.atom_id, S.n_atoms, xyzr);
+    if (S.n_atoms)
+        k_update_positions<<<grid_for(S.n_atoms), kBlock, 0, stream>>>(pos, S.atom_id, S.n_atoms, S.xyzr, xyzr);
     const uint32_t nc = S.atom_clusters + S.bond_clusters;
-    if (nc) k_cluster_boxes<<<grid_for((uint64_t)nc * 64), kBlock, 0, stream>>>(S, cluster_box);
+    SceneDev Sf = S;
+    Sf.xyzr = xyzr;
+    if (nc) k_cluster_boxes<<<grid_for((uint64_t)nc * 64), kBlock, 0, stream>>>(Sf, cluster_box);
     return hipGetLastError();
 }
 
-hipError_t launch_cluster_cull(const Frame& F, const SceneDev& S, Counters* ctr, hipStream_t stream) {
-    const uint32_t nc = S.atom_clusters + S.bond_clusters;
-    if (!nc) return hipSuccess;
-    unsigned g = grid_for(nc);
-    if (g > 2048) g = 2048;
-    k_cluster_cull<<<g, kBlock, 0, stream>>>(F, S, ctr);
+template <class JS>
+hipError_t cull_impl(const JS& js, uint32_t grid, hipStream_t stream) {
+    if (grid == 0) return hipSuccess;
+    k_cluster_cull<JS><<<grid, kBlock, 0, stream>>>(js);
     return hipGetLastError();
 }
+
+hipError_t launch_cluster_cull(const OneJob& js, uint32_t grid, hipStream_t stream) { return cull_impl(js, grid, stream); }
+hipError_t launch_cluster_cull(const JobList& js, uint32_t grid, hipStream_t stream) { return cull_impl(js, grid, stream); }
 
 }  // namespace vtx

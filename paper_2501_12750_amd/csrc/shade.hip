@@ -32,17 +32,27 @@ __device__ inline uint32_t quantize(float c) {
     return (uint32_t)floorf(fmaf(255.0f, c, 0.5f));
 }
 
-__global__ void __launch_bounds__(kBlock) k_shade(Frame F, SampleKernel K, const float* __restrict__ pos,
-                                                  const float* __restrict__ rad, const uint32_t* __restrict__ col,
-                                                  const uint32_t* __restrict__ bonds,
-                                                  const float* __restrict__ depth, const uint32_t* __restrict__ ids,
-                                                  uint32_t* __restrict__ rgba, float* __restrict__ normal_out,
-                                                  uint32_t* __restrict__ albedo_out, float* __restrict__ ao_out) {
+// Work block t of a job is that job's 16x16 tile t.
+template <class JS>
+__global__ void __launch_bounds__(kBlock) k_shade(JS js) {
     __shared__ float zt[kSpan * kSpan];
-    const int tiles_x = (F.W + kTile - 1) / kTile, tiles_y = (F.H + kTile - 1) / kTile;
-    const int T = tiles_x * tiles_y;
-    const int t = xcd_contiguous(blockIdx.x, T);
-    if (t >= T) return;
+    uint32_t tu;
+    const int ji = js.find((uint32_t)xcd_contiguous(blockIdx.x, gridDim.x), tu);
+    if (ji < 0) return;
+    const Job& J = js.job(ji);
+    const Frame F = J.F;
+    const SampleKernel& K = js.samples(ji);
+    const float* __restrict__ const pos = J.pos;
+    const uint32_t* __restrict__ const col = J.col;
+    const uint32_t* __restrict__ const bonds = J.bonds;
+    const float* __restrict__ const depth = J.depth;
+    const uint32_t* __restrict__ const ids = J.id;
+    uint32_t* __restrict__ const rgba = J.rgba;
+    float* __restrict__ const normal_out = J.normal;
+    uint32_t* __restrict__ const albedo_out = J.albedo;
+    float* __restrict__ const ao_out = J.ao;
+    const int tiles_x = (F.W + kTile - 1) / kTile;
+    const int t = (int)tu;
     const int tid = threadIdx.x;
     const int tx0 = (t % tiles_x) * kTile, ty0 = (t / tiles_x) * kTile;
     const int bx0 = tx0 - kHalo, by0 = ty0 - kHalo;
@@ -185,12 +195,14 @@ __global__ void __launch_bounds__(kBlock) k_shade(Frame F, SampleKernel K, const
 
 }  // namespace
 
-hipError_t launch_shade(const Frame& F, const SampleKernel& K, const float* pos, const float* rad,
-                        const uint32_t* col, const uint32_t* bonds, const float* depth, const uint32_t* id,
-                        uint32_t* rgba, float* normal, uint32_t* albedo, float* ao, hipStream_t stream) {
-    const int tiles = ((F.W + kTile - 1) / kTile) * ((F.H + kTile - 1) / kTile);
-    k_shade<<<xcd_grid(tiles), kBlock, 0, stream>>>(F, K, pos, rad, col, bonds, depth, id, rgba, normal, albedo, ao);
+template <class JS>
+hipError_t shade_impl(const JS& js, uint32_t grid, hipStream_t stream) {
+    if (grid == 0) return hipSuccess;
+    k_shade<JS><<<(unsigned)xcd_grid((int)grid), kBlock, 0, stream>>>(js);
     return hipGetLastError();
 }
+
+hipError_t launch_shade(const OneJob& js, uint32_t grid, hipStream_t stream) { return shade_impl(js, grid, stream); }
+hipError_t launch_shade(const JobList& js, uint32_t grid, hipStream_t stream) { return shade_impl(js, grid, stream); }
 
 }  // namespace vtx

@@ -244,31 +244,96 @@ struct SceneDev {
     const uint32_t* atom_id;            // n_atoms: original index of each stored atom
     const uint4* bond_rec;              // n_bonds: (stored index a, stored index b, original bond index, 0)
     const float4* cluster_box;          // 2 per cluster: (min xyz, -), (max xyz, -); bond boxes exclude the radius
-    uint32_t* vis_clusters;             // atom_clusters + bond_clusters: visible cluster ids (per frame)
+    uint32_t* vis_clusters;             // atom_clusters + bond_clusters: visible cluster ids (per render)
 };
-hipError_t launch_cluster_cull(const Frame& F, const SceneDev& S, Counters* ctr, hipStream_t stream);
 size_t scene_build_temp_bytes(uint64_t n, uint64_t m);
 hipError_t scene_build(const float* pos, const float* rad, const uint32_t* bonds, uint64_t n, uint64_t m,
                        SceneDev& S, float4* xyzr, uint32_t* atom_id, uint4* bond_rec, float4* cluster_box,
                        void* tmp, size_t tmp_bytes, uint32_t* m_valid, uint32_t* n_bad, hipStream_t stream);
 hipError_t scene_update_positions(const float* pos, SceneDev& S, float4* xyzr, float4* cluster_box,
                                   hipStream_t stream);
-hipError_t launch_count_scene(const Frame& F, const SceneDev& S, const BinBuffers& bb, hipStream_t stream,
-                              hipEvent_t* marks = nullptr);
 
 // Zeroes n 32-bit words (used when scratch is allocated; the frame kernels
 // leave the tile counts and the counters zeroed for the next frame).
 hipError_t launch_zero(uint32_t* p, size_t n, hipStream_t stream);
 
-// `marks`, when not null, holds events recorded before each kernel launch
-// (bin: clear, project, scan, scatter) for per-kernel timing.
-hipError_t launch_count(const Frame& F, const float* pos, const float* rad, const uint32_t* bonds,
-                        const BinBuffers& bb, hipStream_t stream, hipEvent_t* marks = nullptr);
-hipError_t launch_scatter(const Frame& F, const BinBuffers& bb, hipStream_t stream, hipEvent_t* marks = nullptr);
-hipError_t launch_resolve(const Frame& F, const float* pos, const float* rad, const uint32_t* bonds,
-                          const BinBuffers& bb, float* depth, uint32_t* id, hipStream_t stream);
-hipError_t launch_shade(const Frame& F, const SampleKernel& K, const float* pos, const float* rad,
-                        const uint32_t* col, const uint32_t* bonds, const float* depth, const uint32_t* id,
-                        uint32_t* rgba, float* normal, uint32_t* albedo, float* ao, hipStream_t stream);
+// ---------------------------------------------------------------------------
+// jobs: one render (camera, image, primitives, scratch, outputs)
+// ---------------------------------------------------------------------------
+struct Job {
+    Frame F;
+    // primitives in the caller's order: the plain path bins them, and the
+    // deferred pass reads every render's primitives through them by id
+    const float* pos;
+    const float* rad;
+    const uint32_t* col;
+    const uint32_t* bonds;
+    SceneDev S;              // resident scene (scene path only)
+    BinBuffers bb;           // this render's binning scratch
+    float* depth;
+    uint32_t* id;
+    uint32_t* rgba;
+    float* normal;           // optional deferred outputs (may be null)
+    uint32_t* albedo;
+    float* ao;
+};
+
+// Per-kernel work-block counts of a job (the grid of a launch is the sum over
+// its jobs, padded to a multiple of 8 for the XCD mapping).
+inline uint32_t cull_blocks(const SceneDev& S) {
+    const uint32_t nc = S.atom_clusters + S.bond_clusters;
+    return (nc + kBlock - 1) / kBlock;
+}
+inline uint32_t shade_blocks(const Frame& F) { return (uint32_t)(((F.W + 15) / 16) * ((F.H + 15) / 16)); }
+
+// A launch over one render: the job travels in the kernel arguments.
+struct OneJob {
+    Job j;
+    SampleKernel K;
+    uint32_t blocks;         // work blocks of the launch (the grid may be padded past it)
+    __device__ int find(uint32_t g, uint32_t& local) const {
+        local = g;
+        return g < blocks ? 0 : -1;
+    }
+    __device__ const Job& job(int) const { return j; }
+    __device__ const SampleKernel& samples(int) const { return K; }
+};
+
+// A launch over several renders, described by device tables: job i owns the
+// work blocks [start[i], start[i + 1]).
+struct JobList {
+    const Job* jobs;
+    const SampleKernel* K;
+    const uint32_t* start;   // n + 1 entries
+    uint32_t n;
+    __device__ int find(uint32_t g, uint32_t& local) const {
+        if (g >= start[n]) return -1;
+        uint32_t lo = 0, hi = n;   // the last i with start[i] <= g (jobs without blocks are skipped)
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (start[mid] <= g) lo = mid;
+            else hi = mid;
+        }
+        local = g - start[lo];
+        return (int)lo;
+    }
+    __device__ const Job& job(int i) const { return jobs[i]; }
+    __device__ const SampleKernel& samples(int i) const { return K[i]; }
+};
+
+// Launch wrappers, one overload per job source.  `grid` is the number of
+// work blocks (sum over the jobs); `max_tiles` the largest tile grid of the
+// jobs (LDS of the binning kernels).  `tile` selects the resolve
+// instantiation: every job of one resolve launch has that tile size.
+hipError_t launch_cluster_cull(const OneJob& js, uint32_t grid, hipStream_t stream);
+hipError_t launch_cluster_cull(const JobList& js, uint32_t grid, hipStream_t stream);
+hipError_t launch_count(const OneJob& js, bool scene, uint32_t grid, int max_tiles, hipStream_t stream);
+hipError_t launch_count(const JobList& js, bool scene, uint32_t grid, int max_tiles, hipStream_t stream);
+hipError_t launch_scatter(const OneJob& js, uint32_t grid, int max_tiles, hipStream_t stream);
+hipError_t launch_scatter(const JobList& js, uint32_t grid, int max_tiles, hipStream_t stream);
+hipError_t launch_resolve(const OneJob& js, int tile, uint32_t grid, hipStream_t stream);
+hipError_t launch_resolve(const JobList& js, int tile, uint32_t grid, hipStream_t stream);
+hipError_t launch_shade(const OneJob& js, uint32_t grid, hipStream_t stream);
+hipError_t launch_shade(const JobList& js, uint32_t grid, hipStream_t stream);
 
 }  // namespace vtx

@@ -35,7 +35,8 @@ EXPORTS = ("vtx_render", "vtx_gbuffer", "vtx_shade", "vtx_read_stats", "vtx_set_
            "vtx_read_timings", "vtx_reset_timings", "vtx_release_scratch", "vtx_last_error", "vtx_version",
            "vtx_context_create", "vtx_context_destroy", "vtx_context_bytes_in_use", "vtx_scene_footprint_bytes",
            "vtx_frame_scratch_bytes", "vtx_scene_create", "vtx_scene_update_positions", "vtx_scene_info",
-           "vtx_scene_destroy", "vtx_render_scene")
+           "vtx_scene_destroy", "vtx_render_scene", "vtx_scene_add_frames", "vtx_scene_frames",
+           "vtx_scene_frame_bytes", "vtx_render_batch")
 
 
 class vtx_camera(ctypes.Structure):
@@ -65,6 +66,12 @@ class vtx_timings(ctypes.Structure):
 
     def as_dict(self):
         return {k: (int(getattr(self, k)) if k == "frames" else float(getattr(self, k))) for k, _ in self._fields_}
+
+
+class vtx_job(ctypes.Structure):
+    _fields_ = [("scene", ctypes.c_void_p), ("frame", ctypes.c_int32), ("camera", vtx_camera),
+                ("options", vtx_options), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("rgba", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("id", ctypes.c_void_p)]
 
 
 class VtxError(RuntimeError):
@@ -121,6 +128,14 @@ _lib.vtx_scene_destroy.restype = None
 _lib.vtx_scene_destroy.argtypes = [_P]
 _lib.vtx_render_scene.restype = ctypes.c_int
 _lib.vtx_render_scene.argtypes = [_P, _CAM, _OPT, _I32, _I32, _P, _P, _P, _P]
+_lib.vtx_scene_add_frames.restype = ctypes.c_int
+_lib.vtx_scene_add_frames.argtypes = [_P, _P, _I32, _P, ctypes.POINTER(_I32)]
+_lib.vtx_scene_frames.restype = _I32
+_lib.vtx_scene_frames.argtypes = [_P]
+_lib.vtx_scene_frame_bytes.restype = ctypes.c_size_t
+_lib.vtx_scene_frame_bytes.argtypes = [_I64, _I64]
+_lib.vtx_render_batch.restype = ctypes.c_int
+_lib.vtx_render_batch.argtypes = [_P, ctypes.POINTER(vtx_job), _I32, _P]
 _lib.vtx_last_error.restype = ctypes.c_char_p
 _lib.vtx_last_error.argtypes = []
 _lib.vtx_version.restype = ctypes.c_char_p
@@ -274,6 +289,42 @@ def vtx_render_scene(scene, cam, opts, W, H, rgba, depth, id, stream=None):
     _check(_lib.vtx_render_scene(scene, cp, op, W, H, _addr(rgba), _addr(depth), _addr(id), _stream(stream)))
 
 
+def vtx_scene_add_frames(scene, positions, n_frames, stream=None) -> int:
+    """Stores n_frames trajectory frames (n_frames x n_atoms x 3 on the device);
+    returns the index of the first."""
+    first = _I32()
+    _check(_lib.vtx_scene_add_frames(scene, _addr(positions), int(n_frames), _stream(stream), ctypes.byref(first)))
+    return first.value
+
+
+def vtx_scene_frames(scene) -> int:
+    return int(_lib.vtx_scene_frames(scene))
+
+
+def vtx_scene_frame_bytes(n_atoms, n_bonds) -> int:
+    return int(_lib.vtx_scene_frame_bytes(int(n_atoms), int(n_bonds)))
+
+
+def make_job(scene, frame, cam, opts, W, H, rgba, depth, id) -> vtx_job:
+    j = vtx_job()
+    j.scene = scene
+    j.frame = int(frame)
+    j.camera = cam if isinstance(cam, vtx_camera) else camera_struct(cam)
+    j.options = opts if isinstance(opts, vtx_options) else options_struct(opts)
+    j.width, j.height = int(W), int(H)
+    j.rgba, j.depth, j.id = _addr(rgba), _addr(depth), _addr(id)
+    return j
+
+
+def vtx_render_batch(ctx, jobs, stream=None):
+    """jobs: a sequence of vtx_job (see make_job) or a ctypes array of them."""
+    if not isinstance(jobs, ctypes.Array):
+        arr = (vtx_job * len(jobs))(*jobs)
+    else:
+        arr = jobs
+    _check(_lib.vtx_render_batch(ctx, arr, len(arr), _stream(stream)))
+
+
 def vtx_last_error() -> str:
     return (_lib.vtx_last_error() or b"").decode()
 
@@ -359,6 +410,12 @@ class ResidentScene:
         fr = frame if frame is not None else Frame(W, H)
         vtx_render_scene(self.handle, cam, opts, W, H, fr.rgba, fr.depth, fr.id, stream)
         return fr
+
+    def add_frames(self, positions, n_frames, stream=None) -> int:
+        return vtx_scene_add_frames(self.handle, positions, n_frames, stream)
+
+    def frames(self) -> int:
+        return vtx_scene_frames(self.handle)
 
     def info(self):
         return vtx_scene_info(self.handle)
