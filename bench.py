@@ -1,20 +1,31 @@
 #!/usr/bin/env python3
 """Frames/s of the full per-frame hot path on one MI355X.
 
-One step = one frame of the whole path over a resident synthetic scene:
-project/cull/count -> prefix sum -> scatter into tile lists -> per-tile ray
-cast into the (depth, id) G-buffer -> SSAO + shading into RGBA8, i.e. one
-vtx_render call through the C ABI.  Inputs are resident in device memory
-before the timed region starts.
+One step is one pass of the whole path over synthetic inputs already resident
+in device memory: cluster test and project/cull/count -> prefix sum ->
+scatter into tile lists -> per-tile ray cast into the (depth, id) G-buffer ->
+SSAO + shading into RGBA8.
 
-Prints ONE JSON line.  Besides frames/s it reports atom-fragments/s, the
-p50/p99 latency of single synchronous frames, per-kernel device times from
-HIP events recorded on the render stream inside the timed region, the
-roofline of the dominant kernel, and the CPU oracle timed on the host.
+Workloads:
+  ball_and_stick (default)  1M atoms + 1.04M bonds, 1920x1080, SSAO 16; one
+                            step = one frame (vtx_render_scene, or vtx_render
+                            with --path plain)
+  whole_cell                100M atoms, 3840x2160, SSAO 16; one step = one frame
+  trajectory                50k atoms x 64 trajectory frames x 4 orbit
+                            viewports (720p..1440p) = 256 renders; one step =
+                            one vtx_render_batch call of all 256
+  plain_small               4096 atoms, 256x256 (the small parity case)
+
+Prints ONE JSON line: frames/s (renders/s for the batch) with the contract
+fields, atom-fragments/s, p50/p99 latency, per-kernel device times from HIP
+events recorded on the render stream, the roofline of the dominant kernel,
+the other launch form of the same renders side by side, and the CPU oracle
+timed on the host.
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -29,12 +40,16 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # per sphere / cylinder fragment, per primitive projected
 OPS_PIXEL, OPS_SAMPLE, OPS_SPHERE_FRAG, OPS_CYL_FRAG, OPS_PRIM = 40, 25, 20, 50, 60
 
-
 ROOT = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILES = {"ball_and_stick_1000k_1920x1080": "hbm_traffic_ball_and_stick_1M_1080p.txt",
-                 "whole_cell_100M_3840x2160": "hbm_traffic_whole_cell_100M_4k.txt"}
+                 "whole_cell_100M_3840x2160": "hbm_traffic_whole_cell_100M_4k.txt",
+                 "trajectory_50k_64x4": "hbm_traffic_trajectory_50k_64x4.txt"}
 KERNEL_SOURCES = {"k_resolve": "resolve.hip", "k_count": "bin.hip", "k_scatter": "bin.hip",
                   "k_shade": "shade.hip", "k_cluster_cull": "scene.hip"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def sources_sha(kernel):
@@ -74,36 +89,6 @@ def measured_traffic(workload_name, kernels):
     return total
 
 
-def workload(name):
-    from paper_2501_12750_amd import scenes
-    if name == "ball_and_stick":
-        return scenes.ball_and_stick()
-    if name == "whole_cell":
-        return scenes.whole_cell()
-    if name == "plain_small":
-        return scenes.plain_small()
-    raise SystemExit(f"unknown workload {name}")
-
-
-def cpu_baseline(wl, budget_s=12.0):
-    """The oracle (FP64 C splatter + SSAO + shading) on the host cores, end to
-    end, for as many whole frames as fit the budget (at least one)."""
-    from oracle import osplat
-    osplat.build(force=False)
-    threads = osplat.default_threads()
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        osplat.render(wl.scene, wl.camera, wl.options, wl.width, wl.height, nthreads=threads)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or el / n * (n + 1) > 3 * budget_s:
-            break
-    return {"value": n / el, "unit": "frames/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} full {wl.width}x{wl.height} frame(s) of the same scene and camera, "
-                      f"FP64 footprint splatter with accept sets + SSAO + shading, {el:.1f} s"}
-
-
 def frame_tile(tile, W, H):
     """The tile edge the library uses: the requested one (16 by default),
     doubled while the frame would have more tiles than its binner holds."""
@@ -113,18 +98,138 @@ def frame_tile(tile, W, H):
     return t
 
 
+def n_tiles(tile, W, H):
+    t = frame_tile(tile, W, H)
+    return ((W + t - 1) // t) * ((H + t - 1) // t)
+
+
+# ---------------------------------------------------------------------------
+# runners: one step of each workload, in each launch form
+# ---------------------------------------------------------------------------
+class Render:
+    """One camera view of a scene frame into its own device images."""
+
+    def __init__(self, vtx, frame_index, camera, options, W, H):
+        self.frame_index, self.camera, self.options = frame_index, camera, options
+        self.W, self.H = W, H
+        self.out = vtx.Frame(W, H)
+
+
+class SingleRunner:
+    """One frame per step: vtx_render_scene on a resident scene, or vtx_render."""
+
+    def __init__(self, vtx, wl, path, stream):
+        self.vtx, self.wl, self.stream, self.path = vtx, wl, stream, path
+        self.ds = vtx.DeviceScene(wl.scene)
+        self.renders = [Render(vtx, 0, wl.camera, wl.options, wl.width, wl.height)]
+        self.ctx = self.rs = None
+        if path == "scene":
+            self.ctx = vtx.vtx_context_create(0, 0)
+            t1 = time.perf_counter()
+            self.rs = vtx.ResidentScene(self.ctx, self.ds)
+            log(f"resident scene built in {time.perf_counter() - t1:.2f} s")
+        self.launch_form = "resident scene, vtx_render_scene per frame" if path == "scene" else "vtx_render per frame"
+        self.other_form = "vtx_render per frame (caller's arrays)" if path == "scene" else None
+
+    def step(self, flags=0):
+        r = self.renders[0]
+        o = dataclasses.replace(r.options, flags=flags) if flags else r.options
+        if self.rs is not None:
+            self.vtx.vtx_render_scene(self.rs.handle, r.camera, o, r.W, r.H, r.out.rgba, r.out.depth, r.out.id,
+                                      self.stream)
+        else:
+            self.vtx.vtx_render(*self.ds.args(), r.camera, o, r.W, r.H, r.out.rgba, r.out.depth, r.out.id,
+                                self.stream)
+
+    def other_step(self):
+        r = self.renders[0]
+        self.vtx.vtx_render(*self.ds.args(), r.camera, r.options, r.W, r.H, r.out.rgba, r.out.depth, r.out.id,
+                            self.stream)
+
+    def close(self):
+        if self.rs is not None:
+            self.rs.close()
+            self.vtx.vtx_context_destroy(self.ctx)
+
+
+class BatchRunner:
+    """All renders of a trajectory workload per step: one vtx_render_batch call
+    (the other form: one call per render)."""
+
+    def __init__(self, vtx, scene0, frames, cams, opts, viewports, stream):
+        import torch
+        self.vtx, self.stream = vtx, stream
+        self.ctx = vtx.vtx_context_create(0, 0)
+        self.rs = vtx.ResidentScene(self.ctx, vtx.DeviceScene(scene0))
+        if len(frames) > 1:
+            self.rs.add_frames(torch.from_numpy(np.ascontiguousarray(frames[1:])).to("cuda"), len(frames) - 1)
+        self.renders = []
+        for f in range(len(frames)):
+            for k in range(len(cams)):
+                W, H = viewports[k]
+                self.renders.append(Render(vtx, f, cams[k], opts, W, H))
+        self.arrays = {}
+        self.launch_form = f"vtx_render_batch of {len(self.renders)} renders per step"
+        self.other_form = "one vtx_render_batch call per render (single-render launches)"
+
+    def jobs(self, flags):
+        if flags not in self.arrays:
+            v = self.vtx
+            js = [v.make_job(self.rs.handle, r.frame_index, r.camera,
+                             dataclasses.replace(r.options, flags=flags), r.W, r.H, r.out.rgba, r.out.depth, r.out.id)
+                  for r in self.renders]
+            self.arrays[flags] = ((v.vtx_job * len(js))(*js), [(v.vtx_job * 1)(j) for j in js])
+        return self.arrays[flags]
+
+    def step(self, flags=0):
+        self.vtx.vtx_render_batch(self.ctx, self.jobs(flags)[0], self.stream)
+
+    def other_step(self):
+        for one in self.jobs(0)[1]:
+            self.vtx.vtx_render_batch(self.ctx, one, self.stream)
+
+    def close(self):
+        self.rs.close()
+        self.vtx.vtx_context_destroy(self.ctx)
+
+
+def cpu_baseline(renders, scene_of, budget_s=12.0):
+    """The oracle (FP64 C splatter + SSAO + shading) on the host cores, end to
+    end, for as many whole renders of the workload, in order, as fit the
+    budget (at least one)."""
+    from oracle import osplat
+    osplat.build(force=False)
+    threads = osplat.default_threads()
+    n = 0
+    px = 0
+    t0 = time.perf_counter()
+    while True:
+        r = renders[n % len(renders)]
+        osplat.render(scene_of(r), r.camera, r.options, r.W, r.H, nthreads=threads)
+        n += 1
+        px += r.W * r.H
+        el = time.perf_counter() - t0
+        if el >= budget_s or el / n * (n + 1) > 3 * budget_s:
+            break
+    sizes = sorted({f"{r.W}x{r.H}" for r in renders[:n]})
+    return {"value": n / el, "unit": "frames/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {n} render(s) of the workload ({', '.join(sizes)}; {px / 1e6:.1f} Mpx), "
+                      f"FP64 footprint splatter with accept sets + SSAO + shading, {el:.1f} s"}
+
+
 def main():
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="ball_and_stick", choices=["ball_and_stick", "whole_cell", "plain_small"])
+    ap.add_argument("--steps", type=int, default=0, help="timed steps (0: 200 frames, or 10 batches)")
+    ap.add_argument("--warmup", type=int, default=-1, help="untimed steps first (-1: 20 frames, or 2 batches)")
+    ap.add_argument("--workload", default="ball_and_stick",
+                    choices=["ball_and_stick", "whole_cell", "trajectory", "plain_small"])
     ap.add_argument("--tile", type=int, default=0, help="tile size (0 = library default)")
     ap.add_argument("--path", choices=["scene", "plain"], default="scene",
-                    help="scene: the molecule is a resident scene (vtx_scene_create before timing, "
-                         "vtx_render_scene per frame); plain: vtx_render on the caller's arrays each frame")
-    ap.add_argument("--compare-plain", type=int, default=1,
-                    help="with --path scene, also time the plain vtx_render path (reported beside)")
+                    help="single-frame workloads: scene = resident scene (vtx_scene_create before timing, "
+                         "vtx_render_scene per frame); plain = vtx_render on the caller's arrays each frame")
+    ap.add_argument("--compare", type=int, default=1,
+                    help="also time the other launch form of the same renders (reported beside)")
     ap.add_argument("--latency-frames", type=int, default=50)
     ap.add_argument("--kernel-events", choices=["timed", "separate"], default="separate",
                     help="record the per-kernel HIP events inside the timed region, or in a separate "
@@ -139,43 +244,52 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2501_12750_amd import vtx
+    from paper_2501_12750_amd import scenes, vtx
 
-    def log(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-    t0 = time.perf_counter()
-    wl = workload(args.workload)
-    if args.tile:
-        wl.options.tile_size = args.tile
-    W, H = wl.width, wl.height
-    log(f"workload {wl.name}: {wl.scene.n_atoms} atoms, {wl.scene.n_bonds} bonds, {W}x{H}, "
-        f"generated in {time.perf_counter() - t0:.1f} s")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    ds = vtx.DeviceScene(wl.scene)
-    frame = vtx.Frame(W, H)
     stream = torch.cuda.current_stream()
-    ctx = rs = None
-    if args.path == "scene":
-        ctx = vtx.vtx_context_create(0, 0)
-        t1 = time.perf_counter()
-        rs = vtx.ResidentScene(ctx, ds)
-        log(f"resident scene built in {time.perf_counter() - t1:.2f} s")
+    t0 = time.perf_counter()
+    batch = args.workload == "trajectory"
+    if batch:
+        scene0, frames, cams, opts, viewports = scenes.trajectory()
+        if args.tile:
+            opts = dataclasses.replace(opts, tile_size=args.tile)
+        name = f"trajectory_{scene0.n_atoms // 1000}k_{len(frames)}x{len(cams)}"
+        runner = BatchRunner(vtx, scene0, frames, cams, opts, viewports, stream)
+        N, M = scene0.n_atoms, scene0.n_bonds
 
-    def render(opts):
-        if rs is not None:
-            vtx.vtx_render_scene(rs.handle, wl.camera, opts, W, H, frame.rgba, frame.depth, frame.id, stream)
-        else:
-            vtx.vtx_render(*ds.args(), wl.camera, opts, W, H, frame.rgba, frame.depth, frame.id, stream)
+        def scene_of(r):
+            return scenes.Scene(frames[r.frame_index], scene0.radii, scene0.colors, scene0.bonds)
+        config = {"workload": name, "atoms": N, "bonds": M, "trajectory_frames": len(frames),
+                  "viewports": [list(v) for v in viewports], "renders_per_step": len(runner.renders),
+                  "ssao_samples": int(opts.ssao_samples)}
+        steps = args.steps or 10
+        warmup = args.warmup if args.warmup >= 0 else 2
+    else:
+        wl = {"ball_and_stick": scenes.ball_and_stick, "whole_cell": scenes.whole_cell,
+              "plain_small": scenes.plain_small}[args.workload]()
+        if args.tile:
+            wl.options = dataclasses.replace(wl.options, tile_size=args.tile)
+        name = wl.name
+        runner = SingleRunner(vtx, wl, args.path, stream)
+        N, M = wl.scene.n_atoms, wl.scene.n_bonds
 
-    # exact fragment counts of this scene and camera (early-outs off), untimed
-    import dataclasses
-    opts_stats = dataclasses.replace(wl.options, flags=vtx.VTX_FLAG_STATS)
-    render(opts_stats)
+        def scene_of(r):
+            return wl.scene
+        config = {"workload": name, "atoms": N, "bonds": M, "width": wl.width, "height": wl.height,
+                  "ssao_samples": int(wl.options.ssao_samples),
+                  "tile_size": frame_tile(wl.options.tile_size, wl.width, wl.height)}
+        steps = args.steps or 200
+        warmup = args.warmup if args.warmup >= 0 else 20
+    config["launch"] = runner.launch_form
+    R = len(runner.renders)
+    log(f"workload {name}: {N} atoms, {M} bonds, {R} render(s) per step, set up in {time.perf_counter() - t0:.1f} s")
+
+    # exact fragment counts of these renders (early-outs off), untimed
+    runner.step(vtx.VTX_FLAG_STATS)
     st = vtx.vtx_read_stats(stream)
-    ids = frame.id.cpu().numpy().view(np.uint32)
-    hit_px = int(np.count_nonzero(ids != 0xFFFFFFFF))
+    hit_px = int(sum(int((r.out.id != -1).sum().item()) for r in runner.renders))
     log(f"stats {st}, hit pixels {hit_px}")
 
     if args.calibrate_copy_mb:
@@ -187,64 +301,65 @@ def main():
         log(f"calibration copy of {args.calibrate_copy_mb} MiB done")
         del src, dst
 
-    opts_t = dataclasses.replace(wl.options, flags=vtx.VTX_FLAG_TIMING)
-    for _ in range(args.warmup):
-        render(wl.options)
+    for _ in range(warmup):
+        runner.step()
     torch.cuda.synchronize()
     vtx.vtx_reset_timings(stream)
-    log(f"warmup {args.warmup} done; timing {args.steps} steps")
+    log(f"warmup {warmup} done; timing {steps} steps")
 
-    opts_main = opts_t if args.kernel_events == "timed" else wl.options
+    main_flags = vtx.VTX_FLAG_TIMING if args.kernel_events == "timed" else 0
     torch.cuda.synchronize()
     ts = time.perf_counter()
-    for _ in range(args.steps):
-        render(opts_main)
+    for _ in range(steps):
+        runner.step(main_flags)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - ts
     if args.kernel_events == "separate":
-        for _ in range(args.steps):
-            render(opts_t)
+        for _ in range(steps):
+            runner.step(vtx.VTX_FLAG_TIMING)
     timings = vtx.vtx_read_timings(stream)
     st_after = vtx.vtx_read_stats(stream)
-    ms_per_step = elapsed / args.steps * 1e3
-    fps = args.steps / elapsed
-    log(f"timed: {ms_per_step:.3f} ms/frame, {fps:.1f} frames/s; kernels {timings}")
+    ms_per_step = elapsed / steps * 1e3
+    fps = steps * R / elapsed
+    log(f"timed: {ms_per_step:.3f} ms/step, {fps:.1f} frames/s; kernels {timings}")
 
-    # latency of single frames submitted and awaited one at a time
+    # latency of single steps submitted and awaited one at a time
     lat = []
-    for _ in range(args.latency_frames):
+    for _ in range(args.latency_frames if not batch else min(args.latency_frames, 20)):
         a = time.perf_counter()
-        render(wl.options)
+        runner.step()
         stream.synchronize()
         lat.append((time.perf_counter() - a) * 1e3)
     lat = np.array(lat)
 
-    plain = None
-    if rs is not None and args.compare_plain:
-        for _ in range(args.warmup):
-            vtx.vtx_render(*ds.args(), wl.camera, wl.options, W, H, frame.rgba, frame.depth, frame.id, stream)
+    other = None
+    if args.compare and runner.other_form:
+        for _ in range(max(1, warmup)):
+            runner.other_step()
         torch.cuda.synchronize()
+        o_steps = max(1, steps // 2) if batch else steps
         a = time.perf_counter()
-        for _ in range(args.steps):
-            vtx.vtx_render(*ds.args(), wl.camera, wl.options, W, H, frame.rgba, frame.depth, frame.id, stream)
+        for _ in range(o_steps):
+            runner.other_step()
         torch.cuda.synchronize()
         pe = time.perf_counter() - a
-        plain = {"frames_per_s": round(args.steps / pe, 3), "ms_per_frame": round(pe / args.steps * 1e3, 4)}
-        log(f"plain vtx_render: {plain}")
+        other = {"launch": runner.other_form, "frames_per_s": round(o_steps * R / pe, 3),
+                 "ms_per_step": round(pe / o_steps * 1e3, 4)}
+        log(f"other launch form: {other}")
 
-    # roofline of each kernel; the dominant one goes in the JSON's roofline
-    N, M = wl.scene.n_atoms, wl.scene.n_bonds
-    K = int(wl.options.ssao_samples)
+    # roofline of each kernel (per step = sums over the step's renders); the
+    # dominant one goes in the JSON's roofline
+    K = int(runner.renders[0].options.ssao_samples)
     f_total = st["fragments_hit"]
     f_cyl = st.get("fragments_hit_bond", 0)
     f_sph = f_total - f_cyl
+    tiles = sum(n_tiles(r.options.tile_size, r.W, r.H) for r in runner.renders)
     per_kernel = {
-        "project": ("hbm", 16.0 * N + 8.0 * M, timings["ms_project"]),
+        "project": ("hbm", (16.0 * N + 8.0 * M) * R, timings["ms_project"]),
         "resolve": ("alu", float(OPS_SPHERE_FRAG * f_sph + OPS_CYL_FRAG * f_cyl), timings["ms_resolve"]),
         "shade": ("alu", float((OPS_PIXEL + OPS_SAMPLE * K) * hit_px), timings["ms_shade"]),
         "scatter": ("hbm", 12.0 * st["visible"] + 4.0 * st["pairs"], timings["ms_scatter"]),
-        "scan": ("hbm", 12.0 * ((W + frame_tile(wl.options.tile_size, W, H) - 1) // frame_tile(wl.options.tile_size, W, H))
-                 * ((H + frame_tile(wl.options.tile_size, W, H) - 1) // frame_tile(wl.options.tile_size, W, H)), timings["ms_scan"]),
+        "scan": ("hbm", 12.0 * tiles, timings["ms_scan"]),
     }
     kern = {}
     for k, (bound, work, ms) in per_kernel.items():
@@ -259,34 +374,33 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["ms"])
     roof = dict(kern[dom])
     roof.pop("ms")
-    tile = frame_tile(wl.options.tile_size, W, H)
-    launched = {"project": (["k_cluster_cull", "k_count<SceneSource>"] if rs is not None else ["k_count<PlainSource>"]),
-                "scatter": ["k_scatter"], "resolve": [f"k_resolve<{tile}>"], "shade": ["k_shade"], "scan": []}
-    traffic = measured_traffic(wl.name, launched[dom]) if launched[dom] else None
-    roof = {"kernel": dom, "launches": launched[dom], **roof,
-            "traffic": None if traffic is None else round(traffic)}
+    scene_path = batch or runner.path == "scene"
+    res_tiles = sorted({frame_tile(r.options.tile_size, r.W, r.H) for r in runner.renders})
+    launched = {"project": (["k_cluster_cull", "k_count<SceneSource>"] if scene_path else ["k_count<PlainSource>"]),
+                "scatter": ["k_scatter"], "resolve": [f"k_resolve<{t}>" for t in res_tiles], "shade": ["k_shade"],
+                "scan": []}
+    traffic = measured_traffic(name, launched[dom]) if (launched[dom] and scene_path) else None
+    roof = {"kernel": dom, "launches": launched[dom], **roof, "traffic": None if traffic is None else round(traffic)}
 
     out = {
         "metric": "frames/s",
         "value": round(fps, 3),
         "unit": "frames/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "atoms": N, "bonds": M, "width": W, "height": H,
-                   "ssao_samples": K, "tile_size": frame_tile(wl.options.tile_size, W, H),
-                   "path": "resident scene (vtx_render_scene)" if rs is not None else "vtx_render"},
-        "plain_vtx_render": plain,
-        "atom_fragments_per_s": round(f_total * fps, 1),
-        "atom_fragments": f_total,
+        "config": config,
+        "other_launch_form": other,
+        "atom_fragments_per_s": round(f_total * steps / elapsed, 1),
+        "atom_fragments_per_step": f_total,
         "latency_ms": ({"p50": round(float(np.percentile(lat, 50)), 4),
-                        "p99": round(float(np.percentile(lat, 99)), 4), "frames": int(lat.size)}
+                        "p99": round(float(np.percentile(lat, 99)), 4), "steps": int(lat.size)}
                        if lat.size else None),
         "kernels": kern,
         "roofline": roof,
@@ -294,11 +408,9 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(wl)
+        out["cpu_baseline"] = cpu_baseline(runner.renders, scene_of)
     print(json.dumps(out), flush=True)
-    if rs is not None:
-        rs.close()
-        vtx.vtx_context_destroy(ctx)
+    runner.close()
 
 
 if __name__ == "__main__":

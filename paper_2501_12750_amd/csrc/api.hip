@@ -2,6 +2,7 @@
 // constants, per-stream scratch (tile bins) and the launch sequence
 // cull -> count -> scatter -> resolve -> shade, for one render or a batch.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -64,8 +65,20 @@ struct Bins {
     uint64_t want_capacity = 0;
     uint64_t pending_capacity = 0;
     bool dirty = true;              // tile counts / counters must be zeroed before the next frame
-    uint64_t sized_nprim = ~0ull;   // scene and image size the bins were last sized for
-    int sized_w = -1, sized_h = -1;
+    // (primitives, width, height) of the renders the lists were sized for,
+    // most recent last; the lists only grow, so a render of a known size
+    // needs no new sizing
+    std::vector<std::array<int64_t, 3>> sized;
+    bool was_sized(uint64_t nprim, int w, int h) const {
+        for (const auto& k : sized)
+            if (k[0] == (int64_t)nprim && k[1] == w && k[2] == h) return true;
+        return false;
+    }
+    void mark_sized(uint64_t nprim, int w, int h) {
+        if (was_sized(nprim, w, h)) return;
+        if (sized.size() >= 16) sized.erase(sized.begin());
+        sized.push_back({(int64_t)nprim, (int64_t)w, (int64_t)h});
+    }
 };
 
 // Scratch of one (device, stream).
@@ -373,6 +386,10 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
     F->ty = th;
     F->hx = (double)cam->ortho_half_height * aspect;
     F->hy = (double)cam->ortho_half_height;
+    F->itx = 1.0 / F->tx;
+    F->ity = 1.0 / F->ty;
+    F->ihx = 1.0 / F->hx;
+    F->ihy = 1.0 / F->hy;
     F->txf = (float)F->tx;
     F->tyf = (float)F->ty;
     F->sxf = (float)std::sqrt(1.0 + F->tx * F->tx) * (1.0f + 1e-6f);
@@ -393,6 +410,7 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
     while ((int64_t)((W + ts - 1) / ts) * ((H + ts - 1) / ts) > vtx::kMaxLdsTiles) ts *= 2;
     if (ts > 64) return fail(VTX_EINVAL, "image %dx%d needs more than %d tiles of 64 pixels", W, H, vtx::kMaxLdsTiles);
     F->tile = ts;
+    F->tile_shift = ts == 8 ? 3 : ts == 16 ? 4 : ts == 32 ? 5 : 6;
     F->tiles_x = (W + F->tile - 1) / F->tile;
     F->tiles_y = (H + F->tile - 1) / F->tile;
     F->n_atoms = (uint32_t)n;
@@ -718,8 +736,7 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
         std::vector<size_t> need;
         for (size_t i = 0; i < n; ++i) {
             const Bins* b = ws->slots[i];
-            if (!ws->fixed_capacity && (nprims[i] != b->sized_nprim || d[i].F.W != b->sized_w || d[i].F.H != b->sized_h))
-                need.push_back(i);
+            if (!ws->fixed_capacity && !b->was_sized(nprims[i], d[i].F.W, d[i].F.H)) need.push_back(i);
         }
         if (!need.empty()) {
             std::vector<unsigned long long> counted(n, 0);
@@ -736,9 +753,7 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
                     if ((rc = grow(&b->bb.list, b->list_alloc, (size_t)b->want_capacity, stream, "tile lists"))) return rc;
                 }
                 b->bb.capacity = b->want_capacity;
-                b->sized_nprim = nprims[i];
-                b->sized_w = d[i].F.W;
-                b->sized_h = d[i].F.H;
+                b->mark_sized(nprims[i], d[i].F.W, d[i].F.H);
                 jobs[i].bb.list = b->bb.list;
                 jobs[i].bb.capacity = b->bb.capacity;
             }
@@ -1128,7 +1143,7 @@ int vtx_set_bin_capacity(void* stream, uint64_t entries) {
     ws->fixed_entries = entries;
     for (Bins* b : ws->slots) {
         b->want_capacity = entries;   // 0: re-derived from the next frame's size
-        b->sized_nprim = ~0ull;
+        b->sized.clear();
     }
     return VTX_OK;
 }

@@ -55,47 +55,73 @@ __device__ inline bool bond_record(const Frame& F, const double* A, const double
     return bond_rect(F, A, B, rho, x0, y0, x1, y1);
 }
 
-// Footprint and view-space record of primitive p; false if it cannot show.
-__device__ inline bool primitive_record(const Frame& F, uint32_t p, const float* __restrict__ pos,
-                                        const float* __restrict__ rad, const uint32_t* __restrict__ bonds,
-                                        int& x0, int& y0, int& x1, int& y1, PrimRec& rec, bool& bad) {
-    bad = false;
-    if (p < F.n_atoms) {
+// Raw inputs of one item of a binning workgroup, loaded one loop iteration
+// ahead of its processing so the loads overlap the previous item's math.
+struct Item {
+    float4 a;          // atom: centre and radius | bond: end A (w unused)
+    float4 b;          // bond: end B
+    uint32_t id;       // primitive id
+    uint32_t kind;     // kNone, kAtom, kBond, kBadBond
+};
+constexpr uint32_t kNone = 0, kAtom = 1, kBond = 2, kBadBond = 3;
+
+// Footprint and view-space record of a fetched item; false if it cannot show.
+__device__ inline bool item_record(const Frame& F, const Item& it, int& x0, int& y0, int& x1, int& y1,
+                                   PrimRec& rec) {
+    if (it.kind == kAtom) {
         double vx, vy, vz;
-        to_view(F, pos[3 * (size_t)p], pos[3 * (size_t)p + 1], pos[3 * (size_t)p + 2], vx, vy, vz);
-        return sphere_record(F, vx, vy, vz, (double)rad[p], p, x0, y0, x1, y1, rec);
+        to_view(F, it.a.x, it.a.y, it.a.z, vx, vy, vz);
+        return sphere_record(F, vx, vy, vz, (double)it.a.w, it.id, x0, y0, x1, y1, rec);
     }
-    const size_t b = p - F.n_atoms;
-    const uint32_t ia = bonds[2 * b], ib = bonds[2 * b + 1];
-    if (ia >= F.n_atoms || ib >= F.n_atoms) {
-        bad = true;
-        return false;
-    }
-    if (ia == ib) return false;
-    const float ax = pos[3 * (size_t)ia], ay = pos[3 * (size_t)ia + 1], az = pos[3 * (size_t)ia + 2];
-    const float bx = pos[3 * (size_t)ib], by = pos[3 * (size_t)ib + 1], bz = pos[3 * (size_t)ib + 2];
-    if (ax == bx && ay == by && az == bz) return false;
+    if (it.kind != kBond) return false;
+    if (it.a.x == it.b.x && it.a.y == it.b.y && it.a.z == it.b.z) return false;
     double A[3], B[3];
-    to_view(F, ax, ay, az, A[0], A[1], A[2]);
-    to_view(F, bx, by, bz, B[0], B[1], B[2]);
-    return bond_record(F, A, B, p, x0, y0, x1, y1, rec);
+    to_view(F, it.a.x, it.a.y, it.a.z, A[0], A[1], A[2]);
+    to_view(F, it.b.x, it.b.y, it.b.z, B[0], B[1], B[2]);
+    return bond_record(F, A, B, it.id, x0, y0, x1, y1, rec);
 }
 
 // Primitive sources of the count kernel.  Workgroup b owns items
-// [0, items(b)) and the visible-list region [b * chunk, (b + 1) * chunk).
+// [0, items()) (after begin(b)) and the visible-list region
+// [b * chunk, (b + 1) * chunk).
 struct PlainSource {     // the caller's arrays, primitives in their given order
     const float* pos;
     const float* rad;
     const uint32_t* bonds;
     uint64_t total;
     uint32_t chunk;
-    __device__ uint64_t items(uint32_t b) const {
-        const uint64_t s = (uint64_t)b * chunk;
-        return s < total ? min((uint64_t)chunk, total - s) : 0;
+    uint32_t n_atoms;
+    uint64_t first, count;
+    __device__ void begin(uint32_t b) {
+        first = (uint64_t)b * chunk;
+        count = first < total ? min((uint64_t)chunk, total - first) : 0;
     }
-    __device__ bool record(const Frame& F, uint32_t b, uint64_t k, int& x0, int& y0, int& x1, int& y1, PrimRec& rec,
-                           bool& bad) const {
-        return primitive_record(F, (uint32_t)((uint64_t)b * chunk + k), pos, rad, bonds, x0, y0, x1, y1, rec, bad);
+    __device__ uint64_t items() const { return count; }
+    __device__ Item fetch(uint64_t k) const {
+        Item it;
+        const uint64_t p = first + k;
+        it.id = (uint32_t)p;
+        it.b = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (p < n_atoms) {
+            it.a = make_float4(pos[3 * p], pos[3 * p + 1], pos[3 * p + 2], rad[p]);
+            it.kind = kAtom;
+            return it;
+        }
+        const size_t bi = p - n_atoms;
+        const uint32_t ia = bonds[2 * bi], ib = bonds[2 * bi + 1];
+        it.a = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (ia >= n_atoms || ib >= n_atoms) {
+            it.kind = kBadBond;
+            return it;
+        }
+        if (ia == ib) {
+            it.kind = kNone;
+            return it;
+        }
+        it.a = make_float4(pos[3 * (size_t)ia], pos[3 * (size_t)ia + 1], pos[3 * (size_t)ia + 2], 0.f);
+        it.b = make_float4(pos[3 * (size_t)ib], pos[3 * (size_t)ib + 1], pos[3 * (size_t)ib + 2], 0.f);
+        it.kind = kBond;
+        return it;
     }
 };
 
@@ -103,42 +129,39 @@ struct SceneSource {     // a resident scene: the clusters that passed the frust
     SceneDev S;
     const Counters* ctr;
     uint32_t groups;
-    __device__ void range(uint32_t b, uint32_t& c0, uint32_t& c1) const {
+    uint32_t c0, c1;
+    __device__ void begin(uint32_t b) {
         const uint32_t nvc = ctr->vis_clusters;
         const uint32_t cpw = (nvc + groups - 1) / groups;
         c0 = min(nvc, b * cpw);
         c1 = min(nvc, c0 + cpw);
     }
-    __device__ uint64_t items(uint32_t b) const {
-        uint32_t c0, c1;
-        range(b, c0, c1);
-        return (uint64_t)(c1 - c0) * kCluster;
-    }
-    __device__ bool record(const Frame& F, uint32_t b, uint64_t k, int& x0, int& y0, int& x1, int& y1, PrimRec& rec,
-                           bool& bad) const {
-        bad = false;
-        uint32_t c0, c1;
-        range(b, c0, c1);
+    __device__ uint64_t items() const { return (uint64_t)(c1 - c0) * kCluster; }
+    __device__ Item fetch(uint64_t k) const {
+        Item it;
+        it.kind = kNone;
+        it.id = 0;
+        it.a = make_float4(0.f, 0.f, 0.f, 0.f);
+        it.b = it.a;
         const uint32_t c = S.vis_clusters[c0 + (uint32_t)(k / kCluster)];
         const uint32_t slot = (uint32_t)(k % kCluster);
         if (c < S.atom_clusters) {
             const uint32_t i = c * kCluster + slot;
-            if (i >= S.n_atoms) return false;
-            const float4 a = S.xyzr[i];
-            double vx, vy, vz;
-            to_view(F, a.x, a.y, a.z, vx, vy, vz);
-            return sphere_record(F, vx, vy, vz, (double)a.w, S.atom_id[i], x0, y0, x1, y1, rec);
+            if (i >= S.n_atoms) return it;
+            it.a = S.xyzr[i];
+            it.id = S.atom_id[i];
+            it.kind = kAtom;
+            return it;
         }
         const uint32_t j = (c - S.atom_clusters) * kCluster + slot;
-        if (j >= S.n_bonds) return false;
+        if (j >= S.n_bonds) return it;
         const uint4 br = S.bond_rec[j];
-        if (br.x == br.y) return false;
-        const float4 a = S.xyzr[br.x], bb = S.xyzr[br.y];
-        if (a.x == bb.x && a.y == bb.y && a.z == bb.z) return false;
-        double A[3], B[3];
-        to_view(F, a.x, a.y, a.z, A[0], A[1], A[2]);
-        to_view(F, bb.x, bb.y, bb.z, B[0], B[1], B[2]);
-        return bond_record(F, A, B, F.n_atoms + br.z, x0, y0, x1, y1, rec);
+        if (br.x == br.y) return it;
+        it.a = S.xyzr[br.x];
+        it.b = S.xyzr[br.y];
+        it.id = S.n_atoms + br.z;
+        it.kind = kBond;
+        return it;
     }
 };
 
@@ -147,13 +170,41 @@ struct SourceOf;
 template <>
 struct SourceOf<false> {
     __device__ static PlainSource make(const Job& J) {
-        return PlainSource{J.pos, J.rad, J.bonds, (uint64_t)J.F.n_atoms + J.F.n_bonds, J.bb.chunk};
+        PlainSource s;
+        s.pos = J.pos;
+        s.rad = J.rad;
+        s.bonds = J.bonds;
+        s.total = (uint64_t)J.F.n_atoms + J.F.n_bonds;
+        s.chunk = J.bb.chunk;
+        s.n_atoms = J.F.n_atoms;
+        return s;
     }
 };
 template <>
 struct SourceOf<true> {
-    __device__ static SceneSource make(const Job& J) { return SceneSource{J.S, J.bb.ctr, J.bb.groups}; }
+    __device__ static SceneSource make(const Job& J) {
+        SceneSource s;
+        s.S = J.S;
+        s.ctr = J.bb.ctr;
+        s.groups = J.bb.groups;
+        return s;
+    }
 };
+
+// Adds one to the LDS counter of each lane's tile t (t < 0: nothing).  Lanes
+// of a wave that share a tile are merged into one atomic (Morton-ordered
+// primitives often do), for at most four distinct tiles; the rest add alone.
+__device__ inline void wave_count(uint32_t* hist, int t) {
+    unsigned long long pend = __ballot(t >= 0);
+    for (int it = 0; it < 4 && pend; ++it) {
+        const int leader = __ffsll((long long)pend) - 1;
+        const int tl = __shfl(t, leader);
+        const unsigned long long grp = __ballot(t == tl) & pend;
+        if ((int)__lane_id() == leader) atomicAdd(&hist[tl], (uint32_t)__popcll(grp));
+        pend &= ~grp;
+    }
+    if ((pend >> __lane_id()) & 1ull) atomicAdd(&hist[t], 1u);
+}
 
 // Count.  Work block b of a job is that job's binning workgroup b.
 template <class JS, bool kScene>
@@ -166,7 +217,7 @@ __global__ void __launch_bounds__(kBinThreads) k_count(JS js) {
     if (ji < 0) return;
     const Job& J = js.job(ji);
     const Frame F = J.F;
-    const auto src = SourceOf<kScene>::make(J);
+    const auto src0 = SourceOf<kScene>::make(J);
     const uint32_t chunk = J.bb.chunk;
     PrimRec* __restrict__ const vis_rec = J.bb.vis_rec;
     uint2* __restrict__ const vis_rect = J.bb.vis_rect;
@@ -190,34 +241,43 @@ __global__ void __launch_bounds__(kBinThreads) k_count(JS js) {
     uint32_t mx0 = 0xFFFF, my0 = 0xFFFF, mx1 = 0, my1 = 0, my_pairs = 0;
 
     const uint64_t start = (uint64_t)blk * chunk;
-    const uint64_t nitems = src.items(blk);
-    const int ts = F.tile;
+    auto src = src0;
+    src.begin(blk);
+    const uint64_t nitems = src.items();
+    const int tsh = F.tile_shift;
     uint32_t bad_count = 0;
+    Item cur{make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f), 0u, kNone};
+    if ((uint64_t)tid < nitems) cur = src.fetch(tid);
     for (uint64_t base = 0; base < nitems; base += kBinThreads) {
-        const uint64_t k = base + tid;
+        // the next iteration's inputs are loaded while this one is processed
+        Item nxt{make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f), 0u, kNone};
+        if (base + kBinThreads + tid < nitems) nxt = src.fetch(base + kBinThreads + tid);
         int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
-        bool bad = false;
         PrimRec rec;
-        const bool vis = k < nitems && src.record(F, blk, k, x0, y0, x1, y1, rec, bad);
-        bad_count += bad ? 1u : 0u;
+        const bool vis = item_record(F, cur, x0, y0, x1, y1, rec);
+        bad_count += cur.kind == kBadBond ? 1u : 0u;
         const unsigned long long vmask = __ballot(vis);
         uint32_t slot_base = 0;
         const int leader = __ffsll((long long)(vmask | 1ull)) - 1;
         if (vmask && (int)__lane_id() == leader) slot_base = atomicAdd(&local_n, (uint32_t)__popcll(vmask));
         slot_base = __shfl(slot_base, leader);
+        const int tx0 = x0 >> tsh, tx1 = x1 >> tsh, ty0 = y0 >> tsh, ty1 = y1 >> tsh;
+        const bool single = vis && tx0 == tx1 && ty0 == ty1;
+        wave_count(hist, single ? ty0 * F.tiles_x + tx0 : -1);
         if (vis) {
             const uint64_t slot = start + slot_base + (uint32_t)__popcll(vmask & __lanemask_lt());
-            const int tx0 = x0 / ts, tx1 = x1 / ts, ty0 = y0 / ts, ty1 = y1 / ts;
             vis_rec[slot] = rec;
             vis_rect[slot] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
-            for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&hist[ty * F.tiles_x + tx], 1u);
+            if (!single)
+                for (int ty = ty0; ty <= ty1; ++ty)
+                    for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&hist[ty * F.tiles_x + tx], 1u);
             mx0 = min(mx0, (uint32_t)tx0);
             my0 = min(my0, (uint32_t)ty0);
             mx1 = max(mx1, (uint32_t)tx1);
             my1 = max(my1, (uint32_t)ty1);
             my_pairs += (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
         }
+        cur = nxt;
     }
     if (bad_count) atomicAdd(&ctr->bad_bonds, bad_count);
     if (my_pairs) {
@@ -340,25 +400,77 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js) {
     __syncthreads();
     const uint32_t n = vis_cnt[blk];
     const uint64_t start = (uint64_t)blk * chunk;
-    const int ts = F.tile;
-    for (uint32_t k = tid; k < n; k += kBinThreads) {
-        const float4 g0 = vis_rec[start + k].g0;
-        const uint4 g1 = vis_rec[start + k].g1;
-        const uint2 r = vis_rect[start + k];
+    const int ts = F.tile, tsh = F.tile_shift;
+    // the footprint clipped to tile (tx, ty), in tile-local pixels
+    auto local_fp = [&](int x0, int y0, int x1, int y1, int tx, int ty) -> uint32_t {
+        const int lx0 = max(x0 - tx * ts, 0), ly0 = max(y0 - ty * ts, 0);
+        const int lx1 = min(x1 - tx * ts, ts - 1), ly1 = min(y1 - ty * ts, ts - 1);
+        return (uint32_t)lx0 | ((uint32_t)ly0 << 8) | ((uint32_t)(lx1 - lx0 + 1) << 16) |
+               ((uint32_t)(ly1 - ly0 + 1) << 24);
+    };
+    const uint32_t rounds = (n + kBinThreads - 1) / kBinThreads;   // uniform trip count (wave ops inside)
+    float4 g0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint4 g1 = make_uint4(0u, 0u, 0u, 0u);
+    uint2 r = make_uint2(0u, 0u);
+    if ((uint32_t)tid < n) {
+        g0 = vis_rec[start + tid].g0;
+        g1 = vis_rec[start + tid].g1;
+        r = vis_rect[start + tid];
+    }
+    for (uint32_t it = 0; it < rounds; ++it) {
+        const uint32_t k = it * kBinThreads + tid;
+        const bool have = k < n;
+        // the next record is loaded while this one is placed
+        float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        uint4 n1 = make_uint4(0u, 0u, 0u, 0u);
+        uint2 nr = make_uint2(0u, 0u);
+        if (k + kBinThreads < n) {
+            n0 = vis_rec[start + k + kBinThreads].g0;
+            n1 = vis_rec[start + k + kBinThreads].g1;
+            nr = vis_rect[start + k + kBinThreads];
+        }
         const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16;
-        for (int ty = y0 / ts; ty <= y1 / ts; ++ty)
-            for (int tx = x0 / ts; tx <= x1 / ts; ++tx) {
-                const int t = ty * F.tiles_x + tx;
-                if (cur[t] == kNoRun) continue;
-                // the footprint clipped to this tile, in tile-local pixels
-                const int lx0 = max(x0 - tx * ts, 0), ly0 = max(y0 - ty * ts, 0);
-                const int lx1 = min(x1 - tx * ts, ts - 1), ly1 = min(y1 - ty * ts, ts - 1);
-                const uint32_t fp = (uint32_t)lx0 | ((uint32_t)ly0 << 8) | ((uint32_t)(lx1 - lx0 + 1) << 16) |
-                                    ((uint32_t)(ly1 - ly0 + 1) << 24);
-                PrimRec* dst = &list[atomicAdd(&cur[t], 1u)];
-                dst->g0 = g0;
-                dst->g1 = make_uint4(g1.x, g1.y, g1.z, fp);
+        const int tx0 = x0 >> tsh, tx1 = x1 >> tsh, ty0 = y0 >> tsh, ty1 = y1 >> tsh;
+        const bool single = have && tx0 == tx1 && ty0 == ty1;
+        // single-tile records: lanes sharing a tile take one run of its list
+        // with one LDS atomic (at most four distinct tiles per wave this way)
+        const int t1 = single ? ty0 * F.tiles_x + tx0 : -1;
+        unsigned long long pend = __ballot(single);
+        uint32_t my_slot = kNoRun;
+        for (int g = 0; g < 4 && pend; ++g) {
+            const int leader = __ffsll((long long)pend) - 1;
+            const int tl = __shfl(t1, leader);
+            const unsigned long long grp = __ballot(t1 == tl) & pend;
+            uint32_t base = kNoRun;
+            if ((int)__lane_id() == leader) {
+                base = cur[tl];
+                if (base != kNoRun) base = atomicAdd(&cur[tl], (uint32_t)__popcll(grp));
             }
+            base = __shfl(base, leader);
+            if ((grp >> __lane_id()) & 1ull)
+                my_slot = base == kNoRun ? kNoRun : base + (uint32_t)__popcll(grp & __lanemask_lt());
+            pend &= ~grp;
+        }
+        if (single) {
+            if ((pend >> __lane_id()) & 1ull) my_slot = cur[t1] == kNoRun ? kNoRun : atomicAdd(&cur[t1], 1u);
+            if (my_slot != kNoRun) {
+                PrimRec* dst = &list[my_slot];
+                dst->g0 = g0;
+                dst->g1 = make_uint4(g1.x, g1.y, g1.z, local_fp(x0, y0, x1, y1, tx0, ty0));
+            }
+        } else if (have) {
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx) {
+                    const int t = ty * F.tiles_x + tx;
+                    if (cur[t] == kNoRun) continue;
+                    PrimRec* dst = &list[atomicAdd(&cur[t], 1u)];
+                    dst->g0 = g0;
+                    dst->g1 = make_uint4(g1.x, g1.y, g1.z, local_fp(x0, y0, x1, y1, tx, ty));
+                }
+        }
+        g0 = n0;
+        g1 = n1;
+        r = nr;
     }
 }
 

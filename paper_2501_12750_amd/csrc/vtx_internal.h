@@ -24,6 +24,7 @@ struct Frame {
     double eye[3], s[3], u[3], f[3];   // world -> view basis (x right, y up, z forward)
     double tx, ty;                     // perspective: tan(fovy/2) * W/H, tan(fovy/2)
     double hx, hy;                     // orthographic: h * W/H, h
+    double itx, ity, ihx, ihy;         // their inverses
     float txf, tyf, hxf, hyf;
     float sxf, syf;                    // perspective: sqrt(1 + tx^2), sqrt(1 + ty^2)
     float inv_w2, inv_h2;              // 2/W, 2/H
@@ -32,6 +33,7 @@ struct Frame {
     int32_t proj;                      // 0 perspective, 1 orthographic
     int32_t W, H;
     int32_t tile, tiles_x, tiles_y;
+    int32_t tile_shift;                // tile = 1 << tile_shift
     uint32_t n_atoms, n_bonds;
     uint32_t flags;
 };
@@ -85,23 +87,16 @@ __device__ inline void to_view(const Frame& F, float px, float py, float pz, dou
 }
 
 // Interval of NDC coordinates along one image axis covered by a sphere of
-// view-space centre (c, vz) (c = x or y) and radius r.  Perspective: the two
-// planes through the eye tangent to the sphere have slopes
-// (c vz -+ r sqrt(c^2 + vz^2 - r^2)) / (vz^2 - r^2) when the sphere lies in
-// front of the eye plane; otherwise the footprint is unbounded.
-__device__ inline bool sphere_ndc_interval(const Frame& F, double c, double vz, double r, double tscale,
-                                           double hscale, double& lo, double& hi) {
-    if (F.proj == 0) {
-        if (!(vz > r)) return false;   // unbounded: caller uses the whole axis
-        const double den = vz * vz - r * r;
-        const double sq = r * sqrt(c * c + den);
-        lo = (c * vz - sq) / den / tscale;
-        hi = (c * vz + sq) / den / tscale;
-    } else {
-        lo = (c - r) / hscale;
-        hi = (c + r) / hscale;
-    }
-    return true;
+// view-space centre (c, vz) (c = x or y) and radius r in front of the eye
+// plane (perspective, vz > r): the two planes through the eye tangent to the
+// sphere have slopes (c vz -+ r sqrt(c^2 + vz^2 - r^2)) / (vz^2 - r^2).
+// `den` = vz^2 - r^2 and `scale` = 1 / (den tan) for the axis' tangent `tan`
+// (one division per sphere serves both axes).
+__device__ inline void persp_interval(double c, double vz, double r, double den, double scale, double& lo,
+                                      double& hi) {
+    const double sq = r * sqrt(c * c + den);
+    lo = (c * vz - sq) * scale;
+    hi = (c * vz + sq) * scale;
 }
 
 // Inclusive pixel index range of the pixel centres whose NDC lies in [lo, hi]
@@ -143,9 +138,14 @@ __device__ inline bool sphere_rect(const Frame& F, double vx, double vy, double 
     if (!(r > 0.0)) return false;
     if (vz + r < F.znear || vz - r > F.zfar) return false;
     double lo, hi;
-    if (sphere_ndc_interval(F, vx, vz, r, F.tx, F.hx, lo, hi)) {
+    if (F.proj != 0) {
+        ndc_to_pixels((vx - r) * F.ihx, (vx + r) * F.ihx, F.W, false, x0, x1);
+        ndc_to_pixels((vy - r) * F.ihy, (vy + r) * F.ihy, F.H, true, y0, y1);
+    } else if (vz > r) {
+        const double den = vz * vz - r * r, inv = 1.0 / den;
+        persp_interval(vx, vz, r, den, inv * F.itx, lo, hi);
         ndc_to_pixels(lo, hi, F.W, false, x0, x1);
-        sphere_ndc_interval(F, vy, vz, r, F.ty, F.hy, lo, hi);
+        persp_interval(vy, vz, r, den, inv * F.ity, lo, hi);
         ndc_to_pixels(lo, hi, F.H, true, y0, y1);
     } else {
         const double zl = F.znear, zh = vz + r;
@@ -175,11 +175,19 @@ __device__ inline bool bond_rect(const Frame& F, const double* A, const double* 
         return x0 <= x1 && y0 <= y1;
     }
     double la, ha, lb, hb;
-    sphere_ndc_interval(F, A[0], A[2], rho, F.tx, F.hx, la, ha);
-    sphere_ndc_interval(F, B[0], B[2], rho, F.tx, F.hx, lb, hb);
+    if (F.proj != 0) {
+        ndc_to_pixels((fmin(A[0], B[0]) - rho) * F.ihx, (fmax(A[0], B[0]) + rho) * F.ihx, F.W, false, x0, x1);
+        ndc_to_pixels((fmin(A[1], B[1]) - rho) * F.ihy, (fmax(A[1], B[1]) + rho) * F.ihy, F.H, true, y0, y1);
+        return x0 <= x1 && y0 <= y1;
+    }
+    // both end balls lie in front of the eye plane (zlo > 0)
+    const double da = A[2] * A[2] - rho * rho, db = B[2] * B[2] - rho * rho;
+    const double ia = 1.0 / da, ib = 1.0 / db;
+    persp_interval(A[0], A[2], rho, da, ia * F.itx, la, ha);
+    persp_interval(B[0], B[2], rho, db, ib * F.itx, lb, hb);
     ndc_to_pixels(fmin(la, lb), fmax(ha, hb), F.W, false, x0, x1);
-    sphere_ndc_interval(F, A[1], A[2], rho, F.ty, F.hy, la, ha);
-    sphere_ndc_interval(F, B[1], B[2], rho, F.ty, F.hy, lb, hb);
+    persp_interval(A[1], A[2], rho, da, ia * F.ity, la, ha);
+    persp_interval(B[1], B[2], rho, db, ib * F.ity, lb, hb);
     ndc_to_pixels(fmin(la, lb), fmax(ha, hb), F.H, true, y0, y1);
     return x0 <= x1 && y0 <= y1;
 }
