@@ -617,9 +617,10 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
     if (n == 0) return VTX_OK;
     // one resolve launch per tile size: keep the jobs of a size together
     if (n > 1) std::stable_sort(d.begin(), d.end(), [](const JobDesc& a, const JobDesc& b) { return a.F.tile < b.F.tile; });
-    bool timing = false, scene = false;
+    bool timing = false, scene = false, count = false;
     for (const JobDesc& j : d) {
         timing |= (j.F.flags & VTX_FLAG_TIMING) != 0;
+        count |= (j.F.flags & VTX_FLAG_STATS) != 0;
         scene |= j.scene;
     }
     hipEvent_t* marks = nullptr;
@@ -766,8 +767,9 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
         if (marks) VTX_HIP(hipEventRecord(marks[4], stream));
         for (size_t g = 0; g < groups_ts.size(); ++g) {
             const size_t a = groups_ts[g].first, b = groups_ts[g].second;
-            if (n == 1) VTX_HIP(vtx::launch_resolve(one(groups_grid[g]), d[0].F.tile, groups_grid[g], stream));
-            else VTX_HIP(vtx::launch_resolve(list_of(a, b - a, groups_off[g]), d[a].F.tile, groups_grid[g], stream));
+            if (n == 1) VTX_HIP(vtx::launch_resolve(one(groups_grid[g]), d[0].F.tile, groups_grid[g], count, stream));
+            else
+                VTX_HIP(vtx::launch_resolve(list_of(a, b - a, groups_off[g]), d[a].F.tile, groups_grid[g], count, stream));
         }
         for (size_t i = 0; i < n; ++i) {
             ws->slots[i]->dirty = false;

@@ -24,6 +24,10 @@ namespace vtx {
 namespace {
 
 constexpr int kChunk = kBlock;
+constexpr int kBuckets = 32;      // depth buckets of the front-to-back record order
+constexpr int kSortArea = 16;     // order a chunk when its kept records average more pixels than this
+constexpr int kKeptShift = 21;    // packed scan: footprint area (<= 256 * 64 * 64) below, kept count above
+constexpr uint32_t kAreaMask = (1u << kKeptShift) - 1u;
 template <int TS>
 struct HzGrid {
     static constexpr int kBlocks = (TS / 4) * (TS / 4);
@@ -134,14 +138,19 @@ __device__ inline Rec make_rec(const Frame& F, const PrimRec& p) {
 
 // Work block t of a job is that job's tile t; the launch's blocks are spread
 // over the XCDs in contiguous ranges.
-template <int TS, class JS>
-__global__ void __launch_bounds__(kBlock) k_resolve(JS js) {
+// kCount: the instantiation that can count fragments (jobs with
+// VTX_FLAG_STATS); the other one carries no counters.
+template <int TS, class JS, bool kCount>
+__global__ void __launch_bounds__(kBlock, kCount ? 1 : 7) k_resolve(JS js) {
     __shared__ unsigned long long keys[TS * TS];
     __shared__ Rec recs[kChunk];
     __shared__ uint32_t pref[kChunk + 1];
     __shared__ uint32_t wsum[kBlock / 64];
     constexpr int kHzBlocks = HzGrid<TS>::kBlocks;
     __shared__ uint32_t hz[kHzBlocks];
+    __shared__ float red_lo[kBlock / 64], red_hi[kBlock / 64];
+    __shared__ uint32_t bcnt[kBuckets], bbase[kBuckets];
+    __shared__ uint8_t ord[kChunk];   // depth-ordered chunk: record slots front to back
 
     uint32_t tu;
     const int ji = js.find((uint32_t)xcd_contiguous(blockIdx.x, gridDim.x), tu);
@@ -166,7 +175,7 @@ __global__ void __launch_bounds__(kBlock) k_resolve(JS js) {
     const int T = F.tiles_x * F.tiles_y;
     const int t = (int)tu;
     const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
-    const bool stats = (F.flags & 1u) != 0;
+    const bool stats = kCount && (F.flags & 1u) != 0;
     unsigned long long n_tested = 0, n_hit = 0, n_hit_bond = 0;
 
     if (t < T) {
@@ -245,72 +254,150 @@ __global__ void __launch_bounds__(kBlock) k_resolve(JS js) {
         PrimRec nxt;
         bool nxt_ok = (uint64_t)tid < nsrc && fetch(tid, nxt);
         __syncthreads();
-        for (uint64_t base = 0; base < nsrc; base += kChunk) {
-            const PrimRec pr = nxt;
-            const bool have = nxt_ok;
-            nxt_ok = base + kChunk + tid < nsrc && fetch(base + kChunk + tid, nxt);
-            uint32_t area = 0;
-            if (have) {
-                const Rec rc = make_rec(F, pr);
-                bool keep = true;
-                if (!stats) {
-                    // record cull: its nearest depth lies behind everything the
-                    // 4x4 blocks under its footprint already hold
-                    const int x0 = (int)(rc.rect & 0xFF), y0 = (int)((rc.rect >> 8) & 0xFF);
-                    const int x1 = x0 + (int)((rc.rect >> 16) & 0xFF) - 1, y1 = y0 + (int)(rc.rect >> 24) - 1;
-                    uint32_t m = 0;
-                    for (int by = y0 >> 2; by <= (y1 >> 2); ++by)
-                        for (int bx = x0 >> 2; bx <= (x1 >> 2); ++bx) m = max(m, hz[by * (TS / 4) + bx]);
-                    keep = !(__float_as_uint(rc.zcull) > m && rc.zcull > 0.0f);
-                }
-                if (keep) {
-                    area = ((rc.rect >> 16) & 0xFF) * (rc.rect >> 24);
-                    recs[tid] = rc;
-                }
+        // record cull against the block depths: its nearest possible depth
+        // lies behind everything the 4x4 blocks under its footprint hold
+        auto hz_culled = [&](const Rec& rc) -> bool {
+            const int x0 = (int)(rc.rect & 0xFF), y0 = (int)((rc.rect >> 8) & 0xFF);
+            const int x1 = x0 + (int)((rc.rect >> 16) & 0xFF) - 1, y1 = y0 + (int)(rc.rect >> 24) - 1;
+            uint32_t m = 0;
+            for (int by = y0 >> 2; by <= (y1 >> 2); ++by)
+                for (int bx = x0 >> 2; bx <= (x1 >> 2); ++bx) m = max(m, hz[by * (TS / 4) + bx]);
+            return __float_as_uint(rc.zcull) > m && rc.zcull > 0.0f;
+        };
+        auto rect_area = [](const Rec& rc) -> uint32_t { return ((rc.rect >> 16) & 0xFF) * (rc.rect >> 24); };
+        // refresh the block depths from the tile's depth buffer
+        auto hz_refresh = [&]() {
+            for (int i = tid; i < kHzBlocks; i += kBlock) hz[i] = 0u;
+            __syncthreads();
+            for (int i = tid; i < TS * TS; i += kBlock) {
+                const int ly = i / TS, lx = i - ly * TS;
+                const unsigned long long kk = keys[i];
+                // pixels outside the image never hold a hit: they do not
+                // bound the block
+                const uint32_t zb = (lx < tw && ly < th) ? (kk == ~0ull ? 0x7F800000u : (uint32_t)(kk >> 32)) : 0u;
+                atomicMax(&hz[(ly >> 2) * (TS / 4) + (lx >> 2)], zb);
             }
-            // exclusive prefix of the fragment counts over the workgroup
-            const uint32_t incl = wave_incl_scan(area);
+            __syncthreads();
+        };
+        // exclusive prefix of per-thread fragment counts `a` over the
+        // workgroup into pref[0..kChunk]; the high bits of `a` may carry a
+        // second count (kept records), summed alongside: returns the packed total
+        auto block_scan = [&](uint32_t a) -> uint32_t {
+            const uint32_t incl = wave_incl_scan(a);
             if (lane == 63) wsum[wave] = incl;
             __syncthreads();
-            uint32_t wbase = 0;
-            for (int w = 0; w < wave; ++w) wbase += wsum[w];
-            pref[tid] = wbase + incl - area;
-            if (tid == kBlock - 1) pref[kChunk] = wbase + incl;
+            uint32_t wb = 0, tot = 0;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                wb += w < wave ? wsum[w] : 0u;
+                tot += wsum[w];
+            }
+            pref[tid] = (wb + incl - a) & kAreaMask;
+            if (tid == kBlock - 1) pref[kChunk] = tot & kAreaMask;
             __syncthreads();
+            return tot;
+        };
+        // fragments f of records recs[map(j)], j < span, with prefix pref:
+        // dealt round-robin, so the 64 lanes of a wave take 64 consecutive
+        // fragments, i.e. neighbouring pixels of a few adjacent records, and
+        // early-out decisions agree across the wave
+        auto resolve_fragments = [&](int span, int rbase, bool indirect) {
             const uint32_t total = pref[kChunk];
-            // fragments are dealt round-robin: the 64 lanes of a wave take 64
-            // consecutive fragments, i.e. neighbouring pixels of a few adjacent
-            // records, so early-out decisions agree across the wave
             for (uint32_t f = tid; f < total; f += kBlock) {
-                int lo = 0, hi = kChunk;
+                int lo = 0, hi = span;
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) >> 1;
                     if (pref[mid] <= f) lo = mid;
                     else hi = mid;
                 }
-                const Rec& rc = recs[lo];
+                const Rec& rr = recs[indirect ? (int)ord[rbase + lo] : lo];
                 const uint32_t local = f - pref[lo];
-                const uint32_t rw = (rc.rect >> 16) & 0xFF;
+                const uint32_t rw = (rr.rect >> 16) & 0xFF;
                 // exact: local < 4096 and rw <= 64, so the rounding error of
                 // (local + 1/2) / rw is far below its distance to an integer
                 const uint32_t dy = (uint32_t)(((float)local + 0.5f) * __builtin_amdgcn_rcpf((float)rw));
                 const uint32_t dx = local - dy * rw;
-                test_pixel(rc, (int)(rc.rect & 0xFF) + (int)dx, (int)((rc.rect >> 8) & 0xFF) + (int)dy);
+                test_pixel(rr, (int)(rr.rect & 0xFF) + (int)dx, (int)((rr.rect >> 8) & 0xFF) + (int)dy);
             }
             __syncthreads();
-            if (!stats && base + kChunk < nsrc) {
-                // refresh the block depths for the next chunk's record cull
-                for (int i = tid; i < kHzBlocks; i += kBlock) hz[i] = 0u;
-                __syncthreads();
-                for (int i = tid; i < TS * TS; i += kBlock) {
-                    const int ly = i / TS, lx = i - ly * TS;
-                    const unsigned long long kk = keys[i];
-                    // pixels outside the image never hold a hit: they do not
-                    // bound the block
-                    const uint32_t zb = (lx < tw && ly < th) ? (kk == ~0ull ? 0x7F800000u : (uint32_t)(kk >> 32)) : 0u;
-                    atomicMax(&hz[(ly >> 2) * (TS / 4) + (lx >> 2)], zb);
+        };
+        for (uint64_t base = 0; base < nsrc; base += kChunk) {
+            const PrimRec pr = nxt;
+            const bool have = nxt_ok;
+            nxt_ok = base + kChunk + tid < nsrc && fetch(base + kChunk + tid, nxt);
+            bool keep = false;
+            uint32_t area = 0;
+            float zc = INFINITY;
+            if (have) {
+                const Rec rc = make_rec(F, pr);
+                keep = stats || !hz_culled(rc);
+                if (keep) {
+                    area = rect_area(rc);
+                    zc = rc.zcull;
+                    recs[tid] = rc;
                 }
-                __syncthreads();
+            }
+            const bool more = base + kChunk < nsrc;
+            // prefix of the footprint areas, with the kept records counted in
+            // the high bits
+            const uint32_t packed = block_scan(area | (keep ? 1u << kKeptShift : 0u));
+            const uint32_t atot = packed & kAreaMask, nk = packed >> kKeptShift;
+            // Large footprints (many records cover each pixel): order the
+            // kept records front to back by a counting sort over depth
+            // buckets and resolve them in sub-chunks, refreshing the block
+            // depths in between, so records behind the first layers are
+            // culled whole before any of their pixels is tested.  Sub-chunks
+            // hold about two tiles' worth of footprint: 16 records when they
+            // average 64 pixels or more, else 32.
+            const int sub = atot >= 64u * nk ? 16 : 32;
+            const bool sorted = !stats && nk > (uint32_t)sub && atot > (uint32_t)kSortArea * nk;
+            if (!sorted) {
+                resolve_fragments(kChunk, 0, false);
+                if (!stats && more) hz_refresh();
+                continue;
+            }
+            // depth range of the kept records
+            float zlo = zc, zhi = keep ? zc : -INFINITY;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                zlo = fminf(zlo, __shfl_xor(zlo, o));
+                zhi = fmaxf(zhi, __shfl_xor(zhi, o));
+            }
+            if (lane == 0) {
+                red_lo[wave] = zlo;
+                red_hi[wave] = zhi;
+            }
+            if (tid < kBuckets) bcnt[tid] = 0u;
+            __syncthreads();
+            zlo = fminf(fminf(red_lo[0], red_lo[1]), fminf(red_lo[2], red_lo[3]));
+            zhi = fmaxf(fmaxf(red_hi[0], red_hi[1]), fmaxf(red_hi[2], red_hi[3]));
+            const float span = zhi - zlo;
+            const float scale = span > 0.0f ? (float)kBuckets / span : 0.0f;
+            const int bk = keep ? min(kBuckets - 1, (int)((zc - zlo) * scale)) : 0;
+            if (keep) atomicAdd(&bcnt[bk], 1u);
+            __syncthreads();
+            if (wave == 0) {
+                const uint32_t c = lane < kBuckets ? bcnt[lane] : 0u;
+                const uint32_t inc = wave_incl_scan(c);
+                if (lane < kBuckets) {
+                    bbase[lane] = inc - c;
+                    bcnt[lane] = 0u;
+                }
+            }
+            __syncthreads();
+            if (keep) ord[bbase[bk] + atomicAdd(&bcnt[bk], 1u)] = (uint8_t)tid;
+            const int nsub = (int)((nk + sub - 1) / sub);
+            for (int sc = 0; sc < nsub; ++sc) {
+                const int rbase = sc * sub;
+                __syncthreads();   // the order (and a refreshed hz) are in LDS
+                uint32_t a = 0;
+                const uint32_t j = (uint32_t)(rbase + tid);
+                if (tid < sub && j < nk) {
+                    const Rec& r2 = recs[ord[j]];
+                    a = (sc > 0 && hz_culled(r2)) ? 0u : rect_area(r2);
+                }
+                block_scan(a);
+                resolve_fragments(sub, rbase, true);
+                if (sc + 1 < nsub || more) hz_refresh();
             }
         }
         __syncthreads();
@@ -359,25 +446,26 @@ __global__ void __launch_bounds__(kBlock) k_resolve(JS js) {
 
 }  // namespace
 
-template <class JS>
+template <class JS, bool kCount>
 hipError_t resolve_impl(const JS& js, int tile, uint32_t grid, hipStream_t stream) {
     if (grid == 0) return hipSuccess;
     const unsigned g = (unsigned)xcd_grid((int)grid);
     switch (tile) {
-        case 8: k_resolve<8, JS><<<g, kBlock, 0, stream>>>(js); break;
-        case 16: k_resolve<16, JS><<<g, kBlock, 0, stream>>>(js); break;
-        case 32: k_resolve<32, JS><<<g, kBlock, 0, stream>>>(js); break;
-        case 64: k_resolve<64, JS><<<g, kBlock, 0, stream>>>(js); break;
+        case 8: k_resolve<8, JS, kCount><<<g, kBlock, 0, stream>>>(js); break;
+        case 16: k_resolve<16, JS, kCount><<<g, kBlock, 0, stream>>>(js); break;
+        case 32: k_resolve<32, JS, kCount><<<g, kBlock, 0, stream>>>(js); break;
+        case 64: k_resolve<64, JS, kCount><<<g, kBlock, 0, stream>>>(js); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_resolve(const OneJob& js, int tile, uint32_t grid, hipStream_t stream) {
-    return resolve_impl(js, tile, grid, stream);
+hipError_t launch_resolve(const OneJob& js, int tile, uint32_t grid, bool count, hipStream_t stream) {
+    return count ? resolve_impl<OneJob, true>(js, tile, grid, stream) : resolve_impl<OneJob, false>(js, tile, grid, stream);
 }
-hipError_t launch_resolve(const JobList& js, int tile, uint32_t grid, hipStream_t stream) {
-    return resolve_impl(js, tile, grid, stream);
+hipError_t launch_resolve(const JobList& js, int tile, uint32_t grid, bool count, hipStream_t stream) {
+    return count ? resolve_impl<JobList, true>(js, tile, grid, stream)
+                 : resolve_impl<JobList, false>(js, tile, grid, stream);
 }
 
 }  // namespace vtx

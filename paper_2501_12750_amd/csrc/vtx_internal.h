@@ -332,15 +332,17 @@ struct JobList {
 // Launch wrappers, one overload per job source.  `grid` is the number of
 // work blocks (sum over the jobs); `max_tiles` the largest tile grid of the
 // jobs (LDS of the binning kernels).  `tile` selects the resolve
-// instantiation: every job of one resolve launch has that tile size.
+// instantiation: every job of one resolve launch has that tile size; `count`
+// selects the one that counts fragments (needed when any job sets
+// VTX_FLAG_STATS).
 hipError_t launch_cluster_cull(const OneJob& js, uint32_t grid, hipStream_t stream);
 hipError_t launch_cluster_cull(const JobList& js, uint32_t grid, hipStream_t stream);
 hipError_t launch_count(const OneJob& js, bool scene, uint32_t grid, int max_tiles, hipStream_t stream);
 hipError_t launch_count(const JobList& js, bool scene, uint32_t grid, int max_tiles, hipStream_t stream);
 hipError_t launch_scatter(const OneJob& js, uint32_t grid, int max_tiles, hipStream_t stream);
 hipError_t launch_scatter(const JobList& js, uint32_t grid, int max_tiles, hipStream_t stream);
-hipError_t launch_resolve(const OneJob& js, int tile, uint32_t grid, hipStream_t stream);
-hipError_t launch_resolve(const JobList& js, int tile, uint32_t grid, hipStream_t stream);
+hipError_t launch_resolve(const OneJob& js, int tile, uint32_t grid, bool count, hipStream_t stream);
+hipError_t launch_resolve(const JobList& js, int tile, uint32_t grid, bool count, hipStream_t stream);
 hipError_t launch_shade(const OneJob& js, uint32_t grid, hipStream_t stream);
 hipError_t launch_shade(const JobList& js, uint32_t grid, hipStream_t stream);
 
