@@ -146,6 +146,13 @@ class SingleRunner:
         self.vtx.vtx_render(*self.ds.args(), r.camera, r.options, r.W, r.H, r.out.rgba, r.out.depth, r.out.id,
                             self.stream)
 
+    def autotune(self, cache):
+        if self.rs is None:
+            raise SystemExit("--autotune needs the resident-scene path")
+        r = self.renders[0]
+        job = self.vtx.make_job(self.rs.handle, 0, r.camera, r.options, r.W, r.H, r.out.rgba, r.out.depth, r.out.id)
+        return self.vtx.vtx_autotune(self.ctx, [job], cache, self.stream)
+
     def close(self):
         if self.rs is not None:
             self.rs.close()
@@ -187,6 +194,9 @@ class BatchRunner:
     def other_step(self):
         for one in self.jobs(0)[1]:
             self.vtx.vtx_render_batch(self.ctx, one, self.stream)
+
+    def autotune(self, cache):
+        return self.vtx.vtx_autotune(self.ctx, self.jobs(0)[0], cache, self.stream)
 
     def close(self):
         self.rs.close()
@@ -234,6 +244,10 @@ def main():
     ap.add_argument("--kernel-events", choices=["timed", "separate"], default="separate",
                     help="record the per-kernel HIP events inside the timed region, or in a separate "
                          "pass of the same length after it")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose the tile size with vtx_autotune on the workload's renders before timing "
+                         "(renders that leave tile_size at 0 then use it)")
+    ap.add_argument("--tuning-cache", default=None, help="JSON cache file for --autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before timing, run one device copy of this many MiB (reference for HBM counters)")
@@ -284,6 +298,16 @@ def main():
         warmup = args.warmup if args.warmup >= 0 else 20
     config["launch"] = runner.launch_form
     R = len(runner.renders)
+    tuning = None
+    if args.autotune:
+        if args.tile:
+            raise SystemExit("--autotune and --tile exclude each other")
+        tuning = runner.autotune(args.tuning_cache)
+        log(f"autotune: {tuning}")
+        for r in runner.renders:
+            r.tuned_tile = tuning["tile_size"]
+        config["tile_size"] = tuning["tile_size"]
+        config["autotune"] = tuning
     log(f"workload {name}: {N} atoms, {M} bonds, {R} render(s) per step, set up in {time.perf_counter() - t0:.1f} s")
 
     # exact fragment counts of these renders (early-outs off), untimed
@@ -353,7 +377,9 @@ def main():
     f_total = st["fragments_hit"]
     f_cyl = st.get("fragments_hit_bond", 0)
     f_sph = f_total - f_cyl
-    tiles = sum(n_tiles(r.options.tile_size, r.W, r.H) for r in runner.renders)
+    def eff_tile(r):
+        return frame_tile(getattr(r, "tuned_tile", 0) or r.options.tile_size, r.W, r.H)
+    tiles = sum(n_tiles(eff_tile(r), r.W, r.H) for r in runner.renders)
     per_kernel = {
         "project": ("hbm", (16.0 * N + 8.0 * M) * R, timings["ms_project"]),
         "resolve": ("alu", float(OPS_SPHERE_FRAG * f_sph + OPS_CYL_FRAG * f_cyl), timings["ms_resolve"]),
@@ -375,7 +401,7 @@ def main():
     roof = dict(kern[dom])
     roof.pop("ms")
     scene_path = batch or runner.path == "scene"
-    res_tiles = sorted({frame_tile(r.options.tile_size, r.W, r.H) for r in runner.renders})
+    res_tiles = sorted({eff_tile(r) for r in runner.renders})
     launched = {"project": (["k_cluster_cull", "k_count<SceneSource>"] if scene_path else ["k_count<PlainSource>"]),
                 "scatter": ["k_scatter"], "resolve": [f"k_resolve<{t}>" for t in res_tiles], "shade": ["k_shade"],
                 "scan": []}

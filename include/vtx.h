@@ -286,6 +286,33 @@ typedef struct vtx_job {
  */
 int vtx_render_batch(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, void* stream);
 
+/* Result of vtx_autotune. */
+typedef struct vtx_tuning {
+    int32_t tile_size;        /* chosen screen tile edge (8, 16, 32 or 64) */
+    int32_t from_cache;       /* 1: read from the cache file, nothing was timed */
+    float ms_per_batch;       /* device time of one sample batch at that size */
+    float ms_by_tile[4];      /* at 8, 16, 32, 64 (0 = not tried: too many tiles) */
+    char key[96];             /* shape it applies to: WxH/p<log2(atoms + bonds)>/<projection> */
+} vtx_tuning;
+
+/*
+ * vtx_autotune - chooses the screen tile size for renders shaped like the
+ * sample jobs (a shape is image size, log2 of the primitive count and
+ * projection): times the sample batch (rendered into the jobs' own images,
+ * flags cleared) at every tile size all its images accept, with HIP events on
+ * `stream`, and keeps the fastest in the context for each shape in the batch;
+ * renders of those shapes that leave options.tile_size at 0
+ * (vtx_render_scene, vtx_render_batch) use it.  The images do not depend on
+ * the tile size.  With `cache_path` (NULL: none) the choices are read from
+ * that JSON file when it has every shape of the batch, otherwise measured and
+ * written to it (other shapes' entries are kept).  Waits for the stream.
+ * `out` (may be NULL) describes the choice for jobs[0]'s shape.
+ * The paper's engine tunes nothing; the tile size is this library's own
+ * parameter (its only one that trades speed for nothing).
+ */
+int vtx_autotune(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, const char* cache_path, void* stream,
+                 vtx_tuning* out);
+
 /*
  * vtx_read_stats - waits for `stream` to drain, then returns the counters of
  * the last call queued on it by this library (summed over its jobs for a

@@ -468,6 +468,7 @@ struct vtx_context {
     size_t budget = 0;       // bytes of scenes this context may keep resident (0 = no limit)
     size_t used = 0;
     std::mutex mu;
+    std::map<std::string, int> tuned;   // shape key -> tile size chosen by vtx_autotune
 };
 
 // Positions of one stored trajectory frame.
@@ -548,6 +549,28 @@ void scene_frame(const vtx_scene* sc, int f, vtx::SceneDev* S, const float** pos
         S->cluster_box = fr.cluster_box;
         *pos = fr.pos;
     }
+}
+
+// Shape a tuned tile size applies to: image size, primitive count (by
+// powers of two) and projection.
+std::string shape_key(int32_t W, int32_t H, int64_t n, int64_t m, int32_t projection) {
+    int lg = 0;
+    for (uint64_t v = (uint64_t)(n + m); v > 1; v >>= 1) ++lg;
+    char buf[96];
+    snprintf(buf, sizeof(buf), "%dx%d/p%d/%s", W, H, lg, projection == VTX_ORTHOGRAPHIC ? "ortho" : "persp");
+    return buf;
+}
+
+// Options with the tile size the context tuned for this shape, when the
+// caller left it to the library.
+vtx_options tuned_options(vtx_context* ctx, vtx_options o, const vtx_camera* cam, int32_t W, int32_t H,
+                          int64_t n, int64_t m) {
+    if (o.tile_size != 0 || !ctx || !cam) return o;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->tuned.empty()) return o;
+    auto it = ctx->tuned.find(shape_key(W, H, n, m, cam->projection));
+    if (it != ctx->tuned.end()) o.tile_size = it->second;
+    return o;
 }
 
 // Host description of one render.
@@ -1065,7 +1088,7 @@ void vtx_scene_destroy(vtx_scene* scene) {
 int vtx_render_scene(vtx_scene* scene, const vtx_camera* cam, const vtx_options* opt, int32_t W, int32_t H,
                      uint32_t* rgba, float* depth, uint32_t* id, void* stream) {
     if (!scene) return fail(VTX_EINVAL, "scene is NULL");
-    const vtx_options o = resolve_options(opt);
+    const vtx_options o = tuned_options(scene->ctx, resolve_options(opt), cam, W, H, scene->n, scene->m);
     Frame F;
     int rc = make_frame(cam, o, W, H, scene->n, scene->m, &F);
     if (rc) return rc;
@@ -1100,7 +1123,7 @@ int vtx_render_batch(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, void
         if (j.frame < 0 || j.frame > (int32_t)sc->frames.size())
             return fail(VTX_EINVAL, "job %d: frame %d not in 0..%zu", i, j.frame, sc->frames.size());
         if (!j.rgba || !j.depth || !j.id) return fail(VTX_EINVAL, "job %d: rgba/depth/id outputs are NULL", i);
-        const vtx_options o = resolve_options(&j.options);
+        const vtx_options o = tuned_options(ctx, resolve_options(&j.options), &j.camera, j.width, j.height, sc->n, sc->m);
         Frame F;
         int rc = make_frame(&j.camera, o, j.width, j.height, sc->n, sc->m, &F);
         if (rc) return fail(rc, "job %d: %s", i, g_error.c_str());
@@ -1116,6 +1139,120 @@ int vtx_render_batch(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, void
     }
     std::lock_guard<std::mutex> lk(g_mu);
     return render_locked(d, true, true, (hipStream_t)stream);
+}
+
+int vtx_autotune(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, const char* cache_path, void* stream,
+                 vtx_tuning* out) {
+    if (!ctx) return fail(VTX_EINVAL, "context is NULL");
+    if (n_jobs < 1 || n_jobs > kMaxBatch || !jobs) return fail(VTX_EINVAL, "need 1..%d sample jobs", kMaxBatch);
+    // the shapes of the sample jobs; the batch is timed as a whole and its
+    // choice kept for each of them
+    std::vector<std::string> keys;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+        if (!jobs[i].scene) return fail(VTX_EINVAL, "job %d: scene is NULL", i);
+        const std::string k =
+            shape_key(jobs[i].width, jobs[i].height, jobs[i].scene->n, jobs[i].scene->m, jobs[i].camera.projection);
+        if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
+    }
+    const std::string key = keys[0];
+    std::map<std::string, int> cached;
+    vtx_tuning t;
+    std::memset(&t, 0, sizeof(t));
+    std::snprintf(t.key, sizeof(t.key), "%s", key.c_str());
+    // a cached choice for this shape
+    std::vector<std::pair<std::string, std::string>> lines;   // key -> its cache line
+    if (cache_path && *cache_path) {
+        if (FILE* fh = std::fopen(cache_path, "r")) {
+            char buf[512];
+            while (std::fgets(buf, sizeof(buf), fh)) {
+                char k[160];
+                int tile = 0;
+                if (std::sscanf(buf, " {\"key\": \"%159[^\"]\", \"tile_size\": %d", k, &tile) == 2) {
+                    std::string line(buf);
+                    while (!line.empty() && (line.back() == '\n' || line.back() == ',' || line.back() == ' '))
+                        line.pop_back();
+                    lines.push_back({k, line});
+                    if (tile == 8 || tile == 16 || tile == 32 || tile == 64) cached[k] = tile;
+                }
+            }
+            std::fclose(fh);
+        }
+    }
+    bool all_cached = true;
+    for (const std::string& k : keys) all_cached = all_cached && cached.count(k);
+    if (all_cached) {
+        t.from_cache = 1;
+        t.tile_size = cached[key];
+    } else {
+        // time the sample batch at each tile size every job's image accepts
+        hipStream_t st = (hipStream_t)stream;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        VTX_HIP(hipEventCreate(&e0));
+        VTX_HIP(hipEventCreate(&e1));
+        std::vector<vtx_job> trial(jobs, jobs + n_jobs);
+        const int sizes[4] = {8, 16, 32, 64};
+        float best = 0.0f;
+        int rc = VTX_OK;
+        for (int k = 0; k < 4 && rc == VTX_OK; ++k) {
+            bool ok = true;
+            for (const vtx_job& j : trial)
+                ok = ok && (int64_t)((j.width + sizes[k] - 1) / sizes[k]) * ((j.height + sizes[k] - 1) / sizes[k]) <=
+                               vtx::kMaxLdsTiles;
+            if (!ok) continue;
+            for (vtx_job& j : trial) {
+                j.options.tile_size = sizes[k];
+                j.options.flags = 0;
+            }
+            float ms = 0.0f;
+            for (int rep = 0; rep < 4 && rc == VTX_OK; ++rep) {   // first run sizes the bins: untimed
+                if (rep == 1) rc = hipEventRecord(e0, st) == hipSuccess ? VTX_OK : fail(VTX_EHIP, "hipEventRecord failed");
+                if (rc == VTX_OK) rc = vtx_render_batch(ctx, trial.data(), n_jobs, stream);
+            }
+            if (rc == VTX_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = fail(VTX_EHIP, "timing the sample batch failed");
+            if (rc != VTX_OK) break;
+            ms /= 3.0f;
+            t.ms_by_tile[k] = ms;
+            if (!t.tile_size || ms < best) {
+                best = ms;
+                t.tile_size = sizes[k];
+            }
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        if (rc != VTX_OK) return rc;
+        if (!t.tile_size) return fail(VTX_EINVAL, "no tile size fits the sample images");
+        t.ms_per_batch = best;
+        for (const std::string& k : keys) cached[k] = t.tile_size;
+        if (cache_path && *cache_path) {
+            for (const std::string& k : keys) {
+                char line[256];
+                std::snprintf(line, sizeof(line), "  {\"key\": \"%s\", \"tile_size\": %d, \"ms_per_batch\": %.6f}",
+                              k.c_str(), t.tile_size, (double)best);
+                bool replaced = false;
+                for (auto& l : lines)
+                    if (l.first == k) {
+                        l.second = line;
+                        replaced = true;
+                    }
+                if (!replaced) lines.push_back({k, line});
+            }
+            FILE* fh = std::fopen(cache_path, "w");
+            if (!fh) return fail(VTX_EINVAL, "cannot write the tuning cache %s", cache_path);
+            std::fprintf(fh, "{\"vtx_tuning\": [\n");
+            for (size_t i = 0; i < lines.size(); ++i)
+                std::fprintf(fh, "%s%s\n", lines[i].second.c_str(), i + 1 < lines.size() ? "," : "");
+            std::fprintf(fh, "]}\n");
+            std::fclose(fh);
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (const std::string& k : keys) ctx->tuned[k] = cached[k];
+    }
+    if (out) *out = t;
+    return VTX_OK;
 }
 
 int vtx_read_stats(void* stream, vtx_stats* out) {

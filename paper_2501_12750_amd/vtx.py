@@ -36,7 +36,7 @@ EXPORTS = ("vtx_render", "vtx_gbuffer", "vtx_shade", "vtx_read_stats", "vtx_set_
            "vtx_context_create", "vtx_context_destroy", "vtx_context_bytes_in_use", "vtx_scene_footprint_bytes",
            "vtx_frame_scratch_bytes", "vtx_scene_create", "vtx_scene_update_positions", "vtx_scene_info",
            "vtx_scene_destroy", "vtx_render_scene", "vtx_scene_add_frames", "vtx_scene_frames",
-           "vtx_scene_frame_bytes", "vtx_render_batch")
+           "vtx_scene_frame_bytes", "vtx_render_batch", "vtx_autotune")
 
 
 class vtx_camera(ctypes.Structure):
@@ -72,6 +72,17 @@ class vtx_job(ctypes.Structure):
     _fields_ = [("scene", ctypes.c_void_p), ("frame", ctypes.c_int32), ("camera", vtx_camera),
                 ("options", vtx_options), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
                 ("rgba", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("id", ctypes.c_void_p)]
+
+
+class vtx_tuning(ctypes.Structure):
+    _fields_ = [("tile_size", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("ms_per_batch", ctypes.c_float),
+                ("ms_by_tile", ctypes.c_float * 4), ("key", ctypes.c_char * 96)]
+
+    def as_dict(self):
+        return {"tile_size": self.tile_size, "from_cache": bool(self.from_cache),
+                "ms_per_batch": float(self.ms_per_batch),
+                "ms_by_tile": {t: float(v) for t, v in zip((8, 16, 32, 64), self.ms_by_tile) if v > 0},
+                "key": self.key.decode()}
 
 
 class VtxError(RuntimeError):
@@ -136,6 +147,8 @@ _lib.vtx_scene_frame_bytes.restype = ctypes.c_size_t
 _lib.vtx_scene_frame_bytes.argtypes = [_I64, _I64]
 _lib.vtx_render_batch.restype = ctypes.c_int
 _lib.vtx_render_batch.argtypes = [_P, ctypes.POINTER(vtx_job), _I32, _P]
+_lib.vtx_autotune.restype = ctypes.c_int
+_lib.vtx_autotune.argtypes = [_P, ctypes.POINTER(vtx_job), _I32, ctypes.c_char_p, _P, ctypes.POINTER(vtx_tuning)]
 _lib.vtx_last_error.restype = ctypes.c_char_p
 _lib.vtx_last_error.argtypes = []
 _lib.vtx_version.restype = ctypes.c_char_p
@@ -323,6 +336,14 @@ def vtx_render_batch(ctx, jobs, stream=None):
     else:
         arr = jobs
     _check(_lib.vtx_render_batch(ctx, arr, len(arr), _stream(stream)))
+
+
+def vtx_autotune(ctx, jobs, cache_path=None, stream=None) -> dict:
+    arr = jobs if isinstance(jobs, ctypes.Array) else (vtx_job * len(jobs))(*jobs)
+    t = vtx_tuning()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(_lib.vtx_autotune(ctx, arr, len(arr), path, _stream(stream), ctypes.byref(t)))
+    return t.as_dict()
 
 
 def vtx_last_error() -> str:
