@@ -14,6 +14,10 @@ Workloads:
   trajectory                50k atoms x 64 trajectory frames x 4 orbit
                             viewports (720p..1440p) = 256 renders; one step =
                             one vtx_render_batch call of all 256
+  served                    Poisson arrivals (200/s, 60 s) of session frames on
+                            24 resident scenes of 1e4..1e7 atoms at 720p/1080p/4K,
+                            rendered by vtx_server (continuous batching);
+                            frames/s and arrival-to-completion p50/p99
   plain_small               4096 atoms, 256x256 (the small parity case)
 
 Prints ONE JSON line: frames/s (renders/s for the batch) with the contract
@@ -203,6 +207,152 @@ class BatchRunner:
         self.vtx.vtx_context_destroy(self.ctx)
 
 
+def _build_served_scene(spec):
+    scene, centre, radius = spec.build()
+    return scene, centre, radius
+
+
+def build_served(args, scenes):
+    """Generates the served mix's scene pool on the host cores (before the
+    process touches the GPU)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    pool, reqs = scenes.served_mix(duration_s=args.serve_seconds, rate_hz=args.serve_rate)
+    t0 = time.perf_counter()
+    used = sorted({r.scene for r in reqs})
+    with cf.ProcessPoolExecutor(max_workers=min(8, len(used)), mp_context=mp.get_context("spawn")) as ex:
+        built = dict(zip(used, ex.map(_build_served_scene, [pool[k] for k in used])))
+    log(f"served pool: {len(used)} scenes, {sum(built[k][0].n_atoms for k in used) / 1e6:.1f}M atoms, "
+        f"generated in {time.perf_counter() - t0:.1f} s; {len(reqs)} requests over {args.serve_seconds:.0f} s")
+    return pool, reqs, used, built
+
+
+def run_served(args, vtx, scenes, torch, stream):
+    """The served mix: Poisson arrivals of session frames on a pool of 24
+    resident scenes, rendered by the library's server (continuous batching);
+    latency is arrival -> device completion."""
+    pool, reqs, used, built = args.served_inputs
+    dev_scenes = {k: vtx.DeviceScene(built[k][0]) for k in used}
+    budget = int(args.serve_budget_gb * (1 << 30)) if args.serve_budget_gb > 0 else 0
+    ctx = vtx.vtx_context_create(0, budget)
+    upload = torch.cuda.Stream()
+    server = vtx.vtx_server_create(ctx, args.serve_max_batch, 2, stream)
+    opts = scenes.Options(ssao_samples=16, ssao_radius=2.0)
+    outs = {res: [vtx.Frame(*res) for _ in range(48)] for res in scenes.SERVE_RESOLUTIONS}
+    slot_next = {res: 0 for res in outs}
+    slot_busy = {}                      # (res, slot) -> ticket
+    resident = {}                       # pool index -> ResidentScene
+    last_use = {}
+    outstanding = {}                    # pool index -> in-flight requests
+    ticket_info = {}
+    done = []
+    created = evicted = 0
+
+    def collect(wait_ms=0):
+        for c in vtx.vtx_server_poll(server, 512, wait_ms):
+            info = ticket_info.pop(c["ticket"])
+            outstanding[info["scene"]] -= 1
+            slot_busy.pop(info["slot"], None)
+            c.update(info)
+            done.append(c)
+
+    def ensure_resident(k):
+        nonlocal created, evicted
+        if k in resident:
+            return resident[k]
+        while True:
+            try:
+                rs = vtx.ResidentScene(ctx, dev_scenes[k], stream=upload)
+                created += 1
+                resident[k] = rs
+                return rs
+            except vtx.VtxError as e:
+                if e.code != vtx.VTX_EBUSY:
+                    raise
+                idle = [j for j in resident if outstanding.get(j, 0) == 0]
+                if not idle:
+                    collect(5)
+                    continue
+                j = min(idle, key=lambda j: last_use.get(j, 0.0))
+                resident.pop(j).close()
+                evicted += 1
+
+    start = vtx.vtx_clock_s() + 0.5
+    for r in reqs:
+        arrival = start + r.t
+        while True:
+            collect()
+            dt = arrival - vtx.vtx_clock_s()
+            if dt <= 0:
+                break
+            time.sleep(min(dt, 0.002))
+        rs = ensure_resident(r.scene)
+        res = (r.width, r.height)
+        slot = None
+        while slot is None:
+            cand = (res, slot_next[res])
+            slot_next[res] = (slot_next[res] + 1) % len(outs[res])
+            if cand not in slot_busy:
+                slot = cand
+            else:
+                collect(1)
+        fr = outs[res][slot[1]]
+        sc, centre, radius = built[r.scene]
+        cam = scenes.orbit_camera(centre, radius, r.angle)
+        job = vtx.make_job(rs.handle, 0, cam, opts, r.width, r.height, fr.rgba, fr.depth, fr.id)
+        tk = vtx.vtx_server_submit(server, job)
+        ticket_info[tk] = {"arrival": arrival, "scene": r.scene, "slot": slot, "t": r.t,
+                           "pixels": r.width * r.height}
+        slot_busy[slot] = tk
+        outstanding[r.scene] = outstanding.get(r.scene, 0) + 1
+        last_use[r.scene] = arrival
+    vtx.vtx_server_drain(server)
+    collect()
+    sst = vtx.vtx_server_stats_read(server)
+    vtx.vtx_server_destroy(server)
+    for rs in resident.values():
+        rs.close()
+    vtx.vtx_context_destroy(ctx)
+
+    warm = args.serve_warmup
+    lat = np.array([(c["done_s"] - c["arrival"]) * 1e3 for c in done if c["t"] >= warm])
+    q = np.array([(c["launch_s"] - c["arrival"]) * 1e3 for c in done if c["t"] >= warm])
+    bad = sum(1 for c in done if c["status"] != 0)
+    span = max(c["done_s"] for c in done) - (start + warm)
+    n_after = sum(1 for c in done if c["t"] >= warm)
+    px = sum(c["pixels"] for c in done if c["t"] >= warm)
+    fps = n_after / span
+    out = {
+        "metric": "frames/s",
+        "value": round(fps, 3),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": sum(1 for r in reqs if r.t < warm),
+        "ms_per_step": round(1e3 / fps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"served_mix_{len(pool)}scenes_{args.serve_rate:.0f}hz_{args.serve_seconds:.0f}s",
+                   "scenes": len(used), "atoms_min": min(built[k][0].n_atoms for k in used),
+                   "atoms_max": max(built[k][0].n_atoms for k in used),
+                   "resolutions": [list(x) for x in scenes.SERVE_RESOLUTIONS], "ssao_samples": 16,
+                   "arrival_rate_hz": args.serve_rate, "mean_session_frames": 8,
+                   "hbm_budget_bytes": budget or "full", "max_batch": args.serve_max_batch,
+                   "launch": "vtx_server: continuous batching into vtx_render_batch, 2 batches in flight"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
+                       "mean": round(float(lat.mean()), 3), "queue_p50": round(float(np.percentile(q, 50)), 3),
+                       "frames": int(lat.size), "measured_from": "arrival", "to": "device completion (host callback)"},
+        "megapixels_per_s": round(px / span / 1e6, 2),
+        "server": {**sst, "mean_batch": round(sst["completed"] / max(1, sst["batches"]), 2)},
+        "residency": {"scenes_created": created, "scenes_evicted": evicted},
+        "failed_requests": bad,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(renders, scene_of, budget_s=12.0):
     """The oracle (FP64 C splatter + SSAO + shading) on the host cores, end to
     end, for as many whole renders of the workload, in order, as fit the
@@ -233,7 +383,13 @@ def main():
     ap.add_argument("--steps", type=int, default=0, help="timed steps (0: 200 frames, or 10 batches)")
     ap.add_argument("--warmup", type=int, default=-1, help="untimed steps first (-1: 20 frames, or 2 batches)")
     ap.add_argument("--workload", default="ball_and_stick",
-                    choices=["ball_and_stick", "whole_cell", "trajectory", "plain_small"])
+                    choices=["ball_and_stick", "whole_cell", "trajectory", "served", "plain_small"])
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="served mix: arrival window")
+    ap.add_argument("--serve-warmup", type=float, default=5.0, help="served mix: arrivals excluded from stats")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="served mix: frame requests per second")
+    ap.add_argument("--serve-budget-gb", type=float, default=0.0,
+                    help="served mix: HBM budget of resident scenes (0 = the full memory)")
+    ap.add_argument("--serve-max-batch", type=int, default=64)
     ap.add_argument("--tile", type=int, default=0, help="tile size (0 = library default)")
     ap.add_argument("--path", choices=["scene", "plain"], default="scene",
                     help="single-frame workloads: scene = resident scene (vtx_scene_create before timing, "
@@ -260,9 +416,14 @@ def main():
     import torch
     from paper_2501_12750_amd import scenes, vtx
 
+    if args.workload == "served":
+        args.served_inputs = build_served(args, scenes)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    if args.workload == "served":
+        run_served(args, vtx, scenes, torch, torch.cuda.Stream())
+        return
     t0 = time.perf_counter()
     batch = args.workload == "trajectory"
     if batch:

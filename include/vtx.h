@@ -270,6 +270,11 @@ typedef struct vtx_job {
     uint32_t* id;
 } vtx_job;
 
+/* vtx_check_job - the argument checks vtx_render_batch applies to one job
+ * (ctx may be NULL to skip the context check); VTX_OK or VTX_EINVAL with the
+ * reason in vtx_last_error. */
+int vtx_check_job(const vtx_context* ctx, const vtx_job* job);
+
 /*
  * vtx_render_batch - renders n_jobs (0 .. 4096) independent jobs with one
  * launch per pass for the whole batch (cluster test, count, scatter, one
@@ -312,6 +317,56 @@ typedef struct vtx_tuning {
  */
 int vtx_autotune(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, const char* cache_path, void* stream,
                  vtx_tuning* out);
+
+/* ---------------------------------------------------------------------------
+ * Served renders.  A server owns one worker thread that drains a request
+ * queue into batches: whenever fewer than max_inflight batches are queued on
+ * `stream`, the requests waiting (at most max_batch) are rendered together
+ * with vtx_render_batch (continuous batching).  Each request is a vtx_job;
+ * its scene and images must stay valid until its completion is reported.
+ * Timestamps are seconds of vtx_clock_s (a monotonic host clock); done_s is
+ * taken by a host callback queued on the stream after the request's batch,
+ * i.e. once the device has finished it.  Residency and admission of scenes
+ * are the caller's (vtx_scene_create answers VTX_EBUSY when a scene would
+ * exceed the context budget).  The paper renders interactive sessions of
+ * frames (Methods; Results, trajectories); a server of many such sessions is
+ * this library's own.
+ * ------------------------------------------------------------------------- */
+typedef struct vtx_server vtx_server;
+
+typedef struct vtx_completion {
+    uint64_t ticket;          /* from vtx_server_submit */
+    double submit_s;          /* when it was submitted */
+    double launch_s;          /* when its batch was handed to the device */
+    double done_s;            /* when its batch had finished on the device */
+    int32_t batch_size;       /* requests in its batch */
+    int32_t status;           /* VTX_OK or the error code of its batch */
+} vtx_completion;
+
+typedef struct vtx_server_stats {
+    uint64_t submitted, completed, queued;
+    uint64_t batches;         /* batches launched */
+    uint64_t max_batch_seen;  /* largest batch so far */
+    uint64_t failed;          /* requests completed with an error */
+} vtx_server_stats;
+
+/* vtx_clock_s - the monotonic host clock of the server's timestamps, seconds. */
+double vtx_clock_s(void);
+/* vtx_server_create - starts a server rendering in `ctx` on `stream` (current
+ * device).  max_batch 1..4096, max_inflight 1..64; VTX_EINVAL otherwise. */
+int vtx_server_create(vtx_context* ctx, int32_t max_batch, int32_t max_inflight, void* stream, vtx_server** out);
+/* vtx_server_submit - queues one request (thread-safe; returns at once).
+ * A job that fails vtx_check_job is refused with its error code. */
+int vtx_server_submit(vtx_server* server, const vtx_job* job, uint64_t* ticket);
+/* vtx_server_poll - moves up to `max` completions to `out` (*n of them),
+ * waiting up to wait_ms for the first when none is ready. */
+int vtx_server_poll(vtx_server* server, vtx_completion* out, int32_t max, int32_t wait_ms, int32_t* n);
+/* vtx_server_drain - waits until every submitted request has completed. */
+int vtx_server_drain(vtx_server* server);
+/* vtx_server_stats_read - counters of the server. */
+int vtx_server_stats_read(vtx_server* server, vtx_server_stats* out);
+/* vtx_server_destroy - renders what is queued, waits for it, stops the worker. */
+void vtx_server_destroy(vtx_server* server);
 
 /*
  * vtx_read_stats - waits for `stream` to drain, then returns the counters of

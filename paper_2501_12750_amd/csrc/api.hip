@@ -64,6 +64,8 @@ struct Bins {
     Counters* host_ctr = nullptr;       // host view of the mapped counters
     uint64_t want_capacity = 0;
     uint64_t pending_capacity = 0;
+    uint64_t pending_uid = 0;       // resident scene of the render queued in this slot (0: none)
+    int pending_w = 0, pending_h = 0;
     bool dirty = true;              // tile counts / counters must be zeroed before the next frame
     // (primitives, width, height) of the renders the lists were sized for,
     // most recent last; the lists only grow, so a render of a known size
@@ -107,6 +109,26 @@ struct Workspace {
 
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
+// Largest (primitive, tile) pair count seen per resident scene and image
+// size: a slot that meets a known scene and size sizes its lists from it
+// instead of waiting for the frame's count (serving many scenes in
+// alternation).  Keyed by the scenes' unique ids; guarded by g_mu.
+std::map<uint64_t, std::map<std::pair<int, int>, uint64_t>> g_pairs_seen;
+uint64_t g_next_scene_uid = 1;
+
+void note_pairs(uint64_t uid, int w, int h, uint64_t pairs) {
+    if (!uid) return;
+    uint64_t& v = g_pairs_seen[uid][{w, h}];
+    if (pairs > v) v = pairs;
+}
+
+uint64_t seen_pairs(uint64_t uid, int w, int h) {
+    if (!uid) return 0;
+    auto it = g_pairs_seen.find(uid);
+    if (it == g_pairs_seen.end()) return 0;
+    auto jt = it->second.find({w, h});
+    return jt == it->second.end() ? 0 : jt->second;
+}
 
 constexpr uint64_t kMaxCapacity = 1ull << 28;        // bin entries (8 GiB of 32-byte records)
 constexpr uint64_t kMinCapacity = 1ull << 20;
@@ -171,6 +193,7 @@ void harvest(Workspace* ws) {
         s.overflow_tiles += c.overflow_tiles;
         s.bin_capacity += b->pending_capacity;
         s.bad_bonds += c.bad_bonds;
+        note_pairs(b->pending_uid, b->pending_w, b->pending_h, c.pairs);
         if (c.pairs > b->bb.capacity && !ws->fixed_capacity) {
             uint64_t want = c.pairs + c.pairs / 2 + 1024;
             if (want > kMaxCapacity) want = kMaxCapacity;
@@ -480,6 +503,7 @@ struct SceneFrame {
 
 struct vtx_scene {
     vtx_context* ctx = nullptr;
+    uint64_t uid = 0;        // unique per scene of the process
     int device = 0;
     int64_t n = 0, m = 0;
     uint32_t bad_bonds = 0;
@@ -582,6 +606,7 @@ struct JobDesc {
     const uint32_t* col;
     const uint32_t* bonds;
     bool scene;
+    uint64_t scene_uid;
     vtx::SceneDev S;
     float* depth;
     uint32_t* id;
@@ -695,7 +720,20 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
             chunk = (uint32_t)((cpw ? cpw : 1) * vtx::kCluster);
         }
         Bins* b = ws->slots[i];
+        if (!ws->fixed_capacity && !b->was_sized(nprim, s.F.W, s.F.H)) {
+            // a scene and image size counted before: size from that count
+            const uint64_t seen = seen_pairs(s.scene_uid, s.F.W, s.F.H);
+            if (seen) {
+                uint64_t want = seen + seen / 2 + 1024;
+                if (want > kMaxCapacity) want = kMaxCapacity;
+                if (want > b->want_capacity) b->want_capacity = want;
+                b->mark_sized(nprim, s.F.W, s.F.H);
+            }
+        }
         if ((rc = ensure_bins(ws, b, T, nprim, groups, chunk, nc))) return rc;
+        b->pending_uid = s.scene_uid;
+        b->pending_w = s.F.W;
+        b->pending_h = s.F.H;
         b->dirty = true;   // until the resolve that re-zeroes the tile counts is queued
         J.bb = b->bb;
         if (s.scene) {
@@ -778,6 +816,7 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
                 }
                 b->bb.capacity = b->want_capacity;
                 b->mark_sized(nprims[i], d[i].F.W, d[i].F.H);
+                note_pairs(d[i].scene_uid, d[i].F.W, d[i].F.H, counted[i]);
                 jobs[i].bb.list = b->bb.list;
                 jobs[i].bb.capacity = b->bb.capacity;
             }
@@ -950,6 +989,10 @@ int vtx_scene_create(vtx_context* ctx, const float* positions, const float* radi
     hipStream_t st = (hipStream_t)stream;
     vtx_scene* sc = new vtx_scene();
     sc->ctx = ctx;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        sc->uid = g_next_scene_uid++;
+    }
     sc->device = dev;
     sc->n = n_atoms;
     sc->m = n_bonds;
@@ -1077,6 +1120,10 @@ int vtx_scene_info(const vtx_scene* scene, int64_t* n_atoms, int64_t* n_bonds, u
 void vtx_scene_destroy(vtx_scene* scene) {
     if (!scene) return;
     (void)hipDeviceSynchronize();
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_pairs_seen.erase(scene->uid);
+    }
     scene_free(scene);
     if (scene->ctx) {
         std::lock_guard<std::mutex> lk(scene->ctx->mu);
@@ -1098,12 +1145,26 @@ int vtx_render_scene(vtx_scene* scene, const vtx_camera* cam, const vtx_options*
     if (dev != scene->device) return fail(VTX_EINVAL, "scene lives on device %d, current is %d", scene->device, dev);
     std::vector<JobDesc> d{plain_desc(F, o, scene->pos, scene->rad, scene->col, scene->bonds)};
     d[0].scene = true;
+    d[0].scene_uid = scene->uid;
     d[0].S = scene->S;
     d[0].depth = depth;
     d[0].id = id;
     d[0].rgba = rgba;
     std::lock_guard<std::mutex> lk(g_mu);
     return render_locked(d, true, true, (hipStream_t)stream);
+}
+
+int vtx_check_job(const vtx_context* ctx, const vtx_job* j) {
+    if (!j) return fail(VTX_EINVAL, "job is NULL");
+    const vtx_scene* sc = j->scene;
+    if (!sc) return fail(VTX_EINVAL, "scene is NULL");
+    if (ctx && sc->ctx != ctx) return fail(VTX_EINVAL, "scene belongs to another context");
+    if (j->frame < 0 || j->frame > (int32_t)sc->frames.size())
+        return fail(VTX_EINVAL, "frame %d not in 0..%zu", j->frame, sc->frames.size());
+    if (!j->rgba || !j->depth || !j->id) return fail(VTX_EINVAL, "rgba/depth/id outputs are NULL");
+    const vtx_options o = resolve_options(&j->options);
+    Frame F;
+    return make_frame(&j->camera, o, j->width, j->height, sc->n, sc->m, &F);
 }
 
 int vtx_render_batch(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, void* stream) {
@@ -1132,6 +1193,7 @@ int vtx_render_batch(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, void
         scene_frame(sc, j.frame, &S, &pos);
         d[(size_t)i] = plain_desc(F, o, pos, sc->rad, sc->col, sc->bonds);
         d[(size_t)i].scene = true;
+        d[(size_t)i].scene_uid = sc->uid;
         d[(size_t)i].S = S;
         d[(size_t)i].depth = j.depth;
         d[(size_t)i].id = j.id;

@@ -161,15 +161,22 @@ def greedy_bonds(pos32: np.ndarray, cutoff=1.6, max_degree=4) -> np.ndarray:
     dist = np.linalg.norm(p[lo] - p[hi], axis=1)
     order = np.lexsort((hi, lo, dist))
     lo, hi = lo[order], hi[order]
-    deg = np.zeros(p.shape[0], dtype=np.int32)
-    keep = np.zeros(lo.size, dtype=bool)
-    lo_l, hi_l = lo.tolist(), hi.tolist()
-    for k in range(len(lo_l)):
-        a, b = lo_l[k], hi_l[k]
-        if deg[a] < max_degree and deg[b] < max_degree:
-            deg[a] += 1
-            deg[b] += 1
-            keep[k] = True
+    # An atom with at most max_degree candidate pairs never reaches the cap
+    # before its last one, so only pairs touching a "hot" atom (more
+    # candidates than the cap) can be refused, and only by a hot endpoint's
+    # degree: the greedy pass runs over those pairs alone, in order.
+    cand = np.bincount(np.concatenate([lo, hi]), minlength=p.shape[0])
+    hot = cand > max_degree
+    contested = np.flatnonzero(hot[lo] | hot[hi])
+    keep = np.ones(lo.size, dtype=bool)
+    deg = {}
+    for k, a, b in zip(contested.tolist(), lo[contested].tolist(), hi[contested].tolist()):
+        da, db = deg.get(a, 0), deg.get(b, 0)
+        if da < max_degree and db < max_degree:
+            deg[a] = da + 1
+            deg[b] = db + 1
+        else:
+            keep[k] = False
     out = np.stack([lo[keep], hi[keep]], axis=1)
     out = out[np.lexsort((out[:, 1], out[:, 0]))]      # listed in atom order, like a topology
     return np.ascontiguousarray(out.astype(np.uint32))
@@ -277,3 +284,85 @@ WORKLOADS = {
     "ball_and_stick": ball_and_stick,
     "whole_cell": whole_cell,
 }
+
+
+# ---------------------------------------------------------------------------
+# Served mix: many clients, each a session of consecutive frames of one scene.
+# ---------------------------------------------------------------------------
+SERVE_RESOLUTIONS = ((1280, 720), (1920, 1080), (3840, 2160))
+
+
+@dataclasses.dataclass
+class ServedScene:
+    """One scene of the served pool: vdW spheres (the whole-cell generator
+    scaled to n atoms at the same density) or ball-and-stick globules of 500
+    atoms (the ball-and-stick generator)."""
+    kind: str
+    n_atoms: int
+    seed: int
+
+    def build(self):
+        """Returns (scene, centre, radius of the sphere around the centre that
+        holds 99.9% of the atoms)."""
+        if self.kind == "ball_and_stick":
+            wl = ball_and_stick(n_globules=max(1, self.n_atoms // 500), seed=self.seed)
+        else:
+            s = (self.n_atoms / 1e8) ** (1.0 / 3.0)
+            wl = whole_cell(n_atoms=self.n_atoms, box=5000.0 * s, r_min=300.0 * s, r_max=900.0 * s,
+                            seed=self.seed, eye_clearance=0.0)
+        p = wl.scene.positions.astype(np.float64)
+        c = p.mean(axis=0)
+        r999 = float(np.percentile(np.linalg.norm(p - c, axis=1), 99.9))
+        return wl.scene, c, r999
+
+
+@dataclasses.dataclass
+class ServedRequest:
+    t: float                 # arrival time, seconds from the start
+    session: int
+    scene: int               # index into the pool
+    frame: int               # frame of the session (0, 1, ...)
+    width: int
+    height: int
+    angle: float             # orbit angle of the camera, radians
+
+
+def orbit_camera(centre, radius, angle, fovy_deg=45.0) -> Camera:
+    """Camera on a horizontal circle around `centre`, far enough that a
+    sphere of `radius` fits the vertical field of view."""
+    dist = radius / math.sin(math.radians(fovy_deg) / 2)
+    eye = (centre[0] + dist * math.sin(angle), centre[1], centre[2] + dist * math.cos(angle))
+    return Camera(eye=eye, target=tuple(centre), fovy=math.radians(fovy_deg))
+
+
+def served_mix(duration_s=60.0, rate_hz=200.0, n_scenes=24, n_min=1e4, n_max=1e7, mean_session=8.0,
+               frame_interval_s=1.0 / 30.0, degrees_per_frame=2.0, seed=5):
+    """A seeded arrival schedule: sessions start as a Poisson process of rate
+    rate_hz / mean_session; each lasts a geometric number of frames (mean
+    mean_session) requested every frame_interval_s on one scene of the pool
+    (n log-uniform in [n_min, n_max], vdW and ball-and-stick alternately), at
+    one resolution (uniform over 720p, 1080p, 4K), with the camera orbiting
+    the scene.  Returns (pool, requests sorted by arrival)."""
+    rng = np.random.default_rng(seed)
+    pool = []
+    for k in range(n_scenes):
+        n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        pool.append(ServedScene("vdw" if k % 2 == 0 else "ball_and_stick", n, 100 + k))
+    reqs = []
+    t, sid = 0.0, 0
+    while True:
+        t += rng.exponential(mean_session / rate_hz)
+        if t >= duration_s:
+            break
+        length = int(rng.geometric(1.0 / mean_session))
+        scene = int(rng.integers(n_scenes))
+        W, H = SERVE_RESOLUTIONS[int(rng.integers(len(SERVE_RESOLUTIONS)))]
+        a0 = float(rng.uniform(0.0, 2.0 * math.pi))
+        for f in range(length):
+            tf = t + f * frame_interval_s
+            if tf >= duration_s:
+                break
+            reqs.append(ServedRequest(tf, sid, scene, f, W, H, a0 + math.radians(degrees_per_frame) * f))
+        sid += 1
+    reqs.sort(key=lambda r: (r.t, r.session))
+    return pool, reqs

@@ -36,7 +36,9 @@ EXPORTS = ("vtx_render", "vtx_gbuffer", "vtx_shade", "vtx_read_stats", "vtx_set_
            "vtx_context_create", "vtx_context_destroy", "vtx_context_bytes_in_use", "vtx_scene_footprint_bytes",
            "vtx_frame_scratch_bytes", "vtx_scene_create", "vtx_scene_update_positions", "vtx_scene_info",
            "vtx_scene_destroy", "vtx_render_scene", "vtx_scene_add_frames", "vtx_scene_frames",
-           "vtx_scene_frame_bytes", "vtx_render_batch", "vtx_autotune")
+           "vtx_scene_frame_bytes", "vtx_render_batch", "vtx_autotune", "vtx_clock_s", "vtx_server_create",
+           "vtx_server_submit", "vtx_server_poll", "vtx_server_drain", "vtx_server_stats_read",
+           "vtx_server_destroy", "vtx_check_job")
 
 
 class vtx_camera(ctypes.Structure):
@@ -83,6 +85,19 @@ class vtx_tuning(ctypes.Structure):
                 "ms_per_batch": float(self.ms_per_batch),
                 "ms_by_tile": {t: float(v) for t, v in zip((8, 16, 32, 64), self.ms_by_tile) if v > 0},
                 "key": self.key.decode()}
+
+
+class vtx_completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("submit_s", ctypes.c_double), ("launch_s", ctypes.c_double),
+                ("done_s", ctypes.c_double), ("batch_size", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
+class vtx_server_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "queued", "batches", "max_batch_seen",
+                                               "failed")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class VtxError(RuntimeError):
@@ -149,6 +164,22 @@ _lib.vtx_render_batch.restype = ctypes.c_int
 _lib.vtx_render_batch.argtypes = [_P, ctypes.POINTER(vtx_job), _I32, _P]
 _lib.vtx_autotune.restype = ctypes.c_int
 _lib.vtx_autotune.argtypes = [_P, ctypes.POINTER(vtx_job), _I32, ctypes.c_char_p, _P, ctypes.POINTER(vtx_tuning)]
+_lib.vtx_check_job.restype = ctypes.c_int
+_lib.vtx_check_job.argtypes = [_P, ctypes.POINTER(vtx_job)]
+_lib.vtx_clock_s.restype = ctypes.c_double
+_lib.vtx_clock_s.argtypes = []
+_lib.vtx_server_create.restype = ctypes.c_int
+_lib.vtx_server_create.argtypes = [_P, _I32, _I32, _P, ctypes.POINTER(_P)]
+_lib.vtx_server_submit.restype = ctypes.c_int
+_lib.vtx_server_submit.argtypes = [_P, ctypes.POINTER(vtx_job), ctypes.POINTER(ctypes.c_uint64)]
+_lib.vtx_server_poll.restype = ctypes.c_int
+_lib.vtx_server_poll.argtypes = [_P, ctypes.POINTER(vtx_completion), _I32, _I32, ctypes.POINTER(_I32)]
+_lib.vtx_server_drain.restype = ctypes.c_int
+_lib.vtx_server_drain.argtypes = [_P]
+_lib.vtx_server_stats_read.restype = ctypes.c_int
+_lib.vtx_server_stats_read.argtypes = [_P, ctypes.POINTER(vtx_server_stats)]
+_lib.vtx_server_destroy.restype = None
+_lib.vtx_server_destroy.argtypes = [_P]
 _lib.vtx_last_error.restype = ctypes.c_char_p
 _lib.vtx_last_error.argtypes = []
 _lib.vtx_version.restype = ctypes.c_char_p
@@ -344,6 +375,50 @@ def vtx_autotune(ctx, jobs, cache_path=None, stream=None) -> dict:
     path = None if cache_path is None else os.fsencode(cache_path)
     _check(_lib.vtx_autotune(ctx, arr, len(arr), path, _stream(stream), ctypes.byref(t)))
     return t.as_dict()
+
+
+def vtx_clock_s() -> float:
+    return float(_lib.vtx_clock_s())
+
+
+def vtx_server_create(ctx, max_batch=64, max_inflight=2, stream=None) -> int:
+    h = _P()
+    rc = _lib.vtx_server_create(ctx, int(max_batch), int(max_inflight), _stream(stream), ctypes.byref(h))
+    if rc != VTX_OK:
+        raise VtxError(rc, "vtx_server_create: bad arguments")
+    return h.value
+
+
+def vtx_check_job(ctx, job):
+    _check(_lib.vtx_check_job(ctx, ctypes.byref(job)))
+
+
+def vtx_server_submit(server, job) -> int:
+    t = ctypes.c_uint64()
+    _check(_lib.vtx_server_submit(server, ctypes.byref(job), ctypes.byref(t)))
+    return t.value
+
+
+def vtx_server_poll(server, max_items=256, wait_ms=0) -> list:
+    buf = (vtx_completion * max(1, max_items))()
+    n = _I32()
+    _check(_lib.vtx_server_poll(server, buf, int(max_items), int(wait_ms), ctypes.byref(n)))
+    return [{"ticket": c.ticket, "submit_s": c.submit_s, "launch_s": c.launch_s, "done_s": c.done_s,
+             "batch_size": c.batch_size, "status": c.status} for c in buf[:n.value]]
+
+
+def vtx_server_drain(server):
+    _check(_lib.vtx_server_drain(server))
+
+
+def vtx_server_stats_read(server) -> dict:
+    st = vtx_server_stats()
+    _check(_lib.vtx_server_stats_read(server, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def vtx_server_destroy(server):
+    _lib.vtx_server_destroy(server)
 
 
 def vtx_last_error() -> str:
