@@ -133,7 +133,7 @@ class SingleRunner:
             self.rs = vtx.ResidentScene(self.ctx, self.ds)
             log(f"resident scene built in {time.perf_counter() - t1:.2f} s")
         self.launch_form = "resident scene, vtx_render_scene per frame" if path == "scene" else "vtx_render per frame"
-        self.other_form = "vtx_render per frame (caller's arrays)" if path == "scene" else None
+        self.other_forms = [("vtx_render per frame (caller's arrays)", self.other_step)] if path == "scene" else []
 
     def step(self, flags=0):
         r = self.renders[0]
@@ -180,8 +180,11 @@ class BatchRunner:
                 W, H = viewports[k]
                 self.renders.append(Render(vtx, f, cams[k], opts, W, H))
         self.arrays = {}
-        self.launch_form = f"vtx_render_batch of {len(self.renders)} renders per step"
-        self.other_form = "one vtx_render_batch call per render (single-render launches)"
+        self.graph = vtx.vtx_batch_graph_create(self.ctx, self.jobs(0)[0])
+        self.launch_form = (f"hipGraph of the {len(self.renders)}-render batch (vtx_batch_graph_launch: one graph "
+                            f"launch per step)")
+        self.other_forms = [("vtx_render_batch of the same renders, launched eagerly", self.eager_step),
+                            ("one vtx_render_batch call per render (single-render launches)", self.per_render_step)]
 
     def jobs(self, flags):
         if flags not in self.arrays:
@@ -193,9 +196,15 @@ class BatchRunner:
         return self.arrays[flags]
 
     def step(self, flags=0):
-        self.vtx.vtx_render_batch(self.ctx, self.jobs(flags)[0], self.stream)
+        if flags == 0:
+            self.vtx.vtx_batch_graph_launch(self.graph, self.stream)
+        else:   # statistics and per-kernel events run the same kernels eagerly
+            self.vtx.vtx_render_batch(self.ctx, self.jobs(flags)[0], self.stream)
 
-    def other_step(self):
+    def eager_step(self):
+        self.vtx.vtx_render_batch(self.ctx, self.jobs(0)[0], self.stream)
+
+    def per_render_step(self):
         for one in self.jobs(0)[1]:
             self.vtx.vtx_render_batch(self.ctx, one, self.stream)
 
@@ -203,6 +212,7 @@ class BatchRunner:
         return self.vtx.vtx_autotune(self.ctx, self.jobs(0)[0], cache, self.stream)
 
     def close(self):
+        self.vtx.vtx_batch_graph_destroy(self.graph)
         self.rs.close()
         self.vtx.vtx_context_destroy(self.ctx)
 
@@ -539,20 +549,20 @@ def main():
         lat.append((time.perf_counter() - a) * 1e3)
     lat = np.array(lat)
 
-    other = None
-    if args.compare and runner.other_form:
+    other = []
+    for form, fn in (runner.other_forms if args.compare else []):
         for _ in range(max(1, warmup)):
-            runner.other_step()
+            fn()
         torch.cuda.synchronize()
         o_steps = max(1, steps // 2) if batch else steps
         a = time.perf_counter()
         for _ in range(o_steps):
-            runner.other_step()
+            fn()
         torch.cuda.synchronize()
         pe = time.perf_counter() - a
-        other = {"launch": runner.other_form, "frames_per_s": round(o_steps * R / pe, 3),
-                 "ms_per_step": round(pe / o_steps * 1e3, 4)}
-        log(f"other launch form: {other}")
+        other.append({"launch": form, "frames_per_s": round(o_steps * R / pe, 3),
+                      "ms_per_step": round(pe / o_steps * 1e3, 4)})
+        log(f"other launch form: {other[-1]}")
 
     # roofline of each kernel (per step = sums over the step's renders); the
     # dominant one goes in the JSON's roofline
@@ -605,7 +615,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": config,
-        "other_launch_form": other,
+        "other_launch_forms": other,
         "atom_fragments_per_s": round(f_total * steps / elapsed, 1),
         "atom_fragments_per_step": f_total,
         "latency_ms": ({"p50": round(float(np.percentile(lat, 50)), 4),

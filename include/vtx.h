@@ -291,6 +291,25 @@ int vtx_check_job(const vtx_context* ctx, const vtx_job* job);
  */
 int vtx_render_batch(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, void* stream);
 
+/*
+ * Batch graphs: a batch of jobs captured once into a hipGraph and replayed
+ * with one hipGraphLaunch per call (the trajectory player's case: the same
+ * renders re-run every step, e.g. after vtx_scene_update_positions or with
+ * new frames written in place).  vtx_batch_graph_create checks the jobs as
+ * vtx_render_batch does, renders them once on a private stream to size a
+ * private scratch, then captures the launch sequence (no allocation, copy or
+ * wait is captured).  Each vtx_batch_graph_launch re-renders exactly those
+ * jobs (same scenes, frames, cameras, options and output images), queued on
+ * `stream`; the scenes and images must outlive the graph, and launches of one
+ * graph must not overlap (queue them on one stream).  VTX_FLAG_TIMING is
+ * ignored inside a graph.
+ */
+typedef struct vtx_batch_graph vtx_batch_graph;
+int vtx_batch_graph_create(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, vtx_batch_graph** out);
+int vtx_batch_graph_launch(vtx_batch_graph* graph, void* stream);
+/* vtx_batch_graph_destroy - waits for the device and frees the graph and its scratch. */
+void vtx_batch_graph_destroy(vtx_batch_graph* graph);
+
 /* Result of vtx_autotune. */
 typedef struct vtx_tuning {
     int32_t tile_size;        /* chosen screen tile edge (8, 16, 32 or 64) */

@@ -99,6 +99,11 @@ struct Workspace {
     int tnext = 0;
     uint64_t tframes = 0;
     double tsum[kMarks - 1] = {};
+    // overflowed tiles of a resolve launch (job << 32 | tile) and its two
+    // counters, left zeroed by every launch
+    unsigned long long* d_ovf = nullptr;
+    size_t ovf_cap = 0;
+    uint32_t* d_ovf_n = nullptr;
     // job tables of batched launches: device copy and pinned staging
     char* d_tab = nullptr;
     char* h_tab = nullptr;
@@ -137,7 +142,7 @@ void bins_free(Bins* b) {
     hipFree(b->bb.tile_cnt);
     hipFree(b->bb.tile_off);
     hipFree(b->bb.tile_fill);
-    hipFree(b->bb.vis_rec);
+    hipFree(b->bb.vis_src);
     hipFree(b->bb.vis_rect);
     hipFree(b->bb.vis_cnt);
     hipFree(b->bb.vis_box);
@@ -300,9 +305,9 @@ int ensure_bins(Workspace* ws, Bins* b, int T, uint64_t nprim, uint32_t groups, 
     b->bb.groups = groups;
     b->bb.chunk = chunk;
     const size_t nv = (size_t)groups * chunk;
-    if (nv > b->vis_cap || !b->bb.vis_rec) {
+    if (nv > b->vis_cap || !b->bb.vis_src) {
         size_t c1 = b->vis_cap, c2 = b->vis_cap;
-        if ((rc = grow(&b->bb.vis_rec, c1, nv, st, "visible records"))) return rc;
+        if ((rc = grow(&b->bb.vis_src, c1, nv, st, "visible sources"))) return rc;
         if ((rc = grow(&b->bb.vis_rect, c2, nv, st, "visible rectangles"))) return rc;
         b->vis_cap = nv;
     }
@@ -335,6 +340,19 @@ int ensure_bins(Workspace* ws, Bins* b, int T, uint64_t nprim, uint32_t groups, 
     return VTX_OK;
 }
 
+size_t xcd_round(uint32_t n) { return ((size_t)n + 7) / 8 * 8; }
+
+template <class T>
+int dev_alloc_zeroed(T** p, size_t count, hipStream_t stream) {
+    if (hipMalloc(p, count * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(VTX_ENOMEM, "cannot allocate %zu bytes", count * sizeof(T));
+    }
+    VTX_HIP(vtx::launch_zero(reinterpret_cast<uint32_t*>(*p), count * sizeof(T) / sizeof(uint32_t), stream));
+    return VTX_OK;
+}
+
 void workspace_free(Workspace* ws) {
     for (Bins* b : ws->slots) bins_free(b);
     ws->slots.clear();
@@ -345,6 +363,8 @@ void workspace_free(Workspace* ws) {
     }
     hipFree(ws->d_tab);
     hipHostFree(ws->h_tab);
+    hipFree(ws->d_ovf);
+    hipFree(ws->d_ovf_n);
     hipEventDestroy(ws->done);
     hipEventDestroy(ws->staged);
     delete ws;
@@ -415,6 +435,8 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
     F->ihy = 1.0 / F->hy;
     F->txf = (float)F->tx;
     F->tyf = (float)F->ty;
+    F->itxf = (float)F->itx;
+    F->ityf = (float)F->ity;
     F->sxf = (float)std::sqrt(1.0 + F->tx * F->tx) * (1.0f + 1e-6f);
     F->syf = (float)std::sqrt(1.0 + F->ty * F->ty) * (1.0f + 1e-6f);
     F->hxf = (float)F->hx;
@@ -656,11 +678,18 @@ int upload_tables(Workspace* ws, const std::vector<vtx::Job>& jobs, const std::v
 // depth/id when `bin`, the deferred pass into its rgba when `shade`.  One
 // render launches with its job in the kernel arguments; several launch each
 // kernel once over all of them, from device tables.  Caller holds g_mu.
-int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t stream) {
-    Workspace* ws = nullptr;
-    int rc = get_workspace(stream, &ws);
-    if (rc) return rc;
-    harvest(ws);
+//
+// `own`: a workspace of the caller's (a batch graph's private one) instead of
+// the stream's.  `capture`: the launches are being captured into a graph:
+// nothing may allocate, copy or wait, so the scratch must already be sized and
+// the device job tables already hold these jobs (a first, eager call on the
+// same workspace does both); timing events are left out.
+int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t stream, Workspace* own = nullptr,
+                  bool capture = false) {
+    Workspace* ws = own;
+    int rc = VTX_OK;
+    if (!ws && (rc = get_workspace(stream, &ws))) return rc;
+    if (!capture) harvest(ws);
     const size_t n = d.size();
     if (n == 0) return VTX_OK;
     // one resolve launch per tile size: keep the jobs of a size together
@@ -672,7 +701,7 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
         scene |= j.scene;
     }
     hipEvent_t* marks = nullptr;
-    if (timing) {
+    if (timing && !capture) {
         TimingSlot* slot = nullptr;
         if ((rc = timing_slot(ws, &slot))) return rc;
         marks = slot->ev;
@@ -720,6 +749,10 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
             chunk = (uint32_t)((cpw ? cpw : 1) * vtx::kCluster);
         }
         Bins* b = ws->slots[i];
+        if (capture && (b->dirty || !b->was_sized(nprim, s.F.W, s.F.H) || (size_t)T > b->tiles_cap ||
+                        (size_t)groups * chunk > b->vis_cap || (size_t)groups * T > b->hist_cap ||
+                        (nc && (size_t)nc > b->vc_cap)))
+            return fail(VTX_EINVAL, "job %zu: scratch not sized for capture", i);
         if (!ws->fixed_capacity && !b->was_sized(nprim, s.F.W, s.F.H)) {
             // a scene and image size counted before: size from that count
             const uint64_t seen = seen_pairs(s.scene_uid, s.F.W, s.F.H);
@@ -774,7 +807,19 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
         const uint32_t* ds = reinterpret_cast<const uint32_t*>(ws->d_tab + s_off) + start_index;
         return vtx::JobList{dj, dk, ds, (uint32_t)count};
     };
-    if (n > 1 && (rc = upload_tables(ws, jobs, d, starts, &k_off, &s_off))) return rc;
+    if (n > 1 && capture) {
+        // the tables must be the ones the eager call uploaded
+        k_off = align_up(n * sizeof(vtx::Job), 256);
+        s_off = align_up(k_off + n * sizeof(vtx::SampleKernel), 256);
+        const size_t bytes = s_off + starts.size() * sizeof(uint32_t);
+        bool same = ws->h_tab && bytes <= ws->tab_cap && std::memcmp(ws->h_tab, jobs.data(), n * sizeof(vtx::Job)) == 0 &&
+                    std::memcmp(ws->h_tab + s_off, starts.data(), starts.size() * sizeof(uint32_t)) == 0;
+        for (size_t i = 0; same && i < n; ++i)
+            same = std::memcmp(ws->h_tab + k_off + i * sizeof(vtx::SampleKernel), &d[i].K, sizeof(vtx::SampleKernel)) == 0;
+        if (!same) return fail(VTX_EINVAL, "job tables changed between the sizing call and the capture");
+    } else if (n > 1 && (rc = upload_tables(ws, jobs, d, starts, &k_off, &s_off))) {
+        return rc;
+    }
     auto one = [&](uint32_t blocks) {
         vtx::OneJob o;
         o.j = jobs[0];
@@ -783,6 +828,16 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
         return o;
     };
 
+    if (bin) {
+        uint32_t gmax = 0;
+        for (uint32_t gg : groups_grid) gmax = std::max(gmax, gg);
+        if (!ws->d_ovf_n) {
+            if ((rc = dev_alloc_zeroed(&ws->d_ovf_n, 2, stream))) return rc;
+        }
+        if ((size_t)xcd_round(gmax) > ws->ovf_cap || !ws->d_ovf) {
+            if ((rc = grow(&ws->d_ovf, ws->ovf_cap, (size_t)xcd_round(gmax), stream, "overflow tiles"))) return rc;
+        }
+    }
     if (marks) VTX_HIP(hipEventRecord(marks[0], stream));
     if (marks) VTX_HIP(hipEventRecord(marks[1], stream));
     if (bin) {
@@ -800,6 +855,7 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
             const Bins* b = ws->slots[i];
             if (!ws->fixed_capacity && !b->was_sized(nprims[i], d[i].F.W, d[i].F.H)) need.push_back(i);
         }
+        if (!need.empty() && capture) return fail(VTX_EINVAL, "scratch not sized for capture");
         if (!need.empty()) {
             std::vector<unsigned long long> counted(n, 0);
             for (size_t i : need)
@@ -829,9 +885,12 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
         if (marks) VTX_HIP(hipEventRecord(marks[4], stream));
         for (size_t g = 0; g < groups_ts.size(); ++g) {
             const size_t a = groups_ts[g].first, b = groups_ts[g].second;
-            if (n == 1) VTX_HIP(vtx::launch_resolve(one(groups_grid[g]), d[0].F.tile, groups_grid[g], count, stream));
+            if (n == 1)
+                VTX_HIP(vtx::launch_resolve(one(groups_grid[g]), d[0].F.tile, groups_grid[g], count, ws->d_ovf,
+                                            ws->d_ovf_n, stream));
             else
-                VTX_HIP(vtx::launch_resolve(list_of(a, b - a, groups_off[g]), d[a].F.tile, groups_grid[g], count, stream));
+                VTX_HIP(vtx::launch_resolve(list_of(a, b - a, groups_off[g]), d[a].F.tile, groups_grid[g], count,
+                                            ws->d_ovf, ws->d_ovf_n, stream));
         }
         for (size_t i = 0; i < n; ++i) {
             ws->slots[i]->dirty = false;
@@ -840,9 +899,11 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
         // The scatter's first workgroup (and, with statistics on, the
         // resolve's last one) writes each render's counters into its mapped
         // pinned buffer; the host reads them once this event has completed.
-        VTX_HIP(hipEventRecord(ws->done, stream));
-        ws->pending = true;
-        ws->pending_n = (int)n;
+        if (!capture) {
+            VTX_HIP(hipEventRecord(ws->done, stream));
+            ws->pending = true;
+            ws->pending_n = (int)n;
+        }
     } else if (marks) {
         for (int k = 2; k <= 4; ++k) VTX_HIP(hipEventRecord(marks[k], stream));
     }
@@ -963,7 +1024,7 @@ size_t vtx_frame_scratch_bytes(int32_t W, int32_t H, int64_t n_atoms, int64_t n_
     vtx::bin_grid(nprim, &groups, &chunk);
     uint64_t cap = nprim / 2;
     if (cap < kMinCapacity) cap = kMinCapacity;
-    return (size_t)(T * 16 + (uint64_t)groups * chunk * (sizeof(vtx::PrimRec) + sizeof(uint2)) +
+    return (size_t)(T * 16 + (uint64_t)groups * chunk * (sizeof(uint32_t) + sizeof(uint2)) +
                     (uint64_t)groups * T * 4 + cap * sizeof(vtx::PrimRec) + scene_clusters(n_atoms, n_bonds) * 4 +
                     sizeof(Counters) + 4096);
 }
@@ -1167,15 +1228,19 @@ int vtx_check_job(const vtx_context* ctx, const vtx_job* j) {
     return make_frame(&j->camera, o, j->width, j->height, sc->n, sc->m, &F);
 }
 
-int vtx_render_batch(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Checks a batch and builds its render descriptions.
+int build_batch(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, std::vector<JobDesc>& d) {
     if (!ctx) return fail(VTX_EINVAL, "context is NULL");
     if (n_jobs < 0 || n_jobs > kMaxBatch) return fail(VTX_EINVAL, "n_jobs=%d not in 0..%d", n_jobs, kMaxBatch);
-    if (n_jobs == 0) return VTX_OK;
-    if (!jobs) return fail(VTX_EINVAL, "jobs is NULL");
+    if (n_jobs > 0 && !jobs) return fail(VTX_EINVAL, "jobs is NULL");
     int dev = 0;
     VTX_HIP(hipGetDevice(&dev));
     if (dev != ctx->device) return fail(VTX_EINVAL, "current device %d is not the context's %d", dev, ctx->device);
-    std::vector<JobDesc> d((size_t)n_jobs);
+    d.resize((size_t)n_jobs);
     for (int32_t i = 0; i < n_jobs; ++i) {
         const vtx_job& j = jobs[i];
         const vtx_scene* sc = j.scene;
@@ -1199,8 +1264,105 @@ int vtx_render_batch(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, void
         d[(size_t)i].id = j.id;
         d[(size_t)i].rgba = j.rgba;
     }
+    return VTX_OK;
+}
+
+}  // namespace
+
+struct vtx_batch_graph {
+    vtx_context* ctx = nullptr;
+    int device = 0;
+    hipStream_t cap = nullptr;       // private stream the batch was sized on and captured from
+    Workspace* ws = nullptr;         // private scratch the graph's kernels use
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int vtx_render_batch(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, void* stream) {
+    std::vector<JobDesc> d;
+    int rc = build_batch(ctx, jobs, n_jobs, d);
+    if (rc) return rc;
+    if (d.empty()) return VTX_OK;
     std::lock_guard<std::mutex> lk(g_mu);
     return render_locked(d, true, true, (hipStream_t)stream);
+}
+
+void vtx_batch_graph_destroy(vtx_batch_graph* g) {
+    if (!g) return;
+    if (g->cap) (void)hipStreamSynchronize(g->cap);
+    (void)hipDeviceSynchronize();   // replays on other streams may still run
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    if (g->ws) workspace_free(g->ws);
+    if (g->cap) hipStreamDestroy(g->cap);
+    delete g;
+}
+
+int vtx_batch_graph_create(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, vtx_batch_graph** out) {
+    if (!out) return fail(VTX_EINVAL, "out is NULL");
+    std::vector<JobDesc> d;
+    int rc = build_batch(ctx, jobs, n_jobs, d);
+    if (rc) return rc;
+    if (d.empty()) return fail(VTX_EINVAL, "a batch graph needs at least one job");
+    for (JobDesc& j : d) j.F.flags &= ~VTX_FLAG_TIMING;
+    vtx_batch_graph* g = new vtx_batch_graph();
+    g->ctx = ctx;
+    VTX_HIP(hipGetDevice(&g->device));
+    if (hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        delete g;
+        return fail(VTX_EHIP, "cannot create the capture stream");
+    }
+    g->ws = new Workspace();
+    g->ws->device = g->device;
+    g->ws->stream = g->cap;
+    if (hipEventCreateWithFlags(&g->ws->done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ws->staged, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        vtx_batch_graph_destroy(g);
+        return fail(VTX_EHIP, "cannot create events");
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        // an eager run sizes the private scratch and uploads the job tables
+        std::vector<JobDesc> d0 = d;
+        rc = render_locked(d0, true, true, g->cap, g->ws, false);
+        if (rc == VTX_OK && hipStreamSynchronize(g->cap) != hipSuccess) rc = fail(VTX_EHIP, "sizing run failed");
+        if (rc == VTX_OK) {
+            if (hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                (void)hipGetLastError();
+                rc = fail(VTX_EHIP, "hipStreamBeginCapture failed");
+            } else {
+                std::vector<JobDesc> d1 = d;
+                rc = render_locked(d1, true, true, g->cap, g->ws, true);
+                hipGraph_t graph = nullptr;
+                const hipError_t e = hipStreamEndCapture(g->cap, &graph);
+                g->graph = graph;
+                if (rc == VTX_OK && e != hipSuccess) rc = fail(VTX_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            }
+        }
+    }
+    if (rc == VTX_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = fail(VTX_EHIP, "hipGraphInstantiate failed");
+    }
+    if (rc != VTX_OK) {
+        vtx_batch_graph_destroy(g);
+        return rc;
+    }
+    *out = g;
+    return VTX_OK;
+}
+
+int vtx_batch_graph_launch(vtx_batch_graph* g, void* stream) {
+    if (!g || !g->exec) return fail(VTX_EINVAL, "graph is NULL");
+    int dev = 0;
+    VTX_HIP(hipGetDevice(&dev));
+    if (dev != g->device) return fail(VTX_EINVAL, "graph lives on device %d, current is %d", g->device, dev);
+    VTX_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return VTX_OK;
 }
 
 int vtx_autotune(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, const char* cache_path, void* stream,

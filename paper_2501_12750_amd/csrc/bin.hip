@@ -19,7 +19,7 @@
 // capacity are left empty; the resolve pass then finds those tiles' primitives
 // in the per-workgroup visible lists, so every frame is exact whatever the
 // capacity.
-#include "vtx_internal.h"
+#include "prims.h"
 
 namespace vtx {
 
@@ -31,54 +31,11 @@ __global__ void __launch_bounds__(kBlock) k_zero(uint32_t* p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
 }
 
-// View-space record and footprint of a sphere (id = primitive id); false if
-// it cannot show.  The FP32 frustum test rejects most off-screen spheres
-// before the exact FP64 footprint.
-__device__ inline bool sphere_record(const Frame& F, double vx, double vy, double vz, double r, uint32_t id, int& x0,
-                                     int& y0, int& x1, int& y1, PrimRec& rec) {
-    if (!(r > 0.0) || !sphere_in_frustum(F, vx, vy, vz, r)) return false;
-    rec.g0 = make_float4((float)vx, (float)vy, (float)vz, (float)r);
-    rec.g1 = make_uint4(0u, 0u, id, 0u);
-    return sphere_rect(F, vx, vy, vz, r, x0, y0, x1, y1);
-}
-
-// Same for a bond between view points A and B (the difference B - A is kept
-// from FP64, so the axis is accurate however far the bond is).
-__device__ inline bool bond_record(const Frame& F, const double* A, const double* B, uint32_t id, int& x0, int& y0,
-                                   int& x1, int& y1, PrimRec& rec) {
-    const double rho = F.bond_radius;
-    const double dx = B[0] - A[0], dy = B[1] - A[1], dz = B[2] - A[2];
-    const double half = 0.5 * sqrt(dx * dx + dy * dy + dz * dz);
-    if (!sphere_in_frustum(F, A[0] + 0.5 * dx, A[1] + 0.5 * dy, A[2] + 0.5 * dz, half + rho)) return false;
-    rec.g0 = make_float4((float)A[0], (float)A[1], (float)A[2], (float)dx);
-    rec.g1 = make_uint4(__float_as_uint((float)dy), __float_as_uint((float)dz), id, 0u);
-    return bond_rect(F, A, B, rho, x0, y0, x1, y1);
-}
-
-// Raw inputs of one item of a binning workgroup, loaded one loop iteration
-// ahead of its processing so the loads overlap the previous item's math.
-struct Item {
-    float4 a;          // atom: centre and radius | bond: end A (w unused)
-    float4 b;          // bond: end B
-    uint32_t id;       // primitive id
-    uint32_t kind;     // kNone, kAtom, kBond, kBadBond
-};
-constexpr uint32_t kNone = 0, kAtom = 1, kBond = 2, kBadBond = 3;
-
-// Footprint and view-space record of a fetched item; false if it cannot show.
-__device__ inline bool item_record(const Frame& F, const Item& it, int& x0, int& y0, int& x1, int& y1,
-                                   PrimRec& rec) {
-    if (it.kind == kAtom) {
-        double vx, vy, vz;
-        to_view(F, it.a.x, it.a.y, it.a.z, vx, vy, vz);
-        return sphere_record(F, vx, vy, vz, (double)it.a.w, it.id, x0, y0, x1, y1, rec);
-    }
-    if (it.kind != kBond) return false;
-    if (it.a.x == it.b.x && it.a.y == it.b.y && it.a.z == it.b.z) return false;
-    double A[3], B[3];
-    to_view(F, it.a.x, it.a.y, it.a.z, A[0], A[1], A[2]);
-    to_view(F, it.b.x, it.b.y, it.b.z, B[0], B[1], B[2]);
-    return bond_record(F, A, B, it.id, x0, y0, x1, y1, rec);
+// Footprint of a visible item (its view coordinates from item_view).
+__device__ inline bool item_rect(const Frame& F, const Item& it, const double* v, double r, int& x0, int& y0,
+                                 int& x1, int& y1) {
+    if (it.kind == kAtom) return sphere_rect_fast(F, v[0], v[1], v[2], r, x0, y0, x1, y1);
+    return bond_rect(F, v, v + 3, r, x0, y0, x1, y1);
 }
 
 // Primitive sources of the count kernel.  Workgroup b owns items
@@ -97,32 +54,7 @@ struct PlainSource {     // the caller's arrays, primitives in their given order
         count = first < total ? min((uint64_t)chunk, total - first) : 0;
     }
     __device__ uint64_t items() const { return count; }
-    __device__ Item fetch(uint64_t k) const {
-        Item it;
-        const uint64_t p = first + k;
-        it.id = (uint32_t)p;
-        it.b = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (p < n_atoms) {
-            it.a = make_float4(pos[3 * p], pos[3 * p + 1], pos[3 * p + 2], rad[p]);
-            it.kind = kAtom;
-            return it;
-        }
-        const size_t bi = p - n_atoms;
-        const uint32_t ia = bonds[2 * bi], ib = bonds[2 * bi + 1];
-        it.a = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (ia >= n_atoms || ib >= n_atoms) {
-            it.kind = kBadBond;
-            return it;
-        }
-        if (ia == ib) {
-            it.kind = kNone;
-            return it;
-        }
-        it.a = make_float4(pos[3 * (size_t)ia], pos[3 * (size_t)ia + 1], pos[3 * (size_t)ia + 2], 0.f);
-        it.b = make_float4(pos[3 * (size_t)ib], pos[3 * (size_t)ib + 1], pos[3 * (size_t)ib + 2], 0.f);
-        it.kind = kBond;
-        return it;
-    }
+    __device__ Item fetch(uint64_t k) const { return fetch_plain(pos, rad, bonds, n_atoms, first + k); }
 };
 
 struct SceneSource {     // a resident scene: the clusters that passed the frustum test
@@ -138,30 +70,14 @@ struct SceneSource {     // a resident scene: the clusters that passed the frust
     }
     __device__ uint64_t items() const { return (uint64_t)(c1 - c0) * kCluster; }
     __device__ Item fetch(uint64_t k) const {
-        Item it;
-        it.kind = kNone;
-        it.id = 0;
-        it.a = make_float4(0.f, 0.f, 0.f, 0.f);
-        it.b = it.a;
         const uint32_t c = S.vis_clusters[c0 + (uint32_t)(k / kCluster)];
         const uint32_t slot = (uint32_t)(k % kCluster);
         if (c < S.atom_clusters) {
             const uint32_t i = c * kCluster + slot;
-            if (i >= S.n_atoms) return it;
-            it.a = S.xyzr[i];
-            it.id = S.atom_id[i];
-            it.kind = kAtom;
-            return it;
+            return i < S.n_atoms ? fetch_scene(S, i) : empty_item();
         }
         const uint32_t j = (c - S.atom_clusters) * kCluster + slot;
-        if (j >= S.n_bonds) return it;
-        const uint4 br = S.bond_rec[j];
-        if (br.x == br.y) return it;
-        it.a = S.xyzr[br.x];
-        it.b = S.xyzr[br.y];
-        it.id = S.n_atoms + br.z;
-        it.kind = kBond;
-        return it;
+        return j < S.n_bonds ? fetch_scene(S, S.n_atoms + j) : empty_item();
     }
 };
 
@@ -219,7 +135,7 @@ __global__ void __launch_bounds__(kBinThreads) k_count(JS js) {
     const Frame F = J.F;
     const auto src0 = SourceOf<kScene>::make(J);
     const uint32_t chunk = J.bb.chunk;
-    PrimRec* __restrict__ const vis_rec = J.bb.vis_rec;
+    uint32_t* __restrict__ const vis_src = J.bb.vis_src;
     uint2* __restrict__ const vis_rect = J.bb.vis_rect;
     uint32_t* __restrict__ const vis_cnt = J.bb.vis_cnt;
     uint2* __restrict__ const vis_box = J.bb.vis_box;
@@ -246,15 +162,16 @@ __global__ void __launch_bounds__(kBinThreads) k_count(JS js) {
     const uint64_t nitems = src.items();
     const int tsh = F.tile_shift;
     uint32_t bad_count = 0;
-    Item cur{make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f), 0u, kNone};
+    Item cur = empty_item();
     if ((uint64_t)tid < nitems) cur = src.fetch(tid);
     for (uint64_t base = 0; base < nitems; base += kBinThreads) {
         // the next iteration's inputs are loaded while this one is processed
-        Item nxt{make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f), 0u, kNone};
+        Item nxt = empty_item();
         if (base + kBinThreads + tid < nitems) nxt = src.fetch(base + kBinThreads + tid);
         int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
         PrimRec rec;
-        const bool vis = item_record(F, cur, x0, y0, x1, y1, rec);
+        double v[6], r = 0.0;
+        const bool vis = item_view(F, cur, rec, v, r) && item_rect(F, cur, v, r, x0, y0, x1, y1);
         bad_count += cur.kind == kBadBond ? 1u : 0u;
         const unsigned long long vmask = __ballot(vis);
         uint32_t slot_base = 0;
@@ -266,7 +183,7 @@ __global__ void __launch_bounds__(kBinThreads) k_count(JS js) {
         wave_count(hist, single ? ty0 * F.tiles_x + tx0 : -1);
         if (vis) {
             const uint64_t slot = start + slot_base + (uint32_t)__popcll(vmask & __lanemask_lt());
-            vis_rec[slot] = rec;
+            vis_src[slot] = cur.src;
             vis_rect[slot] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
             if (!single)
                 for (int ty = ty0; ty <= ty1; ++ty)
@@ -322,7 +239,7 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js) {
     const Job& J = js.job(ji);
     const Frame F = J.F;
     const uint32_t chunk = J.bb.chunk;
-    const PrimRec* __restrict__ const vis_rec = J.bb.vis_rec;
+    const uint32_t* __restrict__ const vis_src = J.bb.vis_src;
     const uint2* __restrict__ const vis_rect = J.bb.vis_rect;
     const uint32_t* __restrict__ const vis_cnt = J.bb.vis_cnt;
     const uint32_t* __restrict__ const hist_in = J.bb.hist;
@@ -409,26 +326,30 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js) {
                ((uint32_t)(ly1 - ly0 + 1) << 24);
     };
     const uint32_t rounds = (n + kBinThreads - 1) / kBinThreads;   // uniform trip count (wave ops inside)
-    float4 g0 = make_float4(0.f, 0.f, 0.f, 0.f);
-    uint4 g1 = make_uint4(0u, 0u, 0u, 0u);
+    // Each visible primitive's record is rebuilt from its source (the same
+    // computation as in the count pass), which costs less than storing 32
+    // bytes per primitive there and reading them back here.
+    Item prim = empty_item();
     uint2 r = make_uint2(0u, 0u);
     if ((uint32_t)tid < n) {
-        g0 = vis_rec[start + tid].g0;
-        g1 = vis_rec[start + tid].g1;
+        prim = fetch_src(J, vis_src[start + tid]);
         r = vis_rect[start + tid];
     }
     for (uint32_t it = 0; it < rounds; ++it) {
         const uint32_t k = it * kBinThreads + tid;
         const bool have = k < n;
-        // the next record is loaded while this one is placed
-        float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f);
-        uint4 n1 = make_uint4(0u, 0u, 0u, 0u);
+        // the next primitive is loaded while this one is placed
+        Item nxt = empty_item();
         uint2 nr = make_uint2(0u, 0u);
         if (k + kBinThreads < n) {
-            n0 = vis_rec[start + k + kBinThreads].g0;
-            n1 = vis_rec[start + k + kBinThreads].g1;
+            nxt = fetch_src(J, vis_src[start + k + kBinThreads]);
             nr = vis_rect[start + k + kBinThreads];
         }
+        PrimRec rec;
+        double v[6], rr = 0.0;
+        if (have) item_view(F, prim, rec, v, rr);   // visible in the count pass, so true here
+        const float4 g0 = rec.g0;
+        const uint4 g1 = rec.g1;
         const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16;
         const int tx0 = x0 >> tsh, tx1 = x1 >> tsh, ty0 = y0 >> tsh, ty1 = y1 >> tsh;
         const bool single = have && tx0 == tx1 && ty0 == ty1;
@@ -468,8 +389,7 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js) {
                     dst->g1 = make_uint4(g1.x, g1.y, g1.z, local_fp(x0, y0, x1, y1, tx, ty));
                 }
         }
-        g0 = n0;
-        g1 = n1;
+        prim = nxt;
         r = nr;
     }
 }

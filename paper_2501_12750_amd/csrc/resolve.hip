@@ -17,13 +17,14 @@
 // whose nearest possible depth lies behind everything the 4x4-pixel blocks
 // under its footprint already hold, and a fragment whose pixel already holds
 // a nearer hit.
-#include "vtx_internal.h"
+#include "prims.h"
 
 namespace vtx {
 
 namespace {
 
 constexpr int kChunk = kBlock;
+constexpr unsigned kTailBlocks = 256;   // grid of the overflow (tail) launch
 constexpr int kBuckets = 32;      // depth buckets of the front-to-back record order
 constexpr int kSortArea = 16;     // order a chunk when its kept records average more pixels than this
 constexpr int kKeptShift = 21;    // packed scan: footprint area (<= 256 * 64 * 64) below, kept count above
@@ -136,12 +137,24 @@ __device__ inline Rec make_rec(const Frame& F, const PrimRec& p) {
     return r;
 }
 
+// Record of a visible primitive rebuilt from its source, for tiles whose list
+// overflowed.
+__device__ inline PrimRec overflow_record(const Job& J, uint32_t src) {
+    PrimRec pr;
+    double v[6], rr;
+    item_view(J.F, fetch_src(J, src), pr, v, rr);   // true: it was visible in the count pass
+    return pr;
+}
+
 // Work block t of a job is that job's tile t; the launch's blocks are spread
 // over the XCDs in contiguous ranges.
-// kCount: the instantiation that can count fragments (jobs with
-// VTX_FLAG_STATS); the other one carries no counters.
-template <int TS, class JS, bool kCount>
-__global__ void __launch_bounds__(kBlock, kCount ? 1 : 7) k_resolve(JS js) {
+// Resolves tile t of job J, whose list holds n records from offset o
+// (kTail: the list overflowed and the tile is rebuilt from every binning
+// workgroup's visible list).  Re-arms the tile's count and cursor for the next
+// frame.  The workgroup's LDS holds the tile's depth buffer, one chunk of
+// records and their prefix.
+template <int TS, bool kCount, bool kTail>
+__device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o) {
     __shared__ unsigned long long keys[TS * TS];
     __shared__ Rec recs[kChunk];
     __shared__ uint32_t pref[kChunk + 1];
@@ -152,43 +165,29 @@ __global__ void __launch_bounds__(kBlock, kCount ? 1 : 7) k_resolve(JS js) {
     __shared__ uint32_t bcnt[kBuckets], bbase[kBuckets];
     __shared__ uint8_t ord[kChunk];   // depth-ordered chunk: record slots front to back
 
-    uint32_t tu;
-    const int ji = js.find((uint32_t)xcd_contiguous(blockIdx.x, gridDim.x), tu);
-    if (ji < 0) return;
-    const Job& J = js.job(ji);
     const Frame F = J.F;
     uint32_t* __restrict__ const cnt = J.bb.tile_cnt;
-    const uint64_t* __restrict__ const off = J.bb.tile_off;
     const PrimRec* __restrict__ const list = J.bb.list;
-    const uint64_t capacity = J.bb.capacity;
-    const PrimRec* __restrict__ const vis_rec = J.bb.vis_rec;
+    const uint32_t* __restrict__ const vis_src = J.bb.vis_src;
     const uint2* __restrict__ const vis_rect = J.bb.vis_rect;
     const uint32_t* __restrict__ const vis_cnt = J.bb.vis_cnt;
     const uint2* __restrict__ const vis_box = J.bb.vis_box;
     const uint32_t chunk = J.bb.chunk, groups = J.bb.groups;
     uint32_t* __restrict__ const fill = J.bb.tile_fill;
     Counters* const ctr = J.bb.ctr;
-    Counters* const host_ctr = J.bb.host_ctr;
     float* __restrict__ const depth = J.depth;
     uint32_t* __restrict__ const out_id = J.id;
 
-    const int T = F.tiles_x * F.tiles_y;
-    const int t = (int)tu;
     const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
     const bool stats = kCount && (F.flags & 1u) != 0;
     unsigned long long n_tested = 0, n_hit = 0, n_hit_bond = 0;
 
-    if (t < T) {
+    {
         const int tx = t % F.tiles_x, ty = t / F.tiles_x;
         const int px0 = tx * TS, py0 = ty * TS;
         const int tw = min(TS, F.W - px0), th = min(TS, F.H - py0);
         for (int i = tid; i < TS * TS; i += kBlock) keys[i] = ~0ull;
-
-        const uint32_t n = cnt[t];
-        const uint64_t o = off[t];
-        // a tile whose list did not fit the bins scans every workgroup's visible list
-        const bool overflow = o + n > capacity;
-        const uint64_t nsrc = overflow ? (uint64_t)groups * chunk : n;
+        const uint64_t nsrc = kTail ? (uint64_t)groups * chunk : n;
         const bool persp = F.proj == 0;
         __syncthreads();
         // every wave has read the tile's count (it sets the trip count of the
@@ -222,12 +221,10 @@ __global__ void __launch_bounds__(kBlock, kCount ? 1 : 7) k_resolve(JS js) {
             }
             if (hit) atomicMin(&keys[slot], ((unsigned long long)__float_as_uint(z) << 32) | rc.id);
         };
-        // entry k of the tile's list, or of the visible lists when the tile overflowed
-        auto fetch = [&](uint64_t k, PrimRec& pr) -> bool {
-            if (!overflow) {
-                pr = list[o + k];
-                return true;
-            }
+        // entry k of the visible lists (tiles whose list overflowed): the
+        // record is rebuilt from its source
+        auto fetch_overflow = [&](uint64_t k, PrimRec& pr) -> bool {
+            if constexpr (!kTail) return false;
             const uint32_t g = (uint32_t)(k / chunk);
             if ((uint32_t)(k - (uint64_t)g * chunk) >= vis_cnt[g]) return false;
             const uint2 gb = vis_box[g];    // skip workgroups whose primitives cannot touch this tile
@@ -239,7 +236,7 @@ __global__ void __launch_bounds__(kBlock, kCount ? 1 : 7) k_resolve(JS js) {
             const int x1 = min((int)(r.y & 0xFFFF), px0 + TS - 1) - px0;
             const int y1 = min((int)(r.y >> 16), py0 + TS - 1) - py0;
             if (x0 > x1 || y0 > y1) return false;
-            pr = vis_rec[k];
+            pr = overflow_record(J, vis_src[k]);
             pr.g1.w = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)(x1 - x0 + 1) << 16) |
                       ((uint32_t)(y1 - y0 + 1) << 24);
             return true;
@@ -251,8 +248,11 @@ __global__ void __launch_bounds__(kBlock, kCount ? 1 : 7) k_resolve(JS js) {
         for (int i = tid; i < kHzBlocks; i += kBlock) hz[i] = 0x7F800000u;
         // The tile's list is staged 256 records at a time; the next chunk's
         // records are loaded while this chunk is resolved.
+        // A list's next chunk is loaded while this one is resolved; the
+        // overflow path loads each chunk when it starts.
         PrimRec nxt;
-        bool nxt_ok = (uint64_t)tid < nsrc && fetch(tid, nxt);
+        bool nxt_ok = !kTail && (uint64_t)tid < nsrc;
+        if (nxt_ok) nxt = list[o + tid];
         __syncthreads();
         // record cull against the block depths: its nearest possible depth
         // lies behind everything the 4x4 blocks under its footprint hold
@@ -321,9 +321,14 @@ __global__ void __launch_bounds__(kBlock, kCount ? 1 : 7) k_resolve(JS js) {
             __syncthreads();
         };
         for (uint64_t base = 0; base < nsrc; base += kChunk) {
-            const PrimRec pr = nxt;
-            const bool have = nxt_ok;
-            nxt_ok = base + kChunk + tid < nsrc && fetch(base + kChunk + tid, nxt);
+            PrimRec pr = nxt;
+            bool have = nxt_ok;
+            if constexpr (kTail) {
+                have = base + tid < nsrc && fetch_overflow(base + tid, pr);
+            } else {
+                nxt_ok = base + kChunk + tid < nsrc;
+                if (nxt_ok) nxt = list[o + base + kChunk + tid];
+            }
             bool keep = false;
             uint32_t area = 0;
             float zc = INFINITY;
@@ -425,47 +430,97 @@ __global__ void __launch_bounds__(kBlock, kCount ? 1 : 7) k_resolve(JS js) {
             atomicAdd(&ctr->frag_hit_bond, c);
         }
     }
-    // with exact fragment counting on, the last workgroup to finish publishes
-    // the fragment counters to the host-mapped copy
-    if (stats && host_ctr) {
-        __syncthreads();
-        if (tid == 0) {
+}
+
+// Main launch: work block t of a job is that job's tile t (blocks spread
+// over the XCDs in contiguous ranges).  A tile whose list overflowed the bins
+// is left to the tail launch: it is appended to `ovf` (job << 32 | tile).
+// kCount: the instantiation that can count fragments (jobs with
+// VTX_FLAG_STATS); the other one carries no counters.
+template <int TS, class JS, bool kCount>
+__global__ void __launch_bounds__(kBlock, kCount ? 1 : 7) k_resolve(JS js, unsigned long long* ovf, uint32_t* ovf_n) {
+    uint32_t tu;
+    const int ji = js.find((uint32_t)xcd_contiguous(blockIdx.x, gridDim.x), tu);
+    if (ji < 0) return;
+    const Job& J = js.job(ji);
+    const uint32_t n = J.bb.tile_cnt[tu];
+    const uint64_t o = J.bb.tile_off[tu];
+    if (o + n > J.bb.capacity) {
+        if (threadIdx.x == 0) ovf[atomicAdd(ovf_n, 1u)] = ((unsigned long long)ji << 32) | tu;
+        return;
+    }
+    resolve_tile<TS, kCount, false>(J, (int)tu, n, o);
+}
+
+// Tail launch (a fixed grid, queued right after the main one): resolves the
+// overflowed tiles the main launch listed, then its last workgroup clears the
+// list and publishes the fragment counters of every counting job.  Keeping the
+// rare overflow path out of the main instantiation keeps its register budget.
+template <int TS, class JS, bool kCount>
+__global__ void __launch_bounds__(kBlock) k_resolve_tail(JS js, const unsigned long long* ovf, uint32_t* ovf_n) {
+    const uint32_t total = *(volatile uint32_t*)ovf_n;
+    for (uint32_t e = blockIdx.x; e < total; e += gridDim.x) {
+        const unsigned long long v = ovf[e];
+        const Job& J = js.job((int)(v >> 32));
+        const int t = (int)(v & 0xFFFFFFFFull);
+        resolve_tile<TS, kCount, true>(J, t, J.bb.tile_cnt[t], J.bb.tile_off[t]);
+        __syncthreads();   // the next tile reuses the LDS
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned int ticket = atomicAdd(&ovf_n[1], 1u);
+        if (ticket == gridDim.x - 1) {
             __threadfence();
-            const unsigned int ticket = atomicAdd(&ctr->done_blocks, 1u);
-            if (ticket == (unsigned int)T - 1) {
-                __threadfence();
-                const volatile Counters* src = ctr;
-                host_ctr->frag_tested = src->frag_tested;
-                host_ctr->frag_hit = src->frag_hit;
-                host_ctr->frag_hit_bond = src->frag_hit_bond;
-                __threadfence_system();
+            ovf_n[0] = 0;
+            ovf_n[1] = 0;
+            if (kCount) {
+                for (uint32_t j = 0; j < js.count(); ++j) {
+                    const Job& Jj = js.job((int)j);
+                    if (!(Jj.F.flags & 1u) || !Jj.bb.host_ctr) continue;
+                    const volatile Counters* src = Jj.bb.ctr;
+                    Jj.bb.host_ctr->frag_tested = src->frag_tested;
+                    Jj.bb.host_ctr->frag_hit = src->frag_hit;
+                    Jj.bb.host_ctr->frag_hit_bond = src->frag_hit_bond;
+                }
             }
+            __threadfence_system();
         }
     }
 }
 
+
 }  // namespace
 
+template <int TS, class JS, bool kCount>
+void resolve_launch(const JS& js, unsigned g, unsigned long long* ovf, uint32_t* ovf_n, hipStream_t stream) {
+    k_resolve<TS, JS, kCount><<<g, kBlock, 0, stream>>>(js, ovf, ovf_n);
+    k_resolve_tail<TS, JS, kCount><<<kTailBlocks, kBlock, 0, stream>>>(js, ovf, ovf_n);
+}
+
 template <class JS, bool kCount>
-hipError_t resolve_impl(const JS& js, int tile, uint32_t grid, hipStream_t stream) {
+hipError_t resolve_impl(const JS& js, int tile, uint32_t grid, unsigned long long* ovf, uint32_t* ovf_n,
+                        hipStream_t stream) {
     if (grid == 0) return hipSuccess;
     const unsigned g = (unsigned)xcd_grid((int)grid);
     switch (tile) {
-        case 8: k_resolve<8, JS, kCount><<<g, kBlock, 0, stream>>>(js); break;
-        case 16: k_resolve<16, JS, kCount><<<g, kBlock, 0, stream>>>(js); break;
-        case 32: k_resolve<32, JS, kCount><<<g, kBlock, 0, stream>>>(js); break;
-        case 64: k_resolve<64, JS, kCount><<<g, kBlock, 0, stream>>>(js); break;
+        case 8: resolve_launch<8, JS, kCount>(js, g, ovf, ovf_n, stream); break;
+        case 16: resolve_launch<16, JS, kCount>(js, g, ovf, ovf_n, stream); break;
+        case 32: resolve_launch<32, JS, kCount>(js, g, ovf, ovf_n, stream); break;
+        case 64: resolve_launch<64, JS, kCount>(js, g, ovf, ovf_n, stream); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_resolve(const OneJob& js, int tile, uint32_t grid, bool count, hipStream_t stream) {
-    return count ? resolve_impl<OneJob, true>(js, tile, grid, stream) : resolve_impl<OneJob, false>(js, tile, grid, stream);
+hipError_t launch_resolve(const OneJob& js, int tile, uint32_t grid, bool count, unsigned long long* ovf,
+                          uint32_t* ovf_n, hipStream_t stream) {
+    return count ? resolve_impl<OneJob, true>(js, tile, grid, ovf, ovf_n, stream)
+                 : resolve_impl<OneJob, false>(js, tile, grid, ovf, ovf_n, stream);
 }
-hipError_t launch_resolve(const JobList& js, int tile, uint32_t grid, bool count, hipStream_t stream) {
-    return count ? resolve_impl<JobList, true>(js, tile, grid, stream)
-                 : resolve_impl<JobList, false>(js, tile, grid, stream);
+hipError_t launch_resolve(const JobList& js, int tile, uint32_t grid, bool count, unsigned long long* ovf,
+                          uint32_t* ovf_n, hipStream_t stream) {
+    return count ? resolve_impl<JobList, true>(js, tile, grid, ovf, ovf_n, stream)
+                 : resolve_impl<JobList, false>(js, tile, grid, ovf, ovf_n, stream);
 }
 
 }  // namespace vtx

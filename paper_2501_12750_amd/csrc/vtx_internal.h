@@ -26,6 +26,7 @@ struct Frame {
     double hx, hy;                     // orthographic: h * W/H, h
     double itx, ity, ihx, ihy;         // their inverses
     float txf, tyf, hxf, hyf;
+    float itxf, ityf;                  // 1 / tx, 1 / ty
     float sxf, syf;                    // perspective: sqrt(1 + tx^2), sqrt(1 + ty^2)
     float inv_w2, inv_h2;              // 2/W, 2/H
     float znear, zfar;
@@ -62,13 +63,12 @@ struct Counters {
     unsigned long long pairs_counted;   // total of the tile counts, added by the count kernel
 };
 
-// View-space record of one visible primitive (32 bytes), computed once per
-// frame from FP64 and rounded to FP32.
+// View-space record of one visible primitive in a tile list (32 bytes),
+// computed from FP64 and rounded to FP32.
 //   sphere: g0 = (centre x, y, z, radius),      g1 = (0, 0, id, footprint)
 //   bond:   g0 = (A x, y, z, (B - A).x),         g1 = ((B - A).y, (B - A).z, id, footprint)
-// id >= n_atoms marks a bond.  In the visible list the footprint word is
-// unused (the pixel rectangle is kept beside it); in a tile list it is the
-// footprint clipped to the tile, x0 | y0 << 8 | w << 16 | h << 24 in
+// id >= n_atoms marks a bond.  The footprint word is the primitive's pixel
+// rectangle clipped to the tile, x0 | y0 << 8 | w << 16 | h << 24 in
 // tile-local pixels.
 struct PrimRec {
     float4 g0;
@@ -224,7 +224,7 @@ struct BinBuffers {
     uint32_t* tile_cnt;     // T
     uint64_t* tile_off;     // T
     uint32_t* tile_fill;    // T
-    PrimRec* vis_rec;       // groups * chunk visible-primitive records
+    uint32_t* vis_src;      // groups * chunk: source index of each visible primitive (re-fetched by scatter)
     uint2* vis_rect;        // groups * chunk, pixel rectangle packed (x0 | y0 << 16, x1 | y1 << 16)
     uint32_t* vis_cnt;      // groups: visible primitives of each workgroup
     uint2* vis_box;         // groups: tile-space bounding box of each workgroup's visible
@@ -305,6 +305,7 @@ struct OneJob {
     }
     __device__ const Job& job(int) const { return j; }
     __device__ const SampleKernel& samples(int) const { return K; }
+    __device__ uint32_t count() const { return 1; }
 };
 
 // A launch over several renders, described by device tables: job i owns the
@@ -327,6 +328,7 @@ struct JobList {
     }
     __device__ const Job& job(int i) const { return jobs[i]; }
     __device__ const SampleKernel& samples(int i) const { return K[i]; }
+    __device__ uint32_t count() const { return n; }
 };
 
 // Launch wrappers, one overload per job source.  `grid` is the number of
@@ -341,8 +343,13 @@ hipError_t launch_count(const OneJob& js, bool scene, uint32_t grid, int max_til
 hipError_t launch_count(const JobList& js, bool scene, uint32_t grid, int max_tiles, hipStream_t stream);
 hipError_t launch_scatter(const OneJob& js, uint32_t grid, int max_tiles, hipStream_t stream);
 hipError_t launch_scatter(const JobList& js, uint32_t grid, int max_tiles, hipStream_t stream);
-hipError_t launch_resolve(const OneJob& js, int tile, uint32_t grid, bool count, hipStream_t stream);
-hipError_t launch_resolve(const JobList& js, int tile, uint32_t grid, bool count, hipStream_t stream);
+// The resolve is a main launch plus a small tail launch for the tiles whose
+// lists overflowed: `ovf` holds at least `grid` entries and ovf_n two zeroed
+// counters (both left zeroed again).
+hipError_t launch_resolve(const OneJob& js, int tile, uint32_t grid, bool count, unsigned long long* ovf,
+                          uint32_t* ovf_n, hipStream_t stream);
+hipError_t launch_resolve(const JobList& js, int tile, uint32_t grid, bool count, unsigned long long* ovf,
+                          uint32_t* ovf_n, hipStream_t stream);
 hipError_t launch_shade(const OneJob& js, uint32_t grid, hipStream_t stream);
 hipError_t launch_shade(const JobList& js, uint32_t grid, hipStream_t stream);
 

@@ -38,7 +38,8 @@ EXPORTS = ("vtx_render", "vtx_gbuffer", "vtx_shade", "vtx_read_stats", "vtx_set_
            "vtx_scene_destroy", "vtx_render_scene", "vtx_scene_add_frames", "vtx_scene_frames",
            "vtx_scene_frame_bytes", "vtx_render_batch", "vtx_autotune", "vtx_clock_s", "vtx_server_create",
            "vtx_server_submit", "vtx_server_poll", "vtx_server_drain", "vtx_server_stats_read",
-           "vtx_server_destroy", "vtx_check_job")
+           "vtx_server_destroy", "vtx_check_job", "vtx_batch_graph_create",
+           "vtx_batch_graph_launch", "vtx_batch_graph_destroy")
 
 
 class vtx_camera(ctypes.Structure):
@@ -164,6 +165,12 @@ _lib.vtx_render_batch.restype = ctypes.c_int
 _lib.vtx_render_batch.argtypes = [_P, ctypes.POINTER(vtx_job), _I32, _P]
 _lib.vtx_autotune.restype = ctypes.c_int
 _lib.vtx_autotune.argtypes = [_P, ctypes.POINTER(vtx_job), _I32, ctypes.c_char_p, _P, ctypes.POINTER(vtx_tuning)]
+_lib.vtx_batch_graph_create.restype = ctypes.c_int
+_lib.vtx_batch_graph_create.argtypes = [_P, ctypes.POINTER(vtx_job), _I32, ctypes.POINTER(_P)]
+_lib.vtx_batch_graph_launch.restype = ctypes.c_int
+_lib.vtx_batch_graph_launch.argtypes = [_P, _P]
+_lib.vtx_batch_graph_destroy.restype = None
+_lib.vtx_batch_graph_destroy.argtypes = [_P]
 _lib.vtx_check_job.restype = ctypes.c_int
 _lib.vtx_check_job.argtypes = [_P, ctypes.POINTER(vtx_job)]
 _lib.vtx_clock_s.restype = ctypes.c_double
@@ -387,6 +394,21 @@ def vtx_server_create(ctx, max_batch=64, max_inflight=2, stream=None) -> int:
     if rc != VTX_OK:
         raise VtxError(rc, "vtx_server_create: bad arguments")
     return h.value
+
+
+def vtx_batch_graph_create(ctx, jobs) -> int:
+    arr = jobs if isinstance(jobs, ctypes.Array) else (vtx_job * len(jobs))(*jobs)
+    h = _P()
+    _check(_lib.vtx_batch_graph_create(ctx, arr, len(arr), ctypes.byref(h)))
+    return h.value
+
+
+def vtx_batch_graph_launch(graph, stream=None):
+    _check(_lib.vtx_batch_graph_launch(graph, _stream(stream)))
+
+
+def vtx_batch_graph_destroy(graph):
+    _lib.vtx_batch_graph_destroy(graph)
 
 
 def vtx_check_job(ctx, job):

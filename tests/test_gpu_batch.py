@@ -211,3 +211,58 @@ def test_batch_full_trajectory_sampled(vtx, ctx):
         ref = run_render(vtx, vtx.DeviceScene(sc_f), cam, o, W, H)
         assert_identical(imgs[i].numpy(), ref, f"job {i}")
     rs.close()
+
+
+def test_batch_graph_replays_match_eager_renders(vtx, ctx):
+    """A captured batch replayed several times, with other eager work on the
+    same stream between replays, gives the eager batch's images every time;
+    replays follow updated trajectory positions written in place."""
+    import torch
+    scene0, frames, cams, opts, rs = trajectory_scene(vtx, ctx, 5000, 4)
+    specs = [(rs.handle, f, cams[k], opts, *VIEWPORTS_SMALL[(f + k) % 4]) for f in range(4) for k in range(4)]
+    ref = run_batch(vtx, ctx, specs)
+    imgs = [vtx.Frame(W, H) for (_, _, _, _, W, H) in specs]
+    jobs = [vtx.make_job(h, f, cam, o, W, H, fr.rgba, fr.depth, fr.id)
+            for (h, f, cam, o, W, H), fr in zip(specs, imgs)]
+    graph = vtx.vtx_batch_graph_create(ctx, jobs)
+    other = scenes.plain_small()
+    ds_other = vtx.DeviceScene(other.scene)
+    try:
+        for rep in range(4):
+            for fr in imgs:
+                fr.rgba.zero_()
+                fr.depth.zero_()
+                fr.id.zero_()
+            vtx.vtx_batch_graph_launch(graph)
+            run_render(vtx, ds_other, other.camera, other.options, 256, 256)   # eager work between replays
+            torch.cuda.synchronize()
+            for i, fr in enumerate(imgs):
+                assert_identical(fr.numpy(), ref[i], f"replay {rep} job {i}")
+        # frame 0 moved in place: the replay renders the new positions
+        moved = np.ascontiguousarray(frames[3])
+        rs.update_positions(torch.from_numpy(moved).to("cuda"))
+        torch.cuda.synchronize()
+        vtx.vtx_batch_graph_launch(graph)
+        torch.cuda.synchronize()
+        sc_moved = scenes.Scene(moved, scene0.radii, scene0.colors, scene0.bonds)
+        for i, (_, f, cam, o, W, H) in enumerate(specs):
+            if f == 0:
+                assert_identical(imgs[i].numpy(), run_render(vtx, vtx.DeviceScene(sc_moved), cam, o, W, H),
+                                 f"moved job {i}")
+            else:
+                assert_identical(imgs[i].numpy(), ref[i], f"unmoved job {i}")
+    finally:
+        vtx.vtx_batch_graph_destroy(graph)
+    # a one-job graph (the job travels in the kernel arguments)
+    _, f0, cam0, o0, W0, H0 = specs[0]
+    assert f0 == 0
+    imgs[0].id.zero_()
+    single = vtx.vtx_batch_graph_create(ctx, jobs[:1])
+    imgs[0].id.zero_()
+    vtx.vtx_batch_graph_launch(single)
+    torch.cuda.synchronize()
+    assert_identical(imgs[0].numpy(), run_render(vtx, vtx.DeviceScene(sc_moved), cam0, o0, W0, H0), "one-job graph")
+    vtx.vtx_batch_graph_destroy(single)
+    with pytest.raises(vtx.VtxError):
+        vtx.vtx_batch_graph_create(ctx, [])
+    rs.close()
