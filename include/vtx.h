@@ -100,7 +100,23 @@ typedef struct vtx_options {
                                  more than 15360 tiles (VTX_EINVAL if 64 is not
                                  enough: extreme aspect ratios) */
     uint32_t flags;           /* VTX_FLAG_* */
+    int32_t representation;   /* VTX_REP_* (VTX_REP_BALL_AND_STICK) */
+    float probe_radius;       /* solvent probe of VTX_REP_SAS (1.4) */
 } vtx_options;
+
+/*
+ * options.representation (paper, Methods, "Meshless Representations": the
+ * molecular representations are drawn with the same sphere and cylinder
+ * impostors).  Ids keep their meaning in every representation.
+ *   VTX_REP_BALL_AND_STICK  spheres of the given radii and the bonds
+ *   VTX_REP_VAN_DER_WAALS   spheres of the given radii, no bonds
+ *   VTX_REP_STICKS          spheres of radius bond_radius and the bonds
+ *   VTX_REP_SAS             spheres of radius r + probe_radius (FP32 sum), no bonds
+ */
+#define VTX_REP_BALL_AND_STICK 0
+#define VTX_REP_VAN_DER_WAALS 1
+#define VTX_REP_STICKS 2
+#define VTX_REP_SAS 3
 
 /* Per-frame counters of the last frame queued on a stream. */
 typedef struct vtx_stats {

@@ -70,6 +70,8 @@ def check_gbuffer(dev_depth, dev_id, ref):
 
 
 def primitive_radius(scene, opts, ids):
+    from oracle.ofull import representation_scene
+    scene = representation_scene(scene, opts)
     ids = np.asarray(ids, dtype=np.int64)
     r = np.full(ids.shape, float(opts.bond_radius))
     atom = ids < scene.n_atoms

@@ -244,6 +244,30 @@ def _rgb(c):
     return np.array([c & 255, (c >> 8) & 255, (c >> 16) & 255, (c >> 24) & 255], dtype=np.float64)
 
 
+REP_BALL_AND_STICK, REP_VAN_DER_WAALS, REP_STICKS, REP_SAS = 0, 1, 2, 3
+
+
+def representation_scene(scene, opts):
+    """The spheres and cylinders a molecular representation draws (paper,
+    Methods, "Meshless Representations": ball-and-stick, van der Waals,
+    sticks and the solvent-accessible surface are drawn with the same sphere
+    and cylinder impostors).  Reading: van der Waals and the SAS draw no
+    bonds; sticks draw every atom at the bond radius; the SAS adds the probe
+    radius (default 1.4 A) to each radius, summed in FP32 like the inputs.
+    Ids keep their meaning: atom i stays i and bond b stays N + b."""
+    rep = int(getattr(opts, "representation", REP_BALL_AND_STICK))
+    if rep == REP_BALL_AND_STICK:
+        return scene
+    radii, bonds = scene.radii, scene.bonds
+    if rep in (REP_VAN_DER_WAALS, REP_SAS):
+        bonds = np.zeros((0, 2), dtype=np.uint32)
+    if rep == REP_STICKS:
+        radii = np.full(scene.n_atoms, np.float32(opts.bond_radius), dtype=np.float32)
+    elif rep == REP_SAS:
+        radii = (scene.radii.astype(np.float32) + np.float32(getattr(opts, "probe_radius", 1.4))).astype(np.float32)
+    return type(scene)(scene.positions, radii, scene.colors, bonds)
+
+
 def gbuffer(scene, cam, opts, W, H, window=None):
     """Brute-force G-buffer over ``window`` = (x0, y0, w, h) of the W x H image.
 
@@ -261,6 +285,7 @@ def gbuffer(scene, cam, opts, W, H, window=None):
     """
     if window is None:
         window = (0, 0, W, H)
+    scene = representation_scene(scene, opts)
     x0, y0, w, h = window
     P = w * h
     o, d = pixel_rays(cam, W, H, window)

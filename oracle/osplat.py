@@ -71,8 +71,10 @@ def default_threads() -> int:
 
 
 def gbuffer(scene, cam, opts, W, H, window=None, nthreads=None):
+    from oracle.ofull import representation_scene
     if window is None:
         window = (0, 0, W, H)
+    scene = representation_scene(scene, opts)
     x0, y0, w, h = window
     P = w * h
     pos = np.ascontiguousarray(scene.positions, dtype=np.float32)

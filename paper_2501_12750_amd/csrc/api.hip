@@ -396,6 +396,10 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
         return fail(VTX_EINVAL, "ssao radius/bias must be finite, radius >= 0");
     if (o.tile_size != 0 && o.tile_size != 8 && o.tile_size != 16 && o.tile_size != 32 && o.tile_size != 64)
         return fail(VTX_EINVAL, "tile_size must be 0, 8, 16, 32 or 64");
+    if (o.representation < VTX_REP_BALL_AND_STICK || o.representation > VTX_REP_SAS)
+        return fail(VTX_EINVAL, "unknown representation %d", o.representation);
+    if (o.representation == VTX_REP_SAS && !(o.probe_radius >= 0.0f && std::isfinite(o.probe_radius)))
+        return fail(VTX_EINVAL, "probe_radius must be finite and >= 0");
 
     double e[3], f[3], up[3], s[3], u[3];
     for (int k = 0; k < 3; ++k) {
@@ -459,8 +463,11 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
     F->tiles_x = (W + F->tile - 1) / F->tile;
     F->tiles_y = (H + F->tile - 1) / F->tile;
     F->n_atoms = (uint32_t)n;
-    F->n_bonds = (uint32_t)m;
+    const bool bonds_drawn = o.representation == VTX_REP_BALL_AND_STICK || o.representation == VTX_REP_STICKS;
+    F->n_bonds = bonds_drawn ? (uint32_t)m : 0u;
     F->flags = o.flags;
+    F->rep = o.representation;
+    F->probe = o.probe_radius;
     return VTX_OK;
 }
 
@@ -473,6 +480,8 @@ vtx_options resolve_options(const vtx_options* opt) {
     o.background = 0u;
     o.tile_size = 0;
     o.flags = 0u;
+    o.representation = VTX_REP_BALL_AND_STICK;
+    o.probe_radius = 1.4f;
     return opt ? *opt : o;
 }
 

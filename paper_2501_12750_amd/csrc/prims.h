@@ -81,7 +81,7 @@ __device__ inline Item fetch_src(const Job& J, uint32_t src) {
 __device__ inline bool item_view(const Frame& F, const Item& it, PrimRec& rec, double* v, double& r) {
     if (it.kind == kAtom) {
         to_view(F, it.a.x, it.a.y, it.a.z, v[0], v[1], v[2]);
-        r = (double)it.a.w;
+        r = (double)atom_radius(F, it.a.w);
         if (!(r > 0.0) || !sphere_in_frustum(F, v[0], v[1], v[2], r)) return false;
         rec.g0 = make_float4((float)v[0], (float)v[1], (float)v[2], (float)r);
         rec.g1 = make_uint4(0u, 0u, it.id, 0u);

@@ -179,14 +179,17 @@ __global__ void __launch_bounds__(kBlock) k_cluster_cull(JS js) {
     const Frame F = J.F;
     const SceneDev S = J.S;
     Counters* const ctr = J.bb.ctr;
-    const uint32_t nc = S.atom_clusters + S.bond_clusters;
+    const uint32_t nc = S.atom_clusters + (F.n_bonds ? S.bond_clusters : 0u);
     {
         const uint32_t c = blk * kBlock + threadIdx.x;
         bool vis = false;
         if (c < nc) {
             const float4 lo = S.cluster_box[2 * (size_t)c], hi = S.cluster_box[2 * (size_t)c + 1];
             if (lo.x <= hi.x) {   // empty clusters have an inverted box
-                const float pad = c < S.atom_clusters ? 0.0f : F.bond_radius;
+                // atom boxes hold the given radii: the representation may draw
+                // larger spheres (sticks, solvent-accessible surface)
+                const float pad = c < S.atom_clusters ? (F.rep == 2 ? F.bond_radius : F.rep == 3 ? F.probe : 0.0f)
+                                                      : F.bond_radius;
                 const double hx = 0.5 * ((double)hi.x - lo.x), hy = 0.5 * ((double)hi.y - lo.y),
                              hz = 0.5 * ((double)hi.z - lo.z);
                 double vx, vy, vz;

@@ -35,9 +35,16 @@ struct Frame {
     int32_t W, H;
     int32_t tile, tiles_x, tiles_y;
     int32_t tile_shift;                // tile = 1 << tile_shift
-    uint32_t n_atoms, n_bonds;
+    uint32_t n_atoms, n_bonds;         // n_bonds: bonds drawn (0 when the representation has none)
     uint32_t flags;
+    int32_t rep;                       // VTX_REP_* : radius of the atom spheres
+    float probe;                       // VTX_REP_SAS probe radius
 };
+
+// Sphere radius of an atom of given radius r under the frame's representation.
+__host__ __device__ inline float atom_radius(const Frame& F, float r) {
+    return F.rep == 2 ? F.bond_radius : F.rep == 3 ? r + F.probe : r;
+}
 
 // SSAO sample set (hemisphere direction xyz, radius scale w).
 struct SampleKernel {

@@ -78,11 +78,14 @@ class Options:
     background: int = 0          # packed RGBA8
     tile_size: int = 0           # 0: library default
     flags: int = 0
+    representation: int = 0      # 0 ball-and-stick, 1 van der Waals, 2 sticks, 3 solvent-accessible surface
+    probe_radius: float = 1.4
 
     def __post_init__(self):
         self.bond_radius = f32(self.bond_radius)
         self.ssao_radius = f32(self.ssao_radius)
         self.ssao_bias = f32(self.ssao_bias)
+        self.probe_radius = f32(self.probe_radius)
 
 
 @dataclasses.dataclass

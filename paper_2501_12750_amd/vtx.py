@@ -29,6 +29,7 @@ VTX_MAX_PIXELS = 7680 * 4320
 VTX_MAX_SSAO_SAMPLES = 64
 VTX_FLAG_STATS = 1
 VTX_FLAG_TIMING = 2
+VTX_REP_BALL_AND_STICK, VTX_REP_VAN_DER_WAALS, VTX_REP_STICKS, VTX_REP_SAS = 0, 1, 2, 3
 
 # Every symbol include/vtx.h declares.
 EXPORTS = ("vtx_render", "vtx_gbuffer", "vtx_shade", "vtx_read_stats", "vtx_set_bin_capacity",
@@ -51,7 +52,8 @@ class vtx_camera(ctypes.Structure):
 class vtx_options(ctypes.Structure):
     _fields_ = [("bond_radius", ctypes.c_float), ("ssao_samples", ctypes.c_int32),
                 ("ssao_radius", ctypes.c_float), ("ssao_bias", ctypes.c_float),
-                ("background", ctypes.c_uint32), ("tile_size", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("background", ctypes.c_uint32), ("tile_size", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("representation", ctypes.c_int32), ("probe_radius", ctypes.c_float)]
 
 
 class vtx_stats(ctypes.Structure):
@@ -238,6 +240,8 @@ def options_struct(opts) -> vtx_options:
     o.background = int(opts.background) & 0xFFFFFFFF
     o.tile_size = int(getattr(opts, "tile_size", 0))
     o.flags = int(getattr(opts, "flags", 0))
+    o.representation = int(getattr(opts, "representation", 0))
+    o.probe_radius = float(getattr(opts, "probe_radius", 1.4))
     return o
 
 

@@ -277,3 +277,32 @@ def test_many_consecutive_frames_identical(vtx):
         d = fr.numpy()
         for k in ("rgba", "depth", "id"):
             assert np.array_equal(d[k], ref[k]), k
+
+
+@pytest.mark.parametrize("rep", [1, 2, 3])
+def test_representations(vtx, rep):
+    """Van der Waals, sticks and solvent-accessible surface: the same kernels
+    with other sphere radii and with or without the bonds."""
+    wl = scenes.ball_and_stick(n_globules=8, atoms_per_globule=300, sigma=4.0, pitch=6.0,
+                               width=240, height=160, ssao_samples=16)
+    if rep != 2:
+        # van der Waals radii for the spheres, so the representations differ
+        el = np.random.default_rng(5).choice(5, size=wl.scene.n_atoms, p=scenes.ELEMENT_MIX)
+        wl.scene = scenes.Scene(wl.scene.positions, np.ascontiguousarray(scenes.ELEMENT_VDW[el]),
+                                wl.scene.colors, wl.scene.bonds)
+    wl.options = with_opts(wl.options, representation=rep, probe_radius=1.4)
+    dev, ref, rep_ = full_parity(vtx, wl, name=f"representation {rep}")
+    ids = dev["id"]
+    has_bonds = np.any((ids >= wl.scene.n_atoms) & (ids != 0xFFFFFFFF))
+    assert has_bonds == (rep == 2)
+    # the resident-scene path draws the same images
+    ctx = vtx.vtx_context_create(0, 0)
+    rs = vtx.ResidentScene(ctx, vtx.DeviceScene(wl.scene))
+    import torch
+    got = rs.render(wl.camera, wl.options, wl.width, wl.height).numpy()
+    torch.cuda.synchronize()
+    plain = run_render(vtx, vtx.DeviceScene(wl.scene), wl.camera, wl.options, wl.width, wl.height)
+    for k in ("depth", "id", "rgba"):
+        assert np.array_equal(got[k], plain[k]), k
+    rs.close()
+    vtx.vtx_context_destroy(ctx)

@@ -495,3 +495,46 @@ def test_ssao_step_occlusion_from_geometry(oracle, K):
     assert m.sum() > 100
     assert np.any(exp[m] < 1.0)
     assert np.allclose(res["ao"][m], exp[m], atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# representations: the same impostors with other radii / without bonds
+# ---------------------------------------------------------------------------
+def _disk_count(W, H, half_h, cx, cy, r):
+    scale = Fraction(H, 2) / Fraction(half_h)
+    pcx, pcy = Fraction(W, 2) + cx * scale, Fraction(H, 2) - cy * scale
+    rp2 = (r * scale) ** 2
+    inside = np.zeros((H, W), dtype=bool)
+    for j in range(H):
+        for i in range(W):
+            inside[j, i] = (i + Fraction(1, 2) - pcx) ** 2 + (j + Fraction(1, 2) - pcy) ** 2 < rp2
+    return inside
+
+
+@pytest.mark.parametrize("rep,given,expect", [(scenes.Options().representation, Fraction(5, 2), Fraction(5, 2)),
+                                              (3, Fraction(5, 4), Fraction(5, 2)),      # SAS: 1.25 + 1.25
+                                              (2, Fraction(5, 2), Fraction(3, 4))])     # sticks: bond radius
+def test_representation_sphere_radius(oracle, rep, given, expect):
+    W, H, hh = 64, 64, 8
+    cx, cy = Fraction(7, 16), Fraction(-5, 8)
+    cam = ortho(eye=(0.0, 0.0, 30.0), target=(0.0, 0.0, 0.0), half_h=float(hh))
+    sc = make_scene([(float(cx), float(cy), 0.0)], [float(given)])
+    opts = scenes.Options(representation=rep, probe_radius=1.25, bond_radius=0.75)
+    g = oracle.gbuffer(sc, cam, opts, W, H)
+    inside = _disk_count(W, H, hh, cx, cy, expect)
+    assert np.array_equal(g["id"] == 0, inside)
+    # the pixel nearest the centre sees the front of a sphere of radius `expect`
+    j, i = int(Fraction(H, 2) - cy * Fraction(H, 2) / hh), int(Fraction(W, 2) + cx * Fraction(H, 2) / hh)
+    x = (Fraction(2 * i + 1, W) - 1) * Fraction(W, H) * hh
+    y = (1 - Fraction(2 * j + 1, H)) * hh
+    dz2 = expect ** 2 - (x - cx) ** 2 - (y - cy) ** 2
+    assert abs(g["z"][j, i] - float(30 - mpmath.sqrt(mpmath.mpf(dz2.numerator) / dz2.denominator))) <= 1e-12 * 30
+
+
+def test_representations_without_bonds_keep_ids(oracle):
+    cam = persp(eye=(0.0, 0.0, 40.0), target=(0.0, 0.0, 0.0))
+    sc = make_scene([(-4.0, 0.0, 0.0), (4.0, 0.0, 0.0)], [1.0, 1.5], bonds=[(0, 1)])
+    for rep, has_bond in ((0, True), (1, False), (3, False), (2, True)):
+        g = oracle.gbuffer(sc, cam, scenes.Options(representation=rep, bond_radius=0.5), 96, 64)
+        ids = set(np.unique(g["id"]).tolist())
+        assert ids - {BG} == ({0, 1, 2} if has_bond else {0, 1}), rep
