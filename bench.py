@@ -180,7 +180,7 @@ class BatchRunner:
                 W, H = viewports[k]
                 self.renders.append(Render(vtx, f, cams[k], opts, W, H))
         self.arrays = {}
-        self.graph = vtx.vtx_batch_graph_create(self.ctx, self.jobs(0)[0])
+        self.graph = None   # captured at the first step (after any tuning)
         self.launch_form = (f"hipGraph of the {len(self.renders)}-render batch (vtx_batch_graph_launch: one graph "
                             f"launch per step)")
         self.other_forms = [("vtx_render_batch of the same renders, launched eagerly", self.eager_step),
@@ -197,6 +197,8 @@ class BatchRunner:
 
     def step(self, flags=0):
         if flags == 0:
+            if self.graph is None:
+                self.graph = self.vtx.vtx_batch_graph_create(self.ctx, self.jobs(0)[0])
             self.vtx.vtx_batch_graph_launch(self.graph, self.stream)
         else:   # statistics and per-kernel events run the same kernels eagerly
             self.vtx.vtx_render_batch(self.ctx, self.jobs(flags)[0], self.stream)
@@ -212,7 +214,8 @@ class BatchRunner:
         return self.vtx.vtx_autotune(self.ctx, self.jobs(0)[0], cache, self.stream)
 
     def close(self):
-        self.vtx.vtx_batch_graph_destroy(self.graph)
+        if self.graph is not None:
+            self.vtx.vtx_batch_graph_destroy(self.graph)
         self.rs.close()
         self.vtx.vtx_context_destroy(self.ctx)
 
@@ -432,9 +435,10 @@ def main():
     ap.add_argument("--kernel-events", choices=["timed", "separate"], default="separate",
                     help="record the per-kernel HIP events inside the timed region, or in a separate "
                          "pass of the same length after it")
-    ap.add_argument("--autotune", action="store_true",
-                    help="choose the tile size with vtx_autotune on the workload's renders before timing "
-                         "(renders that leave tile_size at 0 then use it)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: choose the tile size with vtx_autotune on the workload's renders before timing "
+                         "(resident-scene and batch forms; renders that leave tile_size at 0 then use it); "
+                         "0: the library default (16, raised for large images)")
     ap.add_argument("--tuning-cache", default=None, help="JSON cache file for --autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -492,9 +496,7 @@ def main():
     config["launch"] = runner.launch_form
     R = len(runner.renders)
     tuning = None
-    if args.autotune:
-        if args.tile:
-            raise SystemExit("--autotune and --tile exclude each other")
+    if args.autotune and not args.tile and (batch or args.path == "scene"):
         tuning = runner.autotune(args.tuning_cache)
         log(f"autotune: {tuning}")
         for r in runner.renders:
