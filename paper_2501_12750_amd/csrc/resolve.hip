@@ -29,6 +29,9 @@ constexpr int kBuckets = 32;      // depth buckets of the front-to-back record o
 constexpr int kSortArea = 16;     // order a chunk when its kept records average more pixels than this
 constexpr int kKeptShift = 21;    // packed scan: footprint area (<= 256 * 64 * 64) below, kept count above
 constexpr uint32_t kAreaMask = (1u << kKeptShift) - 1u;
+constexpr int kMaxSub = 32;       // records per depth-ordered sub-chunk: 16 or 32
+static_assert((kBlock / 64) * (kMaxSub + 1) <= kChunk + 1, "sub-chunk prefixes fit in the chunk prefix");
+static_assert(kBlock == kChunk, "one 64-slot window per wave in the order array");
 template <int TS>
 struct HzGrid {
     static constexpr int kBlocks = (TS / 4) * (TS / 4);
@@ -46,6 +49,18 @@ struct Rec {
 __device__ inline float wave_max(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Inclusive max-scan over the 64 lanes of a wave by DPP row shifts and row
+// broadcasts (lanes shifted in from outside a row read 0, the identity).
+__device__ inline uint32_t wave_incl_max(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));   // row_shr:1
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));   // row_shr:2
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));   // row_shr:4
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));   // row_shr:8
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));   // row_bcast:31
     return v;
 }
 
@@ -163,7 +178,11 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
     __shared__ uint32_t hz[kHzBlocks];
     __shared__ float red_lo[kBlock / 64], red_hi[kBlock / 64];
     __shared__ uint32_t bcnt[kBuckets], bbase[kBuckets];
-    __shared__ uint8_t ord[kChunk];   // depth-ordered chunk: record slots front to back
+    // depth-ordered chunk: record slots front to back.  Chunks resolved in
+    // list order use it instead as 64 slots per wave, slot i holding j when
+    // record j's first fragment is the i-th of the 64 the wave resolves
+    // next, else 0 (all 0 between uses).
+    __shared__ __align__(16) uint8_t ord[kChunk];
 
     const Frame F = J.F;
     uint32_t* __restrict__ const cnt = J.bb.tile_cnt;
@@ -178,7 +197,8 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
     float* __restrict__ const depth = J.depth;
     uint32_t* __restrict__ const out_id = J.id;
 
-    const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
+    const int tid = threadIdx.x, lane = __lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const bool stats = kCount && (F.flags & 1u) != 0;
     unsigned long long n_tested = 0, n_hit = 0, n_hit_bond = 0;
 
@@ -187,6 +207,7 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
         const int px0 = tx * TS, py0 = ty * TS;
         const int tw = min(TS, F.W - px0), th = min(TS, F.H - py0);
         for (int i = tid; i < TS * TS; i += kBlock) keys[i] = ~0ull;
+        if (tid < kChunk / 4) reinterpret_cast<uint32_t*>(ord)[tid] = 0u;
         const uint64_t nsrc = kTail ? (uint64_t)groups * chunk : n;
         const bool persp = F.proj == 0;
         __syncthreads();
@@ -264,18 +285,31 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
                 for (int bx = x0 >> 2; bx <= (x1 >> 2); ++bx) m = max(m, hz[by * (TS / 4) + bx]);
             return __float_as_uint(rc.zcull) > m && rc.zcull > 0.0f;
         };
-        auto rect_area = [](const Rec& rc) -> uint32_t { return ((rc.rect >> 16) & 0xFF) * (rc.rect >> 24); };
-        // refresh the block depths from the tile's depth buffer
-        auto hz_refresh = [&]() {
-            for (int i = tid; i < kHzBlocks; i += kBlock) hz[i] = 0u;
-            __syncthreads();
-            for (int i = tid; i < TS * TS; i += kBlock) {
-                const int ly = i / TS, lx = i - ly * TS;
-                const unsigned long long kk = keys[i];
-                // pixels outside the image never hold a hit: they do not
-                // bound the block
+        auto rect_area = [](uint32_t rect) -> uint32_t { return ((rect >> 16) & 0xFF) * (rect >> 24); };
+        // farthest depth (float bits) that 4 pixels of row r of 4x4 block
+        // (bx, by) hold: +inf while one is empty; pixels outside the image
+        // never hold a hit and do not bound the block
+        auto row_zmax = [&](int bx, int by, int r) -> uint32_t {
+            const int ly = by * 4 + r;
+            uint32_t m = 0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int lx = bx * 4 + c;
+                const unsigned long long kk = keys[ly * TS + lx];
                 const uint32_t zb = (lx < tw && ly < th) ? (kk == ~0ull ? 0x7F800000u : (uint32_t)(kk >> 32)) : 0u;
-                atomicMax(&hz[(ly >> 2) * (TS / 4) + (lx >> 2)], zb);
+                m = max(m, zb);
+            }
+            return m;
+        };
+        // refresh every block depth from the tile's depth buffer (the whole
+        // workgroup, after its writes): four lanes per block, one row each
+        auto hz_refresh = [&]() {
+            for (int u = tid; u < kHzBlocks * 4; u += kBlock) {
+                const int b = u >> 2;
+                uint32_t m = row_zmax(b % (TS / 4), b / (TS / 4), u & 3);
+                m = max(m, (uint32_t)__shfl_xor((int)m, 1));
+                m = max(m, (uint32_t)__shfl_xor((int)m, 2));
+                if ((u & 3) == 0) hz[b] = m;
             }
             __syncthreads();
         };
@@ -296,29 +330,142 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
             __syncthreads();
             return tot;
         };
-        // fragments f of records recs[map(j)], j < span, with prefix pref:
-        // dealt round-robin, so the 64 lanes of a wave take 64 consecutive
-        // fragments, i.e. neighbouring pixels of a few adjacent records, and
-        // early-out decisions agree across the wave
-        auto resolve_fragments = [&](int span, int rbase, bool indirect) {
+        // fragments f of the chunk's records recs[j] with prefix pref.
+        // Each wave takes an equal contiguous share and resolves it 64
+        // consecutive fragments at a time (neighbouring pixels of a few
+        // adjacent records, so early-out decisions agree across the wave).
+        // The owner of a fragment is the last record starting at or before
+        // it: one search finds it for the share's first fragment; after
+        // that the records starting within each step mark their first
+        // fragment in the wave's slots, and a max-scan over the lanes,
+        // seeded with the previous owner, gives every lane its record.
+        auto resolve_fragments = [&]() {
+            constexpr int span = kChunk;
             const uint32_t total = pref[kChunk];
-            for (uint32_t f = tid; f < total; f += kBlock) {
+            const uint32_t share = (total + kBlock - 1) / kBlock * 64;
+            const uint32_t q0 = min(total, (uint32_t)wave * share), q1 = min(total, q0 + share);
+            if (q0 < q1) {
                 int lo = 0, hi = span;
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) >> 1;
-                    if (pref[mid] <= f) lo = mid;
+                    if (pref[mid] <= q0) lo = mid;
                     else hi = mid;
                 }
-                const Rec& rr = recs[indirect ? (int)ord[rbase + lo] : lo];
-                const uint32_t local = f - pref[lo];
-                const uint32_t rw = (rr.rect >> 16) & 0xFF;
-                // exact: local < 4096 and rw <= 64, so the rounding error of
-                // (local + 1/2) / rw is far below its distance to an integer
-                const uint32_t dy = (uint32_t)(((float)local + 0.5f) * __builtin_amdgcn_rcpf((float)rw));
-                const uint32_t dx = local - dy * rw;
-                test_pixel(rr, (int)(rr.rect & 0xFF) + (int)dx, (int)((rr.rect >> 8) & 0xFF) + (int)dy);
+                uint32_t own = (uint32_t)__builtin_amdgcn_readfirstlane(lo);
+                uint8_t* const st = ord + wave * 64;
+                for (uint32_t f0 = q0; f0 < q1; f0 += 64) {
+                    // records after `own` start at or after f0, in order: mark
+                    // those with fragments that start before f0 + 64
+                    for (uint32_t j0 = own + 1;; j0 += 64) {
+                        const uint32_t j = j0 + (uint32_t)lane;
+                        uint32_t e = ~0u;
+                        bool some = false;
+                        if (j < (uint32_t)span) {
+                            e = pref[j];
+                            some = pref[j + 1] > e;
+                        }
+                        const bool in = e < f0 + 64;
+                        if (in && some) st[e - f0] = (uint8_t)j;
+                        if (!__all(in)) break;
+                    }
+                    // the wave's own LDS writes are seen by its later reads
+                    __builtin_amdgcn_wave_barrier();
+                    uint32_t m = st[lane];
+                    if (m) st[lane] = 0;
+                    m = max(wave_incl_max(m), own);
+                    own = (uint32_t)__builtin_amdgcn_readlane((int)m, 63);
+                    const uint32_t f = f0 + (uint32_t)lane;
+                    if (f < q1) {
+                        const Rec& rr = recs[m];
+                        const uint32_t local = f - pref[m];
+                        const uint32_t rw = (rr.rect >> 16) & 0xFF;
+                        // exact: local < 4096 and rw <= 64, so the rounding error of
+                        // (local + 1/2) / rw is far below its distance to an integer
+                        const uint32_t dy = (uint32_t)(((float)local + 0.5f) * __builtin_amdgcn_rcpf((float)rw));
+                        const uint32_t dx = local - dy * rw;
+                        test_pixel(rr, (int)(rr.rect & 0xFF) + (int)dx, (int)((rr.rect >> 8) & 0xFF) + (int)dy);
+                    }
+                }
             }
             __syncthreads();
+        };
+        // The kept records of a chunk in depth order (ord), resolved `sub`
+        // at a time, front to back.  Every wave culls the sub-chunk against
+        // the block depths (2 or 4 lanes per record; all waves read the same
+        // depths, so they agree) and takes the prefix of the survivors'
+        // footprints in its own slots; the workgroup resolves their
+        // fragments, then refreshes the blocks under them before the next
+        // sub-chunk is culled.
+        auto resolve_sorted = [&](uint32_t nk, int sub, bool more) {
+            const uint32_t nsub = (nk + (uint32_t)sub - 1) / (uint32_t)sub;
+            const int lg = sub == 16 ? 2 : 1;   // log2 of the lanes per record
+            // the chunk's prefix is no longer needed: each wave keeps its
+            // sub-chunk prefix in a slice of it
+            uint32_t* const wp = pref + wave * (kMaxSub + 1);
+            for (uint32_t sc = 0; sc < nsub; ++sc) {
+                const uint32_t rbase = sc * (uint32_t)sub;
+                const uint32_t i = (uint32_t)lane >> lg;
+                const bool real = rbase + i < nk;
+                uint32_t rect = 0;
+                float zcull = 0.0f;
+                if (real) {
+                    const Rec& r = recs[ord[rbase + i]];
+                    rect = r.rect;
+                    zcull = r.zcull;
+                }
+                const int bx0 = (int)(rect & 0xFF) >> 2, by0 = (int)((rect >> 8) & 0xFF) >> 2;
+                const int bx1 = ((int)(rect & 0xFF) + (int)((rect >> 16) & 0xFF) - 1) >> 2;
+                const int by1 = ((int)((rect >> 8) & 0xFF) + (int)(rect >> 24) - 1) >> 2;
+                // the first sub-chunk was culled with the chunk, against the
+                // same block depths
+                uint32_t m = 0;
+                if (real && sc > 0)
+                    for (int by = by0 + (lane & ((1 << lg) - 1)); by <= by1; by += 1 << lg)
+                        for (int bx = bx0; bx <= bx1; ++bx) m = max(m, hz[by * (TS / 4) + bx]);
+                m = max(m, (uint32_t)__shfl_xor((int)m, 1));
+                if (lg == 2) m = max(m, (uint32_t)__shfl_xor((int)m, 2));
+                const bool live = real && !(sc > 0 && __float_as_uint(zcull) > m && zcull > 0.0f);
+                // blocks under the live records (their union rectangle)
+                const uint32_t ux0 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(live ? 255u - bx0 : 0u), 63);
+                const uint32_t uy0 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(live ? 255u - by0 : 0u), 63);
+                const uint32_t ux1 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(live ? bx1 + 1u : 0u), 63);
+                const uint32_t uy1 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(live ? by1 + 1u : 0u), 63);
+                // record i's footprint to lane i, then its prefix
+                const uint32_t ag = (uint32_t)__shfl((int)(live ? rect_area(rect) : 0u), (lane << lg) & 63);
+                const uint32_t incl = wave_incl_scan(lane < sub ? ag : 0u);
+                if (lane < sub) wp[lane + 1] = incl;
+                if (lane == 0) wp[0] = 0u;
+                const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, sub - 1);
+                __builtin_amdgcn_wave_barrier();
+                for (uint32_t f = (uint32_t)tid; f < total; f += kBlock) {
+                    int lo = 0, hi = sub;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (wp[mid] <= f) lo = mid;
+                        else hi = mid;
+                    }
+                    const Rec& rr = recs[ord[rbase + (uint32_t)lo]];
+                    const uint32_t local = f - wp[lo];
+                    const uint32_t rw = (rr.rect >> 16) & 0xFF;
+                    const uint32_t dy = (uint32_t)(((float)local + 0.5f) * __builtin_amdgcn_rcpf((float)rw));
+                    const uint32_t dx = local - dy * rw;
+                    test_pixel(rr, (int)(rr.rect & 0xFF) + (int)dx, (int)((rr.rect >> 8) & 0xFF) + (int)dy);
+                }
+                if (sc + 1 == nsub && !more) break;
+                __syncthreads();   // the sub-chunk's hits are in the depth buffer
+                if (ux1 > 0) {
+                    const int cx0 = 255 - (int)ux0, cy0 = 255 - (int)uy0;
+                    const int bw = (int)ux1 - cx0, nb = bw * ((int)uy1 - cy0);
+                    for (int k = tid; k < 4 * nb; k += kBlock) {
+                        const int b = k >> 2, by = cy0 + b / bw, bx = cx0 + b % bw;
+                        uint32_t z = row_zmax(bx, by, k & 3);
+                        z = max(z, (uint32_t)__shfl_xor((int)z, 1));
+                        z = max(z, (uint32_t)__shfl_xor((int)z, 2));
+                        if ((k & 3) == 0) hz[by * (TS / 4) + bx] = z;
+                    }
+                }
+                __syncthreads();   // refreshed block depths are in LDS
+            }
         };
         for (uint64_t base = 0; base < nsrc; base += kChunk) {
             PrimRec pr = nxt;
@@ -336,7 +483,7 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
                 const Rec rc = make_rec(F, pr);
                 keep = stats || !hz_culled(rc);
                 if (keep) {
-                    area = rect_area(rc);
+                    area = rect_area(rc.rect);
                     zc = rc.zcull;
                     recs[tid] = rc;
                 }
@@ -356,7 +503,7 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
             const int sub = atot >= 64u * nk ? 16 : 32;
             const bool sorted = !stats && nk > (uint32_t)sub && atot > (uint32_t)kSortArea * nk;
             if (!sorted) {
-                resolve_fragments(kChunk, 0, false);
+                resolve_fragments();
                 if (!stats && more) hz_refresh();
                 continue;
             }
@@ -390,20 +537,10 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
             }
             __syncthreads();
             if (keep) ord[bbase[bk] + atomicAdd(&bcnt[bk], 1u)] = (uint8_t)tid;
-            const int nsub = (int)((nk + sub - 1) / sub);
-            for (int sc = 0; sc < nsub; ++sc) {
-                const int rbase = sc * sub;
-                __syncthreads();   // the order (and a refreshed hz) are in LDS
-                uint32_t a = 0;
-                const uint32_t j = (uint32_t)(rbase + tid);
-                if (tid < sub && j < nk) {
-                    const Rec& r2 = recs[ord[j]];
-                    a = (sc > 0 && hz_culled(r2)) ? 0u : rect_area(r2);
-                }
-                block_scan(a);
-                resolve_fragments(sub, rbase, true);
-                if (sc + 1 < nsub || more) hz_refresh();
-            }
+            __syncthreads();   // the order is in LDS
+            resolve_sorted(nk, sub, more);
+            __syncthreads();   // every wave is done with this chunk's records
+            if (tid < kChunk / 4) reinterpret_cast<uint32_t*>(ord)[tid] = 0u;
         }
         __syncthreads();
 
