@@ -814,7 +814,12 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
         const vtx::Job* dj = reinterpret_cast<const vtx::Job*>(ws->d_tab) + first;
         const vtx::SampleKernel* dk = reinterpret_cast<const vtx::SampleKernel*>(ws->d_tab + k_off) + first;
         const uint32_t* ds = reinterpret_cast<const uint32_t*>(ws->d_tab + s_off) + start_index;
-        return vtx::JobList{dj, dk, ds, (uint32_t)count};
+        // jobs of one size (a batch of equal views): the job of a block is a
+        // division rather than a search of the start table
+        uint32_t per = starts[start_index + 1] - starts[start_index];
+        for (size_t i = 1; per && i <= count; ++i)
+            if (starts[start_index + i] - starts[start_index] != (uint32_t)i * per) per = 0;
+        return vtx::JobList{dj, dk, ds, (uint32_t)count, per};
     };
     if (n > 1 && capture) {
         // the tables must be the ones the eager call uploaded

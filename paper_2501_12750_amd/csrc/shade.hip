@@ -8,8 +8,9 @@
 // position is rebuilt from its ray and depth, and its normal and colour from
 // the primitive named by id, so no normal or colour buffer is stored.  The
 // occlusion test of each hemisphere sample reads the depth at the sample's
-// pixel: a 16x16 tile with a 16-pixel halo is staged in LDS and samples that
-// land farther away read the depth buffer through the cache.
+// pixel through the cache: the samples of neighbouring pixels land on
+// neighbouring pixels, which the cache holds (staging a haloed tile in LDS
+// measured slower than the cached reads it saves).
 #include "vtx_internal.h"
 
 namespace vtx {
@@ -17,8 +18,6 @@ namespace vtx {
 namespace {
 
 constexpr int kTile = 16;
-constexpr int kHalo = 16;
-constexpr int kSpan = kTile + 2 * kHalo;
 
 constexpr float kKa = 0.2f, kKd = 0.8f, kKs = 0.25f;
 
@@ -35,7 +34,6 @@ __device__ inline uint32_t quantize(float c) {
 // Work block t of a job is that job's 16x16 tile t.
 template <class JS>
 __global__ void __launch_bounds__(kBlock) k_shade(JS js) {
-    __shared__ float zt[kSpan * kSpan];
     uint32_t tu;
     const int ji = js.find((uint32_t)xcd_contiguous(blockIdx.x, gridDim.x), tu);
     if (ji < 0) return;
@@ -55,14 +53,6 @@ __global__ void __launch_bounds__(kBlock) k_shade(JS js) {
     const int t = (int)tu;
     const int tid = threadIdx.x;
     const int tx0 = (t % tiles_x) * kTile, ty0 = (t / tiles_x) * kTile;
-    const int bx0 = tx0 - kHalo, by0 = ty0 - kHalo;
-    if (K.count > 0) {
-        for (int i = tid; i < kSpan * kSpan; i += kBlock) {
-            const int yy = by0 + i / kSpan, xx = bx0 + i % kSpan;
-            zt[i] = (xx >= 0 && xx < F.W && yy >= 0 && yy < F.H) ? depth[(size_t)yy * F.W + xx] : INFINITY;
-        }
-        __syncthreads();
-    }
     const int x = tx0 + (tid & (kTile - 1)), y = ty0 + (tid >> 4);
     if (x >= F.W || y >= F.H) return;
     const size_t p = (size_t)y * F.W + x;
@@ -162,9 +152,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(JS js) {
             }
             if (!(spx >= 0.0f && spx < (float)F.W && spy >= 0.0f && spy < (float)F.H)) continue;
             const int qx = (int)spx, qy = (int)spy;
-            const int lx = qx - bx0, ly = qy - by0;
-            const float zq = (lx >= 0 && lx < kSpan && ly >= 0 && ly < kSpan) ? zt[ly * kSpan + lx]
-                                                                              : depth[(size_t)qy * F.W + qx];
+            const float zq = depth[(size_t)qy * F.W + qx];
             if (zq <= Sz - K.bias) occ += smooth01(K.radius * __builtin_amdgcn_rcpf(fabsf(Pz - zq)));
         }
         ao = 1.0f - occ / (float)K.count;

@@ -322,7 +322,14 @@ struct JobList {
     const SampleKernel* K;
     const uint32_t* start;   // n + 1 entries
     uint32_t n;
+    uint32_t per;            // when every job has this many blocks (else 0): job g / per
     __device__ int find(uint32_t g, uint32_t& local) const {
+        if (per) {
+            if (g >= n * per) return -1;
+            const uint32_t i = g / per;
+            local = g - i * per;
+            return (int)i;
+        }
         if (g >= start[n]) return -1;
         uint32_t lo = 0, hi = n;   // the last i with start[i] <= g (jobs without blocks are skipped)
         while (hi - lo > 1) {
