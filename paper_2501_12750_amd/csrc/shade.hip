@@ -18,6 +18,7 @@ namespace vtx {
 namespace {
 
 constexpr int kTile = 16;
+constexpr int kBatch = 8;   // SSAO samples whose depth loads are issued together
 
 constexpr float kKa = 0.2f, kKd = 0.8f, kKs = 0.25f;
 
@@ -131,29 +132,42 @@ __global__ void __launch_bounds__(kBlock) k_shade(JS js) {
         const float fpx = 0.5f * (float)F.H / F.tyf;
         const float osc = 0.5f * (float)F.H / F.hyf;
         float occ = 0.0f;
-        for (int k = 0; k < K.count; ++k) {
-            const float4 h = K.h[k];
-            const float sr = K.radius * h.w;
-            const float dx = fmaf(h.x, Tx, fmaf(h.y, Bx, h.z * nx));
-            const float dy = fmaf(h.x, Ty, fmaf(h.y, By, h.z * ny));
-            const float dz = fmaf(h.x, Tz, fmaf(h.y, Bz, h.z * nz));
-            const float Sx = fmaf(sr, dx, Px), Sy = fmaf(sr, dy, Py), Sz = fmaf(sr, dz, Pz);
-            if (!(Sz > F.znear)) continue;
-            float spx, spy;
-            if (F.proj == 0) {
-                // hardware reciprocal (1 ulp): moves the sample by far less than
-                // the 1e-3 px within which a pixel edge makes a sample unstable
-                const float iz = fpx * __builtin_amdgcn_rcpf(Sz);
-                spx = fmaf(Sx, iz, 0.5f * (float)F.W);
-                spy = fmaf(-Sy, iz, 0.5f * (float)F.H);
-            } else {
-                spx = fmaf(Sx, osc, 0.5f * (float)F.W);
-                spy = fmaf(-Sy, osc, 0.5f * (float)F.H);
+        // samples are taken kBatch at a time: every address first, then
+        // the loads, then the tests in sample order, so the loads of a batch
+        // are in flight together
+        for (int k0 = 0; k0 < K.count; k0 += kBatch) {
+            float zq[kBatch], sz[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int k = k0 + u;
+                zq[u] = INFINITY;
+                sz[u] = -INFINITY;   // no sample
+                if (k >= K.count) continue;
+                const float4 h = K.h[k];
+                const float sr = K.radius * h.w;
+                const float dx = fmaf(h.x, Tx, fmaf(h.y, Bx, h.z * nx));
+                const float dy = fmaf(h.x, Ty, fmaf(h.y, By, h.z * ny));
+                const float dz = fmaf(h.x, Tz, fmaf(h.y, Bz, h.z * nz));
+                const float Sx = fmaf(sr, dx, Px), Sy = fmaf(sr, dy, Py), Sz = fmaf(sr, dz, Pz);
+                if (!(Sz > F.znear)) continue;
+                float spx, spy;
+                if (F.proj == 0) {
+                    // hardware reciprocal (1 ulp): moves the sample by far less than
+                    // the 1e-3 px within which a pixel edge makes a sample unstable
+                    const float iz = fpx * __builtin_amdgcn_rcpf(Sz);
+                    spx = fmaf(Sx, iz, 0.5f * (float)F.W);
+                    spy = fmaf(-Sy, iz, 0.5f * (float)F.H);
+                } else {
+                    spx = fmaf(Sx, osc, 0.5f * (float)F.W);
+                    spy = fmaf(-Sy, osc, 0.5f * (float)F.H);
+                }
+                if (!(spx >= 0.0f && spx < (float)F.W && spy >= 0.0f && spy < (float)F.H)) continue;
+                zq[u] = depth[(size_t)(int)spy * F.W + (int)spx];
+                sz[u] = Sz;
             }
-            if (!(spx >= 0.0f && spx < (float)F.W && spy >= 0.0f && spy < (float)F.H)) continue;
-            const int qx = (int)spx, qy = (int)spy;
-            const float zq = depth[(size_t)qy * F.W + qx];
-            if (zq <= Sz - K.bias) occ += smooth01(K.radius * __builtin_amdgcn_rcpf(fabsf(Pz - zq)));
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u)
+                if (zq[u] <= sz[u] - K.bias) occ += smooth01(K.radius * __builtin_amdgcn_rcpf(fabsf(Pz - zq[u])));
         }
         ao = 1.0f - occ / (float)K.count;
     }
