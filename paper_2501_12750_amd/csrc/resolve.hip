@@ -26,7 +26,7 @@ namespace {
 constexpr int kChunk = kBlock;
 constexpr unsigned kTailBlocks = 256;   // grid of the overflow (tail) launch
 constexpr int kBuckets = 32;      // depth buckets of the front-to-back record order
-constexpr int kSortArea = 16;     // order a chunk when its kept records average more pixels than this
+constexpr int kSortArea = 64;     // order a chunk when its kept records average more pixels than this
 constexpr int kKeptShift = 21;    // packed scan: footprint area (<= 256 * 64 * 64) below, kept count above
 constexpr uint32_t kAreaMask = (1u << kKeptShift) - 1u;
 constexpr int kMaxSub = 32;       // records per depth-ordered sub-chunk: 16 or 32
@@ -64,13 +64,14 @@ __device__ inline uint32_t wave_incl_max(uint32_t v) {
     return v;
 }
 
+// Inclusive sum-scan over the 64 lanes of a wave, the same DPP steps.
 __device__ inline uint32_t wave_incl_scan(uint32_t v) {
-    const int lane = __lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t t = __shfl_up(v, o);
-        if (lane >= o) v += t;
-    }
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);   // row_bcast:31
     return v;
 }
 
@@ -184,6 +185,10 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
     // next, else 0 (all 0 between uses).
     __shared__ __align__(16) uint8_t ord[kChunk];
 
+    // record slot j < kChunk, addressed with a 24-bit multiply (full rate)
+    auto rec_at = [&](uint32_t j) -> const Rec& {
+        return *reinterpret_cast<const Rec*>(reinterpret_cast<const char*>(recs) + __umul24(j, (uint32_t)sizeof(Rec)));
+    };
     const Frame F = J.F;
     uint32_t* __restrict__ const cnt = J.bb.tile_cnt;
     const PrimRec* __restrict__ const list = J.bb.list;
@@ -376,13 +381,13 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
                     own = (uint32_t)__builtin_amdgcn_readlane((int)m, 63);
                     const uint32_t f = f0 + (uint32_t)lane;
                     if (f < q1) {
-                        const Rec& rr = recs[m];
+                        const Rec& rr = rec_at(m);
                         const uint32_t local = f - pref[m];
                         const uint32_t rw = (rr.rect >> 16) & 0xFF;
                         // exact: local < 4096 and rw <= 64, so the rounding error of
                         // (local + 1/2) / rw is far below its distance to an integer
                         const uint32_t dy = (uint32_t)(((float)local + 0.5f) * __builtin_amdgcn_rcpf((float)rw));
-                        const uint32_t dx = local - dy * rw;
+                        const uint32_t dx = local - __umul24(dy, rw);
                         test_pixel(rr, (int)(rr.rect & 0xFF) + (int)dx, (int)((rr.rect >> 8) & 0xFF) + (int)dy);
                     }
                 }
@@ -444,11 +449,11 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
                         if (wp[mid] <= f) lo = mid;
                         else hi = mid;
                     }
-                    const Rec& rr = recs[ord[rbase + (uint32_t)lo]];
+                    const Rec& rr = rec_at(ord[rbase + (uint32_t)lo]);
                     const uint32_t local = f - wp[lo];
                     const uint32_t rw = (rr.rect >> 16) & 0xFF;
                     const uint32_t dy = (uint32_t)(((float)local + 0.5f) * __builtin_amdgcn_rcpf((float)rw));
-                    const uint32_t dx = local - dy * rw;
+                    const uint32_t dx = local - __umul24(dy, rw);
                     test_pixel(rr, (int)(rr.rect & 0xFF) + (int)dx, (int)((rr.rect >> 8) & 0xFF) + (int)dy);
                 }
                 if (sc + 1 == nsub && !more) break;

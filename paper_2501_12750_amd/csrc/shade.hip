@@ -18,7 +18,7 @@ namespace vtx {
 namespace {
 
 constexpr int kTile = 16;
-constexpr int kBatch = 8;   // SSAO samples whose depth loads are issued together
+constexpr int kBatch = 16;  // SSAO samples whose depth loads are issued together
 
 constexpr float kKa = 0.2f, kKd = 0.8f, kKs = 0.25f;
 
