@@ -1039,7 +1039,7 @@ size_t vtx_frame_scratch_bytes(int32_t W, int32_t H, int64_t n_atoms, int64_t n_
     uint64_t cap = nprim / 2;
     if (cap < kMinCapacity) cap = kMinCapacity;
     return (size_t)(T * 16 + (uint64_t)groups * chunk * (sizeof(uint32_t) + sizeof(uint2)) +
-                    (uint64_t)groups * T * 4 + cap * sizeof(vtx::PrimRec) + scene_clusters(n_atoms, n_bonds) * 4 +
+                    (uint64_t)groups * T * 4 + cap * sizeof(uint2) + scene_clusters(n_atoms, n_bonds) * 4 +
                     sizeof(Counters) + 4096);
 }
 

@@ -13,7 +13,10 @@
 //   scatter  each workgroup rebuilds the exclusive prefix sum of the tile
 //            counts (list offsets), reserves, per touched tile, one run of the
 //            tile's list (one atomic), then places its primitives with LDS
-//            atomics.
+//            atomics: 8 bytes per (primitive, tile), the source index and the
+//            footprint clipped to the tile.  The resolve rebuilds each
+//            record from its source, so the view-space record is never
+//            written out.
 // So the global atomics scale with (workgroup, touched tile) pairs rather
 // than with (primitive, tile) pairs.  Lists that would not fit the bin
 // capacity are left empty; the resolve pass then finds those tiles' primitives
@@ -246,7 +249,7 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js) {
     const uint32_t* __restrict__ const cnt = J.bb.tile_cnt;
     uint64_t* __restrict__ const off = J.bb.tile_off;
     uint32_t* const fill = J.bb.tile_fill;
-    PrimRec* __restrict__ const list = J.bb.list;
+    uint2* __restrict__ const list = J.bb.list;
     const uint64_t capacity = J.bb.capacity;
     Counters* const ctr = J.bb.ctr;
     Counters* const host_ctr = J.bb.host_ctr;
@@ -326,30 +329,22 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js) {
                ((uint32_t)(ly1 - ly0 + 1) << 24);
     };
     const uint32_t rounds = (n + kBinThreads - 1) / kBinThreads;   // uniform trip count (wave ops inside)
-    // Each visible primitive's record is rebuilt from its source (the same
-    // computation as in the count pass), which costs less than storing 32
-    // bytes per primitive there and reading them back here.
-    Item prim = empty_item();
+    uint32_t src = 0;
     uint2 r = make_uint2(0u, 0u);
     if ((uint32_t)tid < n) {
-        prim = fetch_src(J, vis_src[start + tid]);
+        src = vis_src[start + tid];
         r = vis_rect[start + tid];
     }
     for (uint32_t it = 0; it < rounds; ++it) {
         const uint32_t k = it * kBinThreads + tid;
         const bool have = k < n;
         // the next primitive is loaded while this one is placed
-        Item nxt = empty_item();
+        uint32_t nsrc = 0;
         uint2 nr = make_uint2(0u, 0u);
         if (k + kBinThreads < n) {
-            nxt = fetch_src(J, vis_src[start + k + kBinThreads]);
+            nsrc = vis_src[start + k + kBinThreads];
             nr = vis_rect[start + k + kBinThreads];
         }
-        PrimRec rec;
-        double v[6], rr = 0.0;
-        if (have) item_view(F, prim, rec, v, rr);   // visible in the count pass, so true here
-        const float4 g0 = rec.g0;
-        const uint4 g1 = rec.g1;
         const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16;
         const int tx0 = x0 >> tsh, tx1 = x1 >> tsh, ty0 = y0 >> tsh, ty1 = y1 >> tsh;
         const bool single = have && tx0 == tx1 && ty0 == ty1;
@@ -374,22 +369,16 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js) {
         }
         if (single) {
             if ((pend >> __lane_id()) & 1ull) my_slot = cur[t1] == kNoRun ? kNoRun : atomicAdd(&cur[t1], 1u);
-            if (my_slot != kNoRun) {
-                PrimRec* dst = &list[my_slot];
-                dst->g0 = g0;
-                dst->g1 = make_uint4(g1.x, g1.y, g1.z, local_fp(x0, y0, x1, y1, tx0, ty0));
-            }
+            if (my_slot != kNoRun) list[my_slot] = make_uint2(src, local_fp(x0, y0, x1, y1, tx0, ty0));
         } else if (have) {
             for (int ty = ty0; ty <= ty1; ++ty)
                 for (int tx = tx0; tx <= tx1; ++tx) {
                     const int t = ty * F.tiles_x + tx;
                     if (cur[t] == kNoRun) continue;
-                    PrimRec* dst = &list[atomicAdd(&cur[t], 1u)];
-                    dst->g0 = g0;
-                    dst->g1 = make_uint4(g1.x, g1.y, g1.z, local_fp(x0, y0, x1, y1, tx, ty));
+                    list[atomicAdd(&cur[t], 1u)] = make_uint2(src, local_fp(x0, y0, x1, y1, tx, ty));
                 }
         }
-        prim = nxt;
+        src = nsrc;
         r = nr;
     }
 }

@@ -95,7 +95,9 @@ __device__ inline bool item_view(const Frame& F, const Item& it, PrimRec& rec, d
     // the difference B - A is kept from FP64, so the axis is accurate however
     // far the bond is
     const double dx = v[3] - v[0], dy = v[4] - v[1], dz = v[5] - v[2];
-    const double half = 0.5 * sqrt(dx * dx + dy * dy + dz * dz);
+    // the half length only enters the frustum test, whose margin (1e-4
+    // relative) far exceeds the FP32 square root's error
+    const double half = 0.5 * (double)__builtin_amdgcn_sqrtf((float)(dx * dx + dy * dy + dz * dz));
     if (!sphere_in_frustum(F, v[0] + 0.5 * dx, v[1] + 0.5 * dy, v[2] + 0.5 * dz, half + r)) return false;
     rec.g0 = make_float4((float)v[0], (float)v[1], (float)v[2], (float)dx);
     rec.g1 = make_uint4(__float_as_uint((float)dy), __float_as_uint((float)dz), it.id, 0u);

@@ -153,13 +153,12 @@ __device__ inline Rec make_rec(const Frame& F, const PrimRec& p) {
     return r;
 }
 
-// Record of a visible primitive rebuilt from its source, for tiles whose list
-// overflowed.
-__device__ inline PrimRec overflow_record(const Job& J, uint32_t src) {
-    PrimRec pr;
+// View-space record of a visible primitive, rebuilt from its source (the
+// tile lists hold only source indices and footprints).  False only if the
+// primitive is not visible, which the count pass has already excluded.
+__device__ inline bool source_record(const Job& J, uint32_t src, PrimRec& pr) {
     double v[6], rr;
-    item_view(J.F, fetch_src(J, src), pr, v, rr);   // true: it was visible in the count pass
-    return pr;
+    return item_view(J.F, fetch_src(J, src), pr, v, rr);
 }
 
 // Work block t of a job is that job's tile t; the launch's blocks are spread
@@ -191,7 +190,7 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
     };
     const Frame F = J.F;
     uint32_t* __restrict__ const cnt = J.bb.tile_cnt;
-    const PrimRec* __restrict__ const list = J.bb.list;
+    const uint2* __restrict__ const list = J.bb.list;
     const uint32_t* __restrict__ const vis_src = J.bb.vis_src;
     const uint2* __restrict__ const vis_rect = J.bb.vis_rect;
     const uint32_t* __restrict__ const vis_cnt = J.bb.vis_cnt;
@@ -262,7 +261,7 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
             const int x1 = min((int)(r.y & 0xFFFF), px0 + TS - 1) - px0;
             const int y1 = min((int)(r.y >> 16), py0 + TS - 1) - py0;
             if (x0 > x1 || y0 > y1) return false;
-            pr = overflow_record(J, vis_src[k]);
+            if (!source_record(J, vis_src[k], pr)) return false;
             pr.g1.w = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)(x1 - x0 + 1) << 16) |
                       ((uint32_t)(y1 - y0 + 1) << 24);
             return true;
@@ -276,7 +275,7 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
         // records are loaded while this chunk is resolved.
         // A list's next chunk is loaded while this one is resolved; the
         // overflow path loads each chunk when it starts.
-        PrimRec nxt;
+        uint2 nxt = make_uint2(0u, 0u);
         bool nxt_ok = !kTail && (uint64_t)tid < nsrc;
         if (nxt_ok) nxt = list[o + tid];
         __syncthreads();
@@ -473,11 +472,14 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
             }
         };
         for (uint64_t base = 0; base < nsrc; base += kChunk) {
-            PrimRec pr = nxt;
-            bool have = nxt_ok;
+            PrimRec pr;
+            bool have;
             if constexpr (kTail) {
                 have = base + tid < nsrc && fetch_overflow(base + tid, pr);
             } else {
+                const uint2 e = nxt;
+                have = nxt_ok && source_record(J, e.x, pr);
+                pr.g1.w = e.y;
                 nxt_ok = base + kChunk + tid < nsrc;
                 if (nxt_ok) nxt = list[o + base + kChunk + tid];
             }

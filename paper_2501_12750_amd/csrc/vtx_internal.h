@@ -231,13 +231,13 @@ struct BinBuffers {
     uint32_t* tile_cnt;     // T
     uint64_t* tile_off;     // T
     uint32_t* tile_fill;    // T
-    uint32_t* vis_src;      // groups * chunk: source index of each visible primitive (re-fetched by scatter)
+    uint32_t* vis_src;      // groups * chunk: source index of each visible primitive
     uint2* vis_rect;        // groups * chunk, pixel rectangle packed (x0 | y0 << 16, x1 | y1 << 16)
     uint32_t* vis_cnt;      // groups: visible primitives of each workgroup
     uint2* vis_box;         // groups: tile-space bounding box of each workgroup's visible
                             // primitives, packed like vis_rect (empty: x0 > x1)
     uint32_t* hist;         // groups * T: tile histogram of each workgroup
-    PrimRec* list;          // capacity entries, each tile's records contiguous
+    uint2* list;            // capacity entries (source index, tile-local footprint), each tile's contiguous
     uint64_t capacity;
     uint32_t groups, chunk;
     Counters* ctr;
