@@ -77,12 +77,14 @@ __device__ inline Item fetch_src(const Job& J, uint32_t src) {
 // View-space record of an item (FP64 view transform rounded once to FP32,
 // see PrimRec) and its FP64 view coordinates v (sphere: centre, radius in
 // r; bond: ends A = v[0..2], B = v[3..5]).  False when the item cannot show:
-// degenerate, or outside the view volume by the FP32 frustum test.
+// degenerate, or outside the view volume by the FP32 frustum test (kCull;
+// without it, for items that have passed the test before).
+template <bool kCull = true>
 __device__ inline bool item_view(const Frame& F, const Item& it, PrimRec& rec, double* v, double& r) {
     if (it.kind == kAtom) {
         to_view(F, it.a.x, it.a.y, it.a.z, v[0], v[1], v[2]);
         r = (double)atom_radius(F, it.a.w);
-        if (!(r > 0.0) || !sphere_in_frustum(F, v[0], v[1], v[2], r)) return false;
+        if (!(r > 0.0) || (kCull && !sphere_in_frustum(F, v[0], v[1], v[2], r))) return false;
         rec.g0 = make_float4((float)v[0], (float)v[1], (float)v[2], (float)r);
         rec.g1 = make_uint4(0u, 0u, it.id, 0u);
         return true;
@@ -97,8 +99,10 @@ __device__ inline bool item_view(const Frame& F, const Item& it, PrimRec& rec, d
     const double dx = v[3] - v[0], dy = v[4] - v[1], dz = v[5] - v[2];
     // the half length only enters the frustum test, whose margin (1e-4
     // relative) far exceeds the FP32 square root's error
-    const double half = 0.5 * (double)__builtin_amdgcn_sqrtf((float)(dx * dx + dy * dy + dz * dz));
-    if (!sphere_in_frustum(F, v[0] + 0.5 * dx, v[1] + 0.5 * dy, v[2] + 0.5 * dz, half + r)) return false;
+    if (kCull) {
+        const double half = 0.5 * (double)__builtin_amdgcn_sqrtf((float)(dx * dx + dy * dy + dz * dz));
+        if (!sphere_in_frustum(F, v[0] + 0.5 * dx, v[1] + 0.5 * dy, v[2] + 0.5 * dz, half + r)) return false;
+    }
     rec.g0 = make_float4((float)v[0], (float)v[1], (float)v[2], (float)dx);
     rec.g1 = make_uint4(__float_as_uint((float)dy), __float_as_uint((float)dz), it.id, 0u);
     return true;

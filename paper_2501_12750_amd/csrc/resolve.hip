@@ -154,11 +154,11 @@ __device__ inline Rec make_rec(const Frame& F, const PrimRec& p) {
 }
 
 // View-space record of a visible primitive, rebuilt from its source (the
-// tile lists hold only source indices and footprints).  False only if the
-// primitive is not visible, which the count pass has already excluded.
+// tile lists hold only source indices and footprints).  The count pass has
+// culled it already, so the frustum test is not repeated.
 __device__ inline bool source_record(const Job& J, uint32_t src, PrimRec& pr) {
     double v[6], rr;
-    return item_view(J.F, fetch_src(J, src), pr, v, rr);
+    return item_view<false>(J.F, fetch_src(J, src), pr, v, rr);
 }
 
 // Work block t of a job is that job's tile t; the launch's blocks are spread
