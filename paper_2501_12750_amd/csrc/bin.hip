@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(kBlock) k_zero(uint32_t* p, size_t n) {
 __device__ inline bool item_rect(const Frame& F, const Item& it, const double* v, double r, int& x0, int& y0,
                                  int& x1, int& y1) {
     if (it.kind == kAtom) return sphere_rect_fast(F, v[0], v[1], v[2], r, x0, y0, x1, y1);
-    return bond_rect(F, v, v + 3, r, x0, y0, x1, y1);
+    return bond_rect_fast(F, v, v + 3, r, x0, y0, x1, y1);
 }
 
 // Primitive sources of the count kernel.  Workgroup b owns items
@@ -127,7 +127,7 @@ __device__ inline void wave_count(uint32_t* hist, int t) {
 
 // Count.  Work block b of a job is that job's binning workgroup b.
 template <class JS, bool kScene>
-__global__ void __launch_bounds__(kBinThreads) k_count(JS js) {
+__global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
     extern __shared__ uint32_t hist[];
     __shared__ uint32_t local_n, bx0, by0, bx1, by1;
     __shared__ unsigned long long local_pairs;

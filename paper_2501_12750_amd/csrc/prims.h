@@ -115,21 +115,26 @@ __device__ inline bool item_view(const Frame& F, const Item& it, PrimRec& rec, d
 // its digits), orthographic views and everything else take the FP64 path.
 // A rectangle only has to contain the footprint: a larger one adds pixels
 // whose ray test misses.
-__device__ inline bool sphere_rect_fast(const Frame& F, double vx, double vy, double vz, double r, int& x0, int& y0,
-                                        int& x1, int& y1) {
-    if (F.proj != 0 || !(vz >= 1.05 * r) || vz - r > F.zfar) return sphere_rect(F, vx, vy, vz, r, x0, y0, x1, y1);
-    if (vz + r < F.znear) return false;
+// Pixel-space extent [ax, bx] x [ay, by] (unclamped, pixel centres at
+// i + 1/2) of a sphere with vz >= 1.05 r, perspective, in FP32.
+__device__ inline void sphere_extent_f32(const Frame& F, double vx, double vy, double vz, double r, float& ax,
+                                         float& bx, float& ay, float& by) {
     const float x = (float)vx, y = (float)vy, z = (float)vz, rf = (float)r;
     const float den = fmaf(z, z, -rf * rf);
     const float inv = __builtin_amdgcn_rcpf(den);
     const float sx = rf * __builtin_amdgcn_sqrtf(fmaf(x, x, den));
     const float sy = rf * __builtin_amdgcn_sqrtf(fmaf(y, y, den));
     const float kx = inv * F.itxf * 0.5f * (float)F.W, ky = inv * F.ityf * 0.5f * (float)F.H;
-    // pixel coordinates of the interval ends (pixel centres at i + 1/2)
-    const float ax = fmaf(fmaf(x, z, -sx), kx, 0.5f * (float)F.W);
-    const float bx = fmaf(fmaf(x, z, sx), kx, 0.5f * (float)F.W);
-    const float ay = fmaf(-fmaf(y, z, sy), ky, 0.5f * (float)F.H);
-    const float by = fmaf(-fmaf(y, z, -sy), ky, 0.5f * (float)F.H);
+    ax = fmaf(fmaf(x, z, -sx), kx, 0.5f * (float)F.W);
+    bx = fmaf(fmaf(x, z, sx), kx, 0.5f * (float)F.W);
+    ay = fmaf(-fmaf(y, z, sy), ky, 0.5f * (float)F.H);
+    by = fmaf(-fmaf(y, z, -sy), ky, 0.5f * (float)F.H);
+}
+
+// Pixel rectangle from an FP32 extent, widened by the margin and clamped to
+// the image.
+__device__ inline bool extent_pixels(const Frame& F, float ax, float bx, float ay, float by, int& x0, int& y0,
+                                     int& x1, int& y1) {
     constexpr float kMargin = 0.02f;
     const float fw = (float)F.W, fh = (float)F.H;
     x0 = (int)fminf(fmaxf(ceilf(ax - 0.5f - kMargin), 0.0f), fw);
@@ -137,6 +142,30 @@ __device__ inline bool sphere_rect_fast(const Frame& F, double vx, double vy, do
     y0 = (int)fminf(fmaxf(ceilf(ay - 0.5f - kMargin), 0.0f), fh);
     y1 = (int)fmaxf(fminf(floorf(by - 0.5f + kMargin), fh - 1.0f), -1.0f);
     return x0 <= x1 && y0 <= y1;
+}
+
+__device__ inline bool sphere_rect_fast(const Frame& F, double vx, double vy, double vz, double r, int& x0, int& y0,
+                                        int& x1, int& y1) {
+    if (F.proj != 0 || !(vz >= 1.05 * r) || vz - r > F.zfar) return sphere_rect(F, vx, vy, vz, r, x0, y0, x1, y1);
+    if (vz + r < F.znear) return false;
+    float ax, bx, ay, by;
+    sphere_extent_f32(F, vx, vy, vz, r, ax, bx, ay, by);
+    return extent_pixels(F, ax, bx, ay, by, x0, y0, x1, y1);
+}
+
+// The same for a capped cylinder of radius rho between view points A and B:
+// its projection lies in the union of the two end balls' extents (the
+// capsule's), taken unclamped and then clamped, when both balls are at
+// least 1.05 rho in front of the eye; otherwise bond_rect in FP64.
+__device__ inline bool bond_rect_fast(const Frame& F, const double* A, const double* B, double rho, int& x0,
+                                      int& y0, int& x1, int& y1) {
+    if (F.proj != 0 || !(A[2] >= 1.05 * rho) || !(B[2] >= 1.05 * rho)) return bond_rect(F, A, B, rho, x0, y0, x1, y1);
+    const double zlo = fmin(A[2], B[2]) - rho, zhi = fmax(A[2], B[2]) + rho;
+    if (zhi < F.znear || zlo > F.zfar) return false;
+    float ax, bx, ay, by, cx, dx, cy, dy;
+    sphere_extent_f32(F, A[0], A[1], A[2], rho, ax, bx, ay, by);
+    sphere_extent_f32(F, B[0], B[1], B[2], rho, cx, dx, cy, dy);
+    return extent_pixels(F, fminf(ax, cx), fmaxf(bx, dx), fminf(ay, cy), fmaxf(by, dy), x0, y0, x1, y1);
 }
 
 }  // namespace vtx
