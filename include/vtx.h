@@ -91,7 +91,8 @@ typedef struct vtx_camera {
  */
 typedef struct vtx_options {
     float bond_radius;        /* cylinder radius of every bond (0.15) */
-    int32_t ssao_samples;     /* K hemisphere samples, 0 = no ambient occlusion (0) */
+    int32_t ssao_samples;     /* K hemisphere samples, 0 = no ambient occlusion (0);
+                                 VTX_SSAO_AUTO: the context's choice (see vtx_autotune) */
     float ssao_radius;        /* hemisphere radius (2.0) */
     float ssao_bias;          /* depth bias of the occlusion test (0.05) */
     uint32_t background;      /* RGBA8 of pixels hit by nothing (0 = transparent black) */
@@ -326,29 +327,55 @@ int vtx_batch_graph_launch(vtx_batch_graph* graph, void* stream);
 /* vtx_batch_graph_destroy - waits for the device and frees the graph and its scratch. */
 void vtx_batch_graph_destroy(vtx_batch_graph* graph);
 
-/* Result of vtx_autotune. */
+/* Choices of vtx_autotune for one render shape (all fields are outputs but
+ * frame_budget_ms, which the caller sets before the call). */
 typedef struct vtx_tuning {
     int32_t tile_size;        /* chosen screen tile edge (8, 16, 32 or 64) */
     int32_t from_cache;       /* 1: read from the cache file, nothing was timed */
     float ms_per_batch;       /* device time of one sample batch at that size */
     float ms_by_tile[4];      /* at 8, 16, 32, 64 (0 = not tried: too many tiles) */
     char key[96];             /* shape it applies to: WxH/p<log2(atoms + bonds)>/<projection> */
+    float frame_budget_ms;    /* in: device time per render allowed to sample jobs that ask for
+                                 VTX_SSAO_AUTO samples (<= 0: no budget, 16 samples) */
+    int32_t ssao_samples;     /* SSAO samples of VTX_SSAO_AUTO renders of this shape
+                                 (-1: no sample job asked for them) */
+    uint64_t bin_capacity;    /* tile-list entries reserved for a render of this shape:
+                                 5/4 of the most (primitive, tile) pairs of a sample
+                                 job at the chosen tile size, plus 1024 */
+    float ms_by_samples[9];   /* per-render device time with 64, 48, 32, 24, 16, 12, 8, 4, 0
+                                 samples (0 = not timed) */
 } vtx_tuning;
 
+/* options.ssao_samples value that leaves the count to the context: the one
+ * vtx_autotune chose for the render's shape, else 16 (and 16 for renders that
+ * have no context: vtx_render, vtx_gbuffer + vtx_shade). */
+#define VTX_SSAO_AUTO (-1)
+
 /*
- * vtx_autotune - chooses the screen tile size for renders shaped like the
- * sample jobs (a shape is image size, log2 of the primitive count and
- * projection): times the sample batch (rendered into the jobs' own images,
- * flags cleared) at every tile size all its images accept, with HIP events on
- * `stream`, and keeps the fastest in the context for each shape in the batch;
- * renders of those shapes that leave options.tile_size at 0
- * (vtx_render_scene, vtx_render_batch) use it.  The images do not depend on
- * the tile size.  With `cache_path` (NULL: none) the choices are read from
- * that JSON file when it has every shape of the batch, otherwise measured and
- * written to it (other shapes' entries are kept).  Waits for the stream.
- * `out` (may be NULL) describes the choice for jobs[0]'s shape.
- * The paper's engine tunes nothing; the tile size is this library's own
- * parameter (its only one that trades speed for nothing).
+ * vtx_autotune - chooses, for renders shaped like the sample jobs (a shape is
+ * image size, log2 of the primitive count and projection), the screen tile
+ * size, the tile-list capacity and the SSAO sample count, and keeps them in
+ * the context for each shape in the batch:
+ *  - tile size: the sample batch (rendered into the jobs' own images, flags
+ *    cleared) is timed with HIP events on `stream` at every tile size all its
+ *    images accept; the fastest is used by renders of those shapes that leave
+ *    options.tile_size at 0 (vtx_render_scene, vtx_render_batch).  Images do
+ *    not depend on the tile size.
+ *  - bin capacity: the (primitive, tile) pairs of each sample job are read
+ *    back at the chosen size; a render of the shape whose scratch is new sizes
+ *    its lists from them instead of counting first and waiting for the count.
+ *    Images do not depend on it either (a frame that outgrows its lists is
+ *    resolved exactly from the visible lists).
+ *  - SSAO samples, only when a sample job's options ask for VTX_SSAO_AUTO:
+ *    the largest of 64, 48, 32, 24, 16, 12, 8, 4, 0 whose measured device
+ *    time per render fits out->frame_budget_ms (set by the caller; <= 0 or
+ *    out NULL: 16 without timing).  This one does change the images: fewer
+ *    samples, a coarser ambient occlusion.
+ * With `cache_path` (NULL: none) the choices are read from that JSON file when
+ * it has every shape of the batch, otherwise measured and written to it (other
+ * shapes' entries are kept).  Waits for the stream.  `out` (may be NULL)
+ * describes the choices for jobs[0]'s shape.  The paper's engine tunes
+ * nothing; these are this library's own parameters.
  */
 int vtx_autotune(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, const char* cache_path, void* stream,
                  vtx_tuning* out);

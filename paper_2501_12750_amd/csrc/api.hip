@@ -517,12 +517,20 @@ void sample_kernel(const vtx_options& o, vtx::SampleKernel* K) {
 
 }  // namespace
 
+// Choices of vtx_autotune for one shape.
+struct TunedShape {
+    int tile = 0;            // tile size (0: none)
+    int ssao = -1;           // SSAO samples of VTX_SSAO_AUTO renders (-1: none chosen)
+    uint64_t capacity = 0;   // tile-list entries for a render's new scratch (0: none)
+};
+constexpr int kAutoSsaoDefault = 16;
+
 struct vtx_context {
     int device = 0;
     size_t budget = 0;       // bytes of scenes this context may keep resident (0 = no limit)
     size_t used = 0;
     std::mutex mu;
-    std::map<std::string, int> tuned;   // shape key -> tile size chosen by vtx_autotune
+    std::map<std::string, TunedShape> tuned;   // shape key -> choices of vtx_autotune
 };
 
 // Positions of one stored trajectory frame.
@@ -606,8 +614,8 @@ void scene_frame(const vtx_scene* sc, int f, vtx::SceneDev* S, const float** pos
     }
 }
 
-// Shape a tuned tile size applies to: image size, primitive count (by
-// powers of two) and projection.
+// Shape the tuned choices apply to: image size, primitive count (by powers
+// of two) and projection.
 std::string shape_key(int32_t W, int32_t H, int64_t n, int64_t m, int32_t projection) {
     int lg = 0;
     for (uint64_t v = (uint64_t)(n + m); v > 1; v >>= 1) ++lg;
@@ -616,15 +624,28 @@ std::string shape_key(int32_t W, int32_t H, int64_t n, int64_t m, int32_t projec
     return buf;
 }
 
-// Options with the tile size the context tuned for this shape, when the
-// caller left it to the library.
+// Options with the choices the context tuned for this shape where the
+// caller left them to the library (tile size 0, VTX_SSAO_AUTO samples), and
+// the tuned tile-list capacity (0: none).
 vtx_options tuned_options(vtx_context* ctx, vtx_options o, const vtx_camera* cam, int32_t W, int32_t H,
-                          int64_t n, int64_t m) {
-    if (o.tile_size != 0 || !ctx || !cam) return o;
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    if (ctx->tuned.empty()) return o;
-    auto it = ctx->tuned.find(shape_key(W, H, n, m, cam->projection));
-    if (it != ctx->tuned.end()) o.tile_size = it->second;
+                          int64_t n, int64_t m, uint64_t* capacity = nullptr) {
+    if (capacity) *capacity = 0;
+    if (ctx && cam) {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->tuned.find(shape_key(W, H, n, m, cam->projection));
+        if (it != ctx->tuned.end()) {
+            if (o.tile_size == 0) o.tile_size = it->second.tile;
+            if (o.ssao_samples == VTX_SSAO_AUTO && it->second.ssao >= 0) o.ssao_samples = it->second.ssao;
+            if (capacity) *capacity = it->second.capacity;
+        }
+    }
+    if (o.ssao_samples == VTX_SSAO_AUTO) o.ssao_samples = kAutoSsaoDefault;
+    return o;
+}
+
+// The same for renders without a context.
+vtx_options untuned_options(vtx_options o) {
+    if (o.ssao_samples == VTX_SSAO_AUTO) o.ssao_samples = kAutoSsaoDefault;
     return o;
 }
 
@@ -638,6 +659,7 @@ struct JobDesc {
     const uint32_t* bonds;
     bool scene;
     uint64_t scene_uid;
+    uint64_t tuned_capacity = 0;   // tile-list entries the tuner chose for this render's shape (0: none)
     vtx::SceneDev S;
     float* depth;
     uint32_t* id;
@@ -763,10 +785,11 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
                         (nc && (size_t)nc > b->vc_cap)))
             return fail(VTX_EINVAL, "job %zu: scratch not sized for capture", i);
         if (!ws->fixed_capacity && !b->was_sized(nprim, s.F.W, s.F.H)) {
-            // a scene and image size counted before: size from that count
+            // a shape the tuner sized, or a scene and image size counted
+            // before: size from that, without counting first
             const uint64_t seen = seen_pairs(s.scene_uid, s.F.W, s.F.H);
-            if (seen) {
-                uint64_t want = seen + seen / 2 + 1024;
+            if (s.tuned_capacity || seen) {
+                uint64_t want = s.tuned_capacity ? s.tuned_capacity : seen + seen / 2 + 1024;
                 if (want > kMaxCapacity) want = kMaxCapacity;
                 if (want > b->want_capacity) b->want_capacity = want;
                 b->mark_sized(nprim, s.F.W, s.F.H);
@@ -951,7 +974,7 @@ extern "C" {
 int vtx_gbuffer(const float* positions, const float* radii, const uint32_t* colors, int64_t n_atoms,
                 const uint32_t* bonds, int64_t n_bonds, const vtx_camera* cam, const vtx_options* opt,
                 int32_t W, int32_t H, float* depth, uint32_t* id, void* stream) {
-    const vtx_options o = resolve_options(opt);
+    const vtx_options o = untuned_options(resolve_options(opt));
     Frame F;
     int rc = make_frame(cam, o, W, H, n_atoms, n_bonds, &F);
     if (rc) return rc;
@@ -968,7 +991,7 @@ int vtx_shade(const float* positions, const float* radii, const uint32_t* colors
               const uint32_t* bonds, int64_t n_bonds, const vtx_camera* cam, const vtx_options* opt, int32_t W,
               int32_t H, const float* depth, const uint32_t* id, uint32_t* rgba, float* normal, uint32_t* albedo,
               float* ao, void* stream) {
-    const vtx_options o = resolve_options(opt);
+    const vtx_options o = untuned_options(resolve_options(opt));
     Frame F;
     int rc = make_frame(cam, o, W, H, n_atoms, n_bonds, &F);
     if (rc) return rc;
@@ -988,7 +1011,7 @@ int vtx_shade(const float* positions, const float* radii, const uint32_t* colors
 int vtx_render(const float* positions, const float* radii, const uint32_t* colors, int64_t n_atoms,
                const uint32_t* bonds, int64_t n_bonds, const vtx_camera* cam, const vtx_options* opt,
                int32_t W, int32_t H, uint32_t* rgba, float* depth, uint32_t* id, void* stream) {
-    const vtx_options o = resolve_options(opt);
+    const vtx_options o = untuned_options(resolve_options(opt));
     Frame F;
     int rc = make_frame(cam, o, W, H, n_atoms, n_bonds, &F);
     if (rc) return rc;
@@ -1210,7 +1233,8 @@ void vtx_scene_destroy(vtx_scene* scene) {
 int vtx_render_scene(vtx_scene* scene, const vtx_camera* cam, const vtx_options* opt, int32_t W, int32_t H,
                      uint32_t* rgba, float* depth, uint32_t* id, void* stream) {
     if (!scene) return fail(VTX_EINVAL, "scene is NULL");
-    const vtx_options o = tuned_options(scene->ctx, resolve_options(opt), cam, W, H, scene->n, scene->m);
+    uint64_t tuned_cap = 0;
+    const vtx_options o = tuned_options(scene->ctx, resolve_options(opt), cam, W, H, scene->n, scene->m, &tuned_cap);
     Frame F;
     int rc = make_frame(cam, o, W, H, scene->n, scene->m, &F);
     if (rc) return rc;
@@ -1221,6 +1245,7 @@ int vtx_render_scene(vtx_scene* scene, const vtx_camera* cam, const vtx_options*
     std::vector<JobDesc> d{plain_desc(F, o, scene->pos, scene->rad, scene->col, scene->bonds)};
     d[0].scene = true;
     d[0].scene_uid = scene->uid;
+    d[0].tuned_capacity = tuned_cap;
     d[0].S = scene->S;
     d[0].depth = depth;
     d[0].id = id;
@@ -1237,7 +1262,7 @@ int vtx_check_job(const vtx_context* ctx, const vtx_job* j) {
     if (j->frame < 0 || j->frame > (int32_t)sc->frames.size())
         return fail(VTX_EINVAL, "frame %d not in 0..%zu", j->frame, sc->frames.size());
     if (!j->rgba || !j->depth || !j->id) return fail(VTX_EINVAL, "rgba/depth/id outputs are NULL");
-    const vtx_options o = resolve_options(&j->options);
+    const vtx_options o = untuned_options(resolve_options(&j->options));
     Frame F;
     return make_frame(&j->camera, o, j->width, j->height, sc->n, sc->m, &F);
 }
@@ -1263,7 +1288,9 @@ int build_batch(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, std::vect
         if (j.frame < 0 || j.frame > (int32_t)sc->frames.size())
             return fail(VTX_EINVAL, "job %d: frame %d not in 0..%zu", i, j.frame, sc->frames.size());
         if (!j.rgba || !j.depth || !j.id) return fail(VTX_EINVAL, "job %d: rgba/depth/id outputs are NULL", i);
-        const vtx_options o = tuned_options(ctx, resolve_options(&j.options), &j.camera, j.width, j.height, sc->n, sc->m);
+        uint64_t tuned_cap = 0;
+        const vtx_options o =
+            tuned_options(ctx, resolve_options(&j.options), &j.camera, j.width, j.height, sc->n, sc->m, &tuned_cap);
         Frame F;
         int rc = make_frame(&j.camera, o, j.width, j.height, sc->n, sc->m, &F);
         if (rc) return fail(rc, "job %d: %s", i, g_error.c_str());
@@ -1273,6 +1300,7 @@ int build_batch(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, std::vect
         d[(size_t)i] = plain_desc(F, o, pos, sc->rad, sc->col, sc->bonds);
         d[(size_t)i].scene = true;
         d[(size_t)i].scene_uid = sc->uid;
+        d[(size_t)i].tuned_capacity = tuned_cap;
         d[(size_t)i].S = S;
         d[(size_t)i].depth = j.depth;
         d[(size_t)i].id = j.id;
@@ -1383,51 +1411,88 @@ int vtx_autotune(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, const ch
                  vtx_tuning* out) {
     if (!ctx) return fail(VTX_EINVAL, "context is NULL");
     if (n_jobs < 1 || n_jobs > kMaxBatch || !jobs) return fail(VTX_EINVAL, "need 1..%d sample jobs", kMaxBatch);
+    const float budget = out ? out->frame_budget_ms : 0.0f;
     // the shapes of the sample jobs; the batch is timed as a whole and its
-    // choice kept for each of them
-    std::vector<std::string> keys;
+    // choices kept for each of them
+    std::vector<std::string> keys, job_key;
+    bool want_ssao = false;
     for (int32_t i = 0; i < n_jobs; ++i) {
         if (!jobs[i].scene) return fail(VTX_EINVAL, "job %d: scene is NULL", i);
         const std::string k =
             shape_key(jobs[i].width, jobs[i].height, jobs[i].scene->n, jobs[i].scene->m, jobs[i].camera.projection);
+        job_key.push_back(k);
         if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
+        want_ssao = want_ssao || jobs[i].options.ssao_samples == VTX_SSAO_AUTO;
     }
     const std::string key = keys[0];
-    std::map<std::string, int> cached;
+    std::map<std::string, TunedShape> cached;
     vtx_tuning t;
     std::memset(&t, 0, sizeof(t));
     std::snprintf(t.key, sizeof(t.key), "%s", key.c_str());
-    // a cached choice for this shape
+    t.frame_budget_ms = budget;
+    t.ssao_samples = -1;
+    // cached choices: one line per shape
+    //   {"key": K, "tile_size": T, "ssao_samples": S, "bin_capacity": C, "ms_per_batch": M}
     std::vector<std::pair<std::string, std::string>> lines;   // key -> its cache line
     if (cache_path && *cache_path) {
         if (FILE* fh = std::fopen(cache_path, "r")) {
             char buf[512];
             while (std::fgets(buf, sizeof(buf), fh)) {
                 char k[160];
-                int tile = 0;
-                if (std::sscanf(buf, " {\"key\": \"%159[^\"]\", \"tile_size\": %d", k, &tile) == 2) {
+                int tile = 0, ssao = -1;
+                unsigned long long cap = 0;
+                if (std::sscanf(buf, " {\"key\": \"%159[^\"]\", \"tile_size\": %d, \"ssao_samples\": %d, \"bin_capacity\": %llu",
+                                k, &tile, &ssao, &cap) >= 2) {
                     std::string line(buf);
                     while (!line.empty() && (line.back() == '\n' || line.back() == ',' || line.back() == ' '))
                         line.pop_back();
                     lines.push_back({k, line});
-                    if (tile == 8 || tile == 16 || tile == 32 || tile == 64) cached[k] = tile;
+                    if (tile == 8 || tile == 16 || tile == 32 || tile == 64) {
+                        TunedShape ts;
+                        ts.tile = tile;
+                        ts.ssao = ssao >= 0 && ssao <= VTX_MAX_SSAO_SAMPLES ? ssao : -1;
+                        ts.capacity = cap <= kMaxCapacity ? (uint64_t)cap : 0;
+                        cached[k] = ts;
+                    }
                 }
             }
             std::fclose(fh);
         }
     }
     bool all_cached = true;
-    for (const std::string& k : keys) all_cached = all_cached && cached.count(k);
+    for (const std::string& k : keys)
+        all_cached = all_cached && cached.count(k) && cached[k].capacity && (!want_ssao || cached[k].ssao >= 0);
     if (all_cached) {
         t.from_cache = 1;
-        t.tile_size = cached[key];
+        t.tile_size = cached[key].tile;
+        t.ssao_samples = want_ssao ? cached[key].ssao : -1;
+        t.bin_capacity = cached[key].capacity;
     } else {
-        // time the sample batch at each tile size every job's image accepts
         hipStream_t st = (hipStream_t)stream;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         VTX_HIP(hipEventCreate(&e0));
         VTX_HIP(hipEventCreate(&e1));
         std::vector<vtx_job> trial(jobs, jobs + n_jobs);
+        for (vtx_job& j : trial) {
+            j.options.flags = 0;
+            if (j.options.ssao_samples == VTX_SSAO_AUTO) j.options.ssao_samples = kAutoSsaoDefault;
+        }
+        // device time of one sample batch (the first run sizes the bins and
+        // is not timed)
+        auto time_batch = [&](float* ms_out) -> int {
+            int rc = VTX_OK;
+            for (int rep = 0; rep < 4 && rc == VTX_OK; ++rep) {
+                if (rep == 1) rc = hipEventRecord(e0, st) == hipSuccess ? VTX_OK : fail(VTX_EHIP, "hipEventRecord failed");
+                if (rc == VTX_OK) rc = vtx_render_batch(ctx, trial.data(), n_jobs, stream);
+            }
+            float ms = 0.0f;
+            if (rc == VTX_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = fail(VTX_EHIP, "timing the sample batch failed");
+            *ms_out = ms / 3.0f;
+            return rc;
+        };
+        // 1. tile size: every size all the sample images accept
         const int sizes[4] = {8, 16, 32, 64};
         float best = 0.0f;
         int rc = VTX_OK;
@@ -1437,37 +1502,78 @@ int vtx_autotune(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, const ch
                 ok = ok && (int64_t)((j.width + sizes[k] - 1) / sizes[k]) * ((j.height + sizes[k] - 1) / sizes[k]) <=
                                vtx::kMaxLdsTiles;
             if (!ok) continue;
-            for (vtx_job& j : trial) {
-                j.options.tile_size = sizes[k];
-                j.options.flags = 0;
-            }
+            for (vtx_job& j : trial) j.options.tile_size = sizes[k];
             float ms = 0.0f;
-            for (int rep = 0; rep < 4 && rc == VTX_OK; ++rep) {   // first run sizes the bins: untimed
-                if (rep == 1) rc = hipEventRecord(e0, st) == hipSuccess ? VTX_OK : fail(VTX_EHIP, "hipEventRecord failed");
-                if (rc == VTX_OK) rc = vtx_render_batch(ctx, trial.data(), n_jobs, stream);
-            }
-            if (rc == VTX_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-                rc = fail(VTX_EHIP, "timing the sample batch failed");
-            if (rc != VTX_OK) break;
-            ms /= 3.0f;
+            if ((rc = time_batch(&ms)) != VTX_OK) break;
             t.ms_by_tile[k] = ms;
             if (!t.tile_size || ms < best) {
                 best = ms;
                 t.tile_size = sizes[k];
             }
         }
+        if (rc == VTX_OK && !t.tile_size) rc = fail(VTX_EINVAL, "no tile size fits the sample images");
+        if (rc == VTX_OK) {
+            t.ms_per_batch = best;
+            for (vtx_job& j : trial) j.options.tile_size = t.tile_size;
+        }
+        // 2. bin capacity: the pairs of each sample job at that size
+        std::map<std::string, uint64_t> cap;
+        if (rc == VTX_OK) rc = vtx_render_batch(ctx, trial.data(), n_jobs, stream);
+        if (rc == VTX_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(VTX_EHIP, "hipStreamSynchronize failed");
+        if (rc == VTX_OK) {
+            std::lock_guard<std::mutex> lk(g_mu);
+            int dev = 0;
+            (void)hipGetDevice(&dev);
+            auto it = g_ws.find(std::make_pair(dev, st));
+            if (it == g_ws.end() || (int)it->second->slots.size() < n_jobs) {
+                rc = fail(VTX_EINVAL, "no scratch for the sample batch");
+            } else {
+                for (int32_t i = 0; i < n_jobs; ++i) {
+                    const uint64_t pairs = it->second->slots[(size_t)i]->host_ctr->pairs;
+                    uint64_t c = pairs + pairs / 4 + 1024;
+                    if (c > kMaxCapacity) c = kMaxCapacity;
+                    cap[job_key[(size_t)i]] = std::max(cap[job_key[(size_t)i]], c);
+                }
+            }
+        }
+        // 3. SSAO samples of the jobs that leave them to the context
+        int ssao = -1;
+        if (rc == VTX_OK && want_ssao) {
+            static const int counts[9] = {64, 48, 32, 24, 16, 12, 8, 4, 0};
+            ssao = kAutoSsaoDefault;
+            if (budget > 0.0f) {
+                ssao = -1;
+                for (int c = 0; c < 9 && rc == VTX_OK && ssao < 0; ++c) {
+                    for (int32_t i = 0; i < n_jobs; ++i)
+                        if (jobs[i].options.ssao_samples == VTX_SSAO_AUTO) trial[(size_t)i].options.ssao_samples = counts[c];
+                    float ms = 0.0f;
+                    if ((rc = time_batch(&ms)) != VTX_OK) break;
+                    t.ms_by_samples[c] = ms / (float)n_jobs;
+                    if (t.ms_by_samples[c] <= budget) ssao = counts[c];
+                }
+                if (rc == VTX_OK && ssao < 0) ssao = 0;   // the budget is below even no occlusion: the cheapest
+            }
+        }
         hipEventDestroy(e0);
         hipEventDestroy(e1);
         if (rc != VTX_OK) return rc;
-        if (!t.tile_size) return fail(VTX_EINVAL, "no tile size fits the sample images");
-        t.ms_per_batch = best;
-        for (const std::string& k : keys) cached[k] = t.tile_size;
+        t.ssao_samples = ssao;
+        t.bin_capacity = cap[key];
+        for (const std::string& k : keys) {
+            TunedShape ts;
+            ts.tile = t.tile_size;
+            ts.ssao = ssao >= 0 ? ssao : (cached.count(k) ? cached[k].ssao : -1);
+            ts.capacity = cap[k];
+            cached[k] = ts;
+        }
         if (cache_path && *cache_path) {
             for (const std::string& k : keys) {
-                char line[256];
-                std::snprintf(line, sizeof(line), "  {\"key\": \"%s\", \"tile_size\": %d, \"ms_per_batch\": %.6f}",
-                              k.c_str(), t.tile_size, (double)best);
+                char line[320];
+                std::snprintf(line, sizeof(line),
+                              "  {\"key\": \"%s\", \"tile_size\": %d, \"ssao_samples\": %d, \"bin_capacity\": %llu, "
+                              "\"ms_per_batch\": %.6f}",
+                              k.c_str(), cached[k].tile, cached[k].ssao, (unsigned long long)cached[k].capacity,
+                              (double)best);
                 bool replaced = false;
                 for (auto& l : lines)
                     if (l.first == k) {

@@ -27,6 +27,7 @@ VTX_ORTHOGRAPHIC = 1
 VTX_BACKGROUND_ID = 0xFFFFFFFF
 VTX_MAX_PIXELS = 7680 * 4320
 VTX_MAX_SSAO_SAMPLES = 64
+VTX_SSAO_AUTO = -1
 VTX_FLAG_STATS = 1
 VTX_FLAG_TIMING = 2
 VTX_REP_BALL_AND_STICK, VTX_REP_VAN_DER_WAALS, VTX_REP_STICKS, VTX_REP_SAS = 0, 1, 2, 3
@@ -79,15 +80,22 @@ class vtx_job(ctypes.Structure):
                 ("rgba", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("id", ctypes.c_void_p)]
 
 
+SSAO_COUNTS = (64, 48, 32, 24, 16, 12, 8, 4, 0)   # the sample counts vtx_autotune tries, in its order
+
+
 class vtx_tuning(ctypes.Structure):
     _fields_ = [("tile_size", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("ms_per_batch", ctypes.c_float),
-                ("ms_by_tile", ctypes.c_float * 4), ("key", ctypes.c_char * 96)]
+                ("ms_by_tile", ctypes.c_float * 4), ("key", ctypes.c_char * 96),
+                ("frame_budget_ms", ctypes.c_float), ("ssao_samples", ctypes.c_int32),
+                ("bin_capacity", ctypes.c_uint64), ("ms_by_samples", ctypes.c_float * 9)]
 
     def as_dict(self):
         return {"tile_size": self.tile_size, "from_cache": bool(self.from_cache),
                 "ms_per_batch": float(self.ms_per_batch),
                 "ms_by_tile": {t: float(v) for t, v in zip((8, 16, 32, 64), self.ms_by_tile) if v > 0},
-                "key": self.key.decode()}
+                "key": self.key.decode(), "frame_budget_ms": float(self.frame_budget_ms),
+                "ssao_samples": int(self.ssao_samples), "bin_capacity": int(self.bin_capacity),
+                "ms_by_samples": {k: float(v) for k, v in zip(SSAO_COUNTS, self.ms_by_samples) if v > 0}}
 
 
 class vtx_completion(ctypes.Structure):
@@ -380,9 +388,10 @@ def vtx_render_batch(ctx, jobs, stream=None):
     _check(_lib.vtx_render_batch(ctx, arr, len(arr), _stream(stream)))
 
 
-def vtx_autotune(ctx, jobs, cache_path=None, stream=None) -> dict:
+def vtx_autotune(ctx, jobs, cache_path=None, stream=None, frame_budget_ms=0.0) -> dict:
     arr = jobs if isinstance(jobs, ctypes.Array) else (vtx_job * len(jobs))(*jobs)
     t = vtx_tuning()
+    t.frame_budget_ms = float(frame_budget_ms)
     path = None if cache_path is None else os.fsencode(cache_path)
     _check(_lib.vtx_autotune(ctx, arr, len(arr), path, _stream(stream), ctypes.byref(t)))
     return t.as_dict()

@@ -83,3 +83,51 @@ def test_host_argument_checks(vtx, case):
         vtx.vtx_render(pos, 0x3000, 0x4000, n, None, 0, cam, opt, W, H, out, 0x5000, 0x6000, stream=0)
     assert e.value.code == vtx.VTX_EINVAL
     assert vtx.vtx_last_error()
+
+
+def test_struct_layouts_match_the_header(vtx, tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    the C compiler gives the header's struct of the same name."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [vtx.vtx_camera, vtx.vtx_options, vtx.vtx_stats, vtx.vtx_job, vtx.vtx_tuning, vtx.vtx_completion,
+               vtx.vtx_server_stats]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "vtx.h"', "int main(void) {"]
+    for st in structs:
+        name = st.__name__
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    for st in structs:
+        name = st.__name__
+        assert int(got[name]) == ctypes.sizeof(st), name
+        for f, _ in st._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(st, f).offset, f"{name}.{f}"
+
+
+def test_ssao_auto_is_accepted_without_a_context(vtx):
+    """VTX_SSAO_AUTO passes the host checks of the plain entry point (it
+    means 16 samples there); a count above the maximum does not."""
+    from paper_2501_12750_amd import scenes
+    cam = _cam()
+    opt = vtx.options_struct(scenes.Options())
+    opt.ssao_samples = vtx.VTX_SSAO_AUTO
+    # a null position array is reported after the option checks pass
+    rc = vtx._lib.vtx_render(None, None, None, 4, None, 0, ctypes.byref(cam), ctypes.byref(opt), 16, 16,
+                             ctypes.c_void_p(0x2000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x2000), None)
+    assert rc == vtx.VTX_EINVAL and "NULL" in vtx.vtx_last_error()
+    opt.ssao_samples = -2
+    rc = vtx._lib.vtx_render(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), None, 4, None, 0, ctypes.byref(cam),
+                             ctypes.byref(opt), 16, 16, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x2000),
+                             ctypes.c_void_p(0x2000), None)
+    assert rc == vtx.VTX_EINVAL and "ssao_samples" in vtx.vtx_last_error()
