@@ -162,20 +162,11 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
     const uint64_t start = (uint64_t)blk * chunk;
     auto src = src0;
     src.begin(blk);
-    const uint64_t nitems = src.items();
     const int tsh = F.tile_shift;
     uint32_t bad_count = 0;
-    Item cur = empty_item();
-    if ((uint64_t)tid < nitems) cur = src.fetch(tid);
-    for (uint64_t base = 0; base < nitems; base += kBinThreads) {
-        // the next iteration's inputs are loaded while this one is processed
-        Item nxt = empty_item();
-        if (base + kBinThreads + tid < nitems) nxt = src.fetch(base + kBinThreads + tid);
-        int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
-        PrimRec rec;
-        double v[6], r = 0.0;
-        const bool vis = item_view(F, cur, rec, v, r) && item_rect(F, cur, v, r, x0, y0, x1, y1);
-        bad_count += cur.kind == kBadBond ? 1u : 0u;
+    // One visible-or-not primitive per lane (every lane of the wave calls
+    // it): its slot in the workgroup's visible list, its tile counts.
+    auto emit = [&](bool vis, uint32_t sidx, int x0, int y0, int x1, int y1) {
         const unsigned long long vmask = __ballot(vis);
         uint32_t slot_base = 0;
         const int leader = __ffsll((long long)(vmask | 1ull)) - 1;
@@ -186,7 +177,7 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
         wave_count(hist, single ? ty0 * F.tiles_x + tx0 : -1);
         if (vis) {
             const uint64_t slot = start + slot_base + (uint32_t)__popcll(vmask & __lanemask_lt());
-            vis_src[slot] = cur.src;
+            vis_src[slot] = sidx;
             vis_rect[slot] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
             if (!single)
                 for (int ty = ty0; ty <= ty1; ++ty)
@@ -197,7 +188,65 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
             my1 = max(my1, (uint32_t)ty1);
             my_pairs += (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
         }
-        cur = nxt;
+    };
+    // any primitive (the generic path)
+    auto emit_item = [&](const Item& it) {
+        int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
+        PrimRec rec;
+        double v[6], r = 0.0;
+        const bool vis = item_view(F, it, rec, v, r) && item_rect(F, it, v, r, x0, y0, x1, y1);
+        bad_count += it.kind == kBadBond ? 1u : 0u;
+        emit(vis, it.src, x0, y0, x1, y1);
+    };
+    if constexpr (kScene) {
+        // Resident scene: each wave takes whole clusters (256 primitives of
+        // one kind, so the kind is the same across the wave).  An atom
+        // cluster's four 64-atom quarters are loaded together and take the
+        // sphere-only path.
+        const SceneDev& S = src.S;
+        const uint32_t nw = kBinThreads / 64;
+        const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(tid >> 6);
+        const uint32_t lane = __lane_id();
+        uint32_t cn = src.c0 + wave < src.c1 ? S.vis_clusters[src.c0 + wave] : 0u;
+        for (uint32_t ci = src.c0 + wave; ci < src.c1; ci += nw) {
+            const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int)cn);
+            if (ci + nw < src.c1) cn = S.vis_clusters[ci + nw];   // the next cluster's id, ahead of its use
+            if (c < S.atom_clusters) {
+                float4 a[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t i = c * kCluster + (uint32_t)q * 64u + lane;
+                    a[q] = i < S.n_atoms ? S.xyzr[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t i = c * kCluster + (uint32_t)q * 64u + lane;
+                    int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
+                    double vx, vy, vz;
+                    to_view(F, a[q].x, a[q].y, a[q].z, vx, vy, vz);
+                    const double r = (double)atom_radius(F, a[q].w);
+                    const bool vis = i < S.n_atoms && r > 0.0 && sphere_in_frustum(F, vx, vy, vz, r) &&
+                                     sphere_rect_fast(F, vx, vy, vz, r, x0, y0, x1, y1);
+                    emit(vis, i, x0, y0, x1, y1);
+                }
+            } else {
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t j = (c - S.atom_clusters) * kCluster + (uint32_t)q * 64u + lane;
+                    emit_item(j < S.n_bonds ? fetch_scene(S, S.n_atoms + j) : empty_item());
+                }
+            }
+        }
+    } else {
+        const uint64_t nitems = src.items();
+        Item cur = empty_item();
+        if ((uint64_t)tid < nitems) cur = src.fetch(tid);
+        for (uint64_t base = 0; base < nitems; base += kBinThreads) {
+            // the next iteration's inputs are loaded while this one is processed
+            Item nxt = empty_item();
+            if (base + kBinThreads + tid < nitems) nxt = src.fetch(base + kBinThreads + tid);
+            emit_item(cur);
+            cur = nxt;
+        }
     }
     if (bad_count) atomicAdd(&ctr->bad_bonds, bad_count);
     if (my_pairs) {
