@@ -164,6 +164,8 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
     src.begin(blk);
     const int tsh = F.tile_shift;
     uint32_t bad_count = 0;
+    uint32_t* __restrict__ const my_src = vis_src + start;   // this workgroup's visible list
+    uint2* __restrict__ const my_rect = vis_rect + start;
     // One visible-or-not primitive per lane (every lane of the wave calls
     // it): its slot in the workgroup's visible list, its tile counts.
     auto emit = [&](bool vis, uint32_t sidx, int x0, int y0, int x1, int y1) {
@@ -176,9 +178,9 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
         const bool single = vis && tx0 == tx1 && ty0 == ty1;
         wave_count(hist, single ? ty0 * F.tiles_x + tx0 : -1);
         if (vis) {
-            const uint64_t slot = start + slot_base + (uint32_t)__popcll(vmask & __lanemask_lt());
-            vis_src[slot] = sidx;
-            vis_rect[slot] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
+            const uint32_t slot = slot_base + (uint32_t)__popcll(vmask & __lanemask_lt());
+            my_src[slot] = sidx;
+            my_rect[slot] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
             if (!single)
                 for (int ty = ty0; ty <= ty1; ++ty)
                     for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&hist[ty * F.tiles_x + tx], 1u);
