@@ -57,13 +57,13 @@ def log(msg):
 
 
 def sources_sha(kernel):
-    """sha256[:16] of a kernel's source file followed by the shared internal header."""
+    """sha256[:16] of a kernel's source file followed by the shared headers."""
     import hashlib
     f = KERNEL_SOURCES.get(kernel.split("<")[0])
     if f is None:
         return None
     h = hashlib.sha256()
-    for name in (f, "vtx_internal.h"):
+    for name in (f, "prims.h", "vtx_internal.h"):
         with open(os.path.join(ROOT, "paper_2501_12750_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
