@@ -103,7 +103,35 @@ typedef struct vtx_options {
     uint32_t flags;           /* VTX_FLAG_* */
     int32_t representation;   /* VTX_REP_* (VTX_REP_BALL_AND_STICK) */
     float probe_radius;       /* solvent probe of VTX_REP_SAS (1.4) */
+    /* deferred post-passes (see below) */
+    int32_t shading;          /* VTX_SHADE_* (VTX_SHADE_GLOSSY) */
+    uint32_t fog_color;       /* RGBA8 the fog fades to (alpha ignored) */
+    float fog_start, fog_end; /* view depths (A) where fog begins and is complete;
+                                 fog_end <= fog_start: no fog (0, 0) */
+    uint32_t outline_color;   /* RGBA8 of outline pixels (alpha ignored) */
+    float outline_depth;      /* relative depth step that makes an outline; 0: none (0) */
 } vtx_options;
+
+/*
+ * Deferred post-passes on the G-buffer (paper, Methods, "High Quality
+ * Rendering": shading modes flat, matte, glossy and toon, ambient occlusion,
+ * fog and outline, as post-processing of the deferred pass).  The paper gives
+ * no formulas; these are this library's readings.  With n.V the facing term,
+ * AO the occlusion factor and a the albedo, per hit pixel and channel:
+ *   VTX_SHADE_GLOSSY  a (0.2 + 0.8 n.V) AO + 0.25 max(0, 2 (n.V)^2 - 1)^32
+ *   VTX_SHADE_MATTE   a (0.2 + 0.8 n.V) AO
+ *   VTX_SHADE_FLAT    a AO
+ *   VTX_SHADE_TOON    a (0.2 + 0.8 b) AO, b = min(floor(4 n.V), 3) / 3
+ * then fog: f = clamp((z - fog_start) / (fog_end - fog_start), 0, 1) and
+ * c = (1 - f) c + f fog_color; then outline: a hit pixel whose right, left,
+ * lower or upper neighbour inside the image is background or deeper than
+ * z (1 + outline_depth) takes outline_color.  Background pixels keep
+ * options.background.
+ */
+#define VTX_SHADE_GLOSSY 0
+#define VTX_SHADE_MATTE 1
+#define VTX_SHADE_FLAT 2
+#define VTX_SHADE_TOON 3
 
 /*
  * options.representation (paper, Methods, "Meshless Representations": the

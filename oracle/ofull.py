@@ -32,6 +32,13 @@ notes:
   R6 SSAO       K fixed hemisphere samples oriented by the normal with the
                 branchless orthonormal basis of Duff et al. (JCGT 2017),
                 projected to a pixel and compared with that pixel's depth.
+  R7 post       the deferred post-passes the paper lists (shading flat,
+                matte, glossy, toon; fog; outline): glossy is R5; matte drops
+                its specular term; flat is albedo AO; toon replaces n.V by
+                min(floor(4 n.V), 3)/3 in matte; linear fog blends towards a
+                colour between two view depths; a hit pixel with an in-image
+                4-neighbour that is background or deeper than z (1 + t) takes
+                the outline colour.
 
 Because FP32 on the device and FP64 here can disagree where a result is
 decided by a near-tie, every pixel also carries an accept set: the ids that
@@ -505,15 +512,66 @@ def ssao(cam, W, H, window, Pv, Nv, hit, depth_buf, depth_win, K, R, bias,
 # ---------------------------------------------------------------------------
 # R5: shading
 # ---------------------------------------------------------------------------
-def shade(Nv, Vv, albedo, ao, hit, background):
-    """Packed RGBA8 per pixel.  Vv is the unit direction towards the camera."""
+SHADE_GLOSSY, SHADE_MATTE, SHADE_FLAT, SHADE_TOON = 0, 1, 2, 3
+
+
+def rgb_of(packed):
+    """(P, 3) channels in [0, 1] of packed RGBA8 values."""
+    packed = np.asarray(packed, dtype=np.uint32)
+    return np.stack([(packed >> sh) & 255 for sh in (0, 8, 16)], axis=-1).astype(np.float64) / 255.0
+
+
+def shade(Nv, Vv, albedo, ao, hit, background, shading=SHADE_GLOSSY, z=None, fog=None):
+    """Packed RGBA8 per pixel (R5, R7 without the outline) and the pixels
+    whose toon band sits on an edge.  Vv is the unit direction towards the
+    camera; fog = (start, end, packed colour) or None."""
     nv = np.maximum(0.0, np.einsum("ij,ij->i", Nv, Vv))
-    alb = np.stack([(albedo >> sh) & 255 for sh in (0, 8, 16)], axis=1).astype(np.float64) / 255.0
-    spec = KS * np.maximum(0.0, 2.0 * nv * nv - 1.0) ** SHININESS
-    c = alb * (KA + KD * nv)[:, None] * ao[:, None] + spec[:, None]
+    alb = rgb_of(albedo)
+    band_edge = np.zeros(nv.shape, dtype=bool)
+    if shading == SHADE_FLAT:
+        c = alb * ao[:, None]
+    elif shading == SHADE_TOON:
+        b = np.minimum(np.floor(4.0 * nv), 3.0) / 3.0
+        k = np.round(4.0 * nv)
+        band_edge = (np.abs(4.0 * nv - k) <= 1e-4) & (k >= 1) & (k <= 3)
+        c = alb * (KA + KD * b)[:, None] * ao[:, None]
+    else:
+        c = alb * (KA + KD * nv)[:, None] * ao[:, None]
+        if shading == SHADE_GLOSSY:
+            c = c + (KS * np.maximum(0.0, 2.0 * nv * nv - 1.0) ** SHININESS)[:, None]
+    if fog is not None and fog[1] > fog[0]:
+        f = np.clip((z - fog[0]) / (fog[1] - fog[0]), 0.0, 1.0)[:, None]
+        c = (1.0 - f) * c + f * rgb_of(fog[2])
     q = np.floor(255.0 * np.clip(c, 0.0, 1.0) + 0.5).astype(np.uint32)
     rgba = q[:, 0] | (q[:, 1] << 8) | (q[:, 2] << 16) | (np.uint32(255) << 24)
-    return np.where(hit, rgba, np.uint32(background)).astype(np.uint32)
+    return np.where(hit, rgba, np.uint32(background)).astype(np.uint32), band_edge & hit
+
+
+def outline(W, H, window, z, depth_buf, depth_win, t, depth_rel=1e-5):
+    """R7 outline over the window: pixels to recolour, and pixels where a
+    neighbour's depth is within depth_rel z of the threshold (or is not in
+    depth_buf)."""
+    x0, y0, w, h = window
+    bx0, by0, bw, bh = depth_win
+    zz = z.reshape(h, w)
+    hit = np.isfinite(zz)
+    thr = zz * (1.0 + t)
+    edge = np.zeros((h, w), dtype=bool)
+    unsure = np.zeros((h, w), dtype=bool)
+    X = x0 + np.arange(w)[None, :] + np.zeros((h, 1), dtype=np.int64)
+    Y = y0 + np.arange(h)[:, None] + np.zeros((1, w), dtype=np.int64)
+    for dx, dy in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+        qx, qy = X + dx, Y + dy
+        in_img = (qx >= 0) & (qx < W) & (qy >= 0) & (qy < H)
+        ix, iy = qx - bx0, qy - by0
+        in_buf = in_img & (ix >= 0) & (ix < bw) & (iy >= 0) & (iy < bh)
+        zq = np.full((h, w), np.inf)
+        zq[in_buf] = depth_buf[iy[in_buf], ix[in_buf]]
+        with np.errstate(invalid="ignore"):
+            edge |= hit & in_buf & (zq > thr)
+            unsure |= hit & in_buf & np.isfinite(zq) & (np.abs(zq - thr) <= depth_rel * np.abs(zz))
+        unsure |= hit & in_img & ~in_buf
+    return edge, unsure
 
 
 def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=None, depth_win=None,
@@ -535,7 +593,20 @@ def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=Non
                             int(opts.ssao_samples), float(opts.ssao_radius), float(opts.ssao_bias),
                             edge_px=edge_px, depth_rel=depth_rel)
     Vv = -view_dir(cam, W, H, window)
-    rgba = shade(Nv, Vv, albedo.ravel().astype(np.uint32), ao, hit, int(opts.background))
+    fog = (float(getattr(opts, "fog_start", 0.0)), float(getattr(opts, "fog_end", 0.0)),
+           int(getattr(opts, "fog_color", 0)))
+    rgba, band_edge = shade(Nv, Vv, albedo.ravel().astype(np.uint32), ao, hit, int(opts.background),
+                            shading=int(getattr(opts, "shading", SHADE_GLOSSY)), z=zz, fog=fog)
+    # decisions of the post-passes that FP32 may take the other way count
+    # as unstable samples
+    uns = uns + band_edge.astype(uns.dtype)
+    t = float(getattr(opts, "outline_depth", 0.0))
+    if t > 0.0:
+        edge, unsure = outline(W, H, window, zz, np.asarray(depth_buf, dtype=np.float64), depth_win, t,
+                               depth_rel=depth_rel)
+        oc = np.uint32((int(getattr(opts, "outline_color", 0)) & 0xFFFFFF) | 0xFF000000)
+        rgba = np.where(edge.ravel(), oc, rgba).astype(np.uint32)
+        uns = uns + unsure.ravel().astype(uns.dtype)
     return dict(rgba=rgba.reshape(h, w), ao=ao.reshape(h, w),
                 ssao_unstable=uns.reshape(h, w), ssao_outside=outside.reshape(h, w))
 

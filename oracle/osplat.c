@@ -423,10 +423,18 @@ static double os_smooth(double x) {
 
 /* SSAO (R6) and shading (R5) over the window, from depth z, view normals and albedo.
    depth_buf covers (bx0, by0, bw, bh) of the image and is what samples read. */
+/* Deferred pass (SSAO, then the shading mode, fog and outline) over a
+ * window.  shading: 0 glossy, 1 matte, 2 flat, 3 toon; fog from fog_start to
+ * fog_end (none unless fog_end > fog_start); outline_t > 0 draws outlines.
+ * unstable_out counts every decision FP32 may take the other way: SSAO
+ * samples near a pixel edge or their depth threshold, toon band edges and
+ * outline depth thresholds. */
 int osplat_shade(const double* cam, int W, int H, int x0, int y0, int w, int h,
                  const double* z, const double* nrm, const uint32_t* alb,
                  const double* depth_buf, int bx0, int by0, int bw, int bh,
                  int K, double R, double bias, uint32_t background, double edge_px, double depth_rel,
+                 int shading, double fog_start, double fog_end, uint32_t fog_color,
+                 double outline_t, uint32_t outline_color,
                  int nthreads, uint32_t* rgba, double* ao_out, int32_t* unstable_out, int32_t* outside_out) {
     if (K < 0 || K > 1024) return -1;
     os_cam c;
@@ -512,17 +520,56 @@ int osplat_shade(const double* cam, int W, int H, int x0, int y0, int w, int h,
             double ao = K > 0 ? 1.0 - occ / K : 1.0;
             double nv = dot3(N, V);
             if (nv < 0) nv = 0;
-            double sp = 2.0 * nv * nv - 1.0;
-            double spec = OS_KS * pow(sp > 0 ? sp : 0.0, OS_SHININESS);
+            /* shading mode: lit = ka + kd * (facing term), times AO; glossy
+               adds the white highlight */
+            double lit, spec = 0.0;
+            if (shading == 2) {
+                lit = ao;
+            } else if (shading == 3) {
+                double band = floor(4.0 * nv);
+                if (band > 3.0) band = 3.0;
+                lit = (OS_KA + OS_KD * band / 3.0) * ao;
+                double k = floor(4.0 * nv + 0.5);
+                if (k >= 1.0 && k <= 3.0 && fabs(4.0 * nv - k) <= 1e-4) ++uns;
+            } else {
+                lit = (OS_KA + OS_KD * nv) * ao;
+                if (shading == 0) {
+                    double sp = 2.0 * nv * nv - 1.0;
+                    spec = OS_KS * pow(sp > 0 ? sp : 0.0, OS_SHININESS);
+                }
+            }
+            double fogf = 0.0;
+            if (fog_end > fog_start) {
+                fogf = (zz - fog_start) / (fog_end - fog_start);
+                if (fogf < 0.0) fogf = 0.0;
+                if (fogf > 1.0) fogf = 1.0;
+            }
             uint32_t a = alb[q], out = 0;
             for (int ch = 0; ch < 3; ++ch) {
                 double al = ((a >> (8 * ch)) & 255u) / 255.0;
-                double cc = al * (OS_KA + OS_KD * nv) * ao + spec;
+                double cc = al * lit + spec;
+                cc = (1.0 - fogf) * cc + fogf * (((fog_color >> (8 * ch)) & 255u) / 255.0);
                 if (cc < 0) cc = 0;
                 if (cc > 1) cc = 1;
                 out |= ((uint32_t)floor(255.0 * cc + 0.5)) << (8 * ch);
             }
-            rgba[q] = out | (255u << 24);
+            out |= 255u << 24;
+            if (outline_t > 0.0) {
+                static const int nb[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+                double thr = zz * (1.0 + outline_t);
+                int edge = 0;
+                for (int e = 0; e < 4; ++e) {
+                    int QX = X + nb[e][0], QY = Y + nb[e][1];
+                    if (QX < 0 || QX >= W || QY < 0 || QY >= H) continue;
+                    int ix = QX - bx0, iy = QY - by0;
+                    if (ix < 0 || ix >= bw || iy < 0 || iy >= bh) { ++uns; continue; }
+                    double zq = depth_buf[(int64_t)iy * bw + ix];
+                    if (zq > thr) edge = 1;
+                    if (isfinite(zq) && fabs(zq - thr) <= depth_rel * fabs(zz)) ++uns;
+                }
+                if (edge) out = (outline_color & 0xFFFFFFu) | (255u << 24);
+            }
+            rgba[q] = out;
             ao_out[q] = ao;
             unstable_out[q] = uns;
             outside_out[q] = outside;

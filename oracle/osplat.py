@@ -48,7 +48,10 @@ def lib():
                                    ctypes.c_int, ctypes.c_int, P, P, P, P,
                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
-                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P, P, P]
+                                   ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
+                                   ctypes.c_double, ctypes.c_uint32,
+                                   ctypes.c_int, P, P, P, P]
         _lib = L
     return _lib
 
@@ -135,7 +138,11 @@ def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=Non
     rc = lib().osplat_shade(_ptr(ca), W, H, x0, y0, w, h, _ptr(zz), _ptr(nn), _ptr(al), _ptr(db),
                             bx0, by0, bw, bh, int(opts.ssao_samples), float(opts.ssao_radius),
                             float(opts.ssao_bias), int(opts.background) & 0xFFFFFFFF,
-                            float(edge_px), float(depth_rel), nthreads or default_threads(),
+                            float(edge_px), float(depth_rel), int(getattr(opts, "shading", 0)),
+                            float(getattr(opts, "fog_start", 0.0)), float(getattr(opts, "fog_end", 0.0)),
+                            int(getattr(opts, "fog_color", 0)) & 0xFFFFFFFF,
+                            float(getattr(opts, "outline_depth", 0.0)),
+                            int(getattr(opts, "outline_color", 0)) & 0xFFFFFFFF, nthreads or default_threads(),
                             _ptr(rgba), _ptr(ao), _ptr(uns), _ptr(outside))
     if rc != 0:
         raise RuntimeError(f"osplat_shade failed: {rc}")

@@ -400,6 +400,10 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
         return fail(VTX_EINVAL, "unknown representation %d", o.representation);
     if (o.representation == VTX_REP_SAS && !(o.probe_radius >= 0.0f && std::isfinite(o.probe_radius)))
         return fail(VTX_EINVAL, "probe_radius must be finite and >= 0");
+    if (o.shading < VTX_SHADE_GLOSSY || o.shading > VTX_SHADE_TOON) return fail(VTX_EINVAL, "unknown shading %d", o.shading);
+    if (!std::isfinite(o.fog_start) || !std::isfinite(o.fog_end)) return fail(VTX_EINVAL, "fog depths must be finite");
+    if (!(o.outline_depth >= 0.0f) || !std::isfinite(o.outline_depth))
+        return fail(VTX_EINVAL, "outline_depth must be finite and >= 0");
 
     double e[3], f[3], up[3], s[3], u[3];
     for (int k = 0; k < 3; ++k) {
@@ -468,6 +472,12 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
     F->flags = o.flags;
     F->rep = o.representation;
     F->probe = o.probe_radius;
+    F->shading = o.shading;
+    F->fog_start = o.fog_start;
+    F->fog_inv = o.fog_end > o.fog_start ? (float)(1.0 / ((double)o.fog_end - (double)o.fog_start)) : 0.0f;
+    for (int ch = 0; ch < 3; ++ch) F->fog_rgb[ch] = (float)((o.fog_color >> (8 * ch)) & 255u) * (1.0f / 255.0f);
+    F->outline_t = o.outline_depth;
+    F->outline_rgba = o.outline_color | 0xFF000000u;
     return VTX_OK;
 }
 
@@ -482,6 +492,12 @@ vtx_options resolve_options(const vtx_options* opt) {
     o.flags = 0u;
     o.representation = VTX_REP_BALL_AND_STICK;
     o.probe_radius = 1.4f;
+    o.shading = VTX_SHADE_GLOSSY;
+    o.fog_color = 0u;
+    o.fog_start = 0.0f;
+    o.fog_end = 0.0f;
+    o.outline_color = 0u;
+    o.outline_depth = 0.0f;
     return opt ? *opt : o;
 }
 

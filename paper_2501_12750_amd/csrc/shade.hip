@@ -18,7 +18,7 @@ namespace vtx {
 namespace {
 
 constexpr int kTile = 16;
-constexpr int kBatch = 16;  // SSAO samples whose depth loads are issued together
+constexpr int kBatch = 8;   // SSAO samples whose depth loads are issued together
 
 constexpr float kKa = 0.2f, kKd = 0.8f, kKs = 0.25f;
 
@@ -175,15 +175,39 @@ __global__ void __launch_bounds__(kBlock) k_shade(JS js) {
     uint32_t out = K.background;
     if (hit) {
         const float nv = fmaxf(0.0f, fmaf(nx, Vx, fmaf(ny, Vy, nz * Vz)));
-        float sp = fmaxf(0.0f, fmaf(2.0f * nv, nv, -1.0f));
-        sp *= sp; sp *= sp; sp *= sp; sp *= sp; sp *= sp;     // ^32
-        const float spec = kKs * sp;
-        const float diff = fmaf(kKd, nv, kKa) * ao;
-        const float r = (float)(alb & 255u) * (1.0f / 255.0f);
-        const float g = (float)((alb >> 8) & 255u) * (1.0f / 255.0f);
-        const float bch = (float)((alb >> 16) & 255u) * (1.0f / 255.0f);
-        out = quantize(fmaf(r, diff, spec)) | (quantize(fmaf(g, diff, spec)) << 8) |
-              (quantize(fmaf(bch, diff, spec)) << 16) | (255u << 24);
+        // shading mode: a diffuse factor on the albedo and a white specular term
+        float diff, spec = 0.0f;
+        if (F.shading == 2) {                                  // flat
+            diff = ao;
+        } else if (F.shading == 3) {                           // toon: four bands of n.V
+            diff = fmaf(kKd, fminf(floorf(4.0f * nv), 3.0f) * (1.0f / 3.0f), kKa) * ao;
+        } else {                                               // glossy, matte
+            diff = fmaf(kKd, nv, kKa) * ao;
+            if (F.shading == 0) {
+                float sp = fmaxf(0.0f, fmaf(2.0f * nv, nv, -1.0f));
+                sp *= sp; sp *= sp; sp *= sp; sp *= sp; sp *= sp;     // ^32
+                spec = kKs * sp;
+            }
+        }
+        float c[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) c[ch] = fmaf((float)((alb >> (8 * ch)) & 255u) * (1.0f / 255.0f), diff, spec);
+        if (F.fog_inv > 0.0f) {
+            const float f = fminf(fmaxf((z - F.fog_start) * F.fog_inv, 0.0f), 1.0f);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) c[ch] = fmaf(f, F.fog_rgb[ch] - c[ch], c[ch]);
+        }
+        out = quantize(c[0]) | (quantize(c[1]) << 8) | (quantize(c[2]) << 16) | (255u << 24);
+        if (F.outline_t > 0.0f) {
+            // a neighbour in the image that is background or deeper by the step
+            const float zt = z * (1.0f + F.outline_t);
+            bool edge = false;
+            if (x + 1 < F.W) edge = edge || depth[p + 1] > zt;
+            if (x > 0) edge = edge || depth[p - 1] > zt;
+            if (y + 1 < F.H) edge = edge || depth[p + (size_t)F.W] > zt;
+            if (y > 0) edge = edge || depth[p - (size_t)F.W] > zt;
+            if (edge) out = F.outline_rgba;
+        }
     }
     rgba[p] = out;
     if (normal_out) {

@@ -39,6 +39,11 @@ struct Frame {
     uint32_t flags;
     int32_t rep;                       // VTX_REP_* : radius of the atom spheres
     float probe;                       // VTX_REP_SAS probe radius
+    int32_t shading;                   // VTX_SHADE_*
+    float fog_start, fog_inv;          // fog factor (z - fog_start) * fog_inv; fog_inv = 0: no fog
+    float fog_rgb[3];
+    float outline_t;                   // relative depth step of an outline; 0: none
+    uint32_t outline_rgba;             // packed RGBA8 of outline pixels (alpha 255)
 };
 
 // Sphere radius of an atom of given radius r under the frame's representation.

@@ -80,12 +80,21 @@ class Options:
     flags: int = 0
     representation: int = 0      # 0 ball-and-stick, 1 van der Waals, 2 sticks, 3 solvent-accessible surface
     probe_radius: float = 1.4
+    shading: int = 0             # 0 glossy, 1 matte, 2 flat, 3 toon
+    fog_color: int = 0           # packed RGBA8
+    fog_start: float = 0.0       # view depths; no fog unless fog_end > fog_start
+    fog_end: float = 0.0
+    outline_color: int = 0       # packed RGBA8
+    outline_depth: float = 0.0   # relative depth step of an outline; 0: none
 
     def __post_init__(self):
         self.bond_radius = f32(self.bond_radius)
         self.ssao_radius = f32(self.ssao_radius)
         self.ssao_bias = f32(self.ssao_bias)
         self.probe_radius = f32(self.probe_radius)
+        self.fog_start = f32(self.fog_start)
+        self.fog_end = f32(self.fog_end)
+        self.outline_depth = f32(self.outline_depth)
 
 
 @dataclasses.dataclass

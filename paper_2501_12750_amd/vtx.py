@@ -31,6 +31,7 @@ VTX_SSAO_AUTO = -1
 VTX_FLAG_STATS = 1
 VTX_FLAG_TIMING = 2
 VTX_REP_BALL_AND_STICK, VTX_REP_VAN_DER_WAALS, VTX_REP_STICKS, VTX_REP_SAS = 0, 1, 2, 3
+VTX_SHADE_GLOSSY, VTX_SHADE_MATTE, VTX_SHADE_FLAT, VTX_SHADE_TOON = 0, 1, 2, 3
 
 # Every symbol include/vtx.h declares.
 EXPORTS = ("vtx_render", "vtx_gbuffer", "vtx_shade", "vtx_read_stats", "vtx_set_bin_capacity",
@@ -54,7 +55,9 @@ class vtx_options(ctypes.Structure):
     _fields_ = [("bond_radius", ctypes.c_float), ("ssao_samples", ctypes.c_int32),
                 ("ssao_radius", ctypes.c_float), ("ssao_bias", ctypes.c_float),
                 ("background", ctypes.c_uint32), ("tile_size", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("representation", ctypes.c_int32), ("probe_radius", ctypes.c_float)]
+                ("representation", ctypes.c_int32), ("probe_radius", ctypes.c_float),
+                ("shading", ctypes.c_int32), ("fog_color", ctypes.c_uint32), ("fog_start", ctypes.c_float),
+                ("fog_end", ctypes.c_float), ("outline_color", ctypes.c_uint32), ("outline_depth", ctypes.c_float)]
 
 
 class vtx_stats(ctypes.Structure):
@@ -250,6 +253,12 @@ def options_struct(opts) -> vtx_options:
     o.flags = int(getattr(opts, "flags", 0))
     o.representation = int(getattr(opts, "representation", 0))
     o.probe_radius = float(getattr(opts, "probe_radius", 1.4))
+    o.shading = int(getattr(opts, "shading", 0))
+    o.fog_color = int(getattr(opts, "fog_color", 0)) & 0xFFFFFFFF
+    o.fog_start = float(getattr(opts, "fog_start", 0.0))
+    o.fog_end = float(getattr(opts, "fog_end", 0.0))
+    o.outline_color = int(getattr(opts, "outline_color", 0)) & 0xFFFFFFFF
+    o.outline_depth = float(getattr(opts, "outline_depth", 0.0))
     return o
 
 

@@ -306,3 +306,30 @@ def test_representations(vtx, rep):
         assert np.array_equal(got[k], plain[k]), k
     rs.close()
     vtx.vtx_context_destroy(ctx)
+
+
+@pytest.mark.parametrize("shading", [0, 1, 2, 3])
+def test_post_passes(vtx, shading):
+    """Shading modes, fog and outline (the deferred post-passes): the oracle
+    shades the device's own G-buffer with the same options (cross-fed), and
+    end to end without the outline (whose decision also reads neighbouring
+    pixels' visibility)."""
+    wl = scenes.ball_and_stick(n_globules=8, atoms_per_globule=300, sigma=4.0, pitch=6.0,
+                               width=240, height=160, ssao_samples=16)
+    el = np.random.default_rng(5).choice(5, size=wl.scene.n_atoms, p=scenes.ELEMENT_MIX)
+    wl.scene = scenes.Scene(wl.scene.positions, np.ascontiguousarray(scenes.ELEMENT_VDW[el]),
+                            wl.scene.colors, wl.scene.bonds)
+    dist = float(np.linalg.norm(np.asarray(wl.camera.eye) - np.asarray(wl.camera.target)))
+    fog = dict(fog_color=scenes.pack_rgba(40, 80, 160), fog_start=dist - 15.0, fog_end=dist + 15.0)
+    wl.options = with_opts(wl.options, representation=1, shading=shading, **fog)
+    dev, ref, rep = full_parity(vtx, wl, name=f"post shading={shading} fog")
+    assert rep["shade_checked"] > 0.9 * rep["pixels"]
+    # with the outline: cross-fed
+    oc = scenes.pack_rgba(250, 250, 0)
+    opts = with_opts(wl.options, outline_color=oc, outline_depth=0.2)
+    dev = run_device(vtx, vtx.DeviceScene(wl.scene), wl.camera, opts, wl.width, wl.height)
+    rx = compare.check_shading_crossfed(wl.camera, opts, wl.width, wl.height, dev)
+    print("outline", rx, flush=True)
+    assert rx["rgb_bad"] == 0 and rx["shade_checked"] > 0.9 * wl.width * wl.height
+    drawn = np.asarray(dev["rgba"]) == (oc | (255 << 24))
+    assert drawn.sum() > 100 and (~drawn & (np.asarray(dev["id"]) != 0xFFFFFFFF)).sum() > 1000

@@ -114,3 +114,25 @@ def test_orthographic_scene():
     a = ofull.render(wl.scene, cam, wl.options, wl.width, wl.height)
     b = osplat.render(wl.scene, cam, wl.options, wl.width, wl.height)
     assert_same(a, b, shading=True)
+
+
+@pytest.mark.parametrize("shading", [0, 1, 2, 3])
+def test_post_passes_agree(shading):
+    """Both oracles give the same image and the same unstable counts with a
+    shading mode, fog and outline on, over a crop with a halo (the outline
+    and SSAO read depths across the crop's edge)."""
+    import dataclasses
+    wl = scenes.ball_and_stick(n_globules=6, atoms_per_globule=200, sigma=4.0, pitch=6.0,
+                               width=90, height=80, ssao_samples=8)
+    c = np.asarray(wl.camera.eye, dtype=np.float64)
+    t = np.asarray(wl.camera.target, dtype=np.float64)
+    dist = float(np.linalg.norm(c - t))
+    opts = dataclasses.replace(wl.options, representation=1, shading=shading, fog_color=scenes.pack_rgba(30, 60, 90),
+                               fog_start=dist - 10.0, fog_end=dist + 10.0, outline_color=scenes.pack_rgba(5, 5, 5),
+                               outline_depth=0.2)
+    win = (20, 15, 40, 35)
+    a = ofull.render(wl.scene, wl.camera, opts, wl.width, wl.height, window=win, halo=12)
+    b = osplat.render(wl.scene, wl.camera, opts, wl.width, wl.height, window=win, halo=12)
+    assert_same(a, b, shading=True)
+    outline = a["rgba"] == (scenes.pack_rgba(5, 5, 5) | (255 << 24))
+    assert outline.sum() > 10 and (~outline & (a["id"] != BG)).sum() > 30

@@ -538,3 +538,117 @@ def test_representations_without_bonds_keep_ids(oracle):
         g = oracle.gbuffer(sc, cam, scenes.Options(representation=rep, bond_radius=0.5), 96, 64)
         ids = set(np.unique(g["id"]).tolist())
         assert ids - {BG} == ({0, 1, 2} if has_bond else {0, 1}), rep
+
+
+# ---------------------------------------------------------------------------
+# deferred post-passes: shading modes, fog, outline
+# ---------------------------------------------------------------------------
+def _ortho_disk(W, H, scale, cx, cy, r):
+    """Pixel centres inside the orthographic disk of a sphere (exact)."""
+    pcx = Fraction(W, 2) + cx * scale
+    pcy = Fraction(H, 2) - cy * scale
+    inside = np.zeros((H, W), dtype=bool)
+    rho2 = np.zeros((H, W), dtype=object)
+    for j in range(H):
+        for i in range(W):
+            d2 = ((i + Fraction(1, 2) - pcx) ** 2 + (j + Fraction(1, 2) - pcy) ** 2) / scale ** 2
+            rho2[j, i] = d2
+            inside[j, i] = d2 < r * r
+    return inside, rho2
+
+
+def test_flat_and_matte_shading_give_the_albedo(oracle):
+    """Flat shading without AO is the albedo on every hit pixel; matte on the
+    ray through an orthographic sphere's centre (n.V = 1) is too
+    (0.2 + 0.8 = 1), and glossy adds the 0.25 highlight there."""
+    W, H = 33, 33
+    alb = scenes.pack_rgba(200, 100, 7)
+    cam = ortho(eye=(0.0, 0.0, 20.0), target=(0.0, 0.0, 0.0), half_h=4.0)
+    sc = make_scene([(0.0, 0.0, 0.0)], [3.0], colors=[alb])
+    flat = oracle.render(sc, cam, scenes.Options(shading=2), W, H)
+    hit = flat["id"] == 0
+    assert hit.sum() > 300
+    assert np.all(flat["rgba"][hit] == (alb | (255 << 24)))
+    matte = oracle.render(sc, cam, scenes.Options(shading=1), W, H)
+    assert matte["rgba"][16, 16] == (alb | (255 << 24))
+    # matte never exceeds the albedo; glossy differs from matte only where the
+    # highlight is non-zero, i.e. n.V > 1/sqrt(2)
+    glossy = oracle.render(sc, cam, scenes.Options(shading=0), W, H)
+    assert np.all((matte["rgba"][hit] & 255) <= 200)
+    assert (glossy["rgba"][16, 16] & 255) == 255
+
+
+def test_toon_bands_are_rings_of_the_disk(oracle):
+    """Toon shading of an orthographic sphere: n.V = sqrt(1 - rho^2/r^2), so
+    band k (floor(4 n.V) = k, capped at 3) is the ring of pixel centres with
+    1 - ((k+1)/4)^2 < rho^2/r^2 <= 1 - (k/4)^2; its colour is
+    albedo (0.2 + 0.8 min(k, 3)/3).  Counted on the exact lattice."""
+    W, H, hh = 64, 64, 8.0
+    scale = Fraction(H, 2) / Fraction(8)
+    cx, cy, r = Fraction(3, 16), Fraction(-1, 8), Fraction(6)
+    cam = ortho(eye=(0.0, 0.0, 30.0), target=(0.0, 0.0, 0.0), half_h=hh)
+    alb = scenes.pack_rgba(255, 120, 60)
+    sc = make_scene([(float(cx), float(cy), 0.0)], [float(r)], colors=[alb])
+    res = oracle.render(sc, cam, scenes.Options(shading=3), W, H)
+    inside, rho2 = _ortho_disk(W, H, scale, cx, cy, r)
+    u = np.zeros((H, W), dtype=object)
+    u[inside] = [x / (r * r) for x in rho2[inside]]
+    for k in range(4):
+        lo, hi = 1 - Fraction(k + 1, 4) ** 2, 1 - Fraction(k, 4) ** 2
+        ring = inside & np.vectorize(lambda v, lo=lo, hi=hi: lo < v <= hi if v is not None else False,
+                                     otypes=[bool])(np.where(inside, u, None))
+        if k == 3:
+            ring |= inside & np.vectorize(lambda v: v <= 1 - Fraction(1, 1) ** 2 if v is not None else False,
+                                          otypes=[bool])(np.where(inside, u, None))
+        lit = 0.2 + 0.8 * min(k, 3) / 3
+        exp = [math.floor(255 * min(1.0, ch / 255 * lit) + 0.5) for ch in (255, 120, 60)]
+        packed = exp[0] | (exp[1] << 8) | (exp[2] << 16) | (255 << 24)
+        # pixels on a band edge (FP rounding of 4 n.V) are flagged unstable
+        sure = ring & (res["ssao_unstable"] == 0)
+        assert sure.sum() >= ring.sum() - 8
+        assert np.all(res["rgba"][sure] == packed), k
+
+
+def test_fog_reaches_its_colour_and_blends_halfway(oracle):
+    """Orthographic sphere of radius 3 whose centre is 13 from the eye: the
+    centre pixel's depth is 10.  With fog from 9 to 11 it is half way (flat
+    shading: (albedo + fog)/2 per channel); with fog ending before 7 (the
+    nearest depth) every hit pixel is the fog colour; with fog starting
+    beyond 13 nothing changes."""
+    W, H = 33, 33
+    alb = scenes.pack_rgba(200, 100, 0)
+    fogc = scenes.pack_rgba(0, 100, 250)
+    cam = ortho(eye=(0.0, 0.0, 13.0), target=(0.0, 0.0, 0.0), half_h=4.0)
+    sc = make_scene([(0.0, 0.0, 0.0)], [3.0], colors=[alb])
+    half = oracle.render(sc, cam, scenes.Options(shading=2, fog_color=fogc, fog_start=9.0, fog_end=11.0), W, H)
+    assert half["rgba"][16, 16] == (100 | (100 << 8) | (125 << 16) | (255 << 24))
+    full = oracle.render(sc, cam, scenes.Options(shading=0, fog_color=fogc, fog_start=1.0, fog_end=6.5), W, H)
+    hit = full["id"] == 0
+    assert np.all(full["rgba"][hit] == (fogc | (255 << 24)))
+    none = oracle.render(sc, cam, scenes.Options(fog_color=fogc, fog_start=14.0, fog_end=20.0), W, H)
+    plain = oracle.render(sc, cam, scenes.Options(), W, H)
+    assert np.array_equal(none["rgba"], plain["rgba"])
+
+
+def test_outline_is_the_disk_rim(oracle):
+    """A distant orthographic sphere (depths within 1 % of each other) on a
+    background: with a 2 % step the outline pixels are exactly the hit
+    pixels with a 4-neighbour inside the image and outside the disk."""
+    W, H, hh = 48, 40, 8.0
+    scale = Fraction(H, 2) / Fraction(8)
+    cx, cy, r = Fraction(5, 8), Fraction(1, 4), Fraction(5)
+    cam = ortho(eye=(0.0, 0.0, 1000.0), target=(0.0, 0.0, 0.0), half_h=hh)
+    outline_c = scenes.pack_rgba(1, 2, 3)
+    sc = make_scene([(float(cx), float(cy), 0.0)], [float(r)], colors=[scenes.pack_rgba(90, 90, 90)])
+    res = oracle.render(sc, cam, scenes.Options(outline_color=outline_c, outline_depth=0.02), W, H)
+    inside, _ = _ortho_disk(W, H, scale, cx, cy, r)
+    rim = np.zeros_like(inside)
+    for dj, di in ((0, 1), (0, -1), (1, 0), (-1, 0)):
+        nb = np.ones_like(inside)                                 # outside the image: not counted
+        src = inside[max(0, dj):H + min(0, dj), max(0, di):W + min(0, di)]
+        nb[max(0, -dj):H + min(0, -dj), max(0, -di):W + min(0, -di)] = src
+        rim |= inside & ~nb
+    hit = res["id"] == 0
+    assert np.array_equal(hit, inside)
+    assert rim.sum() > 20
+    assert np.array_equal(res["rgba"] == (outline_c | (255 << 24)), rim)
