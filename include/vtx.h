@@ -110,7 +110,18 @@ typedef struct vtx_options {
                                  fog_end <= fog_start: no fog (0, 0) */
     uint32_t outline_color;   /* RGBA8 of outline pixels (alpha ignored) */
     float outline_depth;      /* relative depth step that makes an outline; 0: none (0) */
+    float clip_plane[4];      /* world plane a, b, c, d; a x + b y + c z + d >= 0 is kept;
+                                 all zero: no clipping (0, 0, 0, 0) */
 } vtx_options;
+
+/*
+ * options.clip_plane (paper, Results, the whole-cell figure shown with and
+ * without clipping): a primitive's ray hit whose surface point lies on the
+ * cut side is dropped, so the primitive draws nothing at that pixel and what
+ * lies behind it shows; the cut primitives' interiors are not drawn.  The
+ * test is made per pixel in FP32 in view space; the images otherwise obey
+ * the same visibility rule.  VTX_EINVAL when (a, b, c) is zero but d is not.
+ */
 
 /*
  * Deferred post-passes on the G-buffer (paper, Methods, "High Quality

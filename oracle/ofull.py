@@ -39,6 +39,9 @@ notes:
                 colour between two view depths; a hit pixel with an in-image
                 4-neighbour that is background or deeper than z (1 + t) takes
                 the outline colour.
+  R8 clip       a world plane a x + b y + c z + d >= 0 keeps its side: a
+                primitive's hit on the cut side is dropped (the primitive
+                draws nothing at that pixel; interiors are not drawn).
 
 Because FP32 on the device and FP64 here can disagree where a result is
 decided by a near-tie, every pixel also carries an accept set: the ids that
@@ -140,7 +143,7 @@ def sphere_candidates(o, d, c, r, e, f, znear, zfar):
     n = (x[sel] - c[None, :]) / r
     return dict(pix=keep[sel], z=z[sel], valid=valid[sel], graze=graze[sel], normal=n,
                 side=np.zeros(sel.size, dtype=np.int8), unstable=np.zeros(sel.size, dtype=bool),
-                tangent_nv=-_dot(n, dd[sel]))
+                tangent_nv=-_dot(n, dd[sel]), x=x[sel])
 
 
 # ---------------------------------------------------------------------------
@@ -240,7 +243,7 @@ def cylinder_candidates(o, d, A, B, rho, e, f, znear, zfar):
     unstable = colour_edge | (side_end[keep][sel]) | (kk != 0) & (capA_graze | capB_graze)[keep][sel]
     return dict(pix=keep[sel], z=z[sel], valid=valid[sel], graze=graze[sel], normal=n,
                 side=kk.astype(np.int8), half_b=half_b, unstable=unstable,
-                tangent_nv=-_dot(n, dd[sel]))
+                tangent_nv=-_dot(n, dd[sel]), x=xs)
 
 
 # ---------------------------------------------------------------------------
@@ -302,8 +305,22 @@ def gbuffer(scene, cam, opts, W, H, window=None):
     rad = scene.radii.astype(np.float64)
     N = scene.n_atoms
     rec = {k: [] for k in ("pix", "id", "z", "valid", "graze", "normal", "albedo", "unstable", "nv")}
+    plane = np.asarray(getattr(opts, "clip_plane", (0.0, 0.0, 0.0, 0.0)), dtype=np.float64)
 
     def add(c, pid, alb):
+        if np.any(plane != 0.0):
+            # R8 clip plane: a surface point with a x + b y + c z + d < 0 is
+            # cut away (the primitive draws nothing there); within rounding
+            # of the plane either outcome is accepted
+            terms = c["x"] * plane[None, :3]
+            v = terms.sum(axis=1) + plane[3]
+            tol = TAU * (np.abs(terms).sum(axis=1) + abs(plane[3]))
+            keep = v >= -tol
+            c = {k: (a[keep] if isinstance(a, np.ndarray) and a.shape[:1] == keep.shape else a) for k, a in c.items()}
+            alb = alb[keep]
+            v, tol = v[keep], tol[keep]
+            c["valid"] = c["valid"] & (v >= 0.0)
+            c["graze"] = c["graze"] | (np.abs(v) <= tol)
         m = c["pix"].size
         rec["pix"].append(c["pix"])
         rec["id"].append(np.full(m, pid, dtype=np.int64))

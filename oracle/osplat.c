@@ -38,6 +38,8 @@ typedef struct {
     double e[3], s[3], u[3], f[3];
     double tanh_, aspect, hh, znear, zfar;
     int proj, W, H;
+    double clip[4];   /* world plane a, b, c, d: a x + b y + c z + d >= 0 is kept */
+    int clip_on;
 } os_cam;
 
 static double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -53,7 +55,8 @@ static void cross3(const double* a, const double* b, double* c) {
     c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-/* cam = eye3, target3, up3, fovy, ortho_half_height, projection, znear, zfar */
+/* cam = eye3, target3, up3, fovy, ortho_half_height, projection, znear, zfar,
+ * clip plane a, b, c, d (all zero: no clipping) */
 static void os_make_cam(const double* cam, int W, int H, os_cam* c) {
     for (int k = 0; k < 3; ++k) { c->e[k] = cam[k]; c->f[k] = cam[3 + k] - cam[k]; }
     norm3(c->f);
@@ -67,6 +70,11 @@ static void os_make_cam(const double* cam, int W, int H, os_cam* c) {
     c->zfar = cam[13];
     c->W = W; c->H = H;
     c->aspect = (double)W / (double)H;
+    c->clip_on = 0;
+    for (int k = 0; k < 4; ++k) {
+        c->clip[k] = cam[14 + k];
+        if (cam[14 + k] != 0.0) c->clip_on = 1;
+    }
 }
 
 static void os_ray(const os_cam* c, int i, int j, double* o, double* d) {
@@ -149,6 +157,23 @@ static void os_zclass(const os_cam* c, double z, int geom_hit, int geom_graze, o
     h->graze = h->cand && (geom_graze || zgr);
 }
 
+/* Clip plane: a candidate whose surface point lies on the cut side is not
+ * drawn (nor is anything behind it of the same primitive); within rounding
+ * of the plane it may go either way. */
+static void os_clip(const os_cam* c, const double* x, os_hit* h) {
+    if (!c->clip_on || !h->cand) return;
+    double v = c->clip[0] * x[0] + c->clip[1] * x[1] + c->clip[2] * x[2] + c->clip[3];
+    double sc = fabs(c->clip[0] * x[0]) + fabs(c->clip[1] * x[1]) + fabs(c->clip[2] * x[2]) + fabs(c->clip[3]);
+    double tol = OS_TAU * sc;
+    if (v < -tol) {
+        h->cand = 0;
+        h->valid = 0;
+        return;
+    }
+    if (v < 0.0) h->valid = 0;
+    if (fabs(v) <= tol) h->graze = 1;
+}
+
 static void os_sphere(const os_cam* c, const double* o, const double* d, const double* ctr, double r, os_hit* h) {
     h->cand = 0;
     double oc[3] = {ctr[0] - o[0], ctr[1] - o[1], ctr[2] - o[2]};
@@ -165,6 +190,7 @@ static void os_sphere(const os_cam* c, const double* o, const double* d, const d
     double rel[3] = {x[0] - c->e[0], x[1] - c->e[1], x[2] - c->e[2]};
     double z = dot3(rel, c->f);
     os_zclass(c, z, gh, gg, h);
+    os_clip(c, x, h);
     if (!h->cand) return;
     h->z = z;
     for (int k = 0; k < 3; ++k) h->n[k] = (x[k] - ctr[k]) / r;
@@ -236,6 +262,7 @@ static void os_cylinder(const os_cam* c, const double* o, const double* d, const
     double rel[3] = {x[0] - c->e[0], x[1] - c->e[1], x[2] - c->e[2]};
     double z = dot3(rel, c->f);
     os_zclass(c, z, geom_hit, any_graze, h);
+    os_clip(c, x, h);
     if (!h->cand) return;
     h->z = z;
     double xa[3] = {x[0] - A[0], x[1] - A[1], x[2] - A[2]};

@@ -60,9 +60,10 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def cam_array(cam) -> np.ndarray:
+def cam_array(cam, opts=None) -> np.ndarray:
+    clip = [float(v) for v in getattr(opts, "clip_plane", (0.0, 0.0, 0.0, 0.0))] if opts is not None else [0.0] * 4
     return np.array(list(cam.eye) + list(cam.target) + list(cam.up)
-                    + [cam.fovy, cam.ortho_half_height, float(cam.projection), cam.znear, cam.zfar],
+                    + [cam.fovy, cam.ortho_half_height, float(cam.projection), cam.znear, cam.zfar] + clip,
                     dtype=np.float64)
 
 
@@ -93,7 +94,7 @@ def gbuffer(scene, cam, opts, W, H, window=None, nthreads=None):
                acc_id=np.empty((P, MAX_ACCEPT), dtype=np.uint32), acc_z=np.empty((P, MAX_ACCEPT)),
                acc_bg=np.empty(P, dtype=np.uint8))
     frag = np.zeros(1, dtype=np.int64)
-    ca = cam_array(cam)
+    ca = cam_array(cam, opts)
     rc = lib().osplat_gbuffer(scene.n_atoms, _ptr(pos), _ptr(rad), _ptr(col), nb, _ptr(bonds),
                               float(opts.bond_radius), _ptr(ca), W, H, x0, y0, w, h,
                               nthreads or default_threads(),

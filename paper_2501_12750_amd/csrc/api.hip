@@ -404,6 +404,10 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
     if (!std::isfinite(o.fog_start) || !std::isfinite(o.fog_end)) return fail(VTX_EINVAL, "fog depths must be finite");
     if (!(o.outline_depth >= 0.0f) || !std::isfinite(o.outline_depth))
         return fail(VTX_EINVAL, "outline_depth must be finite and >= 0");
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(o.clip_plane[k])) return fail(VTX_EINVAL, "clip_plane must be finite");
+    const bool clip_on = o.clip_plane[0] != 0.0f || o.clip_plane[1] != 0.0f || o.clip_plane[2] != 0.0f;
+    if (!clip_on && o.clip_plane[3] != 0.0f) return fail(VTX_EINVAL, "clip_plane has a zero normal");
 
     double e[3], f[3], up[3], s[3], u[3];
     for (int k = 0; k < 3; ++k) {
@@ -478,6 +482,15 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
     for (int ch = 0; ch < 3; ++ch) F->fog_rgb[ch] = (float)((o.fog_color >> (8 * ch)) & 255u) * (1.0f / 255.0f);
     F->outline_t = o.outline_depth;
     F->outline_rgba = o.outline_color | 0xFF000000u;
+    F->clip_on = clip_on ? 1 : 0;
+    if (clip_on) {
+        // a.x + d with x = eye + X s + Y u + Z f: (a.s, a.u, a.f, a.eye + d)
+        const double a[3] = {o.clip_plane[0], o.clip_plane[1], o.clip_plane[2]};
+        F->clip[0] = (float)(a[0] * s[0] + a[1] * s[1] + a[2] * s[2]);
+        F->clip[1] = (float)(a[0] * u[0] + a[1] * u[1] + a[2] * u[2]);
+        F->clip[2] = (float)(a[0] * f[0] + a[1] * f[1] + a[2] * f[2]);
+        F->clip[3] = (float)(a[0] * e[0] + a[1] * e[1] + a[2] * e[2] + (double)o.clip_plane[3]);
+    }
     return VTX_OK;
 }
 
@@ -498,6 +511,7 @@ vtx_options resolve_options(const vtx_options* opt) {
     o.fog_end = 0.0f;
     o.outline_color = 0u;
     o.outline_depth = 0.0f;
+    for (float& v : o.clip_plane) v = 0.0f;
     return opt ? *opt : o;
 }
 

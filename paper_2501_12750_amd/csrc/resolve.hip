@@ -238,7 +238,10 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
                 ox = ndx * F.hxf; oy = ndy * F.hyf; Dx = 0.f; Dy = 0.f;
             }
             const float z = rc.kind == 0 ? hit_sphere(rc.a, ox, oy, Dx, Dy) : hit_cylinder(rc.a, rc.b, ox, oy, Dx, Dy);
-            const bool hit = z >= F.znear && z <= F.zfar;
+            bool hit = z >= F.znear && z <= F.zfar;
+            // clip plane: the hit point (ox + z Dx, oy + z Dy, z) on the cut side draws nothing
+            if (F.clip_on && hit)
+                hit = fmaf(F.clip[0], fmaf(z, Dx, ox), fmaf(F.clip[1], fmaf(z, Dy, oy), fmaf(F.clip[2], z, F.clip[3]))) >= 0.0f;
             if (stats) {
                 n_tested += 1;
                 n_hit += hit ? 1 : 0;

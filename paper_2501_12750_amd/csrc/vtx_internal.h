@@ -44,6 +44,8 @@ struct Frame {
     float fog_rgb[3];
     float outline_t;                   // relative depth step of an outline; 0: none
     uint32_t outline_rgba;             // packed RGBA8 of outline pixels (alpha 255)
+    int32_t clip_on;                   // a clip plane is set
+    float clip[4];                     // the plane in view coordinates: kept where clip . (x, y, z, 1) >= 0
 };
 
 // Sphere radius of an atom of given radius r under the frame's representation.

@@ -86,6 +86,7 @@ class Options:
     fog_end: float = 0.0
     outline_color: int = 0       # packed RGBA8
     outline_depth: float = 0.0   # relative depth step of an outline; 0: none
+    clip_plane: tuple = (0.0, 0.0, 0.0, 0.0)   # a, b, c, d: a x + b y + c z + d >= 0 is kept
 
     def __post_init__(self):
         self.bond_radius = f32(self.bond_radius)
@@ -95,6 +96,7 @@ class Options:
         self.fog_start = f32(self.fog_start)
         self.fog_end = f32(self.fog_end)
         self.outline_depth = f32(self.outline_depth)
+        self.clip_plane = tuple(f32(v) for v in self.clip_plane)
 
 
 @dataclasses.dataclass

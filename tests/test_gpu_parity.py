@@ -333,3 +333,23 @@ def test_post_passes(vtx, shading):
     assert rx["rgb_bad"] == 0 and rx["shade_checked"] > 0.9 * wl.width * wl.height
     drawn = np.asarray(dev["rgba"]) == (oc | (255 << 24))
     assert drawn.sum() > 100 and (~drawn & (np.asarray(dev["id"]) != 0xFFFFFFFF)).sum() > 1000
+
+
+@pytest.mark.parametrize("proj", ["persp", "ortho"])
+def test_clip_plane(vtx, proj):
+    """A clip plane through the scene (bonds included): visibility against the
+    oracle's accept sets, which admit either outcome within rounding of the
+    plane, and the shading on top."""
+    wl = scenes.ball_and_stick(n_globules=27, atoms_per_globule=300, sigma=5.0, pitch=8.0,
+                               width=333, height=221, ssao_samples=16)
+    c = np.asarray(wl.camera.target, dtype=np.float64)
+    if proj == "ortho":
+        e = np.asarray(wl.camera.eye, dtype=np.float64)
+        wl.camera = scenes.Camera(eye=tuple(e), target=tuple(c), projection=scenes.ORTHOGRAPHIC,
+                                  ortho_half_height=25.0)
+    n = np.array([0.6, -0.3, 0.74])
+    wl.options = with_opts(wl.options, clip_plane=(float(n[0]), float(n[1]), float(n[2]), float(-n @ c + 3.0)))
+    dev, ref, rep = full_parity(vtx, wl, name=f"clip plane {proj}")
+    base = run_render(vtx, vtx.DeviceScene(wl.scene), wl.camera, with_opts(wl.options, clip_plane=(0.0, 0.0, 0.0, 0.0)),
+                      wl.width, wl.height)
+    assert np.count_nonzero(dev["id"] != base["id"]) > 1000

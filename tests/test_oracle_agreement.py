@@ -136,3 +136,20 @@ def test_post_passes_agree(shading):
     assert_same(a, b, shading=True)
     outline = a["rgba"] == (scenes.pack_rgba(5, 5, 5) | (255 << 24))
     assert outline.sum() > 10 and (~outline & (a["id"] != BG)).sum() > 30
+
+
+def test_clip_plane_agrees():
+    """Both oracles clip the same (primitive, pixel) hits, bonds included,
+    with the same accept sets where a hit lies within rounding of the plane."""
+    import dataclasses
+    wl = scenes.ball_and_stick(n_globules=6, atoms_per_globule=200, sigma=4.0, pitch=6.0,
+                               width=90, height=80, ssao_samples=8)
+    c = np.asarray(wl.camera.target, dtype=np.float64)
+    n = np.array([0.6, -0.3, 0.74])
+    opts = dataclasses.replace(wl.options, clip_plane=(float(n[0]), float(n[1]), float(n[2]), float(-n @ c)))
+    a = ofull.render(wl.scene, wl.camera, opts, wl.width, wl.height)
+    b = osplat.render(wl.scene, wl.camera, opts, wl.width, wl.height)
+    assert_same(a, b, shading=True)
+    full = osplat.render(wl.scene, wl.camera, wl.options, wl.width, wl.height)
+    assert np.count_nonzero(a["id"] != full["id"]) > 200
+    assert np.any(a["id"] >= wl.scene.n_atoms) and np.any((a["id"] < wl.scene.n_atoms))

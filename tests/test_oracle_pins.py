@@ -652,3 +652,61 @@ def test_outline_is_the_disk_rim(oracle):
     assert np.array_equal(hit, inside)
     assert rim.sum() > 20
     assert np.array_equal(res["rgba"] == (outline_c | (255 << 24)), rim)
+
+
+# ---------------------------------------------------------------------------
+# clip plane
+# ---------------------------------------------------------------------------
+def test_clip_plane_halves_the_disk(oracle):
+    """Orthographic view down -z of a sphere cut by the plane x >= 0: the
+    drawn pixels are exactly the disk's pixel centres with world x >= 0 (no
+    centre lies on the plane), and the rest is background."""
+    W, H, hh = 64, 64, 8.0
+    scale = Fraction(H, 2) / Fraction(8)
+    cx, cy, r = Fraction(-3, 8), Fraction(1, 4), Fraction(11, 4)
+    cam = ortho(eye=(0.0, 0.0, 30.0), target=(0.0, 0.0, 0.0), half_h=hh)
+    sc = make_scene([(float(cx), float(cy), 0.0)], [float(r)])
+    g = oracle.gbuffer(sc, cam, scenes.Options(clip_plane=(1.0, 0.0, 0.0, 0.0)), W, H)
+    inside, _ = _ortho_disk(W, H, scale, cx, cy, r)
+    xs = np.array([(i + Fraction(1, 2) - Fraction(W, 2)) / scale for i in range(W)], dtype=object)
+    keep = inside & (xs[None, :] > 0)
+    assert keep.sum() > 100 and (inside & ~keep).sum() > 200
+    assert np.array_equal(g["id"] == 0, keep)
+
+
+def test_clip_plane_removes_the_cap(oracle):
+    """Cutting z > 3/2 off a sphere of radius 5/2 at the origin, seen from +z:
+    the front surface at distance rho from the axis has height
+    sqrt(r^2 - rho^2), so only the ring 4 <= rho^2 <= r^2 is drawn; the cap's
+    pixels show nothing (no interior), at the ring's depth profile."""
+    W, H, hh = 64, 64, 8.0
+    scale = Fraction(H, 2) / Fraction(8)
+    r = Fraction(5, 2)
+    cam = ortho(eye=(0.0, 0.0, 30.0), target=(0.0, 0.0, 0.0), half_h=hh)
+    sc = make_scene([(0.0, 0.0, 0.0)], [float(r)])
+    g = oracle.gbuffer(sc, cam, scenes.Options(clip_plane=(0.0, 0.0, -1.0, 1.5)), W, H)
+    inside, rho2 = _ortho_disk(W, H, scale, Fraction(0), Fraction(0), r)
+    ring = inside & np.vectorize(lambda v: v >= 4, otypes=[bool])(rho2)
+    edge = np.vectorize(lambda v: v == 4 or v == r * r, otypes=[bool])(rho2)
+    hit = g["id"] == 0
+    assert ring.sum() > 100 and (inside & ~ring).sum() > 100
+    assert np.array_equal(hit[~edge], ring[~edge])
+    for j, i in np.argwhere(ring & ~edge)[::9]:
+        h2 = r * r - rho2[j, i]
+        assert abs(g["z"][j, i] - (30.0 - math.sqrt(float(h2)))) <= 1e-12 * 30
+
+
+def test_clip_plane_uncovers_what_lies_behind(oracle):
+    """A nearer sphere lying wholly on the cut side vanishes and the farther
+    one it hid is drawn, exactly as when the nearer one is absent."""
+    W, H = 96, 96
+    cam = persp(eye=(0.0, 0.0, 30.0), target=(0.0, 0.0, 0.0))
+    both = make_scene([(0.0, 0.0, 5.0), (0.2, -0.1, 0.0)], [1.5, 2.0])
+    alone = make_scene([(0.0, 0.0, 5.0), (0.2, -0.1, 0.0)], [1.5, 2.0])
+    opts = scenes.Options(clip_plane=(0.0, 0.0, -1.0, 2.0))       # keeps z <= 2
+    g = oracle.gbuffer(both, cam, opts, W, H)
+    plain = oracle.gbuffer(alone, cam, scenes.Options(), W, H)
+    assert np.count_nonzero(plain["id"] == 0) > 50                  # the near sphere hides part of the far one
+    ref = oracle.gbuffer(make_scene([(0.2, -0.1, 0.0)], [2.0]), cam, scenes.Options(), W, H)
+    assert np.array_equal(np.where(g["id"] == 1, 0, g["id"]), ref["id"])
+    assert np.array_equal(g["z"], ref["z"])
