@@ -112,7 +112,19 @@ typedef struct vtx_options {
     float outline_depth;      /* relative depth step that makes an outline; 0: none (0) */
     float clip_plane[4];      /* world plane a, b, c, d; a x + b y + c z + d >= 0 is kept;
                                  all zero: no clipping (0, 0, 0, 0) */
+    int32_t supersample;      /* S = 1..4 samples per pixel side (0 or 1: none) */
 } vtx_options;
+
+/*
+ * options.supersample (paper, Methods, "High Quality Rendering": anti-aliasing
+ * is one of the deferred post-processes; the reading here is exact
+ * supersampling, so that the result stays defined pixel by pixel): the frame
+ * is rendered and shaded at (S W) x (S H) in library scratch, with every
+ * other option unchanged; output pixel (i, j) then takes, per RGBA channel,
+ * the mean of its S x S samples rounded half up (integer arithmetic), and
+ * the depth and id of the nearest (depth, id) among them.  Needs
+ * (S W) (S H) <= VTX_MAX_PIXELS.  vtx_gbuffer and vtx_shade refuse S > 1.
+ */
 
 /*
  * options.clip_plane (paper, Results, the whole-cell figure shown with and

@@ -42,6 +42,9 @@ notes:
   R8 clip       a world plane a x + b y + c z + d >= 0 keeps its side: a
                 primitive's hit on the cut side is dropped (the primitive
                 draws nothing at that pixel; interiors are not drawn).
+  R9 AA         exact supersampling: the frame rendered at S times the
+                size, each output channel the rounded-half-up mean of its
+                S x S samples, depth and id the nearest (z, id) among them.
 
 Because FP32 on the device and FP64 here can disagree where a result is
 decided by a near-tie, every pixel also carries an accept set: the ids that
@@ -626,6 +629,31 @@ def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=Non
         uns = uns + unsure.ravel().astype(uns.dtype)
     return dict(rgba=rgba.reshape(h, w), ao=ao.reshape(h, w),
                 ssao_unstable=uns.reshape(h, w), ssao_outside=outside.reshape(h, w))
+
+
+def supersample_reduce(res, S):
+    """R9 anti-aliasing by exact supersampling: an (S H) x (S W) render
+    ``res`` (full frame, from either oracle) reduced to H x W.  Each RGBA
+    channel is the mean of the pixel's S x S samples rounded half up
+    (integers); depth and id are the lexicographic minimum of (z, id); a
+    pixel is checkable when all its samples are strict and free of unstable
+    deferred-pass decisions."""
+    z, ids, rgba = res["z"], res["id"].astype(np.int64), res["rgba"].astype(np.int64)
+    HH, WW = z.shape
+    H, W = HH // S, WW // S
+    blk = lambda a: a.reshape(H, S, W, S).transpose(0, 2, 1, 3).reshape(H, W, S * S)
+    zb, ib = blk(z), blk(ids)
+    order = np.lexsort((ib, zb), axis=-1)[..., 0]
+    zmin = np.take_along_axis(zb, order[..., None], -1)[..., 0]
+    idmin = np.take_along_axis(ib, order[..., None], -1)[..., 0]
+    n = S * S
+    out = np.zeros((H, W), dtype=np.int64)
+    for ch in range(4):
+        total = blk((rgba >> (8 * ch)) & 255).sum(axis=-1)
+        out |= ((total + n // 2) // n) << (8 * ch)
+    strict = (((res["acc_n"] == 1) & ~res["acc_bg"] & ~res["unstable"]) | ((res["acc_n"] == 0) & res["acc_bg"]))
+    ok = strict & (res["ssao_unstable"] == 0) & (res["ssao_outside"] == 0)
+    return dict(z=zmin, id=idmin, rgba=out.astype(np.uint32), stable=blk(ok).all(axis=-1))
 
 
 def render(scene, cam, opts, W, H, window=None, halo=0, edge_px=1e-3, depth_rel=1e-5):

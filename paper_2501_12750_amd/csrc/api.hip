@@ -61,6 +61,11 @@ struct Bins {
     size_t list_alloc = 0;          // allocated bin entries (>= bb.capacity, the entries in use)
     size_t vc_cap = 0;
     uint32_t* vis_clusters = nullptr;   // resident scenes: the clusters that passed the frustum test
+    // supersampled renders: the full-size depth, id and colour images
+    float* ss_depth = nullptr;
+    uint32_t* ss_id = nullptr;
+    uint32_t* ss_rgba = nullptr;
+    size_t ss_cap = 0;
     Counters* host_ctr = nullptr;       // host view of the mapped counters
     uint64_t want_capacity = 0;
     uint64_t pending_capacity = 0;
@@ -150,6 +155,9 @@ void bins_free(Bins* b) {
     hipFree(b->bb.list);
     hipFree(b->bb.ctr);
     hipFree(b->vis_clusters);
+    hipFree(b->ss_depth);
+    hipFree(b->ss_id);
+    hipFree(b->ss_rgba);
     hipHostFree(b->host_ctr);
     delete b;
 }
@@ -375,8 +383,15 @@ bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1])
 int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H, int64_t n, int64_t m,
                Frame* F) {
     if (!cam) return fail(VTX_EINVAL, "camera is NULL");
+    if (o.supersample < 0 || o.supersample > 4) return fail(VTX_EINVAL, "supersample must be in 0..4");
     if (W < 1 || H < 1 || (int64_t)W * H > VTX_MAX_PIXELS)
         return fail(VTX_EINVAL, "image %dx%d outside 1..%d pixels", W, H, VTX_MAX_PIXELS);
+    // a supersampled frame is rendered at S times the size on each side
+    const int ss = o.supersample > 1 ? o.supersample : 1;
+    if ((int64_t)W * ss * H * ss > VTX_MAX_PIXELS)
+        return fail(VTX_EINVAL, "image %dx%d supersampled %d times exceeds %d pixels", W, H, ss, VTX_MAX_PIXELS);
+    W *= ss;
+    H *= ss;
     if (n < 0 || m < 0 || n + m >= (int64_t)0xFFFFFFFFll)
         return fail(VTX_EINVAL, "n_atoms=%lld n_bonds=%lld out of range", (long long)n, (long long)m);
     if (!finite3(cam->eye) || !finite3(cam->target) || !finite3(cam->up))
@@ -512,6 +527,7 @@ vtx_options resolve_options(const vtx_options* opt) {
     o.outline_color = 0u;
     o.outline_depth = 0.0f;
     for (float& v : o.clip_plane) v = 0.0f;
+    o.supersample = 1;
     return opt ? *opt : o;
 }
 
@@ -690,6 +706,7 @@ struct JobDesc {
     bool scene;
     uint64_t scene_uid;
     uint64_t tuned_capacity = 0;   // tile-list entries the tuner chose for this render's shape (0: none)
+    int ss = 1;                    // samples per pixel side: F is S times the outputs' size
     vtx::SceneDev S;
     float* depth;
     uint32_t* id;
@@ -794,6 +811,32 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
         J.normal = s.normal;
         J.albedo = s.albedo;
         J.ao = s.ao;
+        if (s.ss > 1) {
+            // rendered at full size into the slot's images, reduced afterwards
+            Bins* b = ws->slots[i];
+            const size_t px = (size_t)s.F.W * s.F.H;
+            if (px > b->ss_cap) {
+                if (capture) return fail(VTX_EINVAL, "job %zu: supersampling scratch not sized for capture", i);
+                VTX_HIP(hipStreamSynchronize(stream));   // in-flight frames may still use the old images
+                hipFree(b->ss_depth);
+                hipFree(b->ss_id);
+                hipFree(b->ss_rgba);
+                b->ss_depth = nullptr;
+                b->ss_id = nullptr;
+                b->ss_rgba = nullptr;
+                b->ss_cap = 0;
+                if (hipMalloc(&b->ss_depth, px * sizeof(float)) != hipSuccess ||
+                    hipMalloc(&b->ss_id, px * sizeof(uint32_t)) != hipSuccess ||
+                    hipMalloc(&b->ss_rgba, px * sizeof(uint32_t)) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return fail(VTX_ENOMEM, "cannot allocate %zu supersampled pixels", px);
+                }
+                b->ss_cap = px;
+            }
+            J.depth = b->ss_depth;
+            J.id = b->ss_id;
+            J.rgba = b->ss_rgba;
+        }
         starts[2 * (n + 1) + i] = g_shade;
         g_shade += vtx::shade_blocks(s.F);
         if (!bin) continue;
@@ -978,6 +1021,10 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
     if (shade) {
         if (n == 1) VTX_HIP(vtx::launch_shade(one(g_shade), g_shade, stream));
         else VTX_HIP(vtx::launch_shade(list_of(0, n, 2 * (n + 1)), g_shade, stream));
+        for (size_t i = 0; i < n; ++i)
+            if (d[i].ss > 1)
+                VTX_HIP(vtx::launch_downsample(jobs[i].depth, jobs[i].id, jobs[i].rgba, d[i].F.W / d[i].ss,
+                                               d[i].F.H / d[i].ss, d[i].ss, d[i].depth, d[i].id, d[i].rgba, stream));
     }
     if (marks) VTX_HIP(hipEventRecord(marks[6], stream));
     return VTX_OK;
@@ -994,6 +1041,7 @@ JobDesc plain_desc(const Frame& F, const vtx_options& o, const float* pos, const
     j.col = col;
     j.bonds = bonds;
     j.scene = false;
+    j.ss = o.supersample > 1 ? o.supersample : 1;
     return j;
 }
 
@@ -1010,6 +1058,7 @@ int vtx_gbuffer(const float* positions, const float* radii, const uint32_t* colo
     if (rc) return rc;
     if ((rc = check_inputs(positions, radii, colors, n_atoms, bonds, n_bonds, false))) return rc;
     if (!depth || !id) return fail(VTX_EINVAL, "depth/id outputs are NULL");
+    if (o.supersample > 1) return fail(VTX_EINVAL, "vtx_gbuffer does not supersample (use vtx_render)");
     std::vector<JobDesc> d{plain_desc(F, o, positions, radii, colors, bonds)};
     d[0].depth = depth;
     d[0].id = id;
@@ -1027,6 +1076,7 @@ int vtx_shade(const float* positions, const float* radii, const uint32_t* colors
     if (rc) return rc;
     if ((rc = check_inputs(positions, radii, colors, n_atoms, bonds, n_bonds, true))) return rc;
     if (!depth || !id || !rgba) return fail(VTX_EINVAL, "depth/id/rgba are NULL");
+    if (o.supersample > 1) return fail(VTX_EINVAL, "vtx_shade does not supersample (use vtx_render)");
     std::vector<JobDesc> d{plain_desc(F, o, positions, radii, colors, bonds)};
     d[0].depth = const_cast<float*>(depth);
     d[0].id = const_cast<uint32_t*>(id);

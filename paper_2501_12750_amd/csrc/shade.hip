@@ -219,7 +219,47 @@ __global__ void __launch_bounds__(kBlock) k_shade(JS js) {
     if (ao_out) ao_out[p] = ao;
 }
 
+// One output pixel per thread: its S x S samples are reduced to the rounded
+// mean of each RGBA channel and the nearest (depth, id).
+__global__ void __launch_bounds__(kBlock) k_downsample(const float* __restrict__ sdepth,
+                                                       const uint32_t* __restrict__ sid,
+                                                       const uint32_t* __restrict__ srgba, int W, int H, int S,
+                                                       float* __restrict__ depth, uint32_t* __restrict__ id,
+                                                       uint32_t* __restrict__ rgba) {
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (size_t)W * H) return;
+    const int x = (int)(p % (size_t)W), y = (int)(p / (size_t)W);
+    const size_t SW = (size_t)W * S;
+    unsigned long long best = ~0ull;
+    uint32_t sum[4] = {0u, 0u, 0u, 0u};
+    for (int sy = 0; sy < S; ++sy)
+        for (int sx = 0; sx < S; ++sx) {
+            const size_t q = ((size_t)y * S + sy) * SW + (size_t)x * S + sx;
+            const unsigned long long key = ((unsigned long long)__float_as_uint(sdepth[q]) << 32) | sid[q];
+            best = key < best ? key : best;
+            const uint32_t c = srgba[q];
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) sum[ch] += (c >> (8 * ch)) & 255u;
+        }
+    const uint32_t n = (uint32_t)(S * S);
+    uint32_t out = 0;
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) out |= ((sum[ch] + n / 2) / n) << (8 * ch);
+    rgba[p] = out;
+    depth[p] = __uint_as_float((uint32_t)(best >> 32));
+    id[p] = (uint32_t)(best & 0xFFFFFFFFull);
+}
+
 }  // namespace
+
+hipError_t launch_downsample(const float* sdepth, const uint32_t* sid, const uint32_t* srgba, int W, int H, int S,
+                             float* depth, uint32_t* id, uint32_t* rgba, hipStream_t stream) {
+    const size_t px = (size_t)W * H;
+    if (px == 0) return hipSuccess;
+    k_downsample<<<(unsigned)((px + kBlock - 1) / kBlock), kBlock, 0, stream>>>(sdepth, sid, srgba, W, H, S, depth,
+                                                                                 id, rgba);
+    return hipGetLastError();
+}
 
 template <class JS>
 hipError_t shade_impl(const JS& js, uint32_t grid, hipStream_t stream) {

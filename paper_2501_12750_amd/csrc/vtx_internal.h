@@ -371,6 +371,11 @@ hipError_t launch_resolve(const OneJob& js, int tile, uint32_t grid, bool count,
                           uint32_t* ovf_n, hipStream_t stream);
 hipError_t launch_resolve(const JobList& js, int tile, uint32_t grid, bool count, unsigned long long* ovf,
                           uint32_t* ovf_n, hipStream_t stream);
+// Supersampled render: output pixel (x, y) of W x H from its S x S samples
+// of the (S W) x (S H) images (channel means rounded half up, nearest
+// (depth, id)).
+hipError_t launch_downsample(const float* sdepth, const uint32_t* sid, const uint32_t* srgba, int W, int H, int S,
+                             float* depth, uint32_t* id, uint32_t* rgba, hipStream_t stream);
 hipError_t launch_shade(const OneJob& js, uint32_t grid, hipStream_t stream);
 hipError_t launch_shade(const JobList& js, uint32_t grid, hipStream_t stream);
 

@@ -87,6 +87,7 @@ class Options:
     outline_color: int = 0       # packed RGBA8
     outline_depth: float = 0.0   # relative depth step of an outline; 0: none
     clip_plane: tuple = (0.0, 0.0, 0.0, 0.0)   # a, b, c, d: a x + b y + c z + d >= 0 is kept
+    supersample: int = 1         # samples per pixel side (1..4)
 
     def __post_init__(self):
         self.bond_radius = f32(self.bond_radius)

@@ -58,7 +58,7 @@ class vtx_options(ctypes.Structure):
                 ("representation", ctypes.c_int32), ("probe_radius", ctypes.c_float),
                 ("shading", ctypes.c_int32), ("fog_color", ctypes.c_uint32), ("fog_start", ctypes.c_float),
                 ("fog_end", ctypes.c_float), ("outline_color", ctypes.c_uint32), ("outline_depth", ctypes.c_float),
-                ("clip_plane", ctypes.c_float * 4)]
+                ("clip_plane", ctypes.c_float * 4), ("supersample", ctypes.c_int32)]
 
 
 class vtx_stats(ctypes.Structure):
@@ -261,6 +261,7 @@ def options_struct(opts) -> vtx_options:
     o.outline_color = int(getattr(opts, "outline_color", 0)) & 0xFFFFFFFF
     o.outline_depth = float(getattr(opts, "outline_depth", 0.0))
     o.clip_plane[:] = [float(v) for v in getattr(opts, "clip_plane", (0.0, 0.0, 0.0, 0.0))]
+    o.supersample = int(getattr(opts, "supersample", 1))
     return o
 
 

@@ -710,3 +710,39 @@ def test_clip_plane_uncovers_what_lies_behind(oracle):
     ref = oracle.gbuffer(make_scene([(0.2, -0.1, 0.0)], [2.0]), cam, scenes.Options(), W, H)
     assert np.array_equal(np.where(g["id"] == 1, 0, g["id"]), ref["id"])
     assert np.array_equal(g["z"], ref["z"])
+
+
+# ---------------------------------------------------------------------------
+# anti-aliasing by exact supersampling
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("S", [2, 3])
+def test_supersampled_disk_edge_is_the_covered_fraction(oracle, S):
+    """Flat shading of an orthographic sphere on a background, supersampled S
+    times: each output channel is (k A + (S^2 - k) B) / S^2 rounded half up,
+    with k the number of the pixel's S x S sample centres inside the disk
+    (counted on the exact lattice); the output id is the sphere's wherever
+    k > 0, and its depth the nearest sample's."""
+    W, H, hh = 24, 20, 4.0
+    scale = Fraction(S * H, 2) / Fraction(4)                     # samples per angstrom
+    cx, cy, r = Fraction(3, 16), Fraction(-1, 8), Fraction(5, 2)
+    A = (200, 40, 120)
+    B = (10, 250, 30, 77)
+    cam = ortho(eye=(0.0, 0.0, 30.0), target=(0.0, 0.0, 0.0), half_h=hh)
+    sc = make_scene([(float(cx), float(cy), 0.0)], [float(r)], colors=[scenes.pack_rgba(*A)])
+    opts = scenes.Options(shading=2, background=scenes.pack_rgba(*B))
+    hi = oracle.render(sc, cam, opts, S * W, S * H)
+    red = ofull.supersample_reduce(hi, S)
+    inside, rho2 = _ortho_disk(S * W, S * H, scale, cx, cy, r)
+    on_edge = np.vectorize(lambda v: v == r * r, otypes=[bool])(rho2)
+    k = inside.reshape(H, S, W, S).sum(axis=(1, 3))
+    edge = on_edge.reshape(H, S, W, S).any(axis=(1, 3))
+    n = S * S
+    exp = np.zeros((H, W), dtype=np.int64)
+    for ch in range(4):
+        a = A[ch] if ch < 3 else 255
+        exp |= ((k * a + (n - k) * B[ch] + n // 2) // n) << (8 * ch)
+    assert ((k > 0) & (k < n)).sum() > 20
+    assert np.array_equal(red["rgba"].astype(np.int64)[~edge], exp[~edge])
+    assert np.array_equal((red["id"] == 0)[~edge], (k > 0)[~edge])
+    zs = hi["z"].reshape(H, S, W, S)
+    assert np.array_equal(red["z"], zs.min(axis=(1, 3)))
