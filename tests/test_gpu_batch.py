@@ -266,3 +266,38 @@ def test_batch_graph_replays_match_eager_renders(vtx, ctx):
     with pytest.raises(vtx.VtxError):
         vtx.vtx_batch_graph_create(ctx, [])
     rs.close()
+
+
+def test_batch_graph_with_post_passes_clip_and_supersampling(vtx, ctx):
+    """A captured batch whose jobs mix shading modes, fog, outline, a clip
+    plane and supersampling (its full-size scratch sized by the eager render
+    before capture) replays the eager batch's images, every replay."""
+    import dataclasses
+    import torch
+    scene0, frames, cams, opts, rs = trajectory_scene(vtx, ctx, 5000, 2)
+    c = np.zeros(3)
+    variants = [dataclasses.replace(opts, shading=3, outline_color=scenes.pack_rgba(0, 0, 0), outline_depth=0.05),
+                dataclasses.replace(opts, clip_plane=(1.0, 0.2, 0.0, 0.5)),
+                dataclasses.replace(opts, supersample=2, fog_color=scenes.pack_rgba(200, 200, 220), fog_start=120.0,
+                                    fog_end=170.0),
+                dataclasses.replace(opts, shading=2, supersample=3)]
+    specs = [(rs.handle, k % 2, cams[k % 4], variants[k], *VIEWPORTS_SMALL[k]) for k in range(4)]
+    ref = run_batch(vtx, ctx, specs)
+    # each job alone (single-render launches) draws the same image
+    for i, (h, f, cam, o, W, H) in enumerate(specs):
+        assert_identical(run_batch(vtx, ctx, [specs[i]])[0], ref[i], f"alone {i}")
+    imgs = [vtx.Frame(W, H) for (_, _, _, _, W, H) in specs]
+    jobs = [vtx.make_job(h, f, cam, o, W, H, fr.rgba, fr.depth, fr.id)
+            for (h, f, cam, o, W, H), fr in zip(specs, imgs)]
+    graph = vtx.vtx_batch_graph_create(ctx, jobs)
+    try:
+        for rep in range(3):
+            for fr in imgs:
+                fr.rgba.zero_()
+                fr.id.zero_()
+            vtx.vtx_batch_graph_launch(graph)
+            torch.cuda.synchronize()
+            for i, fr in enumerate(imgs):
+                assert_identical(fr.numpy(), ref[i], f"replay {rep} job {i}")
+    finally:
+        vtx.vtx_batch_graph_destroy(graph)
