@@ -29,8 +29,7 @@ constexpr int kBuckets = 32;      // depth buckets of the front-to-back record o
 constexpr int kSortArea = 64;     // order a chunk when its kept records average more pixels than this
 constexpr int kKeptShift = 21;    // packed scan: footprint area (<= 256 * 64 * 64) below, kept count above
 constexpr uint32_t kAreaMask = (1u << kKeptShift) - 1u;
-constexpr int kMaxSub = 32;       // records per depth-ordered sub-chunk: 16 or 32
-static_assert((kBlock / 64) * (kMaxSub + 1) <= kChunk + 1, "sub-chunk prefixes fit in the chunk prefix");
+constexpr int kLaterSub = 32;     // records per depth-ordered sub-chunk after the first (16, 32 or 64)
 static_assert(kBlock == kChunk, "one 64-slot window per wave in the order array");
 template <int TS>
 struct HzGrid {
@@ -403,14 +402,17 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
         // footprints in its own slots; the workgroup resolves their
         // fragments, then refreshes the blocks under them before the next
         // sub-chunk is culled.
-        auto resolve_sorted = [&](uint32_t nk, int sub, bool more) {
-            const uint32_t nsub = (nk + (uint32_t)sub - 1) / (uint32_t)sub;
-            const int lg = sub == 16 ? 2 : 1;   // log2 of the lanes per record
-            // the chunk's prefix is no longer needed: each wave keeps its
-            // sub-chunk prefix in a slice of it
-            uint32_t* const wp = pref + wave * (kMaxSub + 1);
-            for (uint32_t sc = 0; sc < nsub; ++sc) {
-                const uint32_t rbase = sc * (uint32_t)sub;
+        auto resolve_sorted = [&](uint32_t nk, int sub0, bool more) {
+            // All waves compute the same prefix (from the same block depths),
+            // so they share one array, the chunk's prefix, which is no longer
+            // needed: every wave writes it whole before reading it.
+            uint32_t* const wp = pref;
+            uint32_t rbase = 0;
+            for (uint32_t sc = 0; rbase < nk; ++sc) {
+                // the front sub-chunk is small; records after it are mostly
+                // culled whole, so later sub-chunks are larger (fewer passes)
+                const int sub = sc == 0 ? sub0 : kLaterSub;
+                const int lg = sub == 16 ? 2 : sub == 32 ? 1 : 0;   // log2 of the lanes per record
                 const uint32_t i = (uint32_t)lane >> lg;
                 const bool real = rbase + i < nk;
                 uint32_t rect = 0;
@@ -429,7 +431,7 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
                 if (real && sc > 0)
                     for (int by = by0 + (lane & ((1 << lg) - 1)); by <= by1; by += 1 << lg)
                         for (int bx = bx0; bx <= bx1; ++bx) m = max(m, hz[by * (TS / 4) + bx]);
-                m = max(m, (uint32_t)__shfl_xor((int)m, 1));
+                if (lg >= 1) m = max(m, (uint32_t)__shfl_xor((int)m, 1));
                 if (lg == 2) m = max(m, (uint32_t)__shfl_xor((int)m, 2));
                 const bool live = real && !(sc > 0 && __float_as_uint(zcull) > m && zcull > 0.0f);
                 // blocks under the live records (their union rectangle)
@@ -458,7 +460,8 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
                     const uint32_t dx = local - __umul24(dy, rw);
                     test_pixel(rr, (int)(rr.rect & 0xFF) + (int)dx, (int)((rr.rect >> 8) & 0xFF) + (int)dy);
                 }
-                if (sc + 1 == nsub && !more) break;
+                rbase += (uint32_t)sub;
+                if (rbase >= nk && !more) break;
                 __syncthreads();   // the sub-chunk's hits are in the depth buffer
                 if (ux1 > 0) {
                     const int cx0 = 255 - (int)ux0, cy0 = 255 - (int)uy0;
