@@ -477,6 +477,7 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
                 __syncthreads();   // refreshed block depths are in LDS
             }
         };
+        bool hz_set = false;   // the block depths hold a refresh (uniform)
         for (uint64_t base = 0; base < nsrc; base += kChunk) {
             PrimRec pr;
             bool have;
@@ -494,7 +495,8 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
             float zc = INFINITY;
             if (have) {
                 const Rec rc = make_rec(F, pr);
-                keep = stats || !hz_culled(rc);
+                // until a refresh has stored depths every block is +inf: nothing to test
+                keep = stats || !hz_set || !hz_culled(rc);
                 if (keep) {
                     area = rect_area(rc.rect);
                     zc = rc.zcull;
@@ -517,7 +519,10 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
             const bool sorted = !stats && nk > (uint32_t)sub && atot > (uint32_t)kSortArea * nk;
             if (!sorted) {
                 resolve_fragments();
-                if (!stats && more) hz_refresh();
+                if (!stats && more) {
+                    hz_refresh();
+                    hz_set = true;
+                }
                 continue;
             }
             // depth range of the kept records
@@ -552,6 +557,7 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
             if (keep) ord[bbase[bk] + atomicAdd(&bcnt[bk], 1u)] = (uint8_t)tid;
             __syncthreads();   // the order is in LDS
             resolve_sorted(nk, sub, more);
+            hz_set = true;
             __syncthreads();   // every wave is done with this chunk's records
             if (tid < kChunk / 4) reinterpret_cast<uint32_t*>(ord)[tid] = 0u;
         }
