@@ -147,6 +147,7 @@ void bins_free(Bins* b) {
     hipFree(b->bb.tile_cnt);
     hipFree(b->bb.tile_off);
     hipFree(b->bb.tile_fill);
+    hipFree(b->bb.layer_off);
     hipFree(b->bb.vis_src);
     hipFree(b->bb.vis_rect);
     hipFree(b->bb.vis_cnt);
@@ -296,17 +297,18 @@ int ensure_bins(Workspace* ws, Bins* b, int T, uint64_t nprim, uint32_t groups, 
     int rc;
     hipStream_t st = ws->stream;
     if ((size_t)T > b->tiles_cap || !b->bb.tile_cnt) {
-        size_t c1 = b->tiles_cap, c2 = b->tiles_cap, c3 = b->tiles_cap;
+        size_t c1 = b->tiles_cap, c2 = b->tiles_cap, c3 = b->tiles_cap * vtx::kLayers, c4 = c3;
         if ((rc = grow(&b->bb.tile_cnt, c1, (size_t)T, st, "tile counts"))) return rc;
         if ((rc = grow(&b->bb.tile_off, c2, (size_t)T, st, "tile offsets"))) return rc;
-        if ((rc = grow(&b->bb.tile_fill, c3, (size_t)T, st, "tile cursors"))) return rc;
+        if ((rc = grow(&b->bb.tile_fill, c3, (size_t)T * vtx::kLayers, st, "tile cursors"))) return rc;
+        if ((rc = grow(&b->bb.layer_off, c4, (size_t)T * vtx::kLayers, st, "tile layer starts"))) return rc;
         b->tiles_cap = (size_t)T;
         b->dirty = true;
     }
     if (b->dirty) {
         // fresh or abandoned scratch: zero what every frame otherwise leaves zeroed
         VTX_HIP(vtx::launch_zero(b->bb.tile_cnt, b->tiles_cap, st));
-        VTX_HIP(vtx::launch_zero(b->bb.tile_fill, b->tiles_cap, st));
+        VTX_HIP(vtx::launch_zero(b->bb.tile_fill, b->tiles_cap * vtx::kLayers, st));
         VTX_HIP(vtx::launch_zero(reinterpret_cast<uint32_t*>(b->bb.ctr), sizeof(Counters) / sizeof(uint32_t), st));
         b->dirty = false;
     }
@@ -331,8 +333,8 @@ int ensure_bins(Workspace* ws, Bins* b, int T, uint64_t nprim, uint32_t groups, 
         if ((rc = grow(&b->bb.hist, c1, nh, st, "tile histograms"))) return rc;
         b->hist_cap = nh;
     }
-    if (nc && ((size_t)nc > b->vc_cap || !b->vis_clusters)) {
-        if ((rc = grow(&b->vis_clusters, b->vc_cap, (size_t)nc, st, "visible clusters"))) return rc;
+    if (nc && ((size_t)nc * vtx::kDepthBuckets > b->vc_cap || !b->vis_clusters)) {
+        if ((rc = grow(&b->vis_clusters, b->vc_cap, (size_t)nc * vtx::kDepthBuckets, st, "visible clusters"))) return rc;
     }
     uint64_t want = ws->fixed_capacity ? ws->fixed_entries : b->want_capacity;
     if (want == 0) {
@@ -855,7 +857,7 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
         Bins* b = ws->slots[i];
         if (capture && (b->dirty || !b->was_sized(nprim, s.F.W, s.F.H) || (size_t)T > b->tiles_cap ||
                         (size_t)groups * chunk > b->vis_cap || (size_t)groups * T > b->hist_cap ||
-                        (nc && (size_t)nc > b->vc_cap)))
+                        (nc && (size_t)nc * vtx::kDepthBuckets > b->vc_cap)))
             return fail(VTX_EINVAL, "job %zu: scratch not sized for capture", i);
         if (!ws->fixed_capacity && !b->was_sized(nprim, s.F.W, s.F.H)) {
             // a shape the tuner sized, or a scene and image size counted
@@ -874,9 +876,12 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
         b->pending_h = s.F.H;
         b->dirty = true;   // until the resolve that re-zeroes the tile counts is queued
         J.bb = b->bb;
+        J.bb.layers = 1;
         if (s.scene) {
             J.S = s.S;
             J.S.vis_clusters = b->vis_clusters;
+            // binning workgroups run front to back: keep that order in the lists
+            J.bb.layers = std::min<uint32_t>(vtx::kLayers, groups);
         }
         starts[i] = g_cull;
         starts[(n + 1) + i] = g_bin;
@@ -989,6 +994,10 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
             if (n > 1 && (rc = upload_tables(ws, jobs, d, starts, &k_off, &s_off))) return rc;
         }
         if (marks) VTX_HIP(hipEventRecord(marks[2], stream));
+        if (scene) {
+            if (n == 1) VTX_HIP(vtx::launch_layers(one(g_bin), g_bin, stream));
+            else VTX_HIP(vtx::launch_layers(list_of(0, n, n + 1), g_bin, stream));
+        }
         if (marks) VTX_HIP(hipEventRecord(marks[3], stream));
         if (n == 1) VTX_HIP(vtx::launch_scatter(one(g_bin), g_bin, max_tiles, stream));
         else VTX_HIP(vtx::launch_scatter(list_of(0, n, n + 1), g_bin, max_tiles, stream));
@@ -1141,9 +1150,11 @@ size_t vtx_frame_scratch_bytes(int32_t W, int32_t H, int64_t n_atoms, int64_t n_
     vtx::bin_grid(nprim, &groups, &chunk);
     uint64_t cap = nprim / 2;
     if (cap < kMinCapacity) cap = kMinCapacity;
-    return (size_t)(T * 16 + (uint64_t)groups * chunk * (sizeof(uint32_t) + sizeof(uint2)) +
-                    (uint64_t)groups * T * 4 + cap * sizeof(uint2) + scene_clusters(n_atoms, n_bonds) * 4 +
-                    sizeof(Counters) + 4096);
+    // tile counts and offsets, per-layer cursors and starts, visible lists,
+    // histograms, lists, visible clusters per depth class, counters
+    return (size_t)(T * 16 + T * 8 * vtx::kLayers + (uint64_t)groups * chunk * (sizeof(uint32_t) + sizeof(uint2)) +
+                    (uint64_t)groups * T * 4 + cap * sizeof(uint2) +
+                    scene_clusters(n_atoms, n_bonds) * 4 * vtx::kDepthBuckets + sizeof(Counters) + 4096);
 }
 
 int vtx_scene_create(vtx_context* ctx, const float* positions, const float* radii, const uint32_t* colors,

@@ -60,28 +60,9 @@ struct PlainSource {     // the caller's arrays, primitives in their given order
     __device__ Item fetch(uint64_t k) const { return fetch_plain(pos, rad, bonds, n_atoms, first + k); }
 };
 
-struct SceneSource {     // a resident scene: the clusters that passed the frustum test
+struct SceneSource {     // a resident scene: the clusters that passed the frustum test, by depth class
     SceneDev S;
-    const Counters* ctr;
     uint32_t groups;
-    uint32_t c0, c1;
-    __device__ void begin(uint32_t b) {
-        const uint32_t nvc = ctr->vis_clusters;
-        const uint32_t cpw = (nvc + groups - 1) / groups;
-        c0 = min(nvc, b * cpw);
-        c1 = min(nvc, c0 + cpw);
-    }
-    __device__ uint64_t items() const { return (uint64_t)(c1 - c0) * kCluster; }
-    __device__ Item fetch(uint64_t k) const {
-        const uint32_t c = S.vis_clusters[c0 + (uint32_t)(k / kCluster)];
-        const uint32_t slot = (uint32_t)(k % kCluster);
-        if (c < S.atom_clusters) {
-            const uint32_t i = c * kCluster + slot;
-            return i < S.n_atoms ? fetch_scene(S, i) : empty_item();
-        }
-        const uint32_t j = (c - S.atom_clusters) * kCluster + slot;
-        return j < S.n_bonds ? fetch_scene(S, S.n_atoms + j) : empty_item();
-    }
 };
 
 template <bool kScene>
@@ -104,7 +85,6 @@ struct SourceOf<true> {
     __device__ static SceneSource make(const Job& J) {
         SceneSource s;
         s.S = J.S;
-        s.ctr = J.bb.ctr;
         s.groups = J.bb.groups;
         return s;
     }
@@ -131,6 +111,7 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
     extern __shared__ uint32_t hist[];
     __shared__ uint32_t local_n, bx0, by0, bx1, by1;
     __shared__ unsigned long long local_pairs;
+    __shared__ uint32_t cls_end[kDepthBuckets];
     uint32_t blk;
     const int ji = js.find(blockIdx.x, blk);
     if (ji < 0) return;
@@ -148,6 +129,18 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
     const int T = F.tiles_x * F.tiles_y;
     const int tid = threadIdx.x;
     for (int t = tid; t < T; t += kBinThreads) hist[t] = 0;
+    if constexpr (kScene) {
+        // end of each depth class in the front-to-back order of the visible clusters
+        if (tid < 64) {
+            uint32_t v = tid < kDepthBuckets ? ctr->vis_bucket[tid] : 0u;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t u = __shfl_up(v, o);
+                if (tid >= o) v += u;
+            }
+            if (tid < kDepthBuckets) cls_end[tid] = v;
+        }
+    }
     if (tid == 0) {
         local_n = 0;
         local_pairs = 0;
@@ -161,7 +154,7 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
 
     const uint64_t start = (uint64_t)blk * chunk;
     auto src = src0;
-    src.begin(blk);
+    if constexpr (!kScene) src.begin(blk);
     const int tsh = F.tile_shift;
     uint32_t bad_count = 0;
     uint32_t* __restrict__ const my_src = vis_src + start;   // this workgroup's visible list
@@ -205,14 +198,25 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
         // one kind, so the kind is the same across the wave).  An atom
         // cluster's four 64-atom quarters are loaded together and take the
         // sphere-only path.
+        // Workgroup b takes positions [c0, c1) of the visible clusters in
+        // depth-class order, so the workgroups run front to back.
         const SceneDev& S = src.S;
+        const uint32_t stride = S.atom_clusters + S.bond_clusters;
+        const uint32_t nvc = cls_end[kDepthBuckets - 1];
+        const uint32_t cpw = (nvc + src.groups - 1) / src.groups;
+        const uint32_t c0 = min(nvc, blk * cpw), c1 = min(nvc, c0 + cpw);
+        int cls = 0;   // class of the positions this wave reads next (they increase)
+        auto cluster_at = [&](uint32_t q) -> uint32_t {
+            while (cls_end[cls] <= q) ++cls;
+            return S.vis_clusters[(size_t)cls * stride + (q - (cls ? cls_end[cls - 1] : 0u))];
+        };
         const uint32_t nw = kBinThreads / 64;
         const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(tid >> 6);
         const uint32_t lane = __lane_id();
-        uint32_t cn = src.c0 + wave < src.c1 ? S.vis_clusters[src.c0 + wave] : 0u;
-        for (uint32_t ci = src.c0 + wave; ci < src.c1; ci += nw) {
+        uint32_t cn = c0 + wave < c1 ? cluster_at(c0 + wave) : 0u;
+        for (uint32_t ci = c0 + wave; ci < c1; ci += nw) {
             const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int)cn);
-            if (ci + nw < src.c1) cn = S.vis_clusters[ci + nw];   // the next cluster's id, ahead of its use
+            if (ci + nw < c1) cn = cluster_at(ci + nw);   // the next cluster's id, ahead of its use
             if (c < S.atom_clusters) {
                 float4 a[4];
 #pragma unroll
@@ -273,6 +277,46 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
     }
 }
 
+// Layer starts of the tile lists (jobs with layers > 1).  For tile t,
+// layer_off[g][t] is the number of t's entries that the workgroups of layers
+// before g contribute: the exclusive prefix over g of the histogram rows
+// summed per layer.  With P the power of two >= layers, work block b takes
+// the (1024 / P)-tile blocks b, b + groups, ...; thread (g, i) = (tid / W,
+// tid % W) sums layer g's rows at tile i (loads coalesced along i), and the
+// prefix over g goes through LDS.
+template <class JS>
+__global__ void __launch_bounds__(kBinThreads) k_layers(JS js) {
+    static_assert(kBinThreads == 1024 && kLayers <= 32, "tile blocks of 1024 / P tiles, P <= 32");
+    __shared__ uint32_t part[kBinThreads + kLayers];
+    uint32_t blk;
+    const int ji = js.find(blockIdx.x, blk);
+    if (ji < 0) return;
+    const Job& J = js.job(ji);
+    const uint32_t L = J.bb.layers, groups = J.bb.groups;
+    if (L <= 1) return;
+    const uint32_t T = (uint32_t)(J.F.tiles_x * J.F.tiles_y);
+    const uint32_t* __restrict__ const hist = J.bb.hist;
+    uint32_t* __restrict__ const loff = J.bb.layer_off;
+    const uint32_t lsh = 32u - (uint32_t)__builtin_clz(L - 1u);   // P = 1 << lsh >= L (L <= kLayers)
+    const uint32_t wsh = 10u - lsh, W = 1u << wsh;                  // tiles per block: kBinThreads / P
+    const uint32_t g = threadIdx.x >> wsh, i = threadIdx.x & (W - 1u);
+    const uint32_t b0 = g < L ? layer_first(g, groups, L) : 0u, b1 = g < L ? layer_first(g + 1, groups, L) : 0u;
+    for (uint32_t tb = blk; tb * W < T; tb += groups) {   // trip count uniform over the workgroup
+        const uint32_t t = tb * W + i;
+        uint32_t sum = 0;
+        if (t < T) {
+#pragma unroll 8
+            for (uint32_t b = b0; b < b1; ++b) sum += hist[(size_t)b * T + t];
+        }
+        part[g * (W + 1u) + i] = sum;
+        __syncthreads();
+        uint32_t pre = 0;
+        for (uint32_t h = 0; h < g; ++h) pre += part[h * (W + 1u) + i];
+        if (t < T && g < L) loff[(size_t)g * T + t] = pre;
+        __syncthreads();   // part is rewritten by the next tile block
+    }
+}
+
 constexpr uint32_t kNoRun = 0xFFFFFFFFu;
 
 // Scatter.  Every workgroup first rebuilds the exclusive prefix sum of the
@@ -299,12 +343,15 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js) {
     const uint32_t* __restrict__ const hist_in = J.bb.hist;
     const uint32_t* __restrict__ const cnt = J.bb.tile_cnt;
     uint64_t* __restrict__ const off = J.bb.tile_off;
-    uint32_t* const fill = J.bb.tile_fill;
     uint2* __restrict__ const list = J.bb.list;
     const uint64_t capacity = J.bb.capacity;
     Counters* const ctr = J.bb.ctr;
     Counters* const host_ctr = J.bb.host_ctr;
     const int T = F.tiles_x * F.tiles_y;
+    // this workgroup's layer: its runs go after those of the layers before it
+    const uint32_t lay = J.bb.layers > 1 ? layer_of(blk, J.bb.groups, J.bb.layers) : 0u;
+    uint32_t* const fill = J.bb.tile_fill + (size_t)lay * T;
+    const uint32_t* __restrict__ const loff = J.bb.layers > 1 ? J.bb.layer_off + (size_t)lay * T : nullptr;
     const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
     const bool lead = blk == 0;
     const int per = (T + kBinThreads - 1) / kBinThreads;
@@ -333,7 +380,7 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js) {
         const bool fits = run + c <= capacity;      // else the resolve rebuilds this tile from the visible lists
         const uint32_t h = row[t];
         uint32_t r = kNoRun;
-        if (h && fits) r = (uint32_t)(run + atomicAdd(&fill[t], h));
+        if (h && fits) r = (uint32_t)(run + (loff ? loff[t] : 0u) + atomicAdd(&fill[t], h));
         cur[t] = r;
         if (lead) off[t] = run;
         over += fits ? 0u : 1u;
@@ -354,7 +401,7 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js) {
             ctr->frag_hit_bond = 0;
             ctr->done_blocks = 0;
             ctr->pairs_counted = 0;
-            ctr->vis_clusters = 0;         // the next frame's cluster test adds to this
+            for (int k = 0; k < kDepthBuckets; ++k) ctr->vis_bucket[k] = 0;   // the next frame's cluster test adds to these
             if (host_ctr) {
                 host_ctr->vis_count = vis;
                 host_ctr->bad_bonds = bad;
@@ -477,6 +524,14 @@ hipError_t launch_count(const OneJob& js, bool scene, uint32_t grid, int max_til
 }
 hipError_t launch_count(const JobList& js, bool scene, uint32_t grid, int max_tiles, hipStream_t stream) {
     return count_impl(js, scene, grid, max_tiles, stream);
+}
+hipError_t launch_layers(const OneJob& js, uint32_t grid, hipStream_t stream) {
+    k_layers<<<grid, kBinThreads, 0, stream>>>(js);
+    return hipGetLastError();
+}
+hipError_t launch_layers(const JobList& js, uint32_t grid, hipStream_t stream) {
+    k_layers<<<grid, kBinThreads, 0, stream>>>(js);
+    return hipGetLastError();
 }
 hipError_t launch_scatter(const OneJob& js, uint32_t grid, int max_tiles, hipStream_t stream) {
     return scatter_impl(js, grid, max_tiles, stream);

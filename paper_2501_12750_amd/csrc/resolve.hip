@@ -216,10 +216,8 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
         __syncthreads();
         // every wave has read the tile's count (it sets the trip count of the
         // barrier loop below): re-arm it for the next frame's count kernel
-        if (tid == 0) {
-            cnt[t] = 0;
-            fill[t] = 0;
-        }
+        if (tid == 0) cnt[t] = 0;
+        if ((uint32_t)tid < J.bb.layers) fill[(size_t)tid * F.tiles_x * F.tiles_y + t] = 0;
 
         // one (record, pixel) ray test folded into the tile's LDS depth buffer
         auto test_pixel = [&](const Rec& rc, int lx, int ly) {

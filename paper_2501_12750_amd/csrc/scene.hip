@@ -169,9 +169,14 @@ __global__ void __launch_bounds__(kBlock) k_cluster_boxes(SceneDev S, float4* bo
 }
 
 // Per frame: clusters whose bounding sphere meets the view volume, appended
-// to S.vis_clusters (one atomic per wave).
+// to the region of S.vis_clusters of their depth class: the front depth of
+// the bounding sphere on a log scale from znear to zfar, kDepthBuckets
+// classes.  A workgroup's clusters of one class (neighbours in Morton order)
+// take one contiguous run of that class, so a range of the class stays
+// compact in space.
 template <class JS>
 __global__ void __launch_bounds__(kBlock) k_cluster_cull(JS js) {
+    __shared__ uint32_t wcnt[kDepthBuckets], wbase[kDepthBuckets];
     uint32_t blk;
     const int ji = js.find(blockIdx.x, blk);
     if (ji < 0) return;
@@ -179,35 +184,53 @@ __global__ void __launch_bounds__(kBlock) k_cluster_cull(JS js) {
     const Frame F = J.F;
     const SceneDev S = J.S;
     Counters* const ctr = J.bb.ctr;
+    const uint32_t stride = S.atom_clusters + S.bond_clusters;   // entries of one depth class
     const uint32_t nc = S.atom_clusters + (F.n_bonds ? S.bond_clusters : 0u);
-    {
-        const uint32_t c = blk * kBlock + threadIdx.x;
-        bool vis = false;
-        if (c < nc) {
-            const float4 lo = S.cluster_box[2 * (size_t)c], hi = S.cluster_box[2 * (size_t)c + 1];
-            if (lo.x <= hi.x) {   // empty clusters have an inverted box
-                // atom boxes hold the given radii: the representation may draw
-                // larger spheres (sticks, solvent-accessible surface)
-                const float pad = c < S.atom_clusters ? (F.rep == 2 ? F.bond_radius : F.rep == 3 ? F.probe : 0.0f)
-                                                      : F.bond_radius;
-                const double hx = 0.5 * ((double)hi.x - lo.x), hy = 0.5 * ((double)hi.y - lo.y),
-                             hz = 0.5 * ((double)hi.z - lo.z);
-                double vx, vy, vz;
-                to_view(F, (float)(lo.x + hx), (float)(lo.y + hy), (float)(lo.z + hz), vx, vy, vz);
-                // the centre was rounded to FP32: widen by its rounding error
-                const double r = sqrt(hx * hx + hy * hy + hz * hz) + pad +
-                                 1e-6 * (fabs((double)lo.x) + fabs((double)lo.y) + fabs((double)lo.z) + 1.0);
-                vis = sphere_in_frustum(F, vx, vy, vz, r);
+    const uint32_t c = blk * kBlock + threadIdx.x;
+    if (threadIdx.x < kDepthBuckets) wcnt[threadIdx.x] = 0;
+    __syncthreads();
+    int cls = -1;
+    if (c < nc) {
+        const float4 lo = S.cluster_box[2 * (size_t)c], hi = S.cluster_box[2 * (size_t)c + 1];
+        if (lo.x <= hi.x) {   // empty clusters have an inverted box
+            // atom boxes hold the given radii: the representation may draw
+            // larger spheres (sticks, solvent-accessible surface)
+            const float pad = c < S.atom_clusters ? (F.rep == 2 ? F.bond_radius : F.rep == 3 ? F.probe : 0.0f)
+                                                  : F.bond_radius;
+            const double hx = 0.5 * ((double)hi.x - lo.x), hy = 0.5 * ((double)hi.y - lo.y),
+                         hz = 0.5 * ((double)hi.z - lo.z);
+            double vx, vy, vz;
+            to_view(F, (float)(lo.x + hx), (float)(lo.y + hy), (float)(lo.z + hz), vx, vy, vz);
+            // the centre was rounded to FP32: widen by its rounding error
+            const double r = sqrt(hx * hx + hy * hy + hz * hz) + pad +
+                             1e-6 * (fabs((double)lo.x) + fabs((double)lo.y) + fabs((double)lo.z) + 1.0);
+            if (sphere_in_frustum(F, vx, vy, vz, r)) {
+                // only the order of the lists depends on the class, never the image
+                const float zf = fmaxf((float)(vz - r), F.znear);
+                const float q = __log2f(zf / F.znear) * ((float)kDepthBuckets / __log2f(F.zfar / F.znear));
+                cls = q >= 0.0f ? (int)fminf(q, (float)(kDepthBuckets - 1)) : 0;   // NaN: class 0
             }
         }
-        const unsigned long long vmask = __ballot(vis);
-        if (!vmask) return;
-        const int leader = __ffsll((long long)vmask) - 1;
-        uint32_t slot = 0;
-        if ((int)__lane_id() == leader) slot = atomicAdd(&ctr->vis_clusters, (uint32_t)__popcll(vmask));
-        slot = __shfl(slot, leader);
-        if (vis) S.vis_clusters[slot + (uint32_t)__popcll(vmask & __lanemask_lt())] = c;
     }
+    // place within the workgroup's run of the class (lanes sharing a class
+    // take one LDS atomic), then one global atomic per class
+    uint32_t off = 0;
+    unsigned long long pend = __ballot(cls >= 0);
+    while (pend) {
+        const int leader = __ffsll((long long)pend) - 1;
+        const int cl = __shfl(cls, leader);
+        const unsigned long long grp = __ballot(cls == cl) & pend;
+        uint32_t base = 0;
+        if ((int)__lane_id() == leader) base = atomicAdd(&wcnt[cl], (uint32_t)__popcll(grp));
+        base = __shfl(base, leader);
+        if ((grp >> __lane_id()) & 1ull) off = base + (uint32_t)__popcll(grp & __lanemask_lt());
+        pend &= ~grp;
+    }
+    __syncthreads();
+    if (threadIdx.x < kDepthBuckets && wcnt[threadIdx.x])
+        wbase[threadIdx.x] = atomicAdd(&ctr->vis_bucket[threadIdx.x], wcnt[threadIdx.x]);
+    __syncthreads();
+    if (cls >= 0) S.vis_clusters[(size_t)cls * stride + wbase[cls] + off] = c;
 }
 
 inline unsigned grid_for(uint64_t n) {

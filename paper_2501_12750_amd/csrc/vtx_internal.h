@@ -18,6 +18,12 @@ constexpr int kMaxLdsTiles = 15360;          // tile histogram of one binning wo
 constexpr uint32_t kMaxBinGroups = 512;
 constexpr uint32_t kBackground = 0xFFFFFFFFu;
 constexpr int kMaxSamples = 64;
+// Resident scenes bin their visible clusters front to back: the frustum test
+// files each cluster under one of kDepthBuckets depth classes (log spacing
+// from znear to zfar), and the tile lists keep the order of kLayers
+// consecutive ranges of binning workgroups.
+constexpr int kDepthBuckets = 32;
+constexpr int kLayers = 32;
 
 // Per-frame constants, passed by value to every kernel.
 struct Frame {
@@ -73,7 +79,7 @@ struct Counters {
     unsigned long long frag_hit;
     unsigned long long frag_hit_bond;
     unsigned int done_blocks;
-    unsigned int vis_clusters;          // resident scenes: clusters that passed the frustum test
+    unsigned int vis_bucket[kDepthBuckets];   // resident scenes: clusters that passed the frustum test, per depth class
     unsigned long long pairs_counted;   // total of the tile counts, added by the count kernel
 };
 
@@ -229,6 +235,15 @@ __device__ inline int xcd_contiguous(int b, int nblocks) {
 
 inline int xcd_grid(int nblocks) { return ((nblocks + 7) >> 3) << 3; }
 
+// Binning workgroup b of `groups` belongs to layer b * layers / groups; layer
+// g holds the workgroups [layer_first(g), layer_first(g + 1)).
+__device__ inline uint32_t layer_of(uint32_t b, uint32_t groups, uint32_t layers) {
+    return (uint32_t)(((uint64_t)b * layers) / groups);
+}
+__device__ inline uint32_t layer_first(uint32_t g, uint32_t groups, uint32_t layers) {
+    return (uint32_t)(((uint64_t)g * groups + layers - 1) / layers);
+}
+
 // ---------------------------------------------------------------------------
 // host launch wrappers (one per kernel file)
 // ---------------------------------------------------------------------------
@@ -237,7 +252,8 @@ inline int xcd_grid(int nblocks) { return ((nblocks + 7) >> 3) << 3; }
 struct BinBuffers {
     uint32_t* tile_cnt;     // T
     uint64_t* tile_off;     // T
-    uint32_t* tile_fill;    // T
+    uint32_t* tile_fill;    // layers * T: next free entry of each layer's run of each tile list
+    uint32_t* layer_off;    // layers * T: start of each layer's run within each tile list
     uint32_t* vis_src;      // groups * chunk: source index of each visible primitive
     uint2* vis_rect;        // groups * chunk, pixel rectangle packed (x0 | y0 << 16, x1 | y1 << 16)
     uint32_t* vis_cnt;      // groups: visible primitives of each workgroup
@@ -247,6 +263,7 @@ struct BinBuffers {
     uint2* list;            // capacity entries (source index, tile-local footprint), each tile's contiguous
     uint64_t capacity;
     uint32_t groups, chunk;
+    uint32_t layers;        // 1, or kLayers for a resident scene (workgroup ranges of increasing depth)
     Counters* ctr;
     Counters* host_ctr;     // device address of host-mapped counters (may be null)
 };
@@ -266,7 +283,8 @@ struct SceneDev {
     const uint32_t* atom_id;            // n_atoms: original index of each stored atom
     const uint4* bond_rec;              // n_bonds: (stored index a, stored index b, original bond index, 0)
     const float4* cluster_box;          // 2 per cluster: (min xyz, -), (max xyz, -); bond boxes exclude the radius
-    uint32_t* vis_clusters;             // atom_clusters + bond_clusters: visible cluster ids (per render)
+    uint32_t* vis_clusters;             // kDepthBuckets regions of atom_clusters + bond_clusters entries:
+                                        // visible cluster ids per depth class (per render)
 };
 size_t scene_build_temp_bytes(uint64_t n, uint64_t m);
 hipError_t scene_build(const float* pos, const float* rad, const uint32_t* bonds, uint64_t n, uint64_t m,
@@ -362,6 +380,10 @@ hipError_t launch_cluster_cull(const OneJob& js, uint32_t grid, hipStream_t stre
 hipError_t launch_cluster_cull(const JobList& js, uint32_t grid, hipStream_t stream);
 hipError_t launch_count(const OneJob& js, bool scene, uint32_t grid, int max_tiles, hipStream_t stream);
 hipError_t launch_count(const JobList& js, bool scene, uint32_t grid, int max_tiles, hipStream_t stream);
+// Layer starts of every tile list from the count kernel's histograms (jobs
+// with layers > 1; runs on the binning grid).
+hipError_t launch_layers(const OneJob& js, uint32_t grid, hipStream_t stream);
+hipError_t launch_layers(const JobList& js, uint32_t grid, hipStream_t stream);
 hipError_t launch_scatter(const OneJob& js, uint32_t grid, int max_tiles, hipStream_t stream);
 hipError_t launch_scatter(const JobList& js, uint32_t grid, int max_tiles, hipStream_t stream);
 // The resolve is a main launch plus a small tail launch for the tiles whose
