@@ -112,6 +112,7 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
     __shared__ uint32_t local_n, bx0, by0, bx1, by1;
     __shared__ unsigned long long local_pairs;
     __shared__ uint32_t cls_end[kDepthBuckets];
+    __shared__ uint32_t wg_zlo;
     uint32_t blk;
     const int ji = js.find(blockIdx.x, blk);
     if (ji < 0) return;
@@ -143,6 +144,7 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
     }
     if (tid == 0) {
         local_n = 0;
+        wg_zlo = 0x7F800000u;
         local_pairs = 0;
         bx0 = 0xFFFF;
         by0 = 0xFFFF;
@@ -151,6 +153,17 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
     }
     __syncthreads();
     uint32_t mx0 = 0xFFFF, my0 = 0xFFFF, mx1 = 0, my1 = 0, my_pairs = 0;
+    // resident scenes: the least cull depth of this lane's visible primitives
+    // (float bits), a bound the resolve may stop a tile's list at.  The
+    // resolve culls a record by (z - r)(1 - 1e-5) from FP32 coordinates
+    // (bonds: the nearer end's z less the radius, and 1e-6 less); the FP64
+    // value here, 2e-5 of the magnitudes and 2e-6 lower and rounded down,
+    // stays below it.
+    uint32_t my_zlo = 0x7F800000u;
+    auto note_z = [&](double zmin, double mag) {
+        const float lb = __double2float_rd(zmin - 2e-5 * mag - 2e-6);
+        my_zlo = min(my_zlo, lb > 0.0f ? __float_as_uint(lb) : 0u);
+    };
 
     const uint64_t start = (uint64_t)blk * chunk;
     auto src = src0;
@@ -191,6 +204,10 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
         double v[6], r = 0.0;
         const bool vis = item_view(F, it, rec, v, r) && item_rect(F, it, v, r, x0, y0, x1, y1);
         bad_count += it.kind == kBadBond ? 1u : 0u;
+        if (kScene && vis) {
+            if (it.kind == kAtom) note_z(v[2] - r, fabs(v[2]) + r);
+            else note_z(fmin(v[2], v[5]) - r, fabs(v[2]) + fabs(v[5]) + r);
+        }
         emit(vis, it.src, x0, y0, x1, y1);
     };
     if constexpr (kScene) {
@@ -233,6 +250,7 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
                     const double r = (double)atom_radius(F, a[q].w);
                     const bool vis = i < S.n_atoms && r > 0.0 && sphere_in_frustum(F, vx, vy, vz, r) &&
                                      sphere_rect_fast(F, vx, vy, vz, r, x0, y0, x1, y1);
+                    if (vis) note_z(vz - r, fabs(vz) + r);
                     emit(vis, i, x0, y0, x1, y1);
                 }
             } else {
@@ -255,6 +273,7 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
         }
     }
     if (bad_count) atomicAdd(&ctr->bad_bonds, bad_count);
+    if (kScene && my_zlo != 0x7F800000u) atomicMin(&wg_zlo, my_zlo);
     if (my_pairs) {
         atomicMin(&bx0, mx0);
         atomicMin(&by0, my0);
@@ -270,6 +289,8 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
         if (h) atomicAdd(&tile_cnt[t], h);
     }
     if (tid == 0) {
+        if (kScene && J.bb.layers > 1 && wg_zlo != 0x7F800000u)
+            atomicMin(&ctr->layer_zlo[layer_of(blk, J.bb.groups, J.bb.layers)], wg_zlo);
         vis_cnt[blk] = local_n;
         vis_box[blk] = make_uint2(bx0 | (by0 << 16), bx1 | (by1 << 16));
         atomicAdd(&ctr->vis_count, local_n);

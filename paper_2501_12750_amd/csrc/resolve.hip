@@ -177,6 +177,9 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
     __shared__ uint32_t hz[kHzBlocks];
     __shared__ float red_lo[kBlock / 64], red_hi[kBlock / 64];
     __shared__ uint32_t bcnt[kBuckets], bbase[kBuckets];
+    // resident scenes: list position where each layer starts, and the least
+    // cull depth (float bits) of the layers from there on
+    __shared__ uint32_t lay_start[kLayers], lay_zrest[kLayers];
     // depth-ordered chunk: record slots front to back.  Chunks resolved in
     // list order use it instead as 64 slots per wave, slot i holding j when
     // record j's first fragment is the i-th of the 64 the wave resolves
@@ -475,8 +478,33 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
                 __syncthreads();   // refreshed block depths are in LDS
             }
         };
+        // Layered lists (resident scenes) run front to back by layer: once
+        // every record from a layer on lies behind all block depths of the
+        // tile, the rest of the list is culled whole, unread.
+        const uint32_t L = kTail || stats ? 1u : J.bb.layers;
+        if (L > 1 && wave == 0) {
+            uint32_t zr = lane < (int)L ? ctr->layer_zlo[lane] : 0x7F800000u;
+#pragma unroll
+            for (int o2 = 1; o2 < 32; o2 <<= 1) {
+                const uint32_t u = (uint32_t)__shfl_down((int)zr, o2);
+                if (lane + o2 < 64) zr = min(zr, u);
+            }
+            if (lane < (int)L) {
+                lay_zrest[lane] = zr;
+                lay_start[lane] = J.bb.layer_off[(size_t)lane * F.tiles_x * F.tiles_y + t];
+            }
+        }
         bool hz_set = false;   // the block depths hold a refresh (uniform)
         for (uint64_t base = 0; base < nsrc; base += kChunk) {
+            if (L > 1 && hz_set) {
+                // every wave reads the same LDS after the last barrier: a uniform decision
+                uint32_t m = 0;
+                for (int i = lane; i < kHzBlocks; i += 64) m = max(m, hz[i]);
+                m = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(m), 63);
+                const unsigned long long started = __ballot(lane < (int)L && lay_start[lane] <= (uint32_t)base);
+                const uint32_t zr = lay_zrest[63 - __clzll((long long)started)];
+                if (zr > m && zr != 0u) break;
+            }
             PrimRec pr;
             bool have;
             if constexpr (kTail) {

@@ -80,6 +80,10 @@ struct Counters {
     unsigned long long frag_hit_bond;
     unsigned int done_blocks;
     unsigned int vis_bucket[kDepthBuckets];   // resident scenes: clusters that passed the frustum test, per depth class
+    // resident scenes: per layer, float bits of a lower bound of the resolve's
+    // cull depth of every primitive its workgroups binned (+inf: none; 0:
+    // not positive)
+    unsigned int layer_zlo[kLayers];
     unsigned long long pairs_counted;   // total of the tile counts, added by the count kernel
 };
 
