@@ -62,6 +62,22 @@ extern "C" {
                                     disables the depth early-outs */
 #define VTX_FLAG_TIMING 2u       /* vtx_render records a HIP event before and after
                                     each kernel, read back by vtx_read_timings */
+#define VTX_FLAG_TWO_PASS 8u     /* resident scenes: occlusion pre-pass.  The nearest
+                                    eighth of the visible clusters (by depth) is
+                                    binned and resolved first; of the rest, only
+                                    clusters whose bounding sphere is not behind the
+                                    depths of every 16x16-pixel cell under it are
+                                    binned, and resolved on top.  The image is the
+                                    same as without it.  It pays when near surfaces
+                                    close whole cells (a dense slab in front of a
+                                    deep scene bins ~10x fewer primitives) and costs
+                                    a second binning pass when they do not (sparse
+                                    scenes whose cells keep a gap).  Ignored with
+                                    VTX_FLAG_STATS or VTX_FLAG_ONE_PASS, with 8-pixel
+                                    tiles, for jobs in a batch whose other jobs do
+                                    not all set it, and on the first frame of a new
+                                    scene or image size in a render slot */
+#define VTX_FLAG_ONE_PASS 4u     /* resident scenes: never take the pre-pass */
 
 /*
  * Camera (paper, "Improved user experience": trackball and free-fly cameras

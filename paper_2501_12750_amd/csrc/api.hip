@@ -41,11 +41,14 @@ int fail(int code, const char* fmt, ...) {
     } while (0)
 
 constexpr int kTimingRing = 64;
-constexpr int kMarks = 7;   // before clear, project, scan, scatter, resolve, shade; after shade
+constexpr int kMarks = 11;   // events of a timed frame: 7, or 11 with the occlusion pre-pass
+constexpr int kTimeCats = 6;  // clear, project, scan, scatter, resolve, shade
 constexpr int kMaxBatch = 4096;
 
 struct TimingSlot {
     hipEvent_t ev[kMarks] = {};
+    uint8_t cat[kMarks] = {};   // time category of the interval from event m to event m + 1
+    int used = 0;               // events recorded
     bool inflight = false;
 };
 
@@ -60,6 +63,7 @@ struct Bins {
     size_t hist_cap = 0;
     size_t list_alloc = 0;          // allocated bin entries (>= bb.capacity, the entries in use)
     size_t vc_cap = 0;
+    size_t hz16_cap = 0;
     uint32_t* vis_clusters = nullptr;   // resident scenes: the clusters that passed the frustum test
     // supersampled renders: the full-size depth, id and colour images
     float* ss_depth = nullptr;
@@ -103,7 +107,7 @@ struct Workspace {
     TimingSlot* tslots = nullptr;   // ring of kTimingRing, created on first timed frame
     int tnext = 0;
     uint64_t tframes = 0;
-    double tsum[kMarks - 1] = {};
+    double tsum[kTimeCats] = {};
     // overflowed tiles of a resolve launch (job << 32 | tile) and its two
     // counters, left zeroed by every launch
     unsigned long long* d_ovf = nullptr;
@@ -148,6 +152,7 @@ void bins_free(Bins* b) {
     hipFree(b->bb.tile_off);
     hipFree(b->bb.tile_fill);
     hipFree(b->bb.layer_off);
+    hipFree(b->bb.hz16);
     hipFree(b->bb.vis_src);
     hipFree(b->bb.vis_rect);
     hipFree(b->bb.vis_cnt);
@@ -225,11 +230,16 @@ void harvest_timings(Workspace* ws, bool wait) {
         const int i = (ws->tnext + k) % kTimingRing;   // oldest first
         TimingSlot& t = ws->tslots[i];
         if (!t.inflight) continue;
-        if (wait) (void)hipEventSynchronize(t.ev[kMarks - 1]);
-        if (hipEventQuery(t.ev[kMarks - 1]) != hipSuccess) break;
-        for (int m = 0; m < kMarks - 1; ++m) {
+        if (t.used < 2) {   // the frame failed before its events were queued
+            t.inflight = false;
+            continue;
+        }
+        const int last = t.used - 1;
+        if (wait) (void)hipEventSynchronize(t.ev[last]);
+        if (hipEventQuery(t.ev[last]) != hipSuccess) break;
+        for (int m = 0; m < last; ++m) {
             float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, t.ev[m], t.ev[m + 1]) == hipSuccess) ws->tsum[m] += ms;
+            if (hipEventElapsedTime(&ms, t.ev[m], t.ev[m + 1]) == hipSuccess) ws->tsum[t.cat[m]] += ms;
         }
         ws->tframes += 1;
         t.inflight = false;
@@ -248,6 +258,7 @@ int timing_slot(Workspace* ws, TimingSlot** out) {
     if (t->inflight) harvest_timings(ws, true);
     ws->tnext = (ws->tnext + 1) % kTimingRing;
     t->inflight = true;
+    t->used = 0;
     *out = t;
     return VTX_OK;
 }
@@ -293,7 +304,8 @@ int grow(T** p, size_t& cap, size_t want, hipStream_t stream, const char* what) 
 
 // Sizes slot b for a render with T tiles, nprim primitives binned by
 // `groups` workgroups of `chunk`, and nc scene clusters (0 for the plain path).
-int ensure_bins(Workspace* ws, Bins* b, int T, uint64_t nprim, uint32_t groups, uint32_t chunk, uint32_t nc) {
+int ensure_bins(Workspace* ws, Bins* b, int T, uint64_t nprim, uint32_t groups, uint32_t chunk, uint32_t nc, int W,
+                int H) {
     int rc;
     hipStream_t st = ws->stream;
     if ((size_t)T > b->tiles_cap || !b->bb.tile_cnt) {
@@ -332,6 +344,13 @@ int ensure_bins(Workspace* ws, Bins* b, int T, uint64_t nprim, uint32_t groups, 
         size_t c1 = b->hist_cap;
         if ((rc = grow(&b->bb.hist, c1, nh, st, "tile histograms"))) return rc;
         b->hist_cap = nh;
+    }
+    if (nc) {   // resident scenes: 16x16-cell depths of the occlusion pre-pass
+        const size_t cw = (size_t)(W + vtx::kHzCell - 1) / vtx::kHzCell, ch = (size_t)(H + vtx::kHzCell - 1) / vtx::kHzCell;
+        if (cw * ch > b->hz16_cap || !b->bb.hz16) {
+            if ((rc = grow(&b->bb.hz16, b->hz16_cap, cw * ch, st, "cell depths"))) return rc;
+        }
+        b->bb.hz16_w = (int32_t)cw;
     }
     if (nc && ((size_t)nc * vtx::kDepthBuckets > b->vc_cap || !b->vis_clusters)) {
         if ((rc = grow(&b->vis_clusters, b->vc_cap, (size_t)nc * vtx::kDepthBuckets, st, "visible clusters"))) return rc;
@@ -780,12 +799,14 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
         count |= (j.F.flags & VTX_FLAG_STATS) != 0;
         scene |= j.scene;
     }
-    hipEvent_t* marks = nullptr;
-    if (timing && !capture) {
-        TimingSlot* slot = nullptr;
-        if ((rc = timing_slot(ws, &slot))) return rc;
-        marks = slot->ev;
-    }
+    TimingSlot* tslot = nullptr;
+    if (timing && !capture && (rc = timing_slot(ws, &tslot))) return rc;
+    // timed frames: an event, and the time category of the interval it opens
+    auto mark = [&](int cat) -> hipError_t {
+        if (!tslot || tslot->used >= kMarks) return hipSuccess;
+        tslot->cat[tslot->used] = (uint8_t)cat;
+        return hipEventRecord(tslot->ev[tslot->used++], stream);
+    };
     while (bin && ws->slots.size() < n) {
         Bins* b = nullptr;
         if ((rc = bins_new(&b))) return rc;
@@ -857,7 +878,9 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
         Bins* b = ws->slots[i];
         if (capture && (b->dirty || !b->was_sized(nprim, s.F.W, s.F.H) || (size_t)T > b->tiles_cap ||
                         (size_t)groups * chunk > b->vis_cap || (size_t)groups * T > b->hist_cap ||
-                        (nc && (size_t)nc * vtx::kDepthBuckets > b->vc_cap)))
+                        (nc && (size_t)nc * vtx::kDepthBuckets > b->vc_cap) ||
+                        (nc && (size_t)((s.F.W + vtx::kHzCell - 1) / vtx::kHzCell) *
+                                       ((s.F.H + vtx::kHzCell - 1) / vtx::kHzCell) > b->hz16_cap)))
             return fail(VTX_EINVAL, "job %zu: scratch not sized for capture", i);
         if (!ws->fixed_capacity && !b->was_sized(nprim, s.F.W, s.F.H)) {
             // a shape the tuner sized, or a scene and image size counted
@@ -870,7 +893,7 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
                 b->mark_sized(nprim, s.F.W, s.F.H);
             }
         }
-        if ((rc = ensure_bins(ws, b, T, nprim, groups, chunk, nc))) return rc;
+        if ((rc = ensure_bins(ws, b, T, nprim, groups, chunk, nc, s.F.W, s.F.H))) return rc;
         b->pending_uid = s.scene_uid;
         b->pending_w = s.F.W;
         b->pending_h = s.F.H;
@@ -953,15 +976,9 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
             if ((rc = grow(&ws->d_ovf, ws->ovf_cap, (size_t)xcd_round(gmax), stream, "overflow tiles"))) return rc;
         }
     }
-    if (marks) VTX_HIP(hipEventRecord(marks[0], stream));
-    if (marks) VTX_HIP(hipEventRecord(marks[1], stream));
+    VTX_HIP(mark(0));
+    VTX_HIP(mark(1));
     if (bin) {
-        if (scene) {
-            if (n == 1) VTX_HIP(vtx::launch_cluster_cull(one(g_cull), g_cull, stream));
-            else VTX_HIP(vtx::launch_cluster_cull(list_of(0, n, 0), g_cull, stream));
-        }
-        if (n == 1) VTX_HIP(vtx::launch_count(one(g_bin), scene, g_bin, max_tiles, stream));
-        else VTX_HIP(vtx::launch_count(list_of(0, n, n + 1), scene, g_bin, max_tiles, stream));
         // first frame of a new scene or image size in a slot: wait for the
         // tile counts and size its lists, so the frame does not take the
         // overflow path
@@ -971,45 +988,63 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
             if (!ws->fixed_capacity && !b->was_sized(nprims[i], d[i].F.W, d[i].F.H)) need.push_back(i);
         }
         if (!need.empty() && capture) return fail(VTX_EINVAL, "scratch not sized for capture");
-        if (!need.empty()) {
-            std::vector<unsigned long long> counted(n, 0);
-            for (size_t i : need)
-                VTX_HIP(hipMemcpyAsync(&counted[i], &ws->slots[i]->bb.ctr->pairs_counted, sizeof(unsigned long long),
-                                       hipMemcpyDeviceToHost, stream));
-            VTX_HIP(hipStreamSynchronize(stream));
-            for (size_t i : need) {
-                Bins* b = ws->slots[i];
-                uint64_t want = counted[i] + counted[i] / 2 + 1024;
-                if (want > kMaxCapacity) want = kMaxCapacity;
-                if (want > b->want_capacity) b->want_capacity = want;
-                if (b->want_capacity > b->list_alloc) {
-                    if ((rc = grow(&b->bb.list, b->list_alloc, (size_t)b->want_capacity, stream, "tile lists"))) return rc;
-                }
-                b->bb.capacity = b->want_capacity;
-                b->mark_sized(nprims[i], d[i].F.W, d[i].F.H);
-                note_pairs(d[i].scene_uid, d[i].F.W, d[i].F.H, counted[i]);
-                jobs[i].bb.list = b->bb.list;
-                jobs[i].bb.capacity = b->bb.capacity;
-            }
-            if (n > 1 && (rc = upload_tables(ws, jobs, d, starts, &k_off, &s_off))) return rc;
-        }
-        if (marks) VTX_HIP(hipEventRecord(marks[2], stream));
+        // Occlusion pre-pass (asked for by every job, resident scenes with
+        // sized lists): bin and resolve the nearest clusters first, then only
+        // the clusters not hidden behind that pass's depths.
+        bool two_pass = scene && need.empty();
+        for (size_t i = 0; i < n && two_pass; ++i)
+            two_pass = d[i].scene && (d[i].F.flags & VTX_FLAG_TWO_PASS) &&
+                       !(d[i].F.flags & (VTX_FLAG_STATS | VTX_FLAG_ONE_PASS)) && d[i].F.tile >= vtx::kHzCell;
         if (scene) {
-            if (n == 1) VTX_HIP(vtx::launch_layers(one(g_bin), g_bin, stream));
-            else VTX_HIP(vtx::launch_layers(list_of(0, n, n + 1), g_bin, stream));
+            if (n == 1) VTX_HIP(vtx::launch_cluster_cull(one(g_cull), g_cull, stream));
+            else VTX_HIP(vtx::launch_cluster_cull(list_of(0, n, 0), g_cull, stream));
         }
-        if (marks) VTX_HIP(hipEventRecord(marks[3], stream));
-        if (n == 1) VTX_HIP(vtx::launch_scatter(one(g_bin), g_bin, max_tiles, stream));
-        else VTX_HIP(vtx::launch_scatter(list_of(0, n, n + 1), g_bin, max_tiles, stream));
-        if (marks) VTX_HIP(hipEventRecord(marks[4], stream));
-        for (size_t g = 0; g < groups_ts.size(); ++g) {
-            const size_t a = groups_ts[g].first, b = groups_ts[g].second;
-            if (n == 1)
-                VTX_HIP(vtx::launch_resolve(one(groups_grid[g]), d[0].F.tile, groups_grid[g], count, ws->d_ovf,
-                                            ws->d_ovf_n, stream));
-            else
-                VTX_HIP(vtx::launch_resolve(list_of(a, b - a, groups_off[g]), d[a].F.tile, groups_grid[g], count,
-                                            ws->d_ovf, ws->d_ovf_n, stream));
+        for (int pass = 0; pass < (two_pass ? 2 : 1); ++pass) {
+            const int phase = two_pass ? (pass == 0 ? vtx::kPhaseFront : vtx::kPhaseRest) : vtx::kPhaseAll;
+            if (pass > 0) VTX_HIP(mark(1));
+            if (n == 1) VTX_HIP(vtx::launch_count(one(g_bin), scene, phase, g_bin, max_tiles, stream));
+            else VTX_HIP(vtx::launch_count(list_of(0, n, n + 1), scene, phase, g_bin, max_tiles, stream));
+            if (!need.empty()) {
+                std::vector<unsigned long long> counted(n, 0);
+                for (size_t i : need)
+                    VTX_HIP(hipMemcpyAsync(&counted[i], &ws->slots[i]->bb.ctr->pairs_counted,
+                                           sizeof(unsigned long long), hipMemcpyDeviceToHost, stream));
+                VTX_HIP(hipStreamSynchronize(stream));
+                for (size_t i : need) {
+                    Bins* b = ws->slots[i];
+                    uint64_t want = counted[i] + counted[i] / 2 + 1024;
+                    if (want > kMaxCapacity) want = kMaxCapacity;
+                    if (want > b->want_capacity) b->want_capacity = want;
+                    if (b->want_capacity > b->list_alloc) {
+                        if ((rc = grow(&b->bb.list, b->list_alloc, (size_t)b->want_capacity, stream, "tile lists")))
+                            return rc;
+                    }
+                    b->bb.capacity = b->want_capacity;
+                    b->mark_sized(nprims[i], d[i].F.W, d[i].F.H);
+                    note_pairs(d[i].scene_uid, d[i].F.W, d[i].F.H, counted[i]);
+                    jobs[i].bb.list = b->bb.list;
+                    jobs[i].bb.capacity = b->bb.capacity;
+                }
+                if (n > 1 && (rc = upload_tables(ws, jobs, d, starts, &k_off, &s_off))) return rc;
+            }
+            VTX_HIP(mark(2));
+            if (scene) {
+                if (n == 1) VTX_HIP(vtx::launch_layers(one(g_bin), g_bin, stream));
+                else VTX_HIP(vtx::launch_layers(list_of(0, n, n + 1), g_bin, stream));
+            }
+            VTX_HIP(mark(3));
+            if (n == 1) VTX_HIP(vtx::launch_scatter(one(g_bin), phase, g_bin, max_tiles, stream));
+            else VTX_HIP(vtx::launch_scatter(list_of(0, n, n + 1), phase, g_bin, max_tiles, stream));
+            VTX_HIP(mark(4));
+            for (size_t g = 0; g < groups_ts.size(); ++g) {
+                const size_t a = groups_ts[g].first, b = groups_ts[g].second;
+                if (n == 1)
+                    VTX_HIP(vtx::launch_resolve(one(groups_grid[g]), d[0].F.tile, phase, groups_grid[g], count,
+                                                ws->d_ovf, ws->d_ovf_n, stream));
+                else
+                    VTX_HIP(vtx::launch_resolve(list_of(a, b - a, groups_off[g]), d[a].F.tile, phase, groups_grid[g],
+                                                count, ws->d_ovf, ws->d_ovf_n, stream));
+            }
         }
         for (size_t i = 0; i < n; ++i) {
             ws->slots[i]->dirty = false;
@@ -1023,10 +1058,10 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
             ws->pending = true;
             ws->pending_n = (int)n;
         }
-    } else if (marks) {
-        for (int k = 2; k <= 4; ++k) VTX_HIP(hipEventRecord(marks[k], stream));
+    } else {
+        for (int k = 2; k <= 4; ++k) VTX_HIP(mark(k));
     }
-    if (marks) VTX_HIP(hipEventRecord(marks[5], stream));
+    VTX_HIP(mark(5));
     if (shade) {
         if (n == 1) VTX_HIP(vtx::launch_shade(one(g_shade), g_shade, stream));
         else VTX_HIP(vtx::launch_shade(list_of(0, n, 2 * (n + 1)), g_shade, stream));
@@ -1035,7 +1070,7 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
                 VTX_HIP(vtx::launch_downsample(jobs[i].depth, jobs[i].id, jobs[i].rgba, d[i].F.W / d[i].ss,
                                                d[i].F.H / d[i].ss, d[i].ss, d[i].depth, d[i].id, d[i].rgba, stream));
     }
-    if (marks) VTX_HIP(hipEventRecord(marks[6], stream));
+    VTX_HIP(mark(5));
     return VTX_OK;
 }
 
@@ -1151,10 +1186,12 @@ size_t vtx_frame_scratch_bytes(int32_t W, int32_t H, int64_t n_atoms, int64_t n_
     uint64_t cap = nprim / 2;
     if (cap < kMinCapacity) cap = kMinCapacity;
     // tile counts and offsets, per-layer cursors and starts, visible lists,
-    // histograms, lists, visible clusters per depth class, counters
+    // histograms, lists, visible clusters per depth class, cell depths, counters
     return (size_t)(T * 16 + T * 8 * vtx::kLayers + (uint64_t)groups * chunk * (sizeof(uint32_t) + sizeof(uint2)) +
                     (uint64_t)groups * T * 4 + cap * sizeof(uint2) +
-                    scene_clusters(n_atoms, n_bonds) * 4 * vtx::kDepthBuckets + sizeof(Counters) + 4096);
+                    scene_clusters(n_atoms, n_bonds) * 4 * vtx::kDepthBuckets +
+                    (uint64_t)((W + vtx::kHzCell - 1) / vtx::kHzCell) * ((H + vtx::kHzCell - 1) / vtx::kHzCell) * 4 +
+                    sizeof(Counters) + 4096);
 }
 
 int vtx_scene_create(vtx_context* ctx, const float* positions, const float* radii, const uint32_t* colors,

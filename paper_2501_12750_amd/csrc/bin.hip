@@ -105,9 +105,42 @@ __device__ inline void wave_count(uint32_t* hist, int t) {
     if ((pend >> __lane_id()) & 1ull) atomicAdd(&hist[t], 1u);
 }
 
+// Rest pass of a two-pass frame: true when cluster c cannot win a pixel.
+// The lower bound of the cull depth of its primitives (the bounding sphere
+// of its box, widened as in the frustum test, with the margin of the
+// per-primitive bound) lies behind the front pass's depth of every 16x16
+// cell under the sphere's footprint; those depths only decrease later.
+// Called by whole waves with a wave-uniform c: the lanes share the cells.
+__device__ inline bool cluster_hidden(const Frame& F, const SceneDev& S, const BinBuffers& bb, uint32_t c) {
+    const float4 lo = S.cluster_box[2 * (size_t)c], hi = S.cluster_box[2 * (size_t)c + 1];
+    const float pad = c < S.atom_clusters ? (F.rep == 2 ? F.bond_radius : F.rep == 3 ? F.probe : 0.0f) : F.bond_radius;
+    const double hx = 0.5 * ((double)hi.x - lo.x), hy = 0.5 * ((double)hi.y - lo.y), hz = 0.5 * ((double)hi.z - lo.z);
+    double vx, vy, vz;
+    to_view(F, (float)(lo.x + hx), (float)(lo.y + hy), (float)(lo.z + hz), vx, vy, vz);
+    const double r = sqrt(hx * hx + hy * hy + hz * hz) + pad +
+                     1e-6 * (fabs((double)lo.x) + fabs((double)lo.y) + fabs((double)lo.z) + 1.0);
+    const float zlo = __double2float_rd(vz - r - 2e-5 * (fabs(vz) + r) - 2e-6);
+    if (!(zlo > 0.0f)) return false;
+    int x0, y0, x1, y1;
+    if (!sphere_rect_fast(F, vx, vy, vz, r, x0, y0, x1, y1)) return true;   // covers no pixel of the image
+    const int cx0 = x0 / kHzCell, cy0 = y0 / kHzCell, cw = x1 / kHzCell - cx0 + 1;
+    const int n = cw * (y1 / kHzCell - cy0 + 1);
+    if (n > 16 * 64) return false;   // a footprint this large is rarely hidden: not worth the reads
+    uint32_t m = 0;
+    for (int k = (int)__lane_id(); k < n; k += 64) {
+        const int q = k / cw;
+        m = max(m, bb.hz16[(size_t)(cy0 + q) * bb.hz16_w + (cx0 + k - q * cw)]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o));
+    return __float_as_uint(zlo) > m;
+}
+
 // Count.  Work block b of a job is that job's binning workgroup b.
-template <class JS, bool kScene>
-__global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
+// kRest: the rest pass of a two-pass frame (a separate instantiation keeps
+// the cluster test out of the others' registers).
+template <class JS, bool kScene, bool kRest>
+__global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
     extern __shared__ uint32_t hist[];
     __shared__ uint32_t local_n, bx0, by0, bx1, by1;
     __shared__ unsigned long long local_pairs;
@@ -216,12 +249,15 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
         // cluster's four 64-atom quarters are loaded together and take the
         // sphere-only path.
         // Workgroup b takes positions [c0, c1) of the visible clusters in
-        // depth-class order, so the workgroups run front to back.
+        // depth-class order, so the workgroups run front to back.  A
+        // two-pass frame splits the positions at the first 1 / kFrontShare.
         const SceneDev& S = src.S;
         const uint32_t stride = S.atom_clusters + S.bond_clusters;
         const uint32_t nvc = cls_end[kDepthBuckets - 1];
-        const uint32_t cpw = (nvc + src.groups - 1) / src.groups;
-        const uint32_t c0 = min(nvc, blk * cpw), c1 = min(nvc, c0 + cpw);
+        const uint32_t front = (nvc + kFrontShare - 1) / kFrontShare;
+        const uint32_t lo = phase == kPhaseRest ? front : 0u, hi = phase == kPhaseFront ? front : nvc;
+        const uint32_t cpw = (hi - lo + src.groups - 1) / src.groups;
+        const uint32_t c0 = min(hi, lo + blk * cpw), c1 = min(hi, c0 + cpw);
         int cls = 0;   // class of the positions this wave reads next (they increase)
         auto cluster_at = [&](uint32_t q) -> uint32_t {
             while (cls_end[cls] <= q) ++cls;
@@ -234,6 +270,9 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
         for (uint32_t ci = c0 + wave; ci < c1; ci += nw) {
             const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int)cn);
             if (ci + nw < c1) cn = cluster_at(ci + nw);   // the next cluster's id, ahead of its use
+            if constexpr (kRest) {
+                if (cluster_hidden(F, S, J.bb, c)) continue;
+            }
             if (c < S.atom_clusters) {
                 float4 a[4];
 #pragma unroll
@@ -290,7 +329,7 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js) {
     }
     if (tid == 0) {
         if (kScene && J.bb.layers > 1 && wg_zlo != 0x7F800000u)
-            atomicMin(&ctr->layer_zlo[layer_of(blk, J.bb.groups, J.bb.layers)], wg_zlo);
+            atomicMin(&ctr->layer_zlo[phase == kPhaseRest ? 1 : 0][layer_of(blk, J.bb.groups, J.bb.layers)], wg_zlo);
         vis_cnt[blk] = local_n;
         vis_box[blk] = make_uint2(bx0 | (by0 << 16), bx1 | (by1 << 16));
         atomicAdd(&ctr->vis_count, local_n);
@@ -348,7 +387,7 @@ constexpr uint32_t kNoRun = 0xFFFFFFFFu;
 // places its primitives with LDS atomics.  Workgroup 0 also stores the tile
 // offsets for the resolve and publishes the frame counters.
 template <class JS>
-__global__ void __launch_bounds__(kBinThreads) k_scatter(JS js) {
+__global__ void __launch_bounds__(kBinThreads) k_scatter(JS js, int phase) {
     extern __shared__ uint32_t cur[];
     __shared__ unsigned long long wtot[kBinThreads / 64];
     __shared__ unsigned int n_over;
@@ -422,8 +461,19 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js) {
             ctr->frag_hit_bond = 0;
             ctr->done_blocks = 0;
             ctr->pairs_counted = 0;
-            for (int k = 0; k < kDepthBuckets; ++k) ctr->vis_bucket[k] = 0;   // the next frame's cluster test adds to these
-            if (host_ctr) {
+            // the next frame's cluster test adds to these (the rest pass reads them)
+            if (phase != kPhaseFront)
+                for (int k = 0; k < kDepthBuckets; ++k) ctr->vis_bucket[k] = 0;
+            if (host_ctr && phase == kPhaseRest) {
+                // a two-pass frame: visible primitives and overflowed tiles of
+                // both passes, the larger list total
+                host_ctr->vis_count += vis;
+                host_ctr->bad_bonds += bad;
+                if (total > host_ctr->pairs) host_ctr->pairs = total;
+                host_ctr->overflow |= total > capacity ? 1u : 0u;
+                host_ctr->overflow_tiles += n_over;
+                __threadfence_system();
+            } else if (host_ctr) {
                 host_ctr->vis_count = vis;
                 host_ctr->bad_bonds = bad;
                 host_ctr->pairs = total;
@@ -523,28 +573,30 @@ hipError_t launch_zero(uint32_t* p, size_t n, hipStream_t stream) {
 }
 
 template <class JS>
-hipError_t count_impl(const JS& js, bool scene, uint32_t grid, int max_tiles, hipStream_t stream) {
+hipError_t count_impl(const JS& js, bool scene, int phase, uint32_t grid, int max_tiles, hipStream_t stream) {
     if (max_tiles > kMaxLdsTiles) return hipErrorInvalidValue;
+    if (phase != kPhaseAll && !scene) return hipErrorInvalidValue;
     if (grid == 0) return hipSuccess;
     const size_t lds = (size_t)max_tiles * sizeof(uint32_t);
-    if (scene) k_count<JS, true><<<grid, kBinThreads, lds, stream>>>(js);
-    else k_count<JS, false><<<grid, kBinThreads, lds, stream>>>(js);
+    if (scene && phase == kPhaseRest) k_count<JS, true, true><<<grid, kBinThreads, lds, stream>>>(js, phase);
+    else if (scene) k_count<JS, true, false><<<grid, kBinThreads, lds, stream>>>(js, phase);
+    else k_count<JS, false, false><<<grid, kBinThreads, lds, stream>>>(js, phase);
     return hipGetLastError();
 }
 
 template <class JS>
-hipError_t scatter_impl(const JS& js, uint32_t grid, int max_tiles, hipStream_t stream) {
+hipError_t scatter_impl(const JS& js, int phase, uint32_t grid, int max_tiles, hipStream_t stream) {
     if (max_tiles > kMaxLdsTiles) return hipErrorInvalidValue;
     if (grid == 0) return hipSuccess;
-    k_scatter<JS><<<grid, kBinThreads, (size_t)max_tiles * sizeof(uint32_t), stream>>>(js);
+    k_scatter<JS><<<grid, kBinThreads, (size_t)max_tiles * sizeof(uint32_t), stream>>>(js, phase);
     return hipGetLastError();
 }
 
-hipError_t launch_count(const OneJob& js, bool scene, uint32_t grid, int max_tiles, hipStream_t stream) {
-    return count_impl(js, scene, grid, max_tiles, stream);
+hipError_t launch_count(const OneJob& js, bool scene, int phase, uint32_t grid, int max_tiles, hipStream_t stream) {
+    return count_impl(js, scene, phase, grid, max_tiles, stream);
 }
-hipError_t launch_count(const JobList& js, bool scene, uint32_t grid, int max_tiles, hipStream_t stream) {
-    return count_impl(js, scene, grid, max_tiles, stream);
+hipError_t launch_count(const JobList& js, bool scene, int phase, uint32_t grid, int max_tiles, hipStream_t stream) {
+    return count_impl(js, scene, phase, grid, max_tiles, stream);
 }
 hipError_t launch_layers(const OneJob& js, uint32_t grid, hipStream_t stream) {
     k_layers<<<grid, kBinThreads, 0, stream>>>(js);
@@ -554,11 +606,11 @@ hipError_t launch_layers(const JobList& js, uint32_t grid, hipStream_t stream) {
     k_layers<<<grid, kBinThreads, 0, stream>>>(js);
     return hipGetLastError();
 }
-hipError_t launch_scatter(const OneJob& js, uint32_t grid, int max_tiles, hipStream_t stream) {
-    return scatter_impl(js, grid, max_tiles, stream);
+hipError_t launch_scatter(const OneJob& js, int phase, uint32_t grid, int max_tiles, hipStream_t stream) {
+    return scatter_impl(js, phase, grid, max_tiles, stream);
 }
-hipError_t launch_scatter(const JobList& js, uint32_t grid, int max_tiles, hipStream_t stream) {
-    return scatter_impl(js, grid, max_tiles, stream);
+hipError_t launch_scatter(const JobList& js, int phase, uint32_t grid, int max_tiles, hipStream_t stream) {
+    return scatter_impl(js, phase, grid, max_tiles, stream);
 }
 
 }  // namespace vtx

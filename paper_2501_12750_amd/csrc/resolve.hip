@@ -166,9 +166,12 @@ __device__ inline bool source_record(const Job& J, uint32_t src, PrimRec& pr) {
 // (kTail: the list overflowed and the tile is rebuilt from every binning
 // workgroup's visible list).  Re-arms the tile's count and cursor for the next
 // frame.  The workgroup's LDS holds the tile's depth buffer, one chunk of
-// records and their prefix.
-template <int TS, bool kCount, bool kTail>
-__device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o) {
+// records and their prefix.  Two-pass frames: the front pass also stores the
+// farthest depth of each 16x16 cell of the tile; the rest pass starts from the
+// front pass's depth and id.
+template <int TS, bool kCount, bool kTail, bool kTwo>
+__device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o, int phase_arg) {
+    const int phase = kTwo ? phase_arg : (int)kPhaseAll;   // one-pass instantiations drop the two-pass code
     __shared__ unsigned long long keys[TS * TS];
     __shared__ Rec recs[kChunk];
     __shared__ uint32_t pref[kChunk + 1];
@@ -212,7 +215,16 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
         const int tx = t % F.tiles_x, ty = t / F.tiles_x;
         const int px0 = tx * TS, py0 = ty * TS;
         const int tw = min(TS, F.W - px0), th = min(TS, F.H - py0);
-        for (int i = tid; i < TS * TS; i += kBlock) keys[i] = ~0ull;
+        for (int i = tid; i < TS * TS; i += kBlock) {
+            unsigned long long k0 = ~0ull;
+            const int ly = i / TS, lx = i - ly * TS;
+            if (phase == kPhaseRest && lx < tw && ly < th) {
+                const size_t p = (size_t)(py0 + ly) * F.W + (px0 + lx);
+                const uint32_t id0 = out_id[p];
+                if (id0 != kBackground) k0 = ((unsigned long long)__float_as_uint(depth[p]) << 32) | id0;
+            }
+            keys[i] = k0;
+        }
         if (tid < kChunk / 4) reinterpret_cast<uint32_t*>(ord)[tid] = 0u;
         const uint64_t nsrc = kTail ? (uint64_t)groups * chunk : n;
         const bool persp = F.proj == 0;
@@ -483,7 +495,7 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
         // tile, the rest of the list is culled whole, unread.
         const uint32_t L = kTail || stats ? 1u : J.bb.layers;
         if (L > 1 && wave == 0) {
-            uint32_t zr = lane < (int)L ? ctr->layer_zlo[lane] : 0x7F800000u;
+            uint32_t zr = lane < (int)L ? ctr->layer_zlo[phase == kPhaseRest ? 1 : 0][lane] : 0x7F800000u;
 #pragma unroll
             for (int o2 = 1; o2 < 32; o2 <<= 1) {
                 const uint32_t u = (uint32_t)__shfl_down((int)zr, o2);
@@ -495,6 +507,10 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
             }
         }
         bool hz_set = false;   // the block depths hold a refresh (uniform)
+        if (phase == kPhaseRest) {
+            hz_refresh();   // the front pass's depths bound the blocks from the start
+            hz_set = true;
+        }
         for (uint64_t base = 0; base < nsrc; base += kChunk) {
             if (L > 1 && hz_set) {
                 // every wave reads the same LDS after the last barrier: a uniform decision
@@ -588,6 +604,24 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
             if (tid < kChunk / 4) reinterpret_cast<uint32_t*>(ord)[tid] = 0u;
         }
         __syncthreads();
+        if constexpr (TS >= kHzCell) {
+            if (phase == kPhaseFront) {
+                // farthest depth of each 16x16 cell of the tile, for the rest
+                // pass's cluster test (cells past the image edge are not stored)
+                hz_refresh();
+                constexpr int kCells = TS / kHzCell, kSub = kHzCell / 4;
+                if (tid < kCells * kCells) {
+                    const int cy = tid / kCells, cx = tid - cy * kCells;
+                    const int gx = tx * kCells + cx, gy = ty * kCells + cy;
+                    if (gx < J.bb.hz16_w && gy < (F.H + kHzCell - 1) / kHzCell) {
+                        uint32_t m = 0;
+                        for (int by = 0; by < kSub; ++by)
+                            for (int bx = 0; bx < kSub; ++bx) m = max(m, hz[(cy * kSub + by) * (TS / 4) + cx * kSub + bx]);
+                        J.bb.hz16[(size_t)gy * J.bb.hz16_w + gx] = m;
+                    }
+                }
+            }
+        }
 
         for (int i = tid; i < TS * TS; i += kBlock) {
             const int ly = i / TS, lx = i - ly * TS;
@@ -619,8 +653,10 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o)
 // is left to the tail launch: it is appended to `ovf` (job << 32 | tile).
 // kCount: the instantiation that can count fragments (jobs with
 // VTX_FLAG_STATS); the other one carries no counters.
-template <int TS, class JS, bool kCount>
-__global__ void __launch_bounds__(kBlock, kCount ? 1 : 7) k_resolve(JS js, unsigned long long* ovf, uint32_t* ovf_n) {
+// kTwo: the instantiation for the passes of a two-pass frame.
+template <int TS, class JS, bool kCount, bool kTwo>
+__global__ void __launch_bounds__(kBlock, kCount ? 1 : 7) k_resolve(JS js, unsigned long long* ovf, uint32_t* ovf_n,
+                                                                     int phase) {
     uint32_t tu;
     const int ji = js.find((uint32_t)xcd_contiguous(blockIdx.x, gridDim.x), tu);
     if (ji < 0) return;
@@ -631,21 +667,22 @@ __global__ void __launch_bounds__(kBlock, kCount ? 1 : 7) k_resolve(JS js, unsig
         if (threadIdx.x == 0) ovf[atomicAdd(ovf_n, 1u)] = ((unsigned long long)ji << 32) | tu;
         return;
     }
-    resolve_tile<TS, kCount, false>(J, (int)tu, n, o);
+    resolve_tile<TS, kCount, false, kTwo>(J, (int)tu, n, o, phase);
 }
 
 // Tail launch (a fixed grid, queued right after the main one): resolves the
 // overflowed tiles the main launch listed, then its last workgroup clears the
 // list and publishes the fragment counters of every counting job.  Keeping the
 // rare overflow path out of the main instantiation keeps its register budget.
-template <int TS, class JS, bool kCount>
-__global__ void __launch_bounds__(kBlock) k_resolve_tail(JS js, const unsigned long long* ovf, uint32_t* ovf_n) {
+template <int TS, class JS, bool kCount, bool kTwo>
+__global__ void __launch_bounds__(kBlock) k_resolve_tail(JS js, const unsigned long long* ovf, uint32_t* ovf_n,
+                                                          int phase) {
     const uint32_t total = *(volatile uint32_t*)ovf_n;
     for (uint32_t e = blockIdx.x; e < total; e += gridDim.x) {
         const unsigned long long v = ovf[e];
         const Job& J = js.job((int)(v >> 32));
         const int t = (int)(v & 0xFFFFFFFFull);
-        resolve_tile<TS, kCount, true>(J, t, J.bb.tile_cnt[t], J.bb.tile_off[t]);
+        resolve_tile<TS, kCount, true, kTwo>(J, t, J.bb.tile_cnt[t], J.bb.tile_off[t], phase);
         __syncthreads();   // the next tile reuses the LDS
     }
     if (threadIdx.x == 0) {
@@ -674,35 +711,43 @@ __global__ void __launch_bounds__(kBlock) k_resolve_tail(JS js, const unsigned l
 }  // namespace
 
 template <int TS, class JS, bool kCount>
-void resolve_launch(const JS& js, unsigned g, unsigned long long* ovf, uint32_t* ovf_n, hipStream_t stream) {
-    k_resolve<TS, JS, kCount><<<g, kBlock, 0, stream>>>(js, ovf, ovf_n);
-    k_resolve_tail<TS, JS, kCount><<<kTailBlocks, kBlock, 0, stream>>>(js, ovf, ovf_n);
+void resolve_launch(const JS& js, int phase, unsigned g, unsigned long long* ovf, uint32_t* ovf_n, hipStream_t stream) {
+    if constexpr (!kCount && TS >= kHzCell) {
+        if (phase != kPhaseAll) {
+            k_resolve<TS, JS, false, true><<<g, kBlock, 0, stream>>>(js, ovf, ovf_n, phase);
+            k_resolve_tail<TS, JS, false, true><<<kTailBlocks, kBlock, 0, stream>>>(js, ovf, ovf_n, phase);
+            return;
+        }
+    }
+    k_resolve<TS, JS, kCount, false><<<g, kBlock, 0, stream>>>(js, ovf, ovf_n, phase);
+    k_resolve_tail<TS, JS, kCount, false><<<kTailBlocks, kBlock, 0, stream>>>(js, ovf, ovf_n, phase);
 }
 
 template <class JS, bool kCount>
-hipError_t resolve_impl(const JS& js, int tile, uint32_t grid, unsigned long long* ovf, uint32_t* ovf_n,
+hipError_t resolve_impl(const JS& js, int tile, int phase, uint32_t grid, unsigned long long* ovf, uint32_t* ovf_n,
                         hipStream_t stream) {
     if (grid == 0) return hipSuccess;
+    if (phase != kPhaseAll && (kCount || tile < kHzCell)) return hipErrorInvalidValue;
     const unsigned g = (unsigned)xcd_grid((int)grid);
     switch (tile) {
-        case 8: resolve_launch<8, JS, kCount>(js, g, ovf, ovf_n, stream); break;
-        case 16: resolve_launch<16, JS, kCount>(js, g, ovf, ovf_n, stream); break;
-        case 32: resolve_launch<32, JS, kCount>(js, g, ovf, ovf_n, stream); break;
-        case 64: resolve_launch<64, JS, kCount>(js, g, ovf, ovf_n, stream); break;
+        case 8: resolve_launch<8, JS, kCount>(js, phase, g, ovf, ovf_n, stream); break;
+        case 16: resolve_launch<16, JS, kCount>(js, phase, g, ovf, ovf_n, stream); break;
+        case 32: resolve_launch<32, JS, kCount>(js, phase, g, ovf, ovf_n, stream); break;
+        case 64: resolve_launch<64, JS, kCount>(js, phase, g, ovf, ovf_n, stream); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_resolve(const OneJob& js, int tile, uint32_t grid, bool count, unsigned long long* ovf,
+hipError_t launch_resolve(const OneJob& js, int tile, int phase, uint32_t grid, bool count, unsigned long long* ovf,
                           uint32_t* ovf_n, hipStream_t stream) {
-    return count ? resolve_impl<OneJob, true>(js, tile, grid, ovf, ovf_n, stream)
-                 : resolve_impl<OneJob, false>(js, tile, grid, ovf, ovf_n, stream);
+    return count ? resolve_impl<OneJob, true>(js, tile, phase, grid, ovf, ovf_n, stream)
+                 : resolve_impl<OneJob, false>(js, tile, phase, grid, ovf, ovf_n, stream);
 }
-hipError_t launch_resolve(const JobList& js, int tile, uint32_t grid, bool count, unsigned long long* ovf,
+hipError_t launch_resolve(const JobList& js, int tile, int phase, uint32_t grid, bool count, unsigned long long* ovf,
                           uint32_t* ovf_n, hipStream_t stream) {
-    return count ? resolve_impl<JobList, true>(js, tile, grid, ovf, ovf_n, stream)
-                 : resolve_impl<JobList, false>(js, tile, grid, ovf, ovf_n, stream);
+    return count ? resolve_impl<JobList, true>(js, tile, phase, grid, ovf, ovf_n, stream)
+                 : resolve_impl<JobList, false>(js, tile, phase, grid, ovf, ovf_n, stream);
 }
 
 }  // namespace vtx

@@ -188,7 +188,8 @@ __global__ void __launch_bounds__(kBlock) k_cluster_cull(JS js) {
     const uint32_t nc = S.atom_clusters + (F.n_bonds ? S.bond_clusters : 0u);
     const uint32_t c = blk * kBlock + threadIdx.x;
     if (threadIdx.x < kDepthBuckets) wcnt[threadIdx.x] = 0;
-    if (blk == 0 && threadIdx.x < kLayers) ctr->layer_zlo[threadIdx.x] = 0x7F800000u;   // the count kernel lowers these
+    if (blk == 0 && threadIdx.x < 2 * kLayers)   // the count kernel lowers these
+        ctr->layer_zlo[threadIdx.x / kLayers][threadIdx.x % kLayers] = 0x7F800000u;
     __syncthreads();
     int cls = -1;
     if (c < nc) {

@@ -24,6 +24,12 @@ constexpr int kMaxSamples = 64;
 // consecutive ranges of binning workgroups.
 constexpr int kDepthBuckets = 32;
 constexpr int kLayers = 32;
+// Occlusion pre-pass of resident scenes: the nearest 1 / kFrontShare of the
+// depth-ordered visible clusters is binned and resolved first; of the rest
+// only the clusters not behind its 16x16-pixel block depths are binned.
+constexpr int kFrontShare = 8;
+constexpr int kHzCell = 16;
+enum Phase : int { kPhaseAll = 0, kPhaseFront = 1, kPhaseRest = 2 };
 
 // Per-frame constants, passed by value to every kernel.
 struct Frame {
@@ -80,10 +86,10 @@ struct Counters {
     unsigned long long frag_hit_bond;
     unsigned int done_blocks;
     unsigned int vis_bucket[kDepthBuckets];   // resident scenes: clusters that passed the frustum test, per depth class
-    // resident scenes: per layer, float bits of a lower bound of the resolve's
-    // cull depth of every primitive its workgroups binned (+inf: none; 0:
-    // not positive)
-    unsigned int layer_zlo[kLayers];
+    // resident scenes: per pass (one pass or the front pass; the rest) and
+    // layer, float bits of a lower bound of the resolve's cull depth of every
+    // primitive its workgroups binned (+inf: none; 0: not positive)
+    unsigned int layer_zlo[2][kLayers];
     unsigned long long pairs_counted;   // total of the tile counts, added by the count kernel
 };
 
@@ -268,6 +274,9 @@ struct BinBuffers {
     uint64_t capacity;
     uint32_t groups, chunk;
     uint32_t layers;        // 1, or kLayers for a resident scene (workgroup ranges of increasing depth)
+    uint32_t* hz16;         // two-pass frames: float bits of the farthest depth of each 16x16-pixel
+                            // cell after the front pass (+inf while a pixel is empty), hz16_w per row
+    int32_t hz16_w;
     Counters* ctr;
     Counters* host_ctr;     // device address of host-mapped counters (may be null)
 };
@@ -382,20 +391,23 @@ struct JobList {
 // VTX_FLAG_STATS).
 hipError_t launch_cluster_cull(const OneJob& js, uint32_t grid, hipStream_t stream);
 hipError_t launch_cluster_cull(const JobList& js, uint32_t grid, hipStream_t stream);
-hipError_t launch_count(const OneJob& js, bool scene, uint32_t grid, int max_tiles, hipStream_t stream);
-hipError_t launch_count(const JobList& js, bool scene, uint32_t grid, int max_tiles, hipStream_t stream);
+// `phase` (resident scenes): kPhaseAll bins every visible cluster; a
+// two-pass frame runs count to resolve with kPhaseFront, then again with
+// kPhaseRest, whose resolve starts from the front pass's G-buffer.
+hipError_t launch_count(const OneJob& js, bool scene, int phase, uint32_t grid, int max_tiles, hipStream_t stream);
+hipError_t launch_count(const JobList& js, bool scene, int phase, uint32_t grid, int max_tiles, hipStream_t stream);
 // Layer starts of every tile list from the count kernel's histograms (jobs
 // with layers > 1; runs on the binning grid).
 hipError_t launch_layers(const OneJob& js, uint32_t grid, hipStream_t stream);
 hipError_t launch_layers(const JobList& js, uint32_t grid, hipStream_t stream);
-hipError_t launch_scatter(const OneJob& js, uint32_t grid, int max_tiles, hipStream_t stream);
-hipError_t launch_scatter(const JobList& js, uint32_t grid, int max_tiles, hipStream_t stream);
+hipError_t launch_scatter(const OneJob& js, int phase, uint32_t grid, int max_tiles, hipStream_t stream);
+hipError_t launch_scatter(const JobList& js, int phase, uint32_t grid, int max_tiles, hipStream_t stream);
 // The resolve is a main launch plus a small tail launch for the tiles whose
 // lists overflowed: `ovf` holds at least `grid` entries and ovf_n two zeroed
 // counters (both left zeroed again).
-hipError_t launch_resolve(const OneJob& js, int tile, uint32_t grid, bool count, unsigned long long* ovf,
+hipError_t launch_resolve(const OneJob& js, int tile, int phase, uint32_t grid, bool count, unsigned long long* ovf,
                           uint32_t* ovf_n, hipStream_t stream);
-hipError_t launch_resolve(const JobList& js, int tile, uint32_t grid, bool count, unsigned long long* ovf,
+hipError_t launch_resolve(const JobList& js, int tile, int phase, uint32_t grid, bool count, unsigned long long* ovf,
                           uint32_t* ovf_n, hipStream_t stream);
 // Supersampled render: output pixel (x, y) of W x H from its S x S samples
 // of the (S W) x (S H) images (channel means rounded half up, nearest

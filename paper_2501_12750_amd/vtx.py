@@ -30,6 +30,8 @@ VTX_MAX_SSAO_SAMPLES = 64
 VTX_SSAO_AUTO = -1
 VTX_FLAG_STATS = 1
 VTX_FLAG_TIMING = 2
+VTX_FLAG_ONE_PASS = 4
+VTX_FLAG_TWO_PASS = 8
 VTX_REP_BALL_AND_STICK, VTX_REP_VAN_DER_WAALS, VTX_REP_STICKS, VTX_REP_SAS = 0, 1, 2, 3
 VTX_SHADE_GLOSSY, VTX_SHADE_MATTE, VTX_SHADE_FLAT, VTX_SHADE_TOON = 0, 1, 2, 3
 
