@@ -246,15 +246,21 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
     if constexpr (kScene) {
         // Resident scene: each wave takes whole clusters (256 primitives of
         // one kind, so the kind is the same across the wave).  An atom
-        // cluster's four 64-atom quarters are loaded together and take the
-        // sphere-only path.
+        // cluster's 64-atom quarters take the sphere-only path.
         // Workgroup b takes positions [c0, c1) of the visible clusters in
         // depth-class order, so the workgroups run front to back.  A
         // two-pass frame splits the positions at the first 1 / kFrontShare.
         const SceneDev& S = src.S;
         const uint32_t stride = S.atom_clusters + S.bond_clusters;
         const uint32_t nvc = cls_end[kDepthBuckets - 1];
-        const uint32_t front = (nvc + kFrontShare - 1) / kFrontShare;
+        // the front pass ends at a depth-class boundary (the order inside a
+        // class is arbitrary), unless that would take more than half
+        uint32_t front = (nvc + kFrontShare - 1) / kFrontShare;
+        for (int k = 0; k < kDepthBuckets; ++k) {
+            if (cls_end[k] < front) continue;
+            if (cls_end[k] <= nvc / 2) front = cls_end[k];
+            break;
+        }
         const uint32_t lo = phase == kPhaseRest ? front : 0u, hi = phase == kPhaseFront ? front : nvc;
         const uint32_t cpw = (hi - lo + src.groups - 1) / src.groups;
         const uint32_t c0 = min(hi, lo + blk * cpw), c1 = min(hi, c0 + cpw);
@@ -274,19 +280,15 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
                 if (cluster_hidden(F, S, J.bb, c)) continue;
             }
             if (c < S.atom_clusters) {
-                float4 a[4];
-#pragma unroll
+                // one quarter at a time: holding more quarters' atoms spills
+                // registers, which costs more than the load latency it hides
                 for (int q = 0; q < 4; ++q) {
                     const uint32_t i = c * kCluster + (uint32_t)q * 64u + lane;
-                    a[q] = i < S.n_atoms ? S.xyzr[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const uint32_t i = c * kCluster + (uint32_t)q * 64u + lane;
+                    const float4 a = i < S.n_atoms ? S.xyzr[i] : make_float4(0.f, 0.f, 0.f, 0.f);
                     int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
                     double vx, vy, vz;
-                    to_view(F, a[q].x, a[q].y, a[q].z, vx, vy, vz);
-                    const double r = (double)atom_radius(F, a[q].w);
+                    to_view(F, a.x, a.y, a.z, vx, vy, vz);
+                    const double r = (double)atom_radius(F, a.w);
                     const bool vis = i < S.n_atoms && r > 0.0 && sphere_in_frustum(F, vx, vy, vz, r) &&
                                      sphere_rect_fast(F, vx, vy, vz, r, x0, y0, x1, y1);
                     if (vis) note_z(vz - r, fabs(vz) + r);

@@ -493,7 +493,7 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
         // Layered lists (resident scenes) run front to back by layer: once
         // every record from a layer on lies behind all block depths of the
         // tile, the rest of the list is culled whole, unread.
-        const uint32_t L = kTail || stats ? 1u : J.bb.layers;
+        const uint32_t L = kTail || stats || n <= (uint32_t)kChunk ? 1u : J.bb.layers;   // one chunk: nothing to stop
         if (L > 1 && wave == 0) {
             uint32_t zr = lane < (int)L ? ctr->layer_zlo[phase == kPhaseRest ? 1 : 0][lane] : 0x7F800000u;
 #pragma unroll

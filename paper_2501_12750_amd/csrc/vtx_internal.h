@@ -22,11 +22,12 @@ constexpr int kMaxSamples = 64;
 // files each cluster under one of kDepthBuckets depth classes (log spacing
 // from znear to zfar), and the tile lists keep the order of kLayers
 // consecutive ranges of binning workgroups.
-constexpr int kDepthBuckets = 32;
+constexpr int kDepthBuckets = 64;
 constexpr int kLayers = 32;
 // Occlusion pre-pass of resident scenes: the nearest 1 / kFrontShare of the
-// depth-ordered visible clusters is binned and resolved first; of the rest
-// only the clusters not behind its 16x16-pixel block depths are binned.
+// depth-ordered visible clusters (rounded up to whole depth classes) is binned
+// and resolved first; of the rest only the clusters not behind its 16x16-pixel
+// block depths are binned.
 constexpr int kFrontShare = 8;
 constexpr int kHzCell = 16;
 enum Phase : int { kPhaseAll = 0, kPhaseFront = 1, kPhaseRest = 2 };
