@@ -160,8 +160,6 @@ __device__ inline bool source_record(const Job& J, uint32_t src, PrimRec& pr) {
     return item_view<false>(J.F, fetch_src(J, src), pr, v, rr);
 }
 
-// Work block t of a job is that job's tile t; the launch's blocks are spread
-// over the XCDs in contiguous ranges.
 // Resolves tile t of job J, whose list holds n records from offset o
 // (kTail: the list overflowed and the tile is rebuilt from every binning
 // workgroup's visible list).  Re-arms the tile's count and cursor for the next
@@ -648,8 +646,11 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
     }
 }
 
-// Main launch: work block t of a job is that job's tile t (blocks spread
-// over the XCDs in contiguous ranges).  A tile whose list overflowed the bins
+// Main launch: work block t of a job is that job's tile t, so consecutive
+// tiles go to different XCDs (the dispatcher deals blocks round-robin).  The
+// costly tiles lie together, around the footprints of the nearest atoms:
+// contiguous tile ranges per XCD left one XCD with most of them (20 % longer
+// on the whole-cell frame).  A tile whose list overflowed the bins
 // is left to the tail launch: it is appended to `ovf` (job << 32 | tile).
 // kCount: the instantiation that can count fragments (jobs with
 // VTX_FLAG_STATS); the other one carries no counters.
@@ -658,7 +659,7 @@ template <int TS, class JS, bool kCount, bool kTwo>
 __global__ void __launch_bounds__(kBlock, kCount ? 1 : 7) k_resolve(JS js, unsigned long long* ovf, uint32_t* ovf_n,
                                                                      int phase) {
     uint32_t tu;
-    const int ji = js.find((uint32_t)xcd_contiguous(blockIdx.x, gridDim.x), tu);
+    const int ji = js.find(blockIdx.x, tu);
     if (ji < 0) return;
     const Job& J = js.job(ji);
     const uint32_t n = J.bb.tile_cnt[tu];
