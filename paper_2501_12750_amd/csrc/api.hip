@@ -576,8 +576,9 @@ void sample_kernel(const vtx_options& o, vtx::SampleKernel* K) {
         const double st = std::sqrt(1.0 - ct * ct);
         const double ph = two_pi * std::fmod(k * golden, 1.0);
         const double sc = (k + 1.0) / o.ssao_samples;
-        K->h[k] = make_float4((float)(st * std::cos(ph)), (float)(st * std::sin(ph)), (float)ct,
-                              (float)(0.1 + 0.9 * sc * sc));
+        const double len = (double)o.ssao_radius * (0.1 + 0.9 * sc * sc);   // offset length
+        K->h[k] = make_float4((float)(len * st * std::cos(ph)), (float)(len * st * std::sin(ph)), (float)(len * ct),
+                              (float)len);
     }
 }
 

@@ -143,12 +143,10 @@ __global__ void __launch_bounds__(kBlock) k_shade(JS js) {
                 zq[u] = INFINITY;
                 sz[u] = -INFINITY;   // no sample
                 if (k >= K.count) continue;
-                const float4 h = K.h[k];
-                const float sr = K.radius * h.w;
-                const float dx = fmaf(h.x, Tx, fmaf(h.y, Bx, h.z * nx));
-                const float dy = fmaf(h.x, Ty, fmaf(h.y, By, h.z * ny));
-                const float dz = fmaf(h.x, Tz, fmaf(h.y, Bz, h.z * nz));
-                const float Sx = fmaf(sr, dx, Px), Sy = fmaf(sr, dy, Py), Sz = fmaf(sr, dz, Pz);
+                const float4 h = K.h[k];   // offset in the (T, B, n) frame, scaled
+                const float Sx = fmaf(h.x, Tx, fmaf(h.y, Bx, fmaf(h.z, nx, Px)));
+                const float Sy = fmaf(h.x, Ty, fmaf(h.y, By, fmaf(h.z, ny, Py)));
+                const float Sz = fmaf(h.x, Tz, fmaf(h.y, Bz, fmaf(h.z, nz, Pz)));
                 if (!(Sz > F.znear)) continue;
                 float spx, spy;
                 if (F.proj == 0) {

@@ -66,7 +66,9 @@ __host__ __device__ inline float atom_radius(const Frame& F, float r) {
     return F.rep == 2 ? F.bond_radius : F.rep == 3 ? r + F.probe : r;
 }
 
-// SSAO sample set (hemisphere direction xyz, radius scale w).
+// SSAO sample set: h[k].xyz is sample k's offset in the frame (tangent,
+// bitangent, normal) of the surface point, already scaled to its length
+// (the radius times the sample's scale), h[k].w that length.
 struct SampleKernel {
     float4 h[kMaxSamples];
     int32_t count;
