@@ -493,6 +493,9 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
     F->inv_h2 = 2.0f / (float)H;
     F->znear = cam->znear;
     F->zfar = cam->zfar;
+    // depth classes from znear to zfar (resident scenes narrow them to the scene)
+    F->cls_z0 = cam->znear;
+    F->cls_k = (float)(vtx::kDepthBuckets / std::log2((double)cam->zfar / (double)cam->znear));
     F->bond_radius = o.bond_radius;
     F->proj = cam->projection;
     F->W = W;
@@ -627,7 +630,30 @@ struct vtx_scene {
     uint32_t* bonds = nullptr;
     std::vector<SceneFrame> frames;     // frames 1, 2, ... added after creation
     std::vector<void*> frame_blocks;    // their allocations
+    bool have_box = false;              // bounding box of the atoms at creation
+    double box_lo[3] = {}, box_hi[3] = {};
 };
+
+// Depth classes of a resident scene's render: log-spaced over the view depths
+// of the scene's bounding box at creation (trajectory frames and updated
+// positions may stray from it; classes only order the tile lists).
+static void scene_depth_classes(const vtx_scene* sc, Frame* F) {
+    if (!sc->have_box) return;
+    double zlo = INFINITY, zhi = -INFINITY;
+    for (int c = 0; c < 8; ++c) {
+        const double p[3] = {(c & 1) ? sc->box_hi[0] : sc->box_lo[0], (c & 2) ? sc->box_hi[1] : sc->box_lo[1],
+                             (c & 4) ? sc->box_hi[2] : sc->box_lo[2]};
+        const double z = (p[0] - F->eye[0]) * F->f[0] + (p[1] - F->eye[1]) * F->f[1] + (p[2] - F->eye[2]) * F->f[2];
+        zlo = std::min(zlo, z);
+        zhi = std::max(zhi, z);
+    }
+    zlo = std::max(zlo, (double)F->znear);
+    zhi = std::min(zhi, (double)F->zfar);
+    if (!(zlo > 0.0 && zhi > zlo * 1.001)) return;
+    F->cls_z0 = (float)zlo;
+    F->cls_k = (float)(vtx::kDepthBuckets / std::log2(zhi / zlo));
+}
+
 
 namespace {
 
@@ -1257,10 +1283,25 @@ int vtx_scene_create(vtx_context* ctx, const float* positions, const float* radi
     sc->S.atom_id = sc->atom_id;
     sc->S.bond_rec = sc->bond_rec;
     sc->S.vis_clusters = nullptr;   // per render, in the stream's scratch
+    uint32_t box_bits[6] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u};
     hipError_t e = vtx::scene_build(sc->pos, sc->rad, sc->bonds, na, nb, sc->S, sc->xyzr, sc->atom_id, sc->bond_rec,
-                                    sc->cluster_box, tmp, tmp_bytes, &m_valid, &n_bad, st);
+                                    sc->cluster_box, tmp, tmp_bytes, &m_valid, &n_bad, box_bits, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return bail(fail(VTX_EHIP, "building the scene failed: %s", hipGetErrorString(e)));
+    if (na > 0) {
+        auto from_ordered = [](uint32_t u) {
+            const uint32_t b = (u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u;
+            float f;
+            std::memcpy(&f, &b, sizeof f);
+            return (double)f;
+        };
+        for (int k = 0; k < 3; ++k) {
+            sc->box_lo[k] = from_ordered(box_bits[k]);
+            sc->box_hi[k] = from_ordered(box_bits[3 + k]);
+        }
+        sc->have_box = std::isfinite(sc->box_lo[0] + sc->box_lo[1] + sc->box_lo[2] + sc->box_hi[0] + sc->box_hi[1] +
+                                     sc->box_hi[2]);
+    }
     hipFree(tmp);
     sc->bad_bonds = n_bad;
     *out = sc;
@@ -1367,6 +1408,7 @@ int vtx_render_scene(vtx_scene* scene, const vtx_camera* cam, const vtx_options*
     Frame F;
     int rc = make_frame(cam, o, W, H, scene->n, scene->m, &F);
     if (rc) return rc;
+    scene_depth_classes(scene, &F);
     if (!depth || !id || !rgba) return fail(VTX_EINVAL, "rgba/depth/id outputs are NULL");
     int dev = 0;
     VTX_HIP(hipGetDevice(&dev));
@@ -1423,6 +1465,7 @@ int build_batch(vtx_context* ctx, const vtx_job* jobs, int32_t n_jobs, std::vect
         Frame F;
         int rc = make_frame(&j.camera, o, j.width, j.height, sc->n, sc->m, &F);
         if (rc) return fail(rc, "job %d: %s", i, g_error.c_str());
+        scene_depth_classes(sc, &F);
         vtx::SceneDev S;
         const float* pos = nullptr;
         scene_frame(sc, j.frame, &S, &pos);

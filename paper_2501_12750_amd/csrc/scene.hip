@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(kBlock) k_cluster_boxes(SceneDev S, float4* bo
 
 // Per frame: clusters whose bounding sphere meets the view volume, appended
 // to the region of S.vis_clusters of their depth class: the front depth of
-// the bounding sphere on a log scale from znear to zfar, kDepthBuckets
+// the bounding sphere on a log scale (Frame::cls_z0, cls_k), kDepthBuckets
 // classes.  A workgroup's clusters of one class (neighbours in Morton order)
 // take one contiguous run of that class, so a range of the class stays
 // compact in space.
@@ -208,8 +208,8 @@ __global__ void __launch_bounds__(kBlock) k_cluster_cull(JS js) {
                              1e-6 * (fabs((double)lo.x) + fabs((double)lo.y) + fabs((double)lo.z) + 1.0);
             if (sphere_in_frustum(F, vx, vy, vz, r)) {
                 // only the order of the lists depends on the class, never the image
-                const float zf = fmaxf((float)(vz - r), F.znear);
-                const float q = __log2f(zf / F.znear) * ((float)kDepthBuckets / __log2f(F.zfar / F.znear));
+                const float zf = fmaxf((float)(vz - r), F.cls_z0);
+                const float q = __log2f(zf / F.cls_z0) * F.cls_k;
                 cls = q >= 0.0f ? (int)fminf(q, (float)(kDepthBuckets - 1)) : 0;   // NaN: class 0
             }
         }
@@ -258,7 +258,8 @@ size_t scene_build_temp_bytes(uint64_t n, uint64_t m) {
 
 hipError_t scene_build(const float* pos, const float* rad, const uint32_t* bonds, uint64_t n, uint64_t m,
                        SceneDev& S, float4* xyzr, uint32_t* atom_id, uint4* bond_rec, float4* cluster_box,
-                       void* tmp, size_t tmp_bytes, uint32_t* m_valid, uint32_t* n_bad, hipStream_t stream) {
+                       void* tmp, size_t tmp_bytes, uint32_t* m_valid, uint32_t* n_bad, uint32_t* box_bits,
+                       hipStream_t stream) {
     const uint64_t mx = n > m ? n : m;
     char* p = static_cast<char*>(tmp);
     auto take = [&](size_t bytes) {
@@ -311,6 +312,9 @@ hipError_t scene_build(const float* pos, const float* rad, const uint32_t* bonds
     if (nc) k_cluster_boxes<<<grid_for((uint64_t)nc * 64), kBlock, 0, stream>>>(S, cluster_box);
     *m_valid = mv;
     *n_bad = nb;
+    // the atoms' bounding box (order-preserving bits, min xyz then max xyz),
+    // host memory, valid once the stream has reached this point
+    if ((e = hipMemcpyAsync(box_bits, box, 6 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
     return hipGetLastError();
 }
 

@@ -59,6 +59,9 @@ struct Frame {
     uint32_t outline_rgba;             // packed RGBA8 of outline pixels (alpha 255)
     int32_t clip_on;                   // a clip plane is set
     float clip[4];                     // the plane in view coordinates: kept where clip . (x, y, z, 1) >= 0
+    // depth class of a front depth z (resident scenes; orders the lists, never
+    // changes the image): floor(log2(z / cls_z0) * cls_k), clamped to the classes
+    float cls_z0, cls_k;
 };
 
 // Sphere radius of an atom of given radius r under the frame's representation.
@@ -305,7 +308,8 @@ struct SceneDev {
 size_t scene_build_temp_bytes(uint64_t n, uint64_t m);
 hipError_t scene_build(const float* pos, const float* rad, const uint32_t* bonds, uint64_t n, uint64_t m,
                        SceneDev& S, float4* xyzr, uint32_t* atom_id, uint4* bond_rec, float4* cluster_box,
-                       void* tmp, size_t tmp_bytes, uint32_t* m_valid, uint32_t* n_bad, hipStream_t stream);
+                       void* tmp, size_t tmp_bytes, uint32_t* m_valid, uint32_t* n_bad, uint32_t* box_bits,
+                       hipStream_t stream);
 hipError_t scene_update_positions(const float* pos, SceneDev& S, float4* xyzr, float4* cluster_box,
                                   hipStream_t stream);
 
