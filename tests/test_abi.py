@@ -131,3 +131,30 @@ def test_ssao_auto_is_accepted_without_a_context(vtx):
                              ctypes.byref(opt), 16, 16, ctypes.c_void_p(0x2000), ctypes.c_void_p(0x2000),
                              ctypes.c_void_p(0x2000), None)
     assert rc == vtx.VTX_EINVAL and "ssao_samples" in vtx.vtx_last_error()
+
+
+def test_constants_match_the_header(vtx, tmp_path):
+    """Every integer constant the header #defines has the same value in the
+    binding (the C compiler evaluates the header's side)."""
+    import re
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    names = re.findall(r"^#define (VTX_[A-Z0-9_]+) ", open(os.path.join(ROOT, "include", "vtx.h")).read(), re.M)
+    assert {"VTX_FLAG_ONE_PASS", "VTX_FLAG_TWO_PASS", "VTX_SSAO_AUTO"} <= set(names)
+    lines = ['#include <stdio.h>', '#include "vtx.h"', "int main(void) {"]
+    lines += [f'printf("{n} %lld\\n", (long long)({n}));' for n in names]
+    lines.append("return 0; }")
+    src = tmp_path / "consts.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "consts"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    got = {out[i]: int(out[i + 1]) for i in range(0, len(out), 2)}
+    missing = [n for n in names if not hasattr(vtx, n)]
+    assert not missing, f"constants missing from the binding: {missing}"
+    for n in names:
+        want = got[n] & 0xFFFFFFFF if getattr(vtx, n) >= 0 else got[n]
+        assert getattr(vtx, n) == want, n
