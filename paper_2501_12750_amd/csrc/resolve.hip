@@ -413,13 +413,28 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
         // footprints in its own slots; the workgroup resolves their
         // fragments, then refreshes the blocks under them before the next
         // sub-chunk is culled.
-        auto resolve_sorted = [&](uint32_t nk, int sub0, bool more) {
+        // zlo, bstep: the depth buckets' origin and width (bucket b holds cull
+        // depths from zlo + b * bstep on; bstep 0: one bucket)
+        auto resolve_sorted = [&](uint32_t nk, int sub0, bool more, float zlo, float bstep) {
             // All waves compute the same prefix (from the same block depths),
             // so they share one array, the chunk's prefix, which is no longer
             // needed: every wave writes it whole before reading it.
             uint32_t* const wp = pref;
             uint32_t rbase = 0;
             for (uint32_t sc = 0; rbase < nk; ++sc) {
+                if (sc > 0) {
+                    // every record from rbase on lies in rbase's bucket or a later
+                    // one: once that bucket's start (less a rounding margin) is
+                    // behind every block depth of the tile, all of them would be
+                    // culled.  Every wave reads the same LDS: a uniform decision.
+                    const unsigned long long in = __ballot(lane < kBuckets && bbase[lane] <= rbase);
+                    const float zb = fmaf((float)(63 - __clzll((long long)in)), bstep, zlo);
+                    const float bound = zb - 1e-5f * (fabsf(zlo) + fabsf(zb));
+                    uint32_t mt = 0;
+                    for (int b = lane; b < kHzBlocks; b += 64) mt = max(mt, hz[b]);
+                    mt = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(mt), 63);
+                    if (bound > 0.0f && __float_as_uint(bound) > mt) break;
+                }
                 // the front sub-chunk is small; records after it are mostly
                 // culled whole, so later sub-chunks are larger (fewer passes)
                 const int sub = sc == 0 ? sub0 : kLaterSub;
@@ -596,7 +611,7 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
             __syncthreads();
             if (keep) ord[bbase[bk] + atomicAdd(&bcnt[bk], 1u)] = (uint8_t)tid;
             __syncthreads();   // the order is in LDS
-            resolve_sorted(nk, sub, more);
+            resolve_sorted(nk, sub, more, zlo, span > 0.0f ? span * (1.0f / (float)kBuckets) : 0.0f);
             hz_set = true;
             __syncthreads();   // every wave is done with this chunk's records
             if (tid < kChunk / 4) reinterpret_cast<uint32_t*>(ord)[tid] = 0u;
