@@ -25,11 +25,12 @@ namespace {
 
 constexpr int kChunk = kBlock;
 constexpr unsigned kTailBlocks = 256;   // grid of the overflow (tail) launch
-constexpr int kBuckets = 32;      // depth buckets of the front-to-back record order
+constexpr int kBuckets = 64;      // depth buckets of the front-to-back record order
+static_assert(kBuckets <= 64, "one wave scans and searches the buckets");
 constexpr int kSortArea = 64;     // order a chunk when its kept records average more pixels than this
 constexpr int kKeptShift = 21;    // packed scan: footprint area (<= 256 * 64 * 64) below, kept count above
 constexpr uint32_t kAreaMask = (1u << kKeptShift) - 1u;
-constexpr int kLaterSub = 32;     // records per depth-ordered sub-chunk after the first (16, 32 or 64)
+constexpr int kLaterSub = 16;     // records per depth-ordered sub-chunk after the first (16, 32 or 64)
 static_assert(kBlock == kChunk, "one 64-slot window per wave in the order array");
 template <int TS>
 struct HzGrid {
@@ -435,8 +436,8 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
                     mt = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(mt), 63);
                     if (bound > 0.0f && __float_as_uint(bound) > mt) break;
                 }
-                // the front sub-chunk is small; records after it are mostly
-                // culled whole, so later sub-chunks are larger (fewer passes)
+                // later sub-chunks stay small too: the finer the steps, the
+                // sooner the bucket bound above ends the chunk
                 const int sub = sc == 0 ? sub0 : kLaterSub;
                 const int lg = sub == 16 ? 2 : sub == 32 ? 1 : 0;   // log2 of the lanes per record
                 const uint32_t i = (uint32_t)lane >> lg;
