@@ -132,36 +132,32 @@ __global__ void __launch_bounds__(kBlock) k_shade(JS js) {
         const float fpx = 0.5f * (float)F.H / F.tyf;
         const float osc = 0.5f * (float)F.H / F.hyf;
         float occ = 0.0f;
-        // samples are taken kBatch at a time: every address first, then
-        // the loads, then the tests in sample order, so the loads of a batch
-        // are in flight together
+        // Samples are taken kBatch at a time: every address first, then the
+        // loads, then the tests in sample order, so the loads of a batch are
+        // in flight together.  Branch-free: an invalid sample (past the count, behind the near
+        // plane, off the image) reads the pixel's own depth and is masked out
+        // (sz = -inf); entries of h past the count exist (zero).  Byte offsets
+        // into the depth image fit 32 bits (at most 4^2 x 7680 x 4320 pixels).
+        const float hw = 0.5f * (float)F.W, hh = 0.5f * (float)F.H;
+        const uint32_t own = (uint32_t)(y * F.W + x) << 2;
         for (int k0 = 0; k0 < K.count; k0 += kBatch) {
             float zq[kBatch], sz[kBatch];
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
                 const int k = k0 + u;
-                zq[u] = INFINITY;
-                sz[u] = -INFINITY;   // no sample
-                if (k >= K.count) continue;
                 const float4 h = K.h[k];   // offset in the (T, B, n) frame, scaled
                 const float Sx = fmaf(h.x, Tx, fmaf(h.y, Bx, fmaf(h.z, nx, Px)));
                 const float Sy = fmaf(h.x, Ty, fmaf(h.y, By, fmaf(h.z, ny, Py)));
                 const float Sz = fmaf(h.x, Tz, fmaf(h.y, Bz, fmaf(h.z, nz, Pz)));
-                if (!(Sz > F.znear)) continue;
-                float spx, spy;
-                if (F.proj == 0) {
-                    // hardware reciprocal (1 ulp): moves the sample by far less than
-                    // the 1e-3 px within which a pixel edge makes a sample unstable
-                    const float iz = fpx * __builtin_amdgcn_rcpf(Sz);
-                    spx = fmaf(Sx, iz, 0.5f * (float)F.W);
-                    spy = fmaf(-Sy, iz, 0.5f * (float)F.H);
-                } else {
-                    spx = fmaf(Sx, osc, 0.5f * (float)F.W);
-                    spy = fmaf(-Sy, osc, 0.5f * (float)F.H);
-                }
-                if (!(spx >= 0.0f && spx < (float)F.W && spy >= 0.0f && spy < (float)F.H)) continue;
-                zq[u] = depth[(size_t)(int)spy * F.W + (int)spx];
-                sz[u] = Sz;
+                // hardware reciprocal (1 ulp): moves the sample by far less than
+                // the 1e-3 px within which a pixel edge makes a sample unstable
+                const float sc = F.proj == 0 ? fpx * __builtin_amdgcn_rcpf(Sz) : osc;
+                const float spx = fmaf(Sx, sc, hw), spy = fmaf(-Sy, sc, hh);
+                const bool ok = k < K.count && Sz > F.znear && spx >= 0.0f && spx < (float)F.W && spy >= 0.0f &&
+                                spy < (float)F.H;
+                const uint32_t off = ok ? (uint32_t)((int)spy * F.W + (int)spx) << 2 : own;
+                zq[u] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(depth) + off);
+                sz[u] = ok ? Sz : -INFINITY;
             }
 #pragma unroll
             for (int u = 0; u < kBatch; ++u)
