@@ -153,8 +153,9 @@ __global__ void __launch_bounds__(kBlock) k_shade(JS js) {
                 // the 1e-3 px within which a pixel edge makes a sample unstable
                 const float sc = F.proj == 0 ? fpx * __builtin_amdgcn_rcpf(Sz) : osc;
                 const float spx = fmaf(Sx, sc, hw), spy = fmaf(-Sy, sc, hh);
-                const bool ok = k < K.count && Sz > F.znear && spx >= 0.0f && spx < (float)F.W && spy >= 0.0f &&
-                                spy < (float)F.H;
+                // & rather than &&: all tests evaluated, no branches per sample
+                const bool ok = (k < K.count) & (Sz > F.znear) & (spx >= 0.0f) & (spx < (float)F.W) & (spy >= 0.0f) &
+                                (spy < (float)F.H);
                 const uint32_t off = ok ? (uint32_t)((int)spy * F.W + (int)spx) << 2 : own;
                 zq[u] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(depth) + off);
                 sz[u] = ok ? Sz : -INFINITY;
