@@ -30,7 +30,7 @@ static_assert(kBuckets <= 64, "one wave scans and searches the buckets");
 constexpr int kSortArea = 64;     // order a chunk when its kept records average more pixels than this
 constexpr int kKeptShift = 21;    // packed scan: footprint area (<= 256 * 64 * 64) below, kept count above
 constexpr uint32_t kAreaMask = (1u << kKeptShift) - 1u;
-constexpr int kLaterSub = 16;     // records per depth-ordered sub-chunk after the first (16, 32 or 64)
+constexpr int kLaterSub = 8;     // records per depth-ordered sub-chunk after the first (8, 16, 32 or 64)
 static_assert(kBlock == kChunk, "one 64-slot window per wave in the order array");
 template <int TS>
 struct HzGrid {
@@ -439,7 +439,7 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
                 // later sub-chunks stay small too: the finer the steps, the
                 // sooner the bucket bound above ends the chunk
                 const int sub = sc == 0 ? sub0 : kLaterSub;
-                const int lg = sub == 16 ? 2 : sub == 32 ? 1 : 0;   // log2 of the lanes per record
+                const int lg = sub == 4 ? 4 : sub == 8 ? 3 : sub == 16 ? 2 : sub == 32 ? 1 : 0;   // log2 of the lanes per record
                 const uint32_t i = (uint32_t)lane >> lg;
                 const bool real = rbase + i < nk;
                 uint32_t rect = 0;
@@ -459,7 +459,9 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
                     for (int by = by0 + (lane & ((1 << lg) - 1)); by <= by1; by += 1 << lg)
                         for (int bx = bx0; bx <= bx1; ++bx) m = max(m, hz[by * (TS / 4) + bx]);
                 if (lg >= 1) m = max(m, (uint32_t)__shfl_xor((int)m, 1));
-                if (lg == 2) m = max(m, (uint32_t)__shfl_xor((int)m, 2));
+                if (lg >= 2) m = max(m, (uint32_t)__shfl_xor((int)m, 2));
+                if (lg >= 3) m = max(m, (uint32_t)__shfl_xor((int)m, 4));
+                if (lg >= 4) m = max(m, (uint32_t)__shfl_xor((int)m, 8));
                 const bool live = real && !(sc > 0 && __float_as_uint(zcull) > m && zcull > 0.0f);
                 // blocks under the live records (their union rectangle)
                 const uint32_t ux0 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(live ? 255u - bx0 : 0u), 63);
@@ -569,9 +571,9 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
             // buckets and resolve them in sub-chunks, refreshing the block
             // depths in between, so records behind the first layers are
             // culled whole before any of their pixels is tested.  Sub-chunks
-            // hold about two tiles' worth of footprint: 16 records when they
-            // average 64 pixels or more, else 32.
-            const int sub = atot >= 64u * nk ? 16 : 32;
+            // are small (8 records): the block depths are refreshed, and the
+            // bucket bound can end the chunk, after every few records.
+            const int sub = atot >= 64u * nk ? 8 : 32;
             const bool sorted = !stats && nk > (uint32_t)sub && atot > (uint32_t)kSortArea * nk;
             if (!sorted) {
                 resolve_fragments();
