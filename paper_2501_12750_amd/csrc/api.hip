@@ -152,6 +152,7 @@ void bins_free(Bins* b) {
     hipFree(b->bb.tile_off);
     hipFree(b->bb.tile_fill);
     hipFree(b->bb.layer_off);
+    hipFree(b->bb.layer_sum);
     hipFree(b->bb.hz16);
     hipFree(b->bb.vis_src);
     hipFree(b->bb.vis_rect);
@@ -314,6 +315,8 @@ int ensure_bins(Workspace* ws, Bins* b, int T, uint64_t nprim, uint32_t groups, 
         if ((rc = grow(&b->bb.tile_off, c2, (size_t)T, st, "tile offsets"))) return rc;
         if ((rc = grow(&b->bb.tile_fill, c3, (size_t)T * vtx::kLayers, st, "tile cursors"))) return rc;
         if ((rc = grow(&b->bb.layer_off, c4, (size_t)T * vtx::kLayers, st, "tile layer starts"))) return rc;
+        size_t c5 = b->tiles_cap * vtx::kLayers;
+        if ((rc = grow(&b->bb.layer_sum, c5, (size_t)T * vtx::kLayers, st, "tile layer totals"))) return rc;
         b->tiles_cap = (size_t)T;
         b->dirty = true;
     }
@@ -321,6 +324,7 @@ int ensure_bins(Workspace* ws, Bins* b, int T, uint64_t nprim, uint32_t groups, 
         // fresh or abandoned scratch: zero what every frame otherwise leaves zeroed
         VTX_HIP(vtx::launch_zero(b->bb.tile_cnt, b->tiles_cap, st));
         VTX_HIP(vtx::launch_zero(b->bb.tile_fill, b->tiles_cap * vtx::kLayers, st));
+        VTX_HIP(vtx::launch_zero(b->bb.layer_sum, b->tiles_cap * vtx::kLayers, st));
         VTX_HIP(vtx::launch_zero(reinterpret_cast<uint32_t*>(b->bb.ctr), sizeof(Counters) / sizeof(uint32_t), st));
         b->dirty = false;
     }
@@ -1212,9 +1216,9 @@ size_t vtx_frame_scratch_bytes(int32_t W, int32_t H, int64_t n_atoms, int64_t n_
     vtx::bin_grid(nprim, &groups, &chunk);
     uint64_t cap = nprim / 2;
     if (cap < kMinCapacity) cap = kMinCapacity;
-    // tile counts and offsets, per-layer cursors and starts, visible lists,
+    // tile counts and offsets, per-layer cursors, starts and totals, visible lists,
     // histograms, lists, visible clusters per depth class, cell depths, counters
-    return (size_t)(T * 16 + T * 8 * vtx::kLayers + (uint64_t)groups * chunk * (sizeof(uint32_t) + sizeof(uint2)) +
+    return (size_t)(T * 16 + T * 12 * vtx::kLayers + (uint64_t)groups * chunk * (sizeof(uint32_t) + sizeof(uint2)) +
                     (uint64_t)groups * T * 4 + cap * sizeof(uint2) +
                     scene_clusters(n_atoms, n_bonds) * 4 * vtx::kDepthBuckets +
                     (uint64_t)((W + vtx::kHzCell - 1) / vtx::kHzCell) * ((H + vtx::kHzCell - 1) / vtx::kHzCell) * 4 +

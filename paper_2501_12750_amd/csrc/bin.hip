@@ -324,10 +324,15 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
     }
     __syncthreads();
     uint32_t* row = hist_out + (size_t)blk * T;
+    // layered lists: per-layer totals (the layer kernel turns them into list
+    // starts and tile totals); otherwise the tile totals directly
+    uint32_t* const tot = kScene && J.bb.layers > 1
+                              ? J.bb.layer_sum + (size_t)layer_of(blk, J.bb.groups, J.bb.layers) * T
+                              : tile_cnt;
     for (int t = tid; t < T; t += kBinThreads) {
         const uint32_t h = hist[t];
         row[t] = h;
-        if (h) atomicAdd(&tile_cnt[t], h);
+        if (h) atomicAdd(&tot[t], h);
     }
     if (tid == 0) {
         if (kScene && J.bb.layers > 1 && wg_zlo != 0x7F800000u)
@@ -340,12 +345,13 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
 }
 
 // Layer starts of the tile lists (jobs with layers > 1).  For tile t,
-// layer_off[g][t] is the number of t's entries that the workgroups of layers
-// before g contribute: the exclusive prefix over g of the histogram rows
-// summed per layer.  With P the power of two >= layers, work block b takes
-// the (1024 / P)-tile blocks b, b + groups, ...; thread (g, i) = (tid / W,
-// tid % W) sums layer g's rows at tile i (loads coalesced along i), and the
-// prefix over g goes through LDS.
+// layer_off[g][t] is the number of t's entries in the layers before g (the
+// exclusive prefix over g of the count kernel's per-layer totals), and
+// tile_cnt[t] the list's length; the totals are re-zeroed for the next frame.
+// With P the power of two >= layers, work block b takes the (1024 / P)-tile
+// blocks b, b + groups, ...; thread (g, i) = (tid / W, tid % W) holds layer
+// g's total of tile i (loads coalesced along i), and the prefix over g goes
+// through LDS.
 template <class JS>
 __global__ void __launch_bounds__(kBinThreads) k_layers(JS js) {
     static_assert(kBinThreads == 1024 && kLayers <= 32, "tile blocks of 1024 / P tiles, P <= 32");
@@ -357,24 +363,27 @@ __global__ void __launch_bounds__(kBinThreads) k_layers(JS js) {
     const uint32_t L = J.bb.layers, groups = J.bb.groups;
     if (L <= 1) return;
     const uint32_t T = (uint32_t)(J.F.tiles_x * J.F.tiles_y);
-    const uint32_t* __restrict__ const hist = J.bb.hist;
+    uint32_t* __restrict__ const sum = J.bb.layer_sum;
     uint32_t* __restrict__ const loff = J.bb.layer_off;
     const uint32_t lsh = 32u - (uint32_t)__builtin_clz(L - 1u);   // P = 1 << lsh >= L (L <= kLayers)
     const uint32_t wsh = 10u - lsh, W = 1u << wsh;                  // tiles per block: kBinThreads / P
     const uint32_t g = threadIdx.x >> wsh, i = threadIdx.x & (W - 1u);
-    const uint32_t b0 = g < L ? layer_first(g, groups, L) : 0u, b1 = g < L ? layer_first(g + 1, groups, L) : 0u;
     for (uint32_t tb = blk; tb * W < T; tb += groups) {   // trip count uniform over the workgroup
         const uint32_t t = tb * W + i;
-        uint32_t sum = 0;
-        if (t < T) {
-#pragma unroll 8
-            for (uint32_t b = b0; b < b1; ++b) sum += hist[(size_t)b * T + t];
+        const bool mine = t < T && g < L;
+        uint32_t v = 0;
+        if (mine) {
+            v = sum[(size_t)g * T + t];
+            sum[(size_t)g * T + t] = 0u;
         }
-        part[g * (W + 1u) + i] = sum;
+        part[g * (W + 1u) + i] = v;
         __syncthreads();
         uint32_t pre = 0;
         for (uint32_t h = 0; h < g; ++h) pre += part[h * (W + 1u) + i];
-        if (t < T && g < L) loff[(size_t)g * T + t] = pre;
+        if (mine) {
+            loff[(size_t)g * T + t] = pre;
+            if (g == L - 1u) J.bb.tile_cnt[t] = pre + v;
+        }
         __syncthreads();   // part is rewritten by the next tile block
     }
 }

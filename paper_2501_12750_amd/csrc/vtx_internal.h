@@ -270,6 +270,8 @@ struct BinBuffers {
     uint64_t* tile_off;     // T
     uint32_t* tile_fill;    // layers * T: next free entry of each layer's run of each tile list
     uint32_t* layer_off;    // layers * T: start of each layer's run within each tile list
+    uint32_t* layer_sum;    // layers * T: entries of each layer in each tile list, added up by the
+                            // count kernel, read and re-zeroed by the layer kernel
     uint32_t* vis_src;      // groups * chunk: source index of each visible primitive
     uint2* vis_rect;        // groups * chunk, pixel rectangle packed (x0 | y0 << 16, x1 | y1 << 16)
     uint32_t* vis_cnt;      // groups: visible primitives of each workgroup
