@@ -3,20 +3,25 @@
 // "Meshless Representations": ray-casting evaluates the implicit equation of
 // each primitive, which makes the display pixel-exact).
 //
-// One workgroup owns one tile.  The tile's list holds 32-byte view-space
-// records with the footprint clipped to the tile, so it is read contiguously
-// with no gathers.  Records are staged through LDS 256 at a time; their
-// footprints' pixel counts are prefix-summed and the resulting (record,
-// pixel) fragments are dealt to the 256 lanes round-robin, so the load is
-// balanced whatever the mix of tiny and large primitives, and lanes of one
-// wave work on neighbouring pixels of the same few records.  A hit is folded into the tile's depth
-// buffer in LDS with one 64-bit atomicMin of the packed key
-// (float bits of z) << 32 | id: positive floats order like their bit
-// patterns, so the minimum key is the nearest hit and equal depths go to the
-// smaller id, in any order of evaluation.  Depth early-outs skip a record
-// whose nearest possible depth lies behind everything the 4x4-pixel blocks
-// under its footprint already hold, and a fragment whose pixel already holds
-// a nearer hit.
+// One workgroup owns one tile.  The tile's list holds 8-byte entries (source
+// index, footprint clipped to the tile); each chunk of 256 entries is turned
+// back into view-space records from the sources and staged in LDS.  The
+// records' footprint pixel counts are prefix-summed and the resulting
+// (record, pixel) fragments are dealt to the 256 lanes round-robin, so the
+// load is balanced whatever the mix of tiny and large primitives, and lanes of
+// one wave work on neighbouring pixels of the same few records.  A hit is
+// folded into the tile's depth buffer in LDS with one 64-bit atomicMin of the
+// packed key (float bits of z) << 32 | id: positive floats order like their
+// bit patterns, so the minimum key is the nearest hit and equal depths go to
+// the smaller id, in any order of evaluation.
+//
+// Depth early-outs, all conservative (statistics frames switch them off):
+// a record whose nearest possible depth lies behind everything the 4x4-pixel
+// blocks under its footprint hold is dropped; a fragment whose pixel holds a
+// nearer hit is skipped; chunks of large footprints run front to back in
+// small sub-chunks and end once the depth bucket they reached lies behind the
+// whole tile; a resident scene's list, ordered front to back by layers, ends
+// once every layer left lies behind the whole tile.
 #include "prims.h"
 
 namespace vtx {
@@ -30,7 +35,7 @@ static_assert(kBuckets <= 64, "one wave scans and searches the buckets");
 constexpr int kSortArea = 64;     // order a chunk when its kept records average more pixels than this
 constexpr int kKeptShift = 21;    // packed scan: footprint area (<= 256 * 64 * 64) below, kept count above
 constexpr uint32_t kAreaMask = (1u << kKeptShift) - 1u;
-constexpr int kLaterSub = 8;     // records per depth-ordered sub-chunk after the first (8, 16, 32 or 64)
+constexpr int kLaterSub = 8;      // records per depth-ordered sub-chunk after the first (4 to 64, a power of 2)
 static_assert(kBlock == kChunk, "one 64-slot window per wave in the order array");
 template <int TS>
 struct HzGrid {
