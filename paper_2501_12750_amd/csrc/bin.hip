@@ -5,20 +5,26 @@
 // Representations").  Here the quad's role, a conservative footprint, becomes
 // an exact tile rectangle per primitive, and the rasterizer becomes a
 // counting sort of (tile, primitive) pairs:
-//   count    G workgroups each own a contiguous run of primitives: view
-//            transform (FP64), culling, footprint rectangle, a compacted
-//            per-workgroup list of the visible ones, and a tile histogram
-//            in LDS; the histogram row is stored and its non-zero entries are
-//            added to the global tile counts (one atomic per touched tile);
+//   count    G workgroups each own a contiguous run of primitives (resident
+//            scenes: of the visible clusters in depth-class order, so the
+//            workgroups run front to back): view transform (FP64), culling,
+//            footprint rectangle, a compacted per-workgroup list of the
+//            visible ones, and a tile histogram in LDS; the histogram row is
+//            stored and its non-zero entries are added to the tile totals
+//            (resident scenes: to the totals of the workgroup's layer, 1/32
+//            of the workgroups), one atomic per touched tile;
+//   layers   resident scenes: the per-layer totals become the start of each
+//            layer's run in every tile list, and the tile totals;
 //   scatter  each workgroup rebuilds the exclusive prefix sum of the tile
 //            counts (list offsets), reserves, per touched tile, one run of the
-//            tile's list (one atomic), then places its primitives with LDS
-//            atomics: 8 bytes per (primitive, tile), the source index and the
-//            footprint clipped to the tile.  The resolve rebuilds each
-//            record from its source, so the view-space record is never
-//            written out.
+//            tile's list inside its layer's run (one atomic), then places its
+//            primitives with LDS atomics: 8 bytes per (primitive, tile), the
+//            source index and the footprint clipped to the tile.  The resolve
+//            rebuilds each record from its source, so the view-space record
+//            is never written out.
 // So the global atomics scale with (workgroup, touched tile) pairs rather
-// than with (primitive, tile) pairs.  Lists that would not fit the bin
+// than with (primitive, tile) pairs, and a resident scene's tile lists run
+// roughly front to back.  Lists that would not fit the bin
 // capacity are left empty; the resolve pass then finds those tiles' primitives
 // in the per-workgroup visible lists, so every frame is exact whatever the
 // capacity.

@@ -5,7 +5,8 @@
 // At creation the atoms are reordered along a Morton curve of their
 // positions and stored as one xyzr float4 stream, so that every run of 256
 // stored atoms (a cluster) is compact in space: a cluster's bounding box is
-// tested against the frustum once per frame, and the atoms a binning
+// tested against the frustum once per frame (which also files it under a
+// depth class, for front-to-back binning), and the atoms a binning
 // workgroup handles fall on few screen tiles.  Each stored atom keeps its
 // original index, which is the id the renderer reports, so a resident scene
 // renders exactly what the same arrays render through vtx_render.  Bonds
