@@ -63,8 +63,9 @@ extern "C" {
 #define VTX_FLAG_TIMING 2u       /* vtx_render records a HIP event before and after
                                     each kernel, read back by vtx_read_timings */
 #define VTX_FLAG_TWO_PASS 8u     /* resident scenes: occlusion pre-pass.  The nearest
-                                    eighth of the visible clusters (by depth) is
-                                    binned and resolved first; of the rest, only
+                                    eighth of the visible clusters (by depth, rounded
+                                    up to whole depth classes) is binned and
+                                    resolved first; of the rest, only
                                     clusters whose bounding sphere is not behind the
                                     depths of every 16x16-pixel cell under it are
                                     binned, and resolved on top.  The image is the
