@@ -442,16 +442,24 @@ def test_ssao_vanishing_radius_gives_one(oracle):
     assert np.all(res["ao"] == 1.0)
 
 
-@pytest.mark.parametrize("K", [1, 2])
-def test_ssao_step_occlusion_from_geometry(oracle, K):
-    """Far disk at depth 20 (world z = 0), near disk at depth 19 (world z = 1)
-    whose edge crosses the image.  The normal is (0, 0, -1) in view space; for
+# (gap between the disks, weight of an occluding sample): the range weight is
+# the smoothstep 3x^2 - 2x^3 of x = R / gap, clamped to [0, 1]; with R = 1.5,
+# a gap of 1 saturates it (x = 3/2 -> 1), a gap of 4.5 gives x = 1/3 ->
+# 3/9 - 2/27 = 7/27, a gap of 2 gives x = 3/4 -> 27/16 - 27/32 = 27/32
+SSAO_GAPS = [(1.0, Fraction(1)), (4.5, Fraction(7, 27)), (2.0, Fraction(27, 32))]
+
+
+@pytest.mark.parametrize("gap,wgt", SSAO_GAPS, ids=["saturated", "third", "three_quarters"])
+@pytest.mark.parametrize("K", [1, 2, 16])
+def test_ssao_step_occlusion_from_geometry(oracle, K, gap, wgt):
+    """Far disk at depth 20 (world z = 0), near disk at depth 20 - gap whose
+    edge crosses the image.  The normal is (0, 0, -1) in view space; for
     it the basis is T = (1, 0, 0), B = (0, -1, 0) (derived by hand from the
     branchless construction with sign = -1, a = 1/2).  A sample with
     hemisphere direction h and scale s lands R s (h.x, -h.y) to the right/up in
     the view plane and R s h.z nearer to the camera; it is occluded iff its
-    pixel lies on the near disk and 19 <= 20 - R s h.z - bias, with weight
-    smoothstep(R / 1)."""
+    pixel lies on the near disk and 20 - gap <= 20 - R s h.z - bias, and then
+    weighs the value the range falloff takes at R / gap (given above)."""
     W, H, hh = 64, 48, 4.0
     R, bias = 1.5, 0.05
     cam = ortho(eye=(0.0, 0.0, 20.0), target=(0.0, 0.0, 0.0), half_h=hh)
@@ -460,7 +468,7 @@ def test_ssao_step_occlusion_from_geometry(oracle, K):
     near_r = 6.0
     # both disks have the bond radius (6 A): the far one is centred on the
     # axis, the near one 7 A to the right, so its edge crosses the far disk
-    sc = _cap_scene([far, (near_c[0], near_c[1], 1.0, scenes.pack_rgba(90, 90, 90))])
+    sc = _cap_scene([far, (near_c[0], near_c[1], gap, scenes.pack_rgba(90, 90, 90))])
     opts = scenes.Options(bond_radius=near_r, ssao_samples=K, ssao_radius=R, ssao_bias=bias)
     res = oracle.render(sc, cam, opts, W, H)
     scale = (H / 2) / hh
@@ -476,7 +484,7 @@ def test_ssao_step_occlusion_from_geometry(oracle, K):
         ph = 2 * math.pi * ((k * 0.6180339887498949) % 1.0)
         hk.append((float(np.float32(st * math.cos(ph))), float(np.float32(st * math.sin(ph))),
                    float(np.float32(ct)), float(np.float32(0.1 + 0.9 * ((k + 1) / K) ** 2))))
-    wgt = 1.0    # smoothstep(R / |20 - 19|) with R >= 1
+    w = float(wgt)
     exp = np.ones((H, W))
     for (hx, hy, hz, s) in hk:
         sx = X + R * s * hx
@@ -488,8 +496,8 @@ def test_ssao_step_occlusion_from_geometry(oracle, K):
         cyq = (H / 2 - qy - 0.5) / scale
         q_near = (cxq - near_c[0]) ** 2 + (cyq - near_c[1]) ** 2 <= near_r ** 2
         inside = (qx >= 0) & (qx < W) & (qy >= 0) & (qy < H)
-        occl = inside & q_near & (19.0 <= sz - bias)
-        exp -= np.where(occl, wgt / K, 0.0)
+        occl = inside & q_near & (20.0 - gap <= sz - bias)
+        exp -= np.where(occl, w / K, 0.0)
     stable = res["ssao_unstable"] == 0
     m = on_far & stable
     assert m.sum() > 100
@@ -576,6 +584,48 @@ def test_flat_and_matte_shading_give_the_albedo(oracle):
     glossy = oracle.render(sc, cam, scenes.Options(shading=0), W, H)
     assert np.all((matte["rgba"][hit] & 255) <= 200)
     assert (glossy["rgba"][16, 16] & 255) == 255
+
+
+def test_glossy_highlight_follows_the_lobe(oracle):
+    """Glossy shading of an orthographic sphere away from saturation.  With
+    the headlight (L = V) the reflected direction makes R.V = 2 (n.V)^2 - 1,
+    and on an orthographic sphere n.V = sqrt(1 - rho^2 / r^2) at a pixel
+    centre rho away from the centre's projection, so the highlight
+    0.25 max(0, 1 - 2 rho^2 / r^2)^32 is an exact rational on the pixel
+    lattice; the diffuse part albedo (0.2 + 0.8 n.V) is evaluated to 50
+    digits.  A dark albedo keeps every channel below 1, so the highlight is
+    seen unclipped over the whole lobe (n.V from 1 down to 1/sqrt(2))."""
+    W = H = 64
+    hh = 8
+    scale = Fraction(H, 2) / Fraction(hh)
+    cx, cy, r = Fraction(5, 32), Fraction(-3, 16), Fraction(7)
+    cam = ortho(eye=(0.0, 0.0, 30.0), target=(0.0, 0.0, 0.0), half_h=float(hh))
+    rgb = (60, 40, 20)
+    alb = scenes.pack_rgba(*rgb)
+    sc = make_scene([(float(cx), float(cy), 0.0)], [float(r)], colors=[alb])
+    res = oracle.render(sc, cam, scenes.Options(shading=0), W, H)
+    inside, rho2 = _ortho_disk(W, H, scale, cx, cy, r)
+    assert np.array_equal(res["id"] == 0, inside)
+    checked = lobe = 0
+    for j, i in np.argwhere(inside):
+        u = rho2[j, i] / (r * r)
+        spec = Fraction(1, 4) * max(Fraction(0), 1 - 2 * u) ** 32
+        nv = mpmath.sqrt(mpmath.mpf(1 - u.numerator / mpmath.mpf(u.denominator)))
+        want = []
+        for ch in rgb:
+            c = mpmath.mpf(ch) / 255 * (mpmath.mpf(1) / 5 + mpmath.mpf(4) / 5 * nv) + \
+                mpmath.mpf(spec.numerator) / spec.denominator
+            v = 255 * c + mpmath.mpf(1) / 2
+            assert c < 1
+            if abs(v - mpmath.nint(v)) < mpmath.mpf(10) ** -9:
+                break      # on a rounding boundary: FP64 may round either way
+            want.append(int(mpmath.floor(v)))
+        else:
+            got = int(res["rgba"][j, i])
+            assert [(got >> (8 * k)) & 255 for k in range(3)] == want, (i, j, float(nv))
+            checked += 1
+            lobe += spec > Fraction(1, 255)
+    assert checked > 400 and lobe > 20
 
 
 def test_toon_bands_are_rings_of_the_disk(oracle):
