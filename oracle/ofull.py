@@ -348,7 +348,9 @@ def gbuffer(scene, cam, opts, W, H, window=None):
         if c is not None:
             alb = np.where(c["half_b"], scene.colors[ib], scene.colors[ia]).astype(np.uint32)
             add(c, N + b, alb)
-    return _resolve(rec, P, (h, w), (s, u, f))
+    out = _resolve(rec, P, (h, w), (s, u, f))
+    out["view"] = (cam, W, H, window)
+    return out
 
 
 def _resolve(rec, P, shape, basis):
@@ -467,11 +469,15 @@ def _smoothstep01(x):
 
 
 def ssao(cam, W, H, window, Pv, Nv, hit, depth_buf, depth_win, K, R, bias,
-         edge_px=1e-3, depth_rel=1e-5):
+         edge_px=1e-3, depth_rel=1e-5, ambiguous=None):
     """Ambient occlusion at the pixels of ``window``.
 
     Pv, Nv: (n, 3) view-space position and unit normal per pixel; hit: (n,) bool.
     depth_buf: view depth (+inf background) over ``depth_win`` = (x0, y0, w, h).
+    ambiguous: optional bool mask over depth_win of pixels whose visible
+    primitive is not unique (several accepted answers); a sample that reads
+    one counts as unstable, since a correct G-buffer may hold another depth
+    there.
     Returns (ao (n,), unstable (n,) count of samples whose outcome may flip,
     outside (n,) count of on-screen samples that fell outside depth_buf).
     """
@@ -523,6 +529,10 @@ def ssao(cam, W, H, window, Pv, Nv, hit, depth_buf, depth_win, K, R, bias,
         wgt = np.where(np.isfinite(zq), wgt, 0.0)
         occ_sum += np.where(hit & occ, wgt, 0.0)
         margin = np.abs(zq - thr) <= depth_rel * np.abs(S[:, 2])
+        if ambiguous is not None:
+            amb = np.zeros(n, dtype=bool)
+            amb[ok] = ambiguous[iy[ok], ix[ok]]
+            margin = margin | amb
         unstable += (hit & ((front & edge) | near_edge | (ok & margin))).astype(np.int32)
         outside += (hit & onscreen & ~inbuf).astype(np.int32)
     ao = np.where(hit, 1.0 - occ_sum / K, 1.0)
@@ -595,7 +605,7 @@ def outline(W, H, window, z, depth_buf, depth_win, t, depth_rel=1e-5):
 
 
 def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=None, depth_win=None,
-                  edge_px=1e-3, depth_rel=1e-5):
+                  edge_px=1e-3, depth_rel=1e-5, ambiguous=None):
     """Deferred pass: SSAO then shading over ``window``.
 
     z, normal_view, albedo cover the window; depth_buf/depth_win give the depth
@@ -611,7 +621,7 @@ def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=Non
         depth_buf, depth_win = z, window
     ao, uns, outside = ssao(cam, W, H, window, Pv, Nv, hit, depth_buf, depth_win,
                             int(opts.ssao_samples), float(opts.ssao_radius), float(opts.ssao_bias),
-                            edge_px=edge_px, depth_rel=depth_rel)
+                            edge_px=edge_px, depth_rel=depth_rel, ambiguous=ambiguous)
     Vv = -view_dir(cam, W, H, window)
     fog = (float(getattr(opts, "fog_start", 0.0)), float(getattr(opts, "fog_end", 0.0)),
            int(getattr(opts, "fog_color", 0)))
@@ -670,6 +680,14 @@ def render(scene, cam, opts, W, H, window=None, halo=0, edge_px=1e-3, depth_rel=
     sl = (slice(y0 - gy0, y0 - gy0 + h), slice(x0 - gx0, x0 - gx0 + w))
     inner = {k: (v[sl] if isinstance(v, np.ndarray) and v.ndim >= 2 else v) for k, v in g.items()}
     sh = shade_gbuffer(cam, opts, W, H, window, inner["z"], inner["normal_view"], inner["albedo"],
-                       depth_buf=g["z"], depth_win=gwin, edge_px=edge_px, depth_rel=depth_rel)
+                       depth_buf=g["z"], depth_win=gwin, edge_px=edge_px, depth_rel=depth_rel,
+                       ambiguous=ambiguous_pixels(g))
     inner.update(sh)
+    inner["view"] = (cam, W, H, window)
     return inner
+
+
+def ambiguous_pixels(g):
+    """Pixels of a G-buffer whose visible primitive is not unique: the
+    accept set holds several primitives, or a grazing hit and background."""
+    return (g["acc_n"] + g["acc_bg"].astype(np.int32)) > 1

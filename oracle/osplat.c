@@ -106,27 +106,59 @@ static int os_project(const os_cam* c, const double* p, double* px, double* py, 
     return 1;
 }
 
-/* Conservative pixel rectangle of an axis-aligned box; returns 0 if culled. */
+/* Conservative pixel rectangle of an axis-aligned box; returns 0 if culled.
+   Only points with view depth >= zc = znear (1 - 2 tau) can hold a hit (or a
+   grazing candidate), so a perspective box that reaches behind that plane is
+   bounded by the projections of its corners in front of it and of the points
+   where its edges cross it: the vertices of the box cut by the plane. */
 static int os_box_rect(const os_cam* c, const double* lo, const double* hi, int* rx0, int* ry0, int* rx1, int* ry1) {
     double mnx = INFINITY, mny = INFINITY, mxx = -INFINITY, mxy = -INFINITY;
     double zmin = INFINITY, zmax = -INFINITY;
-    int all_front = 1;
+    const double zc = c->znear * (1.0 - 2 * OS_TAU);
+    double cp[8][3], cz[8];
     for (int corner = 0; corner < 8; ++corner) {
-        double p[3] = {(corner & 1) ? hi[0] : lo[0], (corner & 2) ? hi[1] : lo[1], (corner & 4) ? hi[2] : lo[2]};
-        double px, py, zv;
-        if (!os_project(c, p, &px, &py, &zv)) all_front = 0;
-        else {
-            if (px < mnx) mnx = px;
-            if (px > mxx) mxx = px;
-            if (py < mny) mny = py;
-            if (py > mxy) mxy = py;
-        }
-        if (zv < zmin) zmin = zv;
-        if (zv > zmax) zmax = zv;
+        double* p = cp[corner];
+        p[0] = (corner & 1) ? hi[0] : lo[0];
+        p[1] = (corner & 2) ? hi[1] : lo[1];
+        p[2] = (corner & 4) ? hi[2] : lo[2];
+        double r[3] = {p[0] - c->e[0], p[1] - c->e[1], p[2] - c->e[2]};
+        cz[corner] = dot3(r, c->f);
+        if (cz[corner] < zmin) zmin = cz[corner];
+        if (cz[corner] > zmax) zmax = cz[corner];
     }
-    if (zmax < c->znear * (1.0 - 2 * OS_TAU)) return 0;
+    if (zmax < zc) return 0;
     if (zmin > c->zfar * (1.0 + 2 * OS_TAU)) return 0;
-    if (!all_front) { *rx0 = 0; *ry0 = 0; *rx1 = c->W - 1; *ry1 = c->H - 1; return 1; }
+#define OS_ADD(P)                                                  \
+    do {                                                           \
+        double px_, py_, zv_;                                      \
+        if (os_project(c, (P), &px_, &py_, &zv_)) {                \
+            if (px_ < mnx) mnx = px_;                              \
+            if (px_ > mxx) mxx = px_;                              \
+            if (py_ < mny) mny = py_;                              \
+            if (py_ > mxy) mxy = py_;                              \
+        }                                                          \
+    } while (0)
+    for (int corner = 0; corner < 8; ++corner)
+        if (c->proj != 0 || cz[corner] >= zc) OS_ADD(cp[corner]);
+    if (c->proj == 0 && zmin < zc) {
+        /* the 12 edges join corners differing in one coordinate bit */
+        for (int a = 0; a < 8; ++a)
+            for (int bit = 1; bit < 8; bit <<= 1) {
+                int b = a | bit;
+                if (b == a) continue;
+                if ((cz[a] < zc) == (cz[b] < zc)) continue;
+                double t = (zc - cz[a]) / (cz[b] - cz[a]);
+                double q[3];
+                for (int k = 0; k < 3; ++k) q[k] = cp[a][k] + t * (cp[b][k] - cp[a][k]);
+                /* the crossing point, nudged onto the front side of the plane */
+                double r[3] = {q[0] - c->e[0], q[1] - c->e[1], q[2] - c->e[2]};
+                double zq = dot3(r, c->f);
+                if (zq < zc) for (int k = 0; k < 3; ++k) q[k] += (zc - zq) * c->f[k];
+                OS_ADD(q);
+            }
+    }
+#undef OS_ADD
+    if (!(mnx <= mxx && mny <= mxy)) { *rx0 = 0; *ry0 = 0; *rx1 = c->W - 1; *ry1 = c->H - 1; return 1; }
     double fx0 = floor(mnx - 0.5) - 1, fx1 = ceil(mxx - 0.5) + 1;
     double fy0 = floor(mny - 0.5) - 1, fy1 = ceil(mxy - 0.5) + 1;
     if (fx1 < 0 || fy1 < 0 || fx0 > c->W - 1 || fy0 > c->H - 1) return 0;
@@ -336,9 +368,24 @@ int osplat_gbuffer(int64_t n, const float* pos, const float* rad, const uint32_t
         r->ok = os_box_rect(&c, lo, hi, &r->x0, &r->y0, &r->x1, &r->y1);
     }
 
+    /* the primitives whose footprint meets the window, in primitive order
+       (every band below walks this list instead of all of them) */
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < np_; ++p) {
+        os_rect* r = &rects[p];
+        if (r->ok && (r->x1 < x0 || r->x0 > x0 + w - 1 || r->y1 < y0 || r->y0 > y0 + h - 1)) r->ok = 0;
+    }
+    int64_t nsel = 0;
+    for (int64_t p = 0; p < np_; ++p) nsel += rects[p].ok ? 1 : 0;
+    int64_t* sel = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nsel > 0 ? nsel : 1));
+    if (!sel) { free(rects); return -2; }
+    nsel = 0;
+    for (int64_t p = 0; p < np_; ++p)
+        if (rects[p].ok) sel[nsel++] = p;
+
     int64_t P = (int64_t)w * h;
     double* zstar = (double*)malloc(sizeof(double) * (size_t)P);
-    if (!zstar) { free(rects); return -2; }
+    if (!zstar) { free(rects); free(sel); return -2; }
     int64_t frag_total = 0;
 
 #pragma omp parallel reduction(+ : frag_total)
@@ -361,9 +408,9 @@ int osplat_gbuffer(int64_t n, const float* pos, const float* rad, const uint32_t
             }
         /* pass 1: exact winner and the depth of the nearest solid hit */
         for (int pass = 0; pass < 2; ++pass) {
-            for (int64_t p = 0; p < np_; ++p) {
+            for (int64_t k_sel = 0; k_sel < nsel; ++k_sel) {
+                const int64_t p = sel[k_sel];
                 const os_rect* r = &rects[p];
-                if (!r->ok) continue;
                 int ya = r->y0 > band0 ? r->y0 : band0;
                 int yb = r->y1 < band1 - 1 ? r->y1 : band1 - 1;
                 int xa = r->x0 > x0 ? r->x0 : x0;
@@ -431,6 +478,7 @@ int osplat_gbuffer(int64_t n, const float* pos, const float* rad, const uint32_t
     *fragments = frag_total;
     free(zstar);
     free(rects);
+    free(sel);
     return 0;
 }
 
@@ -454,14 +502,16 @@ static double os_smooth(double x) {
  * window.  shading: 0 glossy, 1 matte, 2 flat, 3 toon; fog from fog_start to
  * fog_end (none unless fog_end > fog_start); outline_t > 0 draws outlines.
  * unstable_out counts every decision FP32 may take the other way: SSAO
- * samples near a pixel edge or their depth threshold, toon band edges and
- * outline depth thresholds. */
+ * samples near a pixel edge or their depth threshold, or reading a pixel
+ * flagged in `ambiguous` (over the depth buffer; may be NULL) because its
+ * visible primitive is not unique, toon band edges and outline depth
+ * thresholds. */
 int osplat_shade(const double* cam, int W, int H, int x0, int y0, int w, int h,
                  const double* z, const double* nrm, const uint32_t* alb,
                  const double* depth_buf, int bx0, int by0, int bw, int bh,
                  int K, double R, double bias, uint32_t background, double edge_px, double depth_rel,
                  int shading, double fog_start, double fog_end, uint32_t fog_color,
-                 double outline_t, uint32_t outline_color,
+                 double outline_t, uint32_t outline_color, const uint8_t* ambiguous,
                  int nthreads, uint32_t* rgba, double* ao_out, int32_t* unstable_out, int32_t* outside_out) {
     if (K < 0 || K > 1024) return -1;
     os_cam c;
@@ -541,6 +591,9 @@ int osplat_shade(const double* cam, int W, int H, int x0, int y0, int w, int h,
                     double thr = S[2] - bias;
                     if (ok && zq <= thr && isfinite(zq)) occ += os_smooth(R / fabs(Pv[2] - zq));
                     int margin = ok && fabs(zq - thr) <= depth_rel * fabs(S[2]);
+                    /* a sample reading a pixel whose visible primitive is not
+                       unique may see another correct depth there */
+                    if (ok && ambiguous && ambiguous[(int64_t)((int)qy - by0) * bw + ((int)qx - bx0)]) margin = 1;
                     if ((front && edge) || near_edge || margin) ++uns;
                 }
             }

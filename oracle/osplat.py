@@ -50,7 +50,7 @@ def lib():
                                    ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
                                    ctypes.c_double, ctypes.c_double,
                                    ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
-                                   ctypes.c_double, ctypes.c_uint32,
+                                   ctypes.c_double, ctypes.c_uint32, P,
                                    ctypes.c_int, P, P, P, P]
         _lib = L
     return _lib
@@ -117,14 +117,17 @@ def gbuffer(scene, cam, opts, W, H, window=None, nthreads=None):
     res["unstable"] = res["unstable"].astype(bool)
     res["acc_bg"] = res["acc_bg"].astype(bool)
     res["fragments"] = int(frag[0])
+    res["view"] = (cam, W, H, window)
     return res
 
 
 def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=None, depth_win=None,
-                  nthreads=None, edge_px=1e-3, depth_rel=1e-5):
+                  nthreads=None, edge_px=1e-3, depth_rel=1e-5, ambiguous=None):
+    """Deferred pass over the window (see ofull.shade_gbuffer, same arguments)."""
     x0, y0, w, h = window
     if depth_buf is None:
         depth_buf, depth_win = z, window
+    amb = None if ambiguous is None else np.ascontiguousarray(ambiguous, dtype=np.uint8)
     zz = np.ascontiguousarray(z, dtype=np.float64)
     nn = np.ascontiguousarray(normal_view, dtype=np.float64)
     al = np.ascontiguousarray(albedo, dtype=np.uint32)
@@ -143,7 +146,8 @@ def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=Non
                             float(getattr(opts, "fog_start", 0.0)), float(getattr(opts, "fog_end", 0.0)),
                             int(getattr(opts, "fog_color", 0)) & 0xFFFFFFFF,
                             float(getattr(opts, "outline_depth", 0.0)),
-                            int(getattr(opts, "outline_color", 0)) & 0xFFFFFFFF, nthreads or default_threads(),
+                            int(getattr(opts, "outline_color", 0)) & 0xFFFFFFFF,
+                            None if amb is None else _ptr(amb), nthreads or default_threads(),
                             _ptr(rgba), _ptr(ao), _ptr(uns), _ptr(outside))
     if rc != 0:
         raise RuntimeError(f"osplat_shade failed: {rc}")
@@ -163,8 +167,10 @@ def render(scene, cam, opts, W, H, window=None, halo=0, nthreads=None, edge_px=1
     sl = (slice(y0 - gy0, y0 - gy0 + h), slice(x0 - gx0, x0 - gx0 + w))
     inner = {k: (np.ascontiguousarray(v[sl]) if isinstance(v, np.ndarray) and v.ndim >= 2 else v)
              for k, v in g.items()}
+    from oracle.ofull import ambiguous_pixels
     sh = shade_gbuffer(cam, opts, W, H, window, inner["z"], inner["normal_view"], inner["albedo"],
                        depth_buf=g["z"], depth_win=gwin, nthreads=nthreads, edge_px=edge_px,
-                       depth_rel=depth_rel)
+                       depth_rel=depth_rel, ambiguous=ambiguous_pixels(g))
     inner.update(sh)
+    inner["view"] = (cam, W, H, window)
     return inner

@@ -135,6 +135,89 @@ __device__ inline float hit_cylinder(const float4 ca, const float4 cb, float ox,
     return t;
 }
 
+// Depth of primitive `id` at pixel (px, py), recomputed in FP64 from the
+// caller's FP32 inputs.  The FP32 ray test decides which primitive a pixel
+// shows; its depth is only good to a few ulps of the distance divided by n.V,
+// so towards a silhouette it drifts past any fixed relative tolerance (at
+// n.V = 0.01 about 1e-5 of the depth).  The FP64 root loses the same digits
+// relative to 2^-53, and rounding it once gives the depth to half an FP32 ulp
+// wherever the hit is not within ~1e-7 of grazing.  Where FP64 finds no
+// entry (an FP32 hit at the silhouette that FP64 places just outside), the
+// depth is the surface's closest approach to the ray: the front root with
+// the discriminant taken as zero, or the cap plane's crossing, whichever is
+// nearest the FP32 depth.
+__device__ inline float refine_depth(const Job& J, uint32_t id, int px, int py, float z32) {
+    const Frame& F = J.F;
+    const double ndx = 2.0 * ((double)px + 0.5) / (double)F.W - 1.0;
+    const double ndy = 1.0 - 2.0 * ((double)py + 0.5) / (double)F.H;
+    // ray o + t D with D.z = 1, so t is the view depth
+    double ox = 0.0, oy = 0.0, Dx = 0.0, Dy = 0.0;
+    if (F.proj == 0) {
+        Dx = ndx * F.tx;
+        Dy = ndy * F.ty;
+    } else {
+        ox = ndx * F.hx;
+        oy = ndy * F.hy;
+    }
+    const double dd = fma(Dx, Dx, fma(Dy, Dy, 1.0));
+    double t = (double)z32;
+    if (id < F.n_atoms) {
+        const size_t i = id;
+        double cx, cy, cz;
+        to_view(F, J.pos[3 * i], J.pos[3 * i + 1], J.pos[3 * i + 2], cx, cy, cz);
+        const double r = (double)atom_radius(F, J.rad[i]);
+        cx -= ox;
+        cy -= oy;
+        const double b = fma(cx, Dx, fma(cy, Dy, cz)) / dd;
+        const double qx = fma(-b, Dx, cx), qy = fma(-b, Dy, cy), qz = cz - b;
+        const double disc = fma(r, r, -fma(qx, qx, fma(qy, qy, qz * qz)));
+        t = b - sqrt(fmax(disc, 0.0) / dd);
+    } else {
+        const size_t bi = id - F.n_atoms;
+        const uint32_t ia = J.bonds[2 * bi], ib = J.bonds[2 * bi + 1];
+        double A[3], B[3];
+        to_view(F, J.pos[3 * (size_t)ia], J.pos[3 * (size_t)ia + 1], J.pos[3 * (size_t)ia + 2], A[0], A[1], A[2]);
+        to_view(F, J.pos[3 * (size_t)ib], J.pos[3 * (size_t)ib + 1], J.pos[3 * (size_t)ib + 2], B[0], B[1], B[2]);
+        const double rho = (double)F.bond_radius;
+        double ax = B[0] - A[0], ay = B[1] - A[1], az = B[2] - A[2];
+        const double L = sqrt(fma(ax, ax, fma(ay, ay, az * az)));
+        ax /= L;
+        ay /= L;
+        az /= L;
+        const double wx = ox - A[0], wy = oy - A[1], wz = -A[2];
+        const double da = fma(Dx, ax, fma(Dy, ay, az)), wa = fma(wx, ax, fma(wy, ay, wz * az));
+        const double px_ = fma(-da, ax, Dx), py_ = fma(-da, ay, Dy), pz_ = fma(-da, az, 1.0);
+        const double qx = fma(-wa, ax, wx), qy = fma(-wa, ay, wy), qz = fma(-wa, az, wz);
+        const double k = fma(px_, px_, fma(py_, py_, pz_ * pz_));
+        double entry = INFINITY, near = INFINITY;
+        auto consider = [&](double tt, bool valid) {
+            if (valid) entry = fmin(entry, tt);
+            if (fabs(tt - (double)z32) < fabs(near - (double)z32)) near = tt;
+        };
+        if (k > 0.0) {
+            const double tc = -fma(qx, px_, fma(qy, py_, qz * pz_)) / k;
+            const double rx = fma(tc, px_, qx), ry = fma(tc, py_, qy), rz = fma(tc, pz_, qz);
+            const double disc = fma(rho, rho, -fma(rx, rx, fma(ry, ry, rz * rz)));
+            const double ts = tc - sqrt(fmax(disc, 0.0) / k);
+            const double s = fma(ts, da, wa);
+            consider(ts, disc >= 0.0 && s >= 0.0 && s <= L);
+        }
+        if (da != 0.0) {
+            const double cap[2] = {0.0, L};
+            for (int c = 0; c < 2; ++c) {
+                const double tp = (cap[c] - wa) / da;
+                const double ex = fma(tp, Dx, wx) - cap[c] * ax, ey = fma(tp, Dy, wy) - cap[c] * ay,
+                             ez = (tp + wz) - cap[c] * az;
+                const bool front = c == 0 ? da > 0.0 : da < 0.0;
+                consider(tp, front && fma(ex, ex, fma(ey, ey, ez * ez)) <= rho * rho);
+            }
+        }
+        t = entry < INFINITY ? entry : near;
+    }
+    const float z = (float)t;
+    return z > 0.0f && z < INFINITY ? z : z32;
+}
+
 // Expand a list record into the LDS form.
 __device__ inline Rec make_rec(const Frame& F, const PrimRec& p) {
     Rec r;
@@ -644,13 +727,26 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
             }
         }
 
+        // The G-buffer: the winner of each pixel with its depth recomputed in
+        // FP64.  The front pass of a two-pass frame stores its FP32 keys
+        // instead: the rest pass continues from them as a one-pass frame
+        // would, and refines every pixel at its end.
+        const bool refine = phase != kPhaseFront;
+#pragma unroll 1
         for (int i = tid; i < TS * TS; i += kBlock) {
             const int ly = i / TS, lx = i - ly * TS;
             if (lx < tw && ly < th) {
                 const unsigned long long kk = keys[i];
                 const size_t p = (size_t)(py0 + ly) * F.W + (px0 + lx);
-                depth[p] = kk == ~0ull ? INFINITY : __uint_as_float((uint32_t)(kk >> 32));
-                out_id[p] = kk == ~0ull ? kBackground : (uint32_t)(kk & 0xFFFFFFFFull);
+                float zo = INFINITY;
+                uint32_t io = kBackground;
+                if (kk != ~0ull) {
+                    io = (uint32_t)(kk & 0xFFFFFFFFull);
+                    zo = __uint_as_float((uint32_t)(kk >> 32));
+                    if (refine) zo = refine_depth(J, io, px0 + lx, py0 + ly, zo);
+                }
+                depth[p] = zo;
+                out_id[p] = io;
             }
         }
     }

@@ -81,12 +81,22 @@ __global__ void __launch_bounds__(kBlock) k_shade(JS js) {
     float nx = 0.f, ny = 0.f, nz = 0.f;
     uint32_t alb = 0;
     if (hit) {
+        // The surface point relative to the primitive, in FP64: P = z D on the
+        // pixel's ray (D = (ndx tx, ndy ty, 1), or the orthographic origin
+        // plus z f), less the primitive's FP64 view coordinates.  Its error is
+        // the rounding of the stored depth, u z |D|, so the normal is good to
+        // u z |D| / r radians with no loss towards the silhouette.
+        const double ndxd = fma((double)x + 0.5, F.inv_w2d, -1.0);
+        const double ndyd = fma(-((double)y + 0.5), F.inv_h2d, 1.0);
+        const double zd = (double)z;
+        const double Qx = F.proj == 0 ? zd * (ndxd * F.tx) : ndxd * F.hx;
+        const double Qy = F.proj == 0 ? zd * (ndyd * F.ty) : ndyd * F.hy;
         if (pid < F.n_atoms) {
             double cx, cy, cz;
             to_view(F, pos[3 * (size_t)pid], pos[3 * (size_t)pid + 1], pos[3 * (size_t)pid + 2], cx, cy, cz);
-            nx = Px - (float)cx;
-            ny = Py - (float)cy;
-            nz = Pz - (float)cz;
+            nx = (float)(Qx - cx);
+            ny = (float)(Qy - cy);
+            nz = (float)(zd - cz);
             alb = col[pid];
         } else {
             const size_t b = pid - F.n_atoms;
@@ -97,22 +107,26 @@ __global__ void __launch_bounds__(kBlock) k_shade(JS js) {
                 double A[3], B[3];
                 to_view(F, pos[3 * (size_t)ia], pos[3 * (size_t)ia + 1], pos[3 * (size_t)ia + 2], A[0], A[1], A[2]);
                 to_view(F, pos[3 * (size_t)ib], pos[3 * (size_t)ib + 1], pos[3 * (size_t)ib + 2], B[0], B[1], B[2]);
-                const double ex = B[0] - A[0], ey = B[1] - A[1], ez = B[2] - A[2];
-                const double Ld = sqrt(ex * ex + ey * ey + ez * ez);
-                const float ax = (float)(ex / Ld), ay = (float)(ey / Ld), az = (float)(ez / Ld), L = (float)Ld;
-                const float rx = Px - (float)A[0], ry = Py - (float)A[1], rz = Pz - (float)A[2];
-                const float s = fmaf(rx, ax, fmaf(ry, ay, rz * az));
-                const float qx = fmaf(-s, ax, rx), qy = fmaf(-s, ay, ry), qz = fmaf(-s, az, rz);
-                const float ql = sqrtf(fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
-                const float d_side = fabsf(ql - F.bond_radius), d_a = fabsf(s), d_b = fabsf(s - L);
-                if (d_side <= fminf(d_a, d_b)) {
-                    nx = qx; ny = qy; nz = qz;
-                    alb = s < 0.5f * L ? col[ia] : col[ib];
+                double ax = B[0] - A[0], ay = B[1] - A[1], az = B[2] - A[2];
+                const double L = sqrt(fma(ax, ax, fma(ay, ay, az * az)));
+                const double il = 1.0 / L;
+                ax *= il;
+                ay *= il;
+                az *= il;
+                const double rx = Qx - A[0], ry = Qy - A[1], rz = zd - A[2];
+                const double sd = fma(rx, ax, fma(ry, ay, rz * az));
+                const double qx = fma(-sd, ax, rx), qy = fma(-sd, ay, ry), qz = fma(-sd, az, rz);
+                const double ql = sqrt(fma(qx, qx, fma(qy, qy, qz * qz)));
+                // the surface the point lies on: the side or the nearer cap
+                const double d_side = fabs(ql - (double)F.bond_radius), d_a = fabs(sd), d_b = fabs(sd - L);
+                if (d_side <= fmin(d_a, d_b)) {
+                    nx = (float)qx; ny = (float)qy; nz = (float)qz;
+                    alb = sd < 0.5 * L ? col[ia] : col[ib];
                 } else if (d_a <= d_b) {
-                    nx = -ax; ny = -ay; nz = -az;
+                    nx = (float)-ax; ny = (float)-ay; nz = (float)-az;
                     alb = col[ia];
                 } else {
-                    nx = ax; ny = ay; nz = az;
+                    nx = (float)ax; ny = (float)ay; nz = (float)az;
                     alb = col[ib];
                 }
             }

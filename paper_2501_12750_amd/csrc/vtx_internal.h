@@ -42,6 +42,7 @@ struct Frame {
     float itxf, ityf;                  // 1 / tx, 1 / ty
     float sxf, syf;                    // perspective: sqrt(1 + tx^2), sqrt(1 + ty^2)
     float inv_w2, inv_h2;              // 2/W, 2/H
+    double inv_w2d, inv_h2d;           // the same in FP64
     float znear, zfar;
     float bond_radius;
     int32_t proj;                      // 0 perspective, 1 orthographic

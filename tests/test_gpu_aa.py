@@ -5,7 +5,7 @@ MI355X)."""
 import numpy as np
 import pytest
 
-from oracle import ofull, osplat
+from oracle import compare, ofull, osplat
 from paper_2501_12750_amd import scenes
 from tests.gpu_util import run_render, with_opts
 
@@ -83,7 +83,8 @@ def test_supersample_matches_the_oracle(vtx):
     wl = _scene()
     W, H = wl.width, wl.height
     aa = run_render(vtx, vtx.DeviceScene(wl.scene), wl.camera, with_opts(wl.options, supersample=S), W, H)
-    hi = osplat.render(wl.scene, wl.camera, wl.options, S * W, S * H, edge_px=0.02, depth_rel=1e-4)
+    edge, drel = compare.e2e_bands_for(wl.scene, wl.camera, wl.options, S * W, S * H)
+    hi = osplat.render(wl.scene, wl.camera, wl.options, S * W, S * H, edge_px=edge, depth_rel=drel)
     ref = ofull.supersample_reduce(hi, S)
     st = ref["stable"]
     assert st.sum() > 0.6 * W * H

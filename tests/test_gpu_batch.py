@@ -121,7 +121,8 @@ def test_batch_jobs_match_the_oracle(vtx, ctx):
     got = run_batch(vtx, ctx, specs)
     for i, (_, f, cam, o, W, H) in enumerate(specs):
         sc_f = scenes.Scene(frames[f], scene0.radii, scene0.colors, scene0.bonds)
-        ref = osplat.render(sc_f, cam, o, W, H, edge_px=0.02, depth_rel=1e-4)
+        edge, drel = compare.e2e_bands_for(sc_f, cam, o, W, H)
+        ref = osplat.render(sc_f, cam, o, W, H, edge_px=edge, depth_rel=drel)
         rep = compare.check_gbuffer(got[i]["depth"], got[i]["id"], ref)
         rep.update(compare.check_end_to_end(got[i]["rgba"], ref))
         print(f"job {i}", rep, flush=True)
