@@ -7,10 +7,12 @@ scatter into tile lists -> per-tile ray cast into the (depth, id) G-buffer ->
 SSAO + shading into RGBA8.
 
 Workloads:
-  ball_and_stick (default)  1M atoms + 1.04M bonds, 1920x1080, SSAO 16; one
-                            step = one frame (vtx_render_scene, or vtx_render
-                            with --path plain)
-  whole_cell                100M atoms, 3840x2160, SSAO 16; one step = one frame
+  whole_cell (default)      100M atoms, 3840x2160, SSAO 16; one step = one frame
+                            (vtx_render_scene, or vtx_render with --path plain);
+                            the ball-and-stick frame is timed after it and
+                            reported under its own key (--also)
+  ball_and_stick            1M atoms + 1.04M bonds, 1920x1080, SSAO 16; one
+                            step = one frame
   trajectory                50k atoms x 64 trajectory frames x 4 orbit
                             viewports (720p..1440p) = 256 renders; one step =
                             one vtx_render_batch call of all 256
@@ -21,10 +23,12 @@ Workloads:
   plain_small               4096 atoms, 256x256 (the small parity case)
 
 Prints ONE JSON line: frames/s (renders/s for the batch) with the contract
-fields, atom-fragments/s, p50/p99 latency, per-kernel device times from HIP
-events recorded on the render stream, the roofline of the dominant kernel,
-the other launch form of the same renders side by side, and the CPU oracle
-timed on the host.
+fields, atom-fragments/s, p50/p99 latency, per-kernel device times (each
+kernel dispatched with its own start and stop events on the render stream),
+the roofline of the dominant kernel and of the whole frame, the resolve's
+skip rate (ray tests the early-outs leave, from a counting frame), the other
+launch form of the same renders side by side, and the CPU oracle timed on
+the host.
 """
 from __future__ import annotations
 
@@ -369,32 +373,40 @@ def run_served(args, vtx, scenes, torch, stream):
 def cpu_baseline(renders, scene_of, budget_s=12.0):
     """The oracle (FP64 C splatter + SSAO + shading) on the host cores, end to
     end.  Whole renders of the workload, in order, as many as fit the budget
-    (at least one) when one render fits it; otherwise two centred crops
-    (128^2 and 256^2 pixels with a 32-pixel halo for SSAO) of the first
-    render, and the render's time extrapolated as a fixed part (the oracle
-    projects every primitive for any window) plus a per-pixel part."""
+    (at least one) when one render fits it.  Otherwise a sample of the first
+    render: its fixed part (the oracle projects every primitive for any
+    window), timed on a 1-pixel window, plus three full-width strips of 32
+    rows at a quarter, half and three quarters of the height, whose time less
+    three fixed parts gives the cost per pixel (each strip pixel is ray-cast
+    and shaded once, as in a full frame; SSAO samples that leave a strip are
+    not looked up); the frame's time is the fixed part plus that cost times
+    its pixels."""
     from oracle import osplat
     osplat.build(force=False)
     threads = osplat.default_threads()
     r0 = renders[0]
 
-    def crop(side):
-        w, h = min(side, r0.W), min(side, r0.H)
-        win = ((r0.W - w) // 2, (r0.H - h) // 2, w, h)
+    def timed(win, halo):
         a = time.perf_counter()
-        osplat.render(scene_of(r0), r0.camera, r0.options, r0.W, r0.H, window=win, halo=32, nthreads=threads)
-        return time.perf_counter() - a, w * h
+        osplat.render(scene_of(r0), r0.camera, r0.options, r0.W, r0.H, window=win, halo=halo, nthreads=threads)
+        return time.perf_counter() - a
 
-    t1, a1 = crop(128)
-    if t1 * (r0.W * r0.H) / a1 > budget_s:
-        t2, a2 = crop(256)
-        per_px = max((t2 - t1) / max(1, a2 - a1), 0.0)
-        fixed = max(t1 - per_px * a1, 0.0)
+    fixed = timed((r0.W // 2, r0.H // 2, 1, 1), 0)
+    rows = min(32, r0.H)
+    strips = [(0, max(0, min(r0.H - rows, int(r0.H * f) - rows // 2)), r0.W, rows) for f in (0.25, 0.5, 0.75)]
+    t1 = timed(strips[0], 0)
+    per_px1 = max(t1 - fixed, 0.0) / (r0.W * rows)
+    if fixed + per_px1 * r0.W * r0.H > budget_s:
+        t_rest = sum(timed(w, 0) for w in strips[1:])
+        px = 3 * r0.W * rows
+        per_px = max(t1 + t_rest - 3 * fixed, 0.0) / px
         t_frame = fixed + per_px * r0.W * r0.H
         return {"value": 1.0 / t_frame, "unit": "frames/s", "cores": threads, "kind": "oracle",
-                "sample": f"two centred crops of the first {r0.W}x{r0.H} render (128^2: {t1:.2f} s, 256^2: {t2:.2f} s, "
-                          f"32-px halo); frame time extrapolated as {fixed:.2f} s fixed + {per_px * 1e6:.2f} us per "
-                          f"pixel = {t_frame:.1f} s; FP64 footprint splatter with accept sets + SSAO + shading"}
+                "sample": f"the first {r0.W}x{r0.H} render: fixed part {fixed:.2f} s (1-pixel window), three "
+                          f"{r0.W}x{rows} strips at 1/4, 1/2, 3/4 of the height "
+                          f"({t1 + t_rest:.2f} s for {px} px: {per_px * 1e6:.2f} us per pixel); frame time "
+                          f"extrapolated to {t_frame:.1f} s; FP64 footprint splatter with accept sets + SSAO + "
+                          f"shading"}
     n = 0
     px = 0
     t0 = time.perf_counter()
@@ -412,56 +424,34 @@ def cpu_baseline(renders, scene_of, budget_s=12.0):
                       f"FP64 footprint splatter with accept sets + SSAO + shading, {el:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=0, help="timed steps (0: 200 frames, or 10 batches)")
-    ap.add_argument("--warmup", type=int, default=-1, help="untimed steps first (-1: 20 frames, or 2 batches)")
-    ap.add_argument("--workload", default="ball_and_stick",
-                    choices=["ball_and_stick", "whole_cell", "trajectory", "served", "plain_small"])
-    ap.add_argument("--serve-seconds", type=float, default=60.0, help="served mix: arrival window")
-    ap.add_argument("--serve-warmup", type=float, default=5.0, help="served mix: arrivals excluded from stats")
-    ap.add_argument("--serve-rate", type=float, default=200.0, help="served mix: frame requests per second")
-    ap.add_argument("--serve-budget-gb", type=float, default=0.0,
-                    help="served mix: HBM budget of resident scenes (0 = the full memory)")
-    ap.add_argument("--serve-max-batch", type=int, default=64)
-    ap.add_argument("--tile", type=int, default=0, help="tile size (0 = library default)")
-    ap.add_argument("--path", choices=["scene", "plain"], default="scene",
-                    help="single-frame workloads: scene = resident scene (vtx_scene_create before timing, "
-                         "vtx_render_scene per frame); plain = vtx_render on the caller's arrays each frame")
-    ap.add_argument("--compare", type=int, default=1,
-                    help="also time the other launch form of the same renders (reported beside)")
-    ap.add_argument("--latency-frames", type=int, default=50)
-    ap.add_argument("--kernel-events", choices=["timed", "separate"], default="separate",
-                    help="record the per-kernel HIP events inside the timed region, or in a separate "
-                         "pass of the same length after it")
-    ap.add_argument("--autotune", type=int, default=1,
-                    help="1: choose the tile size with vtx_autotune on the workload's renders before timing "
-                         "(resident-scene and batch forms; renders that leave tile_size at 0 then use it); "
-                         "0: the library default (16, raised for large images)")
-    ap.add_argument("--tuning-cache", default=None, help="JSON cache file for --autotune")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
-                    help="before timing, run one device copy of this many MiB (reference for HBM counters)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the renderer has no multi-GPU path "
-              "(--gpus must be 1)", file=sys.stderr)
-        sys.exit(2)
+def frame_roofline(N, M, st, K, renders, ms_per_step):
+    """The whole frame against its roofline, as the method's algorithmic cost
+    per frame (summed over the step's renders): bytes B = 16 N + 8 M +
+    8 (N_vis + M_vis) + 16 W H + 4 (covered pixels); lane-ops = 60 (N + M) +
+    20 F_sphere + 50 F_cylinder + 25 K W H + 40 W H (F: every atom-fragment,
+    the plain z-buffer count).  Roofline time = max(B / HBM peak,
+    lane-ops / ALU peak); frac = roofline time / measured time."""
+    f_cyl = st.get("fragments_hit_bond", 0)
+    f_sph = st["fragments_hit"] - f_cyl
+    px = sum(r.W * r.H for r in renders)
+    covered = sum(int((r.out.id != -1).sum().item()) for r in renders)
+    R = len(renders)
+    B = 16.0 * N * R + 8.0 * M * R + 8.0 * st["visible"] + 16.0 * px + 4.0 * covered
+    ops = (OPS_PRIM * (N + M) * R + OPS_SPHERE_FRAG * f_sph + OPS_CYL_FRAG * f_cyl + OPS_SAMPLE * K * px +
+           OPS_PIXEL * px)
+    t_hbm = B / (HBM_PEAK_GBS * 1e9) * 1e3
+    t_alu = ops / (ALU_PEAK_TOPS * 1e12) * 1e3
+    t_roof = max(t_hbm, t_alu)
+    return {"bytes": round(B), "lane_ops": round(ops), "t_hbm_ms": round(t_hbm, 4), "t_alu_ms": round(t_alu, 4),
+            "bound": "hbm" if t_hbm >= t_alu else "alu", "roofline_ms": round(t_roof, 4),
+            "measured_ms": round(ms_per_step, 4), "frac": round(t_roof / ms_per_step, 4)}
 
-    import torch
-    from paper_2501_12750_amd import scenes, vtx
 
-    if args.workload == "served":
-        args.served_inputs = build_served(args, scenes)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
-    if args.workload == "served":
-        run_served(args, vtx, scenes, torch, torch.cuda.Stream())
-        return
+def run_workload(args, workload, vtx, scenes, torch, stream, steps_arg, warmup_arg, cpu=True):
+    """Times one workload (a single-frame scene or the trajectory batch) and
+    returns its JSON record."""
     t0 = time.perf_counter()
-    batch = args.workload == "trajectory"
+    batch = workload == "trajectory"
     if batch:
         scene0, frames, cams, opts, viewports = scenes.trajectory()
         if args.tile:
@@ -475,11 +465,11 @@ def main():
         config = {"workload": name, "atoms": N, "bonds": M, "trajectory_frames": len(frames),
                   "viewports": [list(v) for v in viewports], "renders_per_step": len(runner.renders),
                   "ssao_samples": int(opts.ssao_samples)}
-        steps = args.steps or 10
-        warmup = args.warmup if args.warmup >= 0 else 2
+        steps = steps_arg or 10
+        warmup = warmup_arg if warmup_arg >= 0 else 2
     else:
         wl = {"ball_and_stick": scenes.ball_and_stick, "whole_cell": scenes.whole_cell,
-              "plain_small": scenes.plain_small}[args.workload]()
+              "plain_small": scenes.plain_small}[workload]()
         if args.tile:
             wl.options = dataclasses.replace(wl.options, tile_size=args.tile)
         name = wl.name
@@ -491,11 +481,10 @@ def main():
         config = {"workload": name, "atoms": N, "bonds": M, "width": wl.width, "height": wl.height,
                   "ssao_samples": int(wl.options.ssao_samples),
                   "tile_size": frame_tile(wl.options.tile_size, wl.width, wl.height)}
-        steps = args.steps or 200
-        warmup = args.warmup if args.warmup >= 0 else 20
+        steps = steps_arg or 200
+        warmup = warmup_arg if warmup_arg >= 0 else 20
     config["launch"] = runner.launch_form
     R = len(runner.renders)
-    tuning = None
     if args.autotune and not args.tile and (batch or args.path == "scene"):
         tuning = runner.autotune(args.tuning_cache)
         log(f"autotune: {tuning}")
@@ -505,14 +494,18 @@ def main():
         config["autotune"] = tuning
     log(f"workload {name}: {N} atoms, {M} bonds, {R} render(s) per step, set up in {time.perf_counter() - t0:.1f} s")
 
-    # exact fragment counts of these renders (early-outs off), untimed
+    # exact fragment counts of these renders (early-outs off), untimed; then
+    # the ray tests the normal frames run (early-outs on), untimed
     runner.step(vtx.VTX_FLAG_STATS)
     st = vtx.vtx_read_stats(stream)
     hit_px = int(sum(int((r.out.id != -1).sum().item()) for r in runner.renders))
     log(f"stats {st}, hit pixels {hit_px}")
+    runner.step(vtx.VTX_FLAG_COUNT)
+    stc = vtx.vtx_read_stats(stream)
+    log(f"counted frame {stc}")
 
     if args.calibrate_copy_mb:
-        src = torch.empty(args.calibrate_copy_mb << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        src = torch.empty(args.calibrate_copy_mb << 18, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
@@ -566,12 +559,16 @@ def main():
                       "ms_per_step": round(pe / o_steps * 1e3, 4)})
         log(f"other launch form: {other[-1]}")
 
-    # roofline of each kernel (per step = sums over the step's renders); the
-    # dominant one goes in the JSON's roofline
+    # roofline of each kernel (per step = sums over the step's renders, device
+    # time of each kernel from its own dispatch events); the dominant one goes
+    # in the JSON's roofline
     K = int(runner.renders[0].options.ssao_samples)
     f_total = st["fragments_hit"]
     f_cyl = st.get("fragments_hit_bond", 0)
     f_sph = f_total - f_cyl
+    t_cyl = stc.get("fragments_tested_bond", 0)
+    t_sph = stc["fragments_tested"] - t_cyl
+
     def eff_tile(r):
         return frame_tile(getattr(r, "tuned_tile", 0) or r.options.tile_size, r.W, r.H)
     tiles = sum(n_tiles(eff_tile(r), r.W, r.H) for r in runner.renders)
@@ -592,16 +589,28 @@ def main():
             ach, peak, unit = work / (ms * 1e-3) / 1e12, ALU_PEAK_TOPS, "Tops/s"
         kern[k] = {"bound": bound, "ms": round(ms, 5), "achieved": round(ach, 3), "peak": round(peak, 2),
                    "unit": unit, "frac": round(ach / peak, 4)}
+    if "resolve" in kern:
+        # the resolve priced on the ray tests the timed frames run (early-outs
+        # on), beside the plain z-buffer pricing above
+        done = float(OPS_SPHERE_FRAG * t_sph + OPS_CYL_FRAG * t_cyl)
+        ach = done / (timings["ms_resolve"] * 1e-3) / 1e12
+        kern["resolve"].update({
+            "frac_work_done": round(ach / ALU_PEAK_TOPS, 4),
+            "tests_all": st["fragments_tested"], "tests_done": stc["fragments_tested"],
+            "skip_rate": round(1.0 - stc["fragments_tested"] / max(1, st["fragments_tested"]), 4),
+            "tests_done_per_atom_fragment": round(stc["fragments_tested"] / max(1, f_total), 4),
+            "early_outs": {k: stc[k] for k in ("fragments_skipped", "records_culled", "lists_stopped",
+                                               "chunks_stopped")}})
     dom = max(kern, key=lambda k: kern[k]["ms"])
-    roof = dict(kern[dom])
-    roof.pop("ms")
+    roof = {k: v for k, v in kern[dom].items() if k in ("bound", "achieved", "peak", "unit", "frac")}
     scene_path = batch or runner.path == "scene"
     res_tiles = sorted({eff_tile(r) for r in runner.renders})
     launched = {"project": (["k_cluster_cull", "k_count<SceneSource>"] if scene_path else ["k_count<PlainSource>"]),
                 "scatter": ["k_scatter"], "resolve": [f"k_resolve<{t}>" for t in res_tiles], "shade": ["k_shade"],
                 "scan": []}
     traffic = measured_traffic(name, launched[dom]) if (launched[dom] and scene_path) else None
-    roof = {"kernel": dom, "launches": launched[dom], **roof, "traffic": None if traffic is None else round(traffic)}
+    roof = {"kernel": dom, "launches": launched[dom], **roof, "traffic": None if traffic is None else round(traffic),
+            "timing": "per-kernel dispatch events (hipExtLaunchKernel start/stop), mean over the timed steps"}
 
     out = {
         "metric": "frames/s",
@@ -625,13 +634,80 @@ def main():
                        if lat.size else None),
         "kernels": kern,
         "roofline": roof,
+        "frame_roofline": frame_roofline(N, M, st, K, runner.renders, ms_per_step),
         "bins": {"visible": st["visible"], "pairs": st["pairs"], "overflow_tiles": st_after["overflow_tiles"]},
     }
-    if not args.no_cpu_baseline:
+    if cpu and not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(runner.renders, scene_of)
-    print(json.dumps(out), flush=True)
     runner.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=0, help="timed steps (0: 200 frames, or 10 batches)")
+    ap.add_argument("--warmup", type=int, default=-1, help="untimed steps first (-1: 20 frames, or 2 batches)")
+    ap.add_argument("--workload", default="whole_cell",
+                    choices=["ball_and_stick", "whole_cell", "trajectory", "served", "plain_small"])
+    ap.add_argument("--also", default="ball_and_stick",
+                    help="comma-separated workloads also timed and reported under their own key "
+                         "(\"\" for none; default: ball_and_stick beside the whole cell)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="served mix: arrival window")
+    ap.add_argument("--serve-warmup", type=float, default=5.0, help="served mix: arrivals excluded from stats")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="served mix: frame requests per second")
+    ap.add_argument("--serve-budget-gb", type=float, default=0.0,
+                    help="served mix: HBM budget of resident scenes (0 = the full memory)")
+    ap.add_argument("--serve-max-batch", type=int, default=64)
+    ap.add_argument("--tile", type=int, default=0, help="tile size (0 = library default)")
+    ap.add_argument("--path", choices=["scene", "plain"], default="scene",
+                    help="single-frame workloads: scene = resident scene (vtx_scene_create before timing, "
+                         "vtx_render_scene per frame); plain = vtx_render on the caller's arrays each frame")
+    ap.add_argument("--compare", type=int, default=1,
+                    help="also time the other launch form of the same renders (reported beside)")
+    ap.add_argument("--latency-frames", type=int, default=50)
+    ap.add_argument("--kernel-events", choices=["timed", "separate"], default="separate",
+                    help="per-kernel device times: every kernel dispatched with its own start and stop "
+                         "events, in a pass of the same length right after the timed one (separate), or "
+                         "in the timed steps themselves (timed: the events add ~5 us per kernel to the "
+                         "frame time)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: choose the tile size with vtx_autotune on the workload's renders before timing "
+                         "(resident-scene and batch forms; renders that leave tile_size at 0 then use it); "
+                         "0: the library default (16, raised for large images)")
+    ap.add_argument("--tuning-cache", default=None, help="JSON cache file for --autotune")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="before timing, run one device copy of this many MiB (reference for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the renderer has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2501_12750_amd import scenes, vtx
+
+    if args.workload == "served":
+        args.served_inputs = build_served(args, scenes)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    if args.workload == "served":
+        run_served(args, vtx, scenes, torch, torch.cuda.Stream())
+        return
+    out = run_workload(args, args.workload, vtx, scenes, torch, stream, args.steps, args.warmup)
+    for extra in [w for w in args.also.split(",") if w and w != args.workload]:
+        if extra not in ("ball_and_stick", "whole_cell", "trajectory", "plain_small"):
+            raise SystemExit(f"--also: unknown workload {extra}")
+        log(f"also timing {extra}")
+        rec = run_workload(args, extra, vtx, scenes, torch, stream, 0, -1, cpu=False)
+        out[rec["config"]["workload"]] = {k: rec[k] for k in ("value", "unit", "ms_per_step", "config",
+                                                               "other_launch_forms", "atom_fragments_per_s",
+                                                               "latency_ms", "kernels", "roofline",
+                                                               "frame_roofline", "bins")}
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

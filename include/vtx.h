@@ -60,11 +60,13 @@ extern "C" {
 /* options.flags */
 #define VTX_FLAG_STATS 1u        /* count every (primitive, pixel) hit exactly;
                                     disables the depth early-outs */
-#define VTX_FLAG_TIMING 2u       /* vtx_render records a HIP event before and after
-                                    each kernel, read back by vtx_read_timings */
+#define VTX_FLAG_TIMING 2u       /* each kernel of the frame is dispatched with a start
+                                    and a stop event of its own (its dispatch's begin
+                                    and end), read back by vtx_read_timings */
 #define VTX_FLAG_TWO_PASS 8u     /* resident scenes: occlusion pre-pass.  The nearest
-                                    eighth of the visible clusters (by depth, rounded
-                                    up to whole depth classes) is binned and
+                                    eighth of the visible clusters (by depth; rounded
+                                    up to the end of its depth class unless that
+                                    would pass half of them) is binned and
                                     resolved first; of the rest, only
                                     clusters whose bounding sphere is not behind the
                                     depths of every 16x16-pixel cell under it are
@@ -74,11 +76,16 @@ extern "C" {
                                     deep scene bins ~10x fewer primitives) and costs
                                     a second binning pass when they do not (sparse
                                     scenes whose cells keep a gap).  Ignored with
-                                    VTX_FLAG_STATS or VTX_FLAG_ONE_PASS, with 8-pixel
+                                    VTX_FLAG_STATS, VTX_FLAG_COUNT or
+                                    VTX_FLAG_ONE_PASS, with 8-pixel
                                     tiles, for jobs in a batch whose other jobs do
                                     not all set it, and on the first frame of a new
                                     scene or image size in a render slot */
 #define VTX_FLAG_ONE_PASS 4u     /* resident scenes: never take the pre-pass */
+#define VTX_FLAG_COUNT 16u       /* count the ray tests the frame runs with its depth
+                                    early-outs on, and how often each early-out fires
+                                    (vtx_stats); the image is the same, the resolve is
+                                    the slower counting one; no pre-pass */
 
 /*
  * Camera (paper, "Improved user experience": trackball and free-fly cameras
@@ -191,12 +198,20 @@ typedef struct vtx_options {
 typedef struct vtx_stats {
     uint64_t visible;          /* primitives that survived frustum culling */
     uint64_t pairs;            /* (primitive, tile) bin entries */
-    uint64_t fragments_tested; /* (primitive, pixel) ray tests run (VTX_FLAG_STATS) */
+    uint64_t fragments_tested; /* (primitive, pixel) ray tests run (VTX_FLAG_STATS: every
+                                  footprint pixel; VTX_FLAG_COUNT: those the early-outs left) */
     uint64_t fragments_hit;    /* tests that hit: atom-fragments (VTX_FLAG_STATS) */
     uint64_t fragments_hit_bond; /* of which on bond cylinders (VTX_FLAG_STATS) */
     uint64_t overflow_tiles;   /* tiles resolved by the slow path because the bins were full */
     uint64_t bin_capacity;     /* bin entries available for that frame */
     uint64_t bad_bonds;        /* bonds skipped because an index was >= n_atoms */
+    /* VTX_FLAG_STATS or VTX_FLAG_COUNT frames */
+    uint64_t fragments_tested_bond; /* of the ray tests, those on bond cylinders */
+    /* VTX_FLAG_COUNT frames: the depth early-outs of the resolve */
+    uint64_t fragments_skipped; /* footprint pixels not ray-tested: the pixel held a nearer hit */
+    uint64_t records_culled;   /* tile-list records dropped whole: behind every 4x4 block under them */
+    uint64_t lists_stopped;    /* tile lists ended early: every layer left lay behind the tile */
+    uint64_t chunks_stopped;   /* depth-ordered chunks ended early by their depth-bucket bound */
 } vtx_stats;
 
 /* Average device time per kernel of the frames rendered with VTX_FLAG_TIMING. */
@@ -506,8 +521,9 @@ void vtx_server_destroy(vtx_server* server);
 int vtx_read_stats(void* stream, vtx_stats* out);
 
 /*
- * vtx_set_bin_capacity - fixes the number of tile-bin entries (32 bytes
- * each) of the stream's scratch (entries >= 1), or restores automatic sizing
+ * vtx_set_bin_capacity - fixes the number of tile-bin entries (8 bytes
+ * each: a primitive's source index and its footprint in the tile) of the
+ * stream's scratch (entries >= 1), or restores automatic sizing
  * (entries = 0: the bins start at max(2^20, (n_atoms + n_bonds) / 2) entries
  * and grow after a frame that needed more).  A frame whose bins overflow is still exact: the
  * tiles that did not fit are resolved from the list of visible primitives,

@@ -16,6 +16,13 @@
 #include "vtx.h"
 #include "vtx_internal.h"
 
+namespace vtx {
+KernelClock*& kernel_clock() {
+    thread_local KernelClock* c = nullptr;
+    return c;
+}
+}  // namespace vtx
+
 namespace {
 
 using vtx::BinBuffers;
@@ -41,15 +48,22 @@ int fail(int code, const char* fmt, ...) {
     } while (0)
 
 constexpr int kTimingRing = 64;
-constexpr int kMarks = 11;   // events of a timed frame: 7, or 11 with the occlusion pre-pass
 constexpr int kTimeCats = 6;  // clear, project, scan, scatter, resolve, shade
 constexpr int kMaxBatch = 4096;
 
+// Events of one timed frame: a start and a stop event per kernel dispatch.
 struct TimingSlot {
-    hipEvent_t ev[kMarks] = {};
-    uint8_t cat[kMarks] = {};   // time category of the interval from event m to event m + 1
-    int used = 0;               // events recorded
+    vtx::KernelClock clock{};
     bool inflight = false;
+};
+
+// Sets the host thread's kernel clock for the lifetime of a render call.
+struct ClockScope {
+    explicit ClockScope(vtx::KernelClock* c) { vtx::kernel_clock() = c; }
+    ~ClockScope() { vtx::kernel_clock() = nullptr; }
+    void category(int cat) {
+        if (vtx::kernel_clock()) vtx::kernel_clock()->cur = cat;
+    }
 };
 
 // Binning scratch of one render slot: a single render uses slot 0, job i of a
@@ -144,7 +158,7 @@ uint64_t seen_pairs(uint64_t uid, int w, int h) {
     return jt == it->second.end() ? 0 : jt->second;
 }
 
-constexpr uint64_t kMaxCapacity = 1ull << 28;        // bin entries (8 GiB of 32-byte records)
+constexpr uint64_t kMaxCapacity = 1ull << 28;        // bin entries (2 GiB of 8-byte entries)
 constexpr uint64_t kMinCapacity = 1ull << 20;
 
 void bins_free(Bins* b) {
@@ -210,6 +224,11 @@ void harvest(Workspace* ws) {
         s.fragments_tested += c.frag_tested;
         s.fragments_hit += c.frag_hit;
         s.fragments_hit_bond += c.frag_hit_bond;
+        s.fragments_tested_bond += c.frag_tested_bond;
+        s.fragments_skipped += c.frag_skipped;
+        s.records_culled += c.rec_culled;
+        s.lists_stopped += c.lists_stopped;
+        s.chunks_stopped += c.chunks_stopped;
         s.overflow_tiles += c.overflow_tiles;
         s.bin_capacity += b->pending_capacity;
         s.bad_bonds += c.bad_bonds;
@@ -231,16 +250,17 @@ void harvest_timings(Workspace* ws, bool wait) {
         const int i = (ws->tnext + k) % kTimingRing;   // oldest first
         TimingSlot& t = ws->tslots[i];
         if (!t.inflight) continue;
-        if (t.used < 2) {   // the frame failed before its events were queued
+        const vtx::KernelClock& c = t.clock;
+        if (c.used < 1) {   // the frame failed before a kernel was queued
             t.inflight = false;
             continue;
         }
-        const int last = t.used - 1;
-        if (wait) (void)hipEventSynchronize(t.ev[last]);
-        if (hipEventQuery(t.ev[last]) != hipSuccess) break;
-        for (int m = 0; m < last; ++m) {
+        const int last = c.used - 1;
+        if (wait) (void)hipEventSynchronize(c.stop[last]);
+        if (hipEventQuery(c.stop[last]) != hipSuccess) break;
+        for (int m = 0; m < c.used; ++m) {
             float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, t.ev[m], t.ev[m + 1]) == hipSuccess) ws->tsum[t.cat[m]] += ms;
+            if (hipEventElapsedTime(&ms, c.start[m], c.stop[m]) == hipSuccess) ws->tsum[c.cat[m]] += ms;
         }
         ws->tframes += 1;
         t.inflight = false;
@@ -252,14 +272,17 @@ int timing_slot(Workspace* ws, TimingSlot** out) {
     if (!ws->tslots) {
         ws->tslots = new TimingSlot[kTimingRing];
         for (int i = 0; i < kTimingRing; ++i)
-            for (int m = 0; m < kMarks; ++m)
-                if (hipEventCreate(&ws->tslots[i].ev[m]) != hipSuccess) return fail(VTX_EHIP, "hipEventCreate failed");
+            for (int m = 0; m < vtx::KernelClock::kMax; ++m)
+                if (hipEventCreate(&ws->tslots[i].clock.start[m]) != hipSuccess ||
+                    hipEventCreate(&ws->tslots[i].clock.stop[m]) != hipSuccess)
+                    return fail(VTX_EHIP, "hipEventCreate failed");
     }
     TimingSlot* t = &ws->tslots[ws->tnext];
     if (t->inflight) harvest_timings(ws, true);
     ws->tnext = (ws->tnext + 1) % kTimingRing;
     t->inflight = true;
-    t->used = 0;
+    t->clock.used = 0;
+    t->clock.cur = 0;
     *out = t;
     return VTX_OK;
 }
@@ -391,7 +414,10 @@ void workspace_free(Workspace* ws) {
     ws->slots.clear();
     if (ws->tslots) {
         for (int i = 0; i < kTimingRing; ++i)
-            for (int m = 0; m < kMarks; ++m) hipEventDestroy(ws->tslots[i].ev[m]);
+            for (int m = 0; m < vtx::KernelClock::kMax; ++m) {
+                hipEventDestroy(ws->tslots[i].clock.start[m]);
+                hipEventDestroy(ws->tslots[i].clock.stop[m]);
+            }
         delete[] ws->tslots;
     }
     hipFree(ws->d_tab);
@@ -829,16 +855,17 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
     bool timing = false, scene = false, count = false;
     for (const JobDesc& j : d) {
         timing |= (j.F.flags & VTX_FLAG_TIMING) != 0;
-        count |= (j.F.flags & VTX_FLAG_STATS) != 0;
+        count |= (j.F.flags & (VTX_FLAG_STATS | VTX_FLAG_COUNT)) != 0;
         scene |= j.scene;
     }
     TimingSlot* tslot = nullptr;
     if (timing && !capture && (rc = timing_slot(ws, &tslot))) return rc;
-    // timed frames: an event, and the time category of the interval it opens
+    // timed frames: each kernel's own start and stop events, filed under the
+    // time category set before its launch
+    ClockScope clock(tslot ? &tslot->clock : nullptr);
     auto mark = [&](int cat) -> hipError_t {
-        if (!tslot || tslot->used >= kMarks) return hipSuccess;
-        tslot->cat[tslot->used] = (uint8_t)cat;
-        return hipEventRecord(tslot->ev[tslot->used++], stream);
+        clock.category(cat);
+        return hipSuccess;
     };
     while (bin && ws->slots.size() < n) {
         Bins* b = nullptr;
@@ -1027,7 +1054,8 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
         bool two_pass = scene && need.empty();
         for (size_t i = 0; i < n && two_pass; ++i)
             two_pass = d[i].scene && (d[i].F.flags & VTX_FLAG_TWO_PASS) &&
-                       !(d[i].F.flags & (VTX_FLAG_STATS | VTX_FLAG_ONE_PASS)) && d[i].F.tile >= vtx::kHzCell;
+                       !(d[i].F.flags & (VTX_FLAG_STATS | VTX_FLAG_COUNT | VTX_FLAG_ONE_PASS)) &&
+                       d[i].F.tile >= vtx::kHzCell;
         if (scene) {
             if (n == 1) VTX_HIP(vtx::launch_cluster_cull(one(g_cull), g_cull, stream));
             else VTX_HIP(vtx::launch_cluster_cull(list_of(0, n, 0), g_cull, stream));

@@ -476,6 +476,11 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js, int phase) {
             ctr->frag_tested = 0;          // this frame's resolve adds to these
             ctr->frag_hit = 0;
             ctr->frag_hit_bond = 0;
+            ctr->frag_tested_bond = 0;
+            ctr->frag_skipped = 0;
+            ctr->rec_culled = 0;
+            ctr->lists_stopped = 0;
+            ctr->chunks_stopped = 0;
             ctr->done_blocks = 0;
             ctr->pairs_counted = 0;
             // the next frame's cluster test adds to these (the rest pass reads them)
@@ -499,6 +504,11 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js, int phase) {
                 host_ctr->frag_tested = 0;
                 host_ctr->frag_hit = 0;
                 host_ctr->frag_hit_bond = 0;
+                host_ctr->frag_tested_bond = 0;
+                host_ctr->frag_skipped = 0;
+                host_ctr->rec_culled = 0;
+                host_ctr->lists_stopped = 0;
+                host_ctr->chunks_stopped = 0;
                 __threadfence_system();
             }
         }
@@ -595,18 +605,16 @@ hipError_t count_impl(const JS& js, bool scene, int phase, uint32_t grid, int ma
     if (phase != kPhaseAll && !scene) return hipErrorInvalidValue;
     if (grid == 0) return hipSuccess;
     const size_t lds = (size_t)max_tiles * sizeof(uint32_t);
-    if (scene && phase == kPhaseRest) k_count<JS, true, true><<<grid, kBinThreads, lds, stream>>>(js, phase);
-    else if (scene) k_count<JS, true, false><<<grid, kBinThreads, lds, stream>>>(js, phase);
-    else k_count<JS, false, false><<<grid, kBinThreads, lds, stream>>>(js, phase);
-    return hipGetLastError();
+    if (scene && phase == kPhaseRest) return dispatch(k_count<JS, true, true>, grid, kBinThreads, lds, stream, js, phase);
+    if (scene) return dispatch(k_count<JS, true, false>, grid, kBinThreads, lds, stream, js, phase);
+    return dispatch(k_count<JS, false, false>, grid, kBinThreads, lds, stream, js, phase);
 }
 
 template <class JS>
 hipError_t scatter_impl(const JS& js, int phase, uint32_t grid, int max_tiles, hipStream_t stream) {
     if (max_tiles > kMaxLdsTiles) return hipErrorInvalidValue;
     if (grid == 0) return hipSuccess;
-    k_scatter<JS><<<grid, kBinThreads, (size_t)max_tiles * sizeof(uint32_t), stream>>>(js, phase);
-    return hipGetLastError();
+    return dispatch(k_scatter<JS>, grid, kBinThreads, (uint32_t)(max_tiles * sizeof(uint32_t)), stream, js, phase);
 }
 
 hipError_t launch_count(const OneJob& js, bool scene, int phase, uint32_t grid, int max_tiles, hipStream_t stream) {
@@ -616,12 +624,10 @@ hipError_t launch_count(const JobList& js, bool scene, int phase, uint32_t grid,
     return count_impl(js, scene, phase, grid, max_tiles, stream);
 }
 hipError_t launch_layers(const OneJob& js, uint32_t grid, hipStream_t stream) {
-    k_layers<<<grid, kBinThreads, 0, stream>>>(js);
-    return hipGetLastError();
+    return dispatch(k_layers<OneJob>, grid, kBinThreads, 0, stream, js);
 }
 hipError_t launch_layers(const JobList& js, uint32_t grid, hipStream_t stream) {
-    k_layers<<<grid, kBinThreads, 0, stream>>>(js);
-    return hipGetLastError();
+    return dispatch(k_layers<JobList>, grid, kBinThreads, 0, stream, js);
 }
 hipError_t launch_scatter(const OneJob& js, int phase, uint32_t grid, int max_tiles, hipStream_t stream) {
     return scatter_impl(js, phase, grid, max_tiles, stream);

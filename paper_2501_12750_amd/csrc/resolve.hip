@@ -296,7 +296,11 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
     const int tid = threadIdx.x, lane = __lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const bool stats = kCount && (F.flags & 1u) != 0;
-    unsigned long long n_tested = 0, n_hit = 0, n_hit_bond = 0;
+    // counting frames (statistics, or VTX_FLAG_COUNT with the early-outs on):
+    // ray tests and hits, and how often each early-out fired
+    const bool counting = kCount && (F.flags & (1u | 16u)) != 0;
+    unsigned long long n_tested = 0, n_hit = 0, n_hit_bond = 0, n_tested_bond = 0, n_skipped = 0, n_culled = 0;
+    uint32_t n_list_stop = 0, n_chunk_stop = 0;
 
     {
         const int tx = t % F.tiles_x, ty = t / F.tiles_x;
@@ -326,7 +330,10 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
             const int slot = ly * TS + lx;
             if (!stats) {
                 const unsigned long long cur = keys[slot];
-                if (__uint_as_float((uint32_t)(cur >> 32)) < rc.zcull) return;
+                if (__uint_as_float((uint32_t)(cur >> 32)) < rc.zcull) {
+                    if (counting) n_skipped += 1;
+                    return;
+                }
             }
             const float ndx = fmaf((float)(px0 + lx) + 0.5f, F.inv_w2, -1.0f);
             const float ndy = fmaf(-((float)(py0 + ly) + 0.5f), F.inv_h2, 1.0f);
@@ -341,8 +348,9 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
             // clip plane: the hit point (ox + z Dx, oy + z Dy, z) on the cut side draws nothing
             if (F.clip_on && hit)
                 hit = fmaf(F.clip[0], fmaf(z, Dx, ox), fmaf(F.clip[1], fmaf(z, Dy, oy), fmaf(F.clip[2], z, F.clip[3]))) >= 0.0f;
-            if (stats) {
+            if (counting) {
                 n_tested += 1;
+                n_tested_bond += rc.kind == 1 ? 1 : 0;
                 n_hit += hit ? 1 : 0;
                 n_hit_bond += (hit && rc.kind == 1) ? 1 : 0;
             }
@@ -522,7 +530,10 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
                     uint32_t mt = 0;
                     for (int b = lane; b < kHzBlocks; b += 64) mt = max(mt, hz[b]);
                     mt = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(mt), 63);
-                    if (bound > 0.0f && __float_as_uint(bound) > mt) break;
+                    if (bound > 0.0f && __float_as_uint(bound) > mt) {
+                        if (counting && tid == 0) ++n_chunk_stop;
+                        break;
+                    }
                 }
                 // later sub-chunks stay small too: the finer the steps, the
                 // sooner the bucket bound above ends the chunk
@@ -551,6 +562,8 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
                 if (lg >= 3) m = max(m, (uint32_t)__shfl_xor((int)m, 4));
                 if (lg >= 4) m = max(m, (uint32_t)__shfl_xor((int)m, 8));
                 const bool live = real && !(sc > 0 && __float_as_uint(zcull) > m && zcull > 0.0f);
+                // every wave takes the same decisions: wave 0 counts them, one lane per record
+                if (counting && wave == 0 && real && !live && (lane & ((1 << lg) - 1)) == 0) n_culled += 1;
                 // blocks under the live records (their union rectangle)
                 const uint32_t ux0 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(live ? 255u - bx0 : 0u), 63);
                 const uint32_t uy0 = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(live ? 255u - by0 : 0u), 63);
@@ -623,7 +636,10 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
                 m = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_max(m), 63);
                 const unsigned long long started = __ballot(lane < (int)L && lay_start[lane] <= (uint32_t)base);
                 const uint32_t zr = lay_zrest[63 - __clzll((long long)started)];
-                if (zr > m && zr != 0u) break;
+                if (zr > m && zr != 0u) {
+                    if (counting && tid == 0) ++n_list_stop;
+                    break;
+                }
             }
             PrimRec pr;
             bool have;
@@ -643,6 +659,7 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
                 const Rec rc = make_rec(F, pr);
                 // until a refresh has stored depths every block is +inf: nothing to test
                 keep = stats || !hz_set || !hz_culled(rc);
+                if (counting && !keep) n_culled += 1;
                 if (keep) {
                     area = rect_area(rc.rect);
                     zc = rc.zcull;
@@ -750,18 +767,28 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
             }
         }
     }
-    if (stats) {
-        unsigned long long a = n_tested, b = n_hit, c = n_hit_bond;
+    if (counting) {
+        unsigned long long a = n_tested, b = n_hit, c = n_hit_bond, d = n_tested_bond, e = n_skipped, g = n_culled;
         for (int o2 = 32; o2 > 0; o2 >>= 1) {
             a += __shfl_xor(a, o2);
             b += __shfl_xor(b, o2);
             c += __shfl_xor(c, o2);
+            d += __shfl_xor(d, o2);
+            e += __shfl_xor(e, o2);
+            g += __shfl_xor(g, o2);
         }
-        if (lane == 0 && a) {
-            atomicAdd(&ctr->frag_tested, a);
-            atomicAdd(&ctr->frag_hit, b);
-            atomicAdd(&ctr->frag_hit_bond, c);
+        if (lane == 0) {
+            if (a) {
+                atomicAdd(&ctr->frag_tested, a);
+                atomicAdd(&ctr->frag_hit, b);
+                atomicAdd(&ctr->frag_hit_bond, c);
+                atomicAdd(&ctr->frag_tested_bond, d);
+            }
+            if (e) atomicAdd(&ctr->frag_skipped, e);
+            if (g) atomicAdd(&ctr->rec_culled, g);
         }
+        if (tid == 0 && n_list_stop) atomicAdd(&ctr->lists_stopped, (unsigned long long)n_list_stop);
+        if (tid == 0 && n_chunk_stop) atomicAdd(&ctr->chunks_stopped, (unsigned long long)n_chunk_stop);
     }
 }
 
@@ -815,11 +842,16 @@ __global__ void __launch_bounds__(kBlock) k_resolve_tail(JS js, const unsigned l
             if (kCount) {
                 for (uint32_t j = 0; j < js.count(); ++j) {
                     const Job& Jj = js.job((int)j);
-                    if (!(Jj.F.flags & 1u) || !Jj.bb.host_ctr) continue;
+                    if (!(Jj.F.flags & (1u | 16u)) || !Jj.bb.host_ctr) continue;
                     const volatile Counters* src = Jj.bb.ctr;
                     Jj.bb.host_ctr->frag_tested = src->frag_tested;
                     Jj.bb.host_ctr->frag_hit = src->frag_hit;
                     Jj.bb.host_ctr->frag_hit_bond = src->frag_hit_bond;
+                    Jj.bb.host_ctr->frag_tested_bond = src->frag_tested_bond;
+                    Jj.bb.host_ctr->frag_skipped = src->frag_skipped;
+                    Jj.bb.host_ctr->rec_culled = src->rec_culled;
+                    Jj.bb.host_ctr->lists_stopped = src->lists_stopped;
+                    Jj.bb.host_ctr->chunks_stopped = src->chunks_stopped;
                 }
             }
             __threadfence_system();
@@ -831,16 +863,20 @@ __global__ void __launch_bounds__(kBlock) k_resolve_tail(JS js, const unsigned l
 }  // namespace
 
 template <int TS, class JS, bool kCount>
-void resolve_launch(const JS& js, int phase, unsigned g, unsigned long long* ovf, uint32_t* ovf_n, hipStream_t stream) {
+hipError_t resolve_launch(const JS& js, int phase, unsigned g, unsigned long long* ovf, uint32_t* ovf_n,
+                          hipStream_t stream) {
+    hipError_t e;
     if constexpr (!kCount && TS >= kHzCell) {
         if (phase != kPhaseAll) {
-            k_resolve<TS, JS, false, true><<<g, kBlock, 0, stream>>>(js, ovf, ovf_n, phase);
-            k_resolve_tail<TS, JS, false, true><<<kTailBlocks, kBlock, 0, stream>>>(js, ovf, ovf_n, phase);
-            return;
+            if ((e = dispatch(k_resolve<TS, JS, false, true>, g, kBlock, 0, stream, js, ovf, ovf_n, phase)))
+                return e;
+            return dispatch(k_resolve_tail<TS, JS, false, true>, kTailBlocks, kBlock, 0, stream, js,
+                            (const unsigned long long*)ovf, ovf_n, phase);
         }
     }
-    k_resolve<TS, JS, kCount, false><<<g, kBlock, 0, stream>>>(js, ovf, ovf_n, phase);
-    k_resolve_tail<TS, JS, kCount, false><<<kTailBlocks, kBlock, 0, stream>>>(js, ovf, ovf_n, phase);
+    if ((e = dispatch(k_resolve<TS, JS, kCount, false>, g, kBlock, 0, stream, js, ovf, ovf_n, phase))) return e;
+    return dispatch(k_resolve_tail<TS, JS, kCount, false>, kTailBlocks, kBlock, 0, stream, js,
+                    (const unsigned long long*)ovf, ovf_n, phase);
 }
 
 template <class JS, bool kCount>
@@ -850,13 +886,12 @@ hipError_t resolve_impl(const JS& js, int tile, int phase, uint32_t grid, unsign
     if (phase != kPhaseAll && (kCount || tile < kHzCell)) return hipErrorInvalidValue;
     const unsigned g = (unsigned)xcd_grid((int)grid);
     switch (tile) {
-        case 8: resolve_launch<8, JS, kCount>(js, phase, g, ovf, ovf_n, stream); break;
-        case 16: resolve_launch<16, JS, kCount>(js, phase, g, ovf, ovf_n, stream); break;
-        case 32: resolve_launch<32, JS, kCount>(js, phase, g, ovf, ovf_n, stream); break;
-        case 64: resolve_launch<64, JS, kCount>(js, phase, g, ovf, ovf_n, stream); break;
+        case 8: return resolve_launch<8, JS, kCount>(js, phase, g, ovf, ovf_n, stream);
+        case 16: return resolve_launch<16, JS, kCount>(js, phase, g, ovf, ovf_n, stream);
+        case 32: return resolve_launch<32, JS, kCount>(js, phase, g, ovf, ovf_n, stream);
+        case 64: return resolve_launch<64, JS, kCount>(js, phase, g, ovf, ovf_n, stream);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_resolve(const OneJob& js, int tile, int phase, uint32_t grid, bool count, unsigned long long* ovf,

@@ -336,8 +336,7 @@ hipError_t scene_update_positions(const float* pos, SceneDev& S, float4* xyzr, f
 template <class JS>
 hipError_t cull_impl(const JS& js, uint32_t grid, hipStream_t stream) {
     if (grid == 0) return hipSuccess;
-    k_cluster_cull<JS><<<grid, kBlock, 0, stream>>>(js);
-    return hipGetLastError();
+    return dispatch(k_cluster_cull<JS>, grid, kBlock, 0, stream, js);
 }
 
 hipError_t launch_cluster_cull(const OneJob& js, uint32_t grid, hipStream_t stream) { return cull_impl(js, grid, stream); }

@@ -265,16 +265,14 @@ hipError_t launch_downsample(const float* sdepth, const uint32_t* sid, const uin
                              float* depth, uint32_t* id, uint32_t* rgba, hipStream_t stream) {
     const size_t px = (size_t)W * H;
     if (px == 0) return hipSuccess;
-    k_downsample<<<(unsigned)((px + kBlock - 1) / kBlock), kBlock, 0, stream>>>(sdepth, sid, srgba, W, H, S, depth,
-                                                                                 id, rgba);
-    return hipGetLastError();
+    return dispatch(k_downsample, (unsigned)((px + kBlock - 1) / kBlock), kBlock, 0, stream, sdepth, sid, srgba, W, H, S,
+                    depth, id, rgba);
 }
 
 template <class JS>
 hipError_t shade_impl(const JS& js, uint32_t grid, hipStream_t stream) {
     if (grid == 0) return hipSuccess;
-    k_shade<JS><<<(unsigned)xcd_grid((int)grid), kBlock, 0, stream>>>(js);
-    return hipGetLastError();
+    return dispatch(k_shade<JS>, (unsigned)xcd_grid((int)grid), kBlock, 0, stream, js);
 }
 
 hipError_t launch_shade(const OneJob& js, uint32_t grid, hipStream_t stream) { return shade_impl(js, grid, stream); }

@@ -7,6 +7,7 @@
 // shading with screen-space ambient occlusion).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -25,9 +26,9 @@ constexpr int kMaxSamples = 64;
 constexpr int kDepthBuckets = 64;
 constexpr int kLayers = 32;
 // Occlusion pre-pass of resident scenes: the nearest 1 / kFrontShare of the
-// depth-ordered visible clusters (rounded up to whole depth classes) is binned
-// and resolved first; of the rest only the clusters not behind its 16x16-pixel
-// block depths are binned.
+// depth-ordered visible clusters (rounded up to the end of its depth class
+// unless that would pass half of them) is binned and resolved first; of the
+// rest only the clusters not behind its 16x16-pixel block depths are binned.
 constexpr int kFrontShare = 8;
 constexpr int kHzCell = 16;
 enum Phase : int { kPhaseAll = 0, kPhaseFront = 1, kPhaseRest = 2 };
@@ -80,8 +81,9 @@ struct SampleKernel {
     uint32_t background;
 };
 
-// Device-side counters of one frame.  The last resolve workgroup copies them
-// to host-mapped memory.
+// Device-side counters of one frame.  The scatter's first workgroup
+// publishes the binning counters to host-mapped memory; on counting frames
+// the resolve's tail launch publishes the fragment counters.
 struct Counters {
     unsigned int vis_count;
     unsigned int overflow;
@@ -91,6 +93,14 @@ struct Counters {
     unsigned long long frag_tested;
     unsigned long long frag_hit;
     unsigned long long frag_hit_bond;
+    // counting frames: ray tests on bonds, tests skipped by the per-pixel
+    // depth test, records culled by block depths, lists and depth-ordered
+    // chunks ended early
+    unsigned long long frag_tested_bond;
+    unsigned long long frag_skipped;
+    unsigned long long rec_culled;
+    unsigned long long lists_stopped;
+    unsigned long long chunks_stopped;
     unsigned int done_blocks;
     unsigned int vis_bucket[kDepthBuckets];   // resident scenes: clusters that passed the frustum test, per depth class
     // resident scenes: per pass (one pass or the front pass; the rest) and
@@ -100,8 +110,9 @@ struct Counters {
     unsigned long long pairs_counted;   // total of the tile counts, added by the count kernel
 };
 
-// View-space record of one visible primitive in a tile list (32 bytes),
-// computed from FP64 and rounded to FP32.
+// View-space record of one visible primitive (32 bytes), computed from FP64
+// and rounded to FP32; the resolve rebuilds it from the 8-byte tile-list
+// entry (source index, footprint).
 //   sphere: g0 = (centre x, y, z, radius),      g1 = (0, 0, id, footprint)
 //   bond:   g0 = (A x, y, z, (B - A).x),         g1 = ((B - A).y, (B - A).z, id, footprint)
 // id >= n_atoms marks a bond.  The footprint word is the primitive's pixel
@@ -264,6 +275,35 @@ __device__ inline uint32_t layer_first(uint32_t g, uint32_t groups, uint32_t lay
 // ---------------------------------------------------------------------------
 // host launch wrappers (one per kernel file)
 // ---------------------------------------------------------------------------
+// Kernel clock of a timed frame: while one is set on the host thread, every
+// frame kernel is dispatched with a start and a stop event of its own
+// (hipExtLaunchKernel), which take the dispatch's own begin and end
+// timestamps, so the time of each kernel excludes launch gaps and event
+// packets.  `cur` is the time category of the launches queued next.
+struct KernelClock {
+    static constexpr int kMax = 24;
+    hipEvent_t start[kMax], stop[kMax];
+    int cat[kMax];
+    int used;
+    int cur;
+};
+KernelClock*& kernel_clock();
+
+// Dispatches kernel `k` on `stream`, timed when a kernel clock is set.
+template <class... Params, class... Args>
+hipError_t dispatch(void (*k)(Params...), dim3 grid, dim3 block, uint32_t lds, hipStream_t stream, Args... args) {
+    KernelClock* c = kernel_clock();
+    hipEvent_t a = nullptr, b = nullptr;
+    if (c && c->used < KernelClock::kMax) {
+        const int i = c->used++;
+        c->cat[i] = c->cur;
+        a = c->start[i];
+        b = c->stop[i];
+    }
+    hipExtLaunchKernelGGL(k, grid, block, lds, stream, a, b, 0u, static_cast<Params>(args)...);
+    return hipGetLastError();
+}
+
 // Binning scratch.  The `groups` binning workgroups each own `chunk`
 // consecutive primitives and the same range of the visible-list arrays.
 struct BinBuffers {

@@ -32,6 +32,7 @@ VTX_FLAG_STATS = 1
 VTX_FLAG_TIMING = 2
 VTX_FLAG_ONE_PASS = 4
 VTX_FLAG_TWO_PASS = 8
+VTX_FLAG_COUNT = 16
 VTX_REP_BALL_AND_STICK, VTX_REP_VAN_DER_WAALS, VTX_REP_STICKS, VTX_REP_SAS = 0, 1, 2, 3
 VTX_SHADE_GLOSSY, VTX_SHADE_MATTE, VTX_SHADE_FLAT, VTX_SHADE_TOON = 0, 1, 2, 3
 
@@ -66,7 +67,8 @@ class vtx_options(ctypes.Structure):
 class vtx_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in ("visible", "pairs", "fragments_tested", "fragments_hit",
                                                "fragments_hit_bond", "overflow_tiles", "bin_capacity",
-                                               "bad_bonds")]
+                                               "bad_bonds", "fragments_tested_bond", "fragments_skipped",
+                                               "records_culled", "lists_stopped", "chunks_stopped")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -71,3 +71,36 @@ def test_early_outs_do_not_change_the_image(vtx, ctx, name):
     print(name, "hit pixels", hits, "fragments per hit pixel", round(depth_complexity, 2), flush=True)
     assert hits > 1000
     assert depth_complexity > 1.5      # enough overlap for the early-outs to have work
+
+
+@pytest.mark.parametrize("name", ["cell", "globule"])
+def test_early_outs_fire(vtx, ctx, name):
+    """A VTX_FLAG_COUNT frame runs the same early-outs as a normal one and
+    counts them: on the layered cell some tile lists end early, on the deep
+    globule some depth-ordered chunks end at their bucket bound, and on both
+    records are culled whole and covered pixels skip ray tests.  It draws the
+    normal frame's image, and tests fewer fragments than a statistics frame."""
+    import torch
+    wl = workload(name)
+    rs = vtx.ResidentScene(ctx, vtx.DeviceScene(wl.scene))
+    normal = rs.render(wl.camera, wl.options, wl.width, wl.height)
+    torch.cuda.synchronize()
+    normal = normal.numpy()
+    counted = rs.render(wl.camera, with_opts(wl.options, flags=vtx.VTX_FLAG_COUNT), wl.width, wl.height)
+    torch.cuda.synchronize()
+    st = vtx.vtx_read_stats()
+    counted = counted.numpy()
+    rs.render(wl.camera, with_opts(wl.options, flags=vtx.VTX_FLAG_STATS), wl.width, wl.height)
+    torch.cuda.synchronize()
+    full = vtx.vtx_read_stats()
+    rs.close()
+    for k in ("depth", "id", "rgba"):
+        assert np.array_equal(normal[k], counted[k]), k
+    print(name, {k: st[k] for k in ("fragments_tested", "fragments_skipped", "records_culled", "lists_stopped",
+                                    "chunks_stopped")}, "all", full["fragments_tested"], flush=True)
+    assert 0 < st["fragments_tested"] < full["fragments_tested"]
+    assert st["fragments_skipped"] > 0 and st["records_culled"] > 0
+    if name == "cell":
+        assert st["lists_stopped"] > 0
+    else:
+        assert st["chunks_stopped"] > 0
