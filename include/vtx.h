@@ -248,6 +248,30 @@ int vtx_render(const float* positions, const float* radii, const uint32_t* color
                int32_t W, int32_t H, uint32_t* rgba, float* depth, uint32_t* id, void* stream);
 
 /*
+ * vtx_render_static - vtx_render for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, same images as vtx_render.  Every
+ * scratch buffer of the frame (tile counts and lists, visible-primitive
+ * lists, histograms, counters) is carved from one static device array of
+ * 64 MiB that each GPU the library runs on holds until the process ends; the
+ * call allocates nothing, device or pinned (the array's device address is
+ * looked up once per device, on the first call).  The array is shared by
+ * every call on a GPU and keeps the last call's contents: each call clears
+ * what it needs zeroed with a kernel (no memset node), and calls that overlap
+ * on one GPU (different streams, or host threads) race.  The tile lists get
+ * the part of the array the other buffers leave; tiles whose lists do not
+ * fit are resolved exactly from the visible lists, more slowly.  Frames
+ * whose other buffers exceed the array (~ 12 B per primitive plus 4 B per
+ * (binning workgroup, tile)) are refused with VTX_EOVERFLOW, stating the
+ * bytes needed.  supersample > 1 is refused (VTX_EINVAL); VTX_FLAG_TIMING is
+ * ignored; statistics are not read back (vtx_read_stats does not see these
+ * frames).
+ */
+int vtx_render_static(const float* positions, const float* radii, const uint32_t* colors, int64_t n_atoms,
+                      const uint32_t* bonds, int64_t n_bonds, const vtx_camera* cam, const vtx_options* opt,
+                      int32_t W, int32_t H, uint32_t* rgba, float* depth, uint32_t* id, void* stream);
+
+/*
  * vtx_gbuffer - visibility only: bin the primitives into screen tiles and
  * ray-cast each pixel against its tile's primitives (Methods, "Meshless
  * Representations": a quad per primitive, then ray-casting of the implicit

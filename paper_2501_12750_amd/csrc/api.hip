@@ -1210,6 +1210,157 @@ int vtx_render(const float* positions, const float* radii, const uint32_t* color
     return render_locked(d, true, true, (hipStream_t)stream);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// vtx_render_static: vtx_render with every scratch buffer carved from one
+// static device array, for callers that cannot allocate.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+constexpr int kMaxStaticDevices = 64;
+
+// The array itself.  In host code `scratch` names a host-side stand-in, not
+// the device memory: only the address hipGetSymbolAddress returns for it on
+// a device may be handed to kernels or copies.
+__device__ __align__(256) static unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_static_mu;
+unsigned char* g_static_ptr[kMaxStaticDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+int static_scratch(int* device, unsigned char** out) {
+    VTX_HIP(hipGetDevice(device));
+    if (*device < 0 || *device >= kMaxStaticDevices) return fail(VTX_EINVAL, "device %d out of range", *device);
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[*device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(VTX_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", *device, hipGetErrorString(e));
+        }
+        g_static_ptr[*device] = static_cast<unsigned char*>(p);
+    }
+    *out = g_static_ptr[*device];
+    return VTX_OK;
+}
+
+// Byte layout of one frame's binning scratch in the static array (each
+// buffer 256-aligned).  The first region holds what must start at zero and
+// is cleared by a fill kernel at every call: the tile counts and cursors,
+// the frame counters and the overflow counters.  The tile lists take what is
+// left.
+struct StaticLayout {
+    size_t tile_cnt, tile_fill, ctr, ovf_n, zero_end;
+    size_t tile_off, vis_cnt, vis_box, vis_src, vis_rect, hist, ovf, list, fixed_end;
+    uint64_t list_entries;
+};
+
+StaticLayout static_layout(int T, uint32_t groups, uint32_t chunk) {
+    StaticLayout L{};
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = at;
+        at = align_up(at + bytes, 256);
+        return o;
+    };
+    L.tile_cnt = take((size_t)T * sizeof(uint32_t));
+    L.tile_fill = take((size_t)T * sizeof(uint32_t));
+    L.ctr = take(sizeof(Counters));
+    L.ovf_n = take(2 * sizeof(uint32_t));
+    L.zero_end = at;
+    L.tile_off = take((size_t)T * sizeof(uint64_t));
+    L.vis_cnt = take((size_t)vtx::kMaxBinGroups * sizeof(uint32_t));
+    L.vis_box = take((size_t)vtx::kMaxBinGroups * sizeof(uint2));
+    const size_t nv = (size_t)groups * chunk;
+    L.vis_src = take(nv * sizeof(uint32_t));
+    L.vis_rect = take(nv * sizeof(uint2));
+    L.hist = take((size_t)groups * T * sizeof(uint32_t));
+    L.ovf = take(xcd_round((uint32_t)T) * sizeof(unsigned long long));
+    L.list = at;
+    L.fixed_end = at;
+    L.list_entries = at < kStaticScratchBytes ? (kStaticScratchBytes - at) / sizeof(uint2) : 0;
+    if (L.list_entries > kMaxCapacity) L.list_entries = kMaxCapacity;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vtx_render_static(const float* positions, const float* radii, const uint32_t* colors, int64_t n_atoms,
+                      const uint32_t* bonds, int64_t n_bonds, const vtx_camera* cam, const vtx_options* opt,
+                      int32_t W, int32_t H, uint32_t* rgba, float* depth, uint32_t* id, void* stream) {
+    vtx_options o = untuned_options(resolve_options(opt));
+    if (o.supersample > 1) return fail(VTX_EINVAL, "vtx_render_static does not supersample (supersample %d)", o.supersample);
+    o.flags &= ~(uint32_t)VTX_FLAG_TIMING;
+    Frame F;
+    int rc = make_frame(cam, o, W, H, n_atoms, n_bonds, &F);
+    if (rc) return rc;
+    if ((rc = check_inputs(positions, radii, colors, n_atoms, bonds, n_bonds, true))) return rc;
+    if (!depth || !id || !rgba) return fail(VTX_EINVAL, "rgba/depth/id outputs are NULL");
+    const int T = F.tiles_x * F.tiles_y;
+    const uint64_t nprim = (uint64_t)F.n_atoms + F.n_bonds;
+    uint32_t groups, chunk;
+    vtx::bin_grid(nprim, &groups, &chunk);
+    const StaticLayout L = static_layout(T, groups, chunk);
+    if (L.fixed_end + 256 * sizeof(uint2) > kStaticScratchBytes)
+        return fail(VTX_EOVERFLOW,
+                    "vtx_render_static: %lld primitives at %dx%d need %zu bytes of binning scratch before the tile "
+                    "lists; the static scratch holds %zu",
+                    (long long)nprim, W, H, L.fixed_end, kStaticScratchBytes);
+    int device = 0;
+    unsigned char* base = nullptr;
+    if ((rc = static_scratch(&device, &base))) return rc;
+    const hipStream_t st = (hipStream_t)stream;
+
+    vtx::OneJob js;
+    std::memset(&js, 0, sizeof(js));
+    vtx::Job& J = js.j;
+    J.F = F;
+    J.pos = positions;
+    J.rad = radii;
+    J.col = colors;
+    J.bonds = bonds;
+    J.depth = depth;
+    J.id = id;
+    J.rgba = rgba;
+    sample_kernel(o, &js.K);
+    BinBuffers& bb = J.bb;
+    bb.tile_cnt = reinterpret_cast<uint32_t*>(base + L.tile_cnt);
+    bb.tile_fill = reinterpret_cast<uint32_t*>(base + L.tile_fill);
+    bb.ctr = reinterpret_cast<Counters*>(base + L.ctr);
+    bb.host_ctr = nullptr;
+    bb.tile_off = reinterpret_cast<uint64_t*>(base + L.tile_off);
+    bb.vis_cnt = reinterpret_cast<uint32_t*>(base + L.vis_cnt);
+    bb.vis_box = reinterpret_cast<uint2*>(base + L.vis_box);
+    bb.vis_src = reinterpret_cast<uint32_t*>(base + L.vis_src);
+    bb.vis_rect = reinterpret_cast<uint2*>(base + L.vis_rect);
+    bb.hist = reinterpret_cast<uint32_t*>(base + L.hist);
+    bb.list = reinterpret_cast<uint2*>(base + L.list);
+    bb.capacity = L.list_entries;
+    bb.groups = groups;
+    bb.chunk = chunk;
+    bb.layers = 1;   // the caller's primitive order: one layer, no layer tables
+    unsigned long long* ovf = reinterpret_cast<unsigned long long*>(base + L.ovf);
+    uint32_t* ovf_n = reinterpret_cast<uint32_t*>(base + L.ovf_n);
+    // the array keeps the last call's contents: clear the counts, cursors
+    // and counters this frame adds to (a fill kernel, no memset node)
+    VTX_HIP(vtx::launch_zero(reinterpret_cast<uint32_t*>(base), L.zero_end / sizeof(uint32_t), st));
+    const bool count = (F.flags & (VTX_FLAG_STATS | VTX_FLAG_COUNT)) != 0;
+    js.blocks = groups;
+    VTX_HIP(vtx::launch_count(js, false, vtx::kPhaseAll, groups, T, st));
+    VTX_HIP(vtx::launch_scatter(js, vtx::kPhaseAll, groups, T, st));
+    js.blocks = (uint32_t)T;
+    VTX_HIP(vtx::launch_resolve(js, F.tile, vtx::kPhaseAll, (uint32_t)T, count, ovf, ovf_n, st));
+    js.blocks = vtx::shade_blocks(F);
+    VTX_HIP(vtx::launch_shade(js, js.blocks, st));
+    return VTX_OK;
+}
+
 int vtx_context_create(int device, size_t hbm_budget_bytes, vtx_context** out) {
     if (!out) return fail(VTX_EINVAL, "out is NULL");
     int count = 0;

@@ -45,7 +45,7 @@ EXPORTS = ("vtx_render", "vtx_gbuffer", "vtx_shade", "vtx_read_stats", "vtx_set_
            "vtx_scene_frame_bytes", "vtx_render_batch", "vtx_autotune", "vtx_clock_s", "vtx_server_create",
            "vtx_server_submit", "vtx_server_poll", "vtx_server_drain", "vtx_server_stats_read",
            "vtx_server_destroy", "vtx_check_job", "vtx_batch_graph_create",
-           "vtx_batch_graph_launch", "vtx_batch_graph_destroy")
+           "vtx_batch_graph_launch", "vtx_batch_graph_destroy", "vtx_render_static")
 
 
 class vtx_camera(ctypes.Structure):
@@ -138,6 +138,8 @@ _OPT = ctypes.POINTER(vtx_options)
 
 _lib.vtx_render.restype = ctypes.c_int
 _lib.vtx_render.argtypes = [_P, _P, _P, _I64, _P, _I64, _CAM, _OPT, _I32, _I32, _P, _P, _P, _P]
+_lib.vtx_render_static.restype = ctypes.c_int
+_lib.vtx_render_static.argtypes = [_P, _P, _P, _I64, _P, _I64, _CAM, _OPT, _I32, _I32, _P, _P, _P, _P]
 _lib.vtx_gbuffer.restype = ctypes.c_int
 _lib.vtx_gbuffer.argtypes = [_P, _P, _P, _I64, _P, _I64, _CAM, _OPT, _I32, _I32, _P, _P, _P]
 _lib.vtx_shade.restype = ctypes.c_int
@@ -280,6 +282,13 @@ def vtx_render(positions, radii, colors, n_atoms, bonds, n_bonds, cam, opts, W, 
     cp, op, _keep = _cam_opt(cam, opts)
     _check(_lib.vtx_render(_addr(positions), _addr(radii), _addr(colors), n_atoms, _addr(bonds), n_bonds,
                            cp, op, W, H, _addr(rgba), _addr(depth), _addr(id), _stream(stream)))
+
+
+def vtx_render_static(positions, radii, colors, n_atoms, bonds, n_bonds, cam, opts, W, H, rgba, depth, id,
+                      stream=None):
+    cp, op, _keep = _cam_opt(cam, opts)
+    _check(_lib.vtx_render_static(_addr(positions), _addr(radii), _addr(colors), n_atoms, _addr(bonds), n_bonds,
+                                  cp, op, W, H, _addr(rgba), _addr(depth), _addr(id), _stream(stream)))
 
 
 def vtx_gbuffer(positions, radii, colors, n_atoms, bonds, n_bonds, cam, opts, W, H, depth, id, stream=None):
