@@ -137,7 +137,19 @@ typedef struct vtx_options {
     float clip_plane[4];      /* world plane a, b, c, d; a x + b y + c z + d >= 0 is kept;
                                  all zero: no clipping (0, 0, 0, 0) */
     int32_t supersample;      /* S = 1..4 samples per pixel side (0 or 1: none) */
+    int32_t ssao_noise;       /* 1: the noise form of the ambient occlusion (see below); 0: none (0) */
 } vtx_options;
+
+/*
+ * options.ssao_noise (paper, Methods, "High Quality Rendering": screen-space
+ * ambient occlusion after Mittring 2007, whose samples are turned per pixel
+ * by a tiled noise and the result blurred).  The reading here keeps it
+ * deterministic: pixel (x, y) turns its tangent frame about its normal by
+ * 2 pi (B[y mod 4][x mod 4] + 1/2) / 16, B the 4x4 ordered-dither (Bayer)
+ * matrix, so the 16 pixels of each 4x4 block sample 16 directions; the AO
+ * of a hit pixel is then the mean of those values over the hit pixels
+ * (x + dx, y + dy), dx, dy in {-2, -1, 0, 1}, inside the image.
+ */
 
 /*
  * options.supersample (paper, Methods, "High Quality Rendering": anti-aliasing

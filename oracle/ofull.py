@@ -32,6 +32,12 @@ notes:
   R6 SSAO       K fixed hemisphere samples oriented by the normal with the
                 branchless orthonormal basis of Duff et al. (JCGT 2017),
                 projected to a pixel and compared with that pixel's depth.
+  R6b noise     optional: the classic noise-and-blur form of screen-space
+                AO, made deterministic.  Each pixel's tangent frame turns
+                about its normal by an angle from a 4x4 ordered-dither
+                (Bayer) table, so neighbouring pixels sample different
+                directions; a 4x4 box blur over the hit pixels then averages
+                the 16 rotations back into a smooth term.
   R7 post       the deferred post-passes the paper lists (shading flat,
                 matte, glossy, toon; fog; outline): glossy is R5; matte drops
                 its specular term; flat is albedo AO; toon replaces n.V by
@@ -468,8 +474,24 @@ def _smoothstep01(x):
     return x * x * (3.0 - 2.0 * x)
 
 
+BAYER4 = np.array([[0, 8, 2, 10], [12, 4, 14, 6], [3, 11, 1, 9], [15, 7, 13, 5]])
+
+
+def noise_rotation(W, H, window):
+    """R6b: cosine and sine of the turn of each pixel's tangent frame about its
+    normal, 2 pi (B[Y mod 4][X mod 4] + 1/2) / 16 for pixel column X and row
+    Y, B the 4x4 Bayer matrix; evaluated in FP64, rounded to FP32."""
+    x0, y0, w, h = window
+    X = np.arange(x0, x0 + w)[None, :] + np.zeros((h, 1), dtype=np.int64)
+    Y = np.arange(y0, y0 + h)[:, None] + np.zeros((1, w), dtype=np.int64)
+    th = 2.0 * math.pi * (BAYER4[Y % 4, X % 4] + 0.5) / 16.0
+    c = np.cos(th).astype(np.float32).astype(np.float64).ravel()
+    s = np.sin(th).astype(np.float32).astype(np.float64).ravel()
+    return c, s
+
+
 def ssao(cam, W, H, window, Pv, Nv, hit, depth_buf, depth_win, K, R, bias,
-         edge_px=1e-3, depth_rel=1e-5, ambiguous=None):
+         edge_px=1e-3, depth_rel=1e-5, ambiguous=None, rotation=None):
     """Ambient occlusion at the pixels of ``window``.
 
     Pv, Nv: (n, 3) view-space position and unit normal per pixel; hit: (n,) bool.
@@ -478,6 +500,8 @@ def ssao(cam, W, H, window, Pv, Nv, hit, depth_buf, depth_win, K, R, bias,
     primitive is not unique (several accepted answers); a sample that reads
     one counts as unstable, since a correct G-buffer may hold another depth
     there.
+    rotation: optional (cos, sin) per pixel (R6b): the tangent frame becomes
+    T' = cos T + sin B, B' = cos B - sin T.
     Returns (ao (n,), unstable (n,) count of samples whose outcome may flip,
     outside (n,) count of on-screen samples that fell outside depth_buf).
     """
@@ -489,6 +513,9 @@ def ssao(cam, W, H, window, Pv, Nv, hit, depth_buf, depth_win, K, R, bias,
         return ao, unstable, outside
     hk, sk = ssao_kernel(K)
     T, Bv = onb_duff(np.where(hit[:, None], Nv, np.array([0.0, 0.0, -1.0])))
+    if rotation is not None:
+        rc, rs = rotation
+        T, Bv = rc[:, None] * T + rs[:, None] * Bv, rc[:, None] * Bv - rs[:, None] * T
     flip = hit & (np.abs(Nv[:, 2]) <= 1e-4)
     unstable[flip] = K
     bx0, by0, bw, bh = depth_win
@@ -604,8 +631,53 @@ def outline(W, H, window, z, depth_buf, depth_win, t, depth_rel=1e-5):
     return edge, unsure
 
 
+def blurred_ssao(cam, opts, W, H, window, depth_buf, depth_win, normal_buf, edge_px, depth_rel, ambiguous):
+    """R6b: the AO of the window's pixels as the mean of the rotated raw AO
+    over the hit pixels (X + dx, Y + dy), dx, dy in {-2, -1, 0, 1}, inside
+    the image.  Raw values are taken over the window grown by that footprint
+    within the depth buffer; a neighbour the buffer does not cover counts as
+    outside, and the unstable and outside counts of every raw value taken
+    add up."""
+    x0, y0, w, h = window
+    bx0, by0, bw, bh = depth_win
+    gx0, gy0 = max(x0 - 2, bx0), max(y0 - 2, by0)
+    gx1, gy1 = min(x0 + w + 1, bx0 + bw), min(y0 + h + 1, by0 + bh)
+    gwin = (gx0, gy0, gx1 - gx0, gy1 - gy0)
+    db = np.asarray(depth_buf, dtype=np.float64)
+    zg = db[gy0 - by0:gy1 - by0, gx0 - bx0:gx1 - bx0].ravel()
+    ng = np.asarray(normal_buf, dtype=np.float64)[gy0 - by0:gy1 - by0, gx0 - bx0:gx1 - bx0].reshape(-1, 3)
+    hit = np.isfinite(zg)
+    Pv = view_position(cam, W, H, gwin, np.where(hit, zg, 1.0))
+    raw, uns, outside = ssao(cam, W, H, gwin, Pv, ng, hit, depth_buf, depth_win,
+                             int(opts.ssao_samples), float(opts.ssao_radius), float(opts.ssao_bias),
+                             edge_px=edge_px, depth_rel=depth_rel, ambiguous=ambiguous,
+                             rotation=noise_rotation(W, H, gwin))
+    gh, gw = gy1 - gy0, gx1 - gx0
+    raw, uns, outside, hit = (a.reshape(gh, gw) for a in (raw, uns, outside, hit))
+    ao = np.ones((h, w))
+    uo = np.zeros((h, w), dtype=np.int32)
+    oo = np.zeros((h, w), dtype=np.int32)
+    total = np.zeros((h, w))
+    count = np.zeros((h, w))
+    jj, ii = np.mgrid[y0:y0 + h, x0:x0 + w]
+    for dy in (-2, -1, 0, 1):
+        for dx in (-2, -1, 0, 1):
+            qx, qy = ii + dx, jj + dy
+            in_img = (qx >= 0) & (qx < W) & (qy >= 0) & (qy < H)
+            in_g = in_img & (qx >= gx0) & (qx < gx1) & (qy >= gy0) & (qy < gy1)
+            oo += (in_img & ~in_g).astype(np.int32)
+            gi, gj = np.where(in_g, qx - gx0, 0), np.where(in_g, qy - gy0, 0)
+            take = in_g & hit[gj, gi]
+            total += np.where(take, raw[gj, gi], 0.0)
+            count += take
+            uo += np.where(take, uns[gj, gi], 0)
+            oo += np.where(take, outside[gj, gi], 0)
+    ao = np.where(count > 0, total / np.maximum(count, 1), 1.0)
+    return ao.ravel(), uo.ravel(), oo.ravel()
+
+
 def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=None, depth_win=None,
-                  edge_px=1e-3, depth_rel=1e-5, ambiguous=None):
+                  edge_px=1e-3, depth_rel=1e-5, ambiguous=None, normal_buf=None):
     """Deferred pass: SSAO then shading over ``window``.
 
     z, normal_view, albedo cover the window; depth_buf/depth_win give the depth
@@ -619,9 +691,21 @@ def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=Non
     Nv = normal_view.reshape(-1, 3)
     if depth_buf is None:
         depth_buf, depth_win = z, window
-    ao, uns, outside = ssao(cam, W, H, window, Pv, Nv, hit, depth_buf, depth_win,
-                            int(opts.ssao_samples), float(opts.ssao_radius), float(opts.ssao_bias),
-                            edge_px=edge_px, depth_rel=depth_rel, ambiguous=ambiguous)
+        normal_buf = normal_view
+    if normal_buf is None and tuple(depth_win) == tuple(window):
+        normal_buf = normal_view
+    if int(getattr(opts, "ssao_noise", 0)) and int(opts.ssao_samples) > 0:
+        if normal_buf is None:
+            raise ValueError("SSAO noise needs the normals over the depth buffer (normal_buf)")
+        ao, uns, outside = blurred_ssao(cam, opts, W, H, window, depth_buf, depth_win, normal_buf,
+                                        edge_px, depth_rel, ambiguous)
+        ao = np.where(hit, ao, 1.0)
+        uns = np.where(hit, uns, 0)
+        outside = np.where(hit, outside, 0)
+    else:
+        ao, uns, outside = ssao(cam, W, H, window, Pv, Nv, hit, depth_buf, depth_win,
+                                int(opts.ssao_samples), float(opts.ssao_radius), float(opts.ssao_bias),
+                                edge_px=edge_px, depth_rel=depth_rel, ambiguous=ambiguous)
     Vv = -view_dir(cam, W, H, window)
     fog = (float(getattr(opts, "fog_start", 0.0)), float(getattr(opts, "fog_end", 0.0)),
            int(getattr(opts, "fog_color", 0)))
@@ -681,7 +765,7 @@ def render(scene, cam, opts, W, H, window=None, halo=0, edge_px=1e-3, depth_rel=
     inner = {k: (v[sl] if isinstance(v, np.ndarray) and v.ndim >= 2 else v) for k, v in g.items()}
     sh = shade_gbuffer(cam, opts, W, H, window, inner["z"], inner["normal_view"], inner["albedo"],
                        depth_buf=g["z"], depth_win=gwin, edge_px=edge_px, depth_rel=depth_rel,
-                       ambiguous=ambiguous_pixels(g))
+                       ambiguous=ambiguous_pixels(g), normal_buf=g["normal_view"])
     inner.update(sh)
     inner["view"] = (cam, W, H, window)
     return inner

@@ -496,24 +496,106 @@ static double os_smooth(double x) {
     return x * x * (3.0 - 2.0 * x);
 }
 
-/* SSAO (R6) and shading (R5) over the window, from depth z, view normals and albedo.
-   depth_buf covers (bx0, by0, bw, bh) of the image and is what samples read. */
+/* The 4x4 ordered-dither (Bayer) matrix: the noise pattern of the SSAO
+   rotation (R6b). */
+static const int os_bayer4[4][4] = {{0, 8, 2, 10}, {12, 4, 14, 6}, {3, 11, 1, 9}, {15, 7, 13, 5}};
+
+/* SSAO of one hit pixel (R6): the view position Pv and unit normal N, the
+   sample kernel hk/sk, and, with noise, the rotation (cr, sr) of the tangent
+   frame about N.  Returns the occlusion sum; counts unstable samples and
+   on-screen samples that fall outside the depth buffer. */
+static double os_ssao_pixel(const os_cam* c, int W, int H, const double* Pv, const double* N, int K,
+                            double (*hk)[3], const double* sk, double R, double bias, double cr, double sr,
+                            const double* depth_buf, const uint8_t* ambiguous, int bx0, int by0, int bw, int bh,
+                            double edge_px, double depth_rel, int* uns, int* outside) {
+    double fpx = (H / 2.0) / c->tanh_;
+    double osc = (H / 2.0) / c->hh;
+    double T0[3], B0[3], T[3], B[3];
+    os_onb(N, T0, B0);
+    for (int a = 0; a < 3; ++a) {
+        T[a] = cr * T0[a] + sr * B0[a];
+        B[a] = cr * B0[a] - sr * T0[a];
+    }
+    if (fabs(N[2]) <= 1e-4) *uns += K;
+    double occ = 0.0;
+    for (int k = 0; k < K; ++k) {
+        double S[3];
+        double sc = R * sk[k];
+        for (int a = 0; a < 3; ++a) S[a] = Pv[a] + sc * (hk[k][0] * T[a] + hk[k][1] * B[a] + hk[k][2] * N[a]);
+        double px, py;
+        int front = S[2] > c->znear;
+        double za = fabs(S[2]) > c->znear ? fabs(S[2]) : c->znear;
+        int near_edge = fabs(S[2] - c->znear) <= depth_rel * za;
+        if (c->proj == 0) {
+            px = W / 2.0 + fpx * S[0] / S[2];
+            py = H / 2.0 - fpx * S[1] / S[2];
+        } else {
+            px = W / 2.0 + S[0] * osc;
+            py = H / 2.0 - S[1] * osc;
+        }
+        double qx = floor(px), qy = floor(py);
+        int onscreen = front && qx >= 0 && qx < W && qy >= 0 && qy < H;
+        double fx = px - qx, fy = py - qy;
+        int edge = (fmin(fx, 1 - fx) <= edge_px) || (fmin(fy, 1 - fy) <= edge_px);
+        int in_buf = 0, ok = 0;
+        double zq = INFINITY;
+        if (onscreen) {
+            int ix = (int)qx - bx0, iy = (int)qy - by0;
+            in_buf = ix >= 0 && ix < bw && iy >= 0 && iy < bh;
+            if (in_buf) { ok = 1; zq = depth_buf[(int64_t)iy * bw + ix]; }
+            else ++*outside;
+        }
+        double thr = S[2] - bias;
+        if (ok && zq <= thr && isfinite(zq)) occ += os_smooth(R / fabs(Pv[2] - zq));
+        int margin = ok && fabs(zq - thr) <= depth_rel * fabs(S[2]);
+        /* a sample reading a pixel whose visible primitive is not
+           unique may see another correct depth there */
+        if (ok && ambiguous && ambiguous[(int64_t)((int)qy - by0) * bw + ((int)qx - bx0)]) margin = 1;
+        if ((front && edge) || near_edge || margin) ++*uns;
+    }
+    return occ;
+}
+
+/* View position and unit direction towards the eye of pixel (X, Y) at depth zz. */
+static void os_pixel_view(const os_cam* c, int W, int H, int X, int Y, double zz, double* Pv, double* V) {
+    double nx = 2.0 * (X + 0.5) / W - 1.0, ny = 1.0 - 2.0 * (Y + 0.5) / H;
+    if (c->proj == 0) {
+        Pv[0] = zz * nx * c->tanh_ * c->aspect; Pv[1] = zz * ny * c->tanh_; Pv[2] = zz;
+        double dv[3] = {nx * c->tanh_ * c->aspect, ny * c->tanh_, 1.0};
+        norm3(dv);
+        V[0] = -dv[0]; V[1] = -dv[1]; V[2] = -dv[2];
+    } else {
+        Pv[0] = nx * c->hh * c->aspect; Pv[1] = ny * c->hh; Pv[2] = zz;
+        V[0] = 0.0; V[1] = 0.0; V[2] = -1.0;
+    }
+}
+
 /* Deferred pass (SSAO, then the shading mode, fog and outline) over a
  * window.  shading: 0 glossy, 1 matte, 2 flat, 3 toon; fog from fog_start to
  * fog_end (none unless fog_end > fog_start); outline_t > 0 draws outlines.
+ * depth_buf (and normal_buf, the view normals over the same region; may be
+ * NULL when noise is 0) cover (bx0, by0, bw, bh) of the image.
+ * noise != 0 (R6b): each pixel's tangent frame is rotated about its normal
+ * by 2 pi (B[Y mod 4][X mod 4] + 1/2) / 16, B the 4x4 Bayer matrix, with the
+ * cosine and sine rounded to FP32; the AO of a hit pixel is then the mean of
+ * those raw values over the hit pixels (X + dx, Y + dy), dx, dy in
+ * {-2, -1, 0, 1}, inside the image.
  * unstable_out counts every decision FP32 may take the other way: SSAO
  * samples near a pixel edge or their depth threshold, or reading a pixel
  * flagged in `ambiguous` (over the depth buffer; may be NULL) because its
  * visible primitive is not unique, toon band edges and outline depth
- * thresholds. */
+ * thresholds; with noise, those of every raw value the blur takes.
+ * outside_out counts samples (and, with noise, blur neighbours) the buffers
+ * do not cover. */
 int osplat_shade(const double* cam, int W, int H, int x0, int y0, int w, int h,
                  const double* z, const double* nrm, const uint32_t* alb,
-                 const double* depth_buf, int bx0, int by0, int bw, int bh,
-                 int K, double R, double bias, uint32_t background, double edge_px, double depth_rel,
+                 const double* depth_buf, const double* normal_buf, int bx0, int by0, int bw, int bh,
+                 int K, double R, double bias, int noise, uint32_t background, double edge_px, double depth_rel,
                  int shading, double fog_start, double fog_end, uint32_t fog_color,
                  double outline_t, uint32_t outline_color, const uint8_t* ambiguous,
                  int nthreads, uint32_t* rgba, double* ao_out, int32_t* unstable_out, int32_t* outside_out) {
     if (K < 0 || K > 1024) return -1;
+    if (noise && !normal_buf) return -1;
     os_cam c;
     os_make_cam(cam, W, H, &c);
     double hk[1024][3], sk[1024];
@@ -527,9 +609,55 @@ int osplat_shade(const double* cam, int W, int H, int x0, int y0, int w, int h,
         double u = (k + 1.0) / K;
         sk[k] = (float)(0.1 + 0.9 * u * u);
     }
-    double fpx = (H / 2.0) / c.tanh_;
-    double osc = (H / 2.0) / c.hh;
+    double rot_c[16], rot_s[16];
+    for (int b = 0; b < 16; ++b) {
+        double th = 2.0 * OS_PI * (b + 0.5) / 16.0;
+        rot_c[b] = (float)cos(th);
+        rot_s[b] = (float)sin(th);
+    }
     if (nthreads > 0) omp_set_num_threads(nthreads);
+    /* with noise: the raw AO of every pixel of the window grown by the blur
+       footprint (two left and up, one right and down), kept inside the
+       buffers and the image */
+    int gx0 = x0, gy0 = y0, gw = 0, gh = 0;
+    double* raw = NULL;
+    int32_t *raw_uns = NULL, *raw_out = NULL;
+    uint8_t* raw_hit = NULL;
+    if (noise && K > 0) {
+        gx0 = x0 - 2 > bx0 ? x0 - 2 : bx0;
+        gy0 = y0 - 2 > by0 ? y0 - 2 : by0;
+        int gx1 = x0 + w + 1 < bx0 + bw ? x0 + w + 1 : bx0 + bw;
+        int gy1 = y0 + h + 1 < by0 + bh ? y0 + h + 1 : by0 + bh;
+        gw = gx1 - gx0;
+        gh = gy1 - gy0;
+        raw = (double*)malloc(sizeof(double) * (size_t)gw * gh);
+        raw_uns = (int32_t*)malloc(sizeof(int32_t) * (size_t)gw * gh);
+        raw_out = (int32_t*)malloc(sizeof(int32_t) * (size_t)gw * gh);
+        raw_hit = (uint8_t*)malloc((size_t)gw * gh);
+        if (!raw || !raw_uns || !raw_out || !raw_hit) { free(raw); free(raw_uns); free(raw_out); free(raw_hit); return -2; }
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int j = 0; j < gh; ++j)
+            for (int i = 0; i < gw; ++i) {
+                int X = gx0 + i, Y = gy0 + j;
+                int64_t q = (int64_t)j * gw + i;
+                int64_t qb = (int64_t)(Y - by0) * bw + (X - bx0);
+                double zz = depth_buf[qb];
+                raw_hit[q] = isfinite(zz) ? 1 : 0;
+                raw[q] = 0.0;
+                raw_uns[q] = 0;
+                raw_out[q] = 0;
+                if (!raw_hit[q]) continue;
+                double Pv[3], V[3];
+                os_pixel_view(&c, W, H, X, Y, zz, Pv, V);
+                int b = os_bayer4[Y & 3][X & 3];
+                int uns = 0, outside = 0;
+                double occ = os_ssao_pixel(&c, W, H, Pv, normal_buf + 3 * qb, K, hk, sk, R, bias, rot_c[b], rot_s[b],
+                                           depth_buf, ambiguous, bx0, by0, bw, bh, edge_px, depth_rel, &uns, &outside);
+                raw[q] = 1.0 - occ / K;
+                raw_uns[q] = uns;
+                raw_out[q] = outside;
+            }
+    }
 #pragma omp parallel for schedule(dynamic, 4)
     for (int j = 0; j < h; ++j)
         for (int i = 0; i < w; ++i) {
@@ -543,61 +671,33 @@ int osplat_shade(const double* cam, int W, int H, int x0, int y0, int w, int h,
                 outside_out[q] = 0;
                 continue;
             }
-            double nx = 2.0 * (X + 0.5) / W - 1.0, ny = 1.0 - 2.0 * (Y + 0.5) / H;
             double Pv[3], V[3];
-            if (c.proj == 0) {
-                Pv[0] = zz * nx * c.tanh_ * c.aspect; Pv[1] = zz * ny * c.tanh_; Pv[2] = zz;
-                double dv[3] = {nx * c.tanh_ * c.aspect, ny * c.tanh_, 1.0};
-                norm3(dv);
-                V[0] = -dv[0]; V[1] = -dv[1]; V[2] = -dv[2];
-            } else {
-                Pv[0] = nx * c.hh * c.aspect; Pv[1] = ny * c.hh; Pv[2] = zz;
-                V[0] = 0.0; V[1] = 0.0; V[2] = -1.0;
-            }
+            os_pixel_view(&c, W, H, X, Y, zz, Pv, V);
             const double* N = nrm + 3 * q;
             double occ = 0.0;
             int uns = 0, outside = 0;
-            if (K > 0) {
-                double T[3], B[3];
-                os_onb(N, T, B);
-                if (fabs(N[2]) <= 1e-4) uns = K;
-                for (int k = 0; k < K; ++k) {
-                    double S[3];
-                    double sc = R * sk[k];
-                    for (int a = 0; a < 3; ++a) S[a] = Pv[a] + sc * (hk[k][0] * T[a] + hk[k][1] * B[a] + hk[k][2] * N[a]);
-                    double px, py;
-                    int front = S[2] > c.znear;
-                    double za = fabs(S[2]) > c.znear ? fabs(S[2]) : c.znear;
-                    int near_edge = fabs(S[2] - c.znear) <= depth_rel * za;
-                    if (c.proj == 0) {
-                        px = W / 2.0 + fpx * S[0] / S[2];
-                        py = H / 2.0 - fpx * S[1] / S[2];
-                    } else {
-                        px = W / 2.0 + S[0] * osc;
-                        py = H / 2.0 - S[1] * osc;
+            double ao = 1.0;
+            if (K > 0 && !noise) {
+                occ = os_ssao_pixel(&c, W, H, Pv, N, K, hk, sk, R, bias, 1.0, 0.0, depth_buf, ambiguous, bx0, by0, bw,
+                                    bh, edge_px, depth_rel, &uns, &outside);
+                ao = 1.0 - occ / K;
+            } else if (K > 0) {
+                double sum = 0.0;
+                int cnt = 0;
+                for (int dy = -2; dy <= 1; ++dy)
+                    for (int dx = -2; dx <= 1; ++dx) {
+                        int QX = X + dx, QY = Y + dy;
+                        if (QX < 0 || QX >= W || QY < 0 || QY >= H) continue;
+                        if (QX < gx0 || QX >= gx0 + gw || QY < gy0 || QY >= gy0 + gh) { ++outside; continue; }
+                        int64_t g = (int64_t)(QY - gy0) * gw + (QX - gx0);
+                        if (!raw_hit[g]) continue;
+                        sum += raw[g];
+                        ++cnt;
+                        uns += raw_uns[g];
+                        outside += raw_out[g];
                     }
-                    double qx = floor(px), qy = floor(py);
-                    int onscreen = front && qx >= 0 && qx < W && qy >= 0 && qy < H;
-                    double fx = px - qx, fy = py - qy;
-                    int edge = (fmin(fx, 1 - fx) <= edge_px) || (fmin(fy, 1 - fy) <= edge_px);
-                    int in_buf = 0, ok = 0;
-                    double zq = INFINITY;
-                    if (onscreen) {
-                        int ix = (int)qx - bx0, iy = (int)qy - by0;
-                        in_buf = ix >= 0 && ix < bw && iy >= 0 && iy < bh;
-                        if (in_buf) { ok = 1; zq = depth_buf[(int64_t)iy * bw + ix]; }
-                        else ++outside;
-                    }
-                    double thr = S[2] - bias;
-                    if (ok && zq <= thr && isfinite(zq)) occ += os_smooth(R / fabs(Pv[2] - zq));
-                    int margin = ok && fabs(zq - thr) <= depth_rel * fabs(S[2]);
-                    /* a sample reading a pixel whose visible primitive is not
-                       unique may see another correct depth there */
-                    if (ok && ambiguous && ambiguous[(int64_t)((int)qy - by0) * bw + ((int)qx - bx0)]) margin = 1;
-                    if ((front && edge) || near_edge || margin) ++uns;
-                }
+                ao = cnt ? sum / cnt : 1.0;
             }
-            double ao = K > 0 ? 1.0 - occ / K : 1.0;
             double nv = dot3(N, V);
             if (nv < 0) nv = 0;
             /* shading mode: lit = ka + kd * (facing term), times AO; glossy
@@ -654,5 +754,9 @@ int osplat_shade(const double* cam, int W, int H, int x0, int y0, int w, int h,
             unstable_out[q] = uns;
             outside_out[q] = outside;
         }
+    free(raw);
+    free(raw_uns);
+    free(raw_out);
+    free(raw_hit);
     return 0;
 }

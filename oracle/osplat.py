@@ -45,9 +45,9 @@ def lib():
                                      P, P, P, P, P, P, P, P, P, P, P]
         L.osplat_shade.restype = ctypes.c_int
         L.osplat_shade.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                   ctypes.c_int, ctypes.c_int, P, P, P, P,
+                                   ctypes.c_int, ctypes.c_int, P, P, P, P, P,
                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                   ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
+                                   ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_uint32,
                                    ctypes.c_double, ctypes.c_double,
                                    ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
                                    ctypes.c_double, ctypes.c_uint32, P,
@@ -122,11 +122,18 @@ def gbuffer(scene, cam, opts, W, H, window=None, nthreads=None):
 
 
 def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=None, depth_win=None,
-                  nthreads=None, edge_px=1e-3, depth_rel=1e-5, ambiguous=None):
+                  nthreads=None, edge_px=1e-3, depth_rel=1e-5, ambiguous=None, normal_buf=None):
     """Deferred pass over the window (see ofull.shade_gbuffer, same arguments)."""
     x0, y0, w, h = window
     if depth_buf is None:
         depth_buf, depth_win = z, window
+        normal_buf = normal_view
+    if normal_buf is None:
+        normal_buf = normal_view if tuple(depth_win) == tuple(window) else None
+    noise = int(getattr(opts, "ssao_noise", 0))
+    if noise and normal_buf is None:
+        raise ValueError("SSAO noise needs the normals over the depth buffer (normal_buf)")
+    nb = None if normal_buf is None else np.ascontiguousarray(normal_buf, dtype=np.float64)
     amb = None if ambiguous is None else np.ascontiguousarray(ambiguous, dtype=np.uint8)
     zz = np.ascontiguousarray(z, dtype=np.float64)
     nn = np.ascontiguousarray(normal_view, dtype=np.float64)
@@ -140,8 +147,9 @@ def shade_gbuffer(cam, opts, W, H, window, z, normal_view, albedo, depth_buf=Non
     outside = np.empty(P, dtype=np.int32)
     ca = cam_array(cam)
     rc = lib().osplat_shade(_ptr(ca), W, H, x0, y0, w, h, _ptr(zz), _ptr(nn), _ptr(al), _ptr(db),
+                            None if nb is None else _ptr(nb),
                             bx0, by0, bw, bh, int(opts.ssao_samples), float(opts.ssao_radius),
-                            float(opts.ssao_bias), int(opts.background) & 0xFFFFFFFF,
+                            float(opts.ssao_bias), noise, int(opts.background) & 0xFFFFFFFF,
                             float(edge_px), float(depth_rel), int(getattr(opts, "shading", 0)),
                             float(getattr(opts, "fog_start", 0.0)), float(getattr(opts, "fog_end", 0.0)),
                             int(getattr(opts, "fog_color", 0)) & 0xFFFFFFFF,
@@ -170,7 +178,7 @@ def render(scene, cam, opts, W, H, window=None, halo=0, nthreads=None, edge_px=1
     from oracle.ofull import ambiguous_pixels
     sh = shade_gbuffer(cam, opts, W, H, window, inner["z"], inner["normal_view"], inner["albedo"],
                        depth_buf=g["z"], depth_win=gwin, nthreads=nthreads, edge_px=edge_px,
-                       depth_rel=depth_rel, ambiguous=ambiguous_pixels(g))
+                       depth_rel=depth_rel, ambiguous=ambiguous_pixels(g), normal_buf=g["normal_view"])
     inner.update(sh)
     inner["view"] = (cam, W, H, window)
     return inner

@@ -460,6 +460,7 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
         return fail(VTX_EINVAL, "ssao_samples must be in 0..%d", VTX_MAX_SSAO_SAMPLES);
     if (o.ssao_samples > 0 && (!(o.ssao_radius >= 0.0f) || !std::isfinite(o.ssao_radius) || !std::isfinite(o.ssao_bias)))
         return fail(VTX_EINVAL, "ssao radius/bias must be finite, radius >= 0");
+    if (o.ssao_noise != 0 && o.ssao_noise != 1) return fail(VTX_EINVAL, "ssao_noise must be 0 or 1");
     if (o.tile_size != 0 && o.tile_size != 8 && o.tile_size != 16 && o.tile_size != 32 && o.tile_size != 64)
         return fail(VTX_EINVAL, "tile_size must be 0, 8, 16, 32 or 64");
     if (o.representation < VTX_REP_BALL_AND_STICK || o.representation > VTX_REP_SAS)
@@ -584,6 +585,7 @@ vtx_options resolve_options(const vtx_options* opt) {
     o.outline_depth = 0.0f;
     for (float& v : o.clip_plane) v = 0.0f;
     o.supersample = 1;
+    o.ssao_noise = 0;
     return opt ? *opt : o;
 }
 
@@ -604,8 +606,13 @@ void sample_kernel(const vtx_options& o, vtx::SampleKernel* K) {
     K->radius = o.ssao_radius;
     K->bias = o.ssao_bias;
     K->background = o.background;
+    K->noise = o.ssao_noise;
     const double golden = 0.6180339887498949;
     const double two_pi = 6.283185307179586;
+    for (int b = 0; b < 16; ++b) {
+        const double th = two_pi * (b + 0.5) / 16.0;
+        K->rot[b] = make_float2((float)std::cos(th), (float)std::sin(th));
+    }
     for (int k = 0; k < o.ssao_samples; ++k) {
         const double ct = 1.0 - (k + 0.5) / o.ssao_samples;
         const double st = std::sqrt(1.0 - ct * ct);
@@ -1124,8 +1131,10 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
     }
     VTX_HIP(mark(5));
     if (shade) {
-        if (n == 1) VTX_HIP(vtx::launch_shade(one(g_shade), g_shade, stream));
-        else VTX_HIP(vtx::launch_shade(list_of(0, n, 2 * (n + 1)), g_shade, stream));
+        bool noise = false;
+        for (size_t i = 0; i < n; ++i) noise |= d[i].K.noise != 0 && d[i].K.count > 0;
+        if (n == 1) VTX_HIP(vtx::launch_shade(one(g_shade), g_shade, noise, stream));
+        else VTX_HIP(vtx::launch_shade(list_of(0, n, 2 * (n + 1)), g_shade, noise, stream));
         for (size_t i = 0; i < n; ++i)
             if (d[i].ss > 1)
                 VTX_HIP(vtx::launch_downsample(jobs[i].depth, jobs[i].id, jobs[i].rgba, d[i].F.W / d[i].ss,
@@ -1357,7 +1366,7 @@ int vtx_render_static(const float* positions, const float* radii, const uint32_t
     js.blocks = (uint32_t)T;
     VTX_HIP(vtx::launch_resolve(js, F.tile, vtx::kPhaseAll, (uint32_t)T, count, ovf, ovf_n, st));
     js.blocks = vtx::shade_blocks(F);
-    VTX_HIP(vtx::launch_shade(js, js.blocks, st));
+    VTX_HIP(vtx::launch_shade(js, js.blocks, js.K.noise != 0 && js.K.count > 0, st));
     return VTX_OK;
 }
 

@@ -32,55 +32,39 @@ __device__ inline uint32_t quantize(float c) {
     return (uint32_t)floorf(fmaf(255.0f, c, 0.5f));
 }
 
-// Work block t of a job is that job's 16x16 tile t.
-template <class JS>
-__global__ void __launch_bounds__(kBlock) k_shade(JS js) {
-    uint32_t tu;
-    const int ji = js.find((uint32_t)xcd_contiguous(blockIdx.x, gridDim.x), tu);
-    if (ji < 0) return;
-    const Job& J = js.job(ji);
-    const Frame F = J.F;
-    const SampleKernel& K = js.samples(ji);
+// The surface a G-buffer pixel shows: its view position on the pixel's ray,
+// the direction towards the eye, the unit normal and the albedo.
+struct Surface {
+    float Px, Py, Pz;
+    float Vx, Vy, Vz;
+    float nx, ny, nz;
+    uint32_t alb;
+    bool hit;
+};
+
+__device__ inline Surface surface_at(const Job& J, const Frame& F, int x, int y, uint32_t pid, float z) {
     const float* __restrict__ const pos = J.pos;
     const uint32_t* __restrict__ const col = J.col;
     const uint32_t* __restrict__ const bonds = J.bonds;
-    const float* __restrict__ const depth = J.depth;
-    const uint32_t* __restrict__ const ids = J.id;
-    uint32_t* __restrict__ const rgba = J.rgba;
-    float* __restrict__ const normal_out = J.normal;
-    uint32_t* __restrict__ const albedo_out = J.albedo;
-    float* __restrict__ const ao_out = J.ao;
-    const int tiles_x = (F.W + kTile - 1) / kTile;
-    const int t = (int)tu;
-    const int tid = threadIdx.x;
-    const int tx0 = (t % tiles_x) * kTile, ty0 = (t / tiles_x) * kTile;
-    const int x = tx0 + (tid & (kTile - 1)), y = ty0 + (tid >> 4);
-    if (x >= F.W || y >= F.H) return;
-    const size_t p = (size_t)y * F.W + x;
-    const uint32_t pid = ids[p];
-    const float z = depth[p];
-    const uint32_t nprim = F.n_atoms + F.n_bonds;
-
+    Surface s;
     const float ndx = fmaf((float)x + 0.5f, F.inv_w2, -1.0f);
     const float ndy = fmaf(-((float)y + 0.5f), F.inv_h2, 1.0f);
-    float Px, Py, Vx, Vy, Vz;
     if (F.proj == 0) {
         const float Dx = ndx * F.txf, Dy = ndy * F.tyf;
-        Px = z * Dx;
-        Py = z * Dy;
+        s.Px = z * Dx;
+        s.Py = z * Dy;
         const float inv = rsqrtf(fmaf(Dx, Dx, fmaf(Dy, Dy, 1.0f)));
-        Vx = -Dx * inv; Vy = -Dy * inv; Vz = -inv;
+        s.Vx = -Dx * inv; s.Vy = -Dy * inv; s.Vz = -inv;
     } else {
-        Px = ndx * F.hxf;
-        Py = ndy * F.hyf;
-        Vx = 0.f; Vy = 0.f; Vz = -1.f;
+        s.Px = ndx * F.hxf;
+        s.Py = ndy * F.hyf;
+        s.Vx = 0.f; s.Vy = 0.f; s.Vz = -1.f;
     }
-    const float Pz = z;
-
-    bool hit = pid < nprim && z < INFINITY;
+    s.Pz = z;
+    s.hit = pid < F.n_atoms + F.n_bonds && z < INFINITY;
     float nx = 0.f, ny = 0.f, nz = 0.f;
-    uint32_t alb = 0;
-    if (hit) {
+    s.alb = 0;
+    if (s.hit) {
         // The surface point relative to the primitive, in FP64: P = z D on the
         // pixel's ray (D = (ndx tx, ndy ty, 1), or the orthographic origin
         // plus z f), less the primitive's FP64 view coordinates.  Its error is
@@ -97,12 +81,12 @@ __global__ void __launch_bounds__(kBlock) k_shade(JS js) {
             nx = (float)(Qx - cx);
             ny = (float)(Qy - cy);
             nz = (float)(zd - cz);
-            alb = col[pid];
+            s.alb = col[pid];
         } else {
             const size_t b = pid - F.n_atoms;
             const uint32_t ia = bonds[2 * b], ib = bonds[2 * b + 1];
             if (ia >= F.n_atoms || ib >= F.n_atoms) {
-                hit = false;
+                s.hit = false;
             } else {
                 double A[3], B[3];
                 to_view(F, pos[3 * (size_t)ia], pos[3 * (size_t)ia + 1], pos[3 * (size_t)ia + 2], A[0], A[1], A[2]);
@@ -121,64 +105,158 @@ __global__ void __launch_bounds__(kBlock) k_shade(JS js) {
                 const double d_side = fabs(ql - (double)F.bond_radius), d_a = fabs(sd), d_b = fabs(sd - L);
                 if (d_side <= fmin(d_a, d_b)) {
                     nx = (float)qx; ny = (float)qy; nz = (float)qz;
-                    alb = sd < 0.5 * L ? col[ia] : col[ib];
+                    s.alb = sd < 0.5 * L ? col[ia] : col[ib];
                 } else if (d_a <= d_b) {
                     nx = (float)-ax; ny = (float)-ay; nz = (float)-az;
-                    alb = col[ia];
+                    s.alb = col[ia];
                 } else {
                     nx = (float)ax; ny = (float)ay; nz = (float)az;
-                    alb = col[ib];
+                    s.alb = col[ib];
                 }
             }
         }
         const float inv = rsqrtf(fmaf(nx, nx, fmaf(ny, ny, nz * nz)));
         nx *= inv; ny *= inv; nz *= inv;
     }
+    s.nx = nx; s.ny = ny; s.nz = nz;
+    return s;
+}
+
+// Ambient occlusion of a hit surface at pixel (x, y): K hemisphere samples
+// in the normal's tangent frame (kTurn: turned about the normal by the
+// cosine and sine (rc, rs)), each compared with the depth of the pixel it
+// projects to.
+template <bool kTurn>
+__device__ inline float ssao_at(const Frame& F, const SampleKernel& K, const float* __restrict__ depth, int x, int y,
+                                const Surface& s, float rc, float rs) {
+    const float nx = s.nx, ny = s.ny, nz = s.nz, Px = s.Px, Py = s.Py, Pz = s.Pz;
+    // orthonormal basis from the normal (Duff et al., JCGT 2017, branchless
+    // form), turned about the normal: T' = rc T + rs B, B' = rc B - rs T
+    const float sg = copysignf(1.0f, nz);
+    const float a = -1.0f / (sg + nz);
+    const float bb = nx * ny * a;
+    const float T0x = 1.0f + sg * nx * nx * a, T0y = sg * bb, T0z = -sg * nx;
+    const float B0x = bb, B0y = sg + ny * ny * a, B0z = -ny;
+    const float Tx = kTurn ? fmaf(rc, T0x, rs * B0x) : T0x, Ty = kTurn ? fmaf(rc, T0y, rs * B0y) : T0y,
+                Tz = kTurn ? fmaf(rc, T0z, rs * B0z) : T0z;
+    const float Bx = kTurn ? fmaf(rc, B0x, -rs * T0x) : B0x, By = kTurn ? fmaf(rc, B0y, -rs * T0y) : B0y,
+                Bz = kTurn ? fmaf(rc, B0z, -rs * T0z) : B0z;
+    const float fpx = 0.5f * (float)F.H / F.tyf;
+    const float osc = 0.5f * (float)F.H / F.hyf;
+    float occ = 0.0f;
+    // Samples are taken kBatch at a time: every address first, then the
+    // loads, then the tests in sample order, so the loads of a batch are
+    // in flight together.  Branch-free: an invalid sample (past the count, behind the near
+    // plane, off the image) reads the pixel's own depth and is masked out
+    // (sz = -inf); entries of h past the count exist (zero).  Byte offsets
+    // into the depth image fit 32 bits (at most 4^2 x 7680 x 4320 pixels).
+    const float hw = 0.5f * (float)F.W, hh = 0.5f * (float)F.H;
+    const uint32_t own = (uint32_t)(y * F.W + x) << 2;
+    for (int k0 = 0; k0 < K.count; k0 += kBatch) {
+        float zq[kBatch], sz[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int k = k0 + u;
+            const float4 h = K.h[k];   // offset in the (T, B, n) frame, scaled
+            const float Sx = fmaf(h.x, Tx, fmaf(h.y, Bx, fmaf(h.z, nx, Px)));
+            const float Sy = fmaf(h.x, Ty, fmaf(h.y, By, fmaf(h.z, ny, Py)));
+            const float Sz = fmaf(h.x, Tz, fmaf(h.y, Bz, fmaf(h.z, nz, Pz)));
+            // hardware reciprocal (1 ulp): moves the sample by far less than
+            // the 1e-3 px within which a pixel edge makes a sample unstable
+            const float sc = F.proj == 0 ? fpx * __builtin_amdgcn_rcpf(Sz) : osc;
+            const float spx = fmaf(Sx, sc, hw), spy = fmaf(-Sy, sc, hh);
+            // & rather than &&: all tests evaluated, no branches per sample
+            const bool ok = (k < K.count) & (Sz > F.znear) & (spx >= 0.0f) & (spx < (float)F.W) & (spy >= 0.0f) &
+                            (spy < (float)F.H);
+            const uint32_t off = ok ? (uint32_t)((int)spy * F.W + (int)spx) << 2 : own;
+            zq[u] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(depth) + off);
+            sz[u] = ok ? Sz : -INFINITY;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+            if (zq[u] <= sz[u] - K.bias) occ += smooth01(K.radius * __builtin_amdgcn_rcpf(fabsf(Pz - zq[u])));
+    }
+    return 1.0f - occ / (float)K.count;
+}
+
+// Rank of pixel (x, y) in the 4x4 ordered-dither (Bayer) tile: the index of
+// its sample rotation.
+__device__ inline int noise_rank(int x, int y) {
+    constexpr uint32_t kRows[4] = {0xA280u, 0x6E4Cu, 0x91B3u, 0x5D7Fu};   // 4 bits per column, column 0 lowest
+    return (int)((kRows[y & 3] >> (4 * (x & 3))) & 15u);
+}
+
+// Work block t of a job is that job's 16x16 tile t.  kNoise: the
+// instantiation that can take the noise form (launched when a job asks for
+// it; the plain one carries none of its code).
+template <class JS, bool kNoise>
+__global__ void __launch_bounds__(kBlock) k_shade(JS js) {
+    // noise form: the raw AO of the tile and of the 2 pixels left and above
+    // and 1 right and below it that the 4x4 blur reads (-1: not a hit)
+    constexpr int kHalo = kTile + 3;
+    __shared__ float raw[kNoise ? kHalo * kHalo : 1];
+    uint32_t tu;
+    const int ji = js.find((uint32_t)xcd_contiguous(blockIdx.x, gridDim.x), tu);
+    if (ji < 0) return;
+    const Job& J = js.job(ji);
+    const Frame F = J.F;
+    const SampleKernel& K = js.samples(ji);
+    const float* __restrict__ const depth = J.depth;
+    const uint32_t* __restrict__ const ids = J.id;
+    uint32_t* __restrict__ const rgba = J.rgba;
+    float* __restrict__ const normal_out = J.normal;
+    uint32_t* __restrict__ const albedo_out = J.albedo;
+    float* __restrict__ const ao_out = J.ao;
+    const int tiles_x = (F.W + kTile - 1) / kTile;
+    const int t = (int)tu;
+    const int tid = threadIdx.x;
+    const int tx0 = (t % tiles_x) * kTile, ty0 = (t / tiles_x) * kTile;
+    const int x = tx0 + (tid & (kTile - 1)), y = ty0 + (tid >> 4);
+    const bool noise = kNoise && K.noise && K.count > 0;   // the same for the whole workgroup (one job)
+    if (noise) {
+        for (int i = tid; i < kHalo * kHalo; i += kBlock) {
+            const int qx = tx0 - 2 + i % kHalo, qy = ty0 - 2 + i / kHalo;
+            float v = -1.0f;
+            if (qx >= 0 && qx < F.W && qy >= 0 && qy < F.H) {
+                const size_t q = (size_t)qy * F.W + qx;
+                const Surface sq = surface_at(J, F, qx, qy, ids[q], depth[q]);
+                if (sq.hit) {
+                    const float2 r = K.rot[noise_rank(qx, qy)];
+                    v = ssao_at<true>(F, K, depth, qx, qy, sq, r.x, r.y);
+                }
+            }
+            raw[i] = v;
+        }
+        __syncthreads();
+    }
+    if (x >= F.W || y >= F.H) return;
+    const size_t p = (size_t)y * F.W + x;
+    const float z = depth[p];
+    const Surface sf = surface_at(J, F, x, y, ids[p], z);
+    const bool hit = sf.hit;
+    const float nx = sf.nx, ny = sf.ny, nz = sf.nz, Vx = sf.Vx, Vy = sf.Vy, Vz = sf.Vz;
+    const uint32_t alb = sf.alb;
 
     float ao = 1.0f;
-    if (hit && K.count > 0) {
-        // orthonormal basis from the normal (Duff et al., JCGT 2017, branchless form)
-        const float sg = copysignf(1.0f, nz);
-        const float a = -1.0f / (sg + nz);
-        const float bb = nx * ny * a;
-        const float Tx = 1.0f + sg * nx * nx * a, Ty = sg * bb, Tz = -sg * nx;
-        const float Bx = bb, By = sg + ny * ny * a, Bz = -ny;
-        const float fpx = 0.5f * (float)F.H / F.tyf;
-        const float osc = 0.5f * (float)F.H / F.hyf;
-        float occ = 0.0f;
-        // Samples are taken kBatch at a time: every address first, then the
-        // loads, then the tests in sample order, so the loads of a batch are
-        // in flight together.  Branch-free: an invalid sample (past the count, behind the near
-        // plane, off the image) reads the pixel's own depth and is masked out
-        // (sz = -inf); entries of h past the count exist (zero).  Byte offsets
-        // into the depth image fit 32 bits (at most 4^2 x 7680 x 4320 pixels).
-        const float hw = 0.5f * (float)F.W, hh = 0.5f * (float)F.H;
-        const uint32_t own = (uint32_t)(y * F.W + x) << 2;
-        for (int k0 = 0; k0 < K.count; k0 += kBatch) {
-            float zq[kBatch], sz[kBatch];
+    if (hit && noise) {
+        // the mean of the raw AO over the hit pixels of the 4x4 block at
+        // offsets -2..1 (the halo holds the ones outside the tile)
+        const int lx = x - tx0 + 2, ly = y - ty0 + 2;
+        float sum = 0.0f;
+        int cnt = 0;
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                const int k = k0 + u;
-                const float4 h = K.h[k];   // offset in the (T, B, n) frame, scaled
-                const float Sx = fmaf(h.x, Tx, fmaf(h.y, Bx, fmaf(h.z, nx, Px)));
-                const float Sy = fmaf(h.x, Ty, fmaf(h.y, By, fmaf(h.z, ny, Py)));
-                const float Sz = fmaf(h.x, Tz, fmaf(h.y, Bz, fmaf(h.z, nz, Pz)));
-                // hardware reciprocal (1 ulp): moves the sample by far less than
-                // the 1e-3 px within which a pixel edge makes a sample unstable
-                const float sc = F.proj == 0 ? fpx * __builtin_amdgcn_rcpf(Sz) : osc;
-                const float spx = fmaf(Sx, sc, hw), spy = fmaf(-Sy, sc, hh);
-                // & rather than &&: all tests evaluated, no branches per sample
-                const bool ok = (k < K.count) & (Sz > F.znear) & (spx >= 0.0f) & (spx < (float)F.W) & (spy >= 0.0f) &
-                                (spy < (float)F.H);
-                const uint32_t off = ok ? (uint32_t)((int)spy * F.W + (int)spx) << 2 : own;
-                zq[u] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(depth) + off);
-                sz[u] = ok ? Sz : -INFINITY;
+        for (int dy = -2; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -2; dx <= 1; ++dx) {
+                const float v = raw[(ly + dy) * kHalo + (lx + dx)];
+                if (v >= 0.0f) {
+                    sum += v;
+                    ++cnt;
+                }
             }
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u)
-                if (zq[u] <= sz[u] - K.bias) occ += smooth01(K.radius * __builtin_amdgcn_rcpf(fabsf(Pz - zq[u])));
-        }
-        ao = 1.0f - occ / (float)K.count;
+        ao = sum / (float)cnt;
+    } else if (hit && K.count > 0) {
+        ao = ssao_at<false>(F, K, depth, x, y, sf, 1.0f, 0.0f);
     }
 
     uint32_t out = K.background;
@@ -270,12 +348,17 @@ hipError_t launch_downsample(const float* sdepth, const uint32_t* sid, const uin
 }
 
 template <class JS>
-hipError_t shade_impl(const JS& js, uint32_t grid, hipStream_t stream) {
+hipError_t shade_impl(const JS& js, uint32_t grid, bool noise, hipStream_t stream) {
     if (grid == 0) return hipSuccess;
-    return dispatch(k_shade<JS>, (unsigned)xcd_grid((int)grid), kBlock, 0, stream, js);
+    if (noise) return dispatch(k_shade<JS, true>, (unsigned)xcd_grid((int)grid), kBlock, 0, stream, js);
+    return dispatch(k_shade<JS, false>, (unsigned)xcd_grid((int)grid), kBlock, 0, stream, js);
 }
 
-hipError_t launch_shade(const OneJob& js, uint32_t grid, hipStream_t stream) { return shade_impl(js, grid, stream); }
-hipError_t launch_shade(const JobList& js, uint32_t grid, hipStream_t stream) { return shade_impl(js, grid, stream); }
+hipError_t launch_shade(const OneJob& js, uint32_t grid, bool noise, hipStream_t stream) {
+    return shade_impl(js, grid, noise, stream);
+}
+hipError_t launch_shade(const JobList& js, uint32_t grid, bool noise, hipStream_t stream) {
+    return shade_impl(js, grid, noise, stream);
+}
 
 }  // namespace vtx

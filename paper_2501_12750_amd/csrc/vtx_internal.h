@@ -76,9 +76,13 @@ __host__ __device__ inline float atom_radius(const Frame& F, float r) {
 // (the radius times the sample's scale), h[k].w that length.
 struct SampleKernel {
     float4 h[kMaxSamples];
+    // noise form (options.ssao_noise): the turn of the tangent frame of a
+    // pixel of 4x4-tile rank b, (cos, sin) of 2 pi (b + 1/2) / 16
+    float2 rot[16];
     int32_t count;
     float radius, bias;
     uint32_t background;
+    int32_t noise;
 };
 
 // Device-side counters of one frame.  The scatter's first workgroup
@@ -464,7 +468,8 @@ hipError_t launch_resolve(const JobList& js, int tile, int phase, uint32_t grid,
 // (depth, id)).
 hipError_t launch_downsample(const float* sdepth, const uint32_t* sid, const uint32_t* srgba, int W, int H, int S,
                              float* depth, uint32_t* id, uint32_t* rgba, hipStream_t stream);
-hipError_t launch_shade(const OneJob& js, uint32_t grid, hipStream_t stream);
-hipError_t launch_shade(const JobList& js, uint32_t grid, hipStream_t stream);
+// `noise`: some job asks for the noise form of the ambient occlusion.
+hipError_t launch_shade(const OneJob& js, uint32_t grid, bool noise, hipStream_t stream);
+hipError_t launch_shade(const JobList& js, uint32_t grid, bool noise, hipStream_t stream);
 
 }  // namespace vtx

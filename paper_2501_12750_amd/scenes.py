@@ -88,6 +88,7 @@ class Options:
     outline_depth: float = 0.0   # relative depth step of an outline; 0: none
     clip_plane: tuple = (0.0, 0.0, 0.0, 0.0)   # a, b, c, d: a x + b y + c z + d >= 0 is kept
     supersample: int = 1         # samples per pixel side (1..4)
+    ssao_noise: int = 0          # 1: per-pixel rotation of the SSAO samples from a 4x4 table, then a 4x4 blur
 
     def __post_init__(self):
         self.bond_radius = f32(self.bond_radius)

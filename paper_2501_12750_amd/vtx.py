@@ -61,7 +61,7 @@ class vtx_options(ctypes.Structure):
                 ("representation", ctypes.c_int32), ("probe_radius", ctypes.c_float),
                 ("shading", ctypes.c_int32), ("fog_color", ctypes.c_uint32), ("fog_start", ctypes.c_float),
                 ("fog_end", ctypes.c_float), ("outline_color", ctypes.c_uint32), ("outline_depth", ctypes.c_float),
-                ("clip_plane", ctypes.c_float * 4), ("supersample", ctypes.c_int32)]
+                ("clip_plane", ctypes.c_float * 4), ("supersample", ctypes.c_int32), ("ssao_noise", ctypes.c_int32)]
 
 
 class vtx_stats(ctypes.Structure):
@@ -268,6 +268,7 @@ def options_struct(opts) -> vtx_options:
     o.outline_depth = float(getattr(opts, "outline_depth", 0.0))
     o.clip_plane[:] = [float(v) for v in getattr(opts, "clip_plane", (0.0, 0.0, 0.0, 0.0))]
     o.supersample = int(getattr(opts, "supersample", 1))
+    o.ssao_noise = int(getattr(opts, "ssao_noise", 0))
     return o
 
 

@@ -396,3 +396,22 @@ def test_clip_plane(vtx, proj):
     base = run_render(vtx, vtx.DeviceScene(wl.scene), wl.camera, with_opts(wl.options, clip_plane=(0.0, 0.0, 0.0, 0.0)),
                       wl.width, wl.height)
     assert np.count_nonzero(dev["id"] != base["id"]) > 1000
+
+
+@pytest.mark.parametrize("proj", ["persp", "ortho"])
+def test_ssao_noise(vtx, proj):
+    """The noise form of the ambient occlusion (per-pixel rotation from the
+    4x4 Bayer table, 4x4 blur): cross-fed over the whole frame and end to end
+    against the oracle; it differs from the plain form's image."""
+    wl = scenes.ball_and_stick(n_globules=27, atoms_per_globule=300, sigma=5.0, pitch=8.0,
+                               width=333, height=221, ssao_samples=16)
+    if proj == "ortho":
+        c = wl.camera.target
+        wl.camera = scenes.Camera(eye=(c[0] + 5.0, c[1] + 60.0, c[2] + 7.0), target=c, up=(0, 0, 1),
+                                  projection=scenes.ORTHOGRAPHIC, ortho_half_height=25.0)
+    plain = run_render(vtx, vtx.DeviceScene(wl.scene), wl.camera, wl.options, wl.width, wl.height)
+    wl.options = with_opts(wl.options, ssao_noise=1)
+    dev, ref, rep = full_parity(vtx, wl, name=f"ssao noise {proj}")
+    assert rep["shade_checked"] > 0.8 * rep["pixels"] and rep["e2e_checked"] > 0.7 * rep["pixels"]
+    assert np.array_equal(plain["id"], dev["id"])
+    assert np.count_nonzero(plain["rgba"] != dev["rgba"]) > 1000

@@ -153,3 +153,24 @@ def test_clip_plane_agrees():
     full = osplat.render(wl.scene, wl.camera, wl.options, wl.width, wl.height)
     assert np.count_nonzero(a["id"] != full["id"]) > 200
     assert np.any(a["id"] >= wl.scene.n_atoms) and np.any((a["id"] < wl.scene.n_atoms))
+
+
+def test_ssao_noise_agrees_full_frame_and_crop():
+    """The noise form of SSAO (rotation and 4x4 blur): both oracles give the
+    same AO, colours and unstable counts on a full frame, and a crop with a
+    halo gives the full frame's values where its blur footprint is covered."""
+    wl = scenes.ball_and_stick(n_globules=8, atoms_per_globule=200, sigma=4.0, pitch=6.0,
+                               width=100, height=90, ssao_samples=16)
+    opts = scenes.Options(**{**wl.options.__dict__, "ssao_noise": 1})
+    a = ofull.render(wl.scene, wl.camera, opts, wl.width, wl.height)
+    b = osplat.render(wl.scene, wl.camera, opts, wl.width, wl.height)
+    assert_same(a, b, shading=True)
+    plain = osplat.render(wl.scene, wl.camera, wl.options, wl.width, wl.height)
+    assert not np.array_equal(plain["ao"], b["ao"])
+    win = (31, 22, 30, 28)
+    crop = osplat.render(wl.scene, wl.camera, opts, wl.width, wl.height, window=win, halo=24)
+    sl = (slice(win[1], win[1] + win[3]), slice(win[0], win[0] + win[2]))
+    ok = crop["ssao_outside"] == 0
+    assert ok.mean() > 0.9
+    assert np.array_equal(crop["rgba"][ok], b["rgba"][sl][ok])
+    assert np.allclose(crop["ao"][ok], b["ao"][sl][ok], rtol=0, atol=1e-12)

@@ -505,6 +505,79 @@ def test_ssao_step_occlusion_from_geometry(oracle, K, gap, wgt):
     assert np.allclose(res["ao"][m], exp[m], atol=1e-12)
 
 
+# the 4x4 ordered-dither (Bayer) matrix, row by row: entry (row j, column i)
+# orders the 16 cells of the tile so that consecutive ranks lie far apart
+BAYER = [[0, 8, 2, 10], [12, 4, 14, 6], [3, 11, 1, 9], [15, 7, 13, 5]]
+
+
+@pytest.mark.parametrize("K", [2, 16])
+def test_ssao_noise_rotation_and_blur_from_geometry(oracle, K):
+    """The step scene of the test above (gap 4.5, weight 7/27) with the noise
+    form of SSAO.  Pixel (i, j) turns its tangent frame about the normal by
+    t = 2 pi (BAYER[j % 4][i % 4] + 1/2) / 16: with T = (1, 0, 0) and
+    B = (0, -1, 0) the turned frame is T' = (cos t, -sin t, 0) and
+    B' = (-sin t, -cos t, 0), so a sample with hemisphere direction h and
+    scale s lands R s (h.x cos t - h.y sin t, -h.x sin t - h.y cos t) away in
+    the view plane.  The raw AO of far-disk pixels follows as before, near-disk
+    pixels see nothing nearer (raw AO 1), and the AO of a pixel is the mean of
+    the raw AO over the hit pixels of its 4x4 block of offsets -2..1."""
+    W, H, hh = 64, 48, 4.0
+    R, bias, gap = 1.5, 0.05, 4.5
+    wgt = 7.0 / 27.0
+    cam = ortho(eye=(0.0, 0.0, 20.0), target=(0.0, 0.0, 0.0), half_h=hh)
+    near_c, near_r = (7.0, 0.3), 6.0
+    sc = _cap_scene([(0.0, 0.0, 0.0, scenes.pack_rgba(200, 200, 200)),
+                     (near_c[0], near_c[1], gap, scenes.pack_rgba(90, 90, 90))])
+    opts = scenes.Options(bond_radius=near_r, ssao_samples=K, ssao_radius=R, ssao_bias=bias, ssao_noise=1)
+    res = oracle.render(sc, cam, opts, W, H)
+    scale = (H / 2) / hh
+    jj, ii = np.mgrid[0:H, 0:W]
+    X = (ii + 0.5 - W / 2) / scale
+    Y = (H / 2 - jj - 0.5) / scale
+    on_near = (X - near_c[0]) ** 2 + (Y - near_c[1]) ** 2 <= near_r ** 2
+    on_far = (X ** 2 + Y ** 2 <= near_r ** 2) & ~on_near
+    hit = on_near | on_far
+    t = 2 * math.pi * (np.array(BAYER)[jj % 4, ii % 4] + 0.5) / 16
+    ct, st_ = np.cos(t).astype(np.float32).astype(np.float64), np.sin(t).astype(np.float32).astype(np.float64)
+    raw = np.ones((H, W))
+    for k in range(K):
+        c = 1.0 - (k + 0.5) / K
+        sn = math.sqrt(1 - c * c)
+        ph = 2 * math.pi * ((k * 0.6180339887498949) % 1.0)
+        hx, hy, hz = (float(np.float32(v)) for v in (sn * math.cos(ph), sn * math.sin(ph), c))
+        s = float(np.float32(0.1 + 0.9 * ((k + 1) / K) ** 2))
+        sx = X + R * s * (hx * ct - hy * st_)
+        sy = Y + R * s * (-hx * st_ - hy * ct)
+        sz = 20.0 - R * s * hz
+        qx = np.floor(W / 2 + sx * scale)
+        qy = np.floor(H / 2 - sy * scale)
+        cxq = (qx + 0.5 - W / 2) / scale
+        cyq = (H / 2 - qy - 0.5) / scale
+        q_near = (cxq - near_c[0]) ** 2 + (cyq - near_c[1]) ** 2 <= near_r ** 2
+        inside = (qx >= 0) & (qx < W) & (qy >= 0) & (qy < H)
+        occl = on_far & inside & q_near & (20.0 - gap <= sz - bias)
+        raw -= np.where(occl, wgt / K, 0.0)
+    total = np.zeros((H, W))
+    count = np.zeros((H, W))
+    for dy in (-2, -1, 0, 1):
+        for dx in (-2, -1, 0, 1):
+            qi, qj = ii + dx, jj + dy
+            ok = (qi >= 0) & (qi < W) & (qj >= 0) & (qj < H)
+            qi, qj = np.where(ok, qi, 0), np.where(ok, qj, 0)
+            take = ok & hit[qj, qi]
+            total += np.where(take, raw[qj, qi], 0.0)
+            count += take
+    exp = np.where(count > 0, total / np.maximum(count, 1), 1.0)
+    m = hit & (res["ssao_unstable"] == 0)
+    assert m.sum() > 500
+    assert np.any(exp[m] < 1.0) and np.any(exp[m] > exp[m].min())
+    assert np.allclose(res["ao"][m], exp[m], atol=1e-12)
+    # the noise changes the raw samples but a flat, unoccluded surface stays at 1
+    flat = oracle.render(_cap_scene([(0.0, 0.0, 0.0, scenes.pack_rgba(200, 200, 200))]), cam,
+                         scenes.Options(bond_radius=50.0, ssao_samples=K, ssao_radius=2.0, ssao_noise=1), W, H)
+    assert np.all(flat["ao"] == 1.0)
+
+
 # ---------------------------------------------------------------------------
 # representations: the same impostors with other radii / without bonds
 # ---------------------------------------------------------------------------
