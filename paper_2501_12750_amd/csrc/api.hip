@@ -1100,6 +1100,8 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
                 if (n == 1) VTX_HIP(vtx::launch_layers(one(g_bin), g_bin, stream));
                 else VTX_HIP(vtx::launch_layers(list_of(0, n, n + 1), g_bin, stream));
             }
+            if (n == 1) VTX_HIP(vtx::launch_tile_offsets(one(g_bin), stream));
+            else VTX_HIP(vtx::launch_tile_offsets(list_of(0, n, n + 1), stream));
             VTX_HIP(mark(3));
             if (n == 1) VTX_HIP(vtx::launch_scatter(one(g_bin), phase, g_bin, max_tiles, stream));
             else VTX_HIP(vtx::launch_scatter(list_of(0, n, n + 1), phase, g_bin, max_tiles, stream));
@@ -1362,6 +1364,7 @@ int vtx_render_static(const float* positions, const float* radii, const uint32_t
     const bool count = (F.flags & (VTX_FLAG_STATS | VTX_FLAG_COUNT)) != 0;
     js.blocks = groups;
     VTX_HIP(vtx::launch_count(js, false, vtx::kPhaseAll, groups, T, st));
+    VTX_HIP(vtx::launch_tile_offsets(js, st));
     VTX_HIP(vtx::launch_scatter(js, vtx::kPhaseAll, groups, T, st));
     js.blocks = (uint32_t)T;
     VTX_HIP(vtx::launch_resolve(js, F.tile, vtx::kPhaseAll, (uint32_t)T, count, ovf, ovf_n, st));

@@ -111,6 +111,18 @@ __device__ inline void wave_count(uint32_t* hist, int t) {
     if ((pend >> __lane_id()) & 1ull) atomicAdd(&hist[t], 1u);
 }
 
+// Inclusive sum over the 64 lanes of a wave by DPP row shifts and row
+// broadcasts (lanes shifted in from outside a row read 0).
+__device__ inline uint32_t wave_scan_u32(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return v;
+}
+
 // Rest pass of a two-pass frame: true when cluster c cannot win a pixel.
 // The lower bound of the cull depth of its primitives (the bounding sphere
 // of its box, widened as in the frustum test, with the margin of the
@@ -396,17 +408,65 @@ __global__ void __launch_bounds__(kBinThreads) k_layers(JS js) {
 
 constexpr uint32_t kNoRun = 0xFFFFFFFFu;
 
-// Scatter.  Every workgroup first rebuilds the exclusive prefix sum of the
-// tile counts for itself (one read of T counts from L2; lane j owns a
-// contiguous run of tiles, the run totals are scanned with wave shuffles and
-// one LDS exchange), and while walking its run reserves, for each tile its
-// primitives touch, one run of that tile's list (one global atomic).  It then
-// places its primitives with LDS atomics.  Workgroup 0 also stores the tile
-// offsets for the resolve and publishes the frame counters.
+// List offsets: the exclusive prefix sum of the tile counts, once per job
+// (work block j of the launch scans job j's counts), with the list total and
+// the overflow flag in the frame counters.  The counts are read as up to
+// kMaxLdsTiles / 1024 rows of 1024 consecutive tiles, every load issued
+// before the first is used (coalesced, all in flight); each wave scans its
+// 64 lanes of every row with DPP steps, and one LDS exchange of the wave
+// totals gives every (row, wave) its start.
+template <class JS>
+__global__ void __launch_bounds__(kBinThreads) k_tile_offsets(JS js) {
+    constexpr int kRows = (kMaxLdsTiles + kBinThreads - 1) / kBinThreads;
+    constexpr int kWaves = kBinThreads / 64;
+    __shared__ uint32_t wsum[kRows][kWaves];
+    if (blockIdx.x >= js.count()) return;
+    const Job& J = js.job((int)blockIdx.x);
+    const int T = J.F.tiles_x * J.F.tiles_y;
+    const uint32_t* __restrict__ const cnt = J.bb.tile_cnt;
+    uint64_t* __restrict__ const off = J.bb.tile_off;
+    const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
+    const int rows = (T + kBinThreads - 1) / kBinThreads;
+    uint32_t v[kRows], incl[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const int t = r * kBinThreads + tid;
+        v[r] = r < rows && t < T ? cnt[t] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        incl[r] = wave_scan_u32(v[r]);
+        if (lane == 63) wsum[r][wave] = incl[r];
+    }
+    __syncthreads();
+    // start of this thread's tile in each row: the rows before it, then the
+    // waves before it in its row
+    unsigned long long base = 0;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        if (r >= rows) break;
+        unsigned long long row_total = 0, before = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            row_total += wsum[r][w];
+            before += w < wave ? wsum[r][w] : 0u;
+        }
+        const int t = r * kBinThreads + tid;
+        if (t < T) off[t] = base + before + (incl[r] - v[r]);
+        base += row_total;
+    }
+    if (tid == 0) {
+        J.bb.ctr->pairs = base;
+        J.bb.ctr->overflow = base > J.bb.capacity ? 1u : 0u;
+    }
+}
+
+// Scatter.  Every workgroup walks the tile offsets (k_tile_offsets) and
+// reserves, for each tile its primitives touch, one run of that tile's list
+// (one global atomic); it then places its primitives with LDS atomics.
+// Workgroup 0 also publishes the frame counters.
 template <class JS>
 __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js, int phase) {
     extern __shared__ uint32_t cur[];
-    __shared__ unsigned long long wtot[kBinThreads / 64];
     __shared__ unsigned int n_over;
     uint32_t blk;
     const int ji = js.find(blockIdx.x, blk);
@@ -419,7 +479,7 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js, int phase) {
     const uint32_t* __restrict__ const vis_cnt = J.bb.vis_cnt;
     const uint32_t* __restrict__ const hist_in = J.bb.hist;
     const uint32_t* __restrict__ const cnt = J.bb.tile_cnt;
-    uint64_t* __restrict__ const off = J.bb.tile_off;
+    const uint64_t* __restrict__ const off = J.bb.tile_off;
     uint2* __restrict__ const list = J.bb.list;
     const uint64_t capacity = J.bb.capacity;
     Counters* const ctr = J.bb.ctr;
@@ -429,47 +489,27 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js, int phase) {
     const uint32_t lay = J.bb.layers > 1 ? layer_of(blk, J.bb.groups, J.bb.layers) : 0u;
     uint32_t* const fill = J.bb.tile_fill + (size_t)lay * T;
     const uint32_t* __restrict__ const loff = J.bb.layers > 1 ? J.bb.layer_off + (size_t)lay * T : nullptr;
-    const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
+    const int tid = threadIdx.x;
     const bool lead = blk == 0;
-    const int per = (T + kBinThreads - 1) / kBinThreads;
-    const int b = min(T, tid * per), e = min(T, b + per);
-    unsigned long long sum = 0;
-    for (int t = b; t < e; ++t) sum += cnt[t];
-    unsigned long long incl = sum;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned long long v = __shfl_up(incl, o);
-        if (lane >= o) incl += v;
-    }
-    if (lane == 63) wtot[wave] = incl;
     if (tid == 0) n_over = 0;
     __syncthreads();
-    unsigned long long run = incl - sum, total = 0;
-    for (int w = 0; w < kBinThreads / 64; ++w) {
-        const unsigned long long v = wtot[w];
-        run += w < wave ? v : 0ull;
-        total += v;
-    }
     const uint32_t* row = hist_in + (size_t)blk * T;
     unsigned int over = 0;
-    for (int t = b; t < e; ++t) {
-        const uint32_t c = cnt[t];
-        const bool fits = run + c <= capacity;      // else the resolve rebuilds this tile from the visible lists
+    for (int t = tid; t < T; t += kBinThreads) {
+        const uint64_t run = off[t];
+        const bool fits = run + cnt[t] <= capacity;      // else the resolve rebuilds this tile from the visible lists
         const uint32_t h = row[t];
         uint32_t r = kNoRun;
         if (h && fits) r = (uint32_t)(run + (loff ? loff[t] : 0u) + atomicAdd(&fill[t], h));
         cur[t] = r;
-        if (lead) off[t] = run;
         over += fits ? 0u : 1u;
-        run += c;
     }
     if (lead) {
         if (over) atomicAdd(&n_over, over);
         __syncthreads();
         if (tid == 0) {
             const unsigned int vis = ctr->vis_count, bad = ctr->bad_bonds;
-            ctr->pairs = total;
-            ctr->overflow = total > capacity ? 1u : 0u;
+            const unsigned long long total = ctr->pairs;
             ctr->overflow_tiles = n_over;
             ctr->vis_count = 0;            // the next frame's count kernel adds to these
             ctr->bad_bonds = 0;
@@ -628,6 +668,12 @@ hipError_t launch_layers(const OneJob& js, uint32_t grid, hipStream_t stream) {
 }
 hipError_t launch_layers(const JobList& js, uint32_t grid, hipStream_t stream) {
     return dispatch(k_layers<JobList>, grid, kBinThreads, 0, stream, js);
+}
+hipError_t launch_tile_offsets(const OneJob& js, hipStream_t stream) {
+    return dispatch(k_tile_offsets<OneJob>, 1, kBinThreads, 0, stream, js);
+}
+hipError_t launch_tile_offsets(const JobList& js, hipStream_t stream) {
+    return dispatch(k_tile_offsets<JobList>, js.n, kBinThreads, 0, stream, js);
 }
 hipError_t launch_scatter(const OneJob& js, int phase, uint32_t grid, int max_tiles, hipStream_t stream) {
     return scatter_impl(js, phase, grid, max_tiles, stream);

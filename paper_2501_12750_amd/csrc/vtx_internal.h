@@ -454,6 +454,10 @@ hipError_t launch_count(const JobList& js, bool scene, int phase, uint32_t grid,
 // with layers > 1; runs on the binning grid).
 hipError_t launch_layers(const OneJob& js, uint32_t grid, hipStream_t stream);
 hipError_t launch_layers(const JobList& js, uint32_t grid, hipStream_t stream);
+// List offsets of every tile (exclusive prefix sum of the counts), the list
+// total and the overflow flag, one workgroup per job.
+hipError_t launch_tile_offsets(const OneJob& js, hipStream_t stream);
+hipError_t launch_tile_offsets(const JobList& js, hipStream_t stream);
 hipError_t launch_scatter(const OneJob& js, int phase, uint32_t grid, int max_tiles, hipStream_t stream);
 hipError_t launch_scatter(const JobList& js, int phase, uint32_t grid, int max_tiles, hipStream_t stream);
 // The resolve is a main launch plus a small tail launch for the tiles whose
