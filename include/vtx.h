@@ -308,6 +308,48 @@ int vtx_shade(const float* positions, const float* radii, const uint32_t* colors
               float* normal, uint32_t* albedo, float* ao, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Solvent excluded surface (paper, Methods, "Cartoon and SES
+ * representations": the SES is computed by a discrete approach and extracted
+ * with marching cubes).  This library's reading, on a grid of spacing h:
+ *  - grid point (i, j, k) sits at origin + h (i, j, k); it is inside the
+ *    solvent-accessible region when some atom has |p - c| < r + probe (FP64
+ *    test); the other points are places a probe centre can be;
+ *  - f(p) = min(h sqrt(g), W h) - probe, g the least squared grid distance
+ *    from p to such a point (W = ceil(probe / h) + 2: only the sign matters
+ *    beyond), in FP32; the surface encloses f >= 0 (every point at least the
+ *    probe radius from every probe centre);
+ *  - marching cubes over f >= 0: each cube's surface pieces come from its
+ *    faces (a face whose inside corners are diagonal keeps them apart), each
+ *    closed loop of edge points is a triangle or, with more than three
+ *    points, a fan around their mean; a point on edge (a, b) lies at
+ *    f_a / (f_a - f_b) of the way from a.
+ * The surface is closed when the grid reaches past every atom by the probe
+ * radius and one step (the border points are then outside).
+ * ------------------------------------------------------------------------- */
+typedef struct vtx_ses_grid {
+    float origin[3];          /* world position of grid point (0, 0, 0) */
+    float spacing;            /* h > 0 */
+    int32_t dims[3];          /* points along x, y, z: each >= 2, product < 2^31 */
+} vtx_ses_grid;
+
+/*
+ * vtx_ses - the solvent excluded surface of the atoms as triangles.
+ *   positions  n_atoms x 3 float (device), radii n_atoms float (device)
+ *   field      dims[0] x dims[1] x dims[2] float out (device, x fastest), or
+ *              NULL: f at every grid point
+ *   triangles  capacity x 9 float out (device): v0, v1, v2 (x, y, z each);
+ *              counter-clockwise seen from outside.  Triangles are ordered by
+ *              cube (x fastest), then by loop and position in the loop.
+ *   n_triangles one uint64 out (device): the surface's triangle count; those
+ *              past `capacity` are not written (call again with more)
+ * Queued on `stream`; library scratch ~ 13 B per grid point.  VTX_EINVAL for
+ * bad sizes or pointers, VTX_ENOMEM, VTX_EHIP.
+ */
+int vtx_ses(const float* positions, const float* radii, int64_t n_atoms, float probe_radius,
+            const vtx_ses_grid* grid, float* field, float* triangles, int64_t capacity, uint64_t* n_triangles,
+            void* stream);
+
+/* ---------------------------------------------------------------------------
  * Resident scenes.  A context tracks the device memory its scenes hold
  * against a budget; a scene is a library-owned copy of a molecule kept in
  * device memory across frames, laid out for the per-frame passes (atoms

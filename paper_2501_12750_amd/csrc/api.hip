@@ -127,6 +127,10 @@ struct Workspace {
     unsigned long long* d_ovf = nullptr;
     size_t ovf_cap = 0;
     uint32_t* d_ovf_n = nullptr;
+    // solvent excluded surface calls: scratch words and the field when the
+    // caller takes none
+    uint32_t* ses = nullptr;
+    size_t ses_cap = 0;
     // job tables of batched launches: device copy and pinned staging
     char* d_tab = nullptr;
     char* h_tab = nullptr;
@@ -420,6 +424,7 @@ void workspace_free(Workspace* ws) {
             }
         delete[] ws->tslots;
     }
+    hipFree(ws->ses);
     hipFree(ws->d_tab);
     hipHostFree(ws->h_tab);
     hipFree(ws->d_ovf);
@@ -1370,6 +1375,52 @@ int vtx_render_static(const float* positions, const float* radii, const uint32_t
     VTX_HIP(vtx::launch_resolve(js, F.tile, vtx::kPhaseAll, (uint32_t)T, count, ovf, ovf_n, st));
     js.blocks = vtx::shade_blocks(F);
     VTX_HIP(vtx::launch_shade(js, js.blocks, js.K.noise != 0 && js.K.count > 0, st));
+    return VTX_OK;
+}
+
+int vtx_ses(const float* positions, const float* radii, int64_t n_atoms, float probe_radius,
+            const vtx_ses_grid* grid, float* field, float* triangles, int64_t capacity, uint64_t* n_triangles,
+            void* stream) {
+    if (!grid || !n_triangles) return fail(VTX_EINVAL, "grid/n_triangles is NULL");
+    if (n_atoms < 0 || n_atoms > 0xFFFFFFFFll) return fail(VTX_EINVAL, "n_atoms=%lld out of range", (long long)n_atoms);
+    if (n_atoms > 0 && (!positions || !radii)) return fail(VTX_EINVAL, "positions/radii are NULL");
+    if (!(probe_radius >= 0.0f) || !std::isfinite(probe_radius)) return fail(VTX_EINVAL, "probe_radius must be >= 0");
+    if (!(grid->spacing > 0.0f) || !std::isfinite(grid->spacing) || !finite3(grid->origin))
+        return fail(VTX_EINVAL, "grid spacing must be > 0 and the origin finite");
+    int64_t np = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (grid->dims[d] < 2) return fail(VTX_EINVAL, "grid dims must be >= 2");
+        np *= grid->dims[d];
+    }
+    if (np >= ((int64_t)1 << 31)) return fail(VTX_EINVAL, "grid of %lld points is too large", (long long)np);
+    if (capacity < 0 || (capacity > 0 && !triangles)) return fail(VTX_EINVAL, "triangles is NULL or capacity < 0");
+    if ((double)probe_radius / (double)grid->spacing > 1e6) return fail(VTX_EINVAL, "probe_radius / spacing too large");
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace* ws = nullptr;
+    const hipStream_t st = (hipStream_t)stream;
+    int rc = get_workspace(st, &ws);
+    if (rc) return rc;
+    const int dims[3] = {grid->dims[0], grid->dims[1], grid->dims[2]};
+    size_t wm, wg, wc, wb;
+    size_t words = vtx::ses_scratch_words(dims, &wm, &wg, &wc, &wb);
+    const size_t wf = field ? 0 : (size_t)np;
+    words += wf + 64;
+    if ((rc = grow(&ws->ses, ws->ses_cap, words, st, "surface scratch"))) return rc;
+    vtx::SesScratch sc;
+    uint32_t* at = ws->ses;
+    sc.mark = reinterpret_cast<uint8_t*>(at);
+    at += wm;
+    sc.ga = reinterpret_cast<int32_t*>(at);
+    at += wg;
+    sc.gb = reinterpret_cast<int32_t*>(at);
+    at += wg;
+    sc.cnt = at;
+    at += wc;
+    sc.bsum = at;
+    at += wb;
+    float* f = field ? field : reinterpret_cast<float*>(at);
+    VTX_HIP(vtx::ses_run(positions, radii, (uint64_t)n_atoms, probe_radius, grid->origin, grid->spacing, dims, f,
+                         triangles, (uint64_t)capacity, reinterpret_cast<unsigned long long*>(n_triangles), sc, st));
     return VTX_OK;
 }
 

@@ -1,0 +1,431 @@
+// Solvent excluded surface on a grid, extracted by marching cubes (paper,
+// Methods, "Cartoon and SES representations": a discrete SES, as in Lindow
+// et al., extracted with marching cubes).
+//
+// Readings (the paper gives no formulas):
+//  - grid point (i, j, k) is at o + h (i, j, k) in FP64; it lies inside the
+//    solvent-accessible region when some atom has |p - c|^2 < (r + rp)^2,
+//    each square and sum rounded once in FP64; the others are positions a
+//    probe centre can take ("exterior");
+//  - f(p) = min(h sqrt(g), W h) - rp, g the least squared grid distance from
+//    p to an exterior point, W = ceil(rp / h) + 2 (beyond W h only the sign
+//    matters), rounded to FP32; the SES encloses f >= 0;
+//  - marching cubes over f >= 0 with a case table built from the cube's
+//    faces: each face with two crossing edges gives a segment, a face whose
+//    inside corners are diagonal gives two segments cutting off the inside
+//    corners; segments close into loops, oriented from the inside corners to
+//    the outside ones and started at their lowest edge; a 3-edge loop is a
+//    triangle, a longer one a fan around the mean of its vertices.
+//
+// Passes: mark the SAS interior per atom; the exact squared distance to
+// the nearest exterior point within a W-box by three separable 1-D passes
+// in integers (x: nearest exterior point on the row; y and z: the least of
+// g + d^2 over the window); triangle counts per cube; an exclusive scan of
+// the counts; emission of each cube's triangles at its offset.
+#include <mutex>
+
+#include "vtx_internal.h"
+
+namespace vtx {
+
+namespace {
+
+constexpr int kSesBlock = 256;
+constexpr int32_t kFar = 0x3FFFFFFF;   // no exterior point within the window
+
+// Case table: for each case, its loops as a byte string: loop length, then
+// its edges, ..., then 0.  Edges 0-3 run along x, 4-7 along y, 8-11 along z
+// (corner pairs below); corner c sits at (c & 1, c >> 1 & 1, c >> 2 & 1).
+constexpr int kCaseBytes = 24;
+__constant__ uint8_t c_cases[256 * kCaseBytes];
+__constant__ uint8_t c_case_tris[256];
+
+constexpr int kEdgeA[12] = {0, 2, 4, 6, 0, 1, 4, 5, 0, 1, 2, 3};
+constexpr int kEdgeB[12] = {1, 3, 5, 7, 2, 3, 6, 7, 4, 5, 6, 7};
+__constant__ int8_t c_edge_corner[12][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3},
+                                            {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6}, {3, 7}};
+
+int edge_of(int a, int b) {
+    if (a > b) {
+        const int t = a;
+        a = b;
+        b = t;
+    }
+    for (int e = 0; e < 12; ++e)
+        if (kEdgeA[e] == a && kEdgeB[e] == b) return e;
+    return -1;
+}
+
+// The loops of case m, built as the table's rule states.
+void build_case(int m, uint8_t* out, uint8_t* ntri) {
+    static const int faces[6][4] = {{0, 2, 6, 4}, {1, 3, 7, 5}, {0, 1, 5, 4}, {2, 3, 7, 6}, {0, 1, 3, 2}, {4, 5, 7, 6}};
+    int in[8];
+    for (int c = 0; c < 8; ++c) in[c] = (m >> c) & 1;
+    int nb[12][2], deg[12] = {};
+    auto link = [&](int a, int b) {
+        nb[a][deg[a]++] = b;
+        nb[b][deg[b]++] = a;
+    };
+    for (const auto& f : faces) {
+        int e[4], s[4], nc = 0, cr[4];
+        for (int i = 0; i < 4; ++i) {
+            s[i] = in[f[i]];
+            e[i] = edge_of(f[i], f[(i + 1) & 3]);
+        }
+        for (int i = 0; i < 4; ++i)
+            if (s[i] != s[(i + 1) & 3]) cr[nc++] = i;
+        if (nc == 2) {
+            link(e[cr[0]], e[cr[1]]);
+        } else if (nc == 4) {
+            for (int i = 0; i < 4; ++i)
+                if (s[i]) link(e[(i + 3) & 3], e[i]);
+        }
+    }
+    bool used[12] = {};
+    int pos = 0, tris = 0;
+    for (int start = 0; start < 12; ++start) {
+        if (deg[start] == 0 || used[start]) continue;
+        int loop[12], k = 0;
+        loop[k++] = start;
+        used[start] = true;
+        int prev = start, cur = nb[start][0];
+        while (cur != start) {
+            loop[k++] = cur;
+            used[cur] = true;
+            const int nxt = nb[cur][0] == prev ? nb[cur][1] : nb[cur][0];
+            prev = cur;
+            cur = nxt;
+        }
+        // orientation: the loop's normal over its edge midpoints against the
+        // sum of the inside -> outside directions of its edges
+        double mid[12][3], nrm[3] = {0, 0, 0}, dir[3] = {0, 0, 0};
+        for (int i = 0; i < k; ++i) {
+            const int a = kEdgeA[loop[i]], b = kEdgeB[loop[i]];
+            for (int d = 0; d < 3; ++d) {
+                const double pa = (a >> d) & 1, pb = (b >> d) & 1;
+                mid[i][d] = 0.5 * (pa + pb);
+                dir[d] += in[a] ? pb - pa : pa - pb;
+            }
+        }
+        for (int i = 0; i < k; ++i) {
+            const double* p = mid[i];
+            const double* q = mid[(i + 1) % k];
+            nrm[0] += p[1] * q[2] - p[2] * q[1];
+            nrm[1] += p[2] * q[0] - p[0] * q[2];
+            nrm[2] += p[0] * q[1] - p[1] * q[0];
+        }
+        if (nrm[0] * dir[0] + nrm[1] * dir[1] + nrm[2] * dir[2] < 0.0)
+            for (int i = 0; i < k / 2; ++i) {
+                const int t = loop[i];
+                loop[i] = loop[k - 1 - i];
+                loop[k - 1 - i] = t;
+            }
+        int lo = 0;
+        for (int i = 1; i < k; ++i)
+            if (loop[i] < loop[lo]) lo = i;
+        out[pos++] = (uint8_t)k;
+        for (int i = 0; i < k; ++i) out[pos++] = (uint8_t)loop[(lo + i) % k];
+        tris += k == 3 ? 1 : k;
+    }
+    out[pos] = 0;
+    *ntri = (uint8_t)tris;
+}
+
+std::mutex g_case_mu;
+bool g_case_ready[64] = {};
+
+hipError_t ensure_cases(int device) {
+    std::lock_guard<std::mutex> lk(g_case_mu);
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    if (g_case_ready[device]) return hipSuccess;
+    static uint8_t cases[256 * kCaseBytes];
+    static uint8_t ntri[256];
+    for (int m = 0; m < 256; ++m) build_case(m, cases + m * kCaseBytes, ntri + m);
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_cases), cases, sizeof(cases));
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_case_tris), ntri, sizeof(ntri));
+    if (e == hipSuccess) g_case_ready[device] = true;
+    return e;
+}
+
+struct SesGrid {
+    double o[3];
+    double h;
+    int nx, ny, nz;
+    int W;              // distance window in grid steps
+    double rp;
+};
+
+__device__ inline size_t gidx(const SesGrid& G, int i, int j, int k) {
+    return (size_t)i + (size_t)G.nx * ((size_t)j + (size_t)G.ny * k);
+}
+
+// One workgroup per atom: marks the grid points inside its solvent-accessible
+// sphere (interior = 1; points no atom marks stay 0: exterior).
+__global__ void __launch_bounds__(kSesBlock) k_ses_mark(const float* __restrict__ pos, const float* __restrict__ rad,
+                                                        uint32_t n, SesGrid G, uint8_t* __restrict__ mark) {
+#pragma clang fp contract(off)
+    const uint32_t a = blockIdx.x;
+    if (a >= n) return;
+    const double cx = pos[3 * (size_t)a], cy = pos[3 * (size_t)a + 1], cz = pos[3 * (size_t)a + 2];
+    const double R = (double)rad[a] + G.rp;
+    if (!(R > 0.0)) return;
+    const double R2 = R * R;
+    int lo[3], hi[3];
+    const double c[3] = {cx, cy, cz};
+    const int nmax[3] = {G.nx - 1, G.ny - 1, G.nz - 1};
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = max(0, (int)floor((c[d] - R - G.o[d]) / G.h) - 1);
+        hi[d] = min(nmax[d], (int)ceil((c[d] + R - G.o[d]) / G.h) + 1);
+        if (lo[d] > hi[d]) return;
+    }
+    const int bx = hi[0] - lo[0] + 1, by = hi[1] - lo[1] + 1, bz = hi[2] - lo[2] + 1;
+    const int total = bx * by * bz;
+    for (int q = threadIdx.x; q < total; q += kSesBlock) {
+        const int i = lo[0] + q % bx, j = lo[1] + (q / bx) % by, k = lo[2] + q / (bx * by);
+        const double dx = (G.o[0] + G.h * i) - cx, dy = (G.o[1] + G.h * j) - cy, dz = (G.o[2] + G.h * k) - cz;
+        const double d2 = (dx * dx + dy * dy) + dz * dz;
+        if (d2 < R2) mark[gidx(G, i, j, k)] = 1;
+    }
+}
+
+// x pass: squared distance along the row to the nearest exterior point
+// within W steps (kFar if none).
+__global__ void __launch_bounds__(kSesBlock) k_ses_edt_x(SesGrid G, const uint8_t* __restrict__ mark,
+                                                         int32_t* __restrict__ g) {
+    const size_t p = (size_t)blockIdx.x * kSesBlock + threadIdx.x;
+    const size_t n = (size_t)G.nx * G.ny * G.nz;
+    if (p >= n) return;
+    const int i = (int)(p % G.nx);
+    int32_t best = kFar;
+    for (int d = 0; d <= G.W; ++d) {
+        const bool l = i - d >= 0 && !mark[p - d];
+        const bool r = i + d < G.nx && !mark[p + d];
+        if (l || r) {
+            best = d * d;
+            break;
+        }
+    }
+    g[p] = best;
+}
+
+// y or z pass (stride of the axis, length along it): the least of
+// g(p + d e) + d^2 over |d| <= W.  The z pass also writes the field.
+template <bool kLast>
+__global__ void __launch_bounds__(kSesBlock) k_ses_edt_yz(SesGrid G, const int32_t* __restrict__ gin,
+                                                          int32_t* __restrict__ gout, float* __restrict__ field) {
+    const size_t p = (size_t)blockIdx.x * kSesBlock + threadIdx.x;
+    const size_t n = (size_t)G.nx * G.ny * G.nz;
+    if (p >= n) return;
+    const size_t stride = kLast ? (size_t)G.nx * G.ny : (size_t)G.nx;
+    const int len = kLast ? G.nz : G.ny;
+    const int at = kLast ? (int)(p / stride) : (int)((p / G.nx) % G.ny);
+    int32_t best = kFar;
+    for (int d = -G.W; d <= G.W; ++d) {
+        const int q = at + d;
+        if (q < 0 || q >= len) continue;
+        const int32_t v = gin[(size_t)((long long)p + (long long)d * (long long)stride)];
+        if (v < kFar) best = min(best, v + d * d);
+    }
+    if (!kLast) {
+        gout[p] = best;
+        return;
+    }
+    const double cap = G.W * G.h;
+    const double D = best > G.W * G.W ? cap : fmin(G.h * sqrt((double)best), cap);
+    field[p] = (float)(D - G.rp);
+}
+
+__device__ inline int cube_case(const SesGrid& G, const float* __restrict__ f, int i, int j, int k, float v[8]) {
+    int m = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        v[c] = f[gidx(G, i + (c & 1), j + ((c >> 1) & 1), k + ((c >> 2) & 1))];
+        m |= (v[c] >= 0.0f ? 1 : 0) << c;
+    }
+    return m;
+}
+
+// Triangles per cube.
+__global__ void __launch_bounds__(kSesBlock) k_ses_count(SesGrid G, const float* __restrict__ f,
+                                                         uint32_t* __restrict__ cnt) {
+    const size_t q = (size_t)blockIdx.x * kSesBlock + threadIdx.x;
+    const int cx = G.nx - 1, cy = G.ny - 1;
+    const size_t nc = (size_t)cx * cy * (G.nz - 1);
+    if (q >= nc) return;
+    const int i = (int)(q % cx), j = (int)((q / cx) % cy), k = (int)(q / ((size_t)cx * cy));
+    float v[8];
+    cnt[q] = c_case_tris[cube_case(G, f, i, j, k, v)];
+}
+
+// Exclusive scan of n counts in three launches: block sums of 4096-element
+// blocks, a scan of those sums by one workgroup (with the total), then each
+// block's scan plus its start.
+constexpr int kScanPer = 16;
+constexpr int kScanSpan = kSesBlock * kScanPer;
+
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    uint32_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(incl, o);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int w = 0; w < kSesBlock / 64; ++w) {
+        before += w < wave ? wsum[w] : 0u;
+        all += wsum[w];
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - v;
+}
+
+__global__ void __launch_bounds__(kSesBlock) k_scan_sums(const uint32_t* __restrict__ cnt, size_t n,
+                                                         uint32_t* __restrict__ bsum) {
+    __shared__ uint32_t wsum[kSesBlock / 64];
+    const size_t base = (size_t)blockIdx.x * kScanSpan + (size_t)threadIdx.x * kScanPer;
+    uint32_t s = 0;
+    for (int i = 0; i < kScanPer; ++i)
+        if (base + i < n) s += cnt[base + i];
+    uint32_t total;
+    (void)block_excl_scan(s, wsum, &total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kSesBlock) k_scan_top(uint32_t* __restrict__ bsum, uint32_t nb,
+                                                        unsigned long long* __restrict__ n_out) {
+    __shared__ uint32_t wsum[kSesBlock / 64];
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nb; b0 += kSesBlock) {
+        const uint32_t b = b0 + threadIdx.x;
+        const uint32_t v = b < nb ? bsum[b] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_excl_scan(v, wsum, &total);
+        if (b < nb) bsum[b] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) *n_out = carry;
+}
+
+__global__ void __launch_bounds__(kSesBlock) k_scan_apply(uint32_t* __restrict__ cnt, size_t n,
+                                                          const uint32_t* __restrict__ bsum) {
+    __shared__ uint32_t wsum[kSesBlock / 64];
+    const size_t base = (size_t)blockIdx.x * kScanSpan + (size_t)threadIdx.x * kScanPer;
+    uint32_t v[kScanPer], s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        v[i] = base + i < n ? cnt[base + i] : 0u;
+        s += v[i];
+    }
+    uint32_t total;
+    uint32_t run = bsum[blockIdx.x] + block_excl_scan(s, wsum, &total);
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        if (base + i < n) cnt[base + i] = run;
+        run += v[i];
+    }
+}
+
+// Each cube's triangles at its offset (those past the capacity are dropped).
+__global__ void __launch_bounds__(kSesBlock) k_ses_emit(SesGrid G, const float* __restrict__ f,
+                                                        const uint32_t* __restrict__ off, float* __restrict__ tri,
+                                                        unsigned long long capacity) {
+    const size_t q = (size_t)blockIdx.x * kSesBlock + threadIdx.x;
+    const int cx = G.nx - 1, cy = G.ny - 1;
+    const size_t nc = (size_t)cx * cy * (G.nz - 1);
+    if (q >= nc) return;
+    const int i = (int)(q % cx), j = (int)((q / cx) % cy), k = (int)(q / ((size_t)cx * cy));
+    float v[8];
+    const int m = cube_case(G, f, i, j, k, v);
+    if (c_case_tris[m] == 0) return;
+    unsigned long long t = off[q];
+    const float ox = (float)G.o[0], oy = (float)G.o[1], oz = (float)G.o[2], h = (float)G.h;
+    const uint8_t* cs = c_cases + m * kCaseBytes;
+    for (int at = 0; cs[at] != 0;) {
+        const int len = cs[at];
+        float px[8], py[8], pz[8];
+        float sx = 0.f, sy = 0.f, sz = 0.f;
+        for (int e = 0; e < len; ++e) {
+            const int ed = cs[at + 1 + e];
+            const int a = c_edge_corner[ed][0], b = c_edge_corner[ed][1];
+            const float tt = v[a] / (v[a] - v[b]);
+            const float fx = (float)((a & 1) + tt * ((b & 1) - (a & 1)));
+            const float fy = (float)(((a >> 1) & 1) + tt * (((b >> 1) & 1) - ((a >> 1) & 1)));
+            const float fz = (float)(((a >> 2) & 1) + tt * (((b >> 2) & 1) - ((a >> 2) & 1)));
+            px[e] = ox + h * ((float)i + fx);
+            py[e] = oy + h * ((float)j + fy);
+            pz[e] = oz + h * ((float)k + fz);
+            sx += px[e];
+            sy += py[e];
+            sz += pz[e];
+        }
+        auto put = [&](float ax, float ay, float az, int b, int c) {
+            if (t < capacity) {
+                float* o = tri + 9 * t;
+                o[0] = ax; o[1] = ay; o[2] = az;
+                o[3] = px[b]; o[4] = py[b]; o[5] = pz[b];
+                o[6] = px[c]; o[7] = py[c]; o[8] = pz[c];
+            }
+            ++t;
+        };
+        if (len == 3) {
+            put(px[0], py[0], pz[0], 1, 2);
+        } else {
+            const float inv = 1.0f / (float)len;
+            for (int e = 0; e < len; ++e) put(sx * inv, sy * inv, sz * inv, e, (e + 1) % len);
+        }
+        at += 1 + len;
+    }
+}
+
+}  // namespace
+
+hipError_t ses_run(const float* pos, const float* rad, uint64_t n, float probe, const float origin[3], float spacing,
+                   const int dims[3], float* field, float* tri, uint64_t capacity, unsigned long long* n_tri,
+                   SesScratch& s, hipStream_t stream) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if ((e = ensure_cases(dev)) != hipSuccess) return e;
+    SesGrid G;
+    for (int d = 0; d < 3; ++d) G.o[d] = (double)origin[d];
+    G.h = (double)spacing;
+    G.nx = dims[0];
+    G.ny = dims[1];
+    G.nz = dims[2];
+    G.rp = (double)probe;
+    G.W = (int)ceil(G.rp / G.h) + 2;
+    const size_t np = (size_t)G.nx * G.ny * G.nz;
+    const size_t nc = (size_t)(G.nx - 1) * (G.ny - 1) * (G.nz - 1);
+    const size_t nb = (nc + kScanSpan - 1) / kScanSpan;
+    if ((e = launch_zero(reinterpret_cast<uint32_t*>(s.mark), (np + 3) / 4, stream)) != hipSuccess) return e;
+    if (n && (e = dispatch(k_ses_mark, (unsigned)n, kSesBlock, 0, stream, pos, rad, (uint32_t)n, G, s.mark)))
+        return e;
+    const unsigned gp = (unsigned)((np + kSesBlock - 1) / kSesBlock);
+    if ((e = dispatch(k_ses_edt_x, gp, kSesBlock, 0, stream, G, (const uint8_t*)s.mark, s.ga))) return e;
+    if ((e = dispatch(k_ses_edt_yz<false>, gp, kSesBlock, 0, stream, G, (const int32_t*)s.ga, s.gb, (float*)nullptr)))
+        return e;
+    if ((e = dispatch(k_ses_edt_yz<true>, gp, kSesBlock, 0, stream, G, (const int32_t*)s.gb, s.ga, field))) return e;
+    const unsigned gc = (unsigned)((nc + kSesBlock - 1) / kSesBlock);
+    if ((e = dispatch(k_ses_count, gc, kSesBlock, 0, stream, G, (const float*)field, s.cnt))) return e;
+    if ((e = dispatch(k_scan_sums, (unsigned)nb, kSesBlock, 0, stream, (const uint32_t*)s.cnt, nc, s.bsum))) return e;
+    if ((e = dispatch(k_scan_top, 1, kSesBlock, 0, stream, s.bsum, (uint32_t)nb, n_tri))) return e;
+    if ((e = dispatch(k_scan_apply, (unsigned)nb, kSesBlock, 0, stream, s.cnt, nc, (const uint32_t*)s.bsum))) return e;
+    return dispatch(k_ses_emit, gc, kSesBlock, 0, stream, G, (const float*)field, (const uint32_t*)s.cnt, tri,
+                    (unsigned long long)capacity);
+}
+
+size_t ses_scratch_words(const int dims[3], size_t* mark_words, size_t* g_words, size_t* cnt_words, size_t* bsum_words) {
+    const size_t np = (size_t)dims[0] * dims[1] * dims[2];
+    const size_t nc = (size_t)(dims[0] - 1) * (dims[1] - 1) * (dims[2] - 1);
+    *mark_words = (np + 3) / 4;
+    *g_words = np;
+    *cnt_words = nc;
+    *bsum_words = (nc + kScanSpan - 1) / kScanSpan + 1;
+    return *mark_words + 2 * *g_words + *cnt_words + *bsum_words;
+}
+
+}  // namespace vtx

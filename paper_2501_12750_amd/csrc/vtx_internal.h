@@ -476,4 +476,20 @@ hipError_t launch_downsample(const float* sdepth, const uint32_t* sid, const uin
 hipError_t launch_shade(const OneJob& js, uint32_t grid, bool noise, hipStream_t stream);
 hipError_t launch_shade(const JobList& js, uint32_t grid, bool noise, hipStream_t stream);
 
+// Solvent excluded surface (ses.hip): scratch of one call, sized by
+// ses_scratch_words, and the passes (queued on `stream`; field may not be
+// null).
+struct SesScratch {
+    uint8_t* mark;          // grid points: 1 inside the solvent-accessible region
+    int32_t* ga;            // squared distances, x and z passes
+    int32_t* gb;            // squared distances, y pass
+    uint32_t* cnt;          // triangles per cube, then their offsets
+    uint32_t* bsum;         // block sums of the scan
+};
+size_t ses_scratch_words(const int dims[3], size_t* mark_words, size_t* g_words, size_t* cnt_words,
+                         size_t* bsum_words);
+hipError_t ses_run(const float* pos, const float* rad, uint64_t n, float probe, const float origin[3], float spacing,
+                   const int dims[3], float* field, float* tri, uint64_t capacity, unsigned long long* n_tri,
+                   SesScratch& s, hipStream_t stream);
+
 }  // namespace vtx

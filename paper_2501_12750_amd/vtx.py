@@ -45,7 +45,7 @@ EXPORTS = ("vtx_render", "vtx_gbuffer", "vtx_shade", "vtx_read_stats", "vtx_set_
            "vtx_scene_frame_bytes", "vtx_render_batch", "vtx_autotune", "vtx_clock_s", "vtx_server_create",
            "vtx_server_submit", "vtx_server_poll", "vtx_server_drain", "vtx_server_stats_read",
            "vtx_server_destroy", "vtx_check_job", "vtx_batch_graph_create",
-           "vtx_batch_graph_launch", "vtx_batch_graph_destroy", "vtx_render_static")
+           "vtx_batch_graph_launch", "vtx_batch_graph_destroy", "vtx_render_static", "vtx_ses")
 
 
 class vtx_camera(ctypes.Structure):
@@ -62,6 +62,10 @@ class vtx_options(ctypes.Structure):
                 ("shading", ctypes.c_int32), ("fog_color", ctypes.c_uint32), ("fog_start", ctypes.c_float),
                 ("fog_end", ctypes.c_float), ("outline_color", ctypes.c_uint32), ("outline_depth", ctypes.c_float),
                 ("clip_plane", ctypes.c_float * 4), ("supersample", ctypes.c_int32), ("ssao_noise", ctypes.c_int32)]
+
+
+class vtx_ses_grid(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_float * 3), ("spacing", ctypes.c_float), ("dims", ctypes.c_int32 * 3)]
 
 
 class vtx_stats(ctypes.Structure):
@@ -138,6 +142,8 @@ _OPT = ctypes.POINTER(vtx_options)
 
 _lib.vtx_render.restype = ctypes.c_int
 _lib.vtx_render.argtypes = [_P, _P, _P, _I64, _P, _I64, _CAM, _OPT, _I32, _I32, _P, _P, _P, _P]
+_lib.vtx_ses.restype = ctypes.c_int
+_lib.vtx_ses.argtypes = [_P, _P, _I64, ctypes.c_float, ctypes.POINTER(vtx_ses_grid), _P, _P, _I64, _P, _P]
 _lib.vtx_render_static.restype = ctypes.c_int
 _lib.vtx_render_static.argtypes = [_P, _P, _P, _I64, _P, _I64, _CAM, _OPT, _I32, _I32, _P, _P, _P, _P]
 _lib.vtx_gbuffer.restype = ctypes.c_int
@@ -290,6 +296,17 @@ def vtx_render_static(positions, radii, colors, n_atoms, bonds, n_bonds, cam, op
     cp, op, _keep = _cam_opt(cam, opts)
     _check(_lib.vtx_render_static(_addr(positions), _addr(radii), _addr(colors), n_atoms, _addr(bonds), n_bonds,
                                   cp, op, W, H, _addr(rgba), _addr(depth), _addr(id), _stream(stream)))
+
+
+def vtx_ses(positions, radii, n_atoms, probe_radius, origin, spacing, dims, field, triangles, capacity, n_triangles,
+            stream=None):
+    g = vtx_ses_grid()
+    for k in range(3):
+        g.origin[k] = float(origin[k])
+        g.dims[k] = int(dims[k])
+    g.spacing = float(spacing)
+    _check(_lib.vtx_ses(_addr(positions), _addr(radii), n_atoms, float(probe_radius), ctypes.byref(g), _addr(field),
+                        _addr(triangles), int(capacity), _addr(n_triangles), _stream(stream)))
 
 
 def vtx_gbuffer(positions, radii, colors, n_atoms, bonds, n_bonds, cam, opts, W, H, depth, id, stream=None):
