@@ -644,6 +644,72 @@ def run_workload(args, workload, vtx, scenes, torch, stream, steps_arg, warmup_a
     return out
 
 
+def run_ses(args, vtx, scenes, torch, stream, cpu=True):
+    """The solvent excluded surface of the 50k-atom protein-like globule
+    (frame 0 of the trajectory workload, van der Waals radii, probe 1.4 A) on
+    a 0.5 A grid reaching the probe radius and two steps past every atom:
+    one vtx_ses call per step (SAS marking, the three distance passes, the
+    triangle counts, their scan and the emission)."""
+    scene0, _, _, _, _ = scenes.trajectory(n_frames=1)
+    pos, rad = scene0.positions, scene0.radii
+    probe, h = 1.4, 0.5
+    lo = np.min(pos - rad[:, None], axis=0) - probe - 2 * h
+    hi = np.max(pos + rad[:, None], axis=0) + probe + 2 * h
+    dims = tuple(int(d) for d in np.ceil((hi - lo) / h).astype(int) + 1)
+    origin = lo.astype(np.float32)
+    npts = int(np.prod(dims))
+    ncubes = int(np.prod([d - 1 for d in dims]))
+    dp = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
+    dr = torch.from_numpy(np.ascontiguousarray(rad)).cuda()
+    field = torch.empty(dims[::-1], dtype=torch.float32, device="cuda")
+    cap = 4_000_000
+    tri = torch.empty((cap, 9), dtype=torch.float32, device="cuda")
+    ntri = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+    def step():
+        vtx.vtx_ses(dp, dr, pos.shape[0], probe, origin, h, dims, field, tri, cap, ntri, stream)
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    n_tri = int(ntri.item())
+    steps = 20
+    a = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - a) / steps * 1e3
+    # algorithmic bytes: the mark (1 B), three distance passes (4 B written
+    # each, 1 + 4 + 4 B read), the field read by the count and the emission
+    # (4 B each), per cube the count written, scanned and read (12 B), and
+    # 36 B per triangle written; the atoms (16 B each)
+    B = 16.0 * pos.shape[0] + (1 + 12 + 9 + 8) * npts + 12.0 * ncubes + 36.0 * n_tri
+    out = {"value": round(1e3 / ms, 3), "unit": "surfaces/s", "ms_per_step": round(ms, 4), "steps": steps,
+           "config": {"workload": f"ses_globule_{pos.shape[0] // 1000}k_h{h}", "atoms": int(pos.shape[0]),
+                      "probe": probe, "spacing": h, "grid": list(dims), "triangles": n_tri},
+           "roofline": {"bound": "hbm", "achieved": round(B / (ms * 1e-3) / 1e9, 3), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(B / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "bytes": round(B),
+                        "timing": "whole vtx_ses call, host clock over synchronized steps"}}
+    log(f"ses: {out}")
+    if cpu and not args.no_cpu_baseline:
+        # the oracle on a slab of the grid (one eighth of its z extent through
+        # the middle), scaled to the whole grid
+        from oracle import oses
+        nz = max(2, dims[2] // 8)
+        z0 = (dims[2] - nz) // 2
+        sub_origin = (origin + np.array([0.0, 0.0, h * z0])).astype(np.float32)
+        sub_dims = (dims[0], dims[1], nz)
+        a = time.perf_counter()
+        ref = oses.ses_field(pos, rad, probe, sub_origin, np.float32(h), sub_dims)
+        oses.marching_cubes(ref["f"], sub_origin, np.float32(h))
+        el = time.perf_counter() - a
+        t_full = el * (dims[2] - 1) / (nz - 1)
+        out["cpu_baseline"] = {"value": 1.0 / t_full, "unit": "surfaces/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the oracle (NumPy + scipy k-d tree, one core) on the {dims[0]}x{dims[1]}x"
+                                         f"{nz} middle slab of the grid ({el:.1f} s), scaled by the cube layers "
+                                         f"({dims[2] - 1} / {nz - 1})"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -651,9 +717,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=-1, help="untimed steps first (-1: 20 frames, or 2 batches)")
     ap.add_argument("--workload", default="whole_cell",
                     choices=["ball_and_stick", "whole_cell", "trajectory", "served", "plain_small"])
-    ap.add_argument("--also", default="ball_and_stick",
+    ap.add_argument("--also", default="ball_and_stick,ses",
                     help="comma-separated workloads also timed and reported under their own key "
-                         "(\"\" for none; default: ball_and_stick beside the whole cell)")
+                         "(\"\" for none; default: ball_and_stick and ses (the solvent excluded surface "
+                         "of the 50k-atom globule) beside the whole cell)")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="served mix: arrival window")
     ap.add_argument("--serve-warmup", type=float, default=5.0, help="served mix: arrivals excluded from stats")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="served mix: frame requests per second")
@@ -699,6 +766,10 @@ def main():
         return
     out = run_workload(args, args.workload, vtx, scenes, torch, stream, args.steps, args.warmup)
     for extra in [w for w in args.also.split(",") if w and w != args.workload]:
+        if extra == "ses":
+            rec = run_ses(args, vtx, scenes, torch, stream)
+            out[rec["config"]["workload"]] = rec
+            continue
         if extra not in ("ball_and_stick", "whole_cell", "trajectory", "plain_small"):
             raise SystemExit(f"--also: unknown workload {extra}")
         log(f"also timing {extra}")
