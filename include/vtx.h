@@ -420,6 +420,17 @@ size_t vtx_scene_frame_bytes(int64_t n_atoms, int64_t n_bonds);
  * includes its added frames. */
 int vtx_scene_info(const vtx_scene* scene, int64_t* n_atoms, int64_t* n_bonds, uint64_t* bad_bonds, size_t* bytes);
 
+/*
+ * vtx_scene_order - the scene's stored order: atom_order[i] (device, n_atoms
+ * words) gets the original index of stored atom i, bond_order[j] (device,
+ * n_bonds - bad_bonds words) the original index of stored bond j.  Atoms are
+ * stored by their 30-bit Morton key (10 bits per axis over the bounding box
+ * of the positions), bonds by the lower stored index of their two atoms,
+ * each sort keeping the original order of equal keys.  Either pointer may be
+ * NULL.  Queued on `stream`.  VTX_EINVAL, VTX_EHIP.
+ */
+int vtx_scene_order(const vtx_scene* scene, uint32_t* atom_order, uint32_t* bond_order, void* stream);
+
 /* vtx_scene_destroy - waits for the device and frees the scene. */
 void vtx_scene_destroy(vtx_scene* scene);
 

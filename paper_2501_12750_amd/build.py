@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libvtx.so")
-SOURCES = ["api.hip", "bin.hip", "resolve.hip", "shade.hip", "scene.hip", "serve.hip", "ses.hip"]
+SOURCES = ["api.hip", "bin.hip", "resolve.hip", "shade.hip", "scene.hip", "serve.hip", "ses.hip", "scan.hip", "sort.hip"]
 ARCH = os.environ.get("VTX_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -1633,6 +1633,15 @@ int vtx_scene_info(const vtx_scene* scene, int64_t* n_atoms, int64_t* n_bonds, u
     return VTX_OK;
 }
 
+int vtx_scene_order(const vtx_scene* scene, uint32_t* atom_order, uint32_t* bond_order, void* stream) {
+    if (!scene) return fail(VTX_EINVAL, "scene is NULL");
+    int dev = 0;
+    VTX_HIP(hipGetDevice(&dev));
+    if (dev != scene->device) return fail(VTX_EINVAL, "scene lives on device %d, current is %d", scene->device, dev);
+    VTX_HIP(vtx::scene_order(scene->S, atom_order, bond_order, (hipStream_t)stream));
+    return VTX_OK;
+}
+
 void vtx_scene_destroy(vtx_scene* scene) {
     if (!scene) return;
     (void)hipDeviceSynchronize();

@@ -11,9 +11,9 @@
 // original index, which is the id the renderer reports, so a resident scene
 // renders exactly what the same arrays render through vtx_render.  Bonds
 // are re-indexed to stored positions and sorted by their first atom, in
-// clusters of 256 as well.
-#include <rocprim/device/device_radix_sort.hpp>
-
+// clusters of 256 as well.  Both orders come from the stable radix sort of
+// sort.hip, so atoms with equal Morton keys keep their original order, and so
+// do bonds with the same first atom.
 #include "vtx_internal.h"
 
 namespace vtx {
@@ -247,14 +247,11 @@ inline unsigned grid_for(uint64_t n) {
 // `tmp` needs scene_build_temp_bytes(n, m) bytes.  Returns the number of
 // valid bonds in *m_valid (synchronizes the stream).
 size_t scene_build_temp_bytes(uint64_t n, uint64_t m) {
-    size_t s1 = 0;
     const uint64_t mx = n > m ? n : m;
-    rocprim::radix_sort_pairs<rocprim::default_config>(nullptr, s1, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                                                       (uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)(mx ? mx : 1),
-                                                       0, 32);
     // keys in/out, payload in/out, inverse permutation, box and bad count,
     // sort scratch, plus the 256-byte alignment of each of those pieces
-    return 4 * sizeof(uint32_t) * (size_t)(mx ? mx : 1) + sizeof(uint32_t) * (size_t)(n ? n : 1) + 64 + s1 + 8 * 256;
+    return 4 * sizeof(uint32_t) * (size_t)(mx ? mx : 1) + sizeof(uint32_t) * (size_t)(n ? n : 1) + 64 +
+           sizeof(uint32_t) * radix_sort_scratch_words((size_t)mx) + 8 * 256;
 }
 
 hipError_t scene_build(const float* pos, const float* rad, const uint32_t* bonds, uint64_t n, uint64_t m,
@@ -275,35 +272,28 @@ hipError_t scene_build(const float* pos, const float* rad, const uint32_t* bonds
     uint32_t* inv = (uint32_t*)take(sizeof(uint32_t) * (n ? n : 1));
     uint32_t* box = (uint32_t*)take(64);
     uint32_t* bad = box + 8;
-    size_t sort_bytes = tmp_bytes - (size_t)(p - static_cast<char*>(tmp));
-    void* sort_tmp = p;
+    uint32_t* sort_tmp = (uint32_t*)take(sizeof(uint32_t) * radix_sort_scratch_words((size_t)mx));
+    if ((size_t)(p - static_cast<char*>(tmp)) > tmp_bytes) return hipErrorOutOfMemory;
     hipError_t e;
     k_box_init<<<1, 64, 0, stream>>>(box);
     if ((e = launch_zero(bad, 1, stream)) != hipSuccess) return e;
     if (n) {
         k_bbox<<<grid_for(n) < 1024 ? grid_for(n) : 1024, kBlock, 0, stream>>>(pos, (uint32_t)n, box);
         k_morton<<<grid_for(n), kBlock, 0, stream>>>(pos, (uint32_t)n, box, kin, vin);
-        size_t need = 0;
-        if ((e = rocprim::radix_sort_pairs(nullptr, need, kin, kout, vin, atom_id, (size_t)n, 0, 30, stream)) != hipSuccess)
-            return e;
-        if (need > sort_bytes) return hipErrorOutOfMemory;
-        if ((e = rocprim::radix_sort_pairs(sort_tmp, need, kin, kout, vin, atom_id, (size_t)n, 0, 30, stream)) != hipSuccess)
+        if ((e = radix_sort_pairs(kin, kout, vin, vout, atom_id, (size_t)n, 30, sort_tmp, stream)) != hipSuccess)
             return e;
         k_gather_atoms<<<grid_for(n), kBlock, 0, stream>>>(pos, rad, atom_id, (uint32_t)n, xyzr, inv);
     }
     uint32_t mv = 0, nb = 0;
     if (m) {
         k_bond_keys<<<grid_for(m), kBlock, 0, stream>>>(bonds, (uint32_t)m, (uint32_t)n, inv, kin, vin, bad);
-        size_t need = 0;
-        if ((e = rocprim::radix_sort_pairs(nullptr, need, kin, kout, vin, vout, (size_t)m, 0, 32, stream)) != hipSuccess)
-            return e;
-        if (need > sort_bytes) return hipErrorOutOfMemory;
-        if ((e = rocprim::radix_sort_pairs(sort_tmp, need, kin, kout, vin, vout, (size_t)m, 0, 32, stream)) != hipSuccess)
+        // sorted bond indices land in vin
+        if ((e = radix_sort_pairs(kin, kout, vin, vout, vin, (size_t)m, 32, sort_tmp, stream)) != hipSuccess)
             return e;
         if ((e = hipMemcpyAsync(&nb, bad, sizeof(uint32_t), hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
         if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;
         mv = (uint32_t)m - nb;
-        k_bond_records<<<grid_for(mv), kBlock, 0, stream>>>(bonds, vout, mv, inv, bond_rec);
+        if (mv) k_bond_records<<<grid_for(mv), kBlock, 0, stream>>>(bonds, vin, mv, inv, bond_rec);
     }
     S.n_bonds = mv;
     S.bond_clusters = (mv + kCluster - 1) / kCluster;
@@ -316,6 +306,21 @@ hipError_t scene_build(const float* pos, const float* rad, const uint32_t* bonds
     // the atoms' bounding box (order-preserving bits, min xyz then max xyz),
     // host memory, valid once the stream has reached this point
     if ((e = hipMemcpyAsync(box_bits, box, 6 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+// Original index of each stored bond.
+__global__ void __launch_bounds__(kBlock) k_bond_order(const uint4* __restrict__ rec, uint32_t m, uint32_t* out) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < m) out[j] = rec[j].z;
+}
+
+hipError_t scene_order(const SceneDev& S, uint32_t* atom_order, uint32_t* bond_order, hipStream_t stream) {
+    hipError_t e;
+    if (atom_order && S.n_atoms &&
+        (e = hipMemcpyAsync(atom_order, S.atom_id, sizeof(uint32_t) * S.n_atoms, hipMemcpyDeviceToDevice, stream)))
+        return e;
+    if (bond_order && S.n_bonds) k_bond_order<<<grid_for(S.n_bonds), kBlock, 0, stream>>>(S.bond_rec, S.n_bonds, bond_order);
     return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@
 // the nearest exterior point within a W-box by three separable 1-D passes
 // in integers (x: nearest exterior point on the row; y and z: the least of
 // g + d^2 over the window); triangle counts per cube; an exclusive scan of
-// the counts; emission of each cube's triangles at its offset.
+// the counts (scan.hip); emission of each cube's triangles at its offset.
 #include <mutex>
 
 #include "vtx_internal.h"
@@ -257,78 +257,6 @@ __global__ void __launch_bounds__(kSesBlock) k_ses_count(SesGrid G, const float*
     cnt[q] = c_case_tris[cube_case(G, f, i, j, k, v)];
 }
 
-// Exclusive scan of n counts in three launches: block sums of 4096-element
-// blocks, a scan of those sums by one workgroup (with the total), then each
-// block's scan plus its start.
-constexpr int kScanPer = 16;
-constexpr int kScanSpan = kSesBlock * kScanPer;
-
-__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
-    const int lane = __lane_id(), wave = threadIdx.x >> 6;
-    uint32_t incl = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t u = __shfl_up(incl, o);
-        if (lane >= o) incl += u;
-    }
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    uint32_t before = 0, all = 0;
-    for (int w = 0; w < kSesBlock / 64; ++w) {
-        before += w < wave ? wsum[w] : 0u;
-        all += wsum[w];
-    }
-    __syncthreads();
-    *total = all;
-    return before + incl - v;
-}
-
-__global__ void __launch_bounds__(kSesBlock) k_scan_sums(const uint32_t* __restrict__ cnt, size_t n,
-                                                         uint32_t* __restrict__ bsum) {
-    __shared__ uint32_t wsum[kSesBlock / 64];
-    const size_t base = (size_t)blockIdx.x * kScanSpan + (size_t)threadIdx.x * kScanPer;
-    uint32_t s = 0;
-    for (int i = 0; i < kScanPer; ++i)
-        if (base + i < n) s += cnt[base + i];
-    uint32_t total;
-    (void)block_excl_scan(s, wsum, &total);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
-}
-
-__global__ void __launch_bounds__(kSesBlock) k_scan_top(uint32_t* __restrict__ bsum, uint32_t nb,
-                                                        unsigned long long* __restrict__ n_out) {
-    __shared__ uint32_t wsum[kSesBlock / 64];
-    uint32_t carry = 0;
-    for (uint32_t b0 = 0; b0 < nb; b0 += kSesBlock) {
-        const uint32_t b = b0 + threadIdx.x;
-        const uint32_t v = b < nb ? bsum[b] : 0u;
-        uint32_t total;
-        const uint32_t ex = block_excl_scan(v, wsum, &total);
-        if (b < nb) bsum[b] = carry + ex;
-        carry += total;
-    }
-    if (threadIdx.x == 0) *n_out = carry;
-}
-
-__global__ void __launch_bounds__(kSesBlock) k_scan_apply(uint32_t* __restrict__ cnt, size_t n,
-                                                          const uint32_t* __restrict__ bsum) {
-    __shared__ uint32_t wsum[kSesBlock / 64];
-    const size_t base = (size_t)blockIdx.x * kScanSpan + (size_t)threadIdx.x * kScanPer;
-    uint32_t v[kScanPer], s = 0;
-#pragma unroll
-    for (int i = 0; i < kScanPer; ++i) {
-        v[i] = base + i < n ? cnt[base + i] : 0u;
-        s += v[i];
-    }
-    uint32_t total;
-    uint32_t run = bsum[blockIdx.x] + block_excl_scan(s, wsum, &total);
-#pragma unroll
-    for (int i = 0; i < kScanPer; ++i) {
-        if (base + i < n) cnt[base + i] = run;
-        run += v[i];
-    }
-}
-
 // Each cube's triangles at its offset (those past the capacity are dropped).
 __global__ void __launch_bounds__(kSesBlock) k_ses_emit(SesGrid G, const float* __restrict__ f,
                                                         const uint32_t* __restrict__ off, float* __restrict__ tri,
@@ -400,7 +328,6 @@ hipError_t ses_run(const float* pos, const float* rad, uint64_t n, float probe, 
     G.W = (int)ceil(G.rp / G.h) + 2;
     const size_t np = (size_t)G.nx * G.ny * G.nz;
     const size_t nc = (size_t)(G.nx - 1) * (G.ny - 1) * (G.nz - 1);
-    const size_t nb = (nc + kScanSpan - 1) / kScanSpan;
     if ((e = launch_zero(reinterpret_cast<uint32_t*>(s.mark), (np + 3) / 4, stream)) != hipSuccess) return e;
     if (n && (e = dispatch(k_ses_mark, (unsigned)n, kSesBlock, 0, stream, pos, rad, (uint32_t)n, G, s.mark)))
         return e;
@@ -411,9 +338,7 @@ hipError_t ses_run(const float* pos, const float* rad, uint64_t n, float probe, 
     if ((e = dispatch(k_ses_edt_yz<true>, gp, kSesBlock, 0, stream, G, (const int32_t*)s.gb, s.ga, field))) return e;
     const unsigned gc = (unsigned)((nc + kSesBlock - 1) / kSesBlock);
     if ((e = dispatch(k_ses_count, gc, kSesBlock, 0, stream, G, (const float*)field, s.cnt))) return e;
-    if ((e = dispatch(k_scan_sums, (unsigned)nb, kSesBlock, 0, stream, (const uint32_t*)s.cnt, nc, s.bsum))) return e;
-    if ((e = dispatch(k_scan_top, 1, kSesBlock, 0, stream, s.bsum, (uint32_t)nb, n_tri))) return e;
-    if ((e = dispatch(k_scan_apply, (unsigned)nb, kSesBlock, 0, stream, s.cnt, nc, (const uint32_t*)s.bsum))) return e;
+    if ((e = exclusive_scan(s.cnt, nc, s.bsum, n_tri, stream))) return e;
     return dispatch(k_ses_emit, gc, kSesBlock, 0, stream, G, (const float*)field, (const uint32_t*)s.cnt, tri,
                     (unsigned long long)capacity);
 }
@@ -424,7 +349,7 @@ size_t ses_scratch_words(const int dims[3], size_t* mark_words, size_t* g_words,
     *mark_words = (np + 3) / 4;
     *g_words = np;
     *cnt_words = nc;
-    *bsum_words = (nc + kScanSpan - 1) / kScanSpan + 1;
+    *bsum_words = scan_scratch_words(nc);
     return *mark_words + 2 * *g_words + *cnt_words + *bsum_words;
 }
 

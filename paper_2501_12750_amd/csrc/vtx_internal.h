@@ -352,6 +352,17 @@ struct SceneDev {
     uint32_t* vis_clusters;             // kDepthBuckets regions of atom_clusters + bond_clusters entries:
                                         // visible cluster ids per depth class (per render)
 };
+// Stable radix sort (sort.hip) of n (key, value) pairs by the low end_bit
+// bits of the keys, 8 bits per pass.  keys/vals hold the input and are
+// overwritten, like keys_alt/vals_alt; the sorted values go to vals_out,
+// which may be vals when the number of passes is even, vals_alt when it is
+// odd.  scratch holds radix_sort_scratch_words(n) words.
+size_t radix_sort_scratch_words(size_t n);
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt,
+                            uint32_t* vals_out, size_t n, int end_bit, uint32_t* scratch, hipStream_t stream);
+// Original index of each stored atom and of each stored bond (device
+// arrays; either may be null).
+hipError_t scene_order(const SceneDev& S, uint32_t* atom_order, uint32_t* bond_order, hipStream_t stream);
 size_t scene_build_temp_bytes(uint64_t n, uint64_t m);
 hipError_t scene_build(const float* pos, const float* rad, const uint32_t* bonds, uint64_t n, uint64_t m,
                        SceneDev& S, float4* xyzr, uint32_t* atom_id, uint4* bond_rec, float4* cluster_box,
@@ -475,6 +486,11 @@ hipError_t launch_downsample(const float* sdepth, const uint32_t* sid, const uin
 // `noise`: some job asks for the noise form of the ambient occlusion.
 hipError_t launch_shade(const OneJob& js, uint32_t grid, bool noise, hipStream_t stream);
 hipError_t launch_shade(const JobList& js, uint32_t grid, bool noise, hipStream_t stream);
+
+// In-place exclusive prefix sum of n counts (scan.hip); bsum needs
+// scan_scratch_words(n) words; *total (may be null) gets the sum.
+size_t scan_scratch_words(size_t n);
+hipError_t exclusive_scan(uint32_t* v, size_t n, uint32_t* bsum, unsigned long long* total, hipStream_t stream);
 
 // Solvent excluded surface (ses.hip): scratch of one call, sized by
 // ses_scratch_words, and the passes (queued on `stream`; field may not be

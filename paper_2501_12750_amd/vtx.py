@@ -41,7 +41,7 @@ EXPORTS = ("vtx_render", "vtx_gbuffer", "vtx_shade", "vtx_read_stats", "vtx_set_
            "vtx_read_timings", "vtx_reset_timings", "vtx_release_scratch", "vtx_last_error", "vtx_version",
            "vtx_context_create", "vtx_context_destroy", "vtx_context_bytes_in_use", "vtx_scene_footprint_bytes",
            "vtx_frame_scratch_bytes", "vtx_scene_create", "vtx_scene_update_positions", "vtx_scene_info",
-           "vtx_scene_destroy", "vtx_render_scene", "vtx_scene_add_frames", "vtx_scene_frames",
+           "vtx_scene_order", "vtx_scene_destroy", "vtx_render_scene", "vtx_scene_add_frames", "vtx_scene_frames",
            "vtx_scene_frame_bytes", "vtx_render_batch", "vtx_autotune", "vtx_clock_s", "vtx_server_create",
            "vtx_server_submit", "vtx_server_poll", "vtx_server_drain", "vtx_server_stats_read",
            "vtx_server_destroy", "vtx_check_job", "vtx_batch_graph_create",
@@ -177,6 +177,8 @@ _lib.vtx_scene_update_positions.argtypes = [_P, _P, _P]
 _lib.vtx_scene_info.restype = ctypes.c_int
 _lib.vtx_scene_info.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_uint64),
                                 ctypes.POINTER(ctypes.c_size_t)]
+_lib.vtx_scene_order.restype = ctypes.c_int
+_lib.vtx_scene_order.argtypes = [_P, _P, _P, _P]
 _lib.vtx_scene_destroy.restype = None
 _lib.vtx_scene_destroy.argtypes = [_P]
 _lib.vtx_render_scene.restype = ctypes.c_int
@@ -386,6 +388,12 @@ def vtx_scene_info(scene) -> dict:
     return {"n_atoms": n.value, "n_bonds": m.value, "bad_bonds": bad.value, "bytes": nbytes.value}
 
 
+def vtx_scene_order(scene, atom_order, bond_order, stream=None):
+    """Original index of each stored atom / stored bond into device arrays
+    (either may be None)."""
+    _check(_lib.vtx_scene_order(scene, _addr(atom_order), _addr(bond_order), _stream(stream)))
+
+
 def vtx_scene_destroy(scene):
     _lib.vtx_scene_destroy(scene)
 
@@ -593,6 +601,19 @@ class ResidentScene:
 
     def info(self):
         return vtx_scene_info(self.handle)
+
+    def order(self, stream=None):
+        """(atom_order, bond_order) as int64 host arrays: the original index
+        of each stored atom and of each stored bond."""
+        import torch
+        info = self.info()
+        a = torch.empty(max(1, info["n_atoms"]), dtype=torch.int32, device="cuda")
+        b = torch.empty(max(1, info["n_bonds"] - info["bad_bonds"]), dtype=torch.int32, device="cuda")
+        vtx_scene_order(self.handle, a, b, stream)
+        torch.cuda.synchronize()
+        mask = 0xFFFFFFFF
+        return ((a.cpu().numpy().astype("int64") & mask)[:info["n_atoms"]],
+                (b.cpu().numpy().astype("int64") & mask)[:info["n_bonds"] - info["bad_bonds"]])
 
     def close(self):
         if self.handle:
