@@ -55,6 +55,7 @@ extern "C" {
 
 #define VTX_BACKGROUND_ID 0xFFFFFFFFu
 #define VTX_MAX_PIXELS (7680 * 4320)   /* 8K, the paper's largest export size */
+#define VTX_MAX_SIDE 16383             /* pixels on either side of a rendered frame */
 #define VTX_MAX_SSAO_SAMPLES 64
 
 /* options.flags */
@@ -253,7 +254,8 @@ typedef struct vtx_timings {
  *   depth      W x H float out (required: the G-buffer the deferred pass reads)
  *   id         W x H uint32 out (required)
  * Requires n_atoms >= 0, n_bonds >= 0, n_atoms + n_bonds < 2^32 - 1,
- * 1 <= W, H and W * H <= VTX_MAX_PIXELS.  Errors: VTX_EINVAL, VTX_ENOMEM, VTX_EHIP.
+ * 1 <= W, H <= VTX_MAX_SIDE and W * H <= VTX_MAX_PIXELS (both after
+ * supersampling).  Errors: VTX_EINVAL, VTX_ENOMEM, VTX_EHIP.
  */
 int vtx_render(const float* positions, const float* radii, const uint32_t* colors, int64_t n_atoms,
                const uint32_t* bonds, int64_t n_bonds, const vtx_camera* cam, const vtx_options* opt,

@@ -448,6 +448,8 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
         return fail(VTX_EINVAL, "image %dx%d supersampled %d times exceeds %d pixels", W, H, ss, VTX_MAX_PIXELS);
     W *= ss;
     H *= ss;
+    if (W > VTX_MAX_SIDE || H > VTX_MAX_SIDE)
+        return fail(VTX_EINVAL, "image %dx%d has a side above %d pixels", W, H, VTX_MAX_SIDE);
     if (n < 0 || m < 0 || n + m >= (int64_t)0xFFFFFFFFll)
         return fail(VTX_EINVAL, "n_atoms=%lld n_bonds=%lld out of range", (long long)n, (long long)m);
     if (!finite3(cam->eye) || !finite3(cam->target) || !finite3(cam->up))

@@ -406,7 +406,10 @@ __global__ void __launch_bounds__(kBinThreads) k_layers(JS js) {
     }
 }
 
-constexpr uint32_t kNoRun = 0xFFFFFFFFu;
+// Scatter cursor of a tile this workgroup has no run in (its list did not
+// fit, or it has no primitive there).  Slots are below kMaxCapacity <=
+// 2^28, and adding at most a workgroup's pairs keeps the flag bit set.
+constexpr uint32_t kNoRun = 0x80000000u;
 
 // List offsets: the exclusive prefix sum of the tile counts, once per job
 // (work block j of the launch scans job j's counts), with the list total and
@@ -460,12 +463,21 @@ __global__ void __launch_bounds__(kBinThreads) k_tile_offsets(JS js) {
     }
 }
 
-// Scatter.  Every workgroup walks the tile offsets (k_tile_offsets) and
-// reserves, for each tile its primitives touch, one run of that tile's list
-// (one global atomic); it then places its primitives with LDS atomics.
-// Workgroup 0 also publishes the frame counters.
+// Scatter.  Every workgroup reserves, for each tile its primitives touch,
+// one run of that tile's list (one global atomic), then places its visible
+// primitives kScatterPer per thread at a time, all their loads issued
+// before any is used.  Lanes of a wave whose primitive lies in one tile are
+// grouped by tile (up to kScatterGroups groups, the rest alone); every group
+// leader and every ungrouped lane takes its slots with one LDS atomic of the
+// same instruction, and group members follow their leader.  Primitives
+// spanning several tiles take one LDS atomic per tile.  Workgroup 0 also
+// publishes the frame counters.
+constexpr int kScatterPer = 4;
+constexpr int kScatterGroups = 4;
+
 template <class JS>
-__global__ void __launch_bounds__(kBinThreads) k_scatter(JS js, int phase) {
+__global__ void __launch_bounds__(kBinThreads, 8) k_scatter(JS js, int phase) {
+    constexpr int kTileRows = (kMaxLdsTiles + kBinThreads - 1) / kBinThreads;
     extern __shared__ uint32_t cur[];
     __shared__ unsigned int n_over;
     uint32_t blk;
@@ -495,14 +507,29 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js, int phase) {
     __syncthreads();
     const uint32_t* row = hist_in + (size_t)blk * T;
     unsigned int over = 0;
-    for (int t = tid; t < T; t += kBinThreads) {
-        const uint64_t run = off[t];
-        const bool fits = run + cnt[t] <= capacity;      // else the resolve rebuilds this tile from the visible lists
-        const uint32_t h = row[t];
-        uint32_t r = kNoRun;
-        if (h && fits) r = (uint32_t)(run + (loff ? loff[t] : 0u) + atomicAdd(&fill[t], h));
-        cur[t] = r;
-        over += fits ? 0u : 1u;
+    {
+        // this workgroup's count of every tile first, then the reservations
+        // of the touched tiles, so the loads and atomics overlap
+        uint32_t h[kTileRows], r[kTileRows];
+#pragma unroll
+        for (int q = 0; q < kTileRows; ++q) {
+            const int t = q * kBinThreads + tid;
+            h[q] = t < T ? row[t] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < kTileRows; ++q) {
+            const int t = q * kBinThreads + tid;
+            r[q] = h[q] ? atomicAdd(&fill[t], h[q]) : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < kTileRows; ++q) {
+            const int t = q * kBinThreads + tid;
+            if (t >= T) break;
+            const uint64_t run = off[t];
+            const bool fits = run + cnt[t] <= capacity;   // else the resolve rebuilds this tile from the visible lists
+            cur[t] = h[q] && fits ? (uint32_t)(run + (loff ? loff[t] : 0u) + r[q]) : kNoRun;
+            over += fits ? 0u : 1u;
+        }
     }
     if (lead) {
         if (over) atomicAdd(&n_over, over);
@@ -555,7 +582,9 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js, int phase) {
     }
     __syncthreads();
     const uint32_t n = vis_cnt[blk];
-    const uint64_t start = (uint64_t)blk * chunk;
+    if (n == 0) return;
+    const uint32_t* __restrict__ const my_src = vis_src + (size_t)blk * chunk;
+    const uint2* __restrict__ const my_rect = vis_rect + (size_t)blk * chunk;
     const int ts = F.tile, tsh = F.tile_shift;
     // the footprint clipped to tile (tx, ty), in tile-local pixels
     auto local_fp = [&](int x0, int y0, int x1, int y1, int tx, int ty) -> uint32_t {
@@ -564,58 +593,63 @@ __global__ void __launch_bounds__(kBinThreads) k_scatter(JS js, int phase) {
         return (uint32_t)lx0 | ((uint32_t)ly0 << 8) | ((uint32_t)(lx1 - lx0 + 1) << 16) |
                ((uint32_t)(ly1 - ly0 + 1) << 24);
     };
-    const uint32_t rounds = (n + kBinThreads - 1) / kBinThreads;   // uniform trip count (wave ops inside)
-    uint32_t src = 0;
-    uint2 r = make_uint2(0u, 0u);
-    if ((uint32_t)tid < n) {
-        src = vis_src[start + tid];
-        r = vis_rect[start + tid];
-    }
-    for (uint32_t it = 0; it < rounds; ++it) {
-        const uint32_t k = it * kBinThreads + tid;
-        const bool have = k < n;
-        // the next primitive is loaded while this one is placed
-        uint32_t nsrc = 0;
-        uint2 nr = make_uint2(0u, 0u);
-        if (k + kBinThreads < n) {
-            nsrc = vis_src[start + k + kBinThreads];
-            nr = vis_rect[start + k + kBinThreads];
+    const int lane = __lane_id();
+    const unsigned long long lt = __lanemask_lt();
+    constexpr uint32_t kSpan = (uint32_t)kBinThreads * kScatterPer;
+    for (uint32_t base = 0; base < n; base += kSpan) {   // uniform trip count (wave ops inside)
+        uint32_t src[kScatterPer];
+        uint2 rc[kScatterPer];
+#pragma unroll
+        for (int p = 0; p < kScatterPer; ++p) {
+            // past the end: a copy of the last entry, dropped below (loads stay in bounds)
+            const uint32_t k = min(base + (uint32_t)(p * kBinThreads + tid), n - 1u);
+            src[p] = my_src[k];
+            rc[p] = my_rect[k];
         }
-        const int x0 = r.x & 0xFFFF, y0 = r.x >> 16, x1 = r.y & 0xFFFF, y1 = r.y >> 16;
-        const int tx0 = x0 >> tsh, tx1 = x1 >> tsh, ty0 = y0 >> tsh, ty1 = y1 >> tsh;
-        const bool single = have && tx0 == tx1 && ty0 == ty1;
-        // single-tile records: lanes sharing a tile take one run of its list
-        // with one LDS atomic (at most four distinct tiles per wave this way)
-        const int t1 = single ? ty0 * F.tiles_x + tx0 : -1;
-        unsigned long long pend = __ballot(single);
-        uint32_t my_slot = kNoRun;
-        for (int g = 0; g < 4 && pend; ++g) {
-            const int leader = __ffsll((long long)pend) - 1;
-            const int tl = __shfl(t1, leader);
-            const unsigned long long grp = __ballot(t1 == tl) & pend;
-            uint32_t base = kNoRun;
-            if ((int)__lane_id() == leader) {
-                base = cur[tl];
-                if (base != kNoRun) base = atomicAdd(&cur[tl], (uint32_t)__popcll(grp));
+#pragma unroll
+        for (int p = 0; p < kScatterPer; ++p) {
+            const bool have = base + (uint32_t)(p * kBinThreads + tid) < n;
+            const int x0 = rc[p].x & 0xFFFF, y0 = rc[p].x >> 16, x1 = rc[p].y & 0xFFFF, y1 = rc[p].y >> 16;
+            const int tx0 = x0 >> tsh, tx1 = x1 >> tsh, ty0 = y0 >> tsh, ty1 = y1 >> tsh;
+            const bool single = have && tx0 == tx1 && ty0 == ty1;
+            const int t1 = single ? ty0 * F.tiles_x + tx0 : -1;
+            unsigned long long pend = __ballot(single);
+            uint32_t add = 0;
+            int my_group = -1;
+            int leaders[kScatterGroups];
+            unsigned long long groups[kScatterGroups];
+            int ng = 0;
+#pragma unroll
+            for (int g = 0; g < kScatterGroups; ++g) {
+                if (!pend) break;
+                const int leader = __ffsll((long long)pend) - 1;
+                const int tl = __builtin_amdgcn_readlane(t1, leader);
+                const unsigned long long grp = __ballot(t1 == tl) & pend;
+                leaders[g] = leader;
+                groups[g] = grp;
+                ng = g + 1;
+                if ((grp >> lane) & 1ull) my_group = g;
+                if (lane == leader) add = (uint32_t)__popcll(grp);
+                pend &= ~grp;
             }
-            base = __shfl(base, leader);
-            if ((grp >> __lane_id()) & 1ull)
-                my_slot = base == kNoRun ? kNoRun : base + (uint32_t)__popcll(grp & __lanemask_lt());
-            pend &= ~grp;
+            if ((pend >> lane) & 1ull) add = 1u;
+            uint32_t slot = add ? atomicAdd(&cur[t1], add) : 0u;
+#pragma unroll
+            for (int g = 0; g < kScatterGroups; ++g) {
+                if (g >= ng) break;
+                const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)slot, leaders[g]);
+                if (my_group == g) slot = b + (uint32_t)__popcll(groups[g] & lt);
+            }
+            if (single) {
+                if (!(slot & kNoRun)) list[slot] = make_uint2(src[p], local_fp(x0, y0, x1, y1, tx0, ty0));
+            } else if (have) {
+                for (int ty = ty0; ty <= ty1; ++ty)
+                    for (int tx = tx0; tx <= tx1; ++tx) {
+                        const uint32_t sl = atomicAdd(&cur[ty * F.tiles_x + tx], 1u);
+                        if (!(sl & kNoRun)) list[sl] = make_uint2(src[p], local_fp(x0, y0, x1, y1, tx, ty));
+                    }
+            }
         }
-        if (single) {
-            if ((pend >> __lane_id()) & 1ull) my_slot = cur[t1] == kNoRun ? kNoRun : atomicAdd(&cur[t1], 1u);
-            if (my_slot != kNoRun) list[my_slot] = make_uint2(src, local_fp(x0, y0, x1, y1, tx0, ty0));
-        } else if (have) {
-            for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx) {
-                    const int t = ty * F.tiles_x + tx;
-                    if (cur[t] == kNoRun) continue;
-                    list[atomicAdd(&cur[t], 1u)] = make_uint2(src, local_fp(x0, y0, x1, y1, tx, ty));
-                }
-        }
-        src = nsrc;
-        r = nr;
     }
 }
 

@@ -187,6 +187,13 @@ def test_invalid_arguments_raise(vtx):
         vtx.vtx_render(*ds.args(), wl.camera, with_opts(wl.options, tile_size=12), 8, 8, fr.rgba, fr.depth, fr.id)
     with pytest.raises(vtx.VtxError):
         vtx.vtx_render(*ds.args(), wl.camera, wl.options, 8, 8, None, fr.depth, fr.id)
+    # a side above VTX_MAX_SIDE (16383) is refused even when the pixel count fits
+    wide = vtx.Frame(16384, 2)
+    with pytest.raises(vtx.VtxError):
+        vtx.vtx_render(*ds.args(), wl.camera, wl.options, 16384, 2, wide.rgba, wide.depth, wide.id)
+    with pytest.raises(vtx.VtxError):
+        vtx.vtx_render(*ds.args(), wl.camera, with_opts(wl.options, supersample=2), 8192, 2, wide.rgba, wide.depth,
+                       wide.id)
 
 
 def test_fragment_count_matches_oracle(vtx):
