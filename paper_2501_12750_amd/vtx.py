@@ -26,6 +26,7 @@ VTX_PERSPECTIVE = 0
 VTX_ORTHOGRAPHIC = 1
 VTX_BACKGROUND_ID = 0xFFFFFFFF
 VTX_MAX_PIXELS = 7680 * 4320
+VTX_MAX_SIDE = 16383
 VTX_MAX_SSAO_SAMPLES = 64
 VTX_SSAO_AUTO = -1
 VTX_FLAG_STATS = 1
