@@ -123,6 +123,13 @@ __device__ inline uint32_t wave_scan_u32(uint32_t v) {
     return v;
 }
 
+// Tile of entry i of a workgroup's histogram row: the row covers the box of
+// tiles [bx0, bx0 + bw) x [by0, ...) its primitives touch, row-major.
+__device__ inline int box_tile(const Frame& F, uint32_t bx0, uint32_t by0, int bw, int i) {
+    const int q = i / bw;
+    return ((int)by0 + q) * F.tiles_x + (int)bx0 + (i - q * bw);
+}
+
 // Rest pass of a two-pass frame: true when cluster c cannot win a pixel.
 // The lower bound of the cull depth of its primitives (the bounding sphere
 // of its box, widened as in the frustum test, with the margin of the
@@ -347,9 +354,13 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
     uint32_t* const tot = kScene && J.bb.layers > 1
                               ? J.bb.layer_sum + (size_t)layer_of(blk, J.bb.groups, J.bb.layers) * T
                               : tile_cnt;
-    for (int t = tid; t < T; t += kBinThreads) {
+    // the histogram row holds the tiles of the workgroup's box only (see
+    // box_tile), row-major within the box
+    const int bw = bx0 <= bx1 ? (int)(bx1 - bx0) + 1 : 0, nb = bw * (bw ? (int)(by1 - by0) + 1 : 0);
+    for (int i = tid; i < nb; i += kBinThreads) {
+        const int t = box_tile(F, bx0, by0, bw, i);
         const uint32_t h = hist[t];
-        row[t] = h;
+        row[i] = h;
         if (h) atomicAdd(&tot[t], h);
     }
     if (tid == 0) {
@@ -423,6 +434,7 @@ __global__ void __launch_bounds__(kBinThreads) k_tile_offsets(JS js) {
     constexpr int kRows = (kMaxLdsTiles + kBinThreads - 1) / kBinThreads;
     constexpr int kWaves = kBinThreads / 64;
     __shared__ uint32_t wsum[kRows][kWaves];
+    __shared__ uint32_t over_sum;
     if (blockIdx.x >= js.count()) return;
     const Job& J = js.job((int)blockIdx.x);
     const int T = J.F.tiles_x * J.F.tiles_y;
@@ -431,6 +443,8 @@ __global__ void __launch_bounds__(kBinThreads) k_tile_offsets(JS js) {
     const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
     const int rows = (T + kBinThreads - 1) / kBinThreads;
     uint32_t v[kRows], incl[kRows];
+    uint32_t n_over = 0;
+    if (tid == 0) over_sum = 0;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
         const int t = r * kBinThreads + tid;
@@ -454,12 +468,20 @@ __global__ void __launch_bounds__(kBinThreads) k_tile_offsets(JS js) {
             before += w < wave ? wsum[r][w] : 0u;
         }
         const int t = r * kBinThreads + tid;
-        if (t < T) off[t] = base + before + (incl[r] - v[r]);
+        if (t < T) {
+            const uint64_t o = base + before + (incl[r] - v[r]);
+            off[t] = o;
+            n_over += o + v[r] > J.bb.capacity ? 1u : 0u;   // lists the scatter leaves to the resolve's tail
+        }
         base += row_total;
     }
+    for (int o = 32; o > 0; o >>= 1) n_over += (uint32_t)__shfl_xor((int)n_over, o);
+    if (lane == 0 && n_over) atomicAdd(&over_sum, n_over);
+    __syncthreads();
     if (tid == 0) {
         J.bb.ctr->pairs = base;
         J.bb.ctr->overflow = base > J.bb.capacity ? 1u : 0u;
+        J.bb.ctr->overflow_tiles = over_sum;
     }
 }
 
@@ -479,7 +501,6 @@ template <class JS>
 __global__ void __launch_bounds__(kBinThreads, 8) k_scatter(JS js, int phase) {
     constexpr int kTileRows = (kMaxLdsTiles + kBinThreads - 1) / kBinThreads;
     extern __shared__ uint32_t cur[];
-    __shared__ unsigned int n_over;
     uint32_t blk;
     const int ji = js.find(blockIdx.x, blk);
     if (ji < 0) return;
@@ -503,41 +524,40 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_scatter(JS js, int phase) {
     const uint32_t* __restrict__ const loff = J.bb.layers > 1 ? J.bb.layer_off + (size_t)lay * T : nullptr;
     const int tid = threadIdx.x;
     const bool lead = blk == 0;
-    if (tid == 0) n_over = 0;
-    __syncthreads();
     const uint32_t* row = hist_in + (size_t)blk * T;
-    unsigned int over = 0;
     {
-        // this workgroup's count of every tile first, then the reservations
-        // of the touched tiles, so the loads and atomics overlap
+        // the workgroup's tile box (its primitives touch no tile outside it,
+        // whose cursors are never read); the box's counts first, then the
+        // reservations of the touched tiles, so the loads and atomics overlap
+        const uint2 box = J.bb.vis_box[blk];
+        const uint32_t bx0 = box.x & 0xFFFFu, by0 = box.x >> 16, bx1 = box.y & 0xFFFFu, by1 = box.y >> 16;
+        const int bw = bx0 <= bx1 ? (int)(bx1 - bx0) + 1 : 0, nb = bw * (bw ? (int)(by1 - by0) + 1 : 0);
         uint32_t h[kTileRows], r[kTileRows];
 #pragma unroll
         for (int q = 0; q < kTileRows; ++q) {
-            const int t = q * kBinThreads + tid;
-            h[q] = t < T ? row[t] : 0u;
+            const int i = q * kBinThreads + tid;
+            h[q] = i < nb ? row[i] : 0u;
         }
 #pragma unroll
         for (int q = 0; q < kTileRows; ++q) {
-            const int t = q * kBinThreads + tid;
-            r[q] = h[q] ? atomicAdd(&fill[t], h[q]) : 0u;
+            const int i = q * kBinThreads + tid;
+            r[q] = h[q] ? atomicAdd(&fill[box_tile(F, bx0, by0, bw, i)], h[q]) : 0u;
         }
 #pragma unroll
         for (int q = 0; q < kTileRows; ++q) {
-            const int t = q * kBinThreads + tid;
-            if (t >= T) break;
+            const int i = q * kBinThreads + tid;
+            if (i >= nb) break;
+            const int t = box_tile(F, bx0, by0, bw, i);
             const uint64_t run = off[t];
             const bool fits = run + cnt[t] <= capacity;   // else the resolve rebuilds this tile from the visible lists
             cur[t] = h[q] && fits ? (uint32_t)(run + (loff ? loff[t] : 0u) + r[q]) : kNoRun;
-            over += fits ? 0u : 1u;
         }
     }
     if (lead) {
-        if (over) atomicAdd(&n_over, over);
-        __syncthreads();
         if (tid == 0) {
             const unsigned int vis = ctr->vis_count, bad = ctr->bad_bonds;
             const unsigned long long total = ctr->pairs;
-            ctr->overflow_tiles = n_over;
+            const unsigned int n_over = ctr->overflow_tiles;   // from k_tile_offsets
             ctr->vis_count = 0;            // the next frame's count kernel adds to these
             ctr->bad_bonds = 0;
             ctr->frag_tested = 0;          // this frame's resolve adds to these
