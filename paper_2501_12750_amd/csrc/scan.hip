@@ -35,14 +35,18 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t*
     return before + incl - v;
 }
 
-// Thread t of block b sums elements b * kScanSpan + t * kScanPer + [0, kScanPer).
+// Sum of block b's elements (loads coalesced: element b * kScanSpan +
+// r * kScanBlock + t for thread t, round r).
 __global__ void __launch_bounds__(kScanBlock) k_scan_sums(const uint32_t* __restrict__ v, size_t n,
                                                           uint32_t* __restrict__ bsum) {
     __shared__ uint32_t wsum[kScanBlock / 64];
-    const size_t base = (size_t)blockIdx.x * kScanSpan + (size_t)threadIdx.x * kScanPer;
+    const size_t base = (size_t)blockIdx.x * kScanSpan + threadIdx.x;
     uint32_t s = 0;
-    for (int i = 0; i < kScanPer; ++i)
-        if (base + i < n) s += v[base + i];
+#pragma unroll
+    for (int r = 0; r < kScanPer; ++r) {
+        const size_t i = base + (size_t)r * kScanBlock;
+        s += i < n ? v[i] : 0u;
+    }
     uint32_t total;
     (void)block_excl_scan(s, wsum, &total);
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
@@ -63,22 +67,42 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_top(uint32_t* __restrict__ 
     if (threadIdx.x == 0 && total_out) *total_out = carry;
 }
 
+// Block b's elements, loaded and stored coalesced through LDS: thread t
+// scans the kScanPer consecutive elements t * kScanPer + [0, kScanPer) of
+// the block (the LDS index skips one word every 32 so those reads spread
+// over the banks).
+__device__ inline int scan_lds(int i) { return i + (i >> 5); }
+
 __global__ void __launch_bounds__(kScanBlock) k_scan_apply(uint32_t* __restrict__ v, size_t n,
                                                            const uint32_t* __restrict__ bsum) {
     __shared__ uint32_t wsum[kScanBlock / 64];
-    const size_t base = (size_t)blockIdx.x * kScanSpan + (size_t)threadIdx.x * kScanPer;
+    __shared__ uint32_t buf[kScanSpan + kScanSpan / 32];
+    const size_t base = (size_t)blockIdx.x * kScanSpan;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < kScanPer; ++r) {
+        const int i = r * kScanBlock + t;
+        buf[scan_lds(i)] = base + i < n ? v[base + i] : 0u;
+    }
+    __syncthreads();
     uint32_t x[kScanPer], s = 0;
 #pragma unroll
-    for (int i = 0; i < kScanPer; ++i) {
-        x[i] = base + i < n ? v[base + i] : 0u;
-        s += x[i];
+    for (int r = 0; r < kScanPer; ++r) {
+        x[r] = buf[scan_lds(t * kScanPer + r)];
+        s += x[r];
     }
     uint32_t total;
     uint32_t run = bsum[blockIdx.x] + block_excl_scan(s, wsum, &total);
 #pragma unroll
-    for (int i = 0; i < kScanPer; ++i) {
-        if (base + i < n) v[base + i] = run;
-        run += x[i];
+    for (int r = 0; r < kScanPer; ++r) {
+        buf[scan_lds(t * kScanPer + r)] = run;
+        run += x[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kScanPer; ++r) {
+        const int i = r * kScanBlock + t;
+        if (base + i < n) v[base + i] = buf[scan_lds(i)];
     }
 }
 

@@ -160,7 +160,9 @@ __device__ inline size_t gidx(const SesGrid& G, int i, int j, int k) {
 }
 
 // One workgroup per atom: marks the grid points inside its solvent-accessible
-// sphere (interior = 1; points no atom marks stay 0: exterior).
+// sphere (interior = 1; points no atom marks stay 0: exterior).  Each thread
+// takes (i, j) columns of the atom's box and walks them along k with
+// dx^2 + dy^2 computed once per column.
 __global__ void __launch_bounds__(kSesBlock) k_ses_mark(const float* __restrict__ pos, const float* __restrict__ rad,
                                                         uint32_t n, SesGrid G, uint8_t* __restrict__ mark) {
 #pragma clang fp contract(off)
@@ -178,24 +180,40 @@ __global__ void __launch_bounds__(kSesBlock) k_ses_mark(const float* __restrict_
         hi[d] = min(nmax[d], (int)ceil((c[d] + R - G.o[d]) / G.h) + 1);
         if (lo[d] > hi[d]) return;
     }
-    const int bx = hi[0] - lo[0] + 1, by = hi[1] - lo[1] + 1, bz = hi[2] - lo[2] + 1;
-    const int total = bx * by * bz;
-    for (int q = threadIdx.x; q < total; q += kSesBlock) {
-        const int i = lo[0] + q % bx, j = lo[1] + (q / bx) % by, k = lo[2] + q / (bx * by);
-        const double dx = (G.o[0] + G.h * i) - cx, dy = (G.o[1] + G.h * j) - cy, dz = (G.o[2] + G.h * k) - cz;
-        const double d2 = (dx * dx + dy * dy) + dz * dz;
-        if (d2 < R2) mark[gidx(G, i, j, k)] = 1;
+    const int bx = hi[0] - lo[0] + 1, ncol = bx * (hi[1] - lo[1] + 1);
+    const size_t plane = (size_t)G.nx * G.ny;
+    for (int q = threadIdx.x; q < ncol; q += kSesBlock) {
+        const int j = lo[1] + q / bx, i = lo[0] + q % bx;
+        const double dx = (G.o[0] + G.h * i) - cx, dy = (G.o[1] + G.h * j) - cy;
+        const double sxy = dx * dx + dy * dy;
+        size_t p = gidx(G, i, j, lo[2]);
+        for (int k = lo[2]; k <= hi[2]; ++k, p += plane) {
+            const double dz = (G.o[2] + G.h * k) - cz;
+            if (sxy + dz * dz < R2) mark[p] = 1;
+        }
     }
+}
+
+// The per-point and per-cube passes run one thread per point (or cube) in
+// x-fastest order; the grid holds fewer than 2^31 points, so the index and
+// its decomposition stay in 32 bits.
+__device__ inline bool flat_item(uint32_t n, int nx, int ny, int& i, int& j, int& k, uint32_t& p) {
+    p = blockIdx.x * (uint32_t)kSesBlock + threadIdx.x;
+    if (p >= n) return false;
+    const uint32_t r = p / (uint32_t)nx;
+    i = (int)(p - r * (uint32_t)nx);
+    j = (int)(r % (uint32_t)ny);
+    k = (int)(r / (uint32_t)ny);
+    return true;
 }
 
 // x pass: squared distance along the row to the nearest exterior point
 // within W steps (kFar if none).
-__global__ void __launch_bounds__(kSesBlock) k_ses_edt_x(SesGrid G, const uint8_t* __restrict__ mark,
+__global__ void __launch_bounds__(kSesBlock) k_ses_edt_x(SesGrid G, uint32_t np, const uint8_t* __restrict__ mark,
                                                          int32_t* __restrict__ g) {
-    const size_t p = (size_t)blockIdx.x * kSesBlock + threadIdx.x;
-    const size_t n = (size_t)G.nx * G.ny * G.nz;
-    if (p >= n) return;
-    const int i = (int)(p % G.nx);
+    int i, j, k;
+    uint32_t p;
+    if (!flat_item(np, G.nx, G.ny, i, j, k, p)) return;
     int32_t best = kFar;
     for (int d = 0; d <= G.W; ++d) {
         const bool l = i - d >= 0 && !mark[p - d];
@@ -208,22 +226,22 @@ __global__ void __launch_bounds__(kSesBlock) k_ses_edt_x(SesGrid G, const uint8_
     g[p] = best;
 }
 
-// y or z pass (stride of the axis, length along it): the least of
-// g(p + d e) + d^2 over |d| <= W.  The z pass also writes the field.
+// y or z pass: the least of g(p + d e) + d^2 over |d| <= W along the axis.
+// The z pass also writes the field.
 template <bool kLast>
-__global__ void __launch_bounds__(kSesBlock) k_ses_edt_yz(SesGrid G, const int32_t* __restrict__ gin,
+__global__ void __launch_bounds__(kSesBlock) k_ses_edt_yz(SesGrid G, uint32_t np, const int32_t* __restrict__ gin,
                                                           int32_t* __restrict__ gout, float* __restrict__ field) {
-    const size_t p = (size_t)blockIdx.x * kSesBlock + threadIdx.x;
-    const size_t n = (size_t)G.nx * G.ny * G.nz;
-    if (p >= n) return;
-    const size_t stride = kLast ? (size_t)G.nx * G.ny : (size_t)G.nx;
+    int i, j, k;
+    uint32_t p;
+    if (!flat_item(np, G.nx, G.ny, i, j, k, p)) return;
+    const int stride = kLast ? G.nx * G.ny : G.nx;
     const int len = kLast ? G.nz : G.ny;
-    const int at = kLast ? (int)(p / stride) : (int)((p / G.nx) % G.ny);
+    const int at = kLast ? k : j;
     int32_t best = kFar;
     for (int d = -G.W; d <= G.W; ++d) {
         const int q = at + d;
         if (q < 0 || q >= len) continue;
-        const int32_t v = gin[(size_t)((long long)p + (long long)d * (long long)stride)];
+        const int32_t v = gin[(int)p + d * stride];
         if (v < kFar) best = min(best, v + d * d);
     }
     if (!kLast) {
@@ -246,26 +264,22 @@ __device__ inline int cube_case(const SesGrid& G, const float* __restrict__ f, i
 }
 
 // Triangles per cube.
-__global__ void __launch_bounds__(kSesBlock) k_ses_count(SesGrid G, const float* __restrict__ f,
+__global__ void __launch_bounds__(kSesBlock) k_ses_count(SesGrid G, uint32_t nc, const float* __restrict__ f,
                                                          uint32_t* __restrict__ cnt) {
-    const size_t q = (size_t)blockIdx.x * kSesBlock + threadIdx.x;
-    const int cx = G.nx - 1, cy = G.ny - 1;
-    const size_t nc = (size_t)cx * cy * (G.nz - 1);
-    if (q >= nc) return;
-    const int i = (int)(q % cx), j = (int)((q / cx) % cy), k = (int)(q / ((size_t)cx * cy));
+    int i, j, k;
+    uint32_t q;
+    if (!flat_item(nc, G.nx - 1, G.ny - 1, i, j, k, q)) return;
     float v[8];
     cnt[q] = c_case_tris[cube_case(G, f, i, j, k, v)];
 }
 
 // Each cube's triangles at its offset (those past the capacity are dropped).
-__global__ void __launch_bounds__(kSesBlock) k_ses_emit(SesGrid G, const float* __restrict__ f,
+__global__ void __launch_bounds__(kSesBlock) k_ses_emit(SesGrid G, uint32_t nc, const float* __restrict__ f,
                                                         const uint32_t* __restrict__ off, float* __restrict__ tri,
                                                         unsigned long long capacity) {
-    const size_t q = (size_t)blockIdx.x * kSesBlock + threadIdx.x;
-    const int cx = G.nx - 1, cy = G.ny - 1;
-    const size_t nc = (size_t)cx * cy * (G.nz - 1);
-    if (q >= nc) return;
-    const int i = (int)(q % cx), j = (int)((q / cx) % cy), k = (int)(q / ((size_t)cx * cy));
+    int i, j, k;
+    uint32_t q;
+    if (!flat_item(nc, G.nx - 1, G.ny - 1, i, j, k, q)) return;
     float v[8];
     const int m = cube_case(G, f, i, j, k, v);
     if (c_case_tris[m] == 0) return;
@@ -308,7 +322,6 @@ __global__ void __launch_bounds__(kSesBlock) k_ses_emit(SesGrid G, const float* 
         at += 1 + len;
     }
 }
-
 }  // namespace
 
 hipError_t ses_run(const float* pos, const float* rad, uint64_t n, float probe, const float origin[3], float spacing,
@@ -331,16 +344,20 @@ hipError_t ses_run(const float* pos, const float* rad, uint64_t n, float probe, 
     if ((e = launch_zero(reinterpret_cast<uint32_t*>(s.mark), (np + 3) / 4, stream)) != hipSuccess) return e;
     if (n && (e = dispatch(k_ses_mark, (unsigned)n, kSesBlock, 0, stream, pos, rad, (uint32_t)n, G, s.mark)))
         return e;
+    // rows of points along x (y-z rows), then rows of cubes
     const unsigned gp = (unsigned)((np + kSesBlock - 1) / kSesBlock);
-    if ((e = dispatch(k_ses_edt_x, gp, kSesBlock, 0, stream, G, (const uint8_t*)s.mark, s.ga))) return e;
-    if ((e = dispatch(k_ses_edt_yz<false>, gp, kSesBlock, 0, stream, G, (const int32_t*)s.ga, s.gb, (float*)nullptr)))
+    if ((e = dispatch(k_ses_edt_x, gp, kSesBlock, 0, stream, G, (uint32_t)np, (const uint8_t*)s.mark, s.ga))) return e;
+    if ((e = dispatch(k_ses_edt_yz<false>, gp, kSesBlock, 0, stream, G, (uint32_t)np, (const int32_t*)s.ga, s.gb,
+                      (float*)nullptr)))
         return e;
-    if ((e = dispatch(k_ses_edt_yz<true>, gp, kSesBlock, 0, stream, G, (const int32_t*)s.gb, s.ga, field))) return e;
+    if ((e = dispatch(k_ses_edt_yz<true>, gp, kSesBlock, 0, stream, G, (uint32_t)np, (const int32_t*)s.gb, s.ga,
+                      field)))
+        return e;
     const unsigned gc = (unsigned)((nc + kSesBlock - 1) / kSesBlock);
-    if ((e = dispatch(k_ses_count, gc, kSesBlock, 0, stream, G, (const float*)field, s.cnt))) return e;
+    if ((e = dispatch(k_ses_count, gc, kSesBlock, 0, stream, G, (uint32_t)nc, (const float*)field, s.cnt))) return e;
     if ((e = exclusive_scan(s.cnt, nc, s.bsum, n_tri, stream))) return e;
-    return dispatch(k_ses_emit, gc, kSesBlock, 0, stream, G, (const float*)field, (const uint32_t*)s.cnt, tri,
-                    (unsigned long long)capacity);
+    return dispatch(k_ses_emit, gc, kSesBlock, 0, stream, G, (uint32_t)nc, (const float*)field,
+                    (const uint32_t*)s.cnt, tri, (unsigned long long)capacity);
 }
 
 size_t ses_scratch_words(const int dims[3], size_t* mark_words, size_t* g_words, size_t* cnt_words, size_t* bsum_words) {
