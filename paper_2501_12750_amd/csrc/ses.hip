@@ -21,7 +21,8 @@
 // the nearest exterior point within a W-box by three separable 1-D passes
 // in integers (x: nearest exterior point on the row; y and z: the least of
 // g + d^2 over the window); triangle counts per cube; an exclusive scan of
-// the counts (scan.hip); emission of each cube's triangles at its offset.
+// the counts (scan.hip); emission of the triangles of the cubes that have
+// any, each at its offset.
 #include <mutex>
 
 #include "vtx_internal.h"
@@ -31,6 +32,7 @@ namespace vtx {
 namespace {
 
 constexpr int kSesBlock = 256;
+constexpr int kSesMarkBlock = 64;      // one wave per atom: its box setup is paid once per wave
 constexpr int32_t kFar = 0x3FFFFFFF;   // no exterior point within the window
 
 // Case table: for each case, its loops as a byte string: loop length, then
@@ -150,6 +152,7 @@ hipError_t ensure_cases(int device) {
 struct SesGrid {
     double o[3];
     double h;
+    double inv_h;       // 1 / h (bounding boxes only)
     int nx, ny, nz;
     int W;              // distance window in grid steps
     double rp;
@@ -159,12 +162,13 @@ __device__ inline size_t gidx(const SesGrid& G, int i, int j, int k) {
     return (size_t)i + (size_t)G.nx * ((size_t)j + (size_t)G.ny * k);
 }
 
-// One workgroup per atom: marks the grid points inside its solvent-accessible
-// sphere (interior = 1; points no atom marks stay 0: exterior).  Each thread
+// One wave per atom: marks the grid points inside its solvent-accessible
+// sphere (interior = 1; points no atom marks stay 0: exterior).  Each lane
 // takes (i, j) columns of the atom's box and walks them along k with
 // dx^2 + dy^2 computed once per column.
-__global__ void __launch_bounds__(kSesBlock) k_ses_mark(const float* __restrict__ pos, const float* __restrict__ rad,
-                                                        uint32_t n, SesGrid G, uint8_t* __restrict__ mark) {
+__global__ void __launch_bounds__(kSesMarkBlock) k_ses_mark(const float* __restrict__ pos,
+                                                            const float* __restrict__ rad, uint32_t n, SesGrid G,
+                                                            uint8_t* __restrict__ mark) {
 #pragma clang fp contract(off)
     const uint32_t a = blockIdx.x;
     if (a >= n) return;
@@ -175,14 +179,16 @@ __global__ void __launch_bounds__(kSesBlock) k_ses_mark(const float* __restrict_
     int lo[3], hi[3];
     const double c[3] = {cx, cy, cz};
     const int nmax[3] = {G.nx - 1, G.ny - 1, G.nz - 1};
+    // the box only has to hold every point the test can mark: a step of
+    // margin on each side covers the rounding of the product by 1 / h
     for (int d = 0; d < 3; ++d) {
-        lo[d] = max(0, (int)floor((c[d] - R - G.o[d]) / G.h) - 1);
-        hi[d] = min(nmax[d], (int)ceil((c[d] + R - G.o[d]) / G.h) + 1);
+        lo[d] = max(0, (int)floor((c[d] - R - G.o[d]) * G.inv_h) - 1);
+        hi[d] = min(nmax[d], (int)ceil((c[d] + R - G.o[d]) * G.inv_h) + 1);
         if (lo[d] > hi[d]) return;
     }
     const int bx = hi[0] - lo[0] + 1, ncol = bx * (hi[1] - lo[1] + 1);
     const size_t plane = (size_t)G.nx * G.ny;
-    for (int q = threadIdx.x; q < ncol; q += kSesBlock) {
+    for (int q = threadIdx.x; q < ncol; q += kSesMarkBlock) {
         const int j = lo[1] + q / bx, i = lo[0] + q % bx;
         const double dx = (G.o[0] + G.h * i) - cx, dy = (G.o[1] + G.h * j) - cy;
         const double sxy = dx * dx + dy * dy;
@@ -226,6 +232,35 @@ __global__ void __launch_bounds__(kSesBlock) k_ses_edt_x(SesGrid G, uint32_t np,
     g[p] = best;
 }
 
+// The x pass through LDS (W <= kEdtMaxW): work block b takes kSesBlock
+// consecutive points of one row (x block b mod nxb of row b / nxb) and
+// stages their marks and W more on each side.
+template <int kMaxW>
+__global__ void __launch_bounds__(kSesBlock) k_ses_edt_x_lds(SesGrid G, uint32_t nxb,
+                                                             const uint8_t* __restrict__ mark,
+                                                             int32_t* __restrict__ g) {
+    __shared__ uint8_t row[kSesBlock + 2 * kMaxW];
+    const uint32_t r = blockIdx.x / nxb, xb = blockIdx.x - r * nxb;
+    const int W = G.W, x0 = (int)xb * kSesBlock;
+    const size_t base = (size_t)r * G.nx;   // row r = j + ny k starts at r nx
+    for (int t = threadIdx.x; t < kSesBlock + 2 * W; t += kSesBlock) {
+        const int x = x0 - W + t;
+        row[t] = (x >= 0 && x < G.nx) ? mark[base + x] : (uint8_t)2;   // 2: outside the grid
+    }
+    __syncthreads();
+    const int i = x0 + (int)threadIdx.x;
+    if (i >= G.nx) return;
+    int32_t best = kFar;
+    for (int d = 0; d <= W; ++d) {
+        const uint8_t l = row[threadIdx.x + W - d], rr = row[threadIdx.x + W + d];
+        if (l == 0 || rr == 0) {
+            best = d * d;
+            break;
+        }
+    }
+    g[base + i] = best;
+}
+
 // y or z pass: the least of g(p + d e) + d^2 over |d| <= W along the axis.
 // The z pass also writes the field.
 template <bool kLast>
@@ -253,6 +288,53 @@ __global__ void __launch_bounds__(kSesBlock) k_ses_edt_yz(SesGrid G, uint32_t np
     field[p] = (float)(D - G.rp);
 }
 
+// The same passes through LDS (windows of W <= kEdtMaxW): work block b
+// takes kEdtX consecutive x of one slice (z for the y pass, y for the z pass)
+// and kEdtRows consecutive positions along the axis, stages those rows and
+// W more on each side in LDS (one load per staged value), and each thread
+// then takes the window minima of its column from LDS.
+constexpr int kEdtX = 64, kEdtRows = 32, kEdtMaxW = 32;
+
+template <bool kLast>
+__global__ void __launch_bounds__(kSesBlock) k_ses_edt_yz_lds(SesGrid G, uint32_t nxb, uint32_t nrb,
+                                                              const int32_t* __restrict__ gin,
+                                                              int32_t* __restrict__ gout, float* __restrict__ field) {
+    __shared__ int32_t tile[(kEdtRows + 2 * kEdtMaxW) * kEdtX];
+    const uint32_t b = blockIdx.x, xb = b % nxb, rest = b / nxb, rb = rest % nrb, sl = rest / nrb;
+    const int tx = threadIdx.x % kEdtX, ty = threadIdx.x / kEdtX;
+    constexpr int kLanes = kSesBlock / kEdtX;
+    const int x = (int)xb * kEdtX + tx, a0 = (int)rb * kEdtRows, W = G.W;
+    const int len = kLast ? G.nz : G.ny;
+    // element (x, axis position a) of this slice
+    auto at = [&](int a) -> size_t {
+        return kLast ? gidx(G, x, (int)sl, a) : gidx(G, x, a, (int)sl);
+    };
+    const int staged = kEdtRows + 2 * W;
+    for (int r = ty; r < staged; r += kLanes) {
+        const int a = a0 - W + r;
+        tile[r * kEdtX + tx] = (x < G.nx && a >= 0 && a < len) ? gin[at(a)] : kFar;
+    }
+    __syncthreads();
+    if (x >= G.nx) return;
+    for (int o = ty; o < kEdtRows; o += kLanes) {
+        const int a = a0 + o;
+        if (a >= len) break;
+        int32_t best = kFar;
+        for (int d = -W; d <= W; ++d) {
+            const int32_t v = tile[(o + W + d) * kEdtX + tx];
+            if (v < kFar) best = min(best, v + d * d);
+        }
+        const size_t p = at(a);
+        if (!kLast) {
+            gout[p] = best;
+        } else {
+            const double cap = G.W * G.h;
+            const double D = best > G.W * G.W ? cap : fmin(G.h * sqrt((double)best), cap);
+            field[p] = (float)(D - G.rp);
+        }
+    }
+}
+
 __device__ inline int cube_case(const SesGrid& G, const float* __restrict__ f, int i, int j, int k, float v[8]) {
     int m = 0;
 #pragma unroll
@@ -263,26 +345,46 @@ __device__ inline int cube_case(const SesGrid& G, const float* __restrict__ f, i
     return m;
 }
 
-// Triangles per cube.
+// Triangles per cube, and per workgroup of kSesBlock cubes the list of its
+// cubes that have any: active[b * kSesBlock + s] for s < n_active[b].
 __global__ void __launch_bounds__(kSesBlock) k_ses_count(SesGrid G, uint32_t nc, const float* __restrict__ f,
-                                                         uint32_t* __restrict__ cnt) {
+                                                         uint32_t* __restrict__ cnt, uint32_t* __restrict__ active,
+                                                         uint32_t* __restrict__ n_active) {
+    __shared__ uint32_t wave_n[kSesBlock / 64];
     int i, j, k;
     uint32_t q;
-    if (!flat_item(nc, G.nx - 1, G.ny - 1, i, j, k, q)) return;
-    float v[8];
-    cnt[q] = c_case_tris[cube_case(G, f, i, j, k, v)];
+    uint32_t nt = 0;
+    if (flat_item(nc, G.nx - 1, G.ny - 1, i, j, k, q)) {
+        float v[8];
+        nt = c_case_tris[cube_case(G, f, i, j, k, v)];
+        cnt[q] = nt;
+    }
+    const unsigned long long act = __ballot(nt != 0);
+    const int wave = threadIdx.x >> 6;
+    if (__lane_id() == 0) wave_n[wave] = (uint32_t)__popcll(act);
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int w = 0; w < kSesBlock / 64; ++w) {
+        before += w < wave ? wave_n[w] : 0u;
+        all += wave_n[w];
+    }
+    if (nt) active[(size_t)blockIdx.x * kSesBlock + before + (uint32_t)__popcll(act & __lanemask_lt())] = q;
+    if (threadIdx.x == 0) n_active[blockIdx.x] = all;
 }
 
-// Each cube's triangles at its offset (those past the capacity are dropped).
-__global__ void __launch_bounds__(kSesBlock) k_ses_emit(SesGrid G, uint32_t nc, const float* __restrict__ f,
-                                                        const uint32_t* __restrict__ off, float* __restrict__ tri,
-                                                        unsigned long long capacity) {
-    int i, j, k;
-    uint32_t q;
-    if (!flat_item(nc, G.nx - 1, G.ny - 1, i, j, k, q)) return;
+// The triangles of each cube its count workgroup listed, at the cube's
+// offset (those past the capacity are dropped).
+__global__ void __launch_bounds__(kSesBlock) k_ses_emit(SesGrid G, const uint32_t* __restrict__ active,
+                                                        const uint32_t* __restrict__ n_active,
+                                                        const float* __restrict__ f, const uint32_t* __restrict__ off,
+                                                        float* __restrict__ tri, unsigned long long capacity) {
+    if (threadIdx.x >= n_active[blockIdx.x]) return;
+    const uint32_t q = active[(size_t)blockIdx.x * kSesBlock + threadIdx.x];
+    const uint32_t r = q / (uint32_t)(G.nx - 1);
+    const int i = (int)(q - r * (uint32_t)(G.nx - 1)), j = (int)(r % (uint32_t)(G.ny - 1)),
+              k = (int)(r / (uint32_t)(G.ny - 1));
     float v[8];
     const int m = cube_case(G, f, i, j, k, v);
-    if (c_case_tris[m] == 0) return;
     unsigned long long t = off[q];
     const float ox = (float)G.o[0], oy = (float)G.o[1], oz = (float)G.o[2], h = (float)G.h;
     const uint8_t* cs = c_cases + m * kCaseBytes;
@@ -334,6 +436,7 @@ hipError_t ses_run(const float* pos, const float* rad, uint64_t n, float probe, 
     SesGrid G;
     for (int d = 0; d < 3; ++d) G.o[d] = (double)origin[d];
     G.h = (double)spacing;
+    G.inv_h = 1.0 / G.h;
     G.nx = dims[0];
     G.ny = dims[1];
     G.nz = dims[2];
@@ -342,22 +445,48 @@ hipError_t ses_run(const float* pos, const float* rad, uint64_t n, float probe, 
     const size_t np = (size_t)G.nx * G.ny * G.nz;
     const size_t nc = (size_t)(G.nx - 1) * (G.ny - 1) * (G.nz - 1);
     if ((e = launch_zero(reinterpret_cast<uint32_t*>(s.mark), (np + 3) / 4, stream)) != hipSuccess) return e;
-    if (n && (e = dispatch(k_ses_mark, (unsigned)n, kSesBlock, 0, stream, pos, rad, (uint32_t)n, G, s.mark)))
+    if (n && (e = dispatch(k_ses_mark, (unsigned)n, kSesMarkBlock, 0, stream, pos, rad, (uint32_t)n, G, s.mark)))
         return e;
     // rows of points along x (y-z rows), then rows of cubes
     const unsigned gp = (unsigned)((np + kSesBlock - 1) / kSesBlock);
-    if ((e = dispatch(k_ses_edt_x, gp, kSesBlock, 0, stream, G, (uint32_t)np, (const uint8_t*)s.mark, s.ga))) return e;
-    if ((e = dispatch(k_ses_edt_yz<false>, gp, kSesBlock, 0, stream, G, (uint32_t)np, (const int32_t*)s.ga, s.gb,
-                      (float*)nullptr)))
+    const uint64_t nxr = (uint64_t)(G.nx + kSesBlock - 1) / kSesBlock, gx = nxr * (uint64_t)G.ny * (uint64_t)G.nz;
+    if (G.W <= kEdtMaxW && gx * kSesBlock < (1ull << 31)) {
+        if ((e = dispatch(k_ses_edt_x_lds<kEdtMaxW>, (uint32_t)gx, kSesBlock, 0, stream, G, (uint32_t)nxr,
+                          (const uint8_t*)s.mark, s.ga)))
+            return e;
+    } else if ((e = dispatch(k_ses_edt_x, gp, kSesBlock, 0, stream, G, (uint32_t)np, (const uint8_t*)s.mark, s.ga))) {
         return e;
-    if ((e = dispatch(k_ses_edt_yz<true>, gp, kSesBlock, 0, stream, G, (uint32_t)np, (const int32_t*)s.gb, s.ga,
-                      field)))
-        return e;
+    }
+    const uint64_t nxb = (uint64_t)(G.nx + kEdtX - 1) / kEdtX;
+    const uint64_t gy = nxb * (uint64_t)((G.ny + kEdtRows - 1) / kEdtRows) * (uint64_t)G.nz;
+    const uint64_t gz = nxb * (uint64_t)((G.nz + kEdtRows - 1) / kEdtRows) * (uint64_t)G.ny;
+    if (G.W <= kEdtMaxW && gy * kSesBlock < (1ull << 31) && gz * kSesBlock < (1ull << 31)) {
+        if ((e = dispatch(k_ses_edt_yz_lds<false>, (uint32_t)gy, kSesBlock, 0, stream, G, (uint32_t)nxb,
+                          (uint32_t)((G.ny + kEdtRows - 1) / kEdtRows), (const int32_t*)s.ga, s.gb, (float*)nullptr)))
+            return e;
+        if ((e = dispatch(k_ses_edt_yz_lds<true>, (uint32_t)gz, kSesBlock, 0, stream, G, (uint32_t)nxb,
+                          (uint32_t)((G.nz + kEdtRows - 1) / kEdtRows), (const int32_t*)s.gb, s.ga, field)))
+            return e;
+    } else {
+        if ((e = dispatch(k_ses_edt_yz<false>, gp, kSesBlock, 0, stream, G, (uint32_t)np, (const int32_t*)s.ga, s.gb,
+                          (float*)nullptr)))
+            return e;
+        if ((e = dispatch(k_ses_edt_yz<true>, gp, kSesBlock, 0, stream, G, (uint32_t)np, (const int32_t*)s.gb, s.ga,
+                          field)))
+            return e;
+    }
+    // the distance buffers are free once the z pass has run: the y pass's
+    // holds the per-workgroup lists of cubes with triangles, the other one
+    // their lengths
+    uint32_t* const active = reinterpret_cast<uint32_t*>(s.gb);
+    uint32_t* const n_active = reinterpret_cast<uint32_t*>(s.ga);
     const unsigned gc = (unsigned)((nc + kSesBlock - 1) / kSesBlock);
-    if ((e = dispatch(k_ses_count, gc, kSesBlock, 0, stream, G, (uint32_t)nc, (const float*)field, s.cnt))) return e;
+    if ((e = dispatch(k_ses_count, gc, kSesBlock, 0, stream, G, (uint32_t)nc, (const float*)field, s.cnt, active,
+                      n_active)))
+        return e;
     if ((e = exclusive_scan(s.cnt, nc, s.bsum, n_tri, stream))) return e;
-    return dispatch(k_ses_emit, gc, kSesBlock, 0, stream, G, (uint32_t)nc, (const float*)field,
-                    (const uint32_t*)s.cnt, tri, (unsigned long long)capacity);
+    return dispatch(k_ses_emit, gc, kSesBlock, 0, stream, G, (const uint32_t*)active, (const uint32_t*)n_active,
+                    (const float*)field, (const uint32_t*)s.cnt, tri, (unsigned long long)capacity);
 }
 
 size_t ses_scratch_words(const int dims[3], size_t* mark_words, size_t* g_words, size_t* cnt_words, size_t* bsum_words) {
