@@ -246,15 +246,26 @@ def build_served(args, scenes):
 
 def run_served(args, vtx, scenes, torch, stream):
     """The served mix: Poisson arrivals of session frames on a pool of 24
-    resident scenes, rendered by the library's server (continuous batching);
-    latency is arrival -> device completion."""
+    resident scenes; latency is arrival -> device completion.  --serve-mode
+    server renders them through the library's server (continuous batching);
+    plain replays the same arrival trace with one vtx_render_scene per
+    request on one stream, completion taken from an event after each render
+    (device time, referred to the host clock through an event recorded at
+    the start)."""
     pool, reqs, used, built = args.served_inputs
+    plain = args.serve_mode == "plain"
     dev_scenes = {k: vtx.DeviceScene(built[k][0]) for k in used}
     budget = int(args.serve_budget_gb * (1 << 30)) if args.serve_budget_gb > 0 else 0
     ctx = vtx.vtx_context_create(0, budget)
     upload = torch.cuda.Stream()
-    server = vtx.vtx_server_create(ctx, args.serve_max_batch, 2, stream)
+    server = None if plain else vtx.vtx_server_create(ctx, args.serve_max_batch, 2, stream)
     opts = scenes.Options(ssao_samples=16, ssao_radius=2.0)
+    pending = []                        # plain: (event, ticket) in submission order
+    ref_ev = torch.cuda.Event(enable_timing=True)
+    ref_ev.record(stream)
+    stream.synchronize()
+    t_ref = vtx.vtx_clock_s()
+    hbm_peak = 0
     outs = {res: [vtx.Frame(*res) for _ in range(48)] for res in scenes.SERVE_RESOLUTIONS}
     slot_next = {res: 0 for res in outs}
     slot_busy = {}                      # (res, slot) -> ticket
@@ -265,13 +276,24 @@ def run_served(args, vtx, scenes, torch, stream):
     done = []
     created = evicted = 0
 
+    def finish(c):
+        info = ticket_info.pop(c["ticket"])
+        outstanding[info["scene"]] -= 1
+        slot_busy.pop(info["slot"], None)
+        c.update(info)
+        done.append(c)
+
     def collect(wait_ms=0):
-        for c in vtx.vtx_server_poll(server, 512, wait_ms):
-            info = ticket_info.pop(c["ticket"])
-            outstanding[info["scene"]] -= 1
-            slot_busy.pop(info["slot"], None)
-            c.update(info)
-            done.append(c)
+        if not plain:
+            for c in vtx.vtx_server_poll(server, 512, wait_ms):
+                finish(c)
+            return
+        if wait_ms and pending:
+            pending[0][0].synchronize()
+        while pending and pending[0][0].query():
+            ev, tk = pending.pop(0)
+            t = t_ref + ref_ev.elapsed_time(ev) / 1e3
+            finish({"ticket": tk, "status": 0, "done_s": t, "launch_s": ticket_info[tk]["submit"]})
 
     def ensure_resident(k):
         nonlocal created, evicted
@@ -282,6 +304,8 @@ def run_served(args, vtx, scenes, torch, stream):
                 rs = vtx.ResidentScene(ctx, dev_scenes[k], stream=upload)
                 created += 1
                 resident[k] = rs
+                nonlocal hbm_peak
+                hbm_peak = max(hbm_peak, vtx.vtx_context_bytes_in_use(ctx))
                 return rs
             except vtx.VtxError as e:
                 if e.code != vtx.VTX_EBUSY:
@@ -316,17 +340,31 @@ def run_served(args, vtx, scenes, torch, stream):
         fr = outs[res][slot[1]]
         sc, centre, radius = built[r.scene]
         cam = scenes.orbit_camera(centre, radius, r.angle)
-        job = vtx.make_job(rs.handle, 0, cam, opts, r.width, r.height, fr.rgba, fr.depth, fr.id)
-        tk = vtx.vtx_server_submit(server, job)
+        if plain:
+            tk = len(ticket_info) + len(done)
+            sub = vtx.vtx_clock_s()
+            vtx.vtx_render_scene(rs.handle, cam, opts, r.width, r.height, fr.rgba, fr.depth, fr.id, stream)
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(stream)
+            pending.append((ev, tk))
+        else:
+            sub = None
+            job = vtx.make_job(rs.handle, 0, cam, opts, r.width, r.height, fr.rgba, fr.depth, fr.id)
+            tk = vtx.vtx_server_submit(server, job)
         ticket_info[tk] = {"arrival": arrival, "scene": r.scene, "slot": slot, "t": r.t,
-                           "pixels": r.width * r.height}
+                           "pixels": r.width * r.height, "submit": sub}
         slot_busy[slot] = tk
         outstanding[r.scene] = outstanding.get(r.scene, 0) + 1
         last_use[r.scene] = arrival
-    vtx.vtx_server_drain(server)
-    collect()
-    sst = vtx.vtx_server_stats_read(server)
-    vtx.vtx_server_destroy(server)
+    if plain:
+        stream.synchronize()
+        collect()
+        sst = {"completed": len(done), "batches": len(done)}
+    else:
+        vtx.vtx_server_drain(server)
+        collect()
+        sst = vtx.vtx_server_stats_read(server)
+        vtx.vtx_server_destroy(server)
     for rs in resident.values():
         rs.close()
     vtx.vtx_context_destroy(ctx)
@@ -352,13 +390,16 @@ def run_served(args, vtx, scenes, torch, stream):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"served_mix_{len(pool)}scenes_{args.serve_rate:.0f}hz_{args.serve_seconds:.0f}s",
+        "config": {"workload": f"served_mix_{len(pool)}scenes_{args.serve_rate:.0f}hz_{args.serve_seconds:.0f}s"
+                               + ("_plain" if plain else ""),
                    "scenes": len(used), "atoms_min": min(built[k][0].n_atoms for k in used),
                    "atoms_max": max(built[k][0].n_atoms for k in used),
                    "resolutions": [list(x) for x in scenes.SERVE_RESOLUTIONS], "ssao_samples": 16,
                    "arrival_rate_hz": args.serve_rate, "mean_session_frames": 8,
-                   "hbm_budget_bytes": budget or "full", "max_batch": args.serve_max_batch,
-                   "launch": "vtx_server: continuous batching into vtx_render_batch, 2 batches in flight"},
+                   "hbm_budget_bytes": budget or "full", "hbm_scenes_peak_bytes": hbm_peak,
+                   "max_batch": args.serve_max_batch,
+                   "launch": ("one vtx_render_scene per request, one stream" if plain else
+                              "vtx_server: continuous batching into vtx_render_batch, 2 batches in flight")},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
                        "mean": round(float(lat.mean()), 3), "queue_p50": round(float(np.percentile(q, 50)), 3),
                        "frames": int(lat.size), "measured_from": "arrival", "to": "device completion (host callback)"},
@@ -727,6 +768,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=0.0,
                     help="served mix: HBM budget of resident scenes (0 = the full memory)")
     ap.add_argument("--serve-max-batch", type=int, default=64)
+    ap.add_argument("--serve-mode", choices=["server", "plain"], default="server",
+                    help="served mix: the library's server, or one vtx_render_scene per request")
     ap.add_argument("--tile", type=int, default=0, help="tile size (0 = library default)")
     ap.add_argument("--path", choices=["scene", "plain"], default="scene",
                     help="single-frame workloads: scene = resident scene (vtx_scene_create before timing, "
