@@ -562,6 +562,8 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
     F->outline_t = o.outline_depth;
     F->outline_rgba = o.outline_color | 0xFF000000u;
     F->clip_on = clip_on ? 1 : 0;
+    // ids are below n + m: the top bit is free for the resolve's refine mark
+    F->refine_flag = n + m < (int64_t)0x7FFFFFFF ? 1 : 0;
     if (clip_on) {
         // a.x + d with x = eye + X s + Y u + Z f: (a.s, a.u, a.f, a.eye + d)
         const double a[3] = {o.clip_plane[0], o.clip_plane[1], o.clip_plane[2]};
@@ -1123,6 +1125,9 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
                                                 count, ws->d_ovf, ws->d_ovf_n, stream));
             }
         }
+        // batches: FP64 depths of the winners the resolve marked (a single
+        // render's resolve writes them itself)
+        if (n > 1) VTX_HIP(vtx::launch_refine(list_of(0, n, 2 * (n + 1)), g_shade, stream));
         for (size_t i = 0; i < n; ++i) {
             ws->slots[i]->dirty = false;
             ws->slots[i]->pending_capacity = ws->slots[i]->bb.capacity;

@@ -89,14 +89,19 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v) {
 __device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-__device__ inline float hit_sphere(const float4 s, float ox, float oy, float Dx, float Dy) {
+// graze: the hit's n.V (the half chord sqrt(disc) over r) is below
+// kGrazeCos, or the sphere is large against its depth (r > z / 4): where the
+// FP32 root may miss the depth tolerance (see kGrazeCos).
+__device__ inline float hit_sphere(const float4 s, float ox, float oy, float Dx, float Dy, bool& graze) {
     const float cx = s.x - ox, cy = s.y - oy, cz = s.z;
     const float inv_dd = fast_rcp(fmaf(Dx, Dx, fmaf(Dy, Dy, 1.0f)));
     const float b = fmaf(cx, Dx, fmaf(cy, Dy, cz)) * inv_dd;
     const float qx = fmaf(-b, Dx, cx), qy = fmaf(-b, Dy, cy), qz = cz - b;
     const float disc = fmaf(s.w, s.w, -fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
     if (disc < 0.0f) return INFINITY;
-    return b - fast_sqrt(disc * inv_dd);
+    const float t = b - fast_sqrt(disc * inv_dd);
+    graze = disc < kGrazeCos * kGrazeCos * (s.w * s.w) || 4.0f * s.w > t;
+    return t;
 }
 
 // Closed cylinder of radius rho from A along unit axis a for length L: the
@@ -256,7 +261,10 @@ __device__ inline bool source_record(const Job& J, uint32_t src, PrimRec& pr) {
 // records and their prefix.  Two-pass frames: the front pass also stores the
 // farthest depth of each 16x16 cell of the tile; the rest pass starts from the
 // front pass's depth and id.
-template <int TS, bool kCount, bool kTail, bool kTwo>
+// kInline: the write-out recomputes the marked winners' depths in FP64 itself
+// (single renders); otherwise it leaves them to the refine pass (batches,
+// whose instantiations have no registers to spare for it).
+template <int TS, bool kCount, bool kTail, bool kTwo, bool kInline>
 __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o, int phase_arg) {
     const int phase = kTwo ? phase_arg : (int)kPhaseAll;   // one-pass instantiations drop the two-pass code
     __shared__ unsigned long long keys[TS * TS];
@@ -343,7 +351,10 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
             } else {
                 ox = ndx * F.hxf; oy = ndy * F.hyf; Dx = 0.f; Dy = 0.f;
             }
-            const float z = rc.kind == 0 ? hit_sphere(rc.a, ox, oy, Dx, Dy) : hit_cylinder(rc.a, rc.b, ox, oy, Dx, Dy);
+            // cylinder hits are always refined; sphere hits only when grazing
+            bool graze = true;
+            const float z = rc.kind == 0 ? hit_sphere(rc.a, ox, oy, Dx, Dy, graze)
+                                         : hit_cylinder(rc.a, rc.b, ox, oy, Dx, Dy);
             bool hit = z >= F.znear && z <= F.zfar;
             // clip plane: the hit point (ox + z Dx, oy + z Dy, z) on the cut side draws nothing
             if (F.clip_on && hit)
@@ -354,7 +365,9 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
                 n_hit += hit ? 1 : 0;
                 n_hit_bond += (hit && rc.kind == 1) ? 1 : 0;
             }
-            if (hit) atomicMin(&keys[slot], ((unsigned long long)__float_as_uint(z) << 32) | rc.id);
+            if (hit)
+                atomicMin(&keys[slot], ((unsigned long long)__float_as_uint(z) << 32) |
+                                           (rc.id | (graze && F.refine_flag ? kRefineBit : 0u)));
         };
         // entry k of the visible lists (tiles whose list overflowed): the
         // record is rebuilt from its source
@@ -744,11 +757,12 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
             }
         }
 
-        // The G-buffer: the winner of each pixel with its depth recomputed in
-        // FP64.  The front pass of a two-pass frame stores its FP32 keys
-        // instead: the rest pass continues from them as a one-pass frame
-        // would, and refines every pixel at its end.
-        const bool refine = phase != kPhaseFront;
+        // The G-buffer: the winner of each pixel.  Inline, the last pass
+        // writes the marked winners' depths recomputed in FP64 and plain ids;
+        // otherwise (and in the front pass of a two-pass frame, which the
+        // rest pass continues from) the FP32 depth and the id with its refine
+        // mark, for the refine pass.
+        const bool finish = kInline && phase != kPhaseFront;
 #pragma unroll 1
         for (int i = tid; i < TS * TS; i += kBlock) {
             const int ly = i / TS, lx = i - ly * TS;
@@ -760,7 +774,11 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
                 if (kk != ~0ull) {
                     io = (uint32_t)(kk & 0xFFFFFFFFull);
                     zo = __uint_as_float((uint32_t)(kk >> 32));
-                    if (refine) zo = refine_depth(J, io, px0 + lx, py0 + ly, zo);
+                    if (finish) {
+                        const bool marked = !F.refine_flag || (io & kRefineBit);
+                        io &= F.refine_flag ? ~kRefineBit : ~0u;
+                        if (marked) zo = refine_depth(J, io, px0 + lx, py0 + ly, zo);
+                    }
                 }
                 depth[p] = zo;
                 out_id[p] = io;
@@ -814,7 +832,7 @@ __global__ void __launch_bounds__(kBlock, kCount ? 1 : 7) k_resolve(JS js, unsig
         if (threadIdx.x == 0) ovf[atomicAdd(ovf_n, 1u)] = ((unsigned long long)ji << 32) | tu;
         return;
     }
-    resolve_tile<TS, kCount, false, kTwo>(J, (int)tu, n, o, phase);
+    resolve_tile<TS, kCount, false, kTwo, !JS::kMany>(J, (int)tu, n, o, phase);
 }
 
 // Tail launch (a fixed grid, queued right after the main one): resolves the
@@ -829,7 +847,7 @@ __global__ void __launch_bounds__(kBlock) k_resolve_tail(JS js, const unsigned l
         const unsigned long long v = ovf[e];
         const Job& J = js.job((int)(v >> 32));
         const int t = (int)(v & 0xFFFFFFFFull);
-        resolve_tile<TS, kCount, true, kTwo>(J, t, J.bb.tile_cnt[t], J.bb.tile_off[t], phase);
+        resolve_tile<TS, kCount, true, kTwo, !JS::kMany>(J, t, J.bb.tile_cnt[t], J.bb.tile_off[t], phase);
         __syncthreads();   // the next tile reuses the LDS
     }
     if (threadIdx.x == 0) {
@@ -893,6 +911,99 @@ hipError_t resolve_impl(const JS& js, int tile, int phase, uint32_t grid, unsign
         default: return hipErrorInvalidValue;
     }
 }
+
+// Depth refinement of a batch, over the shade's 16x16 blocks, kRefineBlocks
+// of them per workgroup: a pixel whose winner the resolve marked (kRefineBit
+// in the id, or every hit when the frame has too many primitives for the
+// mark) gets its depth recomputed from the primitive's FP64 data
+// (refine_depth) and its mark cleared; every other pixel keeps the resolve's
+// FP32 depth, which is within the tolerance there (see kGrazeCos).
+constexpr int kRefineBlocks = 4;   // 16x16 blocks per refine workgroup: 4 pixels per thread in flight
+
+template <class JS>
+__global__ void __launch_bounds__(kBlock) k_refine(JS js, uint32_t nblocks) {
+    __shared__ uint16_t todo[kRefineBlocks * kBlock];
+    __shared__ uint32_t wave_n[kBlock / 64];
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const uint32_t q = (uint32_t)xcd_contiguous(blockIdx.x, gridDim.x);
+    // the id of this thread's pixel in each of the workgroup's blocks, all
+    // loads issued before any is used
+    int ji[kRefineBlocks];
+    uint32_t tu[kRefineBlocks], raw[kRefineBlocks];
+#pragma unroll
+    for (int s = 0; s < kRefineBlocks; ++s) {
+        const uint32_t b = q * kRefineBlocks + s;
+        ji[s] = b < nblocks ? js.find(b, tu[s]) : -1;
+        raw[s] = kBackground;
+        if (ji[s] >= 0) {
+            const Frame& F = js.job(ji[s]).F;
+            const int tiles_x = (F.W + 15) / 16;
+            const int x = ((int)tu[s] % tiles_x) * 16 + (tid & 15), y = ((int)tu[s] / tiles_x) * 16 + (tid >> 4);
+            if (x < F.W && y < F.H) raw[s] = js.job(ji[s]).id[(size_t)y * F.W + x];
+        }
+    }
+    // the marked pixels, packed into a list so that only as many waves as
+    // they fill run the FP64 recomputation
+    uint32_t mine = 0, n_mine = 0;
+#pragma unroll
+    for (int s = 0; s < kRefineBlocks; ++s) {
+        if (ji[s] < 0 || raw[s] == kBackground) continue;
+        if (!js.job(ji[s]).F.refine_flag || (raw[s] & kRefineBit)) {
+            mine |= 1u << s;
+            ++n_mine;
+        }
+    }
+    uint32_t incl = n_mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)incl, o);
+        if ((int)__lane_id() >= o) incl += u;
+    }
+    if (__lane_id() == 63) wave_n[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        before += w < wave ? wave_n[w] : 0u;
+        total += wave_n[w];
+    }
+    uint32_t at = before + incl - n_mine;
+#pragma unroll
+    for (int s = 0; s < kRefineBlocks; ++s)
+        if (mine & (1u << s)) todo[at++] = (uint16_t)(s * kBlock + tid);
+    __syncthreads();
+    for (uint32_t e = (uint32_t)tid; e < total; e += kBlock) {
+        const int s = todo[e] / kBlock, t = todo[e] % kBlock;
+        // the entry's block, picked from the workgroup's (no second search)
+        int j = ji[0];
+        uint32_t tb = tu[0];
+#pragma unroll
+        for (int k = 1; k < kRefineBlocks; ++k)
+            if (s == k) {
+                j = ji[k];
+                tb = tu[k];
+            }
+        const Job& J = js.job(j);
+        const Frame& F = J.F;
+        const int tiles_x = (F.W + 15) / 16;
+        const int px = ((int)tb % tiles_x) * 16 + (t & 15), py = ((int)tb / tiles_x) * 16 + (t >> 4);
+        const size_t p = (size_t)py * F.W + px;
+        const uint32_t r0 = J.id[p];
+        const uint32_t id = F.refine_flag ? r0 & ~kRefineBit : r0;
+        J.depth[p] = refine_depth(J, id, px, py, J.depth[p]);
+        if (F.refine_flag) J.id[p] = id;
+    }
+}
+
+// One workgroup per kRefineBlocks of the 16x16 blocks, the grid rounded up
+// to whole XCD rounds as xcd_contiguous needs.
+template <class JS>
+hipError_t refine_impl(const JS& js, uint32_t blocks, hipStream_t stream) {
+    if (blocks == 0) return hipSuccess;
+    const int grid = xcd_grid((int)((blocks + kRefineBlocks - 1) / kRefineBlocks));
+    return dispatch(k_refine<JS>, (unsigned)grid, kBlock, 0, stream, js, blocks);
+}
+hipError_t launch_refine(const OneJob& js, uint32_t grid, hipStream_t stream) { return refine_impl(js, grid, stream); }
+hipError_t launch_refine(const JobList& js, uint32_t grid, hipStream_t stream) { return refine_impl(js, grid, stream); }
 
 hipError_t launch_resolve(const OneJob& js, int tile, int phase, uint32_t grid, bool count, unsigned long long* ovf,
                           uint32_t* ovf_n, hipStream_t stream) {

@@ -18,6 +18,18 @@ constexpr int kBinThreads = 1024;            // binning workgroups (16 waves)
 constexpr int kMaxLdsTiles = 15360;          // tile histogram of one binning workgroup (< 64 KiB of LDS)
 constexpr uint32_t kMaxBinGroups = 512;
 constexpr uint32_t kBackground = 0xFFFFFFFFu;
+// A resolve winner whose FP32 depth may miss the depth tolerance (1e-5 of the
+// depth) carries kRefineBit in its id until the refine pass has recomputed the
+// depth in FP64 and cleared it.  Frames with 2^31 - 1 primitives or more have
+// no room for the bit and refine every hit.
+constexpr uint32_t kRefineBit = 0x80000000u;
+// The FP32 sphere root is off by at most about 32 u |c| / (n.V) (u = 2^-24,
+// c the record's view-space centre, rounded once from FP64): the centre's
+// rounding moves the entry by u |c| / (n.V), the discriminant's rounding
+// (a dozen u r |c|) moves its root by that over 2 r (n.V), and the rest is a
+// few u |c|.  Hits with n.V >= kGrazeCos and r <= z / 4 (so |c| <= 1.25 z)
+// are therefore within 6e-6 of the depth; the others are refined.
+constexpr float kGrazeCos = 0.4f;
 constexpr int kMaxSamples = 64;
 // Resident scenes bin their visible clusters front to back: the frustum test
 // files each cluster under one of kDepthBuckets depth classes (log spacing
@@ -60,6 +72,7 @@ struct Frame {
     float outline_t;                   // relative depth step of an outline; 0: none
     uint32_t outline_rgba;             // packed RGBA8 of outline pixels (alpha 255)
     int32_t clip_on;                   // a clip plane is set
+    int32_t refine_flag;               // ids leave room for kRefineBit (fewer than 2^31 - 1 primitives)
     float clip[4];                     // the plane in view coordinates: kept where clip . (x, y, z, 1) >= 0
     // depth class of a front depth z (resident scenes; orders the lists, never
     // changes the image): floor(log2(z / cls_z0) * cls_k), clamped to the classes
@@ -408,6 +421,7 @@ inline uint32_t shade_blocks(const Frame& F) { return (uint32_t)(((F.W + 15) / 1
 struct OneJob {
     Job j;
     SampleKernel K;
+    static constexpr bool kMany = false;
     uint32_t blocks;         // work blocks of the launch (the grid may be padded past it)
     __device__ int find(uint32_t g, uint32_t& local) const {
         local = g;
@@ -421,6 +435,7 @@ struct OneJob {
 // A launch over several renders, described by device tables: job i owns the
 // work blocks [start[i], start[i + 1]).
 struct JobList {
+    static constexpr bool kMany = true;   // a batch launch (see resolve_tile's kInline)
     const Job* jobs;
     const SampleKernel* K;
     const uint32_t* start;   // n + 1 entries
@@ -484,6 +499,10 @@ hipError_t launch_resolve(const JobList& js, int tile, int phase, uint32_t grid,
 hipError_t launch_downsample(const float* sdepth, const uint32_t* sid, const uint32_t* srgba, int W, int H, int S,
                              float* depth, uint32_t* id, uint32_t* rgba, hipStream_t stream);
 // `noise`: some job asks for the noise form of the ambient occlusion.
+// FP64 depths of the pixels the resolve marked, over the shade's 16x16
+// blocks (resolve.hip); runs after the last resolve of a frame.
+hipError_t launch_refine(const OneJob& js, uint32_t grid, hipStream_t stream);
+hipError_t launch_refine(const JobList& js, uint32_t grid, hipStream_t stream);
 hipError_t launch_shade(const OneJob& js, uint32_t grid, bool noise, hipStream_t stream);
 hipError_t launch_shade(const JobList& js, uint32_t grid, bool noise, hipStream_t stream);
 
