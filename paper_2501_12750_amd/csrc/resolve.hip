@@ -918,7 +918,7 @@ hipError_t resolve_impl(const JS& js, int tile, int phase, uint32_t grid, unsign
 // mark) gets its depth recomputed from the primitive's FP64 data
 // (refine_depth) and its mark cleared; every other pixel keeps the resolve's
 // FP32 depth, which is within the tolerance there (see kGrazeCos).
-constexpr int kRefineBlocks = 4;   // 16x16 blocks per refine workgroup: 4 pixels per thread in flight
+constexpr int kRefineBlocks = 4;   // 16x16 blocks per refine workgroup (pixels per thread in flight)
 
 template <class JS>
 __global__ void __launch_bounds__(kBlock) k_refine(JS js, uint32_t nblocks) {
@@ -928,12 +928,17 @@ __global__ void __launch_bounds__(kBlock) k_refine(JS js, uint32_t nblocks) {
     const uint32_t q = (uint32_t)xcd_contiguous(blockIdx.x, gridDim.x);
     // the id of this thread's pixel in each of the workgroup's blocks, all
     // loads issued before any is used
+    // (one search for the first block; the others follow it)
     int ji[kRefineBlocks];
     uint32_t tu[kRefineBlocks], raw[kRefineBlocks];
+    ji[0] = q * kRefineBlocks < nblocks ? js.find(q * kRefineBlocks, tu[0]) : -1;
 #pragma unroll
     for (int s = 0; s < kRefineBlocks; ++s) {
-        const uint32_t b = q * kRefineBlocks + s;
-        ji[s] = b < nblocks ? js.find(b, tu[s]) : -1;
+        if (s > 0) {
+            ji[s] = ji[s - 1];
+            tu[s] = tu[s - 1];
+            js.next(ji[s], tu[s]);
+        }
         raw[s] = kBackground;
         if (ji[s] >= 0) {
             const Frame& F = js.job(ji[s]).F;

@@ -430,6 +430,10 @@ struct OneJob {
     __device__ const Job& job(int) const { return j; }
     __device__ const SampleKernel& samples(int) const { return K; }
     __device__ uint32_t count() const { return 1; }
+    // the work block after (i, local): the next one of the job, else -1
+    __device__ void next(int& i, uint32_t& local) const {
+        if (i >= 0 && ++local >= blocks) i = -1;
+    }
 };
 
 // A launch over several renders, described by device tables: job i owns the
@@ -461,6 +465,17 @@ struct JobList {
     __device__ const Job& job(int i) const { return jobs[i]; }
     __device__ const SampleKernel& samples(int i) const { return K[i]; }
     __device__ uint32_t count() const { return n; }
+    // the work block after (i, local): the next one of job i, else the first
+    // of the next job that has any, else -1 (no search)
+    __device__ void next(int& i, uint32_t& local) const {
+        if (i < 0) return;
+        ++local;
+        while ((uint32_t)i < n && local >= (per ? per : start[i + 1] - start[i])) {
+            ++i;
+            local = 0;
+        }
+        if ((uint32_t)i >= n) i = -1;
+    }
 };
 
 // Launch wrappers, one overload per job source.  `grid` is the number of
