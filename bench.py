@@ -51,9 +51,17 @@ OPS_PIXEL, OPS_SAMPLE, OPS_SPHERE_FRAG, OPS_CYL_FRAG, OPS_PRIM = 40, 25, 20, 50,
 ROOT = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILES = {"ball_and_stick_1000k_1920x1080": "hbm_traffic_ball_and_stick_1M_1080p.txt",
                  "whole_cell_100M_3840x2160": "hbm_traffic_whole_cell_100M_4k.txt",
-                 "trajectory_50k_64x4": "hbm_traffic_trajectory_50k_64x4.txt"}
-KERNEL_SOURCES = {"k_resolve": "resolve.hip", "k_count": "bin.hip", "k_scatter": "bin.hip",
-                  "k_shade": "shade.hip", "k_cluster_cull": "scene.hip"}
+                 "trajectory_50k_64x4": "hbm_traffic_trajectory_50k_64x4.txt",
+                 "ses_globule_50k_h0.5": "hbm_traffic_ses_globule_50k_h0.5.txt"}
+KERNEL_SOURCES = {"k_resolve": "resolve.hip", "k_refine": "resolve.hip", "k_count": "bin.hip",
+                  "k_scatter": "bin.hip", "k_shade": "shade.hip", "k_cluster_cull": "scene.hip",
+                  "k_ses_mark": "ses.hip", "k_ses_edt_x_lds": "ses.hip", "k_ses_edt_yz_lds": "ses.hip",
+                  "k_ses_count": "ses.hip", "k_ses_emit": "ses.hip", "k_scan_sums": "scan.hip",
+                  "k_scan_top": "scan.hip", "k_scan_apply": "scan.hip"}
+# the launches of one vtx_ses call on the benchmark's grid (windows of at
+# most 32 steps: the distance passes staged through LDS)
+SES_KERNELS = ["k_ses_mark", "k_ses_edt_x_lds<32>", "k_ses_edt_yz_lds<false>", "k_ses_edt_yz_lds<true>",
+               "k_ses_count", "k_scan_sums", "k_scan_top", "k_scan_apply", "k_ses_emit"]
 
 
 def log(msg):
@@ -730,6 +738,8 @@ def run_ses(args, vtx, scenes, torch, stream, cpu=True):
            "roofline": {"bound": "hbm", "achieved": round(B / (ms * 1e-3) / 1e9, 3), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(B / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "bytes": round(B),
                         "timing": "whole vtx_ses call, host clock over synchronized steps"}}
+    traffic = measured_traffic(out["config"]["workload"], SES_KERNELS)
+    out["roofline"]["traffic"] = None if traffic is None else round(traffic)
     log(f"ses: {out}")
     if cpu and not args.no_cpu_baseline:
         # the oracle on a slab of the grid (one eighth of its z extent through

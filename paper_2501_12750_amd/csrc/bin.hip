@@ -299,7 +299,9 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
         const uint32_t lane = __lane_id();
         uint32_t cn = c0 + wave < c1 ? cluster_at(c0 + wave) : 0u;
         for (uint32_t ci = c0 + wave; ci < c1; ci += nw) {
-            const uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int)cn);
+            const uint32_t ce = (uint32_t)__builtin_amdgcn_readfirstlane((int)cn);
+            const uint32_t c = ce & ~kClusterInside;
+            const bool inside = (ce & kClusterInside) != 0u;   // its atoms need no frustum test
             if (ci + nw < c1) cn = cluster_at(ci + nw);   // the next cluster's id, ahead of its use
             if constexpr (kRest) {
                 if (cluster_hidden(F, S, J.bb, c)) continue;
@@ -314,7 +316,7 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
                     double vx, vy, vz;
                     to_view(F, a.x, a.y, a.z, vx, vy, vz);
                     const double r = (double)atom_radius(F, a.w);
-                    const bool vis = i < S.n_atoms && r > 0.0 && sphere_in_frustum(F, vx, vy, vz, r) &&
+                    const bool vis = i < S.n_atoms && r > 0.0 && (inside || sphere_in_frustum(F, vx, vy, vz, r)) &&
                                      sphere_rect_fast(F, vx, vy, vz, r, x0, y0, x1, y1);
                     if (vis) note_z(vz - r, fabs(vz) + r);
                     emit(vis, i, x0, y0, x1, y1);

@@ -170,7 +170,8 @@ __global__ void __launch_bounds__(kBlock) k_cluster_boxes(SceneDev S, float4* bo
 }
 
 // Per frame: clusters whose bounding sphere meets the view volume, appended
-// to the region of S.vis_clusters of their depth class: the front depth of
+// (with kClusterInside when the sphere lies wholly inside it) to the region
+// of S.vis_clusters of their depth class: the front depth of
 // the bounding sphere on a log scale (Frame::cls_z0, cls_k), kDepthBuckets
 // classes.  A workgroup's clusters of one class (neighbours in Morton order)
 // take one contiguous run of that class, so a range of the class stays
@@ -193,6 +194,7 @@ __global__ void __launch_bounds__(kBlock) k_cluster_cull(JS js) {
         ctr->layer_zlo[threadIdx.x / kLayers][threadIdx.x % kLayers] = 0x7F800000u;
     __syncthreads();
     int cls = -1;
+    bool inside = false;
     if (c < nc) {
         const float4 lo = S.cluster_box[2 * (size_t)c], hi = S.cluster_box[2 * (size_t)c + 1];
         if (lo.x <= hi.x) {   // empty clusters have an inverted box
@@ -212,6 +214,7 @@ __global__ void __launch_bounds__(kBlock) k_cluster_cull(JS js) {
                 const float zf = fmaxf((float)(vz - r), F.cls_z0);
                 const float q = __log2f(zf / F.cls_z0) * F.cls_k;
                 cls = q >= 0.0f ? (int)fminf(q, (float)(kDepthBuckets - 1)) : 0;   // NaN: class 0
+                inside = sphere_inside_frustum(F, vx, vy, vz, r);
             }
         }
     }
@@ -233,7 +236,7 @@ __global__ void __launch_bounds__(kBlock) k_cluster_cull(JS js) {
     if (threadIdx.x < kDepthBuckets && wcnt[threadIdx.x])
         wbase[threadIdx.x] = atomicAdd(&ctr->vis_bucket[threadIdx.x], wcnt[threadIdx.x]);
     __syncthreads();
-    if (cls >= 0) S.vis_clusters[(size_t)cls * stride + wbase[cls] + off] = c;
+    if (cls >= 0) S.vis_clusters[(size_t)cls * stride + wbase[cls] + off] = c | (inside ? kClusterInside : 0u);
 }
 
 inline unsigned grid_for(uint64_t n) {

@@ -271,6 +271,22 @@ __device__ inline bool sphere_in_frustum(const Frame& F, double vx, double vy, d
     return !(fabsf(x) > F.hxf + rr || fabsf(y) > F.hyf + rr);
 }
 
+// A bounding sphere wholly inside the view volume, by a margin of 1e-3 of
+// its coordinates' magnitudes (FP64): every primitive inside it passes
+// sphere_in_frustum, so the count kernel skips that test for its atoms.
+__device__ inline bool sphere_inside_frustum(const Frame& F, double vx, double vy, double vz, double r) {
+    const double m = 1e-3 * (fabs(vx) + fabs(vy) + fabs(vz) + r) + 1e-3;
+    if (!(vz - r >= (double)F.znear + m) || !(vz + r <= (double)F.zfar - m)) return false;
+    if (F.proj == 0) {
+        const double rx = r * sqrt(1.0 + F.tx * F.tx) + m, ry = r * sqrt(1.0 + F.ty * F.ty) + m;
+        return fabs(vx) + rx <= F.tx * vz && fabs(vy) + ry <= F.ty * vz;
+    }
+    return fabs(vx) + r + m <= F.hx && fabs(vy) + r + m <= F.hy;
+}
+// Flag of a visible-cluster entry whose sphere is wholly inside the view
+// volume (cluster indices stay below 2^31).
+constexpr uint32_t kClusterInside = 0x80000000u;
+
 // Hardware dispatch places workgroup b on XCD (b mod 8).  Give each XCD one
 // contiguous range of work items so neighbouring tiles share an L2.
 __device__ inline int xcd_contiguous(int b, int nblocks) {
