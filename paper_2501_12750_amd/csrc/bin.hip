@@ -163,8 +163,9 @@ __device__ inline bool cluster_hidden(const Frame& F, const SceneDev& S, const B
 
 // Count.  Work block b of a job is that job's binning workgroup b.
 // kRest: the rest pass of a two-pass frame (a separate instantiation keeps
-// the cluster test out of the others' registers).
-template <class JS, bool kScene, bool kRest>
+// the cluster test out of the others' registers).  kAtoms: a scene without
+// bonds (no bond path in the loop: fewer live registers).
+template <class JS, bool kScene, bool kRest, bool kAtoms = false>
 __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
     extern __shared__ uint32_t hist[];
     __shared__ uint32_t local_n, bx0, by0, bx1, by1;
@@ -306,7 +307,7 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
             if constexpr (kRest) {
                 if (cluster_hidden(F, S, J.bb, c)) continue;
             }
-            if (c < S.atom_clusters) {
+            if (kAtoms || c < S.atom_clusters) {
                 // one quarter at a time: holding more quarters' atoms spills
                 // registers, which costs more than the load latency it hides
                 for (int q = 0; q < 4; ++q) {
@@ -318,10 +319,17 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
                     const double r = (double)atom_radius(F, a.w);
                     const bool vis = i < S.n_atoms && r > 0.0 && (inside || sphere_in_frustum(F, vx, vy, vz, r)) &&
                                      sphere_rect_fast(F, vx, vy, vz, r, x0, y0, x1, y1);
-                    if (vis) note_z(vz - r, fabs(vz) + r);
+                    if (vis) {
+                        // in FP32: the resolve takes (z - r)(1 - 1e-5) from
+                        // these same rounded z and r; 3e-5 of the magnitudes
+                        // covers that and the few roundings here
+                        const float zf = (float)vz, rf = (float)r;
+                        const float lb = (zf - rf) - 3e-5f * (fabsf(zf) + rf) - 2e-6f;
+                        my_zlo = min(my_zlo, lb > 0.0f ? __float_as_uint(lb) : 0u);
+                    }
                     emit(vis, i, x0, y0, x1, y1);
                 }
-            } else {
+            } else if constexpr (!kAtoms) {
                 for (int q = 0; q < 4; ++q) {
                     const uint32_t j = (c - S.atom_clusters) * kCluster + (uint32_t)q * 64u + lane;
                     emit_item(j < S.n_bonds ? fetch_scene(S, S.n_atoms + j) : empty_item());
@@ -695,6 +703,10 @@ hipError_t launch_zero(uint32_t* p, size_t n, hipStream_t stream) {
     return hipGetLastError();
 }
 
+// A single render of a scene without bonds takes the atom-only count.
+inline bool atoms_only(const OneJob& js) { return js.j.S.bond_clusters == 0; }
+inline bool atoms_only(const JobList&) { return false; }
+
 template <class JS>
 hipError_t count_impl(const JS& js, bool scene, int phase, uint32_t grid, int max_tiles, hipStream_t stream) {
     if (max_tiles > kMaxLdsTiles) return hipErrorInvalidValue;
@@ -702,6 +714,7 @@ hipError_t count_impl(const JS& js, bool scene, int phase, uint32_t grid, int ma
     if (grid == 0) return hipSuccess;
     const size_t lds = (size_t)max_tiles * sizeof(uint32_t);
     if (scene && phase == kPhaseRest) return dispatch(k_count<JS, true, true>, grid, kBinThreads, lds, stream, js, phase);
+    if (scene && atoms_only(js)) return dispatch(k_count<JS, true, false, true>, grid, kBinThreads, lds, stream, js, phase);
     if (scene) return dispatch(k_count<JS, true, false>, grid, kBinThreads, lds, stream, js, phase);
     return dispatch(k_count<JS, false, false>, grid, kBinThreads, lds, stream, js, phase);
 }
