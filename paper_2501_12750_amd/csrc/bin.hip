@@ -96,19 +96,26 @@ struct SourceOf<true> {
     }
 };
 
-// Adds one to the LDS counter of each lane's tile t (t < 0: nothing).  Lanes
-// of a wave that share a tile are merged into one atomic (Morton-ordered
-// primitives often do), for at most four distinct tiles; the rest add alone.
+// Runs of consecutive lanes whose primitives lie in the same single tile t
+// (t < 0: none); Morton-ordered primitives keep them long.  For such a lane
+// `head` is its run's first lane, and for a head `len` is the run's length
+// (other lanes: head = the lane itself).  Branch-free: one DPP shift, one
+// ballot and a few mask operations.  Every lane of the wave calls it.
+__device__ inline void lane_run(int t, int& head, uint32_t& len) {
+    const int lane = __lane_id();
+    const int tp = __builtin_amdgcn_update_dpp(-1, t, 0x138, 0xf, 0xf, false);   // wave_shr:1: lane - 1's t
+    const unsigned long long cm = __ballot(t >= 0 && lane > 0 && t == tp);     // lanes continuing a run
+    head = 63 - __clzll((long long)(~cm & ((2ull << lane) - 1ull)));            // nearest non-continuing lane <= lane
+    len = (uint32_t)__builtin_ctzll(~((cm >> lane) >> 1)) + 1u;                  // continuing lanes after it, + 1
+}
+
+// Adds one to the LDS counter of each lane's tile t (t < 0: nothing): one
+// atomic per run of lanes with the same tile.
 __device__ inline void wave_count(uint32_t* hist, int t) {
-    unsigned long long pend = __ballot(t >= 0);
-    for (int it = 0; it < 4 && pend; ++it) {
-        const int leader = __ffsll((long long)pend) - 1;
-        const int tl = __shfl(t, leader);
-        const unsigned long long grp = __ballot(t == tl) & pend;
-        if ((int)__lane_id() == leader) atomicAdd(&hist[tl], (uint32_t)__popcll(grp));
-        pend &= ~grp;
-    }
-    if ((pend >> __lane_id()) & 1ull) atomicAdd(&hist[t], 1u);
+    int head;
+    uint32_t len;
+    lane_run(t, head, len);
+    if (t >= 0 && head == (int)__lane_id()) atomicAdd(&hist[t], len);
 }
 
 // Inclusive sum over the 64 lanes of a wave by DPP row shifts and row
@@ -498,14 +505,12 @@ __global__ void __launch_bounds__(kBinThreads) k_tile_offsets(JS js) {
 // Scatter.  Every workgroup reserves, for each tile its primitives touch,
 // one run of that tile's list (one global atomic), then places its visible
 // primitives kScatterPer per thread at a time, all their loads issued
-// before any is used.  Lanes of a wave whose primitive lies in one tile are
-// grouped by tile (up to kScatterGroups groups, the rest alone); every group
-// leader and every ungrouped lane takes its slots with one LDS atomic of the
-// same instruction, and group members follow their leader.  Primitives
-// spanning several tiles take one LDS atomic per tile.  Workgroup 0 also
-// publishes the frame counters.
+// before any is used.  Lanes of a wave whose primitive lies in one tile take
+// their slots by runs of consecutive lanes with the same tile (one LDS
+// atomic per run, in one instruction for the wave).  Primitives spanning
+// several tiles take one LDS atomic per tile.  Workgroup 0 also publishes
+// the frame counters.
 constexpr int kScatterPer = 4;
-constexpr int kScatterGroups = 4;
 
 template <class JS>
 __global__ void __launch_bounds__(kBinThreads, 8) k_scatter(JS js, int phase) {
@@ -624,7 +629,6 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_scatter(JS js, int phase) {
                ((uint32_t)(ly1 - ly0 + 1) << 24);
     };
     const int lane = __lane_id();
-    const unsigned long long lt = __lanemask_lt();
     constexpr uint32_t kSpan = (uint32_t)kBinThreads * kScatterPer;
     for (uint32_t base = 0; base < n; base += kSpan) {   // uniform trip count (wave ops inside)
         uint32_t src[kScatterPer];
@@ -643,33 +647,13 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_scatter(JS js, int phase) {
             const int tx0 = x0 >> tsh, tx1 = x1 >> tsh, ty0 = y0 >> tsh, ty1 = y1 >> tsh;
             const bool single = have && tx0 == tx1 && ty0 == ty1;
             const int t1 = single ? ty0 * F.tiles_x + tx0 : -1;
-            unsigned long long pend = __ballot(single);
-            uint32_t add = 0;
-            int my_group = -1;
-            int leaders[kScatterGroups];
-            unsigned long long groups[kScatterGroups];
-            int ng = 0;
-#pragma unroll
-            for (int g = 0; g < kScatterGroups; ++g) {
-                if (!pend) break;
-                const int leader = __ffsll((long long)pend) - 1;
-                const int tl = __builtin_amdgcn_readlane(t1, leader);
-                const unsigned long long grp = __ballot(t1 == tl) & pend;
-                leaders[g] = leader;
-                groups[g] = grp;
-                ng = g + 1;
-                if ((grp >> lane) & 1ull) my_group = g;
-                if (lane == leader) add = (uint32_t)__popcll(grp);
-                pend &= ~grp;
-            }
-            if ((pend >> lane) & 1ull) add = 1u;
-            uint32_t slot = add ? atomicAdd(&cur[t1], add) : 0u;
-#pragma unroll
-            for (int g = 0; g < kScatterGroups; ++g) {
-                if (g >= ng) break;
-                const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)slot, leaders[g]);
-                if (my_group == g) slot = b + (uint32_t)__popcll(groups[g] & lt);
-            }
+            // one LDS atomic per run of lanes with the same tile; the run's
+            // lanes take consecutive slots after its head's
+            int head;
+            uint32_t len;
+            lane_run(t1, head, len);
+            const uint32_t first = single && head == lane ? atomicAdd(&cur[t1], len) : 0u;
+            const uint32_t slot = (uint32_t)__shfl((int)first, head) + (uint32_t)(lane - head);
             if (single) {
                 if (!(slot & kNoRun)) list[slot] = make_uint2(src[p], local_fp(x0, y0, x1, y1, tx0, ty0));
             } else if (have) {
