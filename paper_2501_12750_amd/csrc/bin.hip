@@ -640,25 +640,39 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_scatter(JS js, int phase) {
             src[p] = my_src[k];
             rc[p] = my_rect[k];
         }
+        // the single-tile primitives of all kScatterPer batches take their
+        // slots first (their atomics and slot exchanges overlap), then write
+        // their entries; the primitives spanning several tiles follow
+        uint32_t slot[kScatterPer];
+        bool single[kScatterPer];
 #pragma unroll
         for (int p = 0; p < kScatterPer; ++p) {
             const bool have = base + (uint32_t)(p * kBinThreads + tid) < n;
             const int x0 = rc[p].x & 0xFFFF, y0 = rc[p].x >> 16, x1 = rc[p].y & 0xFFFF, y1 = rc[p].y >> 16;
-            const int tx0 = x0 >> tsh, tx1 = x1 >> tsh, ty0 = y0 >> tsh, ty1 = y1 >> tsh;
-            const bool single = have && tx0 == tx1 && ty0 == ty1;
-            const int t1 = single ? ty0 * F.tiles_x + tx0 : -1;
+            single[p] = have && (x0 >> tsh) == (x1 >> tsh) && (y0 >> tsh) == (y1 >> tsh);
+            const int t1 = single[p] ? (y0 >> tsh) * F.tiles_x + (x0 >> tsh) : -1;
             // one LDS atomic per run of lanes with the same tile; the run's
             // lanes take consecutive slots after its head's
             int head;
             uint32_t len;
             lane_run(t1, head, len);
-            const uint32_t first = single && head == lane ? atomicAdd(&cur[t1], len) : 0u;
-            const uint32_t slot = (uint32_t)__shfl((int)first, head) + (uint32_t)(lane - head);
-            if (single) {
-                if (!(slot & kNoRun)) list[slot] = make_uint2(src[p], local_fp(x0, y0, x1, y1, tx0, ty0));
-            } else if (have) {
-                for (int ty = ty0; ty <= ty1; ++ty)
-                    for (int tx = tx0; tx <= tx1; ++tx) {
+            const uint32_t first = single[p] && head == lane ? atomicAdd(&cur[t1], len) : 0u;
+            slot[p] = (uint32_t)__shfl((int)first, head) + (uint32_t)(lane - head);
+        }
+#pragma unroll
+        for (int p = 0; p < kScatterPer; ++p) {
+            if (single[p] && !(slot[p] & kNoRun)) {
+                const int x0 = rc[p].x & 0xFFFF, y0 = rc[p].x >> 16, x1 = rc[p].y & 0xFFFF, y1 = rc[p].y >> 16;
+                list[slot[p]] = make_uint2(src[p], local_fp(x0, y0, x1, y1, x0 >> tsh, y0 >> tsh));
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < kScatterPer; ++p) {
+            const bool have = base + (uint32_t)(p * kBinThreads + tid) < n;
+            if (have && !single[p]) {
+                const int x0 = rc[p].x & 0xFFFF, y0 = rc[p].x >> 16, x1 = rc[p].y & 0xFFFF, y1 = rc[p].y >> 16;
+                for (int ty = y0 >> tsh; ty <= (y1 >> tsh); ++ty)
+                    for (int tx = x0 >> tsh; tx <= (x1 >> tsh); ++tx) {
                         const uint32_t sl = atomicAdd(&cur[ty * F.tiles_x + tx], 1u);
                         if (!(sl & kNoRun)) list[sl] = make_uint2(src[p], local_fp(x0, y0, x1, y1, tx, ty));
                     }
