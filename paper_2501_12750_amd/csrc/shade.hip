@@ -18,7 +18,7 @@ namespace vtx {
 namespace {
 
 constexpr int kTile = 16;
-constexpr int kBatch = 8;   // SSAO samples whose depth loads are issued together
+constexpr int kBatch = 16;  // SSAO samples whose depth loads are issued together
 
 constexpr float kKa = 0.2f, kKd = 0.8f, kKs = 0.25f;
 
@@ -168,7 +168,9 @@ __device__ inline float ssao_at(const Frame& F, const SampleKernel& K, const flo
             // & rather than &&: all tests evaluated, no branches per sample
             const bool ok = (k < K.count) & (Sz > F.znear) & (spx >= 0.0f) & (spx < (float)F.W) & (spy >= 0.0f) &
                             (spy < (float)F.H);
-            const uint32_t off = ok ? (uint32_t)((int)spy * F.W + (int)spx) << 2 : own;
+            // a 24-bit multiply (full rate): the pixel indices are below 2^16
+            // where ok, and the offset is discarded elsewhere
+            const uint32_t off = ok ? (__umul24((uint32_t)(int)spy, (uint32_t)F.W) + (uint32_t)(int)spx) << 2 : own;
             zq[u] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(depth) + off);
             sz[u] = ok ? Sz : -INFINITY;
         }
