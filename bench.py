@@ -53,7 +53,8 @@ TRAFFIC_FILES = {"ball_and_stick_1000k_1920x1080": "hbm_traffic_ball_and_stick_1
                  "whole_cell_100M_3840x2160": "hbm_traffic_whole_cell_100M_4k.txt",
                  "trajectory_50k_64x4": "hbm_traffic_trajectory_50k_64x4.txt",
                  "ses_globule_50k_h0.5": "hbm_traffic_ses_globule_50k_h0.5.txt"}
-KERNEL_SOURCES = {"k_resolve": "resolve.hip", "k_refine": "resolve.hip", "k_count": "bin.hip",
+KERNEL_SOURCES = {"k_resolve": "resolve.hip", "k_resolve_tail": "resolve.hip", "k_refine": "resolve.hip",
+                  "k_count": "bin.hip", "k_layers": "bin.hip", "k_tile_offsets": "bin.hip",
                   "k_scatter": "bin.hip", "k_shade": "shade.hip", "k_cluster_cull": "scene.hip",
                   "k_ses_mark": "ses.hip", "k_ses_edt_x_lds": "ses.hip", "k_ses_edt_yz_lds": "ses.hip",
                   "k_ses_count": "ses.hip", "k_ses_emit": "ses.hip", "k_scan_sums": "scan.hip",
@@ -654,8 +655,19 @@ def run_workload(args, workload, vtx, scenes, torch, stream, steps_arg, warmup_a
     roof = {k: v for k, v in kern[dom].items() if k in ("bound", "achieved", "peak", "unit", "frac")}
     scene_path = batch or runner.path == "scene"
     res_tiles = sorted({eff_tile(r) for r in runner.renders})
-    launched = {"project": (["k_cluster_cull", "k_count<SceneSource>"] if scene_path else ["k_count<PlainSource>"]),
-                "scatter": ["k_scatter"], "resolve": [f"k_resolve<{t}>" for t in res_tiles], "shade": ["k_shade"],
+    # the launches of each stage, named as the kernel trace names them (template
+    # arguments: launch form; count: scene, rest pass, atoms only; resolve:
+    # tile, counting, two-pass; shade: noise)
+    form = "JobList" if batch else "OneJob"
+    atoms_only = "true" if (M == 0 and not batch) else "false"
+    noise = "true" if getattr(runner.renders[0].options, "ssao_noise", 0) else "false"
+    launched = {"project": ([f"k_cluster_cull<{form}>", f"k_count<{form},true,false,{atoms_only}>"] if scene_path
+                            else [f"k_count<{form},false,false,false>"]),
+                "scatter": [f"k_scatter<{form}>"],
+                "resolve": ([k for t in res_tiles for k in (f"k_resolve<{t},{form},false,false>",
+                                                             f"k_resolve_tail<{t},{form},false,false>")] +
+                            (["k_refine<JobList>"] if batch else [])),
+                "shade": [f"k_shade<{form},{noise}>"],
                 "scan": []}
     traffic = measured_traffic(name, launched[dom]) if (launched[dom] and scene_path) else None
     roof = {"kernel": dom, "launches": launched[dom], **roof, "traffic": None if traffic is None else round(traffic),
