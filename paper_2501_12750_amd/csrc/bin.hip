@@ -15,13 +15,13 @@
 //            of the workgroups), one atomic per touched tile;
 //   layers   resident scenes: the per-layer totals become the start of each
 //            layer's run in every tile list, and the tile totals;
-//   scatter  each workgroup rebuilds the exclusive prefix sum of the tile
-//            counts (list offsets), reserves, per touched tile, one run of the
-//            tile's list inside its layer's run (one atomic), then places its
-//            primitives with LDS atomics: 8 bytes per (primitive, tile), the
-//            source index and the footprint clipped to the tile.  The resolve
-//            rebuilds each record from its source, so the view-space record
-//            is never written out.
+//   offsets  one exclusive scan of the tile totals per job: the list offsets;
+//   scatter  each workgroup reserves, per touched tile, one run of the tile's
+//            list inside its layer's run (one atomic), then places its
+//            primitives with LDS atomics (one per run of lanes with the same
+//            tile): 8 bytes per (primitive, tile), the source index and the
+//            footprint clipped to the tile.  The resolve rebuilds each record
+//            from its source, so the view-space record is never written out.
 // So the global atomics scale with (workgroup, touched tile) pairs rather
 // than with (primitive, tile) pairs, and a resident scene's tile lists run
 // roughly front to back.  Lists that would not fit the bin
