@@ -41,8 +41,19 @@ def assert_identical(a, b, what):
         assert np.array_equal(a[k], b[k]), f"{what}: {k} differs at {np.count_nonzero(a[k] != b[k])} pixels"
 
 
-@pytest.mark.parametrize("name", ["plain_small", "ball_and_stick_small", "orthographic", "near", "eyeplane", "wide"])
+def _without_bonds(wl):
+    """The same workload with its bonds dropped: a scene without bonds takes
+    the count kernel's atom-only instantiation."""
+    sc = wl.scene
+    wl.scene = scenes.Scene(sc.positions, sc.radii, sc.colors, np.zeros((0, 2), np.uint32))
+    return wl
+
+
+@pytest.mark.parametrize("name", ["plain_small", "ball_and_stick_small", "orthographic", "near", "eyeplane", "wide",
+                                  "orthographic_atoms", "near_atoms", "eyeplane_atoms", "wide_atoms"])
 def test_scene_equals_plain_render(vtx, ctx, name):
+    atoms_only = name.endswith("_atoms")
+    name = name[:-len("_atoms")] if atoms_only else name
     if name == "plain_small":
         wl = scenes.plain_small()
     elif name == "ball_and_stick_small":
@@ -56,6 +67,10 @@ def test_scene_equals_plain_render(vtx, ctx, name):
                                   projection=scenes.ORTHOGRAPHIC, ortho_half_height=14.0)
     else:
         wl = _adversarial(name, 21)
+    if atoms_only:
+        wl = _without_bonds(wl)
+        assert wl.scene.n_bonds == 0
+    print(name, "atoms only" if atoms_only else "", "atoms", wl.scene.n_atoms, "bonds", wl.scene.n_bonds, flush=True)
     got, ds = scene_render(vtx, ctx, wl)
     ref = run_render(vtx, ds, wl.camera, wl.options, wl.width, wl.height)
     assert_identical(got, ref, name)
