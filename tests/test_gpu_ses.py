@@ -74,6 +74,16 @@ def test_ses_protein_like_globule(vtx):
     assert n > 10000
 
 
+def test_ses_slab_many_atoms_per_plane(vtx):
+    """A thin slab of 8k atoms on a 318 x 178 x 23 grid: thousands of atoms
+    reach every z plane, and most grid points lie in several atoms' spheres."""
+    rng = np.random.default_rng(7)
+    n = 8000
+    pos = np.stack([rng.uniform(-75, 75, n), rng.uniform(-40, 40, n), rng.uniform(-1, 1, n)], 1).astype(np.float32)
+    rad = rng.uniform(1.2, 1.9, n).astype(np.float32)
+    assert check(vtx, pos, rad, 1.4, 0.5, "slab 8k") > 10000
+
+
 def test_ses_capacity_and_arguments(vtx):
     import torch
     one = np.array([[0.0, 0.0, 0.0]], dtype=np.float32)
