@@ -218,7 +218,6 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
         by1 = 0;
     }
     __syncthreads();
-    uint32_t mx0 = 0xFFFF, my0 = 0xFFFF, mx1 = 0, my1 = 0, my_pairs = 0;
     // resident scenes: the least cull depth of this lane's visible primitives
     // (float bits), a bound the resolve may stop a tile's list at.  The
     // resolve culls a record by (z - r)(1 - 1e-5) from FP32 coordinates
@@ -256,11 +255,6 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
             if (!single)
                 for (int ty = ty0; ty <= ty1; ++ty)
                     for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&hist[ty * F.tiles_x + tx], 1u);
-            mx0 = min(mx0, (uint32_t)tx0);
-            my0 = min(my0, (uint32_t)ty0);
-            mx1 = max(mx1, (uint32_t)tx1);
-            my1 = max(my1, (uint32_t)ty1);
-            my_pairs += (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
         }
     };
     // any primitive (the generic path)
@@ -357,12 +351,30 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
     }
     if (bad_count) atomicAdd(&ctr->bad_bonds, bad_count);
     if (kScene && my_zlo != 0x7F800000u) atomicMin(&wg_zlo, my_zlo);
-    if (my_pairs) {
-        atomicMin(&bx0, mx0);
-        atomicMin(&by0, my0);
-        atomicMax(&bx1, mx1);
-        atomicMax(&by1, my1);
-        atomicAdd(&local_pairs, (unsigned long long)my_pairs);
+    __syncthreads();   // the histogram is complete
+    {
+        // the workgroup's box of touched tiles and its pair count, read from
+        // the histogram once rather than tracked per primitive
+        uint32_t mx0 = 0xFFFF, my0 = 0xFFFF, mx1 = 0, my1 = 0;
+        unsigned long long my_pairs = 0;
+        for (int t = tid; t < T; t += kBinThreads) {
+            const uint32_t h = hist[t];
+            if (h) {
+                const uint32_t ty = (uint32_t)(t / F.tiles_x), tx = (uint32_t)t - ty * (uint32_t)F.tiles_x;
+                mx0 = min(mx0, tx);
+                my0 = min(my0, ty);
+                mx1 = max(mx1, tx);
+                my1 = max(my1, ty);
+                my_pairs += h;
+            }
+        }
+        if (my_pairs) {
+            atomicMin(&bx0, mx0);
+            atomicMin(&by0, my0);
+            atomicMax(&bx1, mx1);
+            atomicMax(&by1, my1);
+            atomicAdd(&local_pairs, my_pairs);
+        }
     }
     __syncthreads();
     uint32_t* row = hist_out + (size_t)blk * T;
