@@ -674,8 +674,11 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_scatter(JS js, int phase) {
 #pragma unroll
         for (int p = 0; p < kScatterPer; ++p) {
             if (single[p] && !(slot[p] & kNoRun)) {
-                const int x0 = rc[p].x & 0xFFFF, y0 = rc[p].x >> 16, x1 = rc[p].y & 0xFFFF, y1 = rc[p].y >> 16;
-                list[slot[p]] = make_uint2(src[p], local_fp(x0, y0, x1, y1, x0 >> tsh, y0 >> tsh));
+                // inside its one tile: the rectangle in tile-local pixels, unclipped
+                const uint32_t x0 = rc[p].x & 0xFFFFu, y0 = rc[p].x >> 16, x1 = rc[p].y & 0xFFFFu, y1 = rc[p].y >> 16;
+                const uint32_t m = (uint32_t)ts - 1u;
+                list[slot[p]] = make_uint2(src[p], (x0 & m) | ((y0 & m) << 8) | ((x1 - x0 + 1u) << 16) |
+                                                       ((y1 - y0 + 1u) << 24));
             }
         }
 #pragma unroll
