@@ -153,8 +153,8 @@ __device__ inline float hit_cylinder(const float4 ca, const float4 cb, float ox,
 // nearest the FP32 depth.
 __device__ inline float refine_depth(const Job& J, uint32_t id, int px, int py, float z32) {
     const Frame& F = J.F;
-    const double ndx = 2.0 * ((double)px + 0.5) / (double)F.W - 1.0;
-    const double ndy = 1.0 - 2.0 * ((double)py + 0.5) / (double)F.H;
+    const double ndx = fma((double)px + 0.5, F.inv_w2d, -1.0);
+    const double ndy = fma(-((double)py + 0.5), F.inv_h2d, 1.0);
     // ray o + t D with D.z = 1, so t is the view depth
     double ox = 0.0, oy = 0.0, Dx = 0.0, Dy = 0.0;
     if (F.proj == 0) {
@@ -164,7 +164,7 @@ __device__ inline float refine_depth(const Job& J, uint32_t id, int px, int py, 
         ox = ndx * F.hx;
         oy = ndy * F.hy;
     }
-    const double dd = fma(Dx, Dx, fma(Dy, Dy, 1.0));
+    const double dd = fma(Dx, Dx, fma(Dy, Dy, 1.0)), idd = 1.0 / dd;
     double t = (double)z32;
     if (id < F.n_atoms) {
         const size_t i = id;
@@ -173,10 +173,10 @@ __device__ inline float refine_depth(const Job& J, uint32_t id, int px, int py, 
         const double r = (double)atom_radius(F, J.rad[i]);
         cx -= ox;
         cy -= oy;
-        const double b = fma(cx, Dx, fma(cy, Dy, cz)) / dd;
+        const double b = fma(cx, Dx, fma(cy, Dy, cz)) * idd;
         const double qx = fma(-b, Dx, cx), qy = fma(-b, Dy, cy), qz = cz - b;
         const double disc = fma(r, r, -fma(qx, qx, fma(qy, qy, qz * qz)));
-        t = b - sqrt(fmax(disc, 0.0) / dd);
+        t = b - sqrt(fmax(disc, 0.0) * idd);
     } else {
         const size_t bi = id - F.n_atoms;
         const uint32_t ia = J.bonds[2 * bi], ib = J.bonds[2 * bi + 1];
