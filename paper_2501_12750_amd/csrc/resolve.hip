@@ -48,7 +48,7 @@ struct Rec {
     float zcull;       // lower bound of the depth of any hit of this record
     uint32_t id;
     uint32_t rect;     // tile-local x0 | y0 << 8 | w << 16 | h << 24
-    uint32_t kind;     // 0 sphere, 1 cylinder
+    float inv_w;       // 1 / w (hardware reciprocal): splits a footprint offset into row and column
 };
 
 __device__ inline float wave_max(float v) {
@@ -228,11 +228,11 @@ __device__ inline Rec make_rec(const Frame& F, const PrimRec& p) {
     Rec r;
     r.id = p.g1.z;
     r.rect = p.g1.w;
+    r.inv_w = __builtin_amdgcn_rcpf((float)((r.rect >> 16) & 0xFF));
     if (r.id < F.n_atoms) {
         r.a = p.g0;
         r.b = make_float4(0.f, 0.f, 0.f, 0.f);
         r.zcull = (p.g0.z - p.g0.w) * (1.0f - 1e-5f);
-        r.kind = 0;
     } else {
         const float dx = p.g0.w, dy = __uint_as_float(p.g1.x), dz = __uint_as_float(p.g1.y);
         const float L = fast_sqrt(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
@@ -241,7 +241,6 @@ __device__ inline Rec make_rec(const Frame& F, const PrimRec& p) {
         r.a = make_float4(p.g0.x, p.g0.y, p.g0.z, rho);
         r.b = make_float4(dx * inv, dy * inv, dz * inv, L);
         r.zcull = (fminf(p.g0.z, p.g0.z + dz) - rho) * (1.0f - 1e-5f) - 1e-6f;
-        r.kind = 1;
     }
     return r;
 }
@@ -353,7 +352,8 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
             }
             // cylinder hits are always refined; sphere hits only when grazing
             bool graze = true;
-            const float z = rc.kind == 0 ? hit_sphere(rc.a, ox, oy, Dx, Dy, graze)
+            const bool sphere = rc.id < F.n_atoms;   // ids past the atoms are bonds
+            const float z = sphere ? hit_sphere(rc.a, ox, oy, Dx, Dy, graze)
                                          : hit_cylinder(rc.a, rc.b, ox, oy, Dx, Dy);
             bool hit = z >= F.znear && z <= F.zfar;
             // clip plane: the hit point (ox + z Dx, oy + z Dy, z) on the cut side draws nothing
@@ -361,9 +361,9 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
                 hit = fmaf(F.clip[0], fmaf(z, Dx, ox), fmaf(F.clip[1], fmaf(z, Dy, oy), fmaf(F.clip[2], z, F.clip[3]))) >= 0.0f;
             if (counting) {
                 n_tested += 1;
-                n_tested_bond += rc.kind == 1 ? 1 : 0;
+                n_tested_bond += sphere ? 0 : 1;
                 n_hit += hit ? 1 : 0;
-                n_hit_bond += (hit && rc.kind == 1) ? 1 : 0;
+                n_hit_bond += (hit && !sphere) ? 1 : 0;
             }
             if (hit)
                 atomicMin(&keys[slot], ((unsigned long long)__float_as_uint(z) << 32) |
@@ -508,7 +508,7 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
                         const uint32_t rw = (rr.rect >> 16) & 0xFF;
                         // exact: local < 4096 and rw <= 64, so the rounding error of
                         // (local + 1/2) / rw is far below its distance to an integer
-                        const uint32_t dy = (uint32_t)(((float)local + 0.5f) * __builtin_amdgcn_rcpf((float)rw));
+                        const uint32_t dy = (uint32_t)(((float)local + 0.5f) * rr.inv_w);
                         const uint32_t dx = local - __umul24(dy, rw);
                         test_pixel(rr, (int)(rr.rect & 0xFF) + (int)dx, (int)((rr.rect >> 8) & 0xFF) + (int)dy);
                     }
@@ -599,7 +599,7 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
                     const Rec& rr = rec_at(ord[rbase + (uint32_t)lo]);
                     const uint32_t local = f - wp[lo];
                     const uint32_t rw = (rr.rect >> 16) & 0xFF;
-                    const uint32_t dy = (uint32_t)(((float)local + 0.5f) * __builtin_amdgcn_rcpf((float)rw));
+                    const uint32_t dy = (uint32_t)(((float)local + 0.5f) * rr.inv_w);
                     const uint32_t dx = local - __umul24(dy, rw);
                     test_pixel(rr, (int)(rr.rect & 0xFF) + (int)dx, (int)((rr.rect >> 8) & 0xFF) + (int)dy);
                 }
