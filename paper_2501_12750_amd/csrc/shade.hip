@@ -125,9 +125,9 @@ __device__ inline Surface surface_at(const Job& J, const Frame& F, int x, int y,
 // Ambient occlusion of a hit surface at pixel (x, y): K hemisphere samples
 // in the normal's tangent frame (kTurn: turned about the normal by the
 // cosine and sine (rc, rs)), each compared with the depth of the pixel it
-// projects to.
-template <bool kTurn>
-__device__ inline float ssao_at(const Frame& F, const SampleKernel& K, const float* __restrict__ depth, int x, int y,
+// projects to (kPersp: perspective projection, else orthographic).
+template <bool kTurn, bool kPersp>
+__device__ inline float ssao_at_proj(const Frame& F, const SampleKernel& K, const float* __restrict__ depth, int x, int y,
                                 const Surface& s, float rc, float rs) {
     const float nx = s.nx, ny = s.ny, nz = s.nz, Px = s.Px, Py = s.Py, Pz = s.Pz;
     // orthonormal basis from the normal (Duff et al., JCGT 2017, branchless
@@ -163,7 +163,7 @@ __device__ inline float ssao_at(const Frame& F, const SampleKernel& K, const flo
             const float Sz = fmaf(h.x, Tz, fmaf(h.y, Bz, fmaf(h.z, nz, Pz)));
             // hardware reciprocal (1 ulp): moves the sample by far less than
             // the 1e-3 px within which a pixel edge makes a sample unstable
-            const float sc = F.proj == 0 ? fpx * __builtin_amdgcn_rcpf(Sz) : osc;
+            const float sc = kPersp ? fpx * __builtin_amdgcn_rcpf(Sz) : osc;
             const float spx = fmaf(Sx, sc, hw), spy = fmaf(-Sy, sc, hh);
             // & rather than &&: all tests evaluated, no branches per sample
             const bool ok = (k < K.count) & (Sz > F.znear) & (spx >= 0.0f) & (spx < (float)F.W) & (spy >= 0.0f) &
@@ -179,6 +179,14 @@ __device__ inline float ssao_at(const Frame& F, const SampleKernel& K, const flo
             if (zq[u] <= sz[u] - K.bias) occ += smooth01(K.radius * __builtin_amdgcn_rcpf(fabsf(Pz - zq[u])));
     }
     return 1.0f - occ / (float)K.count;
+}
+
+// The projection is the frame's (one branch per pixel, none per sample).
+template <bool kTurn>
+__device__ inline float ssao_at(const Frame& F, const SampleKernel& K, const float* __restrict__ depth, int x, int y,
+                                const Surface& s, float rc, float rs) {
+    return F.proj == 0 ? ssao_at_proj<kTurn, true>(F, K, depth, x, y, s, rc, rs)
+                       : ssao_at_proj<kTurn, false>(F, K, depth, x, y, s, rc, rs);
 }
 
 // Rank of pixel (x, y) in the 4x4 ordered-dither (Bayer) tile: the index of
