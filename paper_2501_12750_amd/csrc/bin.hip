@@ -456,13 +456,15 @@ constexpr uint32_t kNoRun = 0x80000000u;
 // the overflow flag in the frame counters.  The counts are read as up to
 // kMaxLdsTiles / 1024 rows of 1024 consecutive tiles, every load issued
 // before the first is used (coalesced, all in flight); each wave scans its
-// 64 lanes of every row with DPP steps, and one LDS exchange of the wave
-// totals gives every (row, wave) its start.
+// 64 lanes of every row with DPP steps, and one wave scans the (row, wave)
+// totals, which gives every (row, wave) its start.
 template <class JS>
 __global__ void __launch_bounds__(kBinThreads) k_tile_offsets(JS js) {
     constexpr int kRows = (kMaxLdsTiles + kBinThreads - 1) / kBinThreads;
     constexpr int kWaves = kBinThreads / 64;
+    constexpr int kPre = (kRows * kWaves + 63) / 64;
     __shared__ uint32_t wsum[kRows][kWaves];
+    __shared__ unsigned long long wpre[kRows * kWaves + 1];
     __shared__ uint32_t over_sum;
     if (blockIdx.x >= js.count()) return;
     const Job& J = js.job((int)blockIdx.x);
@@ -485,25 +487,44 @@ __global__ void __launch_bounds__(kBinThreads) k_tile_offsets(JS js) {
         if (lane == 63) wsum[r][wave] = incl[r];
     }
     __syncthreads();
-    // start of this thread's tile in each row: the rows before it, then the
-    // waves before it in its row
-    unsigned long long base = 0;
+    // wave 0: the exclusive prefix of the (row, wave) totals in row-major
+    // order, kPre per lane, and the list total after them
+    if (wave == 0) {
+        unsigned long long part[kPre], s = 0;
+#pragma unroll
+        for (int k = 0; k < kPre; ++k) {
+            const int i = lane * kPre + k;
+            part[k] = s;
+            s += i < rows * kWaves ? wsum[i / kWaves][i % kWaves] : 0u;
+        }
+        unsigned long long pre = s;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long u = __shfl_up(pre, o);
+            if (lane >= o) pre += u;
+        }
+        pre -= s;
+#pragma unroll
+        for (int k = 0; k < kPre; ++k) {
+            const int i = lane * kPre + k;
+            if (i < kRows * kWaves) wpre[i] = pre + part[k];
+        }
+        if (lane == 63) wpre[kRows * kWaves] = pre + s;
+    }
+    __syncthreads();
+    // start of this thread's tile in each row: the (row, wave) start, then
+    // the lanes before it
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
         if (r >= rows) break;
-        unsigned long long row_total = 0, before = 0;
-        for (int w = 0; w < kWaves; ++w) {
-            row_total += wsum[r][w];
-            before += w < wave ? wsum[r][w] : 0u;
-        }
         const int t = r * kBinThreads + tid;
         if (t < T) {
-            const uint64_t o = base + before + (incl[r] - v[r]);
+            const uint64_t o = wpre[r * kWaves + wave] + (incl[r] - v[r]);
             off[t] = o;
             n_over += o + v[r] > J.bb.capacity ? 1u : 0u;   // lists the scatter leaves to the resolve's tail
         }
-        base += row_total;
     }
+    const unsigned long long base = wpre[kRows * kWaves];
     for (int o = 32; o > 0; o >>= 1) n_over += (uint32_t)__shfl_xor((int)n_over, o);
     if (lane == 0 && n_over) atomicAdd(&over_sum, n_over);
     __syncthreads();
