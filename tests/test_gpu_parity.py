@@ -309,6 +309,47 @@ def test_max_image_8k(vtx):
     assert np.count_nonzero(dev["id"] != 0xFFFFFFFF) > 1e6
 
 
+def test_tile_grid_past_8192_tiles(vtx):
+    """2560 x 1440 at 16-pixel tiles: 14,400 tiles, so the list offsets scan
+    every one of its 15 rows of 1024 tiles (the benchmark frames have 8,160);
+    windows, the last tiles among them, against the oracle, and the resident
+    scene's frame equal to vtx_render's."""
+    import torch
+    wl = scenes.plain_small(n_atoms=20000, width=2560, height=1440)
+    sc, cam, W, H = wl.scene, wl.camera, wl.width, wl.height
+    opts = with_opts(wl.options, tile_size=16)
+    assert ((W + 15) // 16) * ((H + 15) // 16) == 14400
+    ds = vtx.DeviceScene(sc)
+    dev = run_device(vtx, ds, cam, opts, W, H)
+    # windows on hits in the tiles past the first 8192 (tile rows 52 on)
+    ys, xs = np.nonzero(dev["id"] != 0xFFFFFFFF)
+    late = np.flatnonzero((ys // 16) * ((W + 15) // 16) + xs // 16 >= 8192)
+    assert late.size > 1000
+    picks = [late[0], late[late.size // 2], late[-1]]
+    on_late = [(int(min(max(xs[k] - 32, 0), W - 64)), int(min(max(ys[k] - 32, 0), H - 64)), 64, 64) for k in picks]
+    for win in windows(W, H, 64, 4, seed=5) + [(W // 2 - 32, H // 2 - 32, 64, 64), (W - 48, H - 40, 48, 40)] + on_late:
+        ref = osplat.render(sc, cam, opts, W, H, window=win, halo=0)
+        dv = crop(dev, win)
+        rep = compare.check_gbuffer(dv["depth"], dv["id"], ref)
+        rep.update(compare.check_surface(dv["normal"], dv["albedo"], ref, sc, opts))
+        rep.update(compare.check_end_to_end(dv["rgba"], ref))
+        print(win, {k: rep[k] for k in ("pixels", "hits", "id_bad", "depth_bad")}, flush=True)
+        assert_clean(rep, str(win))
+    assert np.count_nonzero(dev["id"] != 0xFFFFFFFF) > 1e5
+    plain = run_render(vtx, ds, cam, opts, W, H)
+    ctx = vtx.vtx_context_create(0, 0)
+    try:
+        rs = vtx.ResidentScene(ctx, ds)
+        fr = rs.render(cam, opts, W, H)
+        torch.cuda.synchronize()
+        got = fr.numpy()
+        rs.close()
+    finally:
+        vtx.vtx_context_destroy(ctx)
+    for k in ("depth", "id", "rgba"):
+        assert np.array_equal(got[k], plain[k]), f"resident scene: {k} differs at {np.count_nonzero(got[k] != plain[k])} px"
+
+
 def test_many_consecutive_frames_identical(vtx):
     """Back-to-back frames on one stream reuse the tile counts each frame
     re-arms for the next; 300 frames without synchronization must all
