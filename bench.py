@@ -25,7 +25,9 @@ Workloads:
 Prints ONE JSON line: frames/s (renders/s for the batch) with the contract
 fields, atom-fragments/s, p50/p99 latency, per-kernel device times (each
 kernel dispatched with its own start and stop events on the render stream),
-the roofline of the dominant kernel and of the whole frame, the resolve's
+the roofline of the dominant kernel and of the whole frame, the step's
+share of the VALU issue slots (its counted instructions from the committed
+rocprofv3 summary over the measured step time), the resolve's
 skip rate (ray tests the early-outs leave, from a counting frame), the other
 launch form of the same renders side by side, and the CPU oracle timed on
 the host.
@@ -98,6 +100,37 @@ def measured_traffic(workload_name, kernels):
             parts = line.split()
             if len(parts) == 6 and parts[0].startswith("k_"):
                 rows[parts[0]] = (float(parts[4]), parts[5])
+    total = 0.0
+    for k in kernels:
+        if k not in rows or rows[k][1] != sources_sha(k):
+            return None
+        total += rows[k][0]
+    return total
+
+
+VALU_FILES = {"ball_and_stick_1000k_1920x1080": "valu_ball_and_stick_1M_1080p.txt",
+              "whole_cell_100M_3840x2160": "valu_whole_cell_100M_4k.txt",
+              "trajectory_50k_64x4": "valu_trajectory_50k_64x4.txt"}
+
+
+def measured_valu(workload_name, kernels):
+    """VALU wave instructions per launch of the named kernels (SQ_INSTS_VALU),
+    summed, from the committed rocprofv3 counter summary of this workload;
+    None when there is none or when any of the kernels' sources changed since
+    it was taken."""
+    fname = VALU_FILES.get(workload_name)
+    if fname is None:
+        return None
+    path = os.path.join(ROOT, "profiles", fname)
+    if not os.path.exists(path):
+        return None
+    rows = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("k_"):
+                rest = line[44:].split()
+                if len(rest) == 9:
+                    rows[line[:44].replace(" ", "")] = (float(rest[7]), rest[8])
     total = 0.0
     for k in kernels:
         if k not in rows or rows[k][1] != sources_sha(k):
@@ -672,6 +705,20 @@ def run_workload(args, workload, vtx, scenes, torch, stream, steps_arg, warmup_a
     traffic = measured_traffic(name, launched[dom]) if (launched[dom] and scene_path) else None
     roof = {"kernel": dom, "launches": launched[dom], **roof, "traffic": None if traffic is None else round(traffic),
             "timing": "per-kernel dispatch events (hipExtLaunchKernel start/stop), mean over the timed steps"}
+    # the whole step against the chip's VALU issue slots: the counted VALU
+    # wave instructions of every launch of the step (committed counter
+    # summary), 4 cycles each on 1024 SIMDs at 2.4 GHz, over the measured step
+    frame_rl = frame_roofline(N, M, st, K, runner.renders, ms_per_step)
+    frame_valu = None
+    if scene_path:
+        step_kernels = (launched["project"] + [f"k_layers<{form}>", f"k_tile_offsets<{form}>"] + launched["scatter"] +
+                        launched["resolve"] + launched["shade"])
+        v = measured_valu(name, step_kernels)
+        if v is not None:
+            frame_valu = {"valu_wave_instr": round(v), "issue_frac": round(v * 4 / (ms_per_step * 1e-3 * 1024 * 2.4e9), 4),
+                          "lane_instr_per_priced_lane_op": round(v * 64 / max(1.0, frame_rl["lane_ops"]), 3),
+                          "source": "profiles/" + VALU_FILES[name],
+                          "launches": step_kernels}
 
     out = {
         "metric": "frames/s",
@@ -695,7 +742,8 @@ def run_workload(args, workload, vtx, scenes, torch, stream, steps_arg, warmup_a
                        if lat.size else None),
         "kernels": kern,
         "roofline": roof,
-        "frame_roofline": frame_roofline(N, M, st, K, runner.renders, ms_per_step),
+        "frame_roofline": frame_rl,
+        "frame_valu": frame_valu,
         "bins": {"visible": st["visible"], "pairs": st["pairs"], "overflow_tiles": st_after["overflow_tiles"]},
     }
     if cpu and not args.no_cpu_baseline:
@@ -842,7 +890,7 @@ def main():
         out[rec["config"]["workload"]] = {k: rec[k] for k in ("value", "unit", "ms_per_step", "config",
                                                                "other_launch_forms", "atom_fragments_per_s",
                                                                "latency_ms", "kernels", "roofline",
-                                                               "frame_roofline", "bins")}
+                                                               "frame_roofline", "frame_valu", "bins")}
     print(json.dumps(out), flush=True)
 
 
