@@ -921,7 +921,7 @@ hipError_t resolve_impl(const JS& js, int tile, int phase, uint32_t grid, unsign
 constexpr int kRefineBlocks = 8;   // 16x16 blocks per refine workgroup (pixels per thread in flight)
 
 template <class JS>
-__global__ void __launch_bounds__(kBlock) k_refine(JS js, uint32_t nblocks) {
+__global__ void __launch_bounds__(kBlock, 6) k_refine(JS js, uint32_t nblocks) {
     __shared__ uint16_t todo[kRefineBlocks * kBlock];
     __shared__ uint32_t wave_n[kBlock / 64];
     const int tid = threadIdx.x, wave = tid >> 6;
