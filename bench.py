@@ -692,7 +692,7 @@ def run_workload(args, workload, vtx, scenes, torch, stream, steps_arg, warmup_a
     # arguments: launch form; count: scene, rest pass, atoms only; resolve:
     # tile, counting, two-pass; shade: noise)
     form = "JobList" if batch else "OneJob"
-    atoms_only = "true" if (M == 0 and not batch) else "false"
+    atoms_only = "true" if M == 0 else "false"
     noise = "true" if getattr(runner.renders[0].options, "ssao_noise", 0) else "false"
     launched = {"project": ([f"k_cluster_cull<{form}>", f"k_count<{form},true,false,{atoms_only}>"] if scene_path
                             else [f"k_count<{form},false,false,false>"]),

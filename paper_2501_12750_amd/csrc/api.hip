@@ -1019,7 +1019,10 @@ int render_locked(std::vector<JobDesc>& d, bool bin, bool shade, hipStream_t str
         uint32_t per = starts[start_index + 1] - starts[start_index];
         for (size_t i = 1; per && i <= count; ++i)
             if (starts[start_index + i] - starts[start_index] != (uint32_t)i * per) per = 0;
-        return vtx::JobList{dj, dk, ds, (uint32_t)count, per};
+        uint32_t no_bonds = 1;
+        for (size_t i = first; i < first + count; ++i)
+            if (jobs[i].S.bond_clusters || jobs[i].F.n_bonds) no_bonds = 0;
+        return vtx::JobList{dj, dk, ds, (uint32_t)count, per, no_bonds};
     };
     if (n > 1 && capture) {
         // the tables must be the ones the eager call uploaded

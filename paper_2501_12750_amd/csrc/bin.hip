@@ -737,9 +737,9 @@ hipError_t launch_zero(uint32_t* p, size_t n, hipStream_t stream) {
     return hipGetLastError();
 }
 
-// A single render of a scene without bonds takes the atom-only count.
+// A render, or a batch, of scenes without bonds takes the atom-only count.
 inline bool atoms_only(const OneJob& js) { return js.j.S.bond_clusters == 0; }
-inline bool atoms_only(const JobList&) { return false; }
+inline bool atoms_only(const JobList& js) { return js.no_bonds != 0; }
 
 template <class JS>
 hipError_t count_impl(const JS& js, bool scene, int phase, uint32_t grid, int max_tiles, hipStream_t stream) {

@@ -461,6 +461,7 @@ struct JobList {
     const uint32_t* start;   // n + 1 entries
     uint32_t n;
     uint32_t per;            // when every job has this many blocks (else 0): job g / per
+    uint32_t no_bonds;       // no job's scene holds bonds (the count's atom-only instantiation)
     __device__ int find(uint32_t g, uint32_t& local) const {
         if (per) {
             if (g >= n * per) return -1;
