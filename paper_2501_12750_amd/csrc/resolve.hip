@@ -923,7 +923,10 @@ constexpr int kRefineBlocks = 8;   // 16x16 blocks per refine workgroup (pixels 
 template <class JS>
 __global__ void __launch_bounds__(kBlock, 6) k_refine(JS js, uint32_t nblocks) {
     __shared__ uint16_t todo[kRefineBlocks * kBlock];
+    __shared__ uint32_t todo_id[kRefineBlocks * kBlock];   // the entry's id as loaded (mark included)
     __shared__ uint32_t wave_n[kBlock / 64];
+    __shared__ int blk_job[kRefineBlocks];
+    __shared__ uint32_t blk_tile[kRefineBlocks];
     const int tid = threadIdx.x, wave = tid >> 6;
     const uint32_t q = (uint32_t)xcd_contiguous(blockIdx.x, gridDim.x);
     // the id of this thread's pixel in each of the workgroup's blocks, all
@@ -965,6 +968,15 @@ __global__ void __launch_bounds__(kBlock, 6) k_refine(JS js, uint32_t nblocks) {
         if ((int)__lane_id() >= o) incl += u;
     }
     if (__lane_id() == 63) wave_n[wave] = incl;
+    if (tid < kRefineBlocks) {
+        // each entry's job and block, for the threads that take it
+#pragma unroll
+        for (int s = 0; s < kRefineBlocks; ++s)
+            if (tid == s) {
+                blk_job[s] = ji[s];
+                blk_tile[s] = tu[s];
+            }
+    }
     __syncthreads();
     uint32_t before = 0, total = 0;
     for (int w = 0; w < kBlock / 64; ++w) {
@@ -974,25 +986,22 @@ __global__ void __launch_bounds__(kBlock, 6) k_refine(JS js, uint32_t nblocks) {
     uint32_t at = before + incl - n_mine;
 #pragma unroll
     for (int s = 0; s < kRefineBlocks; ++s)
-        if (mine & (1u << s)) todo[at++] = (uint16_t)(s * kBlock + tid);
+        if (mine & (1u << s)) {
+            todo_id[at] = raw[s];
+            todo[at++] = (uint16_t)(s * kBlock + tid);
+        }
     __syncthreads();
     for (uint32_t e = (uint32_t)tid; e < total; e += kBlock) {
         const int s = todo[e] / kBlock, t = todo[e] % kBlock;
-        // the entry's block, picked from the workgroup's (no second search)
-        int j = ji[0];
-        uint32_t tb = tu[0];
-#pragma unroll
-        for (int k = 1; k < kRefineBlocks; ++k)
-            if (s == k) {
-                j = ji[k];
-                tb = tu[k];
-            }
+        // the entry's block, one of the workgroup's (no second search)
+        const int j = blk_job[s];
+        const uint32_t tb = blk_tile[s];
         const Job& J = js.job(j);
         const Frame& F = J.F;
         const int tiles_x = (F.W + 15) / 16;
         const int px = ((int)tb % tiles_x) * 16 + (t & 15), py = ((int)tb / tiles_x) * 16 + (t >> 4);
         const size_t p = (size_t)py * F.W + px;
-        const uint32_t r0 = J.id[p];
+        const uint32_t r0 = todo_id[e];
         const uint32_t id = F.refine_flag ? r0 & ~kRefineBit : r0;
         J.depth[p] = refine_depth(J, id, px, py, J.depth[p]);
         if (F.refine_flag) J.id[p] = id;
