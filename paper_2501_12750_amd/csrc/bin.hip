@@ -63,7 +63,9 @@ struct PlainSource {     // the caller's arrays, primitives in their given order
         count = first < total ? min((uint64_t)chunk, total - first) : 0;
     }
     __device__ uint64_t items() const { return count; }
-    __device__ Item fetch(uint64_t k) const { return fetch_plain(pos, rad, bonds, n_atoms, first + k); }
+    __device__ Item fetch(uint64_t k) const {
+        return fetch_plain(to_global(pos), to_global(rad), to_global(bonds), n_atoms, first + k);
+    }
 };
 
 struct SceneSource {     // a resident scene: the clusters that passed the frustum test, by depth class
@@ -186,11 +188,11 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
     const Frame F = J.F;
     const auto src0 = SourceOf<kScene>::make(J);
     const uint32_t chunk = J.bb.chunk;
-    uint32_t* __restrict__ const vis_src = J.bb.vis_src;
-    uint2* __restrict__ const vis_rect = J.bb.vis_rect;
-    uint32_t* __restrict__ const vis_cnt = J.bb.vis_cnt;
-    uint2* __restrict__ const vis_box = J.bb.vis_box;
-    uint32_t* __restrict__ const hist_out = J.bb.hist;
+    global_t<uint32_t>* __restrict__ const vis_src = to_global(J.bb.vis_src);
+    global_t<uint2>* __restrict__ const vis_rect = to_global(J.bb.vis_rect);
+    global_t<uint32_t>* __restrict__ const vis_cnt = to_global(J.bb.vis_cnt);
+    global_t<uint2>* __restrict__ const vis_box = to_global(J.bb.vis_box);
+    global_t<uint32_t>* __restrict__ const hist_out = to_global(J.bb.hist);
     uint32_t* __restrict__ const tile_cnt = J.bb.tile_cnt;
     Counters* const ctr = J.bb.ctr;
     const int T = F.tiles_x * F.tiles_y;
@@ -235,8 +237,8 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
     if constexpr (!kScene) src.begin(blk);
     const int tsh = F.tile_shift;
     uint32_t bad_count = 0;
-    uint32_t* __restrict__ const my_src = vis_src + start;   // this workgroup's visible list
-    uint2* __restrict__ const my_rect = vis_rect + start;
+    global_t<uint32_t>* __restrict__ const my_src = vis_src + start;   // this workgroup's visible list
+    global_t<uint2>* __restrict__ const my_rect = vis_rect + start;
     // One visible-or-not primitive per lane (every lane of the wave calls
     // it): its slot in the workgroup's visible list, its tile counts.
     auto emit = [&](bool vis, uint32_t sidx, int x0, int y0, int x1, int y1) {
@@ -313,7 +315,8 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
                 // registers, which costs more than the load latency it hides
                 for (int q = 0; q < 4; ++q) {
                     const uint32_t i = c * kCluster + (uint32_t)q * 64u + lane;
-                    const float4 a = i < S.n_atoms ? S.xyzr[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+                    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (i < S.n_atoms) a = to_global(S.xyzr)[i];
                     int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
                     double vx, vy, vz;
                     to_view(F, a.x, a.y, a.z, vx, vy, vz);
@@ -377,7 +380,7 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_count(JS js, int phase) {
         }
     }
     __syncthreads();
-    uint32_t* row = hist_out + (size_t)blk * T;
+    global_t<uint32_t>* const row = hist_out + (size_t)blk * T;
     // layered lists: per-layer totals (the layer kernel turns them into list
     // starts and tile totals); otherwise the tile totals directly
     uint32_t* const tot = kScene && J.bb.layers > 1
@@ -555,13 +558,13 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_scatter(JS js, int phase) {
     const Job& J = js.job(ji);
     const Frame F = J.F;
     const uint32_t chunk = J.bb.chunk;
-    const uint32_t* __restrict__ const vis_src = J.bb.vis_src;
-    const uint2* __restrict__ const vis_rect = J.bb.vis_rect;
-    const uint32_t* __restrict__ const vis_cnt = J.bb.vis_cnt;
-    const uint32_t* __restrict__ const hist_in = J.bb.hist;
-    const uint32_t* __restrict__ const cnt = J.bb.tile_cnt;
-    const uint64_t* __restrict__ const off = J.bb.tile_off;
-    uint2* __restrict__ const list = J.bb.list;
+    const global_t<const uint32_t>* __restrict__ const vis_src = to_global(J.bb.vis_src);
+    const global_t<const uint2>* __restrict__ const vis_rect = to_global(J.bb.vis_rect);
+    const global_t<const uint32_t>* __restrict__ const vis_cnt = to_global(J.bb.vis_cnt);
+    const global_t<const uint32_t>* __restrict__ const hist_in = to_global(J.bb.hist);
+    const global_t<const uint32_t>* __restrict__ const cnt = to_global(J.bb.tile_cnt);
+    const global_t<const uint64_t>* __restrict__ const off = to_global(J.bb.tile_off);
+    global_t<uint2>* __restrict__ const list = to_global(J.bb.list);
     const uint64_t capacity = J.bb.capacity;
     Counters* const ctr = J.bb.ctr;
     Counters* const host_ctr = J.bb.host_ctr;
@@ -569,15 +572,16 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_scatter(JS js, int phase) {
     // this workgroup's layer: its runs go after those of the layers before it
     const uint32_t lay = J.bb.layers > 1 ? layer_of(blk, J.bb.groups, J.bb.layers) : 0u;
     uint32_t* const fill = J.bb.tile_fill + (size_t)lay * T;
-    const uint32_t* __restrict__ const loff = J.bb.layers > 1 ? J.bb.layer_off + (size_t)lay * T : nullptr;
+    const global_t<const uint32_t>* __restrict__ const loff =
+        J.bb.layers > 1 ? to_global(J.bb.layer_off + (size_t)lay * T) : nullptr;
     const int tid = threadIdx.x;
     const bool lead = blk == 0;
-    const uint32_t* row = hist_in + (size_t)blk * T;
+    const global_t<const uint32_t>* const row = hist_in + (size_t)blk * T;
     {
         // the workgroup's tile box (its primitives touch no tile outside it,
         // whose cursors are never read); the box's counts first, then the
         // reservations of the touched tiles, so the loads and atomics overlap
-        const uint2 box = J.bb.vis_box[blk];
+        const uint2 box = to_global(J.bb.vis_box)[blk];
         const uint32_t bx0 = box.x & 0xFFFFu, by0 = box.x >> 16, bx1 = box.y & 0xFFFFu, by1 = box.y >> 16;
         const int bw = bx0 <= bx1 ? (int)(bx1 - bx0) + 1 : 0, nb = bw * (bw ? (int)(by1 - by0) + 1 : 0);
         uint32_t h[kTileRows], r[kTileRows];
@@ -651,8 +655,8 @@ __global__ void __launch_bounds__(kBinThreads, 8) k_scatter(JS js, int phase) {
     __syncthreads();
     const uint32_t n = vis_cnt[blk];
     if (n == 0) return;
-    const uint32_t* __restrict__ const my_src = vis_src + (size_t)blk * chunk;
-    const uint2* __restrict__ const my_rect = vis_rect + (size_t)blk * chunk;
+    const global_t<const uint32_t>* __restrict__ const my_src = vis_src + (size_t)blk * chunk;
+    const global_t<const uint2>* __restrict__ const my_rect = vis_rect + (size_t)blk * chunk;
     const int ts = F.tile, tsh = F.tile_shift;
     // the footprint clipped to tile (tx, ty), in tile-local pixels
     auto local_fp = [&](int x0, int y0, int x1, int y1, int tx, int ty) -> uint32_t {

@@ -24,8 +24,9 @@ __device__ inline Item empty_item() {
 
 // Primitive p of the caller's arrays (atoms first, then bonds): the plain
 // path's source index is p itself.
-__device__ inline Item fetch_plain(const float* __restrict__ pos, const float* __restrict__ rad,
-                                   const uint32_t* __restrict__ bonds, uint32_t n_atoms, uint64_t p) {
+__device__ inline Item fetch_plain(const global_t<const float>* __restrict__ pos,
+                                   const global_t<const float>* __restrict__ rad,
+                                   const global_t<const uint32_t>* __restrict__ bonds, uint32_t n_atoms, uint64_t p) {
     Item it = empty_item();
     it.id = (uint32_t)p;
     it.src = (uint32_t)p;
@@ -51,18 +52,19 @@ __device__ inline Item fetch_plain(const float* __restrict__ pos, const float* _
 __device__ inline Item fetch_scene(const SceneDev& S, uint32_t src) {
     Item it = empty_item();
     it.src = src;
+    const global_t<const float4>* __restrict__ const xyzr = to_global(S.xyzr);
     if (src < S.n_atoms) {
-        it.a = S.xyzr[src];
-        it.id = S.atom_id[src];
+        it.a = xyzr[src];
+        it.id = to_global(S.atom_id)[src];
         it.kind = kAtom;
         return it;
     }
     const uint32_t j = src - S.n_atoms;
     if (j >= S.n_bonds) return it;
-    const uint4 br = S.bond_rec[j];
+    const uint4 br = to_global(S.bond_rec)[j];
     if (br.x == br.y) return it;
-    it.a = S.xyzr[br.x];
-    it.b = S.xyzr[br.y];
+    it.a = xyzr[br.x];
+    it.b = xyzr[br.y];
     it.id = S.n_atoms + br.z;
     it.kind = kBond;
     return it;
@@ -71,7 +73,7 @@ __device__ inline Item fetch_scene(const SceneDev& S, uint32_t src) {
 // A job's primitive by source index (resident scene or the caller's arrays).
 __device__ inline Item fetch_src(const Job& J, uint32_t src) {
     if (J.S.xyzr) return fetch_scene(J.S, src);
-    return fetch_plain(J.pos, J.rad, J.bonds, J.F.n_atoms, src);
+    return fetch_plain(to_global(J.pos), to_global(J.rad), to_global(J.bonds), J.F.n_atoms, src);
 }
 
 // View-space record of an item (FP64 view transform rounded once to FP32,

@@ -153,6 +153,9 @@ __device__ inline float hit_cylinder(const float4 ca, const float4 cb, float ox,
 // nearest the FP32 depth.
 __device__ inline float refine_depth(const Job& J, uint32_t id, int px, int py, float z32) {
     const Frame& F = J.F;
+    const global_t<const float>* __restrict__ const pos = to_global(J.pos);
+    const global_t<const float>* __restrict__ const rad = to_global(J.rad);
+    const global_t<const uint32_t>* __restrict__ const bonds = to_global(J.bonds);
     const double ndx = fma((double)px + 0.5, F.inv_w2d, -1.0);
     const double ndy = fma(-((double)py + 0.5), F.inv_h2d, 1.0);
     // ray o + t D with D.z = 1, so t is the view depth
@@ -169,8 +172,8 @@ __device__ inline float refine_depth(const Job& J, uint32_t id, int px, int py, 
     if (id < F.n_atoms) {
         const size_t i = id;
         double cx, cy, cz;
-        to_view(F, J.pos[3 * i], J.pos[3 * i + 1], J.pos[3 * i + 2], cx, cy, cz);
-        const double r = (double)atom_radius(F, J.rad[i]);
+        to_view(F, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], cx, cy, cz);
+        const double r = (double)atom_radius(F, rad[i]);
         cx -= ox;
         cy -= oy;
         const double b = fma(cx, Dx, fma(cy, Dy, cz)) * idd;
@@ -179,10 +182,10 @@ __device__ inline float refine_depth(const Job& J, uint32_t id, int px, int py, 
         t = b - sqrt(fmax(disc, 0.0) * idd);
     } else {
         const size_t bi = id - F.n_atoms;
-        const uint32_t ia = J.bonds[2 * bi], ib = J.bonds[2 * bi + 1];
+        const uint32_t ia = bonds[2 * bi], ib = bonds[2 * bi + 1];
         double A[3], B[3];
-        to_view(F, J.pos[3 * (size_t)ia], J.pos[3 * (size_t)ia + 1], J.pos[3 * (size_t)ia + 2], A[0], A[1], A[2]);
-        to_view(F, J.pos[3 * (size_t)ib], J.pos[3 * (size_t)ib + 1], J.pos[3 * (size_t)ib + 2], B[0], B[1], B[2]);
+        to_view(F, pos[3 * (size_t)ia], pos[3 * (size_t)ia + 1], pos[3 * (size_t)ia + 2], A[0], A[1], A[2]);
+        to_view(F, pos[3 * (size_t)ib], pos[3 * (size_t)ib + 1], pos[3 * (size_t)ib + 2], B[0], B[1], B[2]);
         const double rho = (double)F.bond_radius;
         double ax = B[0] - A[0], ay = B[1] - A[1], az = B[2] - A[2];
         const double L = sqrt(fma(ax, ax, fma(ay, ay, az * az)));
@@ -289,16 +292,16 @@ __device__ inline void resolve_tile(const Job& J, int t, uint32_t n, uint64_t o,
     };
     const Frame F = J.F;
     uint32_t* __restrict__ const cnt = J.bb.tile_cnt;
-    const uint2* __restrict__ const list = J.bb.list;
-    const uint32_t* __restrict__ const vis_src = J.bb.vis_src;
-    const uint2* __restrict__ const vis_rect = J.bb.vis_rect;
+    const global_t<const uint2>* __restrict__ const list = to_global(J.bb.list);
+    const global_t<const uint32_t>* __restrict__ const vis_src = to_global(J.bb.vis_src);
+    const global_t<const uint2>* __restrict__ const vis_rect = to_global(J.bb.vis_rect);
     const uint32_t* __restrict__ const vis_cnt = J.bb.vis_cnt;
     const uint2* __restrict__ const vis_box = J.bb.vis_box;
     const uint32_t chunk = J.bb.chunk, groups = J.bb.groups;
     uint32_t* __restrict__ const fill = J.bb.tile_fill;
     Counters* const ctr = J.bb.ctr;
-    float* __restrict__ const depth = J.depth;
-    uint32_t* __restrict__ const out_id = J.id;
+    global_t<float>* __restrict__ const depth = to_global(J.depth);
+    global_t<uint32_t>* __restrict__ const out_id = to_global(J.id);
 
     const int tid = threadIdx.x, lane = __lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -947,7 +950,7 @@ __global__ void __launch_bounds__(kBlock, 6) k_refine(JS js, uint32_t nblocks) {
             const Frame& F = js.job(ji[s]).F;
             const int tiles_x = (F.W + 15) / 16;
             const int x = ((int)tu[s] % tiles_x) * 16 + (tid & 15), y = ((int)tu[s] / tiles_x) * 16 + (tid >> 4);
-            if (x < F.W && y < F.H) raw[s] = js.job(ji[s]).id[(size_t)y * F.W + x];
+            if (x < F.W && y < F.H) raw[s] = to_global(js.job(ji[s]).id)[(size_t)y * F.W + x];
         }
     }
     // the marked pixels, packed into a list so that only as many waves as
@@ -1003,8 +1006,9 @@ __global__ void __launch_bounds__(kBlock, 6) k_refine(JS js, uint32_t nblocks) {
         const size_t p = (size_t)py * F.W + px;
         const uint32_t r0 = todo_id[e];
         const uint32_t id = F.refine_flag ? r0 & ~kRefineBit : r0;
-        J.depth[p] = refine_depth(J, id, px, py, J.depth[p]);
-        if (F.refine_flag) J.id[p] = id;
+        global_t<float>* const depth = to_global(J.depth);
+        depth[p] = refine_depth(J, id, px, py, depth[p]);
+        if (F.refine_flag) to_global(J.id)[p] = id;
     }
 }
 

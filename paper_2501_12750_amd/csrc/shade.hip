@@ -43,9 +43,9 @@ struct Surface {
 };
 
 __device__ inline Surface surface_at(const Job& J, const Frame& F, int x, int y, uint32_t pid, float z) {
-    const float* __restrict__ const pos = J.pos;
-    const uint32_t* __restrict__ const col = J.col;
-    const uint32_t* __restrict__ const bonds = J.bonds;
+    const global_t<const float>* __restrict__ const pos = to_global(J.pos);
+    const global_t<const uint32_t>* __restrict__ const col = to_global(J.col);
+    const global_t<const uint32_t>* __restrict__ const bonds = to_global(J.bonds);
     Surface s;
     const float ndx = fmaf((float)x + 0.5f, F.inv_w2, -1.0f);
     const float ndy = fmaf(-((float)y + 0.5f), F.inv_h2, 1.0f);
@@ -127,7 +127,7 @@ __device__ inline Surface surface_at(const Job& J, const Frame& F, int x, int y,
 // cosine and sine (rc, rs)), each compared with the depth of the pixel it
 // projects to (kPersp: perspective projection, else orthographic).
 template <bool kTurn, bool kPersp>
-__device__ inline float ssao_at_proj(const Frame& F, const SampleKernel& K, const float* __restrict__ depth, int x, int y,
+__device__ inline float ssao_at_proj(const Frame& F, const SampleKernel& K, const global_t<const float>* depth, int x, int y,
                                 const Surface& s, float rc, float rs) {
     const float nx = s.nx, ny = s.ny, nz = s.nz, Px = s.Px, Py = s.Py, Pz = s.Pz;
     // orthonormal basis from the normal (Duff et al., JCGT 2017, branchless
@@ -171,7 +171,7 @@ __device__ inline float ssao_at_proj(const Frame& F, const SampleKernel& K, cons
             // a 24-bit multiply (full rate): the pixel indices are below 2^16
             // where ok, and the offset is discarded elsewhere
             const uint32_t off = ok ? (__umul24((uint32_t)(int)spy, (uint32_t)F.W) + (uint32_t)(int)spx) << 2 : own;
-            zq[u] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(depth) + off);
+            zq[u] = *reinterpret_cast<const global_t<const float>*>(reinterpret_cast<const global_t<const char>*>(depth) + off);
             sz[u] = ok ? Sz : -INFINITY;
         }
 #pragma unroll
@@ -183,7 +183,7 @@ __device__ inline float ssao_at_proj(const Frame& F, const SampleKernel& K, cons
 
 // The projection is the frame's (one branch per pixel, none per sample).
 template <bool kTurn>
-__device__ inline float ssao_at(const Frame& F, const SampleKernel& K, const float* __restrict__ depth, int x, int y,
+__device__ inline float ssao_at(const Frame& F, const SampleKernel& K, const global_t<const float>* depth, int x, int y,
                                 const Surface& s, float rc, float rs) {
     return F.proj == 0 ? ssao_at_proj<kTurn, true>(F, K, depth, x, y, s, rc, rs)
                        : ssao_at_proj<kTurn, false>(F, K, depth, x, y, s, rc, rs);
@@ -211,12 +211,12 @@ __global__ void __launch_bounds__(kBlock) k_shade(JS js) {
     const Job& J = js.job(ji);
     const Frame F = J.F;
     const SampleKernel& K = js.samples(ji);
-    const float* __restrict__ const depth = J.depth;
-    const uint32_t* __restrict__ const ids = J.id;
-    uint32_t* __restrict__ const rgba = J.rgba;
-    float* __restrict__ const normal_out = J.normal;
-    uint32_t* __restrict__ const albedo_out = J.albedo;
-    float* __restrict__ const ao_out = J.ao;
+    const global_t<const float>* __restrict__ const depth = to_global(J.depth);
+    const global_t<const uint32_t>* __restrict__ const ids = to_global(J.id);
+    global_t<uint32_t>* __restrict__ const rgba = to_global(J.rgba);
+    global_t<float>* __restrict__ const normal_out = to_global(J.normal);
+    global_t<uint32_t>* __restrict__ const albedo_out = to_global(J.albedo);
+    global_t<float>* __restrict__ const ao_out = to_global(J.ao);
     const int tiles_x = (F.W + kTile - 1) / kTile;
     const int t = (int)tu;
     const int tid = threadIdx.x;

@@ -287,6 +287,23 @@ __device__ inline bool sphere_inside_frustum(const Frame& F, double vx, double v
 // volume (cluster indices stay below 2^31).
 constexpr uint32_t kClusterInside = 0x80000000u;
 
+// A device buffer typed in the global address space.  A pointer a batch
+// reads from its job table is generic to the compiler, which then emits flat
+// accesses (a 64-bit address each, and waits shared with LDS); through this
+// type they take the global form (a scalar base and a 32-bit offset), as
+// accesses through kernel arguments do.  Every buffer the kernels are given
+// is device or host-mapped memory, never LDS or scratch.  (The host pass,
+// which only parses device code, takes the plain type.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using global_t = __attribute__((address_space(1))) T;
+#else
+template <class T>
+using global_t = T;
+#endif
+template <class T>
+__device__ inline global_t<T>* to_global(T* p) { return (global_t<T>*)p; }
+
 // Hardware dispatch places workgroup b on XCD (b mod 8).  Give each XCD one
 // contiguous range of work items so neighbouring tiles share an L2.
 __device__ inline int xcd_contiguous(int b, int nblocks) {
