@@ -22,6 +22,15 @@ constexpr int kBatch = 16;  // SSAO samples whose depth loads are issued togethe
 
 constexpr float kKa = 0.2f, kKd = 0.8f, kKs = 0.25f;
 
+// floor(x) as an integer in one instruction (the compiler emits a floor and
+// a conversion): saturates at the int range, NaN gives 0.  Used only on
+// finite values whose floor decides a range test.
+__device__ inline int floor_to_int(float x) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 __device__ inline float smooth01(float x) {
     x = fminf(fmaxf(x, 0.0f), 1.0f);
     return x * x * (3.0f - 2.0f * x);
@@ -165,12 +174,14 @@ __device__ inline float ssao_at_proj(const Frame& F, const SampleKernel& K, cons
             // the 1e-3 px within which a pixel edge makes a sample unstable
             const float sc = kPersp ? fpx * __builtin_amdgcn_rcpf(Sz) : osc;
             const float spx = fmaf(Sx, sc, hw), spy = fmaf(-Sy, sc, hh);
+            // on the image: 0 <= spx < W and 0 <= spy < H, tested as the
+            // floors' unsigned ranges (the floors are then the pixel's indices)
+            const uint32_t ix = (uint32_t)floor_to_int(spx), iy = (uint32_t)floor_to_int(spy);
             // & rather than &&: all tests evaluated, no branches per sample
-            const bool ok = (k < K.count) & (Sz > F.znear) & (spx >= 0.0f) & (spx < (float)F.W) & (spy >= 0.0f) &
-                            (spy < (float)F.H);
+            const bool ok = (k < K.count) & (Sz > F.znear) & (ix < (uint32_t)F.W) & (iy < (uint32_t)F.H);
             // a 24-bit multiply (full rate): the pixel indices are below 2^16
             // where ok, and the offset is discarded elsewhere
-            const uint32_t off = ok ? (__umul24((uint32_t)(int)spy, (uint32_t)F.W) + (uint32_t)(int)spx) << 2 : own;
+            const uint32_t off = ok ? (__umul24(iy, (uint32_t)F.W) + ix) << 2 : own;
             zq[u] = *reinterpret_cast<const global_t<const float>*>(reinterpret_cast<const global_t<const char>*>(depth) + off);
             sz[u] = ok ? Sz : -INFINITY;
         }
