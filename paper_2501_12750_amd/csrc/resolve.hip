@@ -151,11 +151,10 @@ __device__ inline float hit_cylinder(const float4 ca, const float4 cb, float ox,
 // depth is the surface's closest approach to the ray: the front root with
 // the discriminant taken as zero, or the cap plane's crossing, whichever is
 // nearest the FP32 depth.
-__device__ inline float refine_depth(const Job& J, uint32_t id, int px, int py, float z32) {
-    const Frame& F = J.F;
-    const global_t<const float>* __restrict__ const pos = to_global(J.pos);
-    const global_t<const float>* __restrict__ const rad = to_global(J.rad);
-    const global_t<const uint32_t>* __restrict__ const bonds = to_global(J.bonds);
+__device__ inline float refine_depth_at(const Frame& F, const global_t<const float>* __restrict__ pos,
+                                       const global_t<const float>* __restrict__ rad,
+                                       const global_t<const uint32_t>* __restrict__ bonds, uint32_t id, int px, int py,
+                                       float z32) {
     const double ndx = fma((double)px + 0.5, F.inv_w2d, -1.0);
     const double ndy = fma(-((double)py + 0.5), F.inv_h2d, 1.0);
     // ray o + t D with D.z = 1, so t is the view depth
@@ -224,6 +223,10 @@ __device__ inline float refine_depth(const Job& J, uint32_t id, int px, int py, 
     }
     const float z = (float)t;
     return z > 0.0f && z < INFINITY ? z : z32;
+}
+
+__device__ inline float refine_depth(const Job& J, uint32_t id, int px, int py, float z32) {
+    return refine_depth_at(J.F, to_global(J.pos), to_global(J.rad), to_global(J.bonds), id, px, py, z32);
 }
 
 // Expand a list record into the LDS form.
@@ -994,6 +997,30 @@ __global__ void __launch_bounds__(kBlock, 6) k_refine(JS js, uint32_t nblocks) {
             todo[at++] = (uint16_t)(s * kBlock + tid);
         }
     __syncthreads();
+    if (ji[0] >= 0 && ji[kRefineBlocks - 1] == ji[0]) {
+        // all the workgroup's blocks are one job's (the usual case): block s
+        // is that job's block tu[0] + s, and the job's frame is read once,
+        // into scalar registers, rather than per entry
+        const Job& J = js.job(__builtin_amdgcn_readfirstlane(ji[0]));
+        const Frame& F = J.F;
+        const global_t<const float>* __restrict__ const pos = to_global(J.pos);
+        const global_t<const float>* __restrict__ const rad = to_global(J.rad);
+        const global_t<const uint32_t>* __restrict__ const bonds = to_global(J.bonds);
+        global_t<float>* __restrict__ const depth = to_global(J.depth);
+        global_t<uint32_t>* __restrict__ const out_id = to_global(J.id);
+        const int tiles_x = (F.W + 15) / 16, tb0 = __builtin_amdgcn_readfirstlane((int)tu[0]);
+        for (uint32_t e = (uint32_t)tid; e < total; e += kBlock) {
+            const int s = todo[e] / kBlock, t = todo[e] % kBlock;
+            const int tb = tb0 + s;
+            const int px = (tb % tiles_x) * 16 + (t & 15), py = (tb / tiles_x) * 16 + (t >> 4);
+            const size_t p = (size_t)py * F.W + px;
+            const uint32_t r0 = todo_id[e];
+            const uint32_t id = F.refine_flag ? r0 & ~kRefineBit : r0;
+            depth[p] = refine_depth_at(F, pos, rad, bonds, id, px, py, depth[p]);
+            if (F.refine_flag) out_id[p] = id;
+        }
+        return;
+    }
     for (uint32_t e = (uint32_t)tid; e < total; e += kBlock) {
         const int s = todo[e] / kBlock, t = todo[e] % kBlock;
         // the entry's block, one of the workgroup's (no second search)
