@@ -529,6 +529,8 @@ int make_frame(const vtx_camera* cam, const vtx_options& o, int32_t W, int32_t H
     F->hyf = (float)F->hy;
     F->inv_w2 = 2.0f / (float)W;
     F->inv_h2 = 2.0f / (float)H;
+    F->ssao_fpx = 0.5f * (float)H / F->tyf;
+    F->ssao_osc = 0.5f * (float)H / F->hyf;
     F->inv_w2d = 2.0 / (double)W;
     F->inv_h2d = 2.0 / (double)H;
     F->znear = cam->znear;

@@ -62,7 +62,9 @@ __device__ inline Surface surface_at(const Job& J, const Frame& F, int x, int y,
         const float Dx = ndx * F.txf, Dy = ndy * F.tyf;
         s.Px = z * Dx;
         s.Py = z * Dy;
-        const float inv = rsqrtf(fmaf(Dx, Dx, fmaf(Dy, Dy, 1.0f)));
+        // hardware reciprocal square root: what rsqrtf reduces to for an
+        // argument of at least the smallest normal float (here at least 1)
+        const float inv = __builtin_amdgcn_rsqf(fmaf(Dx, Dx, fmaf(Dy, Dy, 1.0f)));
         s.Vx = -Dx * inv; s.Vy = -Dy * inv; s.Vz = -inv;
     } else {
         s.Px = ndx * F.hxf;
@@ -124,7 +126,9 @@ __device__ inline Surface surface_at(const Job& J, const Frame& F, int x, int y,
                 }
             }
         }
-        const float inv = rsqrtf(fmaf(nx, nx, fmaf(ny, ny, nz * nz)));
+        // (as above: a squared surface offset of an atom or bond, far above
+        // the smallest normal float)
+        const float inv = __builtin_amdgcn_rsqf(fmaf(nx, nx, fmaf(ny, ny, nz * nz)));
         nx *= inv; ny *= inv; nz *= inv;
     }
     s.nx = nx; s.ny = ny; s.nz = nz;
@@ -150,8 +154,7 @@ __device__ inline float ssao_at_proj(const Frame& F, const SampleKernel& K, cons
                 Tz = kTurn ? fmaf(rc, T0z, rs * B0z) : T0z;
     const float Bx = kTurn ? fmaf(rc, B0x, -rs * T0x) : B0x, By = kTurn ? fmaf(rc, B0y, -rs * T0y) : B0y,
                 Bz = kTurn ? fmaf(rc, B0z, -rs * T0z) : B0z;
-    const float fpx = 0.5f * (float)F.H / F.tyf;
-    const float osc = 0.5f * (float)F.H / F.hyf;
+    const float fpx = F.ssao_fpx, osc = F.ssao_osc;
     float occ = 0.0f;
     // Samples are taken kBatch at a time: every address first, then the
     // loads, then the tests in sample order, so the loads of a batch are

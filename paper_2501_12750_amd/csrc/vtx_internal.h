@@ -55,6 +55,7 @@ struct Frame {
     float itxf, ityf;                  // 1 / tx, 1 / ty
     float sxf, syf;                    // perspective: sqrt(1 + tx^2), sqrt(1 + ty^2)
     float inv_w2, inv_h2;              // 2/W, 2/H
+    float ssao_fpx, ssao_osc;          // view to pixel scale of SSAO samples: 0.5 H / ty, 0.5 H / hy (FP32)
     double inv_w2d, inv_h2d;           // the same in FP64
     float znear, zfar;
     float bond_radius;
