@@ -77,6 +77,30 @@ def test_batch_trajectory_equals_single_renders(vtx, ctx):
     rs.close()
 
 
+def test_batch_refine_across_job_boundaries(vtx, ctx):
+    """Jobs of one or two by two shade blocks, so that every refine workgroup
+    (eight blocks) spans several jobs, with every pixel covered by atoms, so
+    that marked winners fall on that path of the refine pass."""
+    scene0, frames, cams, opts, rs = trajectory_scene(vtx, ctx, 5000, 3)
+    c = frames[0].mean(axis=0)
+    sizes = [(24, 24), (20, 28), (32, 16)]
+    specs = []
+    for f in range(3):
+        for k in range(6):
+            ang = 2.0 * math.pi * k / 6.0
+            cam = scenes.Camera(eye=(c[0] + 40.0 * math.sin(ang), c[1] + 6.0, c[2] + 40.0 * math.cos(ang)),
+                                target=tuple(c), fovy=math.radians(20.0))
+            W, H = sizes[(f + k) % 3]
+            specs.append((rs.handle, f, cam, opts, W, H))
+    got = run_batch(vtx, ctx, specs)
+    for i, (_, f, cam, o, W, H) in enumerate(specs):
+        sc_f = scenes.Scene(frames[f], scene0.radii, scene0.colors, scene0.bonds)
+        ref = run_render(vtx, vtx.DeviceScene(sc_f), cam, o, W, H)
+        assert_identical(got[i], ref, f"job {i} (frame {f})")
+        assert np.count_nonzero(ref["id"] == 0xFFFFFFFF) == 0, f"job {i}: background pixels"
+    rs.close()
+
+
 def _mixed_specs(vtx, ctx):
     bas = scenes.ball_and_stick(n_globules=27, atoms_per_globule=300, sigma=5.0, pitch=8.0,
                                 width=333, height=221, ssao_samples=16)
