@@ -125,7 +125,8 @@ def test_autotune_picks_ssao_samples_within_a_budget(vtx, tmp_path):
     assert t2["ssao_samples"] == 0 and set(t2["ms_by_samples"]) == set(vtx.SSAO_COUNTS)
     times = t2["ms_by_samples"]
     assert times[64] > times[0]
-    mid = 0.5 * (times[64] + times[0])
+    # the budget as the tuner holds it (FP32), so that both sides compare the same value
+    mid = float(np.float32(0.5 * (times[64] + times[0])))
     t3 = vtx.vtx_autotune(ctx, jobs, tmp_path / "s.json", frame_budget_ms=mid)
     fits = [k for k in vtx.SSAO_COUNTS if times[k] <= mid]
     print(times, t3)
