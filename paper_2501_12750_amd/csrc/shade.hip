@@ -23,8 +23,9 @@ constexpr int kBatch = 16;  // SSAO samples whose depth loads are issued togethe
 constexpr float kKa = 0.2f, kKd = 0.8f, kKs = 0.25f;
 
 // floor(x) as an integer in one instruction (the compiler emits a floor and
-// a conversion): saturates at the int range, NaN gives 0.  Used only on
-// finite values whose floor decides a range test.
+// a conversion): saturates at the int range, NaN gives 0.  An SSAO sample
+// whose projection is not finite lies behind the near plane, which its own
+// test rejects, so the value then does not matter.
 __device__ inline int floor_to_int(float x) {
     int r;
     asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
