@@ -924,7 +924,7 @@ hipError_t resolve_impl(const JS& js, int tile, int phase, uint32_t grid, unsign
 // mark) gets its depth recomputed from the primitive's FP64 data
 // (refine_depth) and its mark cleared; every other pixel keeps the resolve's
 // FP32 depth, which is within the tolerance there (see kGrazeCos).
-constexpr int kRefineBlocks = 8;   // 16x16 blocks per refine workgroup (pixels per thread in flight)
+constexpr int kRefineBlocks = 16;   // 16x16 blocks per refine workgroup (pixels per thread in flight)
 
 template <class JS>
 __global__ void __launch_bounds__(kBlock, 6) k_refine(JS js, uint32_t nblocks) {
